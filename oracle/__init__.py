@@ -1,0 +1,214 @@
+"""FP64 CPU oracle for 3DGS tile splatting, forward and backward.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the bench's
+CPU-baseline leg may use it; the product path never imports it.
+
+Two independent forms of the same definition:
+  * ``liboracle.so`` (oracle.cpp): the tiled pipeline in double precision,
+    project -> bin (prefix sum, replicate, sort, ranges) -> composite, and the
+    analytic backward of every stage;
+  * ``brute``: per-pixel brute force (numpy / torch float64) with no pairs,
+    no sort and no ranges, differentiable with torch autograd.
+
+Citations are to the paper (XPR, arxiv 2606.11529): Background section
+(blending), Listing "Implementation of XPR-3DGS" (project/evaluate), section
+"Rasterizer" (replicate, tile id, sort, bounds), Algorithm 1 (shader loop).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+@dataclasses.dataclass
+class OracleConfig:
+    """Constants of the method (readings listed in the design notes)."""
+    tile_w: int = 16
+    tile_h: int = 16
+    sh_degree: int = 3
+    lowpass: float = 0.3            # added to both diagonal entries of cov2D
+    alpha_min: float = 1.0 / 255.0  # alpha_thresh of the listing
+    alpha_max: float = 0.99
+    t_min: float = 1e-4             # stop before blending if T(1-a) < t_min
+    z_near: float = 0.2
+    fov_clip: float = 1.3           # Jacobian clamp at fov_clip*tan(fov/2)
+    bg: tuple = (0.0, 0.0, 0.0)
+
+    def proj_cfg(self):
+        return np.array([self.lowpass, self.alpha_min, self.z_near, self.fov_clip],
+                        dtype=np.float64)
+
+    def render_cfg(self):
+        return np.array([self.alpha_min, self.alpha_max, self.t_min, *self.bg],
+                        dtype=np.float64)
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(HERE, "liboracle.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(path)
+        P = ctypes.c_void_p
+        i64, i32 = ctypes.c_int64, ctypes.c_int
+        L.orc_project.argtypes = [i64, P, P, P, P, P, i32, P, i32, i32, P, i32, i32, i32,
+                                  P, P, P, P, P, P, P]
+        L.orc_project.restype = None
+        L.orc_bin.argtypes = [i64, P, P, P, i32, i32, i64, P, P, P, P]
+        L.orc_bin.restype = i64
+        L.orc_render_fwd.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P, P, P, P]
+        L.orc_render_fwd.restype = None
+        L.orc_render_bwd.argtypes = [i32, i32, i32, i32, i64, P, P, P, P, P, P]
+        L.orc_render_bwd.restype = None
+        L.orc_project_bwd.argtypes = [i64, P, P, P, P, P, i32, P, i32, i32, P, i32, i32, i32,
+                                      P, P, P, P, P, P]
+        L.orc_project_bwd.restype = None
+        L.orc_sh_basis.argtypes = [i32, P, P, P]
+        L.orc_sh_basis.restype = None
+        L.orc_num_threads.restype = i32
+        _LIB = L
+    return _LIB
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def cam_vec(cam) -> np.ndarray:
+    """R (9), t (3), fx, fy, cx, cy as float64."""
+    return np.concatenate([np.asarray(cam.R, np.float64).reshape(9),
+                           np.asarray(cam.t, np.float64).reshape(3),
+                           [cam.fx, cam.fy, cam.cx, cam.cy]]).astype(np.float64)
+
+
+def tiles(cam, cfg: OracleConfig):
+    return ((cam.width + cfg.tile_w - 1) // cfg.tile_w,
+            (cam.height + cfg.tile_h - 1) // cfg.tile_h)
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+def sh_basis(deg: int, d, grad: bool = False):
+    d = _f64(d)
+    nb = (deg + 1) ** 2
+    Y = np.zeros(nb)
+    dY = np.zeros((nb, 3)) if grad else None
+    lib().orc_sh_basis(deg, _p(d), _p(Y), _p(dY))
+    return (Y, dY) if grad else Y
+
+
+def _scene_arrays(scene):
+    return (_f64(scene.means), _f64(scene.scales), _f64(scene.quats),
+            _f64(scene.opacities), _f64(scene.sh))
+
+
+def project(scene, cam, cfg: OracleConfig):
+    """Projection of every Gaussian (Listing XPR-3DGS, project)."""
+    m, s, q, o, sh = _scene_arrays(scene)
+    n = o.shape[0]
+    K = sh.shape[0]
+    out = dict(rec=np.zeros((n, 9)), cov=np.zeros((n, 3)), depth=np.zeros(n),
+               rect=np.zeros((n, 4), np.int32), tc=np.zeros(n, np.int32),
+               radius=np.zeros(n, np.int32), guard=np.zeros(n, np.uint8))
+    cv = cam_vec(cam)
+    pc = cfg.proj_cfg()
+    lib().orc_project(n, _p(m), _p(s), _p(q), _p(o), _p(sh), K, _p(cv), cam.width,
+                      cam.height, _p(pc), cfg.tile_w, cfg.tile_h, cfg.sh_degree,
+                      _p(out["rec"]), _p(out["cov"]), _p(out["depth"]), _p(out["rect"]),
+                      _p(out["tc"]), _p(out["radius"]), _p(out["guard"]))
+    return out
+
+
+def bin_pairs(depth, rect, tc, tiles_x: int, tiles_y: int):
+    """Binning (section Rasterizer): offsets, I, keys, vals, ranges."""
+    depth = _f64(depth)
+    rect = np.ascontiguousarray(rect, dtype=np.int32)
+    tc = np.ascontiguousarray(tc, dtype=np.int32)
+    n = depth.shape[0]
+    offsets = np.zeros(n, np.int64)
+    I = int(tc.astype(np.int64).sum())
+    keys = np.zeros(I, np.uint64)
+    vals = np.zeros(I, np.int32)
+    ranges = np.zeros((tiles_x * tiles_y, 2), np.int32)
+    got = lib().orc_bin(n, _p(depth), _p(rect), _p(tc), tiles_x, tiles_y, I, _p(offsets),
+                        _p(keys), _p(vals), _p(ranges))
+    assert got == I
+    return dict(offsets=offsets, I=I, keys=keys, vals=vals, ranges=ranges)
+
+
+def render_fwd(rec, vals, ranges, W: int, H: int, cfg: OracleConfig):
+    """Compositing (Algorithm 1 with the 3DGS evaluate)."""
+    rec = _f64(rec)
+    vals = np.ascontiguousarray(vals, np.int32)
+    ranges = np.ascontiguousarray(ranges, np.int32)
+    out = dict(img=np.zeros((3, H, W)), Tfinal=np.zeros((H, W)),
+               ncontrib=np.zeros((H, W), np.int32), nblend=np.zeros((H, W), np.int32),
+               guard=np.zeros((H, W), np.uint8))
+    rc = cfg.render_cfg()
+    lib().orc_render_fwd(W, H, cfg.tile_w, cfg.tile_h, _p(rec), _p(vals), _p(ranges), _p(rc),
+                         _p(out["img"]), _p(out["Tfinal"]), _p(out["ncontrib"]),
+                         _p(out["nblend"]), _p(out["guard"]))
+    return out
+
+
+def render_bwd(rec, vals, ranges, W: int, H: int, cfg: OracleConfig, dimg):
+    """dL/d(shader data) [n][9] from dL/dimage [3][H][W]."""
+    rec = _f64(rec)
+    n = rec.shape[0]
+    grad = np.zeros((n, 9))
+    rc = cfg.render_cfg()
+    dimg = _f64(dimg)
+    lib().orc_render_bwd(W, H, cfg.tile_w, cfg.tile_h, n, _p(rec),
+                         _p(np.ascontiguousarray(vals, np.int32)),
+                         _p(np.ascontiguousarray(ranges, np.int32)), _p(rc), _p(dimg),
+                         _p(grad))
+    return grad
+
+
+def project_bwd(scene, cam, cfg: OracleConfig, grad9):
+    """Parameter gradients (activated scales/opacity, raw quaternion)."""
+    m, s, q, o, sh = _scene_arrays(scene)
+    n = o.shape[0]
+    K = sh.shape[0]
+    g = dict(means=np.zeros((3, n)), scales=np.zeros((3, n)), quats=np.zeros((4, n)),
+             opacities=np.zeros(n), sh=np.zeros((K, 3, n)))
+    cv = cam_vec(cam)
+    pc = cfg.proj_cfg()
+    lib().orc_project_bwd(n, _p(m), _p(s), _p(q), _p(o), _p(sh), K, _p(cv), cam.width,
+                          cam.height, _p(pc), cfg.tile_w, cfg.tile_h, cfg.sh_degree,
+                          _p(_f64(grad9)), _p(g["means"]), _p(g["scales"]), _p(g["quats"]),
+                          _p(g["opacities"]), _p(g["sh"]))
+    return g
+
+
+def render(scene, cam, cfg: OracleConfig):
+    """Whole forward pipeline in FP64: returns every intermediate."""
+    pr = project(scene, cam, cfg)
+    tx, ty = tiles(cam, cfg)
+    b = bin_pairs(pr["depth"], pr["rect"], pr["tc"], tx, ty)
+    f = render_fwd(pr["rec"], b["vals"], b["ranges"], cam.width, cam.height, cfg)
+    return dict(proj=pr, bins=b, fwd=f)
+
+
+def backward(scene, cam, cfg: OracleConfig, dimg, state=None):
+    """Analytic gradient of <dimg, image> with respect to the scene."""
+    st = render(scene, cam, cfg) if state is None else state
+    g9 = render_bwd(st["proj"]["rec"], st["bins"]["vals"], st["bins"]["ranges"],
+                    cam.width, cam.height, cfg, dimg)
+    g = project_bwd(scene, cam, cfg, g9)
+    g["grad9"] = g9
+    return g

@@ -1,0 +1,166 @@
+"""Per-pixel brute-force renderer in torch float64 (test infrastructure only).
+
+Independent of oracle.cpp: no pair list, no sort, no tile ranges. For every
+pixel it takes the set of Gaussians that are visible and whose tile-space
+rectangle contains the pixel's tile (the support rule of the listing
+"Implementation of XPR-3DGS": the rasterizer only ever pairs a Gaussian with
+the tiles of its bounding box), orders them by (depth as float32, index), and
+composites front to back with the gates of the 3DGS evaluate (power <= 0,
+alpha >= alpha_thresh) and the blending of the Background section.
+
+Decisions (gates, stop, rect, clamps) are taken on detached values, so torch
+autograd yields the same piecewise derivative as the analytic oracle: this is
+its independent check. Meant for tiny scenes (<= a few hundred Gaussians, <=
+64x64 pixels).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import OracleConfig
+
+_PI = math.pi
+
+
+def _sh_real(deg, d):
+    """Real SH (Condon-Shortley phase kept) at unit directions d [G,3]."""
+    x, y, z = d[:, 0], d[:, 1], d[:, 2]
+    out = [torch.full_like(x, 0.5 / math.sqrt(_PI))]
+    if deg >= 1:
+        k1 = math.sqrt(3 / (4 * _PI))
+        out += [-k1 * y, k1 * z, -k1 * x]
+    if deg >= 2:
+        a, b, c = 0.5 * math.sqrt(15 / _PI), 0.25 * math.sqrt(5 / _PI), 0.25 * math.sqrt(15 / _PI)
+        out += [a * x * y, -a * y * z, b * (2 * z * z - x * x - y * y), -a * x * z,
+                c * (x * x - y * y)]
+    if deg >= 3:
+        a = 0.25 * math.sqrt(35 / (2 * _PI))
+        b = 0.5 * math.sqrt(105 / _PI)
+        c = 0.25 * math.sqrt(21 / (2 * _PI))
+        d_ = 0.25 * math.sqrt(7 / _PI)
+        e = 0.25 * math.sqrt(105 / _PI)
+        out += [-a * y * (3 * x * x - y * y), b * x * y * z,
+                -c * y * (4 * z * z - x * x - y * y),
+                d_ * z * (2 * z * z - 3 * x * x - 3 * y * y),
+                -c * x * (4 * z * z - x * x - y * y), e * z * (x * x - y * y),
+                -a * x * (x * x - 3 * y * y)]
+    return torch.stack(out, dim=1)  # [G, nb]
+
+
+def _quat_rot(q):
+    q = q / q.norm(dim=1, keepdim=True)
+    w, x, y, z = q.unbind(1)
+    R = torch.stack([
+        1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+        2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+        2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], dim=1)
+    return R.view(-1, 3, 3)
+
+
+def project_torch(means, scales, quats, opac, sh, cam, cfg: OracleConfig):
+    """means [G,3], scales [G,3], quats [G,4], opac [G], sh [G,K,3] (float64)."""
+    Rw = torch.as_tensor(np.asarray(cam.R), dtype=torch.float64)
+    tw = torch.as_tensor(np.asarray(cam.t), dtype=torch.float64)
+    t = means @ Rw.T + tw
+    tx, ty, tz = t.unbind(1)
+    Rq = _quat_rot(quats)
+    M = Rq * scales[:, None, :]
+    Sigma = M @ M.transpose(1, 2)
+    limx = cfg.fov_clip * cam.width / (2 * cam.fx)
+    limy = cfg.fov_clip * cam.height / (2 * cam.fy)
+    rx, ry = tx / tz, ty / tz
+    if cfg.fov_clip > 0:
+        rx = torch.clamp(rx, -limx, limx)
+        ry = torch.clamp(ry, -limy, limy)
+    zero = torch.zeros_like(tz)
+    J = torch.stack([torch.stack([cam.fx / tz, zero, -cam.fx * rx / tz], 1),
+                     torch.stack([zero, cam.fy / tz, -cam.fy * ry / tz], 1)], 1)
+    T = J @ Rw
+    cov = T @ Sigma @ T.transpose(1, 2)
+    a = cov[:, 0, 0] + cfg.lowpass
+    b = cov[:, 0, 1]
+    c = cov[:, 1, 1] + cfg.lowpass
+    det = a * c - b * b
+    con = torch.stack([c / det, -b / det, a / det], 1)
+    u = cam.fx * tx / tz + cam.cx - 0.5
+    v = cam.fy * ty / tz + cam.cy - 0.5
+    with torch.no_grad():
+        mid = 0.5 * (a + c)
+        lam = mid + torch.sqrt(torch.clamp(mid * mid - det, min=0.0))
+        r = torch.ceil(3 * torch.sqrt(lam))
+        txn = (cam.width + cfg.tile_w - 1) // cfg.tile_w
+        tyn = (cam.height + cfg.tile_h - 1) // cfg.tile_h
+        x0 = torch.clamp(torch.floor((u - r) / cfg.tile_w), 0, txn)
+        x1 = torch.clamp(torch.floor((u + r) / cfg.tile_w) + 1, 0, txn)
+        y0 = torch.clamp(torch.floor((v - r) / cfg.tile_h), 0, tyn)
+        y1 = torch.clamp(torch.floor((v + r) / cfg.tile_h) + 1, 0, tyn)
+        tc = (x1 - x0) * (y1 - y0)
+        visible = (tz > cfg.z_near) & (det > 0) & (opac >= cfg.alpha_min) & (r > 0) & (tc > 0)
+    campos = -(Rw.T @ tw)
+    dvec = means - campos
+    dirs = dvec / dvec.norm(dim=1, keepdim=True)
+    nb = (cfg.sh_degree + 1) ** 2
+    Y = _sh_real(cfg.sh_degree, dirs)
+    raw = 0.5 + torch.einsum("gj,gjc->gc", Y, sh[:, :nb, :])
+    colour = torch.clamp(raw, min=0.0)
+    return dict(u=u, v=v, con=con, colour=colour, depth=tz, visible=visible,
+                rect=torch.stack([x0, y0, x1, y1], 1).long(), opac=opac)
+
+
+def render_torch(means, scales, quats, opac, sh, cam, cfg: OracleConfig):
+    """Differentiable per-pixel brute force; returns image [3,H,W] float64."""
+    pr = project_torch(means, scales, quats, opac, sh, cam, cfg)
+    W, H = cam.width, cam.height
+    G = opac.shape[0]
+    ys, xs = torch.meshgrid(torch.arange(H, dtype=torch.float64),
+                            torch.arange(W, dtype=torch.float64), indexing="ij")
+    xs = xs.reshape(-1)
+    ys = ys.reshape(-1)
+    ptx = (xs // cfg.tile_w).long()
+    pty = (ys // cfg.tile_h).long()
+    # global front-to-back order by (depth as float32, index)
+    d32 = pr["depth"].detach().to(torch.float32).numpy()
+    order = np.lexsort((np.arange(G), d32))
+    img = torch.zeros(3, H * W, dtype=torch.float64)
+    T = torch.ones(H * W, dtype=torch.float64)
+    done = torch.zeros(H * W, dtype=torch.bool)
+    bg = torch.as_tensor(cfg.bg, dtype=torch.float64)
+    for g in order.tolist():
+        if not bool(pr["visible"][g]):
+            continue
+        x0, y0, x1, y1 = [int(z) for z in pr["rect"][g]]
+        inside = (ptx >= x0) & (ptx < x1) & (pty >= y0) & (pty < y1)
+        dx = xs - pr["u"][g]
+        dy = ys - pr["v"][g]
+        con = pr["con"][g]
+        power = -0.5 * (con[0] * dx * dx + con[2] * dy * dy) - con[1] * dx * dy
+        alpha = torch.clamp(opac[g] * torch.exp(power), max=cfg.alpha_max)
+        with torch.no_grad():
+            live = inside & ~done & (power <= 0) & (alpha >= cfg.alpha_min)
+            Tn = T * (1 - alpha)
+            stop = live & (Tn < cfg.t_min)
+            done = done | stop
+            blend = live & ~stop
+        a = torch.where(blend, alpha, torch.zeros_like(alpha))
+        img = img + pr["colour"][g][:, None] * (a * T)[None, :]
+        T = T * (1 - a)
+    img = img + T[None, :] * bg[:, None]
+    return img.view(3, H, W), T.view(H, W)
+
+
+def scene_tensors(scene, requires_grad=False):
+    """float64 torch tensors [G, ...] from a synth.Scene (SoA [k][n])."""
+    def t(a):
+        x = torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64).clone()
+        return x.requires_grad_(requires_grad)
+    return (t(scene.means.T), t(scene.scales.T), t(scene.quats.T), t(scene.opacities),
+            t(np.transpose(scene.sh, (2, 0, 1))))
+
+
+def render(scene, cam, cfg: OracleConfig):
+    with torch.no_grad():
+        img, T = render_torch(*scene_tensors(scene), cam, cfg)
+    return img.numpy(), T.numpy()

@@ -1,0 +1,655 @@
+// FP64 CPU oracle for tile-based splatting of 3D Gaussians (3DGS), forward
+// and backward.
+//
+// TEST INFRASTRUCTURE ONLY. Only the tests, the smoke check and the bench's
+// CPU-baseline leg may load this library. The GPU path shares no code,
+// header, table or helper with it.
+//
+// What it computes follows the paper (XPR, arxiv 2606.11529):
+//   * Background section: 3D Gaussian G(x) with covariance R S S^T R^T,
+//     opacity o, SH colour; alpha blending c = sum c_i a_i T_i with
+//     T_i = prod_{j<i} (1 - a_j) and termination on low transmittance.
+//   * Listing "Implementation of XPR-3DGS", function project: world->camera,
+//     EWA 2D covariance, conic, extents/radius, tile-space bounding box,
+//     tile count, visibility flag, colour, shader data (mu2D, -0.5*con00,
+//     -con01, -0.5*con11, o, c); function evaluate: power and alpha.
+//   * Section "Rasterizer": replicate by prefix sum, tile id
+//     t = y*W' + x with x = xmin + (r mod w), y = ymin + floor(r/w), sort by
+//     (tile id, depth), per-tile segment bounds.
+//   * Section "Shader", Algorithm 1: per-pixel front-to-back loop over the
+//     tile's list, gate and accumulate.
+// Readings where the paper is silent (pixel sample position, low-pass 0.3,
+// 3-sigma radius from the largest eigenvalue, conservative rect rounding,
+// alpha clamp 0.99, stop at T < 1e-4 before blending, ties by index, SH
+// basis with Condon-Shortley phase, +0.5 colour offset and clamp at 0,
+// off-screen Jacobian clamp 1.3*tan(fov/2)) are listed with the design notes.
+//
+// The backward is the analytic derivative of the forward above (the paper
+// differentiates its pipeline with JAX autodiff, section "Key Interfaces"):
+// gate, stop and rect decisions are piecewise constant (zero derivative), and
+// the clamps (Jacobian clamp, colour >= 0, alpha <= 0.99) take the true
+// one-sided derivative.
+//
+// All array arguments are plain host arrays. Per-Gaussian SoA inputs are
+// [k][n] (component-major) in double precision; the caller casts float32
+// inputs exactly.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#include <parallel/algorithm>
+#endif
+
+namespace {
+
+// ----------------------------------------------------------------------------
+// Real spherical harmonics up to degree 3, orthonormal on the unit sphere,
+// with the Condon-Shortley phase kept: for m > 0 the function is
+// sqrt(2) Re Y_l^m, for m < 0 it is sqrt(2) Im Y_l^|m|, ordered m = -l..l.
+// Normalisation constants from the closed forms sqrt((2l+1)/(4pi) (l-m)!/(l+m)!).
+// ----------------------------------------------------------------------------
+struct ShConst {
+  double k0, k1, k2a, k2b, k2c, k3a, k3b, k3c, k3d, k3e;
+  ShConst() {
+    const double pi = 3.14159265358979323846;
+    k0 = 0.5 / std::sqrt(pi);
+    k1 = std::sqrt(3.0 / (4.0 * pi));
+    k2a = 0.5 * std::sqrt(15.0 / pi);
+    k2b = 0.25 * std::sqrt(5.0 / pi);
+    k2c = 0.25 * std::sqrt(15.0 / pi);
+    k3a = 0.25 * std::sqrt(35.0 / (2.0 * pi));
+    k3b = 0.5 * std::sqrt(105.0 / pi);
+    k3c = 0.25 * std::sqrt(21.0 / (2.0 * pi));
+    k3d = 0.25 * std::sqrt(7.0 / pi);
+    k3e = 0.25 * std::sqrt(105.0 / pi);
+  }
+};
+const ShConst SHK;
+
+// Y[j] and dY[j][0..2] = dY_j/d(x,y,z) for j < (deg+1)^2, at unit direction d.
+void sh_basis(int deg, const double d[3], double* Y, double (*dY)[3]) {
+  const double x = d[0], y = d[1], z = d[2];
+  const ShConst& k = SHK;
+  auto set = [&](int j, double v, double gx, double gy, double gz) {
+    Y[j] = v;
+    if (dY) { dY[j][0] = gx; dY[j][1] = gy; dY[j][2] = gz; }
+  };
+  set(0, k.k0, 0, 0, 0);
+  if (deg < 1) return;
+  set(1, -k.k1 * y, 0, -k.k1, 0);
+  set(2, k.k1 * z, 0, 0, k.k1);
+  set(3, -k.k1 * x, -k.k1, 0, 0);
+  if (deg < 2) return;
+  set(4, k.k2a * x * y, k.k2a * y, k.k2a * x, 0);
+  set(5, -k.k2a * y * z, 0, -k.k2a * z, -k.k2a * y);
+  set(6, k.k2b * (2 * z * z - x * x - y * y), -2 * k.k2b * x, -2 * k.k2b * y, 4 * k.k2b * z);
+  set(7, -k.k2a * x * z, -k.k2a * z, 0, -k.k2a * x);
+  set(8, k.k2c * (x * x - y * y), 2 * k.k2c * x, -2 * k.k2c * y, 0);
+  if (deg < 3) return;
+  set(9, -k.k3a * y * (3 * x * x - y * y), -6 * k.k3a * x * y, -k.k3a * (3 * x * x - 3 * y * y), 0);
+  set(10, k.k3b * x * y * z, k.k3b * y * z, k.k3b * x * z, k.k3b * x * y);
+  set(11, -k.k3c * y * (4 * z * z - x * x - y * y), 2 * k.k3c * x * y,
+      -k.k3c * (4 * z * z - x * x - 3 * y * y), -8 * k.k3c * y * z);
+  set(12, k.k3d * z * (2 * z * z - 3 * x * x - 3 * y * y), -6 * k.k3d * x * z, -6 * k.k3d * y * z,
+      k.k3d * (6 * z * z - 3 * x * x - 3 * y * y));
+  set(13, -k.k3c * x * (4 * z * z - x * x - y * y), -k.k3c * (4 * z * z - 3 * x * x - y * y),
+      2 * k.k3c * x * y, -8 * k.k3c * x * z);
+  set(14, k.k3e * z * (x * x - y * y), 2 * k.k3e * x * z, -2 * k.k3e * y * z, k.k3e * (x * x - y * y));
+  set(15, -k.k3a * x * (x * x - 3 * y * y), -k.k3a * (3 * x * x - 3 * y * y), 6 * k.k3a * x * y, 0);
+}
+
+// ----------------------------------------------------------------------------
+// Small dense helpers (row-major 3x3).
+// ----------------------------------------------------------------------------
+struct Cam {
+  double R[9], t[3], fx, fy, cx, cy;
+  int W, H;
+};
+
+Cam read_cam(const double* c, int W, int H) {
+  Cam k;
+  for (int i = 0; i < 9; ++i) k.R[i] = c[i];
+  for (int i = 0; i < 3; ++i) k.t[i] = c[9 + i];
+  k.fx = c[12]; k.fy = c[13]; k.cx = c[14]; k.cy = c[15];
+  k.W = W; k.H = H;
+  return k;
+}
+
+// Rotation matrix of a unit quaternion (w, x, y, z).
+void quat_to_rot(const double q[4], double Rq[9]) {
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  Rq[0] = 1 - 2 * (y * y + z * z); Rq[1] = 2 * (x * y - w * z);     Rq[2] = 2 * (x * z + w * y);
+  Rq[3] = 2 * (x * y + w * z);     Rq[4] = 1 - 2 * (x * x + z * z); Rq[5] = 2 * (y * z - w * x);
+  Rq[6] = 2 * (x * z - w * y);     Rq[7] = 2 * (y * z + w * x);     Rq[8] = 1 - 2 * (x * x + y * y);
+}
+
+// d Rq[k] / d q[c] for c = w, x, y, z.
+void quat_to_rot_jac(const double q[4], double dR[9][4]) {
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  const double J[9][4] = {
+      {0, 0, -4 * y, -4 * z},      {-2 * z, 2 * y, 2 * x, -2 * w}, {2 * y, 2 * z, 2 * w, 2 * x},
+      {2 * z, 2 * y, 2 * x, 2 * w}, {0, -4 * x, 0, -4 * z},        {-2 * x, -2 * w, 2 * z, 2 * y},
+      {-2 * y, 2 * z, -2 * w, 2 * x}, {2 * x, 2 * w, 2 * z, 2 * y}, {0, -4 * x, -4 * y, 0}};
+  std::memcpy(dR, J, sizeof(J));
+}
+
+// Forward quantities of one Gaussian under one camera, kept for the backward.
+struct Proj {
+  double tcam[3];        // camera-space mean
+  double qn[4], qnorm;   // normalised quaternion, norm of the raw one
+  double Rq[9];          // rotation of the Gaussian
+  double s[3];           // scales
+  double Sigma[9];       // 3D covariance
+  double rho[2];         // clamped tx/tz, ty/tz
+  bool clampx, clampy;
+  double T[6];           // 2x3 J*W
+  double a, b, c;        // low-passed 2D covariance
+  double det;
+  double con[3];         // conic (inverse covariance) entries 00, 01, 11
+  double u, v;           // mean2D
+  double lambda, radius;
+  int rect[4];           // x0 y0 x1 y1 (tiles, half-open)
+  int tc;
+  bool visible;
+  double dir[3], dirnorm;  // unit view direction and distance
+  double raw[3], colour[3];
+  double Y[16];
+  bool guard;
+};
+
+// Is x within tol of an integer?
+bool near_int(double x, double tol) { return std::fabs(x - std::nearbyint(x)) <= tol; }
+
+// Projection of Gaussian i (Listing "XPR-3DGS", project).
+void project_one(int64_t i, int64_t n, const double* means, const double* scales,
+                 const double* quats, const double* opac, const double* sh, int K,
+                 const Cam& cam, const double* cfg, int tile_w, int tile_h, int deg, Proj& P) {
+  const double lowpass = cfg[0], alpha_min = cfg[1], z_near = cfg[2], fov_clip = cfg[3];
+  const int tiles_x = (cam.W + tile_w - 1) / tile_w;
+  const int tiles_y = (cam.H + tile_h - 1) / tile_h;
+  std::memset(&P, 0, sizeof(P));
+  const double mu[3] = {means[i], means[n + i], means[2 * n + i]};
+  // world -> camera
+  for (int r = 0; r < 3; ++r)
+    P.tcam[r] = cam.R[3 * r] * mu[0] + cam.R[3 * r + 1] * mu[1] + cam.R[3 * r + 2] * mu[2] + cam.t[r];
+  const double tx = P.tcam[0], ty = P.tcam[1], tz = P.tcam[2];
+  const double o = opac[i];
+  // 3D covariance Sigma = Rq S S^T Rq^T from the normalised quaternion.
+  const double q[4] = {quats[i], quats[n + i], quats[2 * n + i], quats[3 * n + i]};
+  P.qnorm = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  for (int c = 0; c < 4; ++c) P.qn[c] = q[c] / P.qnorm;
+  quat_to_rot(P.qn, P.Rq);
+  for (int c = 0; c < 3; ++c) P.s[c] = scales[c * n + i];
+  double M[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) M[3 * r + c] = P.Rq[3 * r + c] * P.s[c];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      P.Sigma[3 * r + c] = M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1] + M[3 * r + 2] * M[3 * c + 2];
+
+  bool in_front = tz > z_near;
+  P.guard = std::fabs(tz - z_near) <= 1e-6 * std::max(1.0, std::fabs(z_near)) ||
+            std::fabs(o - alpha_min) <= 1e-6 * alpha_min;
+  if (in_front) {
+    // EWA: J (perspective Jacobian at the clamped direction) times W.
+    const double limx = fov_clip * cam.W / (2.0 * cam.fx);
+    const double limy = fov_clip * cam.H / (2.0 * cam.fy);
+    double rx = tx / tz, ry = ty / tz;
+    if (fov_clip > 0) {
+      P.clampx = rx < -limx || rx > limx;
+      P.clampy = ry < -limy || ry > limy;
+      rx = std::min(limx, std::max(-limx, rx));
+      ry = std::min(limy, std::max(-limy, ry));
+    }
+    P.rho[0] = rx; P.rho[1] = ry;
+    const double J[6] = {cam.fx / tz, 0, -cam.fx * rx / tz, 0, cam.fy / tz, -cam.fy * ry / tz};
+    for (int r = 0; r < 2; ++r)
+      for (int c = 0; c < 3; ++c)
+        P.T[3 * r + c] = J[3 * r] * cam.R[c] + J[3 * r + 1] * cam.R[3 + c] + J[3 * r + 2] * cam.R[6 + c];
+    // cov2D = T Sigma T^T + lowpass I
+    double ST0[3], ST1[3];
+    for (int r = 0; r < 3; ++r) {
+      ST0[r] = P.Sigma[3 * r] * P.T[0] + P.Sigma[3 * r + 1] * P.T[1] + P.Sigma[3 * r + 2] * P.T[2];
+      ST1[r] = P.Sigma[3 * r] * P.T[3] + P.Sigma[3 * r + 1] * P.T[4] + P.Sigma[3 * r + 2] * P.T[5];
+    }
+    P.a = P.T[0] * ST0[0] + P.T[1] * ST0[1] + P.T[2] * ST0[2] + lowpass;
+    P.b = P.T[0] * ST1[0] + P.T[1] * ST1[1] + P.T[2] * ST1[2];
+    P.c = P.T[3] * ST1[0] + P.T[4] * ST1[1] + P.T[5] * ST1[2] + lowpass;
+    P.det = P.a * P.c - P.b * P.b;
+    if (std::fabs(P.det) <= 1e-6 * P.a * P.c) P.guard = true;
+    if (P.det > 0) {
+      P.con[0] = P.c / P.det;
+      P.con[1] = -P.b / P.det;
+      P.con[2] = P.a / P.det;
+    }
+    // mean2D: pixel (i, j) is sampled at (i, j), so the continuous image
+    // point f*X/Z + c is shifted by one half pixel.
+    P.u = cam.fx * tx / tz + cam.cx - 0.5;
+    P.v = cam.fy * ty / tz + cam.cy - 0.5;
+    // 3-sigma radius of the largest eigenvalue.
+    const double mid = 0.5 * (P.a + P.c);
+    P.lambda = mid + std::sqrt(std::max(0.0, mid * mid - P.det));
+    const double r3 = 3.0 * std::sqrt(P.lambda);
+    P.radius = std::ceil(r3);
+    // Tile-space bounding box, half-open: covers every pixel sample within
+    // the L-infinity box of half-width r around mean2D.
+    const double r = P.radius;
+    const double fx0 = (P.u - r) / tile_w, fx1 = (P.u + r) / tile_w;
+    const double fy0 = (P.v - r) / tile_h, fy1 = (P.v + r) / tile_h;
+    auto clampi = [](double x, int lo, int hi) {
+      return (int)std::min<double>(hi, std::max<double>(lo, x));
+    };
+    P.rect[0] = clampi(std::floor(fx0), 0, tiles_x);
+    P.rect[1] = clampi(std::floor(fy0), 0, tiles_y);
+    P.rect[2] = clampi(std::floor(fx1) + 1, 0, tiles_x);
+    P.rect[3] = clampi(std::floor(fy1) + 1, 0, tiles_y);
+    P.tc = (P.rect[2] - P.rect[0]) * (P.rect[3] - P.rect[1]);
+    const double g = 1e-5;
+    if (near_int(r3, g * std::max(1.0, r3)) || near_int(fx0, g * std::max(1.0, std::fabs(fx0))) ||
+        near_int(fx1, g * std::max(1.0, std::fabs(fx1))) ||
+        near_int(fy0, g * std::max(1.0, std::fabs(fy0))) ||
+        near_int(fy1, g * std::max(1.0, std::fabs(fy1))))
+      P.guard = true;
+  }
+  P.visible = in_front && P.det > 0 && o >= alpha_min && P.radius > 0 && P.tc > 0;
+  if (!P.visible) P.tc = 0;
+
+  // View-dependent colour from the SH coefficients.
+  const double cp[3] = {
+      -(cam.R[0] * cam.t[0] + cam.R[3] * cam.t[1] + cam.R[6] * cam.t[2]),
+      -(cam.R[1] * cam.t[0] + cam.R[4] * cam.t[1] + cam.R[7] * cam.t[2]),
+      -(cam.R[2] * cam.t[0] + cam.R[5] * cam.t[1] + cam.R[8] * cam.t[2])};
+  double dv[3] = {mu[0] - cp[0], mu[1] - cp[1], mu[2] - cp[2]};
+  P.dirnorm = std::sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+  for (int c = 0; c < 3; ++c) P.dir[c] = dv[c] / P.dirnorm;
+  sh_basis(deg, P.dir, P.Y, nullptr);
+  const int nb = (deg + 1) * (deg + 1);
+  for (int ch = 0; ch < 3; ++ch) {
+    double acc = 0.5;
+    for (int j = 0; j < nb; ++j) acc += sh[(int64_t)(j * 3 + ch) * n + i] * P.Y[j];
+    P.raw[ch] = acc;
+    P.colour[ch] = std::max(0.0, acc);
+  }
+  (void)K;
+}
+
+}  // namespace
+
+extern "C" {
+
+int orc_version(void) { return 1; }
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+// Real SH basis values (and gradients w.r.t. the direction if dY != NULL) at
+// a unit direction d. Y has (deg+1)^2 entries, dY 3 per entry.
+void orc_sh_basis(int deg, const double* d, double* Y, double* dY) {
+  double dYl[16][3];
+  sh_basis(deg, d, Y, dY ? dYl : nullptr);
+  if (dY)
+    for (int j = 0; j < (deg + 1) * (deg + 1); ++j)
+      for (int c = 0; c < 3; ++c) dY[3 * j + c] = dYl[j][c];
+}
+
+// Projection of n Gaussians (Listing "XPR-3DGS", project).
+//   means [3][n], scales [3][n], quats [4][n], opac [n], sh [K][3][n]
+//   cam: R (9, row-major world->camera), t (3), fx, fy, cx, cy
+//   cfg: lowpass, alpha_min, z_near, fov_clip
+// Outputs (any may be NULL):
+//   rec [n][9]: u, v, -0.5*con00, -con01, -0.5*con11, o, r, g, b (shader data)
+//   cov [n][3]: a, b, c of the low-passed 2D covariance
+//   depth [n], rect [n][4] (x0, y0, x1, y1), tc [n], radius [n], guard [n]
+void orc_project(int64_t n, const double* means, const double* scales, const double* quats,
+                 const double* opac, const double* sh, int K, const double* camv, int W, int H,
+                 const double* cfg, int tile_w, int tile_h, int deg, double* rec, double* cov,
+                 double* depth, int32_t* rect, int32_t* tc, int32_t* radius, uint8_t* guard) {
+  const Cam cam = read_cam(camv, W, H);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    Proj P;
+    project_one(i, n, means, scales, quats, opac, sh, K, cam, cfg, tile_w, tile_h, deg, P);
+    if (rec) {
+      double* r = rec + 9 * i;
+      r[0] = P.u; r[1] = P.v;
+      r[2] = -0.5 * P.con[0]; r[3] = -P.con[1]; r[4] = -0.5 * P.con[2];
+      r[5] = opac[i];
+      r[6] = P.colour[0]; r[7] = P.colour[1]; r[8] = P.colour[2];
+    }
+    if (cov) { cov[3 * i] = P.a; cov[3 * i + 1] = P.b; cov[3 * i + 2] = P.c; }
+    if (depth) depth[i] = P.tcam[2];
+    if (rect) for (int c = 0; c < 4; ++c) rect[4 * i + c] = P.rect[c];
+    if (tc) tc[i] = P.tc;
+    if (radius) radius[i] = (int32_t)P.radius;
+    if (guard) guard[i] = P.guard ? 1 : 0;
+  }
+}
+
+// Binning (section "Rasterizer"): prefix sum of the tile counts, replicate,
+// tile id per replicated entry, sort by (tile id, depth) with ties to the
+// lower Gaussian index, per-tile [start, end).
+//   depth [n] (sorted on the float32 value of each entry), rect [n][4], tc [n]
+//   offsets [n] (exclusive prefix sum of tc, may be NULL)
+//   keys [cap]: tile << 32 | float32 bits of depth (may be NULL)
+//   vals [cap]: Gaussian index, ranges [tiles_x*tiles_y][2]
+// Returns I = sum tc; writes the lists only when I <= cap.
+int64_t orc_bin(int64_t n, const double* depth, const int32_t* rect, const int32_t* tc,
+                int tiles_x, int tiles_y, int64_t cap, int64_t* offsets, uint64_t* keys,
+                int32_t* vals, int32_t* ranges) {
+  std::vector<int64_t> off(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) off[i + 1] = off[i] + tc[i];
+  const int64_t I = off[n];
+  if (offsets) for (int64_t i = 0; i < n; ++i) offsets[i] = off[i];
+  if (I > cap) return I;
+  struct Pair { uint32_t tile; float depth; int32_t idx; };
+  std::vector<Pair> pairs(I);
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int64_t i = 0; i < n; ++i) {
+    const int x0 = rect[4 * i], y0 = rect[4 * i + 1], x1 = rect[4 * i + 2];
+    const int w = x1 - x0;
+    for (int64_t r = 0; r < tc[i]; ++r) {
+      const int x = x0 + (int)(r % w);
+      const int y = y0 + (int)(r / w);
+      pairs[off[i] + r] = Pair{(uint32_t)(y * tiles_x + x), (float)depth[i], (int32_t)i};
+    }
+  }
+  auto less = [](const Pair& p, const Pair& q) {
+    if (p.tile != q.tile) return p.tile < q.tile;
+    if (p.depth != q.depth) return p.depth < q.depth;
+    return p.idx < q.idx;
+  };
+#ifdef _OPENMP
+  __gnu_parallel::sort(pairs.begin(), pairs.end(), less);
+#else
+  std::sort(pairs.begin(), pairs.end(), less);
+#endif
+  const int64_t T = (int64_t)tiles_x * tiles_y;
+  for (int64_t t = 0; t < 2 * T; ++t) ranges[t] = 0;
+  for (int64_t k = 0; k < I; ++k) {
+    const Pair& p = pairs[k];
+    if (keys) {
+      uint32_t bits;
+      std::memcpy(&bits, &p.depth, 4);
+      keys[k] = ((uint64_t)p.tile << 32) | bits;
+    }
+    vals[k] = p.idx;
+    if (k == 0 || pairs[k - 1].tile != p.tile) ranges[2 * p.tile] = (int32_t)k;
+    if (k == I - 1 || pairs[k + 1].tile != p.tile) ranges[2 * p.tile + 1] = (int32_t)(k + 1);
+  }
+  return I;
+}
+
+// Forward compositing (Algorithm 1 with the 3DGS evaluate): for pixel (x, y)
+// of tile t, walk the tile's list front to back:
+//   P = A dx^2 + B dx dy + C dy^2 with dx = x - u, dy = y - v (shader data)
+//   skip if P > 0; alpha = min(alpha_max, o e^P); skip if alpha < alpha_min;
+//   stop (without blending) if T (1 - alpha) < t_min; else C += c alpha T,
+//   T *= 1 - alpha.
+// Output C + T bg.
+//   rec [n][9], vals, ranges as produced by orc_bin
+//   cfg: alpha_min, alpha_max, t_min, bg0, bg1, bg2
+//   img [3][H][W], Tfinal [H][W], ncontrib [H][W] (1-based position of the
+//   last blended entry, 0 if none), nblend [H][W] (number blended),
+//   guard [H][W] (1 where a decision sits within the guard band; may be NULL)
+void orc_render_fwd(int W, int H, int tile_w, int tile_h, const double* rec, const int32_t* vals,
+                    const int32_t* ranges, const double* cfg, double* img, double* Tfinal,
+                    int32_t* ncontrib, int32_t* nblend, uint8_t* guard) {
+  const double alpha_min = cfg[0], alpha_max = cfg[1], t_min = cfg[2];
+  const double bg[3] = {cfg[3], cfg[4], cfg[5]};
+  const int tiles_x = (W + tile_w - 1) / tile_w;
+  const int tiles_y = (H + tile_h - 1) / tile_h;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int t = 0; t < tiles_x * tiles_y; ++t) {
+    const int tx = t % tiles_x, ty = t / tiles_x;
+    const int32_t start = ranges[2 * t], end = ranges[2 * t + 1];
+    for (int py = ty * tile_h; py < std::min(H, (ty + 1) * tile_h); ++py)
+      for (int px = tx * tile_w; px < std::min(W, (tx + 1) * tile_w); ++px) {
+        double T = 1.0, C[3] = {0, 0, 0};
+        int32_t last = 0, count = 0;
+        bool g = false;
+        for (int32_t k = start; k < end; ++k) {
+          const double* r = rec + 9 * (int64_t)vals[k];
+          const double dx = px - r[0], dy = py - r[1];
+          const double P = r[2] * dx * dx + r[3] * dx * dy + r[4] * dy * dy;
+          if (std::fabs(P) <= 1e-6) g = true;
+          if (P > 0) continue;
+          const double alpha = std::min(alpha_max, r[5] * std::exp(P));
+          if (std::fabs(alpha - alpha_min) <= 1e-4 * alpha_min) g = true;
+          if (alpha < alpha_min) continue;
+          const double Tn = T * (1.0 - alpha);
+          if (std::fabs(Tn - t_min) <= 1e-3 * t_min) g = true;
+          if (Tn < t_min) break;
+          for (int c = 0; c < 3; ++c) C[c] += r[6 + c] * alpha * T;
+          T = Tn;
+          last = k - start + 1;
+          ++count;
+        }
+        const int64_t p = (int64_t)py * W + px;
+        for (int c = 0; c < 3; ++c) img[(int64_t)c * W * H + p] = C[c] + T * bg[c];
+        if (Tfinal) Tfinal[p] = T;
+        if (ncontrib) ncontrib[p] = last;
+        if (nblend) nblend[p] = count;
+        if (guard) guard[p] = g ? 1 : 0;
+      }
+  }
+}
+
+// Backward of the compositing: given dL/dimg [3][H][W], the derivative of
+// L with respect to each Gaussian's shader data, summed over pixels:
+//   grad [n][9] = dL/d(u, v, A, B, C, o, r, g, b), A = -0.5 con00,
+//   B = -con01, C = -0.5 con11.
+// Each pixel re-runs its forward walk and then differentiates
+//   C = sum_i c_i a_i T_i + T_final bg, T_i = prod_{j<i} (1 - a_j)
+// in reverse order. grad is overwritten.
+void orc_render_bwd(int W, int H, int tile_w, int tile_h, int64_t n, const double* rec,
+                    const int32_t* vals, const int32_t* ranges, const double* cfg,
+                    const double* dimg, double* grad) {
+  const double alpha_min = cfg[0], alpha_max = cfg[1], t_min = cfg[2];
+  const double bg[3] = {cfg[3], cfg[4], cfg[5]};
+  const int tiles_x = (W + tile_w - 1) / tile_w;
+  const int tiles_y = (H + tile_h - 1) / tile_h;
+  int nthreads = 1;
+#ifdef _OPENMP
+  nthreads = omp_get_max_threads();
+#endif
+  std::vector<std::vector<double>> part(nthreads);
+#pragma omp parallel
+  {
+    int tid = 0;
+#ifdef _OPENMP
+    tid = omp_get_thread_num();
+#endif
+    std::vector<double>& acc = part[tid];
+    acc.assign((size_t)n * 9, 0.0);
+    struct Step { int64_t g; double alpha, T, eP, dx, dy; bool clamped; };
+    std::vector<Step> steps;
+#pragma omp for schedule(dynamic, 1)
+    for (int t = 0; t < tiles_x * tiles_y; ++t) {
+      const int tx = t % tiles_x, ty = t / tiles_x;
+      const int32_t start = ranges[2 * t], end = ranges[2 * t + 1];
+      for (int py = ty * tile_h; py < std::min(H, (ty + 1) * tile_h); ++py)
+        for (int px = tx * tile_w; px < std::min(W, (tx + 1) * tile_w); ++px) {
+          steps.clear();
+          double T = 1.0;
+          for (int32_t k = start; k < end; ++k) {
+            const int64_t gi = vals[k];
+            const double* r = rec + 9 * gi;
+            const double dx = px - r[0], dy = py - r[1];
+            const double P = r[2] * dx * dx + r[3] * dx * dy + r[4] * dy * dy;
+            if (P > 0) continue;
+            const double eP = std::exp(P);
+            const double raw = r[5] * eP;
+            const double alpha = std::min(alpha_max, raw);
+            if (alpha < alpha_min) continue;
+            const double Tn = T * (1.0 - alpha);
+            if (Tn < t_min) break;
+            steps.push_back(Step{gi, alpha, T, eP, dx, dy, raw > alpha_max});
+            T = Tn;
+          }
+          const double Tfin = T;
+          const int64_t p = (int64_t)py * W + px;
+          const double G[3] = {dimg[p], dimg[(int64_t)W * H + p], dimg[2 * (int64_t)W * H + p]};
+          const double bgG = bg[0] * G[0] + bg[1] * G[1] + bg[2] * G[2];
+          double S[3] = {0, 0, 0};  // colour behind, normalised by the transmittance
+          for (int s = (int)steps.size() - 1; s >= 0; --s) {
+            const Step& st = steps[s];
+            const double* r = rec + 9 * st.g;
+            double* ga = acc.data() + 9 * st.g;
+            double dalpha = 0;
+            for (int c = 0; c < 3; ++c) {
+              ga[6 + c] += st.alpha * st.T * G[c];
+              dalpha += st.T * (r[6 + c] - S[c]) * G[c];
+            }
+            dalpha -= Tfin * bgG / (1.0 - st.alpha);
+            for (int c = 0; c < 3; ++c) S[c] = st.alpha * r[6 + c] + (1.0 - st.alpha) * S[c];
+            if (st.clamped) continue;
+            const double dP = st.alpha * dalpha;   // alpha = o e^P
+            ga[5] += st.eP * dalpha;
+            const double A = r[2], B = r[3], Cc = r[4];
+            ga[0] += dP * (-(2 * A * st.dx + B * st.dy));
+            ga[1] += dP * (-(2 * Cc * st.dy + B * st.dx));
+            ga[2] += dP * st.dx * st.dx;
+            ga[3] += dP * st.dx * st.dy;
+            ga[4] += dP * st.dy * st.dy;
+          }
+        }
+    }
+  }
+  for (int64_t k = 0; k < n * 9; ++k) {
+    double s = 0;
+    for (int th = 0; th < nthreads; ++th)
+      if (!part[th].empty()) s += part[th][k];
+    grad[k] = s;
+  }
+}
+
+// Backward of the projection: from dL/d(shader data) [n][9] to the gradient
+// of L with respect to the inputs (activated scales and opacity, raw
+// quaternion). Outputs are [k][n] like the inputs and are overwritten.
+void orc_project_bwd(int64_t n, const double* means, const double* scales, const double* quats,
+                     const double* opac, const double* sh, int K, const double* camv, int W, int H,
+                     const double* cfg, int tile_w, int tile_h, int deg, const double* grad,
+                     double* g_means, double* g_scales, double* g_quats, double* g_opac,
+                     double* g_sh) {
+  const Cam cam = read_cam(camv, W, H);
+  const int nb = (deg + 1) * (deg + 1);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    for (int c = 0; c < 3; ++c) { g_means[c * n + i] = 0; g_scales[c * n + i] = 0; }
+    for (int c = 0; c < 4; ++c) g_quats[c * n + i] = 0;
+    g_opac[i] = 0;
+    for (int j = 0; j < K; ++j)
+      for (int ch = 0; ch < 3; ++ch) g_sh[(int64_t)(j * 3 + ch) * n + i] = 0;
+    Proj P;
+    project_one(i, n, means, scales, quats, opac, sh, K, cam, cfg, tile_w, tile_h, deg, P);
+    if (!P.visible) continue;
+    const double* g = grad + 9 * i;
+    double gmu[3] = {0, 0, 0};
+
+    // Colour: colour = max(0, 0.5 + sum_j sh_j Y_j(dir)), dir = (mu - campos)/|.|
+    double Y[16], dY[16][3];
+    sh_basis(deg, P.dir, Y, dY);
+    double graw[3];
+    for (int ch = 0; ch < 3; ++ch) graw[ch] = P.raw[ch] > 0 ? g[6 + ch] : 0.0;
+    double gdir[3] = {0, 0, 0};
+    for (int j = 0; j < nb; ++j)
+      for (int ch = 0; ch < 3; ++ch) {
+        g_sh[(int64_t)(j * 3 + ch) * n + i] = Y[j] * graw[ch];
+        const double w = sh[(int64_t)(j * 3 + ch) * n + i] * graw[ch];
+        for (int c = 0; c < 3; ++c) gdir[c] += w * dY[j][c];
+      }
+    const double dd = P.dir[0] * gdir[0] + P.dir[1] * gdir[1] + P.dir[2] * gdir[2];
+    for (int c = 0; c < 3; ++c) gmu[c] += (gdir[c] - P.dir[c] * dd) / P.dirnorm;
+
+    // Opacity.
+    g_opac[i] = g[5];
+
+    // Conic entries from the shader data A = -0.5 con00, B = -con01, C = -0.5 con11.
+    const double gk00 = -0.5 * g[2], gk01 = -g[3], gk11 = -0.5 * g[4];
+    // con00 = c/det, con01 = -b/det, con11 = a/det, det = a c - b^2.
+    const double a = P.a, b = P.b, c = P.c, d2 = P.det * P.det;
+    const double ga = gk00 * (-c * c / d2) + gk01 * (b * c / d2) + gk11 * (-b * b / d2);
+    const double gb = gk00 * (2 * b * c / d2) + gk01 * (-(a * c + b * b) / d2) + gk11 * (2 * a * b / d2);
+    const double gc = gk00 * (-b * b / d2) + gk01 * (a * b / d2) + gk11 * (-a * a / d2);
+
+    // cov2D entries a = T0 Sigma T0^T, b = T0 Sigma T1^T, c = T1 Sigma T1^T.
+    const double* T0 = P.T;
+    const double* T1 = P.T + 3;
+    double gSigma[9];
+    for (int r = 0; r < 3; ++r)
+      for (int s = 0; s < 3; ++s)
+        gSigma[3 * r + s] = ga * T0[r] * T0[s] + gb * T0[r] * T1[s] + gc * T1[r] * T1[s];
+    double ST0[3], ST1[3];
+    for (int r = 0; r < 3; ++r) {
+      ST0[r] = P.Sigma[3 * r] * T0[0] + P.Sigma[3 * r + 1] * T0[1] + P.Sigma[3 * r + 2] * T0[2];
+      ST1[r] = P.Sigma[3 * r] * T1[0] + P.Sigma[3 * r + 1] * T1[1] + P.Sigma[3 * r + 2] * T1[2];
+    }
+    double gT[6];
+    for (int r = 0; r < 3; ++r) {
+      gT[r] = 2 * ga * ST0[r] + gb * ST1[r];
+      gT[3 + r] = gb * ST0[r] + 2 * gc * ST1[r];
+    }
+    // T = J W  ->  dL/dJ = dL/dT W^T
+    double gJ[6];
+    for (int r = 0; r < 2; ++r)
+      for (int s = 0; s < 3; ++s)
+        gJ[3 * r + s] = gT[3 * r] * cam.R[3 * s] + gT[3 * r + 1] * cam.R[3 * s + 1] +
+                        gT[3 * r + 2] * cam.R[3 * s + 2];
+    // J00 = fx/tz, J02 = -fx rho_x/tz, J11 = fy/tz, J12 = -fy rho_y/tz
+    const double tx = P.tcam[0], ty = P.tcam[1], tz = P.tcam[2];
+    double gt[3] = {0, 0, 0};
+    gt[2] += gJ[0] * (-cam.fx / (tz * tz)) + gJ[2] * (cam.fx * P.rho[0] / (tz * tz)) +
+             gJ[4] * (-cam.fy / (tz * tz)) + gJ[5] * (cam.fy * P.rho[1] / (tz * tz));
+    const double grx = gJ[2] * (-cam.fx / tz), gry = gJ[5] * (-cam.fy / tz);
+    if (!P.clampx) { gt[0] += grx / tz; gt[2] += grx * (-tx / (tz * tz)); }
+    if (!P.clampy) { gt[1] += gry / tz; gt[2] += gry * (-ty / (tz * tz)); }
+    // mean2D
+    gt[0] += g[0] * cam.fx / tz;
+    gt[2] += g[0] * (-cam.fx * tx / (tz * tz));
+    gt[1] += g[1] * cam.fy / tz;
+    gt[2] += g[1] * (-cam.fy * ty / (tz * tz));
+    // t = W mu + t_w
+    for (int c = 0; c < 3; ++c)
+      gmu[c] += cam.R[c] * gt[0] + cam.R[3 + c] * gt[1] + cam.R[6 + c] * gt[2];
+    for (int c = 0; c < 3; ++c) g_means[c * n + i] = gmu[c];
+
+    // Sigma = M M^T, M = Rq S:  dL/dM = (G + G^T) M
+    double M[9];
+    for (int r = 0; r < 3; ++r)
+      for (int s = 0; s < 3; ++s) M[3 * r + s] = P.Rq[3 * r + s] * P.s[s];
+    double gM[9];
+    for (int r = 0; r < 3; ++r)
+      for (int s = 0; s < 3; ++s) {
+        double acc = 0;
+        for (int k = 0; k < 3; ++k) acc += (gSigma[3 * r + k] + gSigma[3 * k + r]) * M[3 * k + s];
+        gM[3 * r + s] = acc;
+      }
+    double gR[9];
+    for (int s = 0; s < 3; ++s) {
+      double acc = 0;
+      for (int r = 0; r < 3; ++r) {
+        acc += gM[3 * r + s] * P.Rq[3 * r + s];
+        gR[3 * r + s] = gM[3 * r + s] * P.s[s];
+      }
+      g_scales[s * n + i] = acc;
+    }
+    double dR[9][4];
+    quat_to_rot_jac(P.qn, dR);
+    double gqn[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 9; ++k)
+      for (int c = 0; c < 4; ++c) gqn[c] += gR[k] * dR[k][c];
+    const double qd = P.qn[0] * gqn[0] + P.qn[1] * gqn[1] + P.qn[2] * gqn[2] + P.qn[3] * gqn[3];
+    for (int c = 0; c < 4; ++c) g_quats[c * n + i] = (gqn[c] - P.qn[c] * qd) / P.qnorm;
+  }
+}
+
+}  // extern "C"
