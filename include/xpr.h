@@ -1,0 +1,234 @@
+/*
+ * xpr.h - C-ABI of the MI355X (gfx950) tile-splatting hot path for 3D
+ * Gaussians: projection, binning (count, prefix sum, duplicate, radix sort,
+ * tile ranges), compositing forward and compositing + projection backward.
+ *
+ * The operations follow the paper "XPR: An Extensible Cross-Platform
+ * Point-Based Differentiable Renderer" (arxiv 2606.11529):
+ *   - Background section: the 3DGS primitive (mean, covariance R S S^T R^T,
+ *     opacity, SH colour) and alpha blending c = sum_i c_i a_i T_i with
+ *     T_i = prod_{j<i} (1 - a_j), ending on low transmittance;
+ *   - Listing "Implementation of XPR-3DGS" (functions project and evaluate);
+ *   - section "Rasterizer" (replicate by prefix sum, tile id, sort by
+ *     (tile id, depth), segment bounds);
+ *   - section "Shader", Algorithm 1 (per-pixel front-to-back loop over the
+ *     tile's depth-sorted list in batches, exit checks at batch boundaries).
+ *
+ * Conventions common to every entry point
+ * ---------------------------------------
+ * - All pointers named as device buffers are device memory of the current
+ *   HIP device; every call only enqueues work on `stream` and returns.
+ *   Host structs (xpr_views, xpr_config and what they point to) are read
+ *   during the call only. The library never allocates device memory: the
+ *   caller passes buffers, including the workspaces sized by the
+ *   *_workspace queries.
+ * - A batch is described by xpr_views: n_views cameras, each rendering one of
+ *   n_scenes scenes (view_scene[v]). Per-view buffers are concatenated over
+ *   views in view order:
+ *     records  (projection outputs): view v starts at R_v = sum_{u<v} n(scene(u))
+ *     tiles    (tile ranges):        view v starts at G_v = sum_{u<v} tx_u * ty_u
+ *              with tx = ceil(W / tile_w), ty = ceil(H / tile_h), row-major
+ *     pixels   (T_final, n_contrib): view v starts at X_v = sum_{u<v} W_u H_u,
+ *              row-major [H][W]
+ *     images   (image, dL/dimage):   view v starts at 3 X_v, planar [3][H][W]
+ * - Errors: arguments are checked on the host before anything is enqueued
+ *   (XPR_ERR_INVALID_ARG, nothing launched); a failed launch returns
+ *   XPR_ERR_HIP. xpr_last_error() returns a thread-local message for the last
+ *   non-OK status. No C++ exception crosses this interface.
+ */
+#ifndef XPR_H
+#define XPR_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define XPR_VERSION 1
+#define XPR_MAX_VIEWS 32  /* views per call */
+#define XPR_MAX_SCENES 8  /* scenes per call */
+
+typedef enum {
+  XPR_OK = 0,
+  XPR_ERR_INVALID_ARG = 1,
+  XPR_ERR_CAPACITY = 2,   /* more tile-Gaussian pairs than isect_capacity */
+  XPR_ERR_HIP = 3,
+  XPR_ERR_UNSUPPORTED = 4
+} xpr_status;
+
+/* Sort strategies of xpr_bin_sort; both produce the identical list. */
+#define XPR_SORT_PRESORT 0 /* sort Gaussians by depth, then pairs by tile */
+#define XPR_SORT_FULL 1    /* one radix sort of 64-bit (tile, depth) keys */
+
+/* Pinhole camera, world -> camera x_c = R x_w + t (R row-major), camera axes
+ * x right, y down, z forward. (cx, cy) is the principal point in continuous
+ * pixel coordinates; pixel (i, j) is sampled at (i, j) + 0.5. The camera
+ * "view" of the paper's project(p, cam, view). */
+typedef struct xpr_camera {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t width, height; /* 1 .. 16384 */
+} xpr_camera;
+
+/* Method constants and tuning knobs. Defaults: xpr_config_default(). */
+typedef struct xpr_config {
+  int32_t tile_w, tile_h; /* 8x8 or 16x16 */
+  int32_t lds_batch;      /* Gaussians staged per LDS batch: 64,128,256,512 */
+  int32_t sh_degree;      /* 0..3 */
+  float lowpass;          /* added to both diagonal entries of cov2D (0.3) */
+  float alpha_min;        /* alpha_thresh of the listing (1/255) */
+  float alpha_max;        /* alpha clamp (0.99) */
+  float t_min;            /* stop before blending when T (1 - a) < t_min (1e-4) */
+  float z_near;           /* cull when camera-space z <= z_near (> 0; 0.2) */
+  float fov_clip;         /* Jacobian clamp at fov_clip * W / (2 fx) (1.3; 0 = off) */
+  float bg[3];            /* background colour (0, 0, 0) */
+  int32_t sort_mode;      /* XPR_SORT_PRESORT or XPR_SORT_FULL */
+  int32_t no_sync;        /* 1: never read back to the host (graph capture) */
+} xpr_config;
+
+/* One scene of n Gaussians, structure of arrays with leading dimension ld:
+ *   means [3][ld], scales [3][ld] (activated, > 0), quats [4][ld] (w,x,y,z,
+ *   any non-zero norm, normalised inside), opacities [ld] (activated, in
+ *   (0,1)), sh [sh_coeffs][3][ld] (coefficient-major, RGB inner), with
+ *   sh_coeffs >= (sh_degree+1)^2. Device memory, read only. The paper's
+ *   PrimitiveParams (mu, s, q, sh, o). */
+typedef struct xpr_scene {
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* opacities;
+  const float* sh;
+  int64_t n;  /* 0 .. 2^31-1 */
+  int64_t ld; /* >= n */
+  int32_t sh_coeffs;
+} xpr_scene;
+
+/* Gradient buffers of one scene, same layout (ld, sh_coeffs) as xpr_scene;
+ * gradients are with respect to the activated scales and opacities and the
+ * raw (unnormalised) quaternion. */
+typedef struct xpr_scene_grad {
+  float* means;
+  float* scales;
+  float* quats;
+  float* opacities;
+  float* sh;
+} xpr_scene_grad;
+
+typedef struct xpr_views {
+  const xpr_scene* scenes;   /* host array [n_scenes] */
+  int32_t n_scenes;          /* 1 .. XPR_MAX_SCENES */
+  const xpr_camera* cams;    /* host array [n_views] */
+  const int32_t* view_scene; /* host array [n_views], values < n_scenes */
+  int32_t n_views;           /* 1 .. XPR_MAX_VIEWS */
+} xpr_views;
+
+/* Per-record projection outputs (device buffers, concatenated over views,
+ * one record per (view, Gaussian)). The paper's ProjectResult:
+ *   splat [total][12] float: u, v, A, B | C, o, r, g | b, 0, 0, 0 where
+ *         (u, v) is mean2D and A = -0.5 con00, B = -con01, C = -0.5 con11
+ *         the scaled conic (the listing's shader data), (r, g, b) the colour
+ *   depth [total] float: camera-space z
+ *   rect  [total][4] int16: tile-space box x0, y0, x1, y1 (half-open)
+ *   tiles_touched [total] int32: (x1-x0)(y1-y0) if visible else 0 */
+typedef struct xpr_projected {
+  float* splat;
+  float* depth;
+  int16_t* rect;
+  int32_t* tiles_touched;
+} xpr_projected;
+
+/* Sizes of a batch: records, tiles and pixels over all views. */
+typedef struct xpr_sizes {
+  int64_t records, tiles, pixels;
+  int32_t tile_bits; /* bits needed for a global tile id */
+} xpr_sizes;
+
+/* Fills *cfg with the defaults listed in xpr_config. */
+void xpr_config_default(xpr_config* cfg);
+
+/* Sizes of the concatenated buffers of a batch (host only). */
+xpr_status xpr_batch_sizes(const xpr_views* views, const xpr_config* cfg, xpr_sizes* out);
+
+/* Projection (listing XPR-3DGS, project), one record per (view, Gaussian):
+ * world->camera; 3D covariance from the normalised quaternion and scales;
+ * EWA 2D covariance J W Sigma W^T J^T + lowpass I with J the perspective
+ * Jacobian at the clamped direction; conic = inverse; mean2D = f X/Z + c - 1/2;
+ * radius ceil(3 sqrt(lambda_max)); tile rect [floor((u-r)/tw),
+ * floor((u+r)/tw)+1) clamped to the grid (likewise v); visibility
+ * det > 0, o >= alpha_min, r > 0, area > 0, z > z_near; colour
+ * max(0, 0.5 + sum_lm sh_lm Y_lm(dir)) with the real SH basis (Condon-Shortley
+ * phase) and dir = (mu - campos) / |mu - campos|. Writes every field of
+ * *out for all records (invisible: tiles_touched = 0). */
+xpr_status xpr_project(const xpr_views* views, const xpr_config* cfg, const xpr_projected* out,
+                       hipStream_t stream);
+
+/* Workspace bytes xpr_bin_sort needs for this batch and capacity. */
+xpr_status xpr_bin_sort_workspace(const xpr_views* views, const xpr_config* cfg,
+                                  int64_t isect_capacity, size_t* bytes);
+
+/* Binning (section Rasterizer): exclusive prefix sum of tiles_touched, one
+ * pair per (record, tile of its rect) with tile id G_v + y tx + x enumerated
+ * row-major in the rect, stable sort by (tile id, depth) so that ties keep
+ * the lower record index, and per-tile [start, end).
+ *   isect_capacity  length of keys/vals (<= 2^31 - 1)
+ *   keys  [cap] uint64 (may be NULL): tile << 32 | float bits of depth
+ *   vals  [cap] int32: record index of each sorted pair
+ *   tile_ranges [tiles][2] int32: [start, end) per global tile, (0,0) if empty
+ *   n_isect  device int64: total number of pairs I (also when I > cap)
+ *   ws / ws_bytes   workspace of at least xpr_bin_sort_workspace() bytes
+ * With cfg->no_sync == 0 the call reads I back (one stream sync) and returns
+ * XPR_ERR_CAPACITY when I > cap (outputs then undefined, *n_isect valid).
+ * With no_sync == 1 nothing is read back and grids are sized from the
+ * capacity; if I > cap the lists are undefined and the caller checks
+ * *n_isect after the stream completes. */
+xpr_status xpr_bin_sort(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
+                        int64_t isect_capacity, uint64_t* keys, int32_t* vals,
+                        int32_t* tile_ranges, int64_t* n_isect, void* ws, size_t ws_bytes,
+                        hipStream_t stream);
+
+/* Forward compositing (Algorithm 1 with the 3DGS evaluate): for each pixel
+ * (x, y), over its tile's list front to back, P = A dx^2 + B dx dy + C dy^2
+ * (dx = x - u, dy = y - v); skip if P > 0; a = min(alpha_max, o e^P); skip
+ * if a < alpha_min; stop without blending if T (1 - a) < t_min; else
+ * C += c a T, T *= 1 - a. Writes
+ *   image [3][H][W] per view: C + T bg
+ *   T_final [H][W] per view: final transmittance
+ *   n_contrib [H][W] per view: 1-based list position of the last blended
+ *   entry (0 if none), used by the backward. */
+xpr_status xpr_render_fwd(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
+                          const int32_t* vals, const int32_t* tile_ranges, float* image,
+                          float* T_final, int32_t* n_contrib, hipStream_t stream);
+
+/* Workspace bytes xpr_render_bwd needs (per-record 2D gradients). */
+xpr_status xpr_render_bwd_workspace(const xpr_views* views, const xpr_config* cfg, size_t* bytes);
+
+/* Backward of compositing and projection. Given dL/dimage (laid out like
+ * image) and the forward's T_final and n_contrib, accumulates the gradient of
+ * L with respect to every scene's parameters, summed over the views that
+ * render it:
+ *   grads [n_scenes] host array of device gradient buffers;
+ *   accumulate 0: overwrite, 1: add to the existing contents;
+ *   grad2d [records][9] float (may be NULL): receives dL/d(u, v, A, B, C, o,
+ *   r, g, b) per record, the derivative with respect to the shader data.
+ * Gradient sums use float atomics, so the last bits vary from run to run. */
+xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
+                          const int32_t* vals, const int32_t* tile_ranges, const float* dL_dimage,
+                          const float* T_final, const int32_t* n_contrib,
+                          const xpr_scene_grad* grads, int32_t accumulate, float* grad2d,
+                          void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Message of the last non-OK status on this thread ("" if none). */
+const char* xpr_last_error(void);
+
+/* XPR_VERSION of the library. */
+int32_t xpr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XPR_H */

@@ -1,0 +1,378 @@
+// Host side of the C-ABI declared in include/xpr.h: argument checks, batch
+// descriptors, workspace carving and kernel launches. No device memory is
+// allocated here; no exception crosses the interface.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "xpr_internal.h"
+
+namespace xpr {
+
+hipError_t launch_project(const Batch& B, int max_n, float* splat, float* depth, int16_t* rect,
+                          int32_t* tc, hipStream_t st);
+hipError_t launch_project_bwd(const Batch& B, int max_n, const float* grad2d, const int32_t* tc,
+                              const GradDev* G, int accumulate, hipStream_t st);
+size_t bin_workspace_bytes(int64_t n_rec, int64_t cap, int sort_mode);
+hipError_t bin_phase1(const Batch& B, int sort_mode, const float* depth, const int32_t* tc,
+                      int64_t n_rec, int64_t cap, int64_t* n_isect, void* ws, hipStream_t st,
+                      const uint32_t** perm_out);
+hipError_t bin_phase2(const Batch& B, int sort_mode, int tile_bits, const float* depth,
+                      const int16_t* rect, const int32_t* tc, const uint32_t* perm, int64_t n_rec,
+                      int64_t cap, int64_t grid_n, const int64_t* n_isect, uint64_t* keys_out,
+                      int32_t* vals, int2* ranges, void* ws, size_t ws_bytes, hipStream_t st);
+hipError_t launch_render_fwd(const Batch& B, int lds_batch, const float* splat,
+                             const int32_t* vals, const int32_t* ranges, float* image, float* Tfin,
+                             int32_t* ncon, hipStream_t st);
+hipError_t launch_render_bwd(const Batch& B, int lds_batch, const float* splat,
+                             const int32_t* vals, const int32_t* ranges, const float* dimg,
+                             const float* Tfin, const int32_t* ncon, float* grad2d,
+                             hipStream_t st);
+hipError_t fill_zero_f32(float* p, int64_t n, hipStream_t st);
+
+static thread_local char g_err[512];
+
+const char* set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return g_err;
+}
+
+#define XPR_CHECK(cond, ...)                  \
+  do {                                        \
+    if (!(cond)) {                            \
+      set_error(__VA_ARGS__);                 \
+      return XPR_ERR_INVALID_ARG;             \
+    }                                         \
+  } while (0)
+
+#define XPR_HIP(expr)                                                          \
+  do {                                                                         \
+    hipError_t e_ = (expr);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      set_error("%s: %s", #expr, hipGetErrorString(e_));                       \
+      return XPR_ERR_HIP;                                                      \
+    }                                                                          \
+  } while (0)
+
+static bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+struct Sizes {
+  int64_t records, tiles, pixels;
+  int tile_bits;
+  int max_n;
+};
+
+static xpr_status check_config(const xpr_config* c) {
+  XPR_CHECK(c != nullptr, "config is NULL");
+  XPR_CHECK((c->tile_w == 8 && c->tile_h == 8) || (c->tile_w == 16 && c->tile_h == 16),
+            "tile size %dx%d not supported (8x8 or 16x16)", c->tile_w, c->tile_h);
+  XPR_CHECK(c->lds_batch == 64 || c->lds_batch == 128 || c->lds_batch == 256 || c->lds_batch == 512,
+            "lds_batch %d not in {64,128,256,512}", c->lds_batch);
+  XPR_CHECK(c->sh_degree >= 0 && c->sh_degree <= 3, "sh_degree %d not in 0..3", c->sh_degree);
+  XPR_CHECK(std::isfinite(c->lowpass) && c->lowpass >= 0.f, "lowpass must be >= 0");
+  XPR_CHECK(c->alpha_min > 0.f && c->alpha_min < 1.f, "alpha_min must be in (0,1)");
+  XPR_CHECK(c->alpha_max > c->alpha_min && c->alpha_max < 1.f,
+            "alpha_max must be in (alpha_min, 1)");
+  XPR_CHECK(c->t_min > 0.f && c->t_min < 1.f, "t_min must be in (0,1)");
+  XPR_CHECK(c->z_near > 0.f && std::isfinite(c->z_near), "z_near must be > 0");
+  XPR_CHECK(c->fov_clip >= 0.f && std::isfinite(c->fov_clip), "fov_clip must be >= 0");
+  XPR_CHECK(std::isfinite(c->bg[0]) && std::isfinite(c->bg[1]) && std::isfinite(c->bg[2]),
+            "bg must be finite");
+  XPR_CHECK(c->sort_mode == XPR_SORT_PRESORT || c->sort_mode == XPR_SORT_FULL,
+            "sort_mode %d unknown", c->sort_mode);
+  return XPR_OK;
+}
+
+// Validates the batch and fills the kernel descriptor.
+static xpr_status build_batch(const xpr_views* vw, const xpr_config* c, Batch* B, Sizes* S) {
+  xpr_status st = check_config(c);
+  if (st != XPR_OK) return st;
+  XPR_CHECK(vw != nullptr, "views is NULL");
+  XPR_CHECK(vw->n_views >= 1 && vw->n_views <= XPR_MAX_VIEWS, "n_views %d not in 1..%d",
+            vw->n_views, XPR_MAX_VIEWS);
+  XPR_CHECK(vw->n_scenes >= 1 && vw->n_scenes <= XPR_MAX_SCENES, "n_scenes %d not in 1..%d",
+            vw->n_scenes, XPR_MAX_SCENES);
+  XPR_CHECK(vw->scenes && vw->cams && vw->view_scene, "views has NULL arrays");
+  std::memset(B, 0, sizeof(*B));
+  const int nb = (c->sh_degree + 1) * (c->sh_degree + 1);
+  int max_n = 0;
+  for (int s = 0; s < vw->n_scenes; ++s) {
+    const xpr_scene& sc = vw->scenes[s];
+    XPR_CHECK(sc.n >= 0 && sc.n < ((int64_t)1 << 31), "scene %d: n=%lld out of range", s,
+              (long long)sc.n);
+    XPR_CHECK(sc.ld >= sc.n && sc.ld < ((int64_t)1 << 31), "scene %d: ld < n", s);
+    XPR_CHECK(sc.sh_coeffs >= nb && sc.sh_coeffs <= 16, "scene %d: sh_coeffs %d < %d", s,
+              sc.sh_coeffs, nb);
+    if (sc.n > 0) {
+      XPR_CHECK(sc.means && sc.scales && sc.quats && sc.opacities && sc.sh,
+                "scene %d: NULL parameter pointer", s);
+      XPR_CHECK(aligned(sc.means, 4) && aligned(sc.scales, 4) && aligned(sc.quats, 4) &&
+                    aligned(sc.opacities, 4) && aligned(sc.sh, 4),
+                "scene %d: misaligned parameter pointer", s);
+    }
+    B->s[s] = SceneDev{sc.means, sc.scales, sc.quats, sc.opacities, sc.sh,
+                       (int32_t)sc.n, (int32_t)sc.ld, sc.sh_coeffs, 0};
+    max_n = std::max<int>(max_n, (int)sc.n);
+  }
+  int64_t rec = 0, tiles = 0, pix = 0;
+  for (int v = 0; v < vw->n_views; ++v) {
+    const xpr_camera& cam = vw->cams[v];
+    const int sidx = vw->view_scene[v];
+    XPR_CHECK(sidx >= 0 && sidx < vw->n_scenes, "view %d: scene index %d out of range", v, sidx);
+    XPR_CHECK(cam.width >= 1 && cam.width <= 16384 && cam.height >= 1 && cam.height <= 16384,
+              "view %d: image %dx%d out of range", v, cam.width, cam.height);
+    XPR_CHECK(cam.fx > 0.f && cam.fy > 0.f && std::isfinite(cam.fx) && std::isfinite(cam.fy) &&
+                  std::isfinite(cam.cx) && std::isfinite(cam.cy),
+              "view %d: bad intrinsics", v);
+    for (int k = 0; k < 9; ++k) XPR_CHECK(std::isfinite(cam.R[k]), "view %d: bad R", v);
+    for (int k = 0; k < 3; ++k) XPR_CHECK(std::isfinite(cam.t[k]), "view %d: bad t", v);
+    ViewDev& d = B->v[v];
+    std::memcpy(d.R, cam.R, sizeof(d.R));
+    std::memcpy(d.t, cam.t, sizeof(d.t));
+    d.fx = cam.fx; d.fy = cam.fy; d.cx = cam.cx; d.cy = cam.cy;
+    d.W = (int16_t)cam.width;
+    d.H = (int16_t)cam.height;
+    const int tx = (cam.width + c->tile_w - 1) / c->tile_w;
+    const int ty = (cam.height + c->tile_h - 1) / c->tile_h;
+    d.tiles_x = (int16_t)tx;
+    d.tiles_y = (int16_t)ty;
+    d.scene = sidx;
+    d.rec_off = (int32_t)rec;
+    d.tile_off = (int32_t)tiles;
+    d.pix_off = (int32_t)pix;
+    rec += vw->scenes[sidx].n;
+    tiles += (int64_t)tx * ty;
+    pix += (int64_t)cam.width * cam.height;
+    XPR_CHECK(rec < ((int64_t)1 << 31) && pix < ((int64_t)1 << 30) && tiles < ((int64_t)1 << 31),
+              "batch too large");
+  }
+  B->n_views = vw->n_views;
+  B->n_scenes = vw->n_scenes;
+  B->total_rec = (int32_t)rec;
+  B->total_tiles = (int32_t)tiles;
+  B->tile_w = c->tile_w;
+  B->tile_h = c->tile_h;
+  B->sh_degree = c->sh_degree;
+  B->lowpass = c->lowpass;
+  B->alpha_min = c->alpha_min;
+  B->alpha_max = c->alpha_max;
+  B->t_min = c->t_min;
+  B->z_near = c->z_near;
+  B->fov_clip = c->fov_clip;
+  B->bg[0] = c->bg[0];
+  B->bg[1] = c->bg[1];
+  B->bg[2] = c->bg[2];
+  int bits = 1;
+  while (bits < 31 && ((int64_t)1 << bits) < tiles) ++bits;
+  XPR_CHECK(bits <= 31, "too many tiles");
+  if (S) {
+    S->records = rec;
+    S->tiles = tiles;
+    S->pixels = pix;
+    S->tile_bits = bits;
+    S->max_n = max_n;
+  }
+  return XPR_OK;
+}
+
+static xpr_status check_proj(const xpr_projected* p, const Sizes& S) {
+  XPR_CHECK(p != nullptr, "projected is NULL");
+  if (S.records > 0) {
+    XPR_CHECK(p->splat && p->depth && p->rect && p->tiles_touched, "projected has NULL buffers");
+    XPR_CHECK(aligned(p->splat, 16) && aligned(p->depth, 4) && aligned(p->rect, 8) &&
+                  aligned(p->tiles_touched, 4),
+              "projected buffers misaligned (splat 16 B, rect 8 B)");
+  }
+  return XPR_OK;
+}
+
+}  // namespace xpr
+
+using namespace xpr;
+
+extern "C" {
+
+int32_t xpr_version(void) { return XPR_VERSION; }
+
+const char* xpr_last_error(void) { return g_err; }
+
+void xpr_config_default(xpr_config* c) {
+  if (!c) return;
+  c->tile_w = 16;
+  c->tile_h = 16;
+  c->lds_batch = 256;
+  c->sh_degree = 3;
+  c->lowpass = 0.3f;
+  c->alpha_min = 1.0f / 255.0f;
+  c->alpha_max = 0.99f;
+  c->t_min = 1e-4f;
+  c->z_near = 0.2f;
+  c->fov_clip = 1.3f;
+  c->bg[0] = c->bg[1] = c->bg[2] = 0.f;
+  c->sort_mode = XPR_SORT_PRESORT;
+  c->no_sync = 0;
+}
+
+xpr_status xpr_batch_sizes(const xpr_views* views, const xpr_config* cfg, xpr_sizes* out) {
+  g_err[0] = 0;
+  Batch B;
+  Sizes S;
+  xpr_status st = build_batch(views, cfg, &B, &S);
+  if (st != XPR_OK) return st;
+  XPR_CHECK(out != nullptr, "out is NULL");
+  out->records = S.records;
+  out->tiles = S.tiles;
+  out->pixels = S.pixels;
+  out->tile_bits = S.tile_bits;
+  return XPR_OK;
+}
+
+xpr_status xpr_project(const xpr_views* views, const xpr_config* cfg, const xpr_projected* out,
+                       hipStream_t stream) {
+  g_err[0] = 0;
+  Batch B;
+  Sizes S;
+  xpr_status st = build_batch(views, cfg, &B, &S);
+  if (st != XPR_OK) return st;
+  st = check_proj(out, S);
+  if (st != XPR_OK) return st;
+  XPR_HIP(launch_project(B, S.max_n, out->splat, out->depth, out->rect, out->tiles_touched, stream));
+  return XPR_OK;
+}
+
+xpr_status xpr_bin_sort_workspace(const xpr_views* views, const xpr_config* cfg,
+                                  int64_t isect_capacity, size_t* bytes) {
+  g_err[0] = 0;
+  Batch B;
+  Sizes S;
+  xpr_status st = build_batch(views, cfg, &B, &S);
+  if (st != XPR_OK) return st;
+  XPR_CHECK(bytes != nullptr, "bytes is NULL");
+  XPR_CHECK(isect_capacity >= 0 && isect_capacity < ((int64_t)1 << 31),
+            "isect_capacity out of range");
+  *bytes = bin_workspace_bytes(S.records, isect_capacity, cfg->sort_mode);
+  return XPR_OK;
+}
+
+xpr_status xpr_bin_sort(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
+                        int64_t isect_capacity, uint64_t* keys, int32_t* vals,
+                        int32_t* tile_ranges, int64_t* n_isect, void* ws, size_t ws_bytes,
+                        hipStream_t stream) {
+  g_err[0] = 0;
+  Batch B;
+  Sizes S;
+  xpr_status st = build_batch(views, cfg, &B, &S);
+  if (st != XPR_OK) return st;
+  st = check_proj(proj, S);
+  if (st != XPR_OK) return st;
+  XPR_CHECK(isect_capacity >= 0 && isect_capacity < ((int64_t)1 << 31),
+            "isect_capacity out of range");
+  XPR_CHECK(tile_ranges && n_isect, "tile_ranges / n_isect NULL");
+  XPR_CHECK(isect_capacity == 0 || vals, "vals NULL");
+  XPR_CHECK(aligned(tile_ranges, 8) && aligned(n_isect, 8) && (!keys || aligned(keys, 8)) &&
+                (!vals || aligned(vals, 4)),
+            "misaligned output buffer");
+  const size_t need = bin_workspace_bytes(S.records, isect_capacity, cfg->sort_mode);
+  XPR_CHECK(ws_bytes >= need && (need == 0 || ws != nullptr),
+            "workspace too small: %zu < %zu bytes", ws_bytes, need);
+  XPR_CHECK(aligned(ws, 256), "workspace must be 256-byte aligned");
+  const uint32_t* perm = nullptr;
+  XPR_HIP(bin_phase1(B, cfg->sort_mode, proj->depth, proj->tiles_touched, S.records,
+                     isect_capacity, n_isect, ws, stream, &perm));
+  int64_t grid_n = isect_capacity;
+  if (!cfg->no_sync) {
+    int64_t I = 0;
+    XPR_HIP(hipMemcpyAsync(&I, n_isect, sizeof(I), hipMemcpyDeviceToHost, stream));
+    XPR_HIP(hipStreamSynchronize(stream));
+    if (I > isect_capacity) {
+      set_error("%lld tile-Gaussian pairs exceed isect_capacity %lld", (long long)I,
+                (long long)isect_capacity);
+      return XPR_ERR_CAPACITY;
+    }
+    grid_n = I;
+  }
+  XPR_HIP(bin_phase2(B, cfg->sort_mode, S.tile_bits, proj->depth, proj->rect,
+                     proj->tiles_touched, perm, S.records, isect_capacity, grid_n, n_isect, keys,
+                     vals, reinterpret_cast<int2*>(tile_ranges), ws, ws_bytes, stream));
+  return XPR_OK;
+}
+
+xpr_status xpr_render_fwd(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
+                          const int32_t* vals, const int32_t* tile_ranges, float* image,
+                          float* T_final, int32_t* n_contrib, hipStream_t stream) {
+  g_err[0] = 0;
+  Batch B;
+  Sizes S;
+  xpr_status st = build_batch(views, cfg, &B, &S);
+  if (st != XPR_OK) return st;
+  st = check_proj(proj, S);
+  if (st != XPR_OK) return st;
+  XPR_CHECK(tile_ranges && image && T_final && n_contrib, "NULL output buffer");
+  XPR_CHECK(aligned(tile_ranges, 8) && aligned(image, 4) && aligned(T_final, 4) &&
+                aligned(n_contrib, 4) && (!vals || aligned(vals, 4)),
+            "misaligned buffer");
+  XPR_HIP(launch_render_fwd(B, cfg->lds_batch, proj->splat, vals, tile_ranges, image, T_final,
+                            n_contrib, stream));
+  return XPR_OK;
+}
+
+xpr_status xpr_render_bwd_workspace(const xpr_views* views, const xpr_config* cfg, size_t* bytes) {
+  g_err[0] = 0;
+  Batch B;
+  Sizes S;
+  xpr_status st = build_batch(views, cfg, &B, &S);
+  if (st != XPR_OK) return st;
+  XPR_CHECK(bytes != nullptr, "bytes is NULL");
+  *bytes = (size_t)9 * sizeof(float) * (size_t)std::max<int64_t>(S.records, 1);
+  return XPR_OK;
+}
+
+xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
+                          const int32_t* vals, const int32_t* tile_ranges, const float* dL_dimage,
+                          const float* T_final, const int32_t* n_contrib,
+                          const xpr_scene_grad* grads, int32_t accumulate, float* grad2d,
+                          void* ws, size_t ws_bytes, hipStream_t stream) {
+  g_err[0] = 0;
+  Batch B;
+  Sizes S;
+  xpr_status st = build_batch(views, cfg, &B, &S);
+  if (st != XPR_OK) return st;
+  st = check_proj(proj, S);
+  if (st != XPR_OK) return st;
+  XPR_CHECK(tile_ranges && dL_dimage && T_final && n_contrib && grads, "NULL buffer");
+  XPR_CHECK(aligned(dL_dimage, 4) && aligned(T_final, 4) && aligned(n_contrib, 4) &&
+                aligned(tile_ranges, 8) && (!grad2d || aligned(grad2d, 4)),
+            "misaligned buffer");
+  float* g2 = grad2d;
+  if (!g2) {
+    const size_t need = (size_t)9 * sizeof(float) * (size_t)std::max<int64_t>(S.records, 1);
+    XPR_CHECK(ws && ws_bytes >= need, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+    XPR_CHECK(aligned(ws, 16), "workspace misaligned");
+    g2 = static_cast<float*>(ws);
+  }
+  GradDev G[XPR_MAX_SCENES];
+  std::memset(G, 0, sizeof(G));
+  for (int s = 0; s < views->n_scenes; ++s) {
+    const xpr_scene_grad& g = grads[s];
+    if (views->scenes[s].n > 0) {
+      XPR_CHECK(g.means && g.scales && g.quats && g.opacities && g.sh,
+                "scene %d: NULL gradient buffer", s);
+      XPR_CHECK(aligned(g.means, 4) && aligned(g.scales, 4) && aligned(g.quats, 4) &&
+                    aligned(g.opacities, 4) && aligned(g.sh, 4),
+                "scene %d: misaligned gradient buffer", s);
+    }
+    G[s] = GradDev{g.means, g.scales, g.quats, g.opacities, g.sh};
+  }
+  XPR_HIP(fill_zero_f32(g2, 9 * S.records, stream));
+  XPR_HIP(launch_render_bwd(B, cfg->lds_batch, proj->splat, vals, tile_ranges, dL_dimage, T_final,
+                            n_contrib, g2, stream));
+  XPR_HIP(launch_project_bwd(B, S.max_n, g2, proj->tiles_touched, G, accumulate ? 1 : 0, stream));
+  return XPR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// Internal declarations of the gfx950 kernels behind include/xpr.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "xpr.h"
+
+namespace xpr {
+
+constexpr int kWave = 64;
+
+// Scene as the kernels see it (kernel-argument copy of xpr_scene).
+struct SceneDev {
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* opac;
+  const float* sh;
+  int32_t n, ld, K, pad;
+};
+
+// One view: camera, image/tile sizes and its offsets in the concatenated
+// per-record, per-tile and per-pixel buffers.
+struct ViewDev {
+  float R[9], t[3];
+  float fx, fy, cx, cy;
+  int16_t W, H, tiles_x, tiles_y;
+  int32_t scene, rec_off, tile_off, pix_off;
+};
+static_assert(sizeof(ViewDev) == 88, "view descriptor layout");
+
+// Whole batch, passed by value as a kernel argument.
+struct Batch {
+  SceneDev s[XPR_MAX_SCENES];
+  ViewDev v[XPR_MAX_VIEWS];
+  int32_t n_views, n_scenes;
+  int32_t total_rec, total_tiles;
+  int32_t tile_w, tile_h;
+  int32_t sh_degree, pad;
+  float lowpass, alpha_min, alpha_max, t_min, z_near, fov_clip;
+  float bg[3], pad2;
+};
+// Gradient destinations of every scene (project backward).
+struct GradDev {
+  float* means;
+  float* scales;
+  float* quats;
+  float* opac;
+  float* sh;
+};
+// Kernel arguments stay below the 4 KiB kernarg limit.
+static_assert(sizeof(Batch) + sizeof(GradDev) * XPR_MAX_SCENES + 64 <= 4096,
+              "kernel argument block too large");
+
+// View owning global tile g (views are few; a scalar linear scan).
+__device__ __forceinline__ int view_of_tile(const Batch& B, int g) {
+  int v = 0;
+  for (int k = 1; k < B.n_views; ++k)
+    if (g >= B.v[k].tile_off) v = k;
+  return v;
+}
+
+// Cross-lane helpers (wave64).
+template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, BANK_MASK, true));
+}
+
+// Sum over the 64 lanes; the total lands in lane 63 (other lanes hold
+// partial sums). Butterflies inside each row of 16 lanes, then the two
+// row broadcasts of the gfx9 DPP.
+__device__ __forceinline__ float wave_sum_lane63(float x) {
+  x += dpp_f<0xB1>(x);          // quad_perm [1,0,3,2]
+  x += dpp_f<0x4E>(x);          // quad_perm [2,3,0,1]
+  x += dpp_f<0x141>(x);         // row_half_mirror
+  x += dpp_f<0x140>(x);         // row_mirror: every lane holds its row sum
+  x += dpp_f<0x142, 0xa>(x);    // row_bcast:15 into rows 1 and 3
+  x += dpp_f<0x143, 0xc>(x);    // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
+__device__ __forceinline__ float lane63(float x) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int lane = threadIdx.x & (kWave - 1);
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Host-side launch helpers (api.hip).
+const char* set_error(const char* fmt, ...);
+
+}  // namespace xpr

@@ -1,0 +1,295 @@
+"""Device-side Python API over the C-ABI: scenes, batches of views and the
+four stages (project, bin_sort, render_fwd, render_bwd).
+
+PyTorch provides device memory and the stream; every stage runs in the HIP
+kernels of libxpr.so. Buffers are SoA float32 tensors laid out as the C-ABI
+expects (component-major, leading dimension ld).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+@dataclasses.dataclass
+class Config:
+    """Method constants and tuning knobs (xpr_config)."""
+    tile: int = 16
+    lds_batch: int = 256
+    sh_degree: int = 3
+    lowpass: float = 0.3
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    t_min: float = 1e-4
+    z_near: float = 0.2
+    fov_clip: float = 1.3
+    bg: tuple = (0.0, 0.0, 0.0)
+    sort_mode: str = "presort"  # or "full"
+    no_sync: bool = False
+
+    def to_c(self) -> L.XprConfig:
+        c = L.XprConfig()
+        c.tile_w = c.tile_h = int(self.tile)
+        c.lds_batch = int(self.lds_batch)
+        c.sh_degree = int(self.sh_degree)
+        c.lowpass = self.lowpass
+        c.alpha_min = self.alpha_min
+        c.alpha_max = self.alpha_max
+        c.t_min = self.t_min
+        c.z_near = self.z_near
+        c.fov_clip = self.fov_clip
+        for k in range(3):
+            c.bg[k] = float(self.bg[k])
+        c.sort_mode = L.XPR_SORT_PRESORT if self.sort_mode == "presort" else L.XPR_SORT_FULL
+        c.no_sync = 1 if self.no_sync else 0
+        return c
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Scene:
+    """Gaussians resident on the device (SoA float32)."""
+
+    def __init__(self, means, scales, quats, opacities, sh):
+        self.n = int(opacities.shape[-1])
+        shapes = ((means, (3, self.n)), (scales, (3, self.n)), (quats, (4, self.n)),
+                  (opacities, (self.n,)))
+        for t, shp in shapes:
+            if tuple(t.shape) != shp or t.dtype != torch.float32:
+                raise ValueError(f"expected float32 {shp}, got {t.dtype} {tuple(t.shape)}")
+        if sh.dim() != 3 or sh.shape[1] != 3 or sh.shape[2] != self.n or sh.dtype != torch.float32:
+            raise ValueError(f"sh must be float32 [K, 3, {self.n}]")
+        self.means, self.scales, self.quats = (t.contiguous() for t in (means, scales, quats))
+        self.opacities, self.sh = opacities.contiguous(), sh.contiguous()
+        self.ld = self.n
+
+    @classmethod
+    def from_host(cls, scene, device="cuda") -> "Scene":
+        """From a synth.Scene (numpy SoA arrays)."""
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+        return cls(t(scene.means), t(scene.scales), t(scene.quats), t(scene.opacities),
+                   t(scene.sh))
+
+    @property
+    def sh_coeffs(self) -> int:
+        return int(self.sh.shape[0])
+
+    def to_c(self) -> L.XprScene:
+        s = L.XprScene()
+        s.means, s.scales, s.quats = (t.data_ptr() for t in (self.means, self.scales, self.quats))
+        s.opacities, s.sh = self.opacities.data_ptr(), self.sh.data_ptr()
+        s.n, s.ld, s.sh_coeffs = self.n, self.ld, self.sh_coeffs
+        return s
+
+    def zeros_like_grads(self):
+        return dict(means=torch.zeros_like(self.means), scales=torch.zeros_like(self.scales),
+                    quats=torch.zeros_like(self.quats),
+                    opacities=torch.zeros_like(self.opacities), sh=torch.zeros_like(self.sh))
+
+    def nbytes(self) -> int:
+        return sum(t.numel() * 4 for t in (self.means, self.scales, self.quats, self.opacities,
+                                            self.sh))
+
+
+def camera_to_c(cam) -> L.XprCamera:
+    c = L.XprCamera()
+    R = np.asarray(cam.R, dtype=np.float64).reshape(9)
+    t = np.asarray(cam.t, dtype=np.float64).reshape(3)
+    for k in range(9):
+        c.R[k] = float(R[k])
+    for k in range(3):
+        c.t[k] = float(t[k])
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+class Views:
+    """A batch: n_views cameras over n_scenes scenes, with the offsets of
+    every view in the concatenated record, tile and pixel buffers."""
+
+    def __init__(self, scenes: Sequence[Scene], cams: Sequence, view_scene: Sequence[int],
+                 cfg: Config):
+        assert 1 <= len(cams) <= L.XPR_MAX_VIEWS and 1 <= len(scenes) <= L.XPR_MAX_SCENES
+        self.scenes = list(scenes)
+        self.cams = list(cams)
+        self.view_scene = [int(s) for s in view_scene]
+        self._scenes_c = (L.XprScene * len(scenes))(*[s.to_c() for s in scenes])
+        self._cams_c = (L.XprCamera * len(cams))(*[camera_to_c(c) for c in cams])
+        self._vs_c = (ctypes.c_int32 * len(cams))(*self.view_scene)
+        self.c = L.XprViews(self._scenes_c, len(scenes), self._cams_c, self._vs_c, len(cams))
+        self.cfg_c = cfg.to_c()
+        sz = L.xpr_batch_sizes(self.c, self.cfg_c)
+        self.records, self.tiles, self.pixels = int(sz.records), int(sz.tiles), int(sz.pixels)
+        self.tile_bits = int(sz.tile_bits)
+        self.rec_off, self.tile_off, self.pix_off = [], [], []
+        r = t = p = 0
+        for v, cam in enumerate(cams):
+            self.rec_off.append(r)
+            self.tile_off.append(t)
+            self.pix_off.append(p)
+            r += self.scenes[self.view_scene[v]].n
+            t += (-(-cam.width // cfg.tile)) * (-(-cam.height // cfg.tile))
+            p += cam.width * cam.height
+        assert (r, t, p) == (self.records, self.tiles, self.pixels)
+
+    @property
+    def n_views(self) -> int:
+        return len(self.cams)
+
+    def image(self, flat: torch.Tensor, v: int) -> torch.Tensor:
+        cam = self.cams[v]
+        o = 3 * self.pix_off[v]
+        return flat[o:o + 3 * cam.width * cam.height].view(3, cam.height, cam.width)
+
+    def plane(self, flat: torch.Tensor, v: int) -> torch.Tensor:
+        cam = self.cams[v]
+        o = self.pix_off[v]
+        return flat[o:o + cam.width * cam.height].view(cam.height, cam.width)
+
+
+@dataclasses.dataclass
+class Projected:
+    splat: torch.Tensor   # [R, 12] f32
+    depth: torch.Tensor   # [R] f32
+    rect: torch.Tensor    # [R, 4] i16
+    tc: torch.Tensor      # [R] i32
+
+    def to_c(self) -> L.XprProjected:
+        return L.XprProjected(self.splat.data_ptr(), self.depth.data_ptr(), self.rect.data_ptr(),
+                              self.tc.data_ptr())
+
+
+@dataclasses.dataclass
+class Bins:
+    vals: torch.Tensor     # [cap] i32
+    ranges: torch.Tensor   # [tiles, 2] i32
+    n_isect: torch.Tensor  # [1] i64 (device)
+    keys: Optional[torch.Tensor] = None  # [cap] i64 (bits of uint64)
+    capacity: int = 0
+    count: int = -1        # host copy of n_isect when known
+
+
+@dataclasses.dataclass
+class Frame:
+    image: torch.Tensor    # [3 * pixels] f32 (view-planar)
+    T_final: torch.Tensor  # [pixels] f32
+    n_contrib: torch.Tensor  # [pixels] i32
+
+
+def empty_projected(n: int, device) -> Projected:
+    n1 = max(n, 1)
+    return Projected(torch.empty((n1, 12), dtype=torch.float32, device=device),
+                     torch.empty(n1, dtype=torch.float32, device=device),
+                     torch.empty((n1, 4), dtype=torch.int16, device=device),
+                     torch.empty(n1, dtype=torch.int32, device=device))
+
+
+def xpr_project(views: Views, cfg: Config, out: Optional[Projected] = None) -> Projected:
+    dev = views.scenes[0].means.device
+    out = out or empty_projected(views.records, dev)
+    L.xpr_project(views.c, views.cfg_c, out.to_c(), _stream())
+    return out
+
+
+class Workspace:
+    """Growing device scratch reused across calls (caller-owned memory)."""
+
+    def __init__(self):
+        self.buf = {}
+
+    def get(self, name: str, nbytes: int, device) -> torch.Tensor:
+        b = self.buf.get(name)
+        if b is None or b.numel() < nbytes:
+            b = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+            self.buf[name] = b
+        return b
+
+
+_WS = Workspace()
+
+
+def xpr_bin_sort(views: Views, cfg: Config, proj: Projected, capacity: Optional[int] = None,
+                 want_keys: bool = False, ws: Optional[Workspace] = None,
+                 out: Optional[Bins] = None) -> Bins:
+    """Binning with a host-side capacity retry on XPR_ERR_CAPACITY."""
+    ws = ws or _WS
+    dev = proj.splat.device
+    cap = capacity if capacity is not None else max(1024, 16 * views.records)
+    if out is not None and out.capacity >= cap:
+        cap = out.capacity
+    while True:
+        if out is None or out.capacity < cap or (want_keys and out.keys is None):
+            out = Bins(vals=torch.empty(max(cap, 1), dtype=torch.int32, device=dev),
+                       ranges=torch.empty((max(views.tiles, 1), 2), dtype=torch.int32, device=dev),
+                       n_isect=torch.zeros(1, dtype=torch.int64, device=dev),
+                       keys=torch.empty(max(cap, 1), dtype=torch.int64, device=dev) if want_keys else None,
+                       capacity=cap)
+        nbytes = L.xpr_bin_sort_workspace(views.c, views.cfg_c, cap)
+        wsb = ws.get("bin", nbytes, dev)
+        st = L.xpr_bin_sort(views.c, views.cfg_c, proj.to_c(), cap,
+                            _ptr(out.keys) if want_keys else None, _ptr(out.vals),
+                            _ptr(out.ranges), _ptr(out.n_isect), _ptr(wsb), wsb.numel(), _stream())
+        if st == L.XPR_OK:
+            if not cfg.no_sync:
+                out.count = int(out.n_isect.item())
+            return out
+        need = int(out.n_isect.item())
+        cap = int(need * 1.125) + 1024
+        out = None
+
+
+def xpr_render_fwd(views: Views, cfg: Config, proj: Projected, bins: Bins,
+                   out: Optional[Frame] = None) -> Frame:
+    dev = proj.splat.device
+    if out is None:
+        out = Frame(torch.empty(3 * views.pixels, dtype=torch.float32, device=dev),
+                    torch.empty(views.pixels, dtype=torch.float32, device=dev),
+                    torch.empty(views.pixels, dtype=torch.int32, device=dev))
+    L.xpr_render_fwd(views.c, views.cfg_c, proj.to_c(), _ptr(bins.vals), _ptr(bins.ranges),
+                     _ptr(out.image), _ptr(out.T_final), _ptr(out.n_contrib), _stream())
+    return out
+
+
+def xpr_render_bwd(views: Views, cfg: Config, proj: Projected, bins: Bins, frame: Frame,
+                   dimage: torch.Tensor, grads: Optional[List[dict]] = None,
+                   accumulate: bool = False, want_grad2d: bool = False,
+                   ws: Optional[Workspace] = None):
+    """Returns (grads per scene, grad2d or None)."""
+    ws = ws or _WS
+    dev = proj.splat.device
+    if grads is None:
+        grads = [s.zeros_like_grads() for s in views.scenes]
+    arr = (L.XprSceneGrad * len(grads))(*[
+        L.XprSceneGrad(g["means"].data_ptr(), g["scales"].data_ptr(), g["quats"].data_ptr(),
+                       g["opacities"].data_ptr(), g["sh"].data_ptr()) for g in grads])
+    dimage = dimage.contiguous()
+    grad2d = torch.empty((max(views.records, 1), 9), dtype=torch.float32, device=dev) \
+        if want_grad2d else None
+    nbytes = L.xpr_render_bwd_workspace(views.c, views.cfg_c)
+    wsb = ws.get("bwd", nbytes, dev)
+    L.xpr_render_bwd(views.c, views.cfg_c, proj.to_c(), _ptr(bins.vals), _ptr(bins.ranges),
+                     _ptr(dimage), _ptr(frame.T_final), _ptr(frame.n_contrib), arr,
+                     1 if accumulate else 0, _ptr(grad2d), _ptr(wsb), wsb.numel(), _stream())
+    return grads, grad2d
+
+
+def render(scene: Scene, cam, cfg: Config, want_keys: bool = False):
+    """One view: returns (image [3,H,W], state dict)."""
+    views = Views([scene], [cam], [0], cfg)
+    proj = xpr_project(views, cfg)
+    bins = xpr_bin_sort(views, cfg, proj, want_keys=want_keys)
+    frame = xpr_render_fwd(views, cfg, proj, bins)
+    return views.image(frame.image, 0), dict(views=views, proj=proj, bins=bins, frame=frame)

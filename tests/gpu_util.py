@@ -1,0 +1,173 @@
+"""Helpers for the GPU parity tests: run the HIP path through the C-ABI and
+compare each stage with the FP64 oracle on the same inputs (the stage-wise
+protocol: each oracle stage is fed the GPU's previous-stage outputs so that
+float32 rounding upstream does not leak into the comparison)."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import torch
+
+import oracle
+from paper_2606_11529_amd import renderer as R
+
+TOL_PIXEL = 1e-5     # max-abs on FP32 pixel colours
+TOL_GRAD = 1e-3      # relative on gradients
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def ocfg_of(cfg: R.Config) -> oracle.OracleConfig:
+    return oracle.OracleConfig(tile_w=cfg.tile, tile_h=cfg.tile, sh_degree=cfg.sh_degree,
+                               lowpass=cfg.lowpass, alpha_min=cfg.alpha_min,
+                               alpha_max=cfg.alpha_max, t_min=cfg.t_min, z_near=cfg.z_near,
+                               fov_clip=cfg.fov_clip, bg=tuple(cfg.bg))
+
+
+def run_gpu(sc, cams, cfg: R.Config, dimgs=None, want_keys=True, want_grad2d=True,
+            device="cuda"):
+    """One batch (one scene, several cameras). Returns numpy copies of every
+    stage's outputs."""
+    if not isinstance(cams, (list, tuple)):
+        cams = [cams]
+    scene = R.Scene.from_host(sc, device)
+    views = R.Views([scene], cams, [0] * len(cams), cfg)
+    proj = R.xpr_project(views, cfg)
+    bins = R.xpr_bin_sort(views, cfg, proj, want_keys=want_keys)
+    frame = R.xpr_render_fwd(views, cfg, proj, bins)
+    out = dict(views=views, scene=scene)
+    if dimgs is not None:
+        flat = torch.cat([torch.from_numpy(np.asarray(d, np.float32)).reshape(-1)
+                          for d in dimgs]).to(device)
+        grads, g2 = R.xpr_render_bwd(views, cfg, proj, bins, frame, flat, want_grad2d=want_grad2d)
+        out["grads"] = {k: v.cpu().numpy() for k, v in grads[0].items()}
+        out["grad2d"] = g2.cpu().numpy()[:views.records] if g2 is not None else None
+    torch.cuda.synchronize()
+    n = views.records
+    I = int(bins.n_isect.item())
+    out.update(
+        splat=proj.splat.cpu().numpy()[:n], depth=proj.depth.cpu().numpy()[:n],
+        rect=proj.rect.cpu().numpy()[:n].astype(np.int32), tc=proj.tc.cpu().numpy()[:n],
+        I=I, vals=bins.vals.cpu().numpy()[:I], ranges=bins.ranges.cpu().numpy()[:views.tiles],
+        keys=bins.keys.cpu().numpy()[:I].view(np.uint64) if want_keys else None,
+        image=[views.image(frame.image, v).cpu().numpy() for v in range(len(cams))],
+        Tfinal=[views.plane(frame.T_final, v).cpu().numpy() for v in range(len(cams))],
+        ncontrib=[views.plane(frame.n_contrib, v).cpu().numpy() for v in range(len(cams))])
+    return out
+
+
+def rec9(splat):
+    return splat[:, :9].astype(np.float64)
+
+
+# ---- P1: projection -------------------------------------------------------
+
+def check_projection(sc, cam, cfg, gpu, rec_off=0, idx=None):
+    """Floats within the stated bounds; rect/tc bit-exact except guard-band
+    Gaussians. Returns (number of guard Gaussians, number checked)."""
+    oc = ocfg_of(cfg)
+    sub = sc if idx is None else sc.subset(idx)
+    ref = oracle.project(sub, cam, oc)
+    n = sub.n
+    sel = np.arange(rec_off, rec_off + sc.n) if idx is None else rec_off + np.asarray(idx)
+    g_rec = rec9(gpu["splat"][sel])
+    g_tc = gpu["tc"][sel]
+    g_rect = gpu["rect"][sel]
+    g_depth = gpu["depth"][sel].astype(np.float64)
+    guard = ref["guard"].astype(bool)
+    vis = (ref["tc"] > 0) & (g_tc > 0)
+    ok = ~guard
+    # integer outputs: bit-exact outside the guard band
+    bad_tc = np.nonzero(ok & (g_tc != ref["tc"]))[0]
+    assert bad_tc.size == 0, f"tc mismatch at {bad_tc[:10]}: gpu {g_tc[bad_tc[:10]]} ref {ref['tc'][bad_tc[:10]]}"
+    vr = ok & (ref["tc"] > 0)
+    assert np.array_equal(g_rect[vr], ref["rect"][vr]), "rect mismatch"
+    # floats, on Gaussians visible on both sides
+    m = vis
+    uv_err = np.abs(g_rec[m, :2] - ref["rec"][m, :2]) / np.maximum(1.0, np.abs(ref["rec"][m, :2]))
+    assert uv_err.max(initial=0) <= 2e-6, f"mean2D rel err {uv_err.max()}"
+    d_err = np.abs(g_depth[m] - ref["depth"][m]) / np.maximum(1.0, np.abs(ref["depth"][m]))
+    assert d_err.max(initial=0) <= 2e-6, f"depth err {d_err.max()}"
+    c_err = np.abs(g_rec[m, 6:9] - ref["rec"][m, 6:9])
+    assert c_err.max(initial=0) <= 1e-6, f"colour err {c_err.max()}"
+    assert np.array_equal(g_rec[m, 5], ref["rec"][m, 5]), "opacity must pass through"
+    cov = ref["cov"][m]
+    tr = cov[:, 0] + cov[:, 2]
+    det = cov[:, 0] * cov[:, 2] - cov[:, 1] ** 2
+    disc = np.sqrt(np.maximum(0, 0.25 * tr * tr - det))
+    cond = (0.5 * tr + disc) / np.maximum(0.5 * tr - disc, 1e-300)
+    con_ref = ref["rec"][m, 2:5]
+    scale = np.abs(con_ref).max(axis=1, keepdims=True)
+    con_err = np.abs(g_rec[m, 2:5] - con_ref) / scale
+    lim = 1e-6 * cond[:, None] + 1e-6
+    worst = (con_err / lim).max(initial=0)
+    assert worst <= 1.0, f"conic error {worst} x bound"
+    return int(guard.sum()), int(n)
+
+
+# ---- P2: binning ----------------------------------------------------------
+
+def check_binning(gpu, tiles_x_total_tiles, rec_sel=None):
+    """Oracle binning fed the GPU's depth / rect / tc: offsets, I, keys, vals
+    and ranges bit-exact. ``tiles_x_total_tiles`` = (tiles_x, tiles_y) for a
+    single view."""
+    tx, ty = tiles_x_total_tiles
+    ref = oracle.bin_pairs(gpu["depth"].astype(np.float64), gpu["rect"], gpu["tc"], tx, ty)
+    assert ref["I"] == gpu["I"], (ref["I"], gpu["I"])
+    assert np.array_equal(gpu["vals"], ref["vals"]), "vals differ"
+    if gpu["keys"] is not None:
+        assert np.array_equal(gpu["keys"], ref["keys"]), "keys differ"
+    assert np.array_equal(gpu["ranges"], ref["ranges"]), "ranges differ"
+    return ref
+
+
+# ---- P3: forward compositing -------------------------------------------
+
+def check_forward(gpu, cam, cfg, v=0, ranges=None, pixel_mask=None):
+    """Oracle compositing on the GPU's splat records and lists. Returns
+    (max error on non-guard pixels, guard pixel count)."""
+    oc = ocfg_of(cfg)
+    rg = gpu["ranges"] if ranges is None else ranges
+    ref = oracle.render_fwd(rec9(gpu["splat"]), gpu["vals"], rg, cam.width, cam.height, oc)
+    guard = ref["guard"].astype(bool)
+    sel = ~guard if pixel_mask is None else (~guard & pixel_mask)
+    img = gpu["image"][v]
+    err = np.abs(img - ref["img"])[:, sel]
+    emax = float(err.max(initial=0))
+    assert emax <= TOL_PIXEL, f"pixel max-abs {emax} > {TOL_PIXEL}"
+    assert np.array_equal(gpu["ncontrib"][v][sel], ref["ncontrib"][sel]), "n_contrib differs"
+    terr = np.abs(gpu["Tfinal"][v][sel] - ref["Tfinal"][sel]) / ref["Tfinal"][sel]
+    assert terr.max(initial=0) <= 1e-5, f"T_final rel err {terr.max()}"
+    gsel = guard if pixel_mask is None else (guard & pixel_mask)
+    if gsel.any():
+        gerr = np.abs(img - ref["img"])[:, gsel].max()
+        assert gerr <= 1e-2, f"guard pixel error {gerr}"
+    return emax, int(gsel.sum()), ref
+
+
+def guard_records(ref_fwd, ranges, vals, tile, tiles_x):
+    """Records listed in any tile that holds a guard pixel."""
+    gy, gx = np.nonzero(ref_fwd["guard"])
+    tiles = np.unique((gy // tile) * tiles_x + gx // tile)
+    out = [vals[ranges[t, 0]:ranges[t, 1]] for t in tiles]
+    return np.unique(np.concatenate(out)) if out else np.zeros(0, np.int64)
+
+
+def rel_check(got, ref, name, mask=None, tol=TOL_GRAD):
+    """abs(g - r) <= tol * max(abs(r), 1e-3 max abs(r)), per column."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    if mask is not None:
+        got, ref = got[mask], ref[mask]
+    if ref.size == 0:
+        return 0.0
+    floor = 1e-3 * np.abs(ref).max(axis=0, keepdims=True)
+    bound = tol * np.maximum(np.abs(ref), floor)
+    ratio = np.abs(got - ref) / np.maximum(bound, 1e-300)
+    worst = float(ratio.max())
+    assert worst <= 1.0, f"{name}: error {worst:.3g} x bound (tol {tol})"
+    return worst
