@@ -1,0 +1,248 @@
+#!/usr/bin/env python
+"""Benchmark: forward + backward per frame of 3DGS tile splatting at 3M
+Gaussians and 1600x1064 on one MI355X, through the C-ABI.
+
+One step = one frame: project -> bin_sort -> render_fwd -> L1 loss against
+a uniform-random target -> render_bwd (compositing) -> project_bwd, for the
+next of 8 cameras on a radius-6 sphere. Inputs (scene, targets) are resident
+in HBM before the timed region. Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd ms/frame @3M Gaussians 1600x1064; served frames/s + p99 latency"
+HBM_PEAK_GBS = 8000.0
+# FP32 VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (no packed math).
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Algorithmic VALU lane-operations per pixel-Gaussian evaluation.
+OPS_FWD = 22
+OPS_BWD = 40
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=24)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--n", type=int, default=3_000_000)
+    ap.add_argument("--width", type=int, default=1600)
+    ap.add_argument("--height", type=int, default=1064)
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--lds-batch", type=int, default=256)
+    ap.add_argument("--sort", default="presort")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2606_11529_amd import renderer as R
+    from synth import random_cameras, scene_clusters
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    sc = scene_clusters(args.n, seed=0)
+    cams = random_cameras(8, 0, (args.width, args.height))
+    log(f"[bench] scene {args.n} generated in {time.time() - t0:.1f}s")
+    cfg = R.Config(tile=args.tile, lds_batch=args.lds_batch, sh_degree=3, sort_mode=args.sort)
+    scene = R.Scene.from_host(sc, dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    H, W = args.height, args.width
+    targets = [torch.rand((3, H, W), generator=gen, device=dev) for _ in cams]
+    views = [R.Views([scene], [c], [0], cfg) for c in cams]
+    proj = R.empty_projected(scene.n, dev)
+    frame = None
+    tw = torch.zeros(views[0].tiles, dtype=torch.int32, device=dev)
+    g2 = torch.empty((scene.n, 9), dtype=torch.float32, device=dev)
+    grads = [scene.zeros_like_grads()]
+    ws = R.Workspace()
+
+    # Capacity for the pair list: one pass over the cameras, +10%.
+    cap = 0
+    for v in views:
+        R.xpr_project(v, cfg, out=proj)
+        b = R.xpr_bin_sort(v, cfg, proj, ws=ws)
+        cap = max(cap, b.count)
+    cap = int(cap * 1.1) + 4096
+    bins = R.xpr_bin_sort(views[0], cfg, proj, capacity=cap, ws=ws)
+    log(f"[bench] pair capacity {cap}")
+
+    names = ["project", "bin_sort", "render_fwd", "loss", "render_bwd", "project_bwd"]
+    n_ev = len(names) + 1
+    ev_all = [[torch.cuda.Event(enable_timing=True) for _ in range(n_ev)]
+              for _ in range(args.steps + 1)]
+    ev = ev_all[-1]
+    stage_ms = {k: [] for k in names}
+    work = {"fwd": [], "bwd": [], "pairs": [], "visible": []}
+
+    def step(k, ev):
+        nonlocal bins, frame
+        v = views[k % len(views)]
+        ev[0].record()
+        R.xpr_project(v, cfg, out=proj)
+        ev[1].record()
+        bins = R.xpr_bin_sort(v, cfg, proj, capacity=cap, ws=ws, out=bins)
+        ev[2].record()
+        frame = R.xpr_render_fwd(v, cfg, proj, bins, out=frame, tile_work=tw)
+        ev[3].record()
+        img = v.image(frame.image, 0)
+        diff = img - targets[k % len(views)]
+        loss = diff.abs().mean()
+        dimg = torch.sign(diff) / diff.numel()
+        ev[4].record()
+        R.xpr_render_bwd(v, cfg, proj, bins, frame, dimg.reshape(-1), params=False, grad2d=g2,
+                         ws=ws)
+        ev[5].record()
+        R.xpr_project_bwd(v, cfg, proj, g2, grads=grads)
+        ev[6].record()
+        return loss
+
+    for k in range(args.warmup):
+        step(k, ev)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup done ({args.warmup} steps)")
+
+    # Timed region: exactly K steps bracketed by device synchronisation.
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        step(args.warmup + k, ev_all[k])
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    for k in range(args.steps):
+        for i, name in enumerate(names):
+            stage_ms[name].append(ev_all[k][i].elapsed_time(ev_all[k][i + 1]))
+    log(f"[bench] timed {args.steps} steps")
+    ms_wall = (t_end - t_start) * 1e3 / args.steps
+
+    # Work per camera (deterministic), outside the timed region.
+    tiles_x = (W + args.tile - 1) // args.tile
+    tiles_y = (H + args.tile - 1) // args.tile
+    npx = args.tile * args.tile
+    for k in range(len(views)):
+        v = views[k]
+        R.xpr_project(v, cfg, out=proj)
+        bins = R.xpr_bin_sort(v, cfg, proj, capacity=cap, ws=ws, out=bins)
+        frame = R.xpr_render_fwd(v, cfg, proj, bins, out=frame, tile_work=tw)
+        nc = v.plane(frame.n_contrib, 0)
+        pad = torch.zeros((tiles_y * args.tile, tiles_x * args.tile), dtype=torch.int32, device=dev)
+        pad[:H, :W] = nc
+        tmax = pad.view(tiles_y, args.tile, tiles_x, args.tile).amax(dim=(1, 3))
+        work["fwd"].append(float(tw.sum().item()) * npx)
+        work["bwd"].append(float(tmax.sum().item()) * npx)
+        work["pairs"].append(bins.count)
+        work["visible"].append(int((proj.tc[:scene.n] > 0).sum().item()))
+    order = [(args.warmup + k) % len(views) for k in range(args.steps)]
+    evals_fwd = float(np.mean([work["fwd"][c] for c in order]))
+    evals_bwd = float(np.mean([work["bwd"][c] for c in order]))
+    pairs = float(np.mean([work["pairs"][c] for c in order]))
+
+    med = {k: float(np.median(v)) for k, v in stage_ms.items()}
+    mean = {k: float(np.mean(v)) for k, v in stage_ms.items()}
+    frame_ms = float(np.mean(np.sum([stage_ms[k] for k in names], axis=0)))
+
+    nG = scene.n
+    proj_bytes = nG * (236 + 64)
+    pbwd_bytes = nG * (236 + 36 + 4 + 236)
+    fwd_tops = evals_fwd * OPS_FWD / (mean["render_fwd"] * 1e-3) / 1e12
+    bwd_tops = evals_bwd * OPS_BWD / (mean["render_bwd"] * 1e-3) / 1e12
+    stages = {
+        "project": {"ms": mean["project"], "bound": "hbm",
+                    "GB/s": proj_bytes / (mean["project"] * 1e-3) / 1e9,
+                    "frac": proj_bytes / (mean["project"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "bin_sort": {"ms": mean["bin_sort"], "pairs": pairs},
+        "render_fwd": {"ms": mean["render_fwd"], "bound": "alu", "evals": evals_fwd,
+                       "TOP/s": fwd_tops, "frac": fwd_tops / VALU_PEAK_TOPS},
+        "loss": {"ms": mean["loss"]},
+        "render_bwd": {"ms": mean["render_bwd"], "bound": "alu", "evals": evals_bwd,
+                       "TOP/s": bwd_tops, "frac": bwd_tops / VALU_PEAK_TOPS},
+        "project_bwd": {"ms": mean["project_bwd"], "bound": "hbm",
+                        "GB/s": pbwd_bytes / (mean["project_bwd"] * 1e-3) / 1e9,
+                        "frac": pbwd_bytes / (mean["project_bwd"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
+    }
+    dom = "render_bwd" if mean["render_bwd"] >= mean["render_fwd"] else "render_fwd"
+    ops = OPS_BWD * evals_bwd if dom == "render_bwd" else OPS_FWD * evals_fwd
+    roof = {"kernel": "k_render_bwd" if dom == "render_bwd" else "k_render_fwd",
+            "bound": "alu", "achieved": stages[dom]["TOP/s"], "peak": VALU_PEAK_TOPS,
+            "unit": "TOP/s", "frac": stages[dom]["frac"], "traffic": None,
+            "ops_per_launch": ops, "launch_ms": mean[dom]}
+
+    out = {
+        "metric": METRIC, "value": round(ms_wall, 4), "unit": "ms/frame", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_wall, 4),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"3DGS forward+backward, {nG} Gaussians (64 normal clusters, "
+                               f"SH degree 3), {W}x{H}, {args.tile}x{args.tile} tiles, 8 cameras "
+                               "on a radius-6 sphere, L1 loss vs U[0,1] target",
+                   "lds_batch": args.lds_batch, "sort": args.sort,
+                   "pairs_per_frame": pairs},
+        "stage_sum_ms": round(frame_ms, 4),
+        "stages_ms_median": med,
+        "stages": stages,
+        "roofline": roof,
+    }
+    log(f"[bench] frame {frame_ms:.3f} ms (stage sum), wall {ms_wall:.3f} ms/step")
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sc, cams[0], cfg)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(sc, cam, cfg):
+    """The FP64 oracle on one full frame of the same workload (camera 0):
+    projection, binning, compositing forward and backward, projection
+    backward, on all host cores."""
+    import numpy as np
+
+    import oracle
+    oc = oracle.OracleConfig(tile_w=cfg.tile, tile_h=cfg.tile, sh_degree=cfg.sh_degree)
+    log(f"[bench] cpu baseline: oracle on {oracle.num_threads()} threads")
+    t0 = time.perf_counter()
+    st = oracle.render(sc, cam, oc)
+    target = np.random.default_rng(7).uniform(size=(3, cam.height, cam.width))
+    diff = st["fwd"]["img"] - target
+    dimg = np.sign(diff) / diff.size
+    oracle.backward(sc, cam, oc, dimg, state=st)
+    dt = time.perf_counter() - t0
+    cpu = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    log(f"[bench] cpu baseline {dt:.1f}s")
+    return {"value": round(dt * 1e3, 1), "unit": "ms/frame", "cores": oracle.num_threads(),
+            "kind": "oracle", "cpu": cpu,
+            "sample": "one full frame (camera 0 of 8): FP64 projection of all Gaussians, "
+                      "binning, compositing forward and backward over every pixel, "
+                      "projection backward"}
+
+
+if __name__ == "__main__":
+    main()

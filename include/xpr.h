@@ -198,10 +198,13 @@ xpr_status xpr_bin_sort(const xpr_views* views, const xpr_config* cfg, const xpr
  *   image [3][H][W] per view: C + T bg
  *   T_final [H][W] per view: final transmittance
  *   n_contrib [H][W] per view: 1-based list position of the last blended
- *   entry (0 if none), used by the backward. */
+ *   entry (0 if none), used by the backward;
+ *   tile_work [tiles] int32 (may be NULL): list entries each tile's
+ *   workgroup evaluated before every pixel was done (the lockstep work). */
 xpr_status xpr_render_fwd(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
                           const int32_t* vals, const int32_t* tile_ranges, float* image,
-                          float* T_final, int32_t* n_contrib, hipStream_t stream);
+                          float* T_final, int32_t* n_contrib, int32_t* tile_work,
+                          hipStream_t stream);
 
 /* Workspace bytes xpr_render_bwd needs (per-record 2D gradients). */
 xpr_status xpr_render_bwd_workspace(const xpr_views* views, const xpr_config* cfg, size_t* bytes);
@@ -210,16 +213,29 @@ xpr_status xpr_render_bwd_workspace(const xpr_views* views, const xpr_config* cf
  * image) and the forward's T_final and n_contrib, accumulates the gradient of
  * L with respect to every scene's parameters, summed over the views that
  * render it:
- *   grads [n_scenes] host array of device gradient buffers;
+ *   grads [n_scenes] host array of device gradient buffers, or NULL to stop
+ *   after the compositing backward (then grad2d is required);
  *   accumulate 0: overwrite, 1: add to the existing contents;
  *   grad2d [records][9] float (may be NULL): receives dL/d(u, v, A, B, C, o,
- *   r, g, b) per record, the derivative with respect to the shader data.
- * Gradient sums use float atomics, so the last bits vary from run to run. */
+ *   r, g, b) per record, the derivative with respect to the shader data;
+ *   when NULL the workspace holds it.
+ * The compositing backward walks each pixel's list in reverse from its last
+ * blended entry (T_i recovered as T_{i+1} / (1 - a_i)). Gradient sums use
+ * float atomics, so the last bits vary from run to run. */
 xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
                           const int32_t* vals, const int32_t* tile_ranges, const float* dL_dimage,
                           const float* T_final, const int32_t* n_contrib,
                           const xpr_scene_grad* grads, int32_t accumulate, float* grad2d,
                           void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Backward of the projection alone: from grad2d [records][9] (as written by
+ * xpr_render_bwd) to the parameter gradients of every scene, summed over the
+ * views that render it (one thread per Gaussian loops over those views, so
+ * the sum is deterministic). Records with tiles_touched == 0 contribute
+ * nothing. grads and accumulate as in xpr_render_bwd. */
+xpr_status xpr_project_bwd(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
+                           const float* grad2d, const xpr_scene_grad* grads, int32_t accumulate,
+                           hipStream_t stream);
 
 /* Message of the last non-OK status on this thread ("" if none). */
 const char* xpr_last_error(void);

@@ -76,7 +76,9 @@ SIGNATURES = {
     "xpr_bin_sort": (_i32, [_P(XprViews), _P(XprConfig), _P(XprProjected), _i64, _vp, _vp, _vp,
                             _vp, _vp, ctypes.c_size_t, _vp]),
     "xpr_render_fwd": (_i32, [_P(XprViews), _P(XprConfig), _P(XprProjected), _vp, _vp, _vp, _vp,
-                              _vp, _vp]),
+                              _vp, _vp, _vp]),
+    "xpr_project_bwd": (_i32, [_P(XprViews), _P(XprConfig), _P(XprProjected), _vp,
+                               _P(XprSceneGrad), _i32, _vp]),
     "xpr_render_bwd_workspace": (_i32, [_P(XprViews), _P(XprConfig), _P(ctypes.c_size_t)]),
     "xpr_render_bwd": (_i32, [_P(XprViews), _P(XprConfig), _P(XprProjected), _vp, _vp, _vp, _vp,
                               _vp, _P(XprSceneGrad), _i32, _vp, _vp, ctypes.c_size_t, _vp]),
@@ -152,9 +154,16 @@ def xpr_bin_sort(views, cfg, proj, capacity, keys, vals, ranges, n_isect, ws, ws
     return st
 
 
-def xpr_render_fwd(views, cfg, proj, vals, ranges, image, T_final, n_contrib, stream) -> None:
+def xpr_render_fwd(views, cfg, proj, vals, ranges, image, T_final, n_contrib, tile_work,
+                   stream) -> None:
     check(lib().xpr_render_fwd(ctypes.byref(views), ctypes.byref(cfg), ctypes.byref(proj), vals,
-                               ranges, image, T_final, n_contrib, stream), "xpr_render_fwd")
+                               ranges, image, T_final, n_contrib, tile_work, stream),
+          "xpr_render_fwd")
+
+
+def xpr_project_bwd(views, cfg, proj, grad2d, grads, accumulate, stream) -> None:
+    check(lib().xpr_project_bwd(ctypes.byref(views), ctypes.byref(cfg), ctypes.byref(proj),
+                                grad2d, grads, accumulate, stream), "xpr_project_bwd")
 
 
 def xpr_render_bwd_workspace(views, cfg) -> int:

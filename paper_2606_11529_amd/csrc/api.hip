@@ -25,7 +25,7 @@ hipError_t bin_phase2(const Batch& B, int sort_mode, int tile_bits, const float*
                       int32_t* vals, int2* ranges, void* ws, size_t ws_bytes, hipStream_t st);
 hipError_t launch_render_fwd(const Batch& B, int lds_batch, const float* splat,
                              const int32_t* vals, const int32_t* ranges, float* image, float* Tfin,
-                             int32_t* ncon, hipStream_t st);
+                             int32_t* ncon, int32_t* tile_work, hipStream_t st);
 hipError_t launch_render_bwd(const Batch& B, int lds_batch, const float* splat,
                              const int32_t* vals, const int32_t* ranges, const float* dimg,
                              const float* Tfin, const int32_t* ncon, float* grad2d,
@@ -191,6 +191,22 @@ static xpr_status check_proj(const xpr_projected* p, const Sizes& S) {
   return XPR_OK;
 }
 
+static xpr_status check_grads(const xpr_views* views, const xpr_scene_grad* grads, GradDev* G) {
+  std::memset(G, 0, sizeof(GradDev) * XPR_MAX_SCENES);
+  for (int s = 0; s < views->n_scenes; ++s) {
+    const xpr_scene_grad& g = grads[s];
+    if (views->scenes[s].n > 0) {
+      XPR_CHECK(g.means && g.scales && g.quats && g.opacities && g.sh,
+                "scene %d: NULL gradient buffer", s);
+      XPR_CHECK(aligned(g.means, 4) && aligned(g.scales, 4) && aligned(g.quats, 4) &&
+                    aligned(g.opacities, 4) && aligned(g.sh, 4),
+                "scene %d: misaligned gradient buffer", s);
+    }
+    G[s] = GradDev{g.means, g.scales, g.quats, g.opacities, g.sh};
+  }
+  return XPR_OK;
+}
+
 }  // namespace xpr
 
 using namespace xpr;
@@ -304,7 +320,8 @@ xpr_status xpr_bin_sort(const xpr_views* views, const xpr_config* cfg, const xpr
 
 xpr_status xpr_render_fwd(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
                           const int32_t* vals, const int32_t* tile_ranges, float* image,
-                          float* T_final, int32_t* n_contrib, hipStream_t stream) {
+                          float* T_final, int32_t* n_contrib, int32_t* tile_work,
+                          hipStream_t stream) {
   g_err[0] = 0;
   Batch B;
   Sizes S;
@@ -316,8 +333,9 @@ xpr_status xpr_render_fwd(const xpr_views* views, const xpr_config* cfg, const x
   XPR_CHECK(aligned(tile_ranges, 8) && aligned(image, 4) && aligned(T_final, 4) &&
                 aligned(n_contrib, 4) && (!vals || aligned(vals, 4)),
             "misaligned buffer");
+  XPR_CHECK(!tile_work || aligned(tile_work, 4), "misaligned tile_work");
   XPR_HIP(launch_render_fwd(B, cfg->lds_batch, proj->splat, vals, tile_ranges, image, T_final,
-                            n_contrib, stream));
+                            n_contrib, tile_work, stream));
   return XPR_OK;
 }
 
@@ -344,7 +362,8 @@ xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const x
   if (st != XPR_OK) return st;
   st = check_proj(proj, S);
   if (st != XPR_OK) return st;
-  XPR_CHECK(tile_ranges && dL_dimage && T_final && n_contrib && grads, "NULL buffer");
+  XPR_CHECK(tile_ranges && dL_dimage && T_final && n_contrib, "NULL buffer");
+  XPR_CHECK(grads || grad2d, "grads and grad2d both NULL");
   XPR_CHECK(aligned(dL_dimage, 4) && aligned(T_final, 4) && aligned(n_contrib, 4) &&
                 aligned(tile_ranges, 8) && (!grad2d || aligned(grad2d, 4)),
             "misaligned buffer");
@@ -356,22 +375,35 @@ xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const x
     g2 = static_cast<float*>(ws);
   }
   GradDev G[XPR_MAX_SCENES];
-  std::memset(G, 0, sizeof(G));
-  for (int s = 0; s < views->n_scenes; ++s) {
-    const xpr_scene_grad& g = grads[s];
-    if (views->scenes[s].n > 0) {
-      XPR_CHECK(g.means && g.scales && g.quats && g.opacities && g.sh,
-                "scene %d: NULL gradient buffer", s);
-      XPR_CHECK(aligned(g.means, 4) && aligned(g.scales, 4) && aligned(g.quats, 4) &&
-                    aligned(g.opacities, 4) && aligned(g.sh, 4),
-                "scene %d: misaligned gradient buffer", s);
-    }
-    G[s] = GradDev{g.means, g.scales, g.quats, g.opacities, g.sh};
+  if (grads) {
+    st = check_grads(views, grads, G);
+    if (st != XPR_OK) return st;
   }
   XPR_HIP(fill_zero_f32(g2, 9 * S.records, stream));
   XPR_HIP(launch_render_bwd(B, cfg->lds_batch, proj->splat, vals, tile_ranges, dL_dimage, T_final,
                             n_contrib, g2, stream));
-  XPR_HIP(launch_project_bwd(B, S.max_n, g2, proj->tiles_touched, G, accumulate ? 1 : 0, stream));
+  if (grads)
+    XPR_HIP(launch_project_bwd(B, S.max_n, g2, proj->tiles_touched, G, accumulate ? 1 : 0, stream));
+  return XPR_OK;
+}
+
+xpr_status xpr_project_bwd(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
+                           const float* grad2d, const xpr_scene_grad* grads, int32_t accumulate,
+                           hipStream_t stream) {
+  g_err[0] = 0;
+  Batch B;
+  Sizes S;
+  xpr_status st = build_batch(views, cfg, &B, &S);
+  if (st != XPR_OK) return st;
+  st = check_proj(proj, S);
+  if (st != XPR_OK) return st;
+  XPR_CHECK(grads != nullptr, "grads is NULL");
+  XPR_CHECK(S.records == 0 || (grad2d && aligned(grad2d, 4)), "grad2d NULL or misaligned");
+  GradDev G[XPR_MAX_SCENES];
+  st = check_grads(views, grads, G);
+  if (st != XPR_OK) return st;
+  XPR_HIP(launch_project_bwd(B, S.max_n, grad2d, proj->tiles_touched, G, accumulate ? 1 : 0,
+                             stream));
   return XPR_OK;
 }
 

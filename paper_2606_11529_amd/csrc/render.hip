@@ -38,7 +38,8 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(Batch B, const float4* __
                                                        const int2* __restrict__ ranges,
                                                        float* __restrict__ image,
                                                        float* __restrict__ Tfin,
-                                                       int32_t* __restrict__ ncon) {
+                                                       int32_t* __restrict__ ncon,
+                                                       int32_t* __restrict__ tile_work) {
   constexpr int NT = TW * TH;
   __shared__ float4 s0[BATCH];
   __shared__ float4 s1[BATCH];
@@ -56,8 +57,10 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(Batch B, const float4* __
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   int last = 0;
   bool done = !inside;
+  int walked = 0;
   for (int base = rg.x; base < rg.y; base += BATCH) {
     if (__syncthreads_count(!done) == 0) break;
+    walked = min(BATCH, rg.y - base) + (base - rg.x);
     for (int k = threadIdx.x; k < BATCH; k += NT) {
       const int idx = base + k;
       if (idx < rg.y) {
@@ -99,6 +102,7 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(Batch B, const float4* __
     Tfin[(size_t)V.pix_off + p] = T;
     ncon[(size_t)V.pix_off + p] = last;
   }
+  if (tile_work && threadIdx.x == 0) tile_work[g] = walked;
 }
 
 // Backward of the compositing. Each pixel walks its list in reverse from
@@ -227,15 +231,15 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd(Batch B, const float4* __
 template <int TW, int TH>
 static hipError_t launch_fwd_t(const Batch& B, int lds_batch, const float* splat,
                                const int32_t* vals, const int32_t* ranges, float* image,
-                               float* Tfin, int32_t* ncon, hipStream_t st) {
+                               float* Tfin, int32_t* ncon, int32_t* tw, hipStream_t st) {
   const dim3 grid(B.total_tiles), block(TW * TH);
   const float4* sp = reinterpret_cast<const float4*>(splat);
   const int2* rg = reinterpret_cast<const int2*>(ranges);
   switch (lds_batch) {
-    case 64: hipLaunchKernelGGL((k_render_fwd<TW, TH, 64>), grid, block, 0, st, B, sp, vals, rg, image, Tfin, ncon); break;
-    case 128: hipLaunchKernelGGL((k_render_fwd<TW, TH, 128>), grid, block, 0, st, B, sp, vals, rg, image, Tfin, ncon); break;
-    case 512: hipLaunchKernelGGL((k_render_fwd<TW, TH, 512>), grid, block, 0, st, B, sp, vals, rg, image, Tfin, ncon); break;
-    default: hipLaunchKernelGGL((k_render_fwd<TW, TH, 256>), grid, block, 0, st, B, sp, vals, rg, image, Tfin, ncon); break;
+    case 64: hipLaunchKernelGGL((k_render_fwd<TW, TH, 64>), grid, block, 0, st, B, sp, vals, rg, image, Tfin, ncon, tw); break;
+    case 128: hipLaunchKernelGGL((k_render_fwd<TW, TH, 128>), grid, block, 0, st, B, sp, vals, rg, image, Tfin, ncon, tw); break;
+    case 512: hipLaunchKernelGGL((k_render_fwd<TW, TH, 512>), grid, block, 0, st, B, sp, vals, rg, image, Tfin, ncon, tw); break;
+    default: hipLaunchKernelGGL((k_render_fwd<TW, TH, 256>), grid, block, 0, st, B, sp, vals, rg, image, Tfin, ncon, tw); break;
   }
   return hipGetLastError();
 }
@@ -259,10 +263,11 @@ static hipError_t launch_bwd_t(const Batch& B, int lds_batch, const float* splat
 
 hipError_t launch_render_fwd(const Batch& B, int lds_batch, const float* splat,
                              const int32_t* vals, const int32_t* ranges, float* image, float* Tfin,
-                             int32_t* ncon, hipStream_t st) {
+                             int32_t* ncon, int32_t* tile_work, hipStream_t st) {
   if (B.total_tiles <= 0) return hipSuccess;
-  if (B.tile_w == 8) return launch_fwd_t<8, 8>(B, lds_batch, splat, vals, ranges, image, Tfin, ncon, st);
-  return launch_fwd_t<16, 16>(B, lds_batch, splat, vals, ranges, image, Tfin, ncon, st);
+  if (B.tile_w == 8)
+    return launch_fwd_t<8, 8>(B, lds_batch, splat, vals, ranges, image, Tfin, ncon, tile_work, st);
+  return launch_fwd_t<16, 16>(B, lds_batch, splat, vals, ranges, image, Tfin, ncon, tile_work, st);
 }
 
 hipError_t launch_render_bwd(const Batch& B, int lds_batch, const float* splat,

@@ -252,38 +252,54 @@ def xpr_bin_sort(views: Views, cfg: Config, proj: Projected, capacity: Optional[
 
 
 def xpr_render_fwd(views: Views, cfg: Config, proj: Projected, bins: Bins,
-                   out: Optional[Frame] = None) -> Frame:
+                   out: Optional[Frame] = None, tile_work: Optional[torch.Tensor] = None) -> Frame:
     dev = proj.splat.device
     if out is None:
         out = Frame(torch.empty(3 * views.pixels, dtype=torch.float32, device=dev),
                     torch.empty(views.pixels, dtype=torch.float32, device=dev),
                     torch.empty(views.pixels, dtype=torch.int32, device=dev))
     L.xpr_render_fwd(views.c, views.cfg_c, proj.to_c(), _ptr(bins.vals), _ptr(bins.ranges),
-                     _ptr(out.image), _ptr(out.T_final), _ptr(out.n_contrib), _stream())
+                     _ptr(out.image), _ptr(out.T_final), _ptr(out.n_contrib), _ptr(tile_work),
+                     _stream())
     return out
+
+
+def _grads_c(grads):
+    return (L.XprSceneGrad * len(grads))(*[
+        L.XprSceneGrad(g["means"].data_ptr(), g["scales"].data_ptr(), g["quats"].data_ptr(),
+                       g["opacities"].data_ptr(), g["sh"].data_ptr()) for g in grads])
 
 
 def xpr_render_bwd(views: Views, cfg: Config, proj: Projected, bins: Bins, frame: Frame,
                    dimage: torch.Tensor, grads: Optional[List[dict]] = None,
                    accumulate: bool = False, want_grad2d: bool = False,
-                   ws: Optional[Workspace] = None):
-    """Returns (grads per scene, grad2d or None)."""
+                   ws: Optional[Workspace] = None, params: bool = True,
+                   grad2d: Optional[torch.Tensor] = None):
+    """Returns (grads per scene or None, grad2d or None). With params=False
+    only the compositing backward runs and grad2d [records, 9] is returned."""
     ws = ws or _WS
     dev = proj.splat.device
-    if grads is None:
+    if params and grads is None:
         grads = [s.zeros_like_grads() for s in views.scenes]
-    arr = (L.XprSceneGrad * len(grads))(*[
-        L.XprSceneGrad(g["means"].data_ptr(), g["scales"].data_ptr(), g["quats"].data_ptr(),
-                       g["opacities"].data_ptr(), g["sh"].data_ptr()) for g in grads])
+    arr = _grads_c(grads) if params else None
     dimage = dimage.contiguous()
-    grad2d = torch.empty((max(views.records, 1), 9), dtype=torch.float32, device=dev) \
-        if want_grad2d else None
+    if grad2d is None and (want_grad2d or not params):
+        grad2d = torch.empty((max(views.records, 1), 9), dtype=torch.float32, device=dev)
     nbytes = L.xpr_render_bwd_workspace(views.c, views.cfg_c)
     wsb = ws.get("bwd", nbytes, dev)
     L.xpr_render_bwd(views.c, views.cfg_c, proj.to_c(), _ptr(bins.vals), _ptr(bins.ranges),
                      _ptr(dimage), _ptr(frame.T_final), _ptr(frame.n_contrib), arr,
                      1 if accumulate else 0, _ptr(grad2d), _ptr(wsb), wsb.numel(), _stream())
-    return grads, grad2d
+    return (grads if params else None), grad2d
+
+
+def xpr_project_bwd(views: Views, cfg: Config, proj: Projected, grad2d: torch.Tensor,
+                    grads: Optional[List[dict]] = None, accumulate: bool = False):
+    if grads is None:
+        grads = [s.zeros_like_grads() for s in views.scenes]
+    L.xpr_project_bwd(views.c, views.cfg_c, proj.to_c(), _ptr(grad2d), _grads_c(grads),
+                      1 if accumulate else 0, _stream())
+    return grads
 
 
 def render(scene: Scene, cam, cfg: Config, want_keys: bool = False):

@@ -88,8 +88,10 @@ def check_projection(sc, cam, cfg, gpu, rec_off=0, idx=None):
     assert np.array_equal(g_rect[vr], ref["rect"][vr]), "rect mismatch"
     # floats, on Gaussians visible on both sides
     m = vis
-    uv_err = np.abs(g_rec[m, :2] - ref["rec"][m, :2]) / np.maximum(1.0, np.abs(ref["rec"][m, :2]))
-    assert uv_err.max(initial=0) <= 2e-6, f"mean2D rel err {uv_err.max()}"
+    # mean2D against the oracle's float32 rounding scale (condition-aware:
+    # the camera-space mean's rounding is amplified by f / z)
+    uv_err = np.abs(g_rec[m, :2] - ref["rec"][m, :2]) / ref["tol_uv"][m]
+    assert uv_err.max(initial=0) <= 1.0, f"mean2D error {uv_err.max()} x bound"
     d_err = np.abs(g_depth[m] - ref["depth"][m]) / np.maximum(1.0, np.abs(ref["depth"][m]))
     assert d_err.max(initial=0) <= 2e-6, f"depth err {d_err.max()}"
     c_err = np.abs(g_rec[m, 6:9] - ref["rec"][m, 6:9])
@@ -103,7 +105,9 @@ def check_projection(sc, cam, cfg, gpu, rec_off=0, idx=None):
     con_ref = ref["rec"][m, 2:5]
     scale = np.abs(con_ref).max(axis=1, keepdims=True)
     con_err = np.abs(g_rec[m, 2:5] - con_ref) / scale
-    lim = 1e-6 * cond[:, None] + 1e-6
+    # ~40 float32 roundings from the inputs to the 2D covariance, amplified by
+    # the condition number in the inverse: 64 eps (cond + 1)
+    lim = 64 * 2.0 ** -24 * (cond[:, None] + 1.0)
     worst = (con_err / lim).max(initial=0)
     assert worst <= 1.0, f"conic error {worst} x bound"
     return int(guard.sum()), int(n)
@@ -140,8 +144,10 @@ def check_forward(gpu, cam, cfg, v=0, ranges=None, pixel_mask=None):
     emax = float(err.max(initial=0))
     assert emax <= TOL_PIXEL, f"pixel max-abs {emax} > {TOL_PIXEL}"
     assert np.array_equal(gpu["ncontrib"][v][sel], ref["ncontrib"][sel]), "n_contrib differs"
-    terr = np.abs(gpu["Tfinal"][v][sel] - ref["Tfinal"][sel]) / ref["Tfinal"][sel]
-    assert terr.max(initial=0) <= 1e-5, f"T_final rel err {terr.max()}"
+    # absolute, like the colour: after a Gaussian with alpha near alpha_max the
+    # relative error of T is amplified by 1 / (1 - alpha) ~ 100
+    terr = np.abs(gpu["Tfinal"][v][sel] - ref["Tfinal"][sel])
+    assert terr.max(initial=0) <= TOL_PIXEL, f"T_final abs err {terr.max()}"
     gsel = guard if pixel_mask is None else (guard & pixel_mask)
     if gsel.any():
         gerr = np.abs(img - ref["img"])[:, gsel].max()
@@ -149,12 +155,18 @@ def check_forward(gpu, cam, cfg, v=0, ranges=None, pixel_mask=None):
     return emax, int(gsel.sum()), ref
 
 
-def guard_records(ref_fwd, ranges, vals, tile, tiles_x):
-    """Records listed in any tile that holds a guard pixel."""
+def guard_records(ref_fwd, gpu_ncontrib, ranges, vals, tile, tiles_x):
+    """Records whose gradient a guard-band decision can reach: at each guard
+    pixel, the prefix of its tile's list up to one past the later of the two
+    last-blended positions (a flip changes T for later entries and the
+    colour-behind of earlier ones)."""
     gy, gx = np.nonzero(ref_fwd["guard"])
-    tiles = np.unique((gy // tile) * tiles_x + gx // tile)
-    out = [vals[ranges[t, 0]:ranges[t, 1]] for t in tiles]
-    return np.unique(np.concatenate(out)) if out else np.zeros(0, np.int64)
+    if gy.size == 0:
+        return np.zeros(0, np.int64)
+    t = (gy // tile) * tiles_x + gx // tile
+    n = np.maximum(ref_fwd["ncontrib"][gy, gx], gpu_ncontrib[gy, gx]) + 1
+    out = [vals[ranges[tt, 0]:min(ranges[tt, 1], ranges[tt, 0] + nn)] for tt, nn in zip(t, n)]
+    return np.unique(np.concatenate(out))
 
 
 def rel_check(got, ref, name, mask=None, tol=TOL_GRAD):

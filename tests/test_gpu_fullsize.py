@@ -1,0 +1,121 @@
+"""Parity at the full benchmark size (3M Gaussians, SH degree 3, 1600x1064,
+16x16 tiles), in the launch configuration the bench times, on sampled
+outputs the oracle computes one by one: 100k sampled Gaussians for the
+projection, 48 sampled tiles for binning (their complete lists), forward
+compositing and gradients (dL/dimage restricted to those tiles), plus
+size-independent properties of the whole pair list."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import (check_forward, check_projection, guard_records, log, ocfg_of, rec9,
+                      rel_check, run_gpu)
+from paper_2606_11529_amd import renderer as R
+from synth import random_cameras, scene_clusters
+
+pytestmark = pytest.mark.gpu
+
+_STATE = {}
+
+
+def _state():
+    if not _STATE:
+        log("[full] generating 3M-Gaussian scene")
+        sc = scene_clusters(3_000_000, seed=0)
+        cam = random_cameras(8, 0, (1600, 1064))[0]
+        cfg = R.Config()
+        H, W = cam.height, cam.width
+        tx, ty = (W + 15) // 16, (H + 15) // 16
+        g = run_gpu(sc, cam, cfg)
+        rng = np.random.default_rng(3)
+        nonempty = np.nonzero(g["ranges"][:, 1] > g["ranges"][:, 0])[0]
+        tiles = np.sort(rng.choice(nonempty, 48, replace=False))
+        mask = np.zeros((H, W), bool)
+        for t in tiles:
+            y, x = divmod(int(t), tx)
+            mask[16 * y:16 * y + 16, 16 * x:16 * x + 16] = True
+        dimg = (rng.normal(size=(3, H, W)) * mask[None]).astype(np.float32) / (3 * W * H)
+        log(f"[full] I={g['I']} sampled tiles={tiles.size}")
+        _STATE.update(sc=sc, cam=cam, cfg=cfg, g=g, tiles=tiles, mask=mask, dimg=dimg,
+                      tx=tx, ty=ty)
+    return _STATE
+
+
+def test_fullsize_projection_sampled():
+    s = _state()
+    idx = np.sort(np.random.default_rng(4).choice(s["sc"].n, 100_000, replace=False))
+    ng, n = check_projection(s["sc"], s["cam"], s["cfg"], s["g"], idx=idx)
+    log(f"[full P1] {n} checked, {ng} guard")
+
+
+def test_fullsize_binning_sampled_tiles_and_invariants():
+    s = _state()
+    g, tx = s["g"], s["tx"]
+    # whole-list invariants
+    assert g["I"] == int(g["tc"].astype(np.int64).sum())
+    keys = g["keys"]
+    assert np.all(keys[1:] >= keys[:-1]), "keys not sorted"
+    tile_of = (keys >> np.uint64(32)).astype(np.int64)
+    starts = np.flatnonzero(np.r_[True, tile_of[1:] != tile_of[:-1]])
+    ends = np.r_[starts[1:], keys.size]
+    r = g["ranges"]
+    assert np.array_equal(r[tile_of[starts], 0], starts) and np.array_equal(r[tile_of[starts], 1], ends)
+    assert np.all(r[np.setdiff1d(np.arange(r.shape[0]), tile_of[starts])] == 0)
+    assert np.array_equal(keys & np.uint64(0xffffffff),
+                          g["depth"][g["vals"]].view(np.uint32).astype(np.uint64))
+    # sampled tiles: the oracle's complete lists from the records touching them
+    rect = g["rect"]
+    touch = np.zeros(rect.shape[0], bool)
+    for t in s["tiles"]:
+        y, x = divmod(int(t), tx)
+        touch |= (g["tc"] > 0) & (rect[:, 0] <= x) & (x < rect[:, 2]) & (rect[:, 1] <= y) & (y < rect[:, 3])
+    sub = np.flatnonzero(touch)
+    ref = oracle.bin_pairs(g["depth"][sub].astype(np.float64), rect[sub], g["tc"][sub], tx, s["ty"])
+    for t in s["tiles"]:
+        a, b = ref["ranges"][t]
+        want = sub[ref["vals"][a:b]]
+        got = g["vals"][r[t, 0]:r[t, 1]]
+        assert np.array_equal(got, want), f"tile {t}"
+    log(f"[full P2] {len(s['tiles'])} tiles bit-exact, {sub.size} records")
+
+
+def _masked_ranges(s):
+    r = np.zeros_like(s["g"]["ranges"])
+    r[s["tiles"]] = s["g"]["ranges"][s["tiles"]]
+    return r
+
+
+def test_fullsize_forward_sampled_tiles():
+    s = _state()
+    emax, ng, _ = check_forward(s["g"], s["cam"], s["cfg"], ranges=_masked_ranges(s),
+                                pixel_mask=s["mask"])
+    log(f"[full P3] max-abs {emax:.2e}, guard {ng}")
+
+
+def test_fullsize_backward_sampled_tiles():
+    s = _state()
+    sc, cam, cfg = s["sc"], s["cam"], s["cfg"]
+    oc = ocfg_of(cfg)
+    g = run_gpu(sc, cam, cfg, dimgs=[s["dimg"]], want_keys=False)
+    assert np.array_equal(g["vals"], s["g"]["vals"])
+    rg = _masked_ranges(s)
+    r9 = rec9(g["splat"])
+    ref_f = oracle.render_fwd(r9, g["vals"], rg, cam.width, cam.height, oc)
+    g9 = oracle.render_bwd(r9, g["vals"], rg, cam.width, cam.height, oc, s["dimg"].astype(np.float64))
+    excl = guard_records(ref_f, g["ncontrib"][0], rg, g["vals"], cfg.tile, s["tx"])
+    touched = np.unique(np.concatenate([g["vals"][rg[t, 0]:rg[t, 1]] for t in s["tiles"]]))
+    keep = np.zeros(sc.n, bool)
+    keep[touched] = True
+    keep[excl] = False
+    w = rel_check(g["grad2d"], g9, "grad2d", keep)
+    # untouched records receive exactly nothing
+    assert np.all(g["grad2d"][~np.isin(np.arange(sc.n), touched)] == 0)
+    idx = np.flatnonzero(keep & (g["tc"] > 0))
+    ref_p = oracle.project_bwd(sc.subset(idx), cam, oc, g["grad2d"][idx].astype(np.float64))
+    worst = {}
+    for k in ("means", "scales", "quats", "opacities", "sh"):
+        gk = g["grads"][k][..., idx]
+        rk = ref_p[k]
+        worst[k] = rel_check(gk.reshape(-1, idx.size).T, rk.reshape(-1, idx.size).T, k)
+    log(f"[full P4] grad2d {w:.2e} x bound over {keep.sum()} records, params {worst}")

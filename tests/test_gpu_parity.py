@@ -82,7 +82,7 @@ def test_backward(name):
     g9 = oracle.render_bwd(r9, g["vals"], g["ranges"], cam.width, cam.height, oc,
                            dimg.astype(np.float64))
     tx, _ = oracle.tiles(cam, oc)
-    excl = guard_records(ref_f, g["ranges"], g["vals"], cfg.tile, tx)
+    excl = guard_records(ref_f, g["ncontrib"][0], g["ranges"], g["vals"], cfg.tile, tx)
     mask = np.ones(sc.n, bool)
     mask[excl] = False
     w2 = rel_check(g["grad2d"], g9, "grad2d", mask)
