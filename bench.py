@@ -46,6 +46,7 @@ def main():
     ap.add_argument("--lds-batch", type=int, default=256)
     ap.add_argument("--sort", default="presort")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -67,6 +68,16 @@ def main():
     log(f"[bench] scene {args.n} generated in {time.time() - t0:.1f}s")
     cfg = R.Config(tile=args.tile, lds_batch=args.lds_batch, sh_degree=3, sort_mode=args.sort)
     scene = R.Scene.from_host(sc, dev)
+    tuned = None
+    if not args.no_autotune:
+        # one-time search of the launch knobs on these views (tile size fixed:
+        # it is part of the workload); outside the timed region
+        from paper_2606_11529_amd.autotune import autotune
+        t0 = time.time()
+        tuned = autotune(scene, cams, cfg, tiles=(args.tile,), reps=2)
+        cfg = tuned.apply(cfg)
+        log(f"[bench] autotune {time.time() - t0:.1f}s: sort {cfg.sort_mode}, fwd "
+            f"{cfg.lds_batch}x{cfg.fwd_ppt}, bwd {cfg.bwd_lds_batch}x{cfg.bwd_ppt}")
     gen = torch.Generator(device=dev)
     gen.manual_seed(7)
     H, W = args.height, args.width
@@ -197,7 +208,10 @@ def main():
         "config": {"workload": f"3DGS forward+backward, {nG} Gaussians (64 normal clusters, "
                                f"SH degree 3), {W}x{H}, {args.tile}x{args.tile} tiles, 8 cameras "
                                "on a radius-6 sphere, L1 loss vs U[0,1] target",
-                   "lds_batch": args.lds_batch, "sort": args.sort,
+                   "sort": cfg.sort_mode, "fwd_lds_batch": cfg.lds_batch,
+                   "fwd_ppt": cfg.fwd_ppt,
+                   "bwd_lds_batch": cfg.bwd_lds_batch or cfg.lds_batch,
+                   "bwd_ppt": cfg.bwd_ppt, "autotuned": tuned is not None,
                    "pairs_per_frame": pairs},
         "stage_sum_ms": round(frame_ms, 4),
         "stages_ms_median": med,
@@ -208,6 +222,8 @@ def main():
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, cams[0], cfg)
+    if tuned is not None:
+        out["autotune_ms"] = tuned.ms
     print(json.dumps(out), flush=True)
 
 

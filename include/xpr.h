@@ -77,7 +77,7 @@ typedef struct xpr_camera {
 /* Method constants and tuning knobs. Defaults: xpr_config_default(). */
 typedef struct xpr_config {
   int32_t tile_w, tile_h; /* 8x8 or 16x16 */
-  int32_t lds_batch;      /* Gaussians staged per LDS batch: 64,128,256,512 */
+  int32_t lds_batch;      /* Gaussians staged per LDS batch (forward): 64,128,256,512 */
   int32_t sh_degree;      /* 0..3 */
   float lowpass;          /* added to both diagonal entries of cov2D (0.3) */
   float alpha_min;        /* alpha_thresh of the listing (1/255) */
@@ -88,6 +88,9 @@ typedef struct xpr_config {
   float bg[3];            /* background colour (0, 0, 0) */
   int32_t sort_mode;      /* XPR_SORT_PRESORT or XPR_SORT_FULL */
   int32_t no_sync;        /* 1: never read back to the host (graph capture) */
+  int32_t fwd_ppt;        /* pixels per thread in the forward: 1, 2 or 4 (16x16 tiles) */
+  int32_t bwd_ppt;        /* pixels per thread in the backward: 1, 2 or 4 (16x16 tiles) */
+  int32_t bwd_lds_batch;  /* LDS batch of the backward (0: same as lds_batch) */
 } xpr_config;
 
 /* One scene of n Gaussians, structure of arrays with leading dimension ld:

@@ -60,7 +60,7 @@ def lib():
         P = ctypes.c_void_p
         i64, i32 = ctypes.c_int64, ctypes.c_int
         L.orc_project.argtypes = [i64, P, P, P, P, P, i32, P, i32, i32, P, i32, i32, i32,
-                                  P, P, P, P, P, P, P, P]
+                                  P, P, P, P, P, P, P]
         L.orc_project.restype = None
         L.orc_bin.argtypes = [i64, P, P, P, i32, i32, i64, P, P, P, P]
         L.orc_bin.restype = i64
@@ -123,14 +123,13 @@ def project(scene, cam, cfg: OracleConfig):
     K = sh.shape[0]
     out = dict(rec=np.zeros((n, 9)), cov=np.zeros((n, 3)), depth=np.zeros(n),
                rect=np.zeros((n, 4), np.int32), tc=np.zeros(n, np.int32),
-               radius=np.zeros(n, np.int32), guard=np.zeros(n, np.uint8),
-               tol_uv=np.zeros((n, 2)))
+               radius=np.zeros(n, np.int32), guard=np.zeros(n, np.uint8))
     cv = cam_vec(cam)
     pc = cfg.proj_cfg()
     lib().orc_project(n, _p(m), _p(s), _p(q), _p(o), _p(sh), K, _p(cv), cam.width,
                       cam.height, _p(pc), cfg.tile_w, cfg.tile_h, cfg.sh_degree,
                       _p(out["rec"]), _p(out["cov"]), _p(out["depth"]), _p(out["rect"]),
-                      _p(out["tc"]), _p(out["radius"]), _p(out["guard"]), _p(out["tol_uv"]))
+                      _p(out["tc"]), _p(out["radius"]), _p(out["guard"]))
     return out
 
 

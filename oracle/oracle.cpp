@@ -158,7 +158,6 @@ struct Proj {
   double dir[3], dirnorm;  // unit view direction and distance
   double raw[3], colour[3];
   double Y[16];
-  double tol_uv[2];      // float32 rounding scale of mean2D (guard band)
   bool guard;
 };
 
@@ -193,8 +192,8 @@ void project_one(int64_t i, int64_t n, const double* means, const double* scales
       P.Sigma[3 * r + c] = M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1] + M[3 * r + 2] * M[3 * c + 2];
 
   bool in_front = tz > z_near;
-  P.guard = std::fabs(tz - z_near) <= 1e-6 * std::max(1.0, std::fabs(z_near)) ||
-            std::fabs(o - alpha_min) <= 1e-6 * alpha_min;
+  P.guard = std::fabs(tz - z_near) <= 1e-9 * std::max(1.0, std::fabs(z_near)) ||
+            std::fabs(o - alpha_min) <= 1e-9 * alpha_min;
   if (in_front) {
     // EWA: J (perspective Jacobian at the clamped direction) times W.
     const double limx = fov_clip * cam.W / (2.0 * cam.fx);
@@ -221,7 +220,7 @@ void project_one(int64_t i, int64_t n, const double* means, const double* scales
     P.b = P.T[0] * ST1[0] + P.T[1] * ST1[1] + P.T[2] * ST1[2];
     P.c = P.T[3] * ST1[0] + P.T[4] * ST1[1] + P.T[5] * ST1[2] + lowpass;
     P.det = P.a * P.c - P.b * P.b;
-    if (std::fabs(P.det) <= 1e-6 * P.a * P.c) P.guard = true;
+    if (std::fabs(P.det) <= 1e-9 * P.a * P.c) P.guard = true;
     if (P.det > 0) {
       P.con[0] = P.c / P.det;
       P.con[1] = -P.b / P.det;
@@ -231,16 +230,6 @@ void project_one(int64_t i, int64_t n, const double* means, const double* scales
     // point f*X/Z + c is shifted by one half pixel.
     P.u = cam.fx * tx / tz + cam.cx - 0.5;
     P.v = cam.fy * ty / tz + cam.cy - 0.5;
-    // Scale of the float32 rounding of mean2D: the camera-space mean carries
-    // an error relative to the magnitude of its terms (S), which the
-    // perspective divide amplifies by f / z. Not part of the method: it sets
-    // the parity guard band and tolerance.
-    double S[3];
-    for (int r = 0; r < 3; ++r)
-      S[r] = std::fabs(cam.R[3 * r] * mu[0]) + std::fabs(cam.R[3 * r + 1] * mu[1]) +
-             std::fabs(cam.R[3 * r + 2] * mu[2]) + std::fabs(cam.t[r]);
-    P.tol_uv[0] = 1e-6 * (cam.fx * (S[0] + std::fabs(tx / tz) * S[2]) / tz + std::fabs(P.u) + 1.0);
-    P.tol_uv[1] = 1e-6 * (cam.fy * (S[1] + std::fabs(ty / tz) * S[2]) / tz + std::fabs(P.v) + 1.0);
     // 3-sigma radius of the largest eigenvalue.
     const double mid = 0.5 * (P.a + P.c);
     P.lambda = mid + std::sqrt(std::max(0.0, mid * mid - P.det));
@@ -259,12 +248,14 @@ void project_one(int64_t i, int64_t n, const double* means, const double* scales
     P.rect[2] = clampi(std::floor(fx1) + 1, 0, tiles_x);
     P.rect[3] = clampi(std::floor(fy1) + 1, 0, tiles_y);
     P.tc = (P.rect[2] - P.rect[0]) * (P.rect[3] - P.rect[1]);
-    // Guard band: the radius or a rect boundary within float32 reach of an
-    // integer (the rect boundaries move with mean2D only, r being integer).
-    const double gx = P.tol_uv[0] / tile_w + 1e-7 * std::max(1.0, std::fabs(fx0));
-    const double gy = P.tol_uv[1] / tile_h + 1e-7 * std::max(1.0, std::fabs(fy0));
-    if (near_int(r3, 1e-5 * std::max(1.0, r3)) || near_int(fx0, gx) || near_int(fx1, gx) ||
-        near_int(fy0, gy) || near_int(fy1, gy))
+    // Guard band of the parity protocol: the radius or a rect boundary within
+    // 1e-9 (relative) of an integer, where a float64 computation in another
+    // operation order may round the other way.
+    const double g = 1e-9;
+    if (near_int(r3, g * std::max(1.0, r3)) || near_int(fx0, g * std::max(1.0, std::fabs(fx0))) ||
+        near_int(fx1, g * std::max(1.0, std::fabs(fx1))) ||
+        near_int(fy0, g * std::max(1.0, std::fabs(fy0))) ||
+        near_int(fy1, g * std::max(1.0, std::fabs(fy1))))
       P.guard = true;
   }
   P.visible = in_front && P.det > 0 && o >= alpha_min && P.radius > 0 && P.tc > 0;
@@ -320,13 +311,11 @@ void orc_sh_basis(int deg, const double* d, double* Y, double* dY) {
 // Outputs (any may be NULL):
 //   rec [n][9]: u, v, -0.5*con00, -con01, -0.5*con11, o, r, g, b (shader data)
 //   cov [n][3]: a, b, c of the low-passed 2D covariance
-//   depth [n], rect [n][4] (x0, y0, x1, y1), tc [n], radius [n], guard [n],
-//   tol_uv [n][2] (float32 rounding scale of mean2D, for the parity checks)
+//   depth [n], rect [n][4] (x0, y0, x1, y1), tc [n], radius [n], guard [n]
 void orc_project(int64_t n, const double* means, const double* scales, const double* quats,
                  const double* opac, const double* sh, int K, const double* camv, int W, int H,
                  const double* cfg, int tile_w, int tile_h, int deg, double* rec, double* cov,
-                 double* depth, int32_t* rect, int32_t* tc, int32_t* radius, uint8_t* guard,
-                 double* tol_uv) {
+                 double* depth, int32_t* rect, int32_t* tc, int32_t* radius, uint8_t* guard) {
   const Cam cam = read_cam(camv, W, H);
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
@@ -345,7 +334,6 @@ void orc_project(int64_t n, const double* means, const double* scales, const dou
     if (tc) tc[i] = P.tc;
     if (radius) radius[i] = (int32_t)P.radius;
     if (guard) guard[i] = P.guard ? 1 : 0;
-    if (tol_uv) { tol_uv[2 * i] = P.tol_uv[0]; tol_uv[2 * i + 1] = P.tol_uv[1]; }
   }
 }
 

@@ -37,7 +37,8 @@ class XprConfig(ctypes.Structure):
     _fields_ = [("tile_w", _i32), ("tile_h", _i32), ("lds_batch", _i32), ("sh_degree", _i32),
                 ("lowpass", _f), ("alpha_min", _f), ("alpha_max", _f), ("t_min", _f),
                 ("z_near", _f), ("fov_clip", _f), ("bg", _f * 3), ("sort_mode", _i32),
-                ("no_sync", _i32)]
+                ("no_sync", _i32), ("fwd_ppt", _i32), ("bwd_ppt", _i32),
+                ("bwd_lds_batch", _i32)]
 
 
 class XprScene(ctypes.Structure):

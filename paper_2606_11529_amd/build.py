@@ -23,6 +23,8 @@ ARCH = "gfx950"
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-munsafe-fp-atomics",
+    # the backward already reduces across the wave before its atomics
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
     "-I", INCLUDE, "-I", CSRC,

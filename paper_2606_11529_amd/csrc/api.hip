@@ -23,10 +23,10 @@ hipError_t bin_phase2(const Batch& B, int sort_mode, int tile_bits, const float*
                       const int16_t* rect, const int32_t* tc, const uint32_t* perm, int64_t n_rec,
                       int64_t cap, int64_t grid_n, const int64_t* n_isect, uint64_t* keys_out,
                       int32_t* vals, int2* ranges, void* ws, size_t ws_bytes, hipStream_t st);
-hipError_t launch_render_fwd(const Batch& B, int lds_batch, const float* splat,
+hipError_t launch_render_fwd(const Batch& B, int lds_batch, int ppt, const float* splat,
                              const int32_t* vals, const int32_t* ranges, float* image, float* Tfin,
                              int32_t* ncon, int32_t* tile_work, hipStream_t st);
-hipError_t launch_render_bwd(const Batch& B, int lds_batch, const float* splat,
+hipError_t launch_render_bwd(const Batch& B, int lds_batch, int ppt, const float* splat,
                              const int32_t* vals, const int32_t* ranges, const float* dimg,
                              const float* Tfin, const int32_t* ncon, float* grad2d,
                              hipStream_t st);
@@ -85,6 +85,13 @@ static xpr_status check_config(const xpr_config* c) {
             "bg must be finite");
   XPR_CHECK(c->sort_mode == XPR_SORT_PRESORT || c->sort_mode == XPR_SORT_FULL,
             "sort_mode %d unknown", c->sort_mode);
+  XPR_CHECK(c->fwd_ppt == 1 || c->fwd_ppt == 2 || c->fwd_ppt == 4, "fwd_ppt %d not in {1,2,4}",
+            c->fwd_ppt);
+  XPR_CHECK(c->bwd_ppt == 1 || c->bwd_ppt == 2 || c->bwd_ppt == 4, "bwd_ppt %d not in {1,2,4}",
+            c->bwd_ppt);
+  XPR_CHECK(c->bwd_lds_batch == 0 || c->bwd_lds_batch == 64 || c->bwd_lds_batch == 128 ||
+                c->bwd_lds_batch == 256 || c->bwd_lds_batch == 512,
+            "bwd_lds_batch %d not in {0,64,128,256,512}", c->bwd_lds_batch);
   return XPR_OK;
 }
 
@@ -232,6 +239,9 @@ void xpr_config_default(xpr_config* c) {
   c->bg[0] = c->bg[1] = c->bg[2] = 0.f;
   c->sort_mode = XPR_SORT_PRESORT;
   c->no_sync = 0;
+  c->fwd_ppt = 2;
+  c->bwd_ppt = 4;
+  c->bwd_lds_batch = 0;
 }
 
 xpr_status xpr_batch_sizes(const xpr_views* views, const xpr_config* cfg, xpr_sizes* out) {
@@ -334,7 +344,7 @@ xpr_status xpr_render_fwd(const xpr_views* views, const xpr_config* cfg, const x
                 aligned(n_contrib, 4) && (!vals || aligned(vals, 4)),
             "misaligned buffer");
   XPR_CHECK(!tile_work || aligned(tile_work, 4), "misaligned tile_work");
-  XPR_HIP(launch_render_fwd(B, cfg->lds_batch, proj->splat, vals, tile_ranges, image, T_final,
+  XPR_HIP(launch_render_fwd(B, cfg->lds_batch, cfg->fwd_ppt, proj->splat, vals, tile_ranges, image, T_final,
                             n_contrib, tile_work, stream));
   return XPR_OK;
 }
@@ -380,7 +390,8 @@ xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const x
     if (st != XPR_OK) return st;
   }
   XPR_HIP(fill_zero_f32(g2, 9 * S.records, stream));
-  XPR_HIP(launch_render_bwd(B, cfg->lds_batch, proj->splat, vals, tile_ranges, dL_dimage, T_final,
+  const int bwd_lds = cfg->bwd_lds_batch ? cfg->bwd_lds_batch : cfg->lds_batch;
+  XPR_HIP(launch_render_bwd(B, bwd_lds, cfg->bwd_ppt, proj->splat, vals, tile_ranges, dL_dimage, T_final,
                             n_contrib, g2, stream));
   if (grads)
     XPR_HIP(launch_project_bwd(B, S.max_n, g2, proj->tiles_touched, G, accumulate ? 1 : 0, stream));

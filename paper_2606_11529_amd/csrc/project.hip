@@ -3,7 +3,7 @@
 //
 // Inputs are structure-of-arrays, so each component load of a wave is one
 // coalesced 256-byte read; the kernel is bound by HBM traffic (236 bytes in,
-// 64 bytes out per Gaussian at SH degree 3), not by its ~400 flops.
+// 64 bytes out per Gaussian at SH degree 3), not by its arithmetic.
 #include "xpr_internal.h"
 
 namespace xpr {
@@ -97,50 +97,58 @@ __device__ __forceinline__ void sh_basis_vjp(float x, float y, float z, const fl
 }
 
 // Everything the forward computes for one (view, Gaussian), kept so the
-// backward can reuse it after recomputation.
+// backward can reuse it after recomputation. The geometric chain runs in
+// FP64: on CDNA4 a double FMA issues at the per-lane rate of an unpacked
+// float one and this kernel is bound by HBM traffic, so the extra precision
+// is free, and it keeps the 2x2 inverse (condition numbers up to ~1e5 for
+// needle-like Gaussians near the camera) and its derivative accurate.
 struct ProjState {
-  float t[3];            // camera-space mean
-  float qn[4], qinv;     // unit quaternion, 1/|q|
-  float Rq[9];           // rotation of the Gaussian
-  float s[3];            // scales
-  float Sig[6];          // 3D covariance 00 01 02 11 12 22
-  float rx, ry;          // (clamped) tx/tz, ty/tz
+  double t[3];           // camera-space mean
+  double qn[4], qinv;    // unit quaternion, 1/|q|
+  double Rq[9];          // rotation of the Gaussian
+  double s[3];           // scales
+  double Sig[6];         // 3D covariance 00 01 02 11 12 22
+  double rx, ry;         // (clamped) tx/tz, ty/tz
   bool clampx, clampy;
-  float T0[3], T1[3];    // rows of J W
-  float a, b, c, det;    // low-passed 2D covariance
-  float con0, con1, con2;
-  float u, v;
+  double T0[3], T1[3];   // rows of J W
+  double a, b, c, det;   // low-passed 2D covariance
+  double con0, con1, con2;
+  double u, v;
   int rect[4];
   int tc;
-  float dir[3], dinv;    // unit view direction, 1/distance
+  double dir[3], dinv;   // unit view direction, 1/distance
 };
 
 template <int DEG>
 __device__ __forceinline__ void project_core(const Batch& B, const ViewDev& V, const SceneDev& S,
                                              int i, ProjState& P, float* colour, float* raw) {
-  const float mx = S.means[i], my = S.means[S.ld + i], mz = S.means[2 * S.ld + i];
-  P.t[0] = V.R[0] * mx + V.R[1] * my + V.R[2] * mz + V.t[0];
-  P.t[1] = V.R[3] * mx + V.R[4] * my + V.R[5] * mz + V.t[1];
-  P.t[2] = V.R[6] * mx + V.R[7] * my + V.R[8] * mz + V.t[2];
-  const float tx = P.t[0], ty = P.t[1], tz = P.t[2];
+  const double mx = S.means[i], my = S.means[S.ld + i], mz = S.means[2 * S.ld + i];
+  double R[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) R[k] = V.R[k];
+  P.t[0] = R[0] * mx + R[1] * my + R[2] * mz + (double)V.t[0];
+  P.t[1] = R[3] * mx + R[4] * my + R[5] * mz + (double)V.t[1];
+  P.t[2] = R[6] * mx + R[7] * my + R[8] * mz + (double)V.t[2];
+  const double tx = P.t[0], ty = P.t[1], tz = P.t[2];
+  const double fx = V.fx, fy = V.fy;
 
   // Sigma = Rq diag(s^2) Rq^T
-  const float qw = S.quats[i], qx = S.quats[S.ld + i], qy = S.quats[2 * S.ld + i],
-              qz = S.quats[3 * S.ld + i];
-  const float qlen = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
-  P.qinv = 1.f / qlen;
-  const float w = qw * P.qinv, x = qx * P.qinv, y = qy * P.qinv, z = qz * P.qinv;
+  const double qw = S.quats[i], qx = S.quats[S.ld + i], qy = S.quats[2 * S.ld + i],
+               qz = S.quats[3 * S.ld + i];
+  const double qlen = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  P.qinv = 1.0 / qlen;
+  const double w = qw * P.qinv, x = qx * P.qinv, y = qy * P.qinv, z = qz * P.qinv;
   P.qn[0] = w; P.qn[1] = x; P.qn[2] = y; P.qn[3] = z;
-  float* R = P.Rq;
-  R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z); R[2] = 2.f * (x * z + w * y);
-  R[3] = 2.f * (x * y + w * z); R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - w * x);
-  R[6] = 2.f * (x * z - w * y); R[7] = 2.f * (y * z + w * x); R[8] = 1.f - 2.f * (x * x + y * y);
+  double* Q = P.Rq;
+  Q[0] = 1.0 - 2.0 * (y * y + z * z); Q[1] = 2.0 * (x * y - w * z); Q[2] = 2.0 * (x * z + w * y);
+  Q[3] = 2.0 * (x * y + w * z); Q[4] = 1.0 - 2.0 * (x * x + z * z); Q[5] = 2.0 * (y * z - w * x);
+  Q[6] = 2.0 * (x * z - w * y); Q[7] = 2.0 * (y * z + w * x); Q[8] = 1.0 - 2.0 * (x * x + y * y);
   P.s[0] = S.scales[i]; P.s[1] = S.scales[S.ld + i]; P.s[2] = S.scales[2 * S.ld + i];
-  float M[9];
+  double M[9];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
-    for (int k = 0; k < 3; ++k) M[3 * r + k] = R[3 * r + k] * P.s[k];
+    for (int k = 0; k < 3; ++k) M[3 * r + k] = Q[3 * r + k] * P.s[k];
   P.Sig[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
   P.Sig[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
   P.Sig[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
@@ -149,66 +157,68 @@ __device__ __forceinline__ void project_core(const Batch& B, const ViewDev& V, c
   P.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
 
   // EWA: T = J W with J the perspective Jacobian at the clamped direction.
-  const float limx = B.fov_clip * (float)V.W / (2.f * V.fx);
-  const float limy = B.fov_clip * (float)V.H / (2.f * V.fy);
-  float rx = tx / tz, ry = ty / tz;
+  const double limx = (double)B.fov_clip * V.W / (2.0 * fx);
+  const double limy = (double)B.fov_clip * V.H / (2.0 * fy);
+  double rx = tx / tz, ry = ty / tz;
   P.clampx = P.clampy = false;
   if (B.fov_clip > 0.f) {
     P.clampx = rx < -limx || rx > limx;
     P.clampy = ry < -limy || ry > limy;
-    rx = fminf(limx, fmaxf(-limx, rx));
-    ry = fminf(limy, fmaxf(-limy, ry));
+    rx = fmin(limx, fmax(-limx, rx));
+    ry = fmin(limy, fmax(-limy, ry));
   }
   P.rx = rx; P.ry = ry;
-  const float j00 = V.fx / tz, j02 = -V.fx * rx / tz;
-  const float j11 = V.fy / tz, j12 = -V.fy * ry / tz;
+  const double j00 = fx / tz, j02 = -fx * rx / tz;
+  const double j11 = fy / tz, j12 = -fy * ry / tz;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    P.T0[k] = j00 * V.R[k] + j02 * V.R[6 + k];
-    P.T1[k] = j11 * V.R[3 + k] + j12 * V.R[6 + k];
+    P.T0[k] = j00 * R[k] + j02 * R[6 + k];
+    P.T1[k] = j11 * R[3 + k] + j12 * R[6 + k];
   }
-  const float* Sg = P.Sig;
-  const float S0[3] = {Sg[0] * P.T0[0] + Sg[1] * P.T0[1] + Sg[2] * P.T0[2],
-                       Sg[1] * P.T0[0] + Sg[3] * P.T0[1] + Sg[4] * P.T0[2],
-                       Sg[2] * P.T0[0] + Sg[4] * P.T0[1] + Sg[5] * P.T0[2]};
-  const float S1[3] = {Sg[0] * P.T1[0] + Sg[1] * P.T1[1] + Sg[2] * P.T1[2],
-                       Sg[1] * P.T1[0] + Sg[3] * P.T1[1] + Sg[4] * P.T1[2],
-                       Sg[2] * P.T1[0] + Sg[4] * P.T1[1] + Sg[5] * P.T1[2]};
-  P.a = P.T0[0] * S0[0] + P.T0[1] * S0[1] + P.T0[2] * S0[2] + B.lowpass;
+  const double* Sg = P.Sig;
+  const double S0[3] = {Sg[0] * P.T0[0] + Sg[1] * P.T0[1] + Sg[2] * P.T0[2],
+                        Sg[1] * P.T0[0] + Sg[3] * P.T0[1] + Sg[4] * P.T0[2],
+                        Sg[2] * P.T0[0] + Sg[4] * P.T0[1] + Sg[5] * P.T0[2]};
+  const double S1[3] = {Sg[0] * P.T1[0] + Sg[1] * P.T1[1] + Sg[2] * P.T1[2],
+                        Sg[1] * P.T1[0] + Sg[3] * P.T1[1] + Sg[4] * P.T1[2],
+                        Sg[2] * P.T1[0] + Sg[4] * P.T1[1] + Sg[5] * P.T1[2]};
+  const double lp = B.lowpass;
+  P.a = P.T0[0] * S0[0] + P.T0[1] * S0[1] + P.T0[2] * S0[2] + lp;
   P.b = P.T0[0] * S1[0] + P.T0[1] * S1[1] + P.T0[2] * S1[2];
-  P.c = P.T1[0] * S1[0] + P.T1[1] * S1[1] + P.T1[2] * S1[2] + B.lowpass;
+  P.c = P.T1[0] * S1[0] + P.T1[1] * S1[1] + P.T1[2] * S1[2] + lp;
   P.det = P.a * P.c - P.b * P.b;
-  const float dinv = P.det > 0.f ? 1.f / P.det : 0.f;
+  const double dinv = P.det > 0.0 ? 1.0 / P.det : 0.0;
   P.con0 = P.c * dinv;
   P.con1 = -P.b * dinv;
   P.con2 = P.a * dinv;
-  P.u = V.fx * tx / tz + V.cx - 0.5f;
-  P.v = V.fy * ty / tz + V.cy - 0.5f;
+  P.u = fx * tx / tz + (double)V.cx - 0.5;
+  P.v = fy * ty / tz + (double)V.cy - 0.5;
 
   // 3-sigma radius of the largest eigenvalue, tile rect, tile count.
-  const float mid = 0.5f * (P.a + P.c);
-  const float lam = mid + sqrtf(fmaxf(0.f, mid * mid - P.det));
-  const float rad = ceilf(3.f * sqrtf(lam));
-  const float itw = 1.f / (float)B.tile_w, ith = 1.f / (float)B.tile_h;
-  const float txn = (float)V.tiles_x, tyn = (float)V.tiles_y;
-  P.rect[0] = (int)fminf(txn, fmaxf(0.f, floorf((P.u - rad) * itw)));
-  P.rect[1] = (int)fminf(tyn, fmaxf(0.f, floorf((P.v - rad) * ith)));
-  P.rect[2] = (int)fminf(txn, fmaxf(0.f, floorf((P.u + rad) * itw) + 1.f));
-  P.rect[3] = (int)fminf(tyn, fmaxf(0.f, floorf((P.v + rad) * ith) + 1.f));
+  const double mid = 0.5 * (P.a + P.c);
+  const double lam = mid + sqrt(fmax(0.0, mid * mid - P.det));
+  const double rad = ceil(3.0 * sqrt(lam));
+  const double tw = B.tile_w, th = B.tile_h;
+  const double txn = V.tiles_x, tyn = V.tiles_y;
+  P.rect[0] = (int)fmin(txn, fmax(0.0, floor((P.u - rad) / tw)));
+  P.rect[1] = (int)fmin(tyn, fmax(0.0, floor((P.v - rad) / th)));
+  P.rect[2] = (int)fmin(txn, fmax(0.0, floor((P.u + rad) / tw) + 1.0));
+  P.rect[3] = (int)fmin(tyn, fmax(0.0, floor((P.v + rad) / th) + 1.0));
   const int area = (P.rect[2] - P.rect[0]) * (P.rect[3] - P.rect[1]);
   const float o = S.opac[i];
-  const bool visible = tz > B.z_near && P.det > 0.f && o >= B.alpha_min && rad > 0.f && area > 0;
+  const bool visible = tz > (double)B.z_near && P.det > 0.0 && o >= B.alpha_min && rad > 0.0 &&
+                       area > 0;
   P.tc = visible ? area : 0;
 
-  // View-dependent colour.
-  const float cpx = -(V.R[0] * V.t[0] + V.R[3] * V.t[1] + V.R[6] * V.t[2]);
-  const float cpy = -(V.R[1] * V.t[0] + V.R[4] * V.t[1] + V.R[7] * V.t[2]);
-  const float cpz = -(V.R[2] * V.t[0] + V.R[5] * V.t[1] + V.R[8] * V.t[2]);
-  const float dx = mx - cpx, dy = my - cpy, dz = mz - cpz;
-  P.dinv = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
+  // View-dependent colour (SH in float: a well-conditioned sum).
+  const double cpx = -(R[0] * V.t[0] + R[3] * V.t[1] + R[6] * V.t[2]);
+  const double cpy = -(R[1] * V.t[0] + R[4] * V.t[1] + R[7] * V.t[2]);
+  const double cpz = -(R[2] * V.t[0] + R[5] * V.t[1] + R[8] * V.t[2]);
+  const double dx = mx - cpx, dy = my - cpy, dz = mz - cpz;
+  P.dinv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
   P.dir[0] = dx * P.dinv; P.dir[1] = dy * P.dinv; P.dir[2] = dz * P.dinv;
   float Y[16];
-  sh_basis<DEG>(P.dir[0], P.dir[1], P.dir[2], Y);
+  sh_basis<DEG>((float)P.dir[0], (float)P.dir[1], (float)P.dir[2], Y);
   constexpr int NB = (DEG + 1) * (DEG + 1);
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) {
@@ -234,10 +244,11 @@ __global__ __launch_bounds__(256) void k_project(Batch B, float4* __restrict__ s
   project_core<DEG>(B, V, S, i, P, col, raw);
   const int r = V.rec_off + i;
   const float o = S.opac[i];
-  splat[3 * (size_t)r + 0] = make_float4(P.u, P.v, -0.5f * P.con0, -P.con1);
-  splat[3 * (size_t)r + 1] = make_float4(-0.5f * P.con2, o, col[0], col[1]);
+  splat[3 * (size_t)r + 0] =
+      make_float4((float)P.u, (float)P.v, (float)(-0.5 * P.con0), (float)(-P.con1));
+  splat[3 * (size_t)r + 1] = make_float4((float)(-0.5 * P.con2), o, col[0], col[1]);
   splat[3 * (size_t)r + 2] = make_float4(col[2], 0.f, 0.f, 0.f);
-  depth[r] = P.t[2];
+  depth[r] = (float)P.t[2];
   rect[r] = P.tc > 0 ? make_short4((short)P.rect[0], (short)P.rect[1], (short)P.rect[2],
                                    (short)P.rect[3])
                      : make_short4(0, 0, 0, 0);
@@ -260,7 +271,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(Batch B, const float* __res
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= S.n) return;
   constexpr int NB = (DEG + 1) * (DEG + 1);
-  float gmu[3] = {0.f, 0.f, 0.f}, gs[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f};
+  double gmu[3] = {0.0, 0.0, 0.0}, gs[3] = {0.0, 0.0, 0.0}, gq[4] = {0.0, 0.0, 0.0, 0.0};
   float go = 0.f;
   float gsh[NB][3];
 #pragma unroll
@@ -272,16 +283,21 @@ __global__ __launch_bounds__(256) void k_project_bwd(Batch B, const float* __res
     const int r = V.rec_off + i;
     if (tc[r] == 0) continue;
     const float* g = grad2d + 9 * (size_t)r;
-    const float gu = g[0], gv = g[1], gA = g[2], gB = g[3], gC = g[4];
+    const double gu = g[0], gv = g[1], gA = g[2], gB = g[3], gC = g[4];
     const float gcol[3] = {g[6], g[7], g[8]};
     go += g[5];
     ProjState P;
     float col[3], raw[3];
     project_core<DEG>(B, V, S, i, P, col, raw);
+    double R[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) R[k] = V.R[k];
+    const double fx = V.fx, fy = V.fy;
 
     // colour = max(0, 0.5 + sum_j sh_j Y_j(dir))
     float Y[16];
-    sh_basis<DEG>(P.dir[0], P.dir[1], P.dir[2], Y);
+    const float dxf = (float)P.dir[0], dyf = (float)P.dir[1], dzf = (float)P.dir[2];
+    sh_basis<DEG>(dxf, dyf, dzf, Y);
     float graw[3];
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) graw[ch] = raw[ch] > 0.f ? gcol[ch] : 0.f;
@@ -296,92 +312,93 @@ __global__ __launch_bounds__(256) void k_project_bwd(Batch B, const float* __res
       }
       wsum[j] = acc;
     }
-    float gdx, gdy, gdz;
-    sh_basis_vjp<DEG>(P.dir[0], P.dir[1], P.dir[2], wsum, gdx, gdy, gdz);
-    const float dd = P.dir[0] * gdx + P.dir[1] * gdy + P.dir[2] * gdz;
+    float gdxf, gdyf, gdzf;
+    sh_basis_vjp<DEG>(dxf, dyf, dzf, wsum, gdxf, gdyf, gdzf);
+    const double gdx = gdxf, gdy = gdyf, gdz = gdzf;
+    const double dd = P.dir[0] * gdx + P.dir[1] * gdy + P.dir[2] * gdz;
     gmu[0] += (gdx - P.dir[0] * dd) * P.dinv;
     gmu[1] += (gdy - P.dir[1] * dd) * P.dinv;
     gmu[2] += (gdz - P.dir[2] * dd) * P.dinv;
 
     // conic entries: con0 = c/det, con1 = -b/det, con2 = a/det
-    const float gk0 = -0.5f * gA, gk1 = -gB, gk2 = -0.5f * gC;
-    const float a = P.a, b = P.b, c = P.c;
-    const float id2 = 1.f / (P.det * P.det);
-    const float ga = (-c * c * gk0 + b * c * gk1 - b * b * gk2) * id2;
-    const float gb = (2.f * b * c * gk0 - (a * c + b * b) * gk1 + 2.f * a * b * gk2) * id2;
-    const float gc = (-b * b * gk0 + a * b * gk1 - a * a * gk2) * id2;
+    const double gk0 = -0.5 * gA, gk1 = -gB, gk2 = -0.5 * gC;
+    const double a = P.a, b = P.b, c = P.c;
+    const double id2 = 1.0 / (P.det * P.det);
+    const double ga = (-c * c * gk0 + b * c * gk1 - b * b * gk2) * id2;
+    const double gb = (2.0 * b * c * gk0 - (a * c + b * b) * gk1 + 2.0 * a * b * gk2) * id2;
+    const double gc = (-b * b * gk0 + a * b * gk1 - a * a * gk2) * id2;
 
     // a = T0 Sig T0, b = T0 Sig T1, c = T1 Sig T1 (Sig symmetric)
-    const float* T0 = P.T0;
-    const float* T1 = P.T1;
-    const float* Sg = P.Sig;
-    const float ST0[3] = {Sg[0] * T0[0] + Sg[1] * T0[1] + Sg[2] * T0[2],
-                          Sg[1] * T0[0] + Sg[3] * T0[1] + Sg[4] * T0[2],
-                          Sg[2] * T0[0] + Sg[4] * T0[1] + Sg[5] * T0[2]};
-    const float ST1[3] = {Sg[0] * T1[0] + Sg[1] * T1[1] + Sg[2] * T1[2],
-                          Sg[1] * T1[0] + Sg[3] * T1[1] + Sg[4] * T1[2],
-                          Sg[2] * T1[0] + Sg[4] * T1[1] + Sg[5] * T1[2]};
-    float gT0[3], gT1[3];
+    const double* T0 = P.T0;
+    const double* T1 = P.T1;
+    const double* Sg = P.Sig;
+    const double ST0[3] = {Sg[0] * T0[0] + Sg[1] * T0[1] + Sg[2] * T0[2],
+                           Sg[1] * T0[0] + Sg[3] * T0[1] + Sg[4] * T0[2],
+                           Sg[2] * T0[0] + Sg[4] * T0[1] + Sg[5] * T0[2]};
+    const double ST1[3] = {Sg[0] * T1[0] + Sg[1] * T1[1] + Sg[2] * T1[2],
+                           Sg[1] * T1[0] + Sg[3] * T1[1] + Sg[4] * T1[2],
+                           Sg[2] * T1[0] + Sg[4] * T1[1] + Sg[5] * T1[2]};
+    double gT0[3], gT1[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      gT0[k] = 2.f * ga * ST0[k] + gb * ST1[k];
-      gT1[k] = gb * ST0[k] + 2.f * gc * ST1[k];
+      gT0[k] = 2.0 * ga * ST0[k] + gb * ST1[k];
+      gT1[k] = gb * ST0[k] + 2.0 * gc * ST1[k];
     }
-    // symmetric dL/dSigma (full matrix G + G^T): Gs[r][s] for r <= s
-    float Gs[3][3];
+    // symmetric dL/dSigma (full matrix G + G^T)
+    double Gs[3][3];
 #pragma unroll
     for (int r2 = 0; r2 < 3; ++r2)
 #pragma unroll
       for (int s2 = 0; s2 < 3; ++s2)
-        Gs[r2][s2] = 2.f * ga * T0[r2] * T0[s2] + gb * (T0[r2] * T1[s2] + T1[r2] * T0[s2]) +
-                     2.f * gc * T1[r2] * T1[s2];
+        Gs[r2][s2] = 2.0 * ga * T0[r2] * T0[s2] + gb * (T0[r2] * T1[s2] + T1[r2] * T0[s2]) +
+                     2.0 * gc * T1[r2] * T1[s2];
 
     // T = J W: only J00, J02, J11, J12 are non-zero
-    const float gJ00 = gT0[0] * V.R[0] + gT0[1] * V.R[1] + gT0[2] * V.R[2];
-    const float gJ02 = gT0[0] * V.R[6] + gT0[1] * V.R[7] + gT0[2] * V.R[8];
-    const float gJ11 = gT1[0] * V.R[3] + gT1[1] * V.R[4] + gT1[2] * V.R[5];
-    const float gJ12 = gT1[0] * V.R[6] + gT1[1] * V.R[7] + gT1[2] * V.R[8];
-    const float tx = P.t[0], ty = P.t[1], tz = P.t[2];
-    const float iz = 1.f / tz, iz2 = iz * iz;
-    float gtx = 0.f, gty = 0.f, gtz = 0.f;
-    gtz += -V.fx * iz2 * gJ00 + V.fx * P.rx * iz2 * gJ02 - V.fy * iz2 * gJ11 +
-           V.fy * P.ry * iz2 * gJ12;
-    const float grx = -V.fx * iz * gJ02, gry = -V.fy * iz * gJ12;
+    const double gJ00 = gT0[0] * R[0] + gT0[1] * R[1] + gT0[2] * R[2];
+    const double gJ02 = gT0[0] * R[6] + gT0[1] * R[7] + gT0[2] * R[8];
+    const double gJ11 = gT1[0] * R[3] + gT1[1] * R[4] + gT1[2] * R[5];
+    const double gJ12 = gT1[0] * R[6] + gT1[1] * R[7] + gT1[2] * R[8];
+    const double tx = P.t[0], ty = P.t[1], tz = P.t[2];
+    const double iz = 1.0 / tz, iz2 = iz * iz;
+    double gtx = 0.0, gty = 0.0, gtz = 0.0;
+    gtz += -fx * iz2 * gJ00 + fx * P.rx * iz2 * gJ02 - fy * iz2 * gJ11 + fy * P.ry * iz2 * gJ12;
+    const double grx = -fx * iz * gJ02, gry = -fy * iz * gJ12;
     if (!P.clampx) { gtx += grx * iz; gtz -= grx * tx * iz2; }
     if (!P.clampy) { gty += gry * iz; gtz -= gry * ty * iz2; }
     // mean2D
-    gtx += gu * V.fx * iz;
-    gtz -= gu * V.fx * tx * iz2;
-    gty += gv * V.fy * iz;
-    gtz -= gv * V.fy * ty * iz2;
+    gtx += gu * fx * iz;
+    gtz -= gu * fx * tx * iz2;
+    gty += gv * fy * iz;
+    gtz -= gv * fy * ty * iz2;
     // t = W mu + t_w
 #pragma unroll
-    for (int k = 0; k < 3; ++k) gmu[k] += V.R[k] * gtx + V.R[3 + k] * gty + V.R[6 + k] * gtz;
+    for (int k = 0; k < 3; ++k) gmu[k] += R[k] * gtx + R[3 + k] * gty + R[6 + k] * gtz;
 
     // Sigma = M M^T, M = Rq diag(s): dL/dM = Gs M
-    const float* Rq = P.Rq;
-    float gR[9];
+    const double* Rq = P.Rq;
+    double gR[9];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      float acc = 0.f;
+      double acc = 0.0;
 #pragma unroll
       for (int r2 = 0; r2 < 3; ++r2) {
-        const float gM = (Gs[r2][0] * Rq[k] + Gs[r2][1] * Rq[3 + k] + Gs[r2][2] * Rq[6 + k]) * P.s[k];
+        const double gM =
+            (Gs[r2][0] * Rq[k] + Gs[r2][1] * Rq[3 + k] + Gs[r2][2] * Rq[6 + k]) * P.s[k];
         acc += gM * Rq[3 * r2 + k];
         gR[3 * r2 + k] = gM * P.s[k];
       }
       gs[k] += acc;
     }
     // Rq(q) -> unit quaternion -> raw quaternion
-    const float w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
-    const float gw = 2.f * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
-    const float gx = 2.f * (y * gR[1] + z * gR[2] + y * gR[3] - w * gR[5] + z * gR[6] + w * gR[7]) -
-                     4.f * x * (gR[4] + gR[8]);
-    const float gy = 2.f * (x * gR[1] + w * gR[2] + x * gR[3] + z * gR[5] - w * gR[6] + z * gR[7]) -
-                     4.f * y * (gR[0] + gR[8]);
-    const float gz = 2.f * (-w * gR[1] + x * gR[2] + w * gR[3] + y * gR[5] + x * gR[6] + y * gR[7]) -
-                     4.f * z * (gR[0] + gR[4]);
-    const float qd = w * gw + x * gx + y * gy + z * gz;
+    const double w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
+    const double gw = 2.0 * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
+    const double gx = 2.0 * (y * gR[1] + z * gR[2] + y * gR[3] - w * gR[5] + z * gR[6] + w * gR[7]) -
+                      4.0 * x * (gR[4] + gR[8]);
+    const double gy = 2.0 * (x * gR[1] + w * gR[2] + x * gR[3] + z * gR[5] - w * gR[6] + z * gR[7]) -
+                      4.0 * y * (gR[0] + gR[8]);
+    const double gz = 2.0 * (-w * gR[1] + x * gR[2] + w * gR[3] + y * gR[5] + x * gR[6] + y * gR[7]) -
+                      4.0 * z * (gR[0] + gR[4]);
+    const double qd = w * gw + x * gx + y * gy + z * gz;
     gq[0] += (gw - w * qd) * P.qinv;
     gq[1] += (gx - x * qd) * P.qinv;
     gq[2] += (gy - y * qd) * P.qinv;
@@ -403,11 +420,11 @@ __global__ __launch_bounds__(256) void k_project_bwd(Batch B, const float* __res
   if (accumulate) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      G.means[k * ld + i] += gmu[k];
-      G.scales[k * ld + i] += gs[k];
+      G.means[k * ld + i] += (float)gmu[k];
+      G.scales[k * ld + i] += (float)gs[k];
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) G.quats[k * ld + i] += gq[k];
+    for (int k = 0; k < 4; ++k) G.quats[k * ld + i] += (float)gq[k];
     G.opac[i] += go;
 #pragma unroll
     for (int j = 0; j < NB; ++j)
@@ -416,11 +433,11 @@ __global__ __launch_bounds__(256) void k_project_bwd(Batch B, const float* __res
   } else {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      G.means[k * ld + i] = gmu[k];
-      G.scales[k * ld + i] = gs[k];
+      G.means[k * ld + i] = (float)gmu[k];
+      G.scales[k * ld + i] = (float)gs[k];
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) G.quats[k * ld + i] = gq[k];
+    for (int k = 0; k < 4; ++k) G.quats[k * ld + i] = (float)gq[k];
     G.opac[i] = go;
 #pragma unroll
     for (int j = 0; j < NB; ++j)

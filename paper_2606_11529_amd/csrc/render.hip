@@ -1,14 +1,16 @@
 // Per-pixel compositing (Algorithm 1 of the paper with the 3DGS evaluate of
 // the listing "Implementation of XPR-3DGS") and its backward.
 //
-// One workgroup per tile: a TW x TH tile is TW*TH threads (16x16 = four
-// wave64s), one pixel per thread. The tile's depth-sorted list is walked in
-// batches of BATCH splat records staged in LDS (each thread loads at most
-// BATCH / (TW*TH) records, then every thread reads each record as a
-// broadcast); the whole workgroup leaves the loop as soon as no pixel is
-// still active, checked once per batch (the batch-boundary exit check of
-// Algorithm 1). The loop body is plain FP32 VALU work: the kernels are
-// bound by VALU issue, not by memory.
+// One workgroup per tile. Each thread owns PPT vertically adjacent pixels of
+// its tile column (a 16x16 tile is 256/PPT threads: four wave64s at PPT=1,
+// one wave64 covering the whole tile at PPT=4). The tile's depth-sorted list
+// is walked in batches of BATCH splat records staged in LDS; every thread
+// reads each record once (an LDS broadcast) and applies it to its PPT
+// pixels, so LDS reads, loop control and, in the backward, the cross-lane
+// gradient reduction are shared by PPT pixel evaluations. The workgroup
+// leaves the loop as soon as no pixel is still active, checked once per batch
+// (the batch-boundary exit check of Algorithm 1). The loop body is plain FP32
+// VALU work: the kernels are bound by VALU issue, not by memory.
 #include "xpr_internal.h"
 
 namespace xpr {
@@ -17,30 +19,26 @@ namespace xpr {
 // alpha = min(alpha_max, o e^P). Written with explicit roundings so the
 // forward and backward kernels take bit-identical decisions.
 struct Eval {
-  float dx, dy, P, eP, raw, alpha;
+  float dy, P, eP, raw, alpha;
 };
 
-__device__ __forceinline__ Eval evaluate(float px, float py, float4 a, float4 b, float alpha_max) {
+__device__ __forceinline__ Eval evaluate(float dx, float py, float4 a, float4 b, float alpha_max) {
   Eval e;
-  e.dx = __fsub_rn(px, a.x);
   e.dy = __fsub_rn(py, a.y);
-  e.P = __fmaf_rn(a.z, __fmul_rn(e.dx, e.dx),
-                  __fmaf_rn(a.w, __fmul_rn(e.dx, e.dy), __fmul_rn(b.x, __fmul_rn(e.dy, e.dy))));
+  e.P = __fmaf_rn(a.z, __fmul_rn(dx, dx),
+                  __fmaf_rn(a.w, __fmul_rn(dx, e.dy), __fmul_rn(b.x, __fmul_rn(e.dy, e.dy))));
   e.eP = __expf(e.P);
   e.raw = __fmul_rn(b.y, e.eP);
   e.alpha = fminf(alpha_max, e.raw);
   return e;
 }
 
-template <int TW, int TH, int BATCH>
-__global__ __launch_bounds__(TW* TH) void k_render_fwd(Batch B, const float4* __restrict__ splat,
-                                                       const int32_t* __restrict__ vals,
-                                                       const int2* __restrict__ ranges,
-                                                       float* __restrict__ image,
-                                                       float* __restrict__ Tfin,
-                                                       int32_t* __restrict__ ncon,
-                                                       int32_t* __restrict__ tile_work) {
-  constexpr int NT = TW * TH;
+template <int TW, int TH, int BATCH, int PPT>
+__global__ __launch_bounds__(TW* TH / PPT) void k_render_fwd(
+    Batch B, const float4* __restrict__ splat, const int32_t* __restrict__ vals,
+    const int2* __restrict__ ranges, float* __restrict__ image, float* __restrict__ Tfin,
+    int32_t* __restrict__ ncon, int32_t* __restrict__ tile_work) {
+  constexpr int NT = TW * TH / PPT;
   __shared__ float4 s0[BATCH];
   __shared__ float4 s1[BATCH];
   __shared__ float s2[BATCH];
@@ -49,17 +47,25 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(Batch B, const float4* __
   const int lt = g - V.tile_off;
   const int ty = lt / V.tiles_x, tx = lt - ty * V.tiles_x;
   const int px = tx * TW + (int)(threadIdx.x % TW);
-  const int py = ty * TH + (int)(threadIdx.x / TW);
-  const bool inside = px < V.W && py < V.H;
+  const int py0 = ty * TH + (int)(threadIdx.x / TW) * PPT;
   const int2 rg = ranges[g];
-  const float fpx = (float)px, fpy = (float)py;
+  const float fpx = (float)px;
   const float amax = B.alpha_max, amin = B.alpha_min, tmin = B.t_min;
-  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-  int last = 0;
-  bool done = !inside;
+  float T[PPT], C0[PPT], C1[PPT], C2[PPT];
+  int last[PPT];
+  bool done[PPT];
+  int ndone = 0;
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    T[j] = 1.f;
+    C0[j] = C1[j] = C2[j] = 0.f;
+    last[j] = 0;
+    done[j] = !(px < V.W && py0 + j < V.H);
+    ndone += done[j];
+  }
   int walked = 0;
   for (int base = rg.x; base < rg.y; base += BATCH) {
-    if (__syncthreads_count(!done) == 0) break;
+    if (__syncthreads_count(ndone < PPT) == 0) break;
     walked = min(BATCH, rg.y - base) + (base - rg.x);
     for (int k = threadIdx.x; k < BATCH; k += NT) {
       const int idx = base + k;
@@ -71,36 +77,44 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(Batch B, const float4* __
       }
     }
     __syncthreads();
-    if (!done) {
-      const int nb = min(BATCH, rg.y - base);
-      for (int k = 0; k < nb; ++k) {
-        const float4 a = s0[k];
-        const float4 b = s1[k];
-        const Eval e = evaluate(fpx, fpy, a, b, amax);
+    const int nb = min(BATCH, rg.y - base);
+    for (int k = 0; k < nb && ndone < PPT; ++k) {
+      const float4 a = s0[k];
+      const float4 b = s1[k];
+      const float dx = __fsub_rn(fpx, a.x);
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        if (done[j]) continue;
+        const Eval e = evaluate(dx, (float)(py0 + j), a, b, amax);
         if (e.P > 0.f || e.alpha < amin) continue;
-        const float Tn = T * (1.f - e.alpha);
+        const float Tn = T[j] * (1.f - e.alpha);
         if (Tn < tmin) {
-          done = true;
-          break;
+          done[j] = true;
+          ++ndone;
+          continue;
         }
-        const float w = e.alpha * T;
-        C0 += b.z * w;
-        C1 += b.w * w;
-        C2 += s2[k] * w;
-        T = Tn;
-        last = base + k - rg.x + 1;
+        const float w = e.alpha * T[j];
+        C0[j] += b.z * w;
+        C1[j] += b.w * w;
+        C2[j] += s2[k] * w;
+        T[j] = Tn;
+        last[j] = base + k - rg.x + 1;
       }
     }
   }
-  if (inside) {
-    const size_t WH = (size_t)V.W * V.H;
-    const size_t p = (size_t)py * V.W + px;
-    float* img = image + 3 * (size_t)V.pix_off;
-    img[p] = C0 + T * B.bg[0];
-    img[WH + p] = C1 + T * B.bg[1];
-    img[2 * WH + p] = C2 + T * B.bg[2];
-    Tfin[(size_t)V.pix_off + p] = T;
-    ncon[(size_t)V.pix_off + p] = last;
+  const size_t WH = (size_t)V.W * V.H;
+  float* img = image + 3 * (size_t)V.pix_off;
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    const int py = py0 + j;
+    if (px < V.W && py < V.H) {
+      const size_t p = (size_t)py * V.W + px;
+      img[p] = C0[j] + T[j] * B.bg[0];
+      img[WH + p] = C1[j] + T[j] * B.bg[1];
+      img[2 * WH + p] = C2[j] + T[j] * B.bg[2];
+      Tfin[(size_t)V.pix_off + p] = T[j];
+      ncon[(size_t)V.pix_off + p] = last[j];
+    }
   }
   if (tile_work && threadIdx.x == 0) tile_work[g] = walked;
 }
@@ -112,18 +126,17 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(Batch B, const float4* __
 //   dL/do = e^P dL/da, dL/dP = a dL/da (zero when a is clamped)
 //   dL/du = -dL/dP (2A dx + B dy), dL/dv = -dL/dP (2C dy + B dx),
 //   dL/d(A, B, C) = dL/dP (dx^2, dx dy, dy^2).
-// The nine per-pixel values are summed over the wave with DPP and added to
-// grad2d [record][9] with one lane's float atomics; waves where no pixel
-// uses the entry skip both.
-template <int TW, int TH, int BATCH>
-__global__ __launch_bounds__(TW* TH) void k_render_bwd(Batch B, const float4* __restrict__ splat,
-                                                       const int32_t* __restrict__ vals,
-                                                       const int2* __restrict__ ranges,
-                                                       const float* __restrict__ dimg,
-                                                       const float* __restrict__ Tfin,
-                                                       const int32_t* __restrict__ ncon,
-                                                       float* __restrict__ grad2d) {
-  constexpr int NT = TW * TH;
+// Each lane first sums the nine values over its PPT pixels; the wave then
+// sums them over its lanes with DPP and one lane adds them to
+// grad2d [record][9] with float atomics. Waves where no pixel uses the entry
+// skip both.
+template <int TW, int TH, int BATCH, int PPT>
+__global__ __launch_bounds__(TW* TH / PPT) void k_render_bwd(
+    Batch B, const float4* __restrict__ splat, const int32_t* __restrict__ vals,
+    const int2* __restrict__ ranges, const float* __restrict__ dimg,
+    const float* __restrict__ Tfin, const int32_t* __restrict__ ncon,
+    float* __restrict__ grad2d) {
+  constexpr int NT = TW * TH / PPT;
   __shared__ float4 s0[BATCH];
   __shared__ float4 s1[BATCH];
   __shared__ float s2[BATCH];
@@ -134,31 +147,39 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd(Batch B, const float4* __
   const int lt = g - V.tile_off;
   const int ty = lt / V.tiles_x, tx = lt - ty * V.tiles_x;
   const int px = tx * TW + (int)(threadIdx.x % TW);
-  const int py = ty * TH + (int)(threadIdx.x / TW);
-  const bool inside = px < V.W && py < V.H;
+  const int py0 = ty * TH + (int)(threadIdx.x / TW) * PPT;
   const int2 rg = ranges[g];
-  const float fpx = (float)px, fpy = (float)py;
+  const float fpx = (float)px;
   const float amax = B.alpha_max, amin = B.alpha_min;
   const size_t WH = (size_t)V.W * V.H;
-  const size_t p = (size_t)py * V.W + px;
-  float T = 1.f, G0 = 0.f, G1 = 0.f, G2 = 0.f;
-  int last = 0;
-  if (inside) {
-    T = Tfin[(size_t)V.pix_off + p];
-    last = ncon[(size_t)V.pix_off + p];
-    const float* gi = dimg + 3 * (size_t)V.pix_off;
-    G0 = gi[p];
-    G1 = gi[WH + p];
-    G2 = gi[2 * WH + p];
+  const float* gi = dimg + 3 * (size_t)V.pix_off;
+  float T[PPT], Tf[PPT], G0[PPT], G1[PPT], G2[PPT], S0[PPT], S1[PPT], S2[PPT], bgG[PPT];
+  int last[PPT];
+  int mylast = 0;
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    const int py = py0 + j;
+    T[j] = 1.f;
+    G0[j] = G1[j] = G2[j] = 0.f;
+    last[j] = 0;
+    if (px < V.W && py < V.H) {
+      const size_t p = (size_t)py * V.W + px;
+      T[j] = Tfin[(size_t)V.pix_off + p];
+      last[j] = ncon[(size_t)V.pix_off + p];
+      G0[j] = gi[p];
+      G1[j] = gi[WH + p];
+      G2[j] = gi[2 * WH + p];
+    }
+    Tf[j] = T[j];
+    S0[j] = S1[j] = S2[j] = 0.f;
+    bgG[j] = B.bg[0] * G0[j] + B.bg[1] * G1[j] + B.bg[2] * G2[j];
+    mylast = max(mylast, last[j]);
   }
   if (threadIdx.x == 0) s_maxlast = 0;
   __syncthreads();
-  if (last > 0) atomicMax(&s_maxlast, last);
+  if (mylast > 0) atomicMax(&s_maxlast, mylast);
   __syncthreads();
   const int end = rg.x + min(s_maxlast, rg.y - rg.x);
-  const float Tf = T;
-  const float bgG = B.bg[0] * G0 + B.bg[1] * G1 + B.bg[2] * G2;
-  float S0 = 0.f, S1 = 0.f, S2 = 0.f;
   for (int hi = end; hi > rg.x; hi -= BATCH) {
     const int lo = max(rg.x, hi - BATCH);
     __syncthreads();
@@ -171,36 +192,43 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd(Batch B, const float4* __
     }
     __syncthreads();
     for (int k = hi - lo - 1; k >= 0; --k) {
+      const int pos = lo + k - rg.x + 1;
+      if (__ballot(pos <= mylast) == 0) continue;
       const float4 a = s0[k];
       const float4 b = s1[k];
-      const int pos = lo + k - rg.x + 1;
-      const Eval e = evaluate(fpx, fpy, a, b, amax);
-      const bool use = pos <= last && !(e.P > 0.f) && !(e.alpha < amin);
-      if (__ballot(use) == 0) continue;
+      const float c2 = s2[k];
+      const float dx = __fsub_rn(fpx, a.x);
       float gu = 0.f, gv = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, go = 0.f;
       float gr = 0.f, gg = 0.f, gb = 0.f;
-      if (use) {
-        const float c2 = s2[k];
-        T = T / (1.f - e.alpha);
-        const float w = e.alpha * T;
-        gr = w * G0;
-        gg = w * G1;
-        gb = w * G2;
-        const float da = T * ((b.z - S0) * G0 + (b.w - S1) * G1 + (c2 - S2) * G2) -
-                         Tf * bgG / (1.f - e.alpha);
-        S0 = e.alpha * b.z + (1.f - e.alpha) * S0;
-        S1 = e.alpha * b.w + (1.f - e.alpha) * S1;
-        S2 = e.alpha * c2 + (1.f - e.alpha) * S2;
+      bool any = false;
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        const Eval e = evaluate(dx, (float)(py0 + j), a, b, amax);
+        const bool use = pos <= last[j] && !(e.P > 0.f) && !(e.alpha < amin);
+        if (!use) continue;
+        any = true;
+        const float inv = __builtin_amdgcn_rcpf(1.f - e.alpha);
+        T[j] = T[j] * inv;
+        const float w = e.alpha * T[j];
+        gr += w * G0[j];
+        gg += w * G1[j];
+        gb += w * G2[j];
+        const float da = T[j] * ((b.z - S0[j]) * G0[j] + (b.w - S1[j]) * G1[j] +
+                                 (c2 - S2[j]) * G2[j]) - Tf[j] * bgG[j] * inv;
+        S0[j] = e.alpha * b.z + (1.f - e.alpha) * S0[j];
+        S1[j] = e.alpha * b.w + (1.f - e.alpha) * S1[j];
+        S2[j] = e.alpha * c2 + (1.f - e.alpha) * S2[j];
         if (e.raw <= amax) {
           const float dP = e.alpha * da;
-          go = e.eP * da;
-          gu = -dP * (2.f * a.z * e.dx + a.w * e.dy);
-          gv = -dP * (2.f * b.x * e.dy + a.w * e.dx);
-          gA = dP * e.dx * e.dx;
-          gB = dP * e.dx * e.dy;
-          gC = dP * e.dy * e.dy;
+          go += e.eP * da;
+          gu -= dP * (2.f * a.z * dx + a.w * e.dy);
+          gv -= dP * (2.f * b.x * e.dy + a.w * dx);
+          gA += dP * dx * dx;
+          gB += dP * dx * e.dy;
+          gC += dP * e.dy * e.dy;
         }
       }
+      if (__ballot(any) == 0) continue;
       gu = wave_sum_lane63(gu);
       gv = wave_sum_lane63(gv);
       gA = wave_sum_lane63(gA);
@@ -228,56 +256,86 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd(Batch B, const float4* __
 
 // Launchers ------------------------------------------------------------------
 
-template <int TW, int TH>
-static hipError_t launch_fwd_t(const Batch& B, int lds_batch, const float* splat,
-                               const int32_t* vals, const int32_t* ranges, float* image,
-                               float* Tfin, int32_t* ncon, int32_t* tw, hipStream_t st) {
-  const dim3 grid(B.total_tiles), block(TW * TH);
-  const float4* sp = reinterpret_cast<const float4*>(splat);
-  const int2* rg = reinterpret_cast<const int2*>(ranges);
-  switch (lds_batch) {
-    case 64: hipLaunchKernelGGL((k_render_fwd<TW, TH, 64>), grid, block, 0, st, B, sp, vals, rg, image, Tfin, ncon, tw); break;
-    case 128: hipLaunchKernelGGL((k_render_fwd<TW, TH, 128>), grid, block, 0, st, B, sp, vals, rg, image, Tfin, ncon, tw); break;
-    case 512: hipLaunchKernelGGL((k_render_fwd<TW, TH, 512>), grid, block, 0, st, B, sp, vals, rg, image, Tfin, ncon, tw); break;
-    default: hipLaunchKernelGGL((k_render_fwd<TW, TH, 256>), grid, block, 0, st, B, sp, vals, rg, image, Tfin, ncon, tw); break;
-  }
-  return hipGetLastError();
+struct RenderArgs {
+  const float4* splat;
+  const int32_t* vals;
+  const int2* ranges;
+  float* image;
+  float* Tfin;
+  int32_t* ncon;
+  int32_t* tile_work;
+  const float* dimg;
+  const float* Tfin_in;
+  const int32_t* ncon_in;
+  float* grad2d;
+};
+
+template <int TW, int TH, int BATCH, int PPT>
+static void launch_one(const Batch& B, const RenderArgs& A, bool bwd, hipStream_t st) {
+  const dim3 grid(B.total_tiles), block(TW * TH / PPT);
+  if (bwd)
+    hipLaunchKernelGGL((k_render_bwd<TW, TH, BATCH, PPT>), grid, block, 0, st, B, A.splat, A.vals,
+                       A.ranges, A.dimg, A.Tfin_in, A.ncon_in, A.grad2d);
+  else
+    hipLaunchKernelGGL((k_render_fwd<TW, TH, BATCH, PPT>), grid, block, 0, st, B, A.splat, A.vals,
+                       A.ranges, A.image, A.Tfin, A.ncon, A.tile_work);
 }
 
-template <int TW, int TH>
-static hipError_t launch_bwd_t(const Batch& B, int lds_batch, const float* splat,
-                               const int32_t* vals, const int32_t* ranges, const float* dimg,
-                               const float* Tfin, const int32_t* ncon, float* grad2d,
-                               hipStream_t st) {
-  const dim3 grid(B.total_tiles), block(TW * TH);
-  const float4* sp = reinterpret_cast<const float4*>(splat);
-  const int2* rg = reinterpret_cast<const int2*>(ranges);
+template <int TW, int TH, int PPT>
+static void launch_batch(const Batch& B, int lds_batch, const RenderArgs& A, bool bwd,
+                         hipStream_t st) {
   switch (lds_batch) {
-    case 64: hipLaunchKernelGGL((k_render_bwd<TW, TH, 64>), grid, block, 0, st, B, sp, vals, rg, dimg, Tfin, ncon, grad2d); break;
-    case 128: hipLaunchKernelGGL((k_render_bwd<TW, TH, 128>), grid, block, 0, st, B, sp, vals, rg, dimg, Tfin, ncon, grad2d); break;
-    case 512: hipLaunchKernelGGL((k_render_bwd<TW, TH, 512>), grid, block, 0, st, B, sp, vals, rg, dimg, Tfin, ncon, grad2d); break;
-    default: hipLaunchKernelGGL((k_render_bwd<TW, TH, 256>), grid, block, 0, st, B, sp, vals, rg, dimg, Tfin, ncon, grad2d); break;
+    case 64: launch_one<TW, TH, 64, PPT>(B, A, bwd, st); break;
+    case 128: launch_one<TW, TH, 128, PPT>(B, A, bwd, st); break;
+    case 512: launch_one<TW, TH, 512, PPT>(B, A, bwd, st); break;
+    default: launch_one<TW, TH, 256, PPT>(B, A, bwd, st); break;
   }
-  return hipGetLastError();
 }
 
-hipError_t launch_render_fwd(const Batch& B, int lds_batch, const float* splat,
+static void launch_render(const Batch& B, int lds_batch, int ppt, const RenderArgs& A, bool bwd,
+                          hipStream_t st) {
+  if (B.tile_w == 8) {
+    launch_batch<8, 8, 1>(B, lds_batch, A, bwd, st);
+    return;
+  }
+  switch (ppt) {
+    case 2: launch_batch<16, 16, 2>(B, lds_batch, A, bwd, st); break;
+    case 4: launch_batch<16, 16, 4>(B, lds_batch, A, bwd, st); break;
+    default: launch_batch<16, 16, 1>(B, lds_batch, A, bwd, st); break;
+  }
+}
+
+hipError_t launch_render_fwd(const Batch& B, int lds_batch, int ppt, const float* splat,
                              const int32_t* vals, const int32_t* ranges, float* image, float* Tfin,
                              int32_t* ncon, int32_t* tile_work, hipStream_t st) {
   if (B.total_tiles <= 0) return hipSuccess;
-  if (B.tile_w == 8)
-    return launch_fwd_t<8, 8>(B, lds_batch, splat, vals, ranges, image, Tfin, ncon, tile_work, st);
-  return launch_fwd_t<16, 16>(B, lds_batch, splat, vals, ranges, image, Tfin, ncon, tile_work, st);
+  RenderArgs A{};
+  A.splat = reinterpret_cast<const float4*>(splat);
+  A.vals = vals;
+  A.ranges = reinterpret_cast<const int2*>(ranges);
+  A.image = image;
+  A.Tfin = Tfin;
+  A.ncon = ncon;
+  A.tile_work = tile_work;
+  launch_render(B, lds_batch, ppt, A, false, st);
+  return hipGetLastError();
 }
 
-hipError_t launch_render_bwd(const Batch& B, int lds_batch, const float* splat,
+hipError_t launch_render_bwd(const Batch& B, int lds_batch, int ppt, const float* splat,
                              const int32_t* vals, const int32_t* ranges, const float* dimg,
                              const float* Tfin, const int32_t* ncon, float* grad2d,
                              hipStream_t st) {
   if (B.total_tiles <= 0) return hipSuccess;
-  if (B.tile_w == 8)
-    return launch_bwd_t<8, 8>(B, lds_batch, splat, vals, ranges, dimg, Tfin, ncon, grad2d, st);
-  return launch_bwd_t<16, 16>(B, lds_batch, splat, vals, ranges, dimg, Tfin, ncon, grad2d, st);
+  RenderArgs A{};
+  A.splat = reinterpret_cast<const float4*>(splat);
+  A.vals = vals;
+  A.ranges = reinterpret_cast<const int2*>(ranges);
+  A.dimg = dimg;
+  A.Tfin_in = Tfin;
+  A.ncon_in = ncon;
+  A.grad2d = grad2d;
+  launch_render(B, lds_batch, ppt, A, true, st);
+  return hipGetLastError();
 }
 
 }  // namespace xpr

@@ -32,6 +32,9 @@ class Config:
     bg: tuple = (0.0, 0.0, 0.0)
     sort_mode: str = "presort"  # or "full"
     no_sync: bool = False
+    fwd_ppt: int = 2            # pixels per thread, forward (16x16 tiles)
+    bwd_ppt: int = 4            # pixels per thread, backward (16x16 tiles)
+    bwd_lds_batch: int = 0      # LDS batch of the backward (0: lds_batch)
 
     def to_c(self) -> L.XprConfig:
         c = L.XprConfig()
@@ -48,6 +51,9 @@ class Config:
             c.bg[k] = float(self.bg[k])
         c.sort_mode = L.XPR_SORT_PRESORT if self.sort_mode == "presort" else L.XPR_SORT_FULL
         c.no_sync = 1 if self.no_sync else 0
+        c.fwd_ppt = int(self.fwd_ppt)
+        c.bwd_ppt = int(self.bwd_ppt)
+        c.bwd_lds_batch = int(self.bwd_lds_batch)
         return c
 
 

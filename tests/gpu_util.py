@@ -88,12 +88,15 @@ def check_projection(sc, cam, cfg, gpu, rec_off=0, idx=None):
     assert np.array_equal(g_rect[vr], ref["rect"][vr]), "rect mismatch"
     # floats, on Gaussians visible on both sides
     m = vis
-    # mean2D against the oracle's float32 rounding scale (condition-aware:
-    # the camera-space mean's rounding is amplified by f / z)
-    uv_err = np.abs(g_rec[m, :2] - ref["rec"][m, :2]) / ref["tol_uv"][m]
-    assert uv_err.max(initial=0) <= 1.0, f"mean2D error {uv_err.max()} x bound"
+    # The projection's geometry is evaluated in float64 and rounded to float32
+    # on output, so each float output is within one float32 ulp of the
+    # oracle (plus float64 noise amplified by the 2x2 inverse's condition).
+    ulp = 2.0 ** -23
+    uv_err = np.abs(g_rec[m, :2] - ref["rec"][m, :2]) / np.maximum(1.0, np.abs(ref["rec"][m, :2]))
+    assert uv_err.max(initial=0) <= ulp, f"mean2D error {uv_err.max()}"
     d_err = np.abs(g_depth[m] - ref["depth"][m]) / np.maximum(1.0, np.abs(ref["depth"][m]))
-    assert d_err.max(initial=0) <= 2e-6, f"depth err {d_err.max()}"
+    assert d_err.max(initial=0) <= ulp, f"depth err {d_err.max()}"
+    # colour: the SH sum is accumulated in float32
     c_err = np.abs(g_rec[m, 6:9] - ref["rec"][m, 6:9])
     assert c_err.max(initial=0) <= 1e-6, f"colour err {c_err.max()}"
     assert np.array_equal(g_rec[m, 5], ref["rec"][m, 5]), "opacity must pass through"
@@ -104,11 +107,8 @@ def check_projection(sc, cam, cfg, gpu, rec_off=0, idx=None):
     cond = (0.5 * tr + disc) / np.maximum(0.5 * tr - disc, 1e-300)
     con_ref = ref["rec"][m, 2:5]
     scale = np.abs(con_ref).max(axis=1, keepdims=True)
-    con_err = np.abs(g_rec[m, 2:5] - con_ref) / scale
-    # ~40 float32 roundings from the inputs to the 2D covariance, amplified by
-    # the condition number in the inverse: 64 eps (cond + 1)
-    lim = 64 * 2.0 ** -24 * (cond[:, None] + 1.0)
-    worst = (con_err / lim).max(initial=0)
+    lim = ulp * np.abs(con_ref) + 2.0 ** -40 * (cond[:, None] + 1.0) * scale
+    worst = (np.abs(g_rec[m, 2:5] - con_ref) / lim).max(initial=0)
     assert worst <= 1.0, f"conic error {worst} x bound"
     return int(guard.sum()), int(n)
 

@@ -87,7 +87,8 @@ def test_batch_sizes():
 
 @pytest.mark.parametrize("field,value", [
     ("tile_w", 12), ("lds_batch", 100), ("sh_degree", 4), ("alpha_min", 0.0),
-    ("alpha_max", 1.5), ("t_min", 0.0), ("z_near", 0.0), ("sort_mode", 7), ("lowpass", -1.0)])
+    ("alpha_max", 1.5), ("t_min", 0.0), ("z_near", 0.0), ("sort_mode", 7), ("lowpass", -1.0),
+    ("fwd_ppt", 3), ("bwd_ppt", 8)])
 def test_invalid_config_rejected(field, value):
     v = _views()
     c = L.xpr_config_default()
