@@ -91,6 +91,7 @@ typedef struct xpr_config {
   int32_t fwd_ppt;        /* pixels per thread in the forward: 1, 2 or 4 (16x16 tiles) */
   int32_t bwd_ppt;        /* pixels per thread in the backward: 1, 2 or 4 (16x16 tiles) */
   int32_t bwd_lds_batch;  /* LDS batch of the backward (0: same as lds_batch) */
+  int32_t persistent;     /* 1: persistent render grids pulling from tile_order */
 } xpr_config;
 
 /* One scene of n Gaussians, structure of arrays with leading dimension ld:
@@ -169,6 +170,24 @@ xpr_status xpr_batch_sizes(const xpr_views* views, const xpr_config* cfg, xpr_si
 xpr_status xpr_project(const xpr_views* views, const xpr_config* cfg, const xpr_projected* out,
                        hipStream_t stream);
 
+/* Pair lists and tile ranges produced by xpr_bin_sort (device buffers).
+ *   keys  [capacity] uint64 (may be NULL): tile << 32 | float bits of depth
+ *   vals  [capacity] int32: record index of each sorted pair
+ *   tile_ranges [tiles][2] int32: [start, end) per global tile, (0,0) if empty
+ *   n_isect  int64: total number of pairs I (written also when I > capacity)
+ *   tile_order [tiles + 1] int32 (may be NULL): the tiles by decreasing list
+ *   length (ties by tile id), the order in which the render calls schedule
+ *   them; the last entry is queue state the render calls reset and use.
+ *   capacity  length of keys and vals (<= 2^31 - 1) */
+typedef struct xpr_bins {
+  uint64_t* keys;
+  int32_t* vals;
+  int32_t* tile_ranges;
+  int64_t* n_isect;
+  int32_t* tile_order;
+  int64_t capacity;
+} xpr_bins;
+
 /* Workspace bytes xpr_bin_sort needs for this batch and capacity. */
 xpr_status xpr_bin_sort_workspace(const xpr_views* views, const xpr_config* cfg,
                                   int64_t isect_capacity, size_t* bytes);
@@ -176,38 +195,36 @@ xpr_status xpr_bin_sort_workspace(const xpr_views* views, const xpr_config* cfg,
 /* Binning (section Rasterizer): exclusive prefix sum of tiles_touched, one
  * pair per (record, tile of its rect) with tile id G_v + y tx + x enumerated
  * row-major in the rect, stable sort by (tile id, depth) so that ties keep
- * the lower record index, and per-tile [start, end).
- *   isect_capacity  length of keys/vals (<= 2^31 - 1)
- *   keys  [cap] uint64 (may be NULL): tile << 32 | float bits of depth
- *   vals  [cap] int32: record index of each sorted pair
- *   tile_ranges [tiles][2] int32: [start, end) per global tile, (0,0) if empty
- *   n_isect  device int64: total number of pairs I (also when I > cap)
+ * the lower record index, per-tile [start, end), and (if requested) the
+ * longest-list-first tile order.
+ *   out     buffers as described at xpr_bins
  *   ws / ws_bytes   workspace of at least xpr_bin_sort_workspace() bytes
  * With cfg->no_sync == 0 the call reads I back (one stream sync) and returns
- * XPR_ERR_CAPACITY when I > cap (outputs then undefined, *n_isect valid).
- * With no_sync == 1 nothing is read back and grids are sized from the
- * capacity; if I > cap the lists are undefined and the caller checks
+ * XPR_ERR_CAPACITY when I > capacity (outputs then undefined, *n_isect
+ * valid). With no_sync == 1 nothing is read back and grids are sized from
+ * the capacity; if I > capacity the lists are undefined and the caller checks
  * *n_isect after the stream completes. */
 xpr_status xpr_bin_sort(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
-                        int64_t isect_capacity, uint64_t* keys, int32_t* vals,
-                        int32_t* tile_ranges, int64_t* n_isect, void* ws, size_t ws_bytes,
-                        hipStream_t stream);
+                        const xpr_bins* out, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Forward compositing (Algorithm 1 with the 3DGS evaluate): for each pixel
  * (x, y), over its tile's list front to back, P = A dx^2 + B dx dy + C dy^2
  * (dx = x - u, dy = y - v); skip if P > 0; a = min(alpha_max, o e^P); skip
  * if a < alpha_min; stop without blending if T (1 - a) < t_min; else
- * C += c a T, T *= 1 - a. Writes
+ * C += c a T, T *= 1 - a. Reads bins->vals, tile_ranges and (if not NULL)
+ * tile_order. Writes
  *   image [3][H][W] per view: C + T bg
  *   T_final [H][W] per view: final transmittance
  *   n_contrib [H][W] per view: 1-based list position of the last blended
  *   entry (0 if none), used by the backward;
  *   tile_work [tiles] int32 (may be NULL): list entries each tile's
- *   workgroup evaluated before every pixel was done (the lockstep work). */
+ *   workgroup evaluated before every pixel was done (the lockstep work).
+ * Tiles are scheduled in tile_order when given; with cfg->persistent a grid
+ * sized to fill the device pulls tiles from that order through an atomic
+ * counter (then tile_order is required). */
 xpr_status xpr_render_fwd(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
-                          const int32_t* vals, const int32_t* tile_ranges, float* image,
-                          float* T_final, int32_t* n_contrib, int32_t* tile_work,
-                          hipStream_t stream);
+                          const xpr_bins* bins, float* image, float* T_final, int32_t* n_contrib,
+                          int32_t* tile_work, hipStream_t stream);
 
 /* Workspace bytes xpr_render_bwd needs (per-record 2D gradients). */
 xpr_status xpr_render_bwd_workspace(const xpr_views* views, const xpr_config* cfg, size_t* bytes);
@@ -223,13 +240,14 @@ xpr_status xpr_render_bwd_workspace(const xpr_views* views, const xpr_config* cf
  *   r, g, b) per record, the derivative with respect to the shader data;
  *   when NULL the workspace holds it.
  * The compositing backward walks each pixel's list in reverse from its last
- * blended entry (T_i recovered as T_{i+1} / (1 - a_i)). Gradient sums use
- * float atomics, so the last bits vary from run to run. */
+ * blended entry (T_i recovered as T_{i+1} / (1 - a_i)); tiles are scheduled
+ * as in xpr_render_fwd. Gradient sums use float atomics, so the last bits
+ * vary from run to run. */
 xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
-                          const int32_t* vals, const int32_t* tile_ranges, const float* dL_dimage,
-                          const float* T_final, const int32_t* n_contrib,
-                          const xpr_scene_grad* grads, int32_t accumulate, float* grad2d,
-                          void* ws, size_t ws_bytes, hipStream_t stream);
+                          const xpr_bins* bins, const float* dL_dimage, const float* T_final,
+                          const int32_t* n_contrib, const xpr_scene_grad* grads,
+                          int32_t accumulate, float* grad2d, void* ws, size_t ws_bytes,
+                          hipStream_t stream);
 
 /* Backward of the projection alone: from grad2d [records][9] (as written by
  * xpr_render_bwd) to the parameter gradients of every scene, summed over the

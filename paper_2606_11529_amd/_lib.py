@@ -38,7 +38,7 @@ class XprConfig(ctypes.Structure):
                 ("lowpass", _f), ("alpha_min", _f), ("alpha_max", _f), ("t_min", _f),
                 ("z_near", _f), ("fov_clip", _f), ("bg", _f * 3), ("sort_mode", _i32),
                 ("no_sync", _i32), ("fwd_ppt", _i32), ("bwd_ppt", _i32),
-                ("bwd_lds_batch", _i32)]
+                ("bwd_lds_batch", _i32), ("persistent", _i32)]
 
 
 class XprScene(ctypes.Structure):
@@ -61,6 +61,11 @@ class XprProjected(ctypes.Structure):
     _fields_ = [("splat", _vp), ("depth", _vp), ("rect", _vp), ("tiles_touched", _vp)]
 
 
+class XprBins(ctypes.Structure):
+    _fields_ = [("keys", _vp), ("vals", _vp), ("tile_ranges", _vp), ("n_isect", _vp),
+                ("tile_order", _vp), ("capacity", _i64)]
+
+
 class XprSizes(ctypes.Structure):
     _fields_ = [("records", _i64), ("tiles", _i64), ("pixels", _i64), ("tile_bits", _i32)]
 
@@ -74,15 +79,15 @@ SIGNATURES = {
     "xpr_batch_sizes": (_i32, [_P(XprViews), _P(XprConfig), _P(XprSizes)]),
     "xpr_project": (_i32, [_P(XprViews), _P(XprConfig), _P(XprProjected), _vp]),
     "xpr_bin_sort_workspace": (_i32, [_P(XprViews), _P(XprConfig), _i64, _P(ctypes.c_size_t)]),
-    "xpr_bin_sort": (_i32, [_P(XprViews), _P(XprConfig), _P(XprProjected), _i64, _vp, _vp, _vp,
-                            _vp, _vp, ctypes.c_size_t, _vp]),
-    "xpr_render_fwd": (_i32, [_P(XprViews), _P(XprConfig), _P(XprProjected), _vp, _vp, _vp, _vp,
-                              _vp, _vp, _vp]),
+    "xpr_bin_sort": (_i32, [_P(XprViews), _P(XprConfig), _P(XprProjected), _P(XprBins), _vp,
+                            ctypes.c_size_t, _vp]),
+    "xpr_render_fwd": (_i32, [_P(XprViews), _P(XprConfig), _P(XprProjected), _P(XprBins), _vp,
+                              _vp, _vp, _vp, _vp]),
     "xpr_project_bwd": (_i32, [_P(XprViews), _P(XprConfig), _P(XprProjected), _vp,
                                _P(XprSceneGrad), _i32, _vp]),
     "xpr_render_bwd_workspace": (_i32, [_P(XprViews), _P(XprConfig), _P(ctypes.c_size_t)]),
-    "xpr_render_bwd": (_i32, [_P(XprViews), _P(XprConfig), _P(XprProjected), _vp, _vp, _vp, _vp,
-                              _vp, _P(XprSceneGrad), _i32, _vp, _vp, ctypes.c_size_t, _vp]),
+    "xpr_render_bwd": (_i32, [_P(XprViews), _P(XprConfig), _P(XprProjected), _P(XprBins), _vp,
+                              _vp, _vp, _P(XprSceneGrad), _i32, _vp, _vp, ctypes.c_size_t, _vp]),
     "xpr_last_error": (ctypes.c_char_p, []),
     "xpr_version": (_i32, []),
 }
@@ -145,20 +150,18 @@ def xpr_bin_sort_workspace(views, cfg, capacity: int) -> int:
     return int(b.value)
 
 
-def xpr_bin_sort(views, cfg, proj, capacity, keys, vals, ranges, n_isect, ws, ws_bytes,
-                 stream) -> int:
+def xpr_bin_sort(views, cfg, proj, bins, ws, ws_bytes, stream) -> int:
     """Returns the raw status (XPR_ERR_CAPACITY is handled by the caller)."""
-    st = lib().xpr_bin_sort(ctypes.byref(views), ctypes.byref(cfg), ctypes.byref(proj), capacity,
-                            keys, vals, ranges, n_isect, ws, ws_bytes, stream)
+    st = lib().xpr_bin_sort(ctypes.byref(views), ctypes.byref(cfg), ctypes.byref(proj),
+                            ctypes.byref(bins), ws, ws_bytes, stream)
     if st not in (XPR_OK, XPR_ERR_CAPACITY):
         check(st, "xpr_bin_sort")
     return st
 
 
-def xpr_render_fwd(views, cfg, proj, vals, ranges, image, T_final, n_contrib, tile_work,
-                   stream) -> None:
-    check(lib().xpr_render_fwd(ctypes.byref(views), ctypes.byref(cfg), ctypes.byref(proj), vals,
-                               ranges, image, T_final, n_contrib, tile_work, stream),
+def xpr_render_fwd(views, cfg, proj, bins, image, T_final, n_contrib, tile_work, stream) -> None:
+    check(lib().xpr_render_fwd(ctypes.byref(views), ctypes.byref(cfg), ctypes.byref(proj),
+                               ctypes.byref(bins), image, T_final, n_contrib, tile_work, stream),
           "xpr_render_fwd")
 
 
@@ -174,11 +177,11 @@ def xpr_render_bwd_workspace(views, cfg) -> int:
     return int(b.value)
 
 
-def xpr_render_bwd(views, cfg, proj, vals, ranges, dimage, T_final, n_contrib, grads,
-                   accumulate, grad2d, ws, ws_bytes, stream) -> None:
-    check(lib().xpr_render_bwd(ctypes.byref(views), ctypes.byref(cfg), ctypes.byref(proj), vals,
-                               ranges, dimage, T_final, n_contrib, grads, accumulate, grad2d, ws,
-                               ws_bytes, stream), "xpr_render_bwd")
+def xpr_render_bwd(views, cfg, proj, bins, dimage, T_final, n_contrib, grads, accumulate,
+                   grad2d, ws, ws_bytes, stream) -> None:
+    check(lib().xpr_render_bwd(ctypes.byref(views), ctypes.byref(cfg), ctypes.byref(proj),
+                               ctypes.byref(bins), dimage, T_final, n_contrib, grads, accumulate,
+                               grad2d, ws, ws_bytes, stream), "xpr_render_bwd")
 
 
 def xpr_last_error() -> str:

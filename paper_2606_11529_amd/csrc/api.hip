@@ -15,21 +15,23 @@ hipError_t launch_project(const Batch& B, int max_n, float* splat, float* depth,
                           int32_t* tc, hipStream_t st);
 hipError_t launch_project_bwd(const Batch& B, int max_n, const float* grad2d, const int32_t* tc,
                               const GradDev* G, int accumulate, hipStream_t st);
-size_t bin_workspace_bytes(int64_t n_rec, int64_t cap, int sort_mode);
+size_t bin_workspace_bytes(int64_t n_rec, int64_t cap, int64_t tiles, int sort_mode);
 hipError_t bin_phase1(const Batch& B, int sort_mode, const float* depth, const int32_t* tc,
                       int64_t n_rec, int64_t cap, int64_t* n_isect, void* ws, hipStream_t st,
                       const uint32_t** perm_out);
 hipError_t bin_phase2(const Batch& B, int sort_mode, int tile_bits, const float* depth,
                       const int16_t* rect, const int32_t* tc, const uint32_t* perm, int64_t n_rec,
                       int64_t cap, int64_t grid_n, const int64_t* n_isect, uint64_t* keys_out,
-                      int32_t* vals, int2* ranges, void* ws, size_t ws_bytes, hipStream_t st);
-hipError_t launch_render_fwd(const Batch& B, int lds_batch, int ppt, const float* splat,
-                             const int32_t* vals, const int32_t* ranges, float* image, float* Tfin,
-                             int32_t* ncon, int32_t* tile_work, hipStream_t st);
-hipError_t launch_render_bwd(const Batch& B, int lds_batch, int ppt, const float* splat,
-                             const int32_t* vals, const int32_t* ranges, const float* dimg,
-                             const float* Tfin, const int32_t* ncon, float* grad2d,
-                             hipStream_t st);
+                      int32_t* vals, int2* ranges, int32_t* tile_order, void* ws, size_t ws_bytes,
+                      hipStream_t st);
+hipError_t launch_render_fwd(const Batch& B, int lds_batch, int ppt, bool persistent,
+                             const float* splat, const int32_t* vals, const int32_t* ranges,
+                             int32_t* order, float* image, float* Tfin, int32_t* ncon,
+                             int32_t* tile_work, hipStream_t st);
+hipError_t launch_render_bwd(const Batch& B, int lds_batch, int ppt, bool persistent,
+                             const float* splat, const int32_t* vals, const int32_t* ranges,
+                             int32_t* order, const float* dimg, const float* Tfin,
+                             const int32_t* ncon, float* grad2d, hipStream_t st);
 hipError_t fill_zero_f32(float* p, int64_t n, hipStream_t st);
 
 static thread_local char g_err[512];
@@ -242,6 +244,7 @@ void xpr_config_default(xpr_config* c) {
   c->fwd_ppt = 2;
   c->bwd_ppt = 4;
   c->bwd_lds_batch = 0;
+  c->persistent = 0;
 }
 
 xpr_status xpr_batch_sizes(const xpr_views* views, const xpr_config* cfg, xpr_sizes* out) {
@@ -281,14 +284,12 @@ xpr_status xpr_bin_sort_workspace(const xpr_views* views, const xpr_config* cfg,
   XPR_CHECK(bytes != nullptr, "bytes is NULL");
   XPR_CHECK(isect_capacity >= 0 && isect_capacity < ((int64_t)1 << 31),
             "isect_capacity out of range");
-  *bytes = bin_workspace_bytes(S.records, isect_capacity, cfg->sort_mode);
+  *bytes = bin_workspace_bytes(S.records, isect_capacity, S.tiles, cfg->sort_mode);
   return XPR_OK;
 }
 
 xpr_status xpr_bin_sort(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
-                        int64_t isect_capacity, uint64_t* keys, int32_t* vals,
-                        int32_t* tile_ranges, int64_t* n_isect, void* ws, size_t ws_bytes,
-                        hipStream_t stream) {
+                        const xpr_bins* out, void* ws, size_t ws_bytes, hipStream_t stream) {
   g_err[0] = 0;
   Batch B;
   Sizes S;
@@ -296,42 +297,44 @@ xpr_status xpr_bin_sort(const xpr_views* views, const xpr_config* cfg, const xpr
   if (st != XPR_OK) return st;
   st = check_proj(proj, S);
   if (st != XPR_OK) return st;
-  XPR_CHECK(isect_capacity >= 0 && isect_capacity < ((int64_t)1 << 31),
-            "isect_capacity out of range");
-  XPR_CHECK(tile_ranges && n_isect, "tile_ranges / n_isect NULL");
-  XPR_CHECK(isect_capacity == 0 || vals, "vals NULL");
-  XPR_CHECK(aligned(tile_ranges, 8) && aligned(n_isect, 8) && (!keys || aligned(keys, 8)) &&
-                (!vals || aligned(vals, 4)),
+  XPR_CHECK(out != nullptr, "bins is NULL");
+  const int64_t cap = out->capacity;
+  XPR_CHECK(cap >= 0 && cap < ((int64_t)1 << 31), "capacity out of range");
+  XPR_CHECK(out->tile_ranges && out->n_isect, "tile_ranges / n_isect NULL");
+  XPR_CHECK(cap == 0 || out->vals, "vals NULL");
+  XPR_CHECK(aligned(out->tile_ranges, 8) && aligned(out->n_isect, 8) &&
+                (!out->keys || aligned(out->keys, 8)) && (!out->vals || aligned(out->vals, 4)) &&
+                (!out->tile_order || aligned(out->tile_order, 4)),
             "misaligned output buffer");
-  const size_t need = bin_workspace_bytes(S.records, isect_capacity, cfg->sort_mode);
+  const size_t need = bin_workspace_bytes(S.records, cap, S.tiles, cfg->sort_mode);
   XPR_CHECK(ws_bytes >= need && (need == 0 || ws != nullptr),
             "workspace too small: %zu < %zu bytes", ws_bytes, need);
   XPR_CHECK(aligned(ws, 256), "workspace must be 256-byte aligned");
   const uint32_t* perm = nullptr;
-  XPR_HIP(bin_phase1(B, cfg->sort_mode, proj->depth, proj->tiles_touched, S.records,
-                     isect_capacity, n_isect, ws, stream, &perm));
-  int64_t grid_n = isect_capacity;
+  XPR_HIP(bin_phase1(B, cfg->sort_mode, proj->depth, proj->tiles_touched, S.records, cap,
+                     out->n_isect, ws, stream, &perm));
+  int64_t grid_n = cap;
   if (!cfg->no_sync) {
     int64_t I = 0;
-    XPR_HIP(hipMemcpyAsync(&I, n_isect, sizeof(I), hipMemcpyDeviceToHost, stream));
+    XPR_HIP(hipMemcpyAsync(&I, out->n_isect, sizeof(I), hipMemcpyDeviceToHost, stream));
     XPR_HIP(hipStreamSynchronize(stream));
-    if (I > isect_capacity) {
+    if (I > cap) {
       set_error("%lld tile-Gaussian pairs exceed isect_capacity %lld", (long long)I,
-                (long long)isect_capacity);
+                (long long)cap);
       return XPR_ERR_CAPACITY;
     }
     grid_n = I;
   }
   XPR_HIP(bin_phase2(B, cfg->sort_mode, S.tile_bits, proj->depth, proj->rect,
-                     proj->tiles_touched, perm, S.records, isect_capacity, grid_n, n_isect, keys,
-                     vals, reinterpret_cast<int2*>(tile_ranges), ws, ws_bytes, stream));
+                     proj->tiles_touched, perm, S.records, cap, grid_n, out->n_isect, out->keys,
+                     out->vals, reinterpret_cast<int2*>(out->tile_ranges), out->tile_order, ws,
+                     ws_bytes, stream));
   return XPR_OK;
 }
 
 xpr_status xpr_render_fwd(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
-                          const int32_t* vals, const int32_t* tile_ranges, float* image,
-                          float* T_final, int32_t* n_contrib, int32_t* tile_work,
-                          hipStream_t stream) {
+                          const xpr_bins* bins, float* image, float* T_final, int32_t* n_contrib,
+                          int32_t* tile_work, hipStream_t stream) {
   g_err[0] = 0;
   Batch B;
   Sizes S;
@@ -339,12 +342,14 @@ xpr_status xpr_render_fwd(const xpr_views* views, const xpr_config* cfg, const x
   if (st != XPR_OK) return st;
   st = check_proj(proj, S);
   if (st != XPR_OK) return st;
-  XPR_CHECK(tile_ranges && image && T_final && n_contrib, "NULL output buffer");
-  XPR_CHECK(aligned(tile_ranges, 8) && aligned(image, 4) && aligned(T_final, 4) &&
-                aligned(n_contrib, 4) && (!vals || aligned(vals, 4)),
+  XPR_CHECK(bins && bins->tile_ranges && image && T_final && n_contrib, "NULL buffer");
+  XPR_CHECK(!cfg->persistent || bins->tile_order, "persistent needs bins->tile_order");
+  XPR_CHECK(aligned(bins->tile_ranges, 8) && aligned(image, 4) && aligned(T_final, 4) &&
+                aligned(n_contrib, 4) && (!bins->vals || aligned(bins->vals, 4)) &&
+                (!tile_work || aligned(tile_work, 4)),
             "misaligned buffer");
-  XPR_CHECK(!tile_work || aligned(tile_work, 4), "misaligned tile_work");
-  XPR_HIP(launch_render_fwd(B, cfg->lds_batch, cfg->fwd_ppt, proj->splat, vals, tile_ranges, image, T_final,
+  XPR_HIP(launch_render_fwd(B, cfg->lds_batch, cfg->fwd_ppt, cfg->persistent != 0, proj->splat,
+                            bins->vals, bins->tile_ranges, bins->tile_order, image, T_final,
                             n_contrib, tile_work, stream));
   return XPR_OK;
 }
@@ -361,10 +366,10 @@ xpr_status xpr_render_bwd_workspace(const xpr_views* views, const xpr_config* cf
 }
 
 xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
-                          const int32_t* vals, const int32_t* tile_ranges, const float* dL_dimage,
-                          const float* T_final, const int32_t* n_contrib,
-                          const xpr_scene_grad* grads, int32_t accumulate, float* grad2d,
-                          void* ws, size_t ws_bytes, hipStream_t stream) {
+                          const xpr_bins* bins, const float* dL_dimage, const float* T_final,
+                          const int32_t* n_contrib, const xpr_scene_grad* grads,
+                          int32_t accumulate, float* grad2d, void* ws, size_t ws_bytes,
+                          hipStream_t stream) {
   g_err[0] = 0;
   Batch B;
   Sizes S;
@@ -372,10 +377,11 @@ xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const x
   if (st != XPR_OK) return st;
   st = check_proj(proj, S);
   if (st != XPR_OK) return st;
-  XPR_CHECK(tile_ranges && dL_dimage && T_final && n_contrib, "NULL buffer");
+  XPR_CHECK(bins && bins->tile_ranges && dL_dimage && T_final && n_contrib, "NULL buffer");
   XPR_CHECK(grads || grad2d, "grads and grad2d both NULL");
+  XPR_CHECK(!cfg->persistent || bins->tile_order, "persistent needs bins->tile_order");
   XPR_CHECK(aligned(dL_dimage, 4) && aligned(T_final, 4) && aligned(n_contrib, 4) &&
-                aligned(tile_ranges, 8) && (!grad2d || aligned(grad2d, 4)),
+                aligned(bins->tile_ranges, 8) && (!grad2d || aligned(grad2d, 4)),
             "misaligned buffer");
   float* g2 = grad2d;
   if (!g2) {
@@ -391,7 +397,8 @@ xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const x
   }
   XPR_HIP(fill_zero_f32(g2, 9 * S.records, stream));
   const int bwd_lds = cfg->bwd_lds_batch ? cfg->bwd_lds_batch : cfg->lds_batch;
-  XPR_HIP(launch_render_bwd(B, bwd_lds, cfg->bwd_ppt, proj->splat, vals, tile_ranges, dL_dimage, T_final,
+  XPR_HIP(launch_render_bwd(B, bwd_lds, cfg->bwd_ppt, cfg->persistent != 0, proj->splat,
+                            bins->vals, bins->tile_ranges, bins->tile_order, dL_dimage, T_final,
                             n_contrib, g2, stream));
   if (grads)
     XPR_HIP(launch_project_bwd(B, S.max_n, g2, proj->tiles_touched, G, accumulate ? 1 : 0, stream));

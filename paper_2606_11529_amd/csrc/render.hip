@@ -11,6 +11,8 @@
 // leaves the loop as soon as no pixel is still active, checked once per batch
 // (the batch-boundary exit check of Algorithm 1). The loop body is plain FP32
 // VALU work: the kernels are bound by VALU issue, not by memory.
+#include <algorithm>
+
 #include "xpr_internal.h"
 
 namespace xpr {
@@ -34,15 +36,14 @@ __device__ __forceinline__ Eval evaluate(float dx, float py, float4 a, float4 b,
 }
 
 template <int TW, int TH, int BATCH, int PPT>
-__global__ __launch_bounds__(TW* TH / PPT) void k_render_fwd(
-    Batch B, const float4* __restrict__ splat, const int32_t* __restrict__ vals,
-    const int2* __restrict__ ranges, float* __restrict__ image, float* __restrict__ Tfin,
-    int32_t* __restrict__ ncon, int32_t* __restrict__ tile_work) {
+__device__ __forceinline__ void fwd_tile(const Batch& B, int g, const float4* __restrict__ splat,
+                                         const int32_t* __restrict__ vals,
+                                         const int2* __restrict__ ranges,
+                                         float* __restrict__ image, float* __restrict__ Tfin,
+                                         int32_t* __restrict__ ncon,
+                                         int32_t* __restrict__ tile_work, float4* s0, float4* s1,
+                                         float* s2) {
   constexpr int NT = TW * TH / PPT;
-  __shared__ float4 s0[BATCH];
-  __shared__ float4 s1[BATCH];
-  __shared__ float s2[BATCH];
-  const int g = blockIdx.x;
   const ViewDev& V = B.v[view_of_tile(B, g)];
   const int lt = g - V.tile_off;
   const int ty = lt / V.tiles_x, tx = lt - ty * V.tiles_x;
@@ -119,6 +120,37 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_render_fwd(
   if (tile_work && threadIdx.x == 0) tile_work[g] = walked;
 }
 
+// Tile scheduling: with PERSIST the grid is sized to the device and each
+// workgroup takes the next tile of ``order`` from an atomic counter until
+// the list is exhausted; otherwise workgroup b renders order[b] (or tile b).
+__device__ __forceinline__ int next_tile(int* s_next, int32_t* qhead) {
+  __syncthreads();
+  if (threadIdx.x == 0) *s_next = atomicAdd(qhead, 1);
+  __syncthreads();
+  return *s_next;
+}
+
+template <int TW, int TH, int BATCH, int PPT, bool PERSIST>
+__global__ __launch_bounds__(TW* TH / PPT) void k_render_fwd(
+    Batch B, const float4* __restrict__ splat, const int32_t* __restrict__ vals,
+    const int2* __restrict__ ranges, float* __restrict__ image, float* __restrict__ Tfin,
+    int32_t* __restrict__ ncon, int32_t* __restrict__ tile_work, const int32_t* order,
+    int32_t* qhead) {
+  __shared__ float4 s0[BATCH];
+  __shared__ float4 s1[BATCH];
+  __shared__ float s2[BATCH];
+  if (!PERSIST) {
+    const int g = order ? order[blockIdx.x] : (int)blockIdx.x;
+    fwd_tile<TW, TH, BATCH, PPT>(B, g, splat, vals, ranges, image, Tfin, ncon, tile_work, s0, s1,
+                                 s2);
+    return;
+  }
+  __shared__ int s_next;
+  for (int q = next_tile(&s_next, qhead); q < B.total_tiles; q = next_tile(&s_next, qhead))
+    fwd_tile<TW, TH, BATCH, PPT>(B, order[q], splat, vals, ranges, image, Tfin, ncon, tile_work,
+                                 s0, s1, s2);
+}
+
 // Backward of the compositing. Each pixel walks its list in reverse from
 // its last blended entry, recovering T_i = T_{i+1} / (1 - a_i) and the
 // colour behind S_i, and forms
@@ -131,18 +163,16 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_render_fwd(
 // grad2d [record][9] with float atomics. Waves where no pixel uses the entry
 // skip both.
 template <int TW, int TH, int BATCH, int PPT>
-__global__ __launch_bounds__(TW* TH / PPT) void k_render_bwd(
-    Batch B, const float4* __restrict__ splat, const int32_t* __restrict__ vals,
-    const int2* __restrict__ ranges, const float* __restrict__ dimg,
-    const float* __restrict__ Tfin, const int32_t* __restrict__ ncon,
-    float* __restrict__ grad2d) {
+__device__ __forceinline__ void bwd_tile(const Batch& B, int g, const float4* __restrict__ splat,
+                                         const int32_t* __restrict__ vals,
+                                         const int2* __restrict__ ranges,
+                                         const float* __restrict__ dimg,
+                                         const float* __restrict__ Tfin,
+                                         const int32_t* __restrict__ ncon,
+                                         float* __restrict__ grad2d, float4* s0, float4* s1,
+                                         float* s2, int32_t* srec, int32_t* s_maxlast_p) {
   constexpr int NT = TW * TH / PPT;
-  __shared__ float4 s0[BATCH];
-  __shared__ float4 s1[BATCH];
-  __shared__ float s2[BATCH];
-  __shared__ int32_t srec[BATCH];
-  __shared__ int32_t s_maxlast;
-  const int g = blockIdx.x;
+  int32_t& s_maxlast = *s_maxlast_p;
   const ViewDev& V = B.v[view_of_tile(B, g)];
   const int lt = g - V.tile_off;
   const int ty = lt / V.tiles_x, tx = lt - ty * V.tiles_x;
@@ -175,6 +205,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_render_bwd(
     bgG[j] = B.bg[0] * G0[j] + B.bg[1] * G1[j] + B.bg[2] * G2[j];
     mylast = max(mylast, last[j]);
   }
+  __syncthreads();
   if (threadIdx.x == 0) s_maxlast = 0;
   __syncthreads();
   if (mylast > 0) atomicMax(&s_maxlast, mylast);
@@ -254,6 +285,29 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_render_bwd(
   }
 }
 
+template <int TW, int TH, int BATCH, int PPT, bool PERSIST>
+__global__ __launch_bounds__(TW* TH / PPT) void k_render_bwd(
+    Batch B, const float4* __restrict__ splat, const int32_t* __restrict__ vals,
+    const int2* __restrict__ ranges, const float* __restrict__ dimg,
+    const float* __restrict__ Tfin, const int32_t* __restrict__ ncon,
+    float* __restrict__ grad2d, const int32_t* order, int32_t* qhead) {
+  __shared__ float4 s0[BATCH];
+  __shared__ float4 s1[BATCH];
+  __shared__ float s2[BATCH];
+  __shared__ int32_t srec[BATCH];
+  __shared__ int32_t s_maxlast;
+  if (!PERSIST) {
+    const int g = order ? order[blockIdx.x] : (int)blockIdx.x;
+    bwd_tile<TW, TH, BATCH, PPT>(B, g, splat, vals, ranges, dimg, Tfin, ncon, grad2d, s0, s1, s2,
+                                 srec, &s_maxlast);
+    return;
+  }
+  __shared__ int s_next;
+  for (int q = next_tile(&s_next, qhead); q < B.total_tiles; q = next_tile(&s_next, qhead))
+    bwd_tile<TW, TH, BATCH, PPT>(B, order[q], splat, vals, ranges, dimg, Tfin, ncon, grad2d, s0,
+                                 s1, s2, srec, &s_maxlast);
+}
+
 // Launchers ------------------------------------------------------------------
 
 struct RenderArgs {
@@ -268,17 +322,53 @@ struct RenderArgs {
   const float* Tfin_in;
   const int32_t* ncon_in;
   float* grad2d;
+  const int32_t* order;
+  int32_t* qhead;
+  bool persistent;
 };
+
+__global__ void k_zero_i32(int32_t* p) {
+  if (threadIdx.x == 0) *p = 0;
+}
+
+// Workgroups that fill the device once: resident blocks per CU x CUs.
+template <typename K>
+static int persistent_grid(K kernel, int threads) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess)
+    return 0;
+  return std::max(1, per_cu) * std::max(1, cus);
+}
 
 template <int TW, int TH, int BATCH, int PPT>
 static void launch_one(const Batch& B, const RenderArgs& A, bool bwd, hipStream_t st) {
-  const dim3 grid(B.total_tiles), block(TW * TH / PPT);
+  const int threads = TW * TH / PPT;
+  if (A.persistent) {
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, A.qhead);
+    if (bwd) {
+      auto k = k_render_bwd<TW, TH, BATCH, PPT, true>;
+      const int grid = std::min(B.total_tiles, persistent_grid(k, threads));
+      hipLaunchKernelGGL(k, dim3(std::max(grid, 1)), dim3(threads), 0, st, B, A.splat, A.vals,
+                         A.ranges, A.dimg, A.Tfin_in, A.ncon_in, A.grad2d, A.order, A.qhead);
+    } else {
+      auto k = k_render_fwd<TW, TH, BATCH, PPT, true>;
+      const int grid = std::min(B.total_tiles, persistent_grid(k, threads));
+      hipLaunchKernelGGL(k, dim3(std::max(grid, 1)), dim3(threads), 0, st, B, A.splat, A.vals,
+                         A.ranges, A.image, A.Tfin, A.ncon, A.tile_work, A.order, A.qhead);
+    }
+    return;
+  }
+  const dim3 grid(B.total_tiles), block(threads);
   if (bwd)
-    hipLaunchKernelGGL((k_render_bwd<TW, TH, BATCH, PPT>), grid, block, 0, st, B, A.splat, A.vals,
-                       A.ranges, A.dimg, A.Tfin_in, A.ncon_in, A.grad2d);
+    hipLaunchKernelGGL((k_render_bwd<TW, TH, BATCH, PPT, false>), grid, block, 0, st, B, A.splat,
+                       A.vals, A.ranges, A.dimg, A.Tfin_in, A.ncon_in, A.grad2d, A.order,
+                       A.qhead);
   else
-    hipLaunchKernelGGL((k_render_fwd<TW, TH, BATCH, PPT>), grid, block, 0, st, B, A.splat, A.vals,
-                       A.ranges, A.image, A.Tfin, A.ncon, A.tile_work);
+    hipLaunchKernelGGL((k_render_fwd<TW, TH, BATCH, PPT, false>), grid, block, 0, st, B, A.splat,
+                       A.vals, A.ranges, A.image, A.Tfin, A.ncon, A.tile_work, A.order, A.qhead);
 }
 
 template <int TW, int TH, int PPT>
@@ -305,9 +395,10 @@ static void launch_render(const Batch& B, int lds_batch, int ppt, const RenderAr
   }
 }
 
-hipError_t launch_render_fwd(const Batch& B, int lds_batch, int ppt, const float* splat,
-                             const int32_t* vals, const int32_t* ranges, float* image, float* Tfin,
-                             int32_t* ncon, int32_t* tile_work, hipStream_t st) {
+hipError_t launch_render_fwd(const Batch& B, int lds_batch, int ppt, bool persistent,
+                             const float* splat, const int32_t* vals, const int32_t* ranges,
+                             int32_t* order, float* image, float* Tfin, int32_t* ncon,
+                             int32_t* tile_work, hipStream_t st) {
   if (B.total_tiles <= 0) return hipSuccess;
   RenderArgs A{};
   A.splat = reinterpret_cast<const float4*>(splat);
@@ -317,14 +408,17 @@ hipError_t launch_render_fwd(const Batch& B, int lds_batch, int ppt, const float
   A.Tfin = Tfin;
   A.ncon = ncon;
   A.tile_work = tile_work;
+  A.order = order;
+  A.qhead = order ? order + B.total_tiles : nullptr;
+  A.persistent = persistent && order;
   launch_render(B, lds_batch, ppt, A, false, st);
   return hipGetLastError();
 }
 
-hipError_t launch_render_bwd(const Batch& B, int lds_batch, int ppt, const float* splat,
-                             const int32_t* vals, const int32_t* ranges, const float* dimg,
-                             const float* Tfin, const int32_t* ncon, float* grad2d,
-                             hipStream_t st) {
+hipError_t launch_render_bwd(const Batch& B, int lds_batch, int ppt, bool persistent,
+                             const float* splat, const int32_t* vals, const int32_t* ranges,
+                             int32_t* order, const float* dimg, const float* Tfin,
+                             const int32_t* ncon, float* grad2d, hipStream_t st) {
   if (B.total_tiles <= 0) return hipSuccess;
   RenderArgs A{};
   A.splat = reinterpret_cast<const float4*>(splat);
@@ -334,6 +428,9 @@ hipError_t launch_render_bwd(const Batch& B, int lds_batch, int ppt, const float
   A.Tfin_in = Tfin;
   A.ncon_in = ncon;
   A.grad2d = grad2d;
+  A.order = order;
+  A.qhead = order ? order + B.total_tiles : nullptr;
+  A.persistent = persistent && order;
   launch_render(B, lds_batch, ppt, A, true, st);
   return hipGetLastError();
 }

@@ -456,6 +456,8 @@ __global__ void k_copy_u32(const uint32_t* __restrict__ a, const int64_t* n_dev,
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct BinWs {
+  uint32_t* okey[2];   // [tiles]  (tile order)
+  uint32_t* oval[2];   // [tiles]
   uint32_t* offsets;   // [n_rec]
   uint64_t* partials;  // scan block sums
   uint32_t* counts;    // [256 * nb]
@@ -467,7 +469,7 @@ struct BinWs {
   size_t bytes;
 };
 
-static BinWs bin_ws_layout(int64_t n_rec, int64_t cap, int sort_mode, char* base) {
+static BinWs bin_ws_layout(int64_t n_rec, int64_t cap, int64_t tiles, int sort_mode, char* base) {
   BinWs L{};
   size_t off = 0;
   auto take = [&](size_t bytes) -> char* {
@@ -475,7 +477,10 @@ static BinWs bin_ws_layout(int64_t n_rec, int64_t cap, int sort_mode, char* base
     off += align256(bytes);
     return p;
   };
-  const int64_t nb_max = (std::max(cap, n_rec) + kSortTile - 1) / kSortTile + 1;
+  const int64_t nb_max =
+      (std::max(std::max(cap, n_rec), tiles) + kSortTile - 1) / kSortTile + 1;
+  for (int k = 0; k < 2; ++k) L.okey[k] = (uint32_t*)take(4 * (size_t)std::max<int64_t>(tiles, 1));
+  for (int k = 0; k < 2; ++k) L.oval[k] = (uint32_t*)take(4 * (size_t)std::max<int64_t>(tiles, 1));
   const int64_t scan_n = std::max<int64_t>(256 * nb_max, n_rec);
   const int64_t nparts = (scan_n + kScanTile - 1) / kScanTile + 1;
   L.offsets = (uint32_t*)take(4 * (size_t)std::max<int64_t>(n_rec, 1));
@@ -493,8 +498,8 @@ static BinWs bin_ws_layout(int64_t n_rec, int64_t cap, int sort_mode, char* base
   return L;
 }
 
-size_t bin_workspace_bytes(int64_t n_rec, int64_t cap, int sort_mode) {
-  return bin_ws_layout(n_rec, cap, sort_mode, nullptr).bytes;
+size_t bin_workspace_bytes(int64_t n_rec, int64_t cap, int64_t tiles, int sort_mode) {
+  return bin_ws_layout(n_rec, cap, tiles, sort_mode, nullptr).bytes;
 }
 
 static inline int grid1(int64_t n, int bs = 256) { return (int)((n + bs - 1) / bs); }
@@ -504,8 +509,7 @@ static inline int grid1(int64_t n, int bs = 256) { return (int)((n + bs - 1) / b
 hipError_t bin_phase1(const Batch& B, int sort_mode, const float* depth, const int32_t* tc,
                       int64_t n_rec, int64_t cap, int64_t* n_isect, void* ws, hipStream_t st,
                       const uint32_t** perm_out) {
-  BinWs L = bin_ws_layout(n_rec, cap, sort_mode, (char*)ws);
-  (void)B;
+  BinWs L = bin_ws_layout(n_rec, cap, B.total_tiles, sort_mode, (char*)ws);
   *perm_out = nullptr;
   if (n_rec == 0) {
     hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, st, n_isect, (int64_t)0);
@@ -524,15 +528,45 @@ hipError_t bin_phase1(const Batch& B, int sort_mode, const float* depth, const i
   return device_scan(LoadCount{tc}, n_rec, L.offsets, L.partials, n_isect, st);
 }
 
+// Tiles by decreasing list length (ties by tile id): a stable sort of
+// 65535 - min(length, 65535).
+__global__ void k_tile_len_keys(const int2* __restrict__ ranges, int tiles, uint32_t* key,
+                                uint32_t* val) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= tiles) return;
+  const int2 r = ranges[t];
+  key[t] = 65535u - (uint32_t)min(r.y - r.x, 65535);
+  val[t] = (uint32_t)t;
+}
+
+static hipError_t tile_order_lpt(const Batch& B, const BinWs& L, const int2* ranges,
+                                 int32_t* order, hipStream_t st) {
+  const int64_t T = B.total_tiles;
+  if (T <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_len_keys, dim3(grid1(T)), dim3(256), 0, st, ranges, (int)T,
+                     L.okey[0], L.oval[0]);
+  uint32_t *ko, *vo;
+  hipError_t e = radix_sort<uint32_t>(L.okey[0], L.oval[0], L.okey[1], L.oval[1], nullptr, T, T,
+                                      16, L.counts, L.partials, &ko, &vo, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_copy_u32, dim3(grid1(T)), dim3(256), 0, st, vo, (const int64_t*)nullptr, T,
+                     (uint32_t*)order);
+  return hipGetLastError();
+}
+
 hipError_t bin_phase2(const Batch& B, int sort_mode, int tile_bits, const float* depth,
                       const int16_t* rect, const int32_t* tc, const uint32_t* perm, int64_t n_rec,
                       int64_t cap, int64_t grid_n, const int64_t* n_isect, uint64_t* keys_out,
-                      int32_t* vals, int2* ranges, void* ws, size_t ws_bytes, hipStream_t st) {
+                      int32_t* vals, int2* ranges, int32_t* tile_order, void* ws, size_t ws_bytes,
+                      hipStream_t st) {
   (void)ws_bytes;
-  BinWs L = bin_ws_layout(n_rec, cap, sort_mode, (char*)ws);
+  BinWs L = bin_ws_layout(n_rec, cap, B.total_tiles, sort_mode, (char*)ws);
   hipLaunchKernelGGL(k_fill_u32, dim3(grid1(2 * (int64_t)B.total_tiles)), dim3(256), 0, st,
                      (uint32_t*)ranges, 2 * (int64_t)B.total_tiles, 0u);
-  if (n_rec == 0 || grid_n == 0) return hipGetLastError();
+  if (n_rec == 0 || grid_n == 0) {
+    if (tile_order) return tile_order_lpt(B, L, ranges, tile_order, st);
+    return hipGetLastError();
+  }
   const short4* rc = reinterpret_cast<const short4*>(rect);
   uint32_t* vals_u = reinterpret_cast<uint32_t*>(vals);
   const int nbd = grid1(n_rec);
@@ -576,6 +610,7 @@ hipError_t bin_phase2(const Batch& B, int sort_mode, int tile_bits, const float*
       hipLaunchKernelGGL(k_copy_u32, dim3(grid1(grid_n)), dim3(256), 0, st, vo, n_isect, cap,
                          vals_u);
   }
+  if (tile_order) return tile_order_lpt(B, L, ranges, tile_order, st);
   return hipGetLastError();
 }
 

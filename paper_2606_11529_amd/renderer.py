@@ -35,6 +35,7 @@ class Config:
     fwd_ppt: int = 2            # pixels per thread, forward (16x16 tiles)
     bwd_ppt: int = 4            # pixels per thread, backward (16x16 tiles)
     bwd_lds_batch: int = 0      # LDS batch of the backward (0: lds_batch)
+    persistent: bool = False    # persistent render grids over the tile order
 
     def to_c(self) -> L.XprConfig:
         c = L.XprConfig()
@@ -54,6 +55,7 @@ class Config:
         c.fwd_ppt = int(self.fwd_ppt)
         c.bwd_ppt = int(self.bwd_ppt)
         c.bwd_lds_batch = int(self.bwd_lds_batch)
+        c.persistent = 1 if self.persistent else 0
         return c
 
 
@@ -186,6 +188,13 @@ class Bins:
     keys: Optional[torch.Tensor] = None  # [cap] i64 (bits of uint64)
     capacity: int = 0
     count: int = -1        # host copy of n_isect when known
+    tile_order: Optional[torch.Tensor] = None  # [tiles + 1] i32
+
+    def to_c(self) -> L.XprBins:
+        return L.XprBins(self.keys.data_ptr() if self.keys is not None else None,
+                         self.vals.data_ptr(), self.ranges.data_ptr(), self.n_isect.data_ptr(),
+                         self.tile_order.data_ptr() if self.tile_order is not None else None,
+                         self.capacity)
 
 
 @dataclasses.dataclass
@@ -229,25 +238,37 @@ _WS = Workspace()
 
 def xpr_bin_sort(views: Views, cfg: Config, proj: Projected, capacity: Optional[int] = None,
                  want_keys: bool = False, ws: Optional[Workspace] = None,
-                 out: Optional[Bins] = None) -> Bins:
-    """Binning with a host-side capacity retry on XPR_ERR_CAPACITY."""
+                 out: Optional[Bins] = None, want_order: Optional[bool] = None) -> Bins:
+    """Binning with a host-side capacity retry on XPR_ERR_CAPACITY. The
+    longest-first tile order is produced when ``want_order`` (default: when
+    the config is persistent)."""
     ws = ws or _WS
     dev = proj.splat.device
+    want_order = cfg.persistent if want_order is None else want_order
     cap = capacity if capacity is not None else max(1024, 16 * views.records)
     if out is not None and out.capacity >= cap:
         cap = out.capacity
     while True:
-        if out is None or out.capacity < cap or (want_keys and out.keys is None):
+        if (out is None or out.capacity < cap or (want_keys and out.keys is None)
+                or out.ranges.shape[0] < views.tiles
+                or (want_order and (out.tile_order is None
+                                    or out.tile_order.numel() < views.tiles + 1))):
             out = Bins(vals=torch.empty(max(cap, 1), dtype=torch.int32, device=dev),
                        ranges=torch.empty((max(views.tiles, 1), 2), dtype=torch.int32, device=dev),
                        n_isect=torch.zeros(1, dtype=torch.int64, device=dev),
                        keys=torch.empty(max(cap, 1), dtype=torch.int64, device=dev) if want_keys else None,
-                       capacity=cap)
+                       capacity=cap,
+                       tile_order=torch.empty(views.tiles + 1, dtype=torch.int32, device=dev)
+                       if want_order else None)
+        bc = out.to_c()
+        if not want_keys:
+            bc.keys = None
+        if not want_order:
+            bc.tile_order = None
         nbytes = L.xpr_bin_sort_workspace(views.c, views.cfg_c, cap)
         wsb = ws.get("bin", nbytes, dev)
-        st = L.xpr_bin_sort(views.c, views.cfg_c, proj.to_c(), cap,
-                            _ptr(out.keys) if want_keys else None, _ptr(out.vals),
-                            _ptr(out.ranges), _ptr(out.n_isect), _ptr(wsb), wsb.numel(), _stream())
+        st = L.xpr_bin_sort(views.c, views.cfg_c, proj.to_c(), bc, _ptr(wsb), wsb.numel(),
+                            _stream())
         if st == L.XPR_OK:
             if not cfg.no_sync:
                 out.count = int(out.n_isect.item())
@@ -264,9 +285,8 @@ def xpr_render_fwd(views: Views, cfg: Config, proj: Projected, bins: Bins,
         out = Frame(torch.empty(3 * views.pixels, dtype=torch.float32, device=dev),
                     torch.empty(views.pixels, dtype=torch.float32, device=dev),
                     torch.empty(views.pixels, dtype=torch.int32, device=dev))
-    L.xpr_render_fwd(views.c, views.cfg_c, proj.to_c(), _ptr(bins.vals), _ptr(bins.ranges),
-                     _ptr(out.image), _ptr(out.T_final), _ptr(out.n_contrib), _ptr(tile_work),
-                     _stream())
+    L.xpr_render_fwd(views.c, views.cfg_c, proj.to_c(), bins.to_c(), _ptr(out.image),
+                     _ptr(out.T_final), _ptr(out.n_contrib), _ptr(tile_work), _stream())
     return out
 
 
@@ -293,9 +313,9 @@ def xpr_render_bwd(views: Views, cfg: Config, proj: Projected, bins: Bins, frame
         grad2d = torch.empty((max(views.records, 1), 9), dtype=torch.float32, device=dev)
     nbytes = L.xpr_render_bwd_workspace(views.c, views.cfg_c)
     wsb = ws.get("bwd", nbytes, dev)
-    L.xpr_render_bwd(views.c, views.cfg_c, proj.to_c(), _ptr(bins.vals), _ptr(bins.ranges),
-                     _ptr(dimage), _ptr(frame.T_final), _ptr(frame.n_contrib), arr,
-                     1 if accumulate else 0, _ptr(grad2d), _ptr(wsb), wsb.numel(), _stream())
+    L.xpr_render_bwd(views.c, views.cfg_c, proj.to_c(), bins.to_c(), _ptr(dimage),
+                     _ptr(frame.T_final), _ptr(frame.n_contrib), arr, 1 if accumulate else 0,
+                     _ptr(grad2d), _ptr(wsb), wsb.numel(), _stream())
     return (grads if params else None), grad2d
 
 

@@ -36,6 +36,7 @@ def test_library_exports_every_symbol():
 def test_struct_layouts_match_c_header(tmp_path):
     # sizeof/offsetof of every struct from the C compiler vs the ctypes mirror
     structs = {"xpr_camera": L.XprCamera, "xpr_config": L.XprConfig, "xpr_scene": L.XprScene,
+               "xpr_bins": L.XprBins,
                "xpr_scene_grad": L.XprSceneGrad, "xpr_views": L.XprViews,
                "xpr_projected": L.XprProjected, "xpr_sizes": L.XprSizes}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "xpr.h"', "int main(void) {"]
@@ -88,7 +89,7 @@ def test_batch_sizes():
 @pytest.mark.parametrize("field,value", [
     ("tile_w", 12), ("lds_batch", 100), ("sh_degree", 4), ("alpha_min", 0.0),
     ("alpha_max", 1.5), ("t_min", 0.0), ("z_near", 0.0), ("sort_mode", 7), ("lowpass", -1.0),
-    ("fwd_ppt", 3), ("bwd_ppt", 8)])
+    ("fwd_ppt", 3), ("bwd_ppt", 8), ("bwd_lds_batch", 100)])
 def test_invalid_config_rejected(field, value):
     v = _views()
     c = L.xpr_config_default()
@@ -143,8 +144,9 @@ def test_workspace_queries_host_only():
 def test_bin_sort_rejects_small_workspace():
     v = _views(n=100)
     c = L.xpr_config_default()
+    bins = L.XprBins(None, 4096, 4096, 4096, None, 1000)
     st = L.lib().xpr_bin_sort(ctypes.byref(v), ctypes.byref(c),
-                              ctypes.byref(L.XprProjected(4096, 4096, 4096, 4096)), 1000,
-                              None, 4096, 4096, 4096, 4096, 16, None)
+                              ctypes.byref(L.XprProjected(4096, 4096, 4096, 4096)),
+                              ctypes.byref(bins), 4096, 16, None)
     assert st == L.XPR_ERR_INVALID_ARG
     assert "workspace" in L.xpr_last_error()

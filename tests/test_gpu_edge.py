@@ -105,20 +105,17 @@ def test_capacity_error_and_retry():
     n_isect = torch.zeros(1, dtype=torch.int64, device="cuda")
     nb = L.xpr_bin_sort_workspace(views.c, views.cfg_c, cap)
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
-    st = L.xpr_bin_sort(views.c, views.cfg_c, proj.to_c(), cap, None,
-                        ctypes.c_void_p(vals.data_ptr()), ctypes.c_void_p(ranges.data_ptr()),
-                        ctypes.c_void_p(n_isect.data_ptr()), ctypes.c_void_p(ws.data_ptr()), nb,
-                        R._stream())
+    bins = L.XprBins(None, vals.data_ptr(), ranges.data_ptr(), n_isect.data_ptr(), None, cap)
+    st = L.xpr_bin_sort(views.c, views.cfg_c, proj.to_c(), bins, ctypes.c_void_p(ws.data_ptr()),
+                        nb, R._stream())
     assert st == L.XPR_ERR_CAPACITY
     assert int(n_isect.item()) == I
     assert "exceed" in L.xpr_last_error()
     # no-readback mode: status OK, the caller sees n_isect > capacity
     cfg2 = R.Config(no_sync=True)
     views2 = R.Views([scene], [cam], [0], cfg2)
-    st = L.xpr_bin_sort(views2.c, views2.cfg_c, proj.to_c(), cap, None,
-                        ctypes.c_void_p(vals.data_ptr()), ctypes.c_void_p(ranges.data_ptr()),
-                        ctypes.c_void_p(n_isect.data_ptr()), ctypes.c_void_p(ws.data_ptr()), nb,
-                        R._stream())
+    st = L.xpr_bin_sort(views2.c, views2.cfg_c, proj.to_c(), bins, ctypes.c_void_p(ws.data_ptr()),
+                        nb, R._stream())
     assert st == L.XPR_OK
     torch.cuda.synchronize()
     assert int(n_isect.item()) == I
@@ -176,3 +173,29 @@ def test_multi_scene_batch():
     for v, (sc, cam) in enumerate(zip([a, b, a], cams)):
         one = run_gpu(sc, cam, cfg)
         assert np.array_equal(views.image(frame.image, v).cpu().numpy(), one["image"][0]), v
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_tile_order_and_persistent_grids_match(persistent):
+    sc = _small(6000, seed=12)
+    cams = random_cameras(3, 9, [(96, 64), (130, 77), (48, 48)], radius=4.5)
+    rng = np.random.default_rng(0)
+    dimgs = [rng.normal(size=(3, c.height, c.width)).astype(np.float32) for c in cams]
+    ref = run_gpu(sc, cams, R.Config(), dimgs=dimgs)
+    cfg = R.Config(persistent=persistent)
+    scene = R.Scene.from_host(sc)
+    views = R.Views([scene], cams, [0] * len(cams), cfg)
+    proj = R.xpr_project(views, cfg)
+    bins = R.xpr_bin_sort(views, cfg, proj, want_order=True)
+    order = bins.tile_order[:views.tiles].cpu().numpy()
+    lens = (bins.ranges[:, 1] - bins.ranges[:, 0]).cpu().numpy()
+    assert sorted(order.tolist()) == list(range(views.tiles))
+    assert np.all(np.diff(lens[order]) <= 0)
+    frame = R.xpr_render_fwd(views, cfg, proj, bins)
+    flat = torch.cat([torch.from_numpy(d).reshape(-1) for d in dimgs]).cuda()
+    _, g2 = R.xpr_render_bwd(views, cfg, proj, bins, frame, flat, params=False)
+    torch.cuda.synchronize()
+    for v in range(len(cams)):
+        assert np.array_equal(views.image(frame.image, v).cpu().numpy(), ref["image"][v])
+    g2 = g2.cpu().numpy()[:views.records]
+    np.testing.assert_allclose(g2, ref["grad2d"], rtol=1e-4, atol=1e-6 * np.abs(ref["grad2d"]).max())
