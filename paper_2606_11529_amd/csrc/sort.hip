@@ -411,19 +411,34 @@ static hipError_t radix_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const int
 static inline int radix_passes(int bits) { return (bits + 7) / 8; }
 
 // ---------------------------------------------------------------------------
-// Tile ranges from sorted keys (tile in the high part for 64-bit keys).
+// Tile ranges from sorted keys (tile in the high part for 64-bit keys). Each
+// thread reads 4 consecutive keys plus the one before them and writes the
+// starts and ends of the tiles that change inside that window.
+template <typename K>
+__device__ __forceinline__ uint32_t tile_of(K k) {
+  return (uint32_t)(k >> (sizeof(K) == 8 ? 32 : 0));
+}
 
 template <typename K>
 __global__ void k_ranges(const K* __restrict__ keys, const int64_t* n_dev, int64_t cap,
                          int total_tiles, int2* __restrict__ ranges) {
   const int64_t n = clamp_n(n_dev, cap);
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int sh = sizeof(K) == 8 ? 32 : 0;
-  const uint32_t tile = (uint32_t)(keys[i] >> sh);
-  if (tile >= (uint32_t)total_tiles) return;
-  if (i == 0 || (uint32_t)(keys[i - 1] >> sh) != tile) ranges[tile].x = (int)i;
-  if (i == n - 1 || (uint32_t)(keys[i + 1] >> sh) != tile) ranges[tile].y = (int)(i + 1);
+  const int64_t i0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  if (i0 >= n) return;
+  uint32_t t[5];
+  t[0] = i0 > 0 ? tile_of(keys[i0 - 1]) : 0xffffffffu;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) t[j + 1] = i0 + j < n ? tile_of(keys[i0 + j]) : 0xffffffffu;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t i = i0 + j;
+    if (i >= n) break;
+    const uint32_t cur = t[j + 1];
+    if (cur >= (uint32_t)total_tiles) continue;
+    if (t[j] != cur) ranges[cur].x = (int)i;
+    const uint32_t nxt = j < 3 ? t[j + 2] : (i + 1 < n ? tile_of(keys[i + 1]) : 0xffffffffu);
+    if (nxt != cur) ranges[cur].y = (int)(i + 1);
+  }
 }
 
 // 64-bit output keys of the presort path: tile << 32 | depth bits.
@@ -581,8 +596,8 @@ hipError_t bin_phase2(const Batch& B, int sort_mode, int tile_bits, const float*
     hipError_t e = radix_sort<uint32_t>(L.tkey[0], v_start, L.tkey[1], v_other, n_isect, cap,
                                         grid_n, tile_bits, L.counts, L.partials, &ko, &vo, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ranges<uint32_t>, dim3(grid1(grid_n)), dim3(256), 0, st, ko, n_isect, cap,
-                       B.total_tiles, ranges);
+    hipLaunchKernelGGL(k_ranges<uint32_t>, dim3(grid1((grid_n + 3) / 4)), dim3(256), 0, st, ko,
+                       n_isect, cap, B.total_tiles, ranges);
     if (keys_out)
       hipLaunchKernelGGL(k_make_keys64, dim3(grid1(grid_n)), dim3(256), 0, st, ko, vo, depth,
                          n_isect, cap, keys_out);
@@ -601,8 +616,8 @@ hipError_t bin_phase2(const Batch& B, int sort_mode, int tile_bits, const float*
     hipError_t e = radix_sort<uint64_t>(L.key64[0], v_start, L.key64[1], v_other, n_isect, cap,
                                         grid_n, bits, L.counts, L.partials, &ko, &vo, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ranges<uint64_t>, dim3(grid1(grid_n)), dim3(256), 0, st, ko, n_isect, cap,
-                       B.total_tiles, ranges);
+    hipLaunchKernelGGL(k_ranges<uint64_t>, dim3(grid1((grid_n + 3) / 4)), dim3(256), 0, st, ko,
+                       n_isect, cap, B.total_tiles, ranges);
     if (keys_out)
       hipLaunchKernelGGL(k_copy_u64, dim3(grid1(grid_n)), dim3(256), 0, st, ko, n_isect, cap,
                          keys_out);
