@@ -267,18 +267,19 @@ __global__ __launch_bounds__(256) void k_duplicate(Batch B, const short4* __rest
 }
 
 // ---------------------------------------------------------------------------
-// LSD radix sort, 8-bit digits.
+// LSD radix sort with BITS-bit digits (7 or 8).
 
-template <typename K>
+template <int BITS, typename K>
 __device__ __forceinline__ uint32_t digit_of(K k, int shift) {
-  return (uint32_t)(k >> shift) & 0xffu;
+  return (uint32_t)(k >> shift) & ((1u << BITS) - 1u);
 }
 
-// Lanes of the wave holding the same 8-bit digit (among active lanes).
+// Lanes of the wave holding the same BITS-bit digit (among active lanes).
+template <int BITS>
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool active) {
   uint64_t m = __ballot(active);
 #pragma unroll
-  for (int b = 0; b < 8; ++b) {
+  for (int b = 0; b < BITS; ++b) {
     const bool bit = (d >> b) & 1u;
     const uint64_t bb = __ballot(bit);
     m &= bit ? bb : ~bb;
@@ -291,30 +292,41 @@ __device__ __forceinline__ int64_t clamp_n(const int64_t* n_dev, int64_t cap) {
   return n < cap ? n : cap;
 }
 
-template <typename K>
+// Digit counts of one block of kSortTile keys, written digit-major
+// (counts[d * nblocks + b]) for the scan. Eight lane-indexed copies of the
+// histogram keep LDS atomic collisions at most 8-way.
+template <int BITS, typename K>
 __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys,
                                                     const int64_t* n_dev, int64_t cap, int shift,
                                                     uint32_t* __restrict__ counts, int nblocks) {
-  __shared__ uint32_t h[kSortWaves][256];
-  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  for (int k = t; k < kSortWaves * 256; k += 256) (&h[0][0])[k] = 0;
+  constexpr int RADIX = 1 << BITS;
+  constexpr int COPIES = 8;
+  __shared__ uint32_t h[COPIES][RADIX];
+  const int t = threadIdx.x;
+  for (int k = t; k < COPIES * RADIX; k += 256) (&h[0][0])[k] = 0;
   __syncthreads();
   const int64_t n = clamp_n(n_dev, cap);
-  const int64_t base = (int64_t)blockIdx.x * kSortTile + w * (64 * kSortItems);
-  const uint64_t lt = lanemask_lt();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  uint32_t* mine = h[t & (COPIES - 1)];
 #pragma unroll 4
   for (int j = 0; j < kSortItems; ++j) {
-    const int64_t idx = base + j * 64 + lane;
-    const bool ok = idx < n;
-    const uint32_t d = ok ? digit_of(keys[idx], shift) : 0u;
-    const uint64_t m = match_digit(d, ok);
-    if (ok && (m & lt) == 0) h[w][d] += (uint32_t)__popcll(m);
+    const int64_t idx = base + j * 256 + t;
+    if (idx < n) atomicAdd(&mine[digit_of<BITS>(keys[idx], shift)], 1u);
   }
   __syncthreads();
-  counts[(int64_t)t * nblocks + blockIdx.x] = h[0][t] + h[1][t] + h[2][t] + h[3][t];
+  if (t < RADIX) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < COPIES; ++k) c += h[k][t];
+    counts[(int64_t)t * nblocks + blockIdx.x] = c;
+  }
 }
 
-template <typename K>
+// Stable scatter of one block: rank the block's keys by digit in LDS (per
+// wave, slot by slot, the wave64 ballot match gives the rank among lanes
+// with the same digit), then write them out in digit order so each digit's
+// run is a contiguous global store.
+template <int BITS, typename K>
 __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin,
                                                        const uint32_t* __restrict__ vin,
                                                        K* __restrict__ kout,
@@ -323,13 +335,14 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
                                                        int shift,
                                                        const uint32_t* __restrict__ offsets,
                                                        int nblocks) {
-  __shared__ uint32_t wcnt[kSortWaves][256];
-  __shared__ uint32_t dstart[256];
+  constexpr int RADIX = 1 << BITS;
+  __shared__ uint32_t wcnt[kSortWaves][RADIX];
+  __shared__ uint32_t dstart[RADIX];
   __shared__ uint32_t s_wave[4];
   __shared__ K skey[kSortTile];
   __shared__ uint32_t sval[kSortTile];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  for (int k = t; k < kSortWaves * 256; k += 256) (&wcnt[0][0])[k] = 0;
+  for (int k = t; k < kSortWaves * RADIX; k += 256) (&wcnt[0][0])[k] = 0;
   __syncthreads();
   const int64_t n = clamp_n(n_dev, cap);
   const int64_t bbase = (int64_t)blockIdx.x * kSortTile;
@@ -344,27 +357,35 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
     const bool ok = idx < n;
     key[j] = ok ? kin[idx] : (K)0;
     val[j] = ok ? vin[idx] : 0u;
-    const uint32_t d = digit_of(key[j], shift);
-    const uint64_t m = match_digit(d, ok);
+    const uint32_t d = digit_of<BITS>(key[j], shift);
+    const uint64_t m = match_digit<BITS>(d, ok);
     const uint32_t before = wcnt[w][d];
     lofs[j] = before + (uint32_t)__popcll(m & lt);
     if (ok && (m & lt) == 0) wcnt[w][d] = before + (uint32_t)__popcll(m);
   }
   __syncthreads();
   // digit t: block totals, exclusive block start, per-wave starts
-  const uint32_t c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
+  uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+  if (t < RADIX) {
+    c0 = wcnt[0][t];
+    c1 = wcnt[1][t];
+    c2 = wcnt[2][t];
+    c3 = wcnt[3][t];
+  }
   const uint32_t start = block_excl_scan256(c0 + c1 + c2 + c3, s_wave, nullptr);
-  dstart[t] = start;
-  wcnt[0][t] = start;
-  wcnt[1][t] = start + c0;
-  wcnt[2][t] = start + c0 + c1;
-  wcnt[3][t] = start + c0 + c1 + c2;
+  if (t < RADIX) {
+    dstart[t] = start;
+    wcnt[0][t] = start;
+    wcnt[1][t] = start + c0;
+    wcnt[2][t] = start + c0 + c1;
+    wcnt[3][t] = start + c0 + c1 + c2;
+  }
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < kSortItems; ++j) {
     const int64_t idx = base + j * 64 + lane;
     if (idx < n) {
-      const uint32_t pos = wcnt[w][digit_of(key[j], shift)] + lofs[j];
+      const uint32_t pos = wcnt[w][digit_of<BITS>(key[j], shift)] + lofs[j];
       skey[pos] = key[j];
       sval[pos] = val[j];
     }
@@ -374,11 +395,34 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
   const int nvalid = rem <= 0 ? 0 : (rem < kSortTile ? (int)rem : kSortTile);
   for (int k = t; k < nvalid; k += 256) {
     const K kk = skey[k];
-    const uint32_t d = digit_of(kk, shift);
+    const uint32_t d = digit_of<BITS>(kk, shift);
     const uint32_t g = offsets[(int64_t)d * nblocks + blockIdx.x] + (uint32_t)k - dstart[d];
     kout[g] = kk;
     vout[g] = sval[k];
   }
+}
+
+// Digit width for sorting `bits` bits: 7 when that needs no more passes than
+// 8 (longer per-digit runs in the scatter, one ballot fewer per key).
+static inline int radix_digit_bits(int bits) { return (bits + 6) / 7 == (bits + 7) / 8 ? 7 : 8; }
+
+// Number of passes radix_sort makes for `bits`.
+static inline int radix_passes(int bits) {
+  const int d = radix_digit_bits(bits);
+  return (bits + d - 1) / d;
+}
+
+template <int BITS, typename K>
+static hipError_t radix_pass(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const int64_t* n_dev,
+                             int64_t cap, int nb, int shift, uint32_t* counts,
+                             uint64_t* partials, hipStream_t st) {
+  hipLaunchKernelGGL((k_radix_hist<BITS, K>), dim3(nb), dim3(256), 0, st, k0, n_dev, cap, shift,
+                     counts, nb);
+  hipError_t e = device_scan(LoadArray{counts}, (int64_t)nb << BITS, counts, partials, nullptr, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_radix_scatter<BITS, K>), dim3(nb), dim3(256), 0, st, k0, v0, k1, v1, n_dev,
+                     cap, shift, counts, nb);
+  return hipGetLastError();
 }
 
 // Sorts (keys, vals) of length n_dev (<= cap) on bits [0, bits). The data
@@ -392,13 +436,12 @@ static hipError_t radix_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const int
   *v_out = v0;
   if (grid_n <= 0) return hipSuccess;
   const int nb = (int)((grid_n + kSortTile - 1) / kSortTile);
-  for (int shift = 0; shift < bits; shift += 8) {
-    hipLaunchKernelGGL(k_radix_hist<K>, dim3(nb), dim3(256), 0, st, k0, n_dev, cap, shift, counts,
-                       nb);
-    hipError_t e = device_scan(LoadArray{counts}, (int64_t)nb * 256, counts, partials, nullptr, st);
+  const int dbits = radix_digit_bits(bits);
+  for (int shift = 0; shift < bits; shift += dbits) {
+    hipError_t e = dbits == 7
+                       ? radix_pass<7, K>(k0, v0, k1, v1, n_dev, cap, nb, shift, counts, partials, st)
+                       : radix_pass<8, K>(k0, v0, k1, v1, n_dev, cap, nb, shift, counts, partials, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_radix_scatter<K>, dim3(nb), dim3(256), 0, st, k0, v0, k1, v1, n_dev, cap,
-                       shift, counts, nb);
     K* tk = k0; k0 = k1; k1 = tk;
     uint32_t* tv = v0; v0 = v1; v1 = tv;
   }
@@ -406,9 +449,6 @@ static hipError_t radix_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const int
   *v_out = v0;
   return hipGetLastError();
 }
-
-// Number of passes radix_sort makes for `bits`.
-static inline int radix_passes(int bits) { return (bits + 7) / 8; }
 
 // ---------------------------------------------------------------------------
 // Tile ranges from sorted keys (tile in the high part for 64-bit keys). Each
