@@ -12,6 +12,7 @@ in HBM before the timed region. Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import platform
@@ -47,6 +48,9 @@ def main():
     ap.add_argument("--sort", default="presort")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=1000)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -220,11 +224,121 @@ def main():
     }
     log(f"[bench] frame {frame_ms:.3f} ms (stage sum), wall {ms_wall:.3f} ms/step")
 
+    del scene, proj, bins, frame, g2, grads, targets, views
+    torch.cuda.empty_cache()
+    if not args.no_batch:
+        out["batched"] = bench_batched()
+    if not args.no_serve:
+        out["serving"] = bench_serving(args.serve_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, cams[0], cfg)
     if tuned is not None:
         out["autotune_ms"] = tuned.ms
     print(json.dumps(out), flush=True)
+
+
+def bench_batched(n=2_000_000, n_views=16, reps=5):
+    """16 cameras at uneven resolutions of one 2M-Gaussian scene: one
+    graph-captured batched step (autotuned knobs, gradients summed over the
+    views) against the same step as 16 plain per-view launches."""
+    import numpy as np
+    import torch
+
+    from paper_2606_11529_amd import renderer as R
+    from paper_2606_11529_amd.autotune import autotune
+    from paper_2606_11529_amd.batch import BatchRenderer, per_view_step
+    from synth import CONFIGS, random_cameras, scene_clusters
+
+    t0 = time.time()
+    sc = scene_clusters(n, seed=0)
+    cams = random_cameras(n_views, 0, CONFIGS["c4"]["res_set"])
+    scene = R.Scene.from_host(sc)
+    del sc
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    targets = [torch.rand((3, c.height, c.width), generator=gen, device="cuda") for c in cams]
+    pixels = sum(c.width * c.height for c in cams)
+    log(f"[batch] scene {n}, {n_views} views, {pixels / 1e6:.1f} Mpx ({time.time() - t0:.1f}s)")
+    tuned = autotune(scene, cams, R.Config(persistent=True), tiles=(8, 16), reps=1)
+    cfg = tuned.apply(R.Config(persistent=True))
+    log(f"[batch] autotuned tile {cfg.tile}, sort {cfg.sort_mode}, fwd {cfg.lds_batch}x"
+        f"{cfg.fwd_ppt}, bwd {cfg.bwd_lds_batch}x{cfg.bwd_ppt}")
+    br = BatchRenderer([scene], cams, [0] * n_views, cfg, targets)
+    br.capture()
+    br.run()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        br.run()
+    ev[1].record()
+    torch.cuda.synchronize()
+    batched_ms = ev[0].elapsed_time(ev[1]) / reps
+    overflow = br.overflowed()
+    pairs = int(br.bins.n_isect.item())
+    img_b = [br.image(v).clone() for v in range(n_views)]
+    del br
+    torch.cuda.empty_cache()
+    # the same work as plain per-view launches (tile size as tuned)
+    pcfg = dataclasses.replace(cfg, persistent=False)
+    ws = R.Workspace()
+    states = [dict() for _ in cams]
+    for v, cam in enumerate(cams):
+        per_view_step(scene, cam, pcfg, targets[v], ws=ws, state=states[v])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        for v, cam in enumerate(cams):
+            per_view_step(scene, cam, pcfg, targets[v], ws=ws, state=states[v])
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t1) * 1e3 / reps
+    same = all(torch.equal(img_b[v], states[v]["views"].image(states[v]["frame"].image, 0))
+               for v in range(n_views))
+    log(f"[batch] graph batched {batched_ms:.2f} ms vs per-view {plain_ms:.2f} ms per 16-view step")
+    return {"workload": f"{n} Gaussians, {n_views} views at uneven resolutions "
+                        f"({pixels / 1e6:.1f} Mpx), forward+backward, gradients summed",
+            "pairs": pairs, "overflow": overflow, "tuned": dataclasses.asdict(tuned),
+            "batched_graph_ms_per_step": batched_ms, "per_view_plain_ms_per_step": plain_ms,
+            "speedup": plain_ms / batched_ms, "ms_per_view_batched": batched_ms / n_views,
+            "images_identical": bool(same)}
+
+
+def bench_serving(n_requests=1000):
+    """Four resident scenes (100k, 500k, 1.5M, 3M); Poisson view requests at
+    200/s, uniform scene, random camera on the radius-6 sphere, resolution
+    uniform in {512x512, 1280x720, 1920x1080}; forward only. The continuous-
+    batching server against a FIFO server that renders one request at a
+    time with plain launches."""
+    import torch
+
+    from paper_2606_11529_amd import renderer as R
+    from paper_2606_11529_amd import serve as S
+    from synth import CONFIGS, request_stream, scene_clusters
+
+    c5 = CONFIGS["c5"]
+    scenes = {k: R.Scene.from_host(scene_clusters(n, seed=k)) for k, n in enumerate(c5["scenes"])}
+    arrivals = request_stream(n_requests + 100, c5["rate_hz"], len(scenes), c5["res_set"])
+    cfg = R.Config()
+    out = {"workload": f"4 resident scenes {c5['scenes']}, Poisson {c5['rate_hz']:.0f}/s, "
+                       f"{n_requests} requests after 100 warm-up, forward only, 4 GiB budget"}
+    for name, mv, slots in (("continuous_batching", 8, 2), ("fifo_one_at_a_time", 1, 1)):
+        srv = S.Server(scenes, cfg, 4 << 30, max_views=mv, slots=slots, keep_images=False)
+        S.replay(srv, arrivals[:100])            # warm-up (estimator, allocator)
+        srv.done.clear()
+        torch.cuda.synchronize()
+        t0 = arrivals[100][0]
+        rest = [(a - t0, sid, cam) for a, sid, cam in arrivals[100:]]
+        wall = S.replay(srv, rest)
+        st = S.latency_stats(srv.done)
+        st.update(frames_per_s=len(srv.done) / wall, wall_s=wall, max_views=mv, slots=slots)
+        # saturation: all requests at once
+        srv.done.clear()
+        wall_sat = S.replay(srv, [(0.0, sid, cam) for _, sid, cam in rest])
+        st["saturated_frames_per_s"] = len(srv.done) / wall_sat
+        log(f"[serve] {name}: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms "
+            f"{st['frames_per_s']:.1f} fps, saturated {st['saturated_frames_per_s']:.1f} fps")
+        out[name] = st
+    return out
 
 
 def cpu_baseline(sc, cam, cfg):
