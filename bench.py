@@ -51,6 +51,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--fwd-ppt", type=int, default=None)
+    ap.add_argument("--bwd-ppt", type=int, default=None)
+    ap.add_argument("--bwd-lds-batch", type=int, default=None)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -71,6 +74,9 @@ def main():
     cams = random_cameras(8, 0, (args.width, args.height))
     log(f"[bench] scene {args.n} generated in {time.time() - t0:.1f}s")
     cfg = R.Config(tile=args.tile, lds_batch=args.lds_batch, sh_degree=3, sort_mode=args.sort)
+    for k in ("fwd_ppt", "bwd_ppt", "bwd_lds_batch"):
+        if getattr(args, k) is not None:
+            cfg = dataclasses.replace(cfg, **{k: getattr(args, k)})
     scene = R.Scene.from_host(sc, dev)
     tuned = None
     if not args.no_autotune:

@@ -21,6 +21,16 @@ def log(*a):
     sys.stdout.flush()
 
 
+def cam32(cam):
+    """The camera exactly as the C-ABI receives it (float32 fields), as
+    float64 values for the oracle: both sides then start from identical
+    inputs."""
+    import dataclasses
+    f = lambda x: np.asarray(x, np.float32).astype(np.float64)
+    return dataclasses.replace(cam, R=f(cam.R), t=f(cam.t), fx=float(f(cam.fx)),
+                               fy=float(f(cam.fy)), cx=float(f(cam.cx)), cy=float(f(cam.cy)))
+
+
 def ocfg_of(cfg: R.Config) -> oracle.OracleConfig:
     return oracle.OracleConfig(tile_w=cfg.tile, tile_h=cfg.tile, sh_degree=cfg.sh_degree,
                                lowpass=cfg.lowpass, alpha_min=cfg.alpha_min,
@@ -71,7 +81,7 @@ def check_projection(sc, cam, cfg, gpu, rec_off=0, idx=None):
     Gaussians. Returns (number of guard Gaussians, number checked)."""
     oc = ocfg_of(cfg)
     sub = sc if idx is None else sc.subset(idx)
-    ref = oracle.project(sub, cam, oc)
+    ref = oracle.project(sub, cam32(cam), oc)
     n = sub.n
     sel = np.arange(rec_off, rec_off + sc.n) if idx is None else rec_off + np.asarray(idx)
     g_rec = rec9(gpu["splat"][sel])

@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import log, ocfg_of
+from gpu_util import cam32, log, ocfg_of
 from paper_2606_11529_amd import renderer as R
 from paper_2606_11529_amd.autograd import GaussianModel, RasterizeViews, rasterize
 from synth import camera_look_at, random_cameras, scene_clusters
@@ -42,7 +42,7 @@ def test_autograd_matches_direct_backward_and_oracle():
         assert (p.grad - ref).abs().max().item() <= 1e-5 * scale, k
     # end-to-end against the FP64 oracle's analytic gradient (report + bound)
     oc = ocfg_of(cfg)
-    og = oracle.backward(sc, cam, oc, dimg.cpu().numpy().astype(np.float64))
+    og = oracle.backward(sc, cam32(cam), oc, dimg.cpu().numpy().astype(np.float64))
     for p, k in zip(params, names):
         g = p.grad.cpu().numpy().astype(np.float64)
         r = og[k]

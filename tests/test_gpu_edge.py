@@ -80,10 +80,15 @@ def test_deterministic_and_order_invariant():
     b = run_gpu(sc, cam, R.Config())
     assert np.array_equal(a["image"][0], b["image"][0])
     assert np.array_equal(a["vals"], b["vals"])
+    # relabelling: keep Gaussians with distinct float32 depths (a tie is
+    # broken by the index, which a relabelling changes)
+    _, first, counts = np.unique(a["depth"], return_index=True, return_counts=True)
+    keep = np.sort(first[counts == 1])
+    sc = sc.subset(keep)
+    a = run_gpu(sc, cam, R.Config())
     perm = np.random.default_rng(0).permutation(sc.n)
     c = run_gpu(sc.subset(perm), cam, R.Config())
     # the same Gaussians composited in the same depth order
-    assert len(np.unique(a["depth"][a["tc"] > 0])) == int((a["tc"] > 0).sum())
     assert np.array_equal(a["image"][0], c["image"][0])
     assert np.array_equal(perm[c["vals"]], a["vals"])
 

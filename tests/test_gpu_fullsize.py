@@ -9,8 +9,8 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import (check_forward, check_projection, guard_records, log, ocfg_of, rec9,
-                      rel_check, run_gpu)
+from gpu_util import (cam32, check_forward, check_projection, guard_records, log, ocfg_of,
+                      rec9, rel_check, run_gpu)
 from paper_2606_11529_amd import renderer as R
 from synth import random_cameras, scene_clusters
 
@@ -112,7 +112,7 @@ def test_fullsize_backward_sampled_tiles():
     # untouched records receive exactly nothing
     assert np.all(g["grad2d"][~np.isin(np.arange(sc.n), touched)] == 0)
     idx = np.flatnonzero(keep & (g["tc"] > 0))
-    ref_p = oracle.project_bwd(sc.subset(idx), cam, oc, g["grad2d"][idx].astype(np.float64))
+    ref_p = oracle.project_bwd(sc.subset(idx), cam32(cam), oc, g["grad2d"][idx].astype(np.float64))
     worst = {}
     for k in ("means", "scales", "quats", "opacities", "sh"):
         gk = g["grads"][k][..., idx]

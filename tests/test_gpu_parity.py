@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import (check_binning, check_forward, check_projection, guard_records, log,
+from gpu_util import (cam32, check_binning, check_forward, check_projection, guard_records, log,
                       ocfg_of, rec9, rel_check, run_gpu)
 from paper_2606_11529_amd import renderer as R
 from synth import camera_config1, camera_look_at, random_cameras, scene_clusters, scene_config1
@@ -87,7 +87,7 @@ def test_backward(name):
     mask[excl] = False
     w2 = rel_check(g["grad2d"], g9, "grad2d", mask)
     # projection backward from the GPU's 2D gradients
-    ref_p = oracle.project_bwd(sc, cam, oc, g["grad2d"].astype(np.float64))
+    ref_p = oracle.project_bwd(sc, cam32(cam), oc, g["grad2d"].astype(np.float64))
     worst = {}
     for k in ("means", "scales", "quats", "opacities", "sh"):
         gk, rk = g["grads"][k], ref_p[k]
