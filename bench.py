@@ -100,6 +100,14 @@ def main():
     grads = [scene.zeros_like_grads()]
     ws = R.Workspace()
 
+    # A plain copy of known size (256 MiB read + 256 MiB written), so that
+    # hardware byte counters of a profiled run can be calibrated against it.
+    calib = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+    calib_dst = torch.empty_like(calib)
+    calib_dst.copy_(calib)
+    torch.cuda.synchronize()
+    del calib, calib_dst
+
     # Capacity for the pair list: one pass over the cameras, +10%.
     cap = 0
     for v in views:

@@ -23,8 +23,13 @@ def _state():
     if not _STATE:
         log("[full] generating 3M-Gaussian scene")
         sc = scene_clusters(3_000_000, seed=0)
-        cam = random_cameras(8, 0, (1600, 1064))[0]
-        cfg = R.Config()
+        cams = random_cameras(8, 0, (1600, 1064))
+        cam = cams[0]
+        # the launch configuration the bench times: knobs from the autotuner
+        from paper_2606_11529_amd.autotune import autotune
+        tuned = autotune(R.Scene.from_host(sc), cams[:2], R.Config(), tiles=(16,), reps=1)
+        cfg = tuned.apply(R.Config())
+        log(f"[full] tuned fwd {cfg.lds_batch}x{cfg.fwd_ppt} bwd {cfg.bwd_lds_batch}x{cfg.bwd_ppt}")
         H, W = cam.height, cam.width
         tx, ty = (W + 15) // 16, (H + 15) // 16
         g = run_gpu(sc, cam, cfg)
