@@ -337,7 +337,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
                                                        int nblocks) {
   constexpr int RADIX = 1 << BITS;
   __shared__ uint32_t wcnt[kSortWaves][RADIX];
-  __shared__ uint32_t dstart[RADIX];
+  __shared__ uint32_t gbase[RADIX];  // global offset of the digit's run minus its block start
   __shared__ uint32_t s_wave[4];
   __shared__ K skey[kSortTile];
   __shared__ uint32_t sval[kSortTile];
@@ -374,7 +374,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
   }
   const uint32_t start = block_excl_scan256(c0 + c1 + c2 + c3, s_wave, nullptr);
   if (t < RADIX) {
-    dstart[t] = start;
+    gbase[t] = offsets[(int64_t)t * nblocks + blockIdx.x] - start;
     wcnt[0][t] = start;
     wcnt[1][t] = start + c0;
     wcnt[2][t] = start + c0 + c1;
@@ -395,8 +395,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
   const int nvalid = rem <= 0 ? 0 : (rem < kSortTile ? (int)rem : kSortTile);
   for (int k = t; k < nvalid; k += 256) {
     const K kk = skey[k];
-    const uint32_t d = digit_of<BITS>(kk, shift);
-    const uint32_t g = offsets[(int64_t)d * nblocks + blockIdx.x] + (uint32_t)k - dstart[d];
+    const uint32_t g = gbase[digit_of<BITS>(kk, shift)] + (uint32_t)k;
     kout[g] = kk;
     vout[g] = sval[k];
   }
