@@ -32,10 +32,13 @@ def cam32(cam):
 
 
 def ocfg_of(cfg: R.Config) -> oracle.OracleConfig:
+    """The method constants exactly as the C-ABI receives them (float32)."""
+    f = lambda x: float(np.float32(x))
     return oracle.OracleConfig(tile_w=cfg.tile, tile_h=cfg.tile, sh_degree=cfg.sh_degree,
-                               lowpass=cfg.lowpass, alpha_min=cfg.alpha_min,
-                               alpha_max=cfg.alpha_max, t_min=cfg.t_min, z_near=cfg.z_near,
-                               fov_clip=cfg.fov_clip, bg=tuple(cfg.bg))
+                               lowpass=f(cfg.lowpass), alpha_min=f(cfg.alpha_min),
+                               alpha_max=f(cfg.alpha_max), t_min=f(cfg.t_min),
+                               z_near=f(cfg.z_near), fov_clip=f(cfg.fov_clip),
+                               bg=tuple(f(b) for b in cfg.bg))
 
 
 def run_gpu(sc, cams, cfg: R.Config, dimgs=None, want_keys=True, want_grad2d=True,
