@@ -213,10 +213,18 @@ def main():
     }
     dom = "render_bwd" if mean["render_bwd"] >= mean["render_fwd"] else "render_fwd"
     ops = OPS_BWD * evals_bwd if dom == "render_bwd" else OPS_FWD * evals_fwd
-    roof = {"kernel": "k_render_bwd" if dom == "render_bwd" else "k_render_fwd",
-            "bound": "alu", "achieved": stages[dom]["TOP/s"], "peak": VALU_PEAK_TOPS,
-            "unit": "TOP/s", "frac": stages[dom]["frac"], "traffic": None,
-            "ops_per_launch": ops, "launch_ms": mean[dom]}
+    if dom == "render_bwd":
+        kname = (f"xpr::k_render_bwd<{args.tile},{args.tile},"
+                 f"{cfg.bwd_lds_batch or cfg.lds_batch},{cfg.bwd_ppt},false>")
+    else:
+        kname = f"xpr::k_render_fwd<{args.tile},{args.tile},{cfg.lds_batch},{cfg.fwd_ppt},false>"
+    # HBM bytes per launch from the committed counter record, only while the
+    # kernel sources are the ones it was taken from
+    from paper_2606_11529_amd.profiling import traffic_of
+    traffic = traffic_of(os.path.join(ROOT, "profiles", "hbm_traffic_c3.txt"), kname)
+    roof = {"kernel": kname, "bound": "alu", "achieved": stages[dom]["TOP/s"],
+            "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": stages[dom]["frac"],
+            "traffic": traffic, "ops_per_launch": ops, "launch_ms": mean[dom]}
 
     out = {
         "metric": METRIC, "value": round(ms_wall, 4), "unit": "ms/frame", "n_gpus": 1,

@@ -17,22 +17,37 @@
 
 namespace xpr {
 
-// The evaluate of the listing: power P = A dx^2 + B dx dy + C dy^2 and
-// alpha = min(alpha_max, o e^P). Written with explicit roundings so the
-// forward and backward kernels take bit-identical decisions.
-struct Eval {
-  float dy, P, eP, raw, alpha;
-};
+// Records are staged in LDS with the conic scaled by log2(e), so the power
+// comes out in base-2 units and alpha = min(alpha_max, o 2^P2) needs no
+// extra multiply, and with a per-record power threshold
+//   thr = log2(alpha_min / o) - 2^-10,
+// below which o 2^P2 < alpha_min holds with a wide margin over the rounding
+// of exp2 and of the product: such pairs are skipped before exp2 is taken
+// (whole waves skip it when all their lanes are below). Every pair at or
+// above thr takes the exact test, so the accept decisions are the ones the
+// plain alpha < alpha_min gate takes on the same P2. Staged layout:
+//   s0 = (u, v, A', B'), s1 = (C', thr, o, red), s2 = (green, blue).
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+constexpr float kThrMargin = 1.0f / 1024.0f;
 
-__device__ __forceinline__ Eval evaluate(float dx, float py, float4 a, float4 b, float alpha_max) {
-  Eval e;
-  e.dy = __fsub_rn(py, a.y);
-  e.P = __fmaf_rn(a.z, __fmul_rn(dx, dx),
-                  __fmaf_rn(a.w, __fmul_rn(dx, e.dy), __fmul_rn(b.x, __fmul_rn(e.dy, e.dy))));
-  e.eP = __expf(e.P);
-  e.raw = __fmul_rn(b.y, e.eP);
-  e.alpha = fminf(alpha_max, e.raw);
-  return e;
+__device__ __forceinline__ void stage_record(const float4* __restrict__ splat, size_t r,
+                                             float alpha_min, float4& o0, float4& o1,
+                                             float2& o2) {
+  const float4 p0 = splat[3 * r];
+  const float4 p1 = splat[3 * r + 1];
+  const float p2 = splat[3 * r + 2].x;
+  o0 = make_float4(p0.x, p0.y, p0.z * kLog2e, p0.w * kLog2e);
+  o1 = make_float4(p1.x * kLog2e, __log2f(alpha_min / p1.y) - kThrMargin, p1.y, p1.z);
+  o2 = make_float2(p1.w, p2);
+}
+
+// The evaluate of the listing on the staged record: power P2 = A' dx^2 +
+// B' dx dy + C' dy^2 (base 2), written with explicit roundings so the
+// forward and backward kernels take bit-identical decisions.
+__device__ __forceinline__ float power2(float dx, float dy, float4 a, float c) {
+  return __fmaf_rn(a.z, __fmul_rn(dx, dx),
+                   __fmaf_rn(a.w, __fmul_rn(dx, dy), __fmul_rn(c, __fmul_rn(dy, dy))));
 }
 
 template <int TW, int TH, int BATCH, int PPT>
@@ -42,7 +57,7 @@ __device__ __forceinline__ void fwd_tile(const Batch& B, int g, const float4* __
                                          float* __restrict__ image, float* __restrict__ Tfin,
                                          int32_t* __restrict__ ncon,
                                          int32_t* __restrict__ tile_work, float4* s0, float4* s1,
-                                         float* s2) {
+                                         float2* s2) {
   constexpr int NT = TW * TH / PPT;
   const ViewDev& V = B.v[view_of_tile(B, g)];
   const int lt = g - V.tile_off;
@@ -70,12 +85,7 @@ __device__ __forceinline__ void fwd_tile(const Batch& B, int g, const float4* __
     walked = min(BATCH, rg.y - base) + (base - rg.x);
     for (int k = threadIdx.x; k < BATCH; k += NT) {
       const int idx = base + k;
-      if (idx < rg.y) {
-        const size_t r = (size_t)vals[idx];
-        s0[k] = splat[3 * r];
-        s1[k] = splat[3 * r + 1];
-        s2[k] = splat[3 * r + 2].x;
-      }
+      if (idx < rg.y) stage_record(splat, (size_t)vals[idx], amin, s0[k], s1[k], s2[k]);
     }
     __syncthreads();
     const int nb = min(BATCH, rg.y - base);
@@ -86,18 +96,21 @@ __device__ __forceinline__ void fwd_tile(const Batch& B, int g, const float4* __
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
         if (done[j]) continue;
-        const Eval e = evaluate(dx, (float)(py0 + j), a, b, amax);
-        if (e.P > 0.f || e.alpha < amin) continue;
-        const float Tn = T[j] * (1.f - e.alpha);
+        const float P2 = power2(dx, __fsub_rn((float)(py0 + j), a.y), a, b.x);
+        if (P2 < b.y) continue;
+        const float alpha = fminf(amax, __fmul_rn(b.z, __builtin_amdgcn_exp2f(P2)));
+        if (P2 > 0.f || alpha < amin) continue;
+        const float Tn = T[j] * (1.f - alpha);
         if (Tn < tmin) {
           done[j] = true;
           ++ndone;
           continue;
         }
-        const float w = e.alpha * T[j];
-        C0[j] += b.z * w;
-        C1[j] += b.w * w;
-        C2[j] += s2[k] * w;
+        const float w = alpha * T[j];
+        const float2 gb = s2[k];
+        C0[j] += b.w * w;
+        C1[j] += gb.x * w;
+        C2[j] += gb.y * w;
         T[j] = Tn;
         last[j] = base + k - rg.x + 1;
       }
@@ -138,7 +151,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_render_fwd(
     int32_t* qhead) {
   __shared__ float4 s0[BATCH];
   __shared__ float4 s1[BATCH];
-  __shared__ float s2[BATCH];
+  __shared__ float2 s2[BATCH];
   if (!PERSIST) {
     const int g = order ? order[blockIdx.x] : (int)blockIdx.x;
     fwd_tile<TW, TH, BATCH, PPT>(B, g, splat, vals, ranges, image, Tfin, ncon, tile_work, s0, s1,
@@ -170,7 +183,7 @@ __device__ __forceinline__ void bwd_tile(const Batch& B, int g, const float4* __
                                          const float* __restrict__ Tfin,
                                          const int32_t* __restrict__ ncon,
                                          float* __restrict__ grad2d, float4* s0, float4* s1,
-                                         float* s2, int32_t* srec, int32_t* s_maxlast_p) {
+                                         float2* s2, int32_t* srec, int32_t* s_maxlast_p) {
   constexpr int NT = TW * TH / PPT;
   int32_t& s_maxlast = *s_maxlast_p;
   const ViewDev& V = B.v[view_of_tile(B, g)];
@@ -217,9 +230,7 @@ __device__ __forceinline__ void bwd_tile(const Batch& B, int g, const float4* __
     for (int k = threadIdx.x; k < hi - lo; k += NT) {
       const int r = vals[lo + k];
       srec[k] = r;
-      s0[k] = splat[3 * (size_t)r];
-      s1[k] = splat[3 * (size_t)r + 1];
-      s2[k] = splat[3 * (size_t)r + 2].x;
+      stage_record(splat, (size_t)r, amin, s0[k], s1[k], s2[k]);
     }
     __syncthreads();
     for (int k = hi - lo - 1; k >= 0; --k) {
@@ -227,36 +238,44 @@ __device__ __forceinline__ void bwd_tile(const Batch& B, int g, const float4* __
       if (__ballot(pos <= mylast) == 0) continue;
       const float4 a = s0[k];
       const float4 b = s1[k];
-      const float c2 = s2[k];
+      const float2 c = s2[k];
+      const float cr = b.w, cg = c.x, cb = c.y;
       const float dx = __fsub_rn(fpx, a.x);
       float gu = 0.f, gv = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, go = 0.f;
       float gr = 0.f, gg = 0.f, gb = 0.f;
       bool any = false;
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
-        const Eval e = evaluate(dx, (float)(py0 + j), a, b, amax);
-        const bool use = pos <= last[j] && !(e.P > 0.f) && !(e.alpha < amin);
-        if (!use) continue;
+        if (pos > last[j]) continue;
+        const float dy = __fsub_rn((float)(py0 + j), a.y);
+        const float P2 = power2(dx, dy, a, b.x);
+        if (P2 < b.y) continue;
+        const float eP = __builtin_amdgcn_exp2f(P2);
+        const float raw = __fmul_rn(b.z, eP);
+        const float alpha = fminf(amax, raw);
+        if (P2 > 0.f || alpha < amin) continue;
         any = true;
-        const float inv = __builtin_amdgcn_rcpf(1.f - e.alpha);
+        const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
         T[j] = T[j] * inv;
-        const float w = e.alpha * T[j];
+        const float w = alpha * T[j];
         gr += w * G0[j];
         gg += w * G1[j];
         gb += w * G2[j];
-        const float da = T[j] * ((b.z - S0[j]) * G0[j] + (b.w - S1[j]) * G1[j] +
-                                 (c2 - S2[j]) * G2[j]) - Tf[j] * bgG[j] * inv;
-        S0[j] = e.alpha * b.z + (1.f - e.alpha) * S0[j];
-        S1[j] = e.alpha * b.w + (1.f - e.alpha) * S1[j];
-        S2[j] = e.alpha * c2 + (1.f - e.alpha) * S2[j];
-        if (e.raw <= amax) {
-          const float dP = e.alpha * da;
-          go += e.eP * da;
-          gu -= dP * (2.f * a.z * dx + a.w * e.dy);
-          gv -= dP * (2.f * b.x * e.dy + a.w * dx);
+        const float da = T[j] * ((cr - S0[j]) * G0[j] + (cg - S1[j]) * G1[j] +
+                                 (cb - S2[j]) * G2[j]) - Tf[j] * bgG[j] * inv;
+        S0[j] = alpha * cr + (1.f - alpha) * S0[j];
+        S1[j] = alpha * cg + (1.f - alpha) * S1[j];
+        S2[j] = alpha * cb + (1.f - alpha) * S2[j];
+        if (raw <= amax) {
+          // dL/dP in natural-log units; the staged conic carries log2(e)
+          const float dP = alpha * da;
+          const float dPn = dP * kLn2;
+          go += eP * da;
+          gu -= dPn * (2.f * a.z * dx + a.w * dy);
+          gv -= dPn * (2.f * b.x * dy + a.w * dx);
           gA += dP * dx * dx;
-          gB += dP * dx * e.dy;
-          gC += dP * e.dy * e.dy;
+          gB += dP * dx * dy;
+          gC += dP * dy * dy;
         }
       }
       if (__ballot(any) == 0) continue;
@@ -293,7 +312,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_render_bwd(
     float* __restrict__ grad2d, const int32_t* order, int32_t* qhead) {
   __shared__ float4 s0[BATCH];
   __shared__ float4 s1[BATCH];
-  __shared__ float s2[BATCH];
+  __shared__ float2 s2[BATCH];
   __shared__ int32_t srec[BATCH];
   __shared__ int32_t s_maxlast;
   if (!PERSIST) {

@@ -48,6 +48,24 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t* s_w
   return off + inc - x;
 }
 
+// Exclusive running maximum of one value per thread over a 256-thread block.
+__device__ __forceinline__ uint32_t block_excl_max256(uint32_t x, uint32_t* s_wave) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t inc = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(inc, d, 64);
+    if (lane >= d) inc = max(inc, y);
+  }
+  uint32_t ex = __shfl_up(inc, 1, 64);
+  if (lane == 0) ex = 0;
+  if (lane == 63) s_wave[w] = inc;
+  __syncthreads();
+  for (int k = 0; k < w; ++k) ex = max(ex, s_wave[k]);
+  __syncthreads();
+  return ex;
+}
+
 __device__ __forceinline__ uint64_t block_sum256_u64(uint64_t x, uint64_t* s_wave) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
@@ -70,13 +88,6 @@ struct LoadArray {
 struct LoadCount {  // tile counts of records, in record order
   const int32_t* tc;
   __device__ __forceinline__ uint32_t operator()(int64_t i) const { return (uint32_t)tc[i]; }
-};
-struct LoadCountPerm {  // tile counts of records, in depth order
-  const int32_t* tc;
-  const uint32_t* perm;
-  __device__ __forceinline__ uint32_t operator()(int64_t i) const {
-    return (uint32_t)tc[perm[i]];
-  }
 };
 
 template <class L>
@@ -222,8 +233,12 @@ __global__ __launch_bounds__(256) void k_duplicate(Batch B, const short4* __rest
   __shared__ int32_t s_tx[256];
   __shared__ uint32_t s_depth[256];
   const int t = threadIdx.x;
-  const int64_t i = (int64_t)blockIdx.x * 256 + t;
-  const int64_t last = min(n_rec, (int64_t)blockIdx.x * 256 + 256) - 1;
+  // no XCD swizzle here: blocks hold very different pair counts (the front
+  // of the depth order has the largest footprints), and round-robin
+  // dispatch spreads them evenly over the XCDs
+  const int blk = blockIdx.x;
+  const int64_t i = (int64_t)blk * 256 + t;
+  const int64_t last = min(n_rec, (int64_t)blk * 256 + 256) - 1;
   if (i <= last) {
     const uint32_t r = PERM ? perm[i] : (uint32_t)i;
     int v = 0;
@@ -238,7 +253,7 @@ __global__ __launch_bounds__(256) void k_duplicate(Batch B, const short4* __rest
     if (i == last) s_off[256] = offsets[i] + (uint32_t)tc[r];
   }
   __syncthreads();
-  const int nvalid = (int)(last - (int64_t)blockIdx.x * 256 + 1);
+  const int nvalid = (int)(last - (int64_t)blk * 256 + 1);
   if (t >= nvalid) s_off[t] = s_off[256];
   __syncthreads();
   const uint32_t beg = s_off[0], end = s_off[256];
@@ -306,7 +321,8 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys,
   for (int k = t; k < COPIES * RADIX; k += 256) (&h[0][0])[k] = 0;
   __syncthreads();
   const int64_t n = clamp_n(n_dev, cap);
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const int part = xcd_swizzle(blockIdx.x, nblocks);
+  const int64_t base = (int64_t)part * kSortTile;
   uint32_t* mine = h[t & (COPIES - 1)];
 #pragma unroll 4
   for (int j = 0; j < kSortItems; ++j) {
@@ -318,7 +334,37 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys,
     uint32_t c = 0;
 #pragma unroll
     for (int k = 0; k < COPIES; ++k) c += h[k][t];
-    counts[(int64_t)t * nblocks + blockIdx.x] = c;
+    counts[(int64_t)t * nblocks + part] = c;
+  }
+}
+
+// Writes a block's keys, ranked into digit order in LDS, to their global
+// runs. With RANGES (the last pass over tile keys) the output is the final
+// order, so a tile's pairs form one contiguous span across all blocks: each
+// block records where the tiles it holds begin and end inside it, and the
+// minimum start / maximum end over blocks are the tile ranges. Keys are only
+// stored when kout is given. With aux_dst, aux_dst[g] = aux_src[value] is
+// stored beside each value (a per-record quantity carried into sorted
+// order).
+template <int BITS, typename KS, typename KO, bool RANGES>
+__device__ __forceinline__ void write_sorted(const KS* skey, const uint32_t* sval,
+                                             const uint32_t* gbase, int nvalid, int shift,
+                                             KO* __restrict__ kout, uint32_t* __restrict__ vout,
+                                             int2* __restrict__ ranges,
+                                             const int32_t* __restrict__ aux_src,
+                                             uint32_t* __restrict__ aux_dst) {
+  for (int k = threadIdx.x; k < nvalid; k += 256) {
+    const KS kk = skey[k];
+    const uint32_t g = gbase[digit_of<BITS>(kk, shift)] + (uint32_t)k;
+    if (!RANGES || kout) kout[g] = (KO)kk;
+    const uint32_t v = sval[k];
+    vout[g] = v;
+    if (aux_dst) aux_dst[g] = (uint32_t)aux_src[v];
+    if (RANGES) {
+      const uint32_t tile = (uint32_t)kk;
+      if (k == 0 || (uint32_t)skey[k - 1] != tile) atomicMin(&ranges[tile].x, (int)g);
+      if (k == nvalid - 1 || (uint32_t)skey[k + 1] != tile) atomicMax(&ranges[tile].y, (int)g + 1);
+    }
   }
 }
 
@@ -326,7 +372,7 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys,
 // wave, slot by slot, the wave64 ballot match gives the rank among lanes
 // with the same digit), then write them out in digit order so each digit's
 // run is a contiguous global store.
-template <int BITS, typename K>
+template <int BITS, typename K, bool RANGES>
 __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin,
                                                        const uint32_t* __restrict__ vin,
                                                        K* __restrict__ kout,
@@ -334,7 +380,9 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
                                                        const int64_t* n_dev, int64_t cap,
                                                        int shift,
                                                        const uint32_t* __restrict__ offsets,
-                                                       int nblocks) {
+                                                       int nblocks, int2* __restrict__ ranges,
+                                                       const int32_t* __restrict__ aux_src,
+                                                       uint32_t* __restrict__ aux_dst) {
   constexpr int RADIX = 1 << BITS;
   __shared__ uint32_t wcnt[kSortWaves][RADIX];
   __shared__ uint32_t gbase[RADIX];  // global offset of the digit's run minus its block start
@@ -345,7 +393,8 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
   for (int k = t; k < kSortWaves * RADIX; k += 256) (&wcnt[0][0])[k] = 0;
   __syncthreads();
   const int64_t n = clamp_n(n_dev, cap);
-  const int64_t bbase = (int64_t)blockIdx.x * kSortTile;
+  const int part = xcd_swizzle(blockIdx.x, nblocks);
+  const int64_t bbase = (int64_t)part * kSortTile;
   const int64_t base = bbase + w * (64 * kSortItems);
   const uint64_t lt = lanemask_lt();
   K key[kSortItems];
@@ -374,7 +423,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
   }
   const uint32_t start = block_excl_scan256(c0 + c1 + c2 + c3, s_wave, nullptr);
   if (t < RADIX) {
-    gbase[t] = offsets[(int64_t)t * nblocks + blockIdx.x] - start;
+    gbase[t] = offsets[(int64_t)t * nblocks + part] - start;
     wcnt[0][t] = start;
     wcnt[1][t] = start + c0;
     wcnt[2][t] = start + c0 + c1;
@@ -393,12 +442,270 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
   __syncthreads();
   const int64_t rem = n - bbase;
   const int nvalid = rem <= 0 ? 0 : (rem < kSortTile ? (int)rem : kSortTile);
-  for (int k = t; k < nvalid; k += 256) {
-    const K kk = skey[k];
-    const uint32_t g = gbase[digit_of<BITS>(kk, shift)] + (uint32_t)k;
-    kout[g] = kk;
-    vout[g] = sval[k];
+  write_sorted<BITS, K, K, RANGES>(skey, sval, gbase, nvalid, shift, kout, vout, ranges, aux_src,
+                                   aux_dst);
+}
+
+// ---------------------------------------------------------------------------
+// Replication fused into the first pass of the tile sort (depth-presort
+// path). The pairs are never stored unsorted: the first pass's histogram and
+// scatter each regenerate the pairs of their sort block from the records.
+// Sort block b owns pairs [b T, b T + T) of the depth-ordered pair sequence
+// (T = kSortTile); first[b] is the record (depth-order position) holding its
+// first pair, and first[b + 1] the one holding the pair after its last, so
+// records first[b] .. first[b + 1] hold all of its pairs.
+
+// One pass over the records in depth order: the packed record each sort
+// block reads contiguously (pair offset, record id, tile id of the rect's
+// top-left corner, rect width | tiles_x << 16), and first[b] for every block
+// b with b T < n, plus first[ceil(n / T)] = the record holding pair n - 1,
+// where n = min(I, capacity).
+__global__ void k_pair_records(Batch B, const short4* __restrict__ rect,
+                               const uint32_t* __restrict__ tc_sorted,
+                               const uint32_t* __restrict__ perm,
+                               const uint32_t* __restrict__ offsets, int64_t n_rec,
+                               const int64_t* n_isect, int64_t cap, uint4* __restrict__ packed,
+                               uint32_t* __restrict__ first) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_rec) return;
+  const int64_t n = clamp_n(n_isect, cap);
+  const int64_t o = offsets[j];
+  const int64_t e = min(o + (int64_t)tc_sorted[j], n);
+  if (e <= o) return;
+  const uint32_t r = perm[j];
+  int v = 0;
+  for (int q = 1; q < B.n_views; ++q)
+    if ((int32_t)r >= B.v[q].rec_off) v = q;
+  const short4 rc = rect[r];
+  const uint32_t tx = (uint32_t)B.v[v].tiles_x;
+  packed[j] = make_uint4((uint32_t)o, r,
+                         (uint32_t)B.v[v].tile_off + (uint32_t)rc.y * tx + (uint32_t)rc.x,
+                         (uint32_t)(rc.z - rc.x) | (tx << 16));
+  for (int64_t b = (o + kSortTile - 1) / kSortTile; b * kSortTile < e; ++b) first[b] = (uint32_t)j;
+  if (e == n) first[(n + kSortTile - 1) / kSortTile] = (uint32_t)j;
+}
+
+// Up to 256 packed records of a sort block, staged in LDS.
+struct RecChunk {
+  uint32_t off[257];
+  uint32_t rec[256];
+  uint32_t base[256];
+  uint32_t wtx[256];
+};
+
+// LDS position of slot s in the pair staging arrays: one pad word per 16
+// slots, so a thread owning 16 consecutive slots and its neighbours hit
+// distinct banks.
+__device__ __forceinline__ int spad(int s) { return s + (s >> 4); }
+constexpr int kSortTilePad = kSortTile + kSortTile / 16;
+
+// Calls emit(slot, tile, record) once for every pair of sort block `part`
+// (slot = pair index - part T; pairs at or beyond n are skipped). Tiles of a
+// record are its rect in row-major order. Must be called by all threads of
+// the block. `marks` is LDS scratch of kSortTilePad words.
+//
+// Common case (at most 256 records in the block): each record marks the
+// slot of its first pair, and a block-wide running maximum over the slots
+// gives every slot its record; thread t then handles slots 16t .. 16t + 15,
+// stepping through its record's rect and dividing only when the record
+// changes. Otherwise the records go through LDS 256 at a time and each pair
+// finds its record by binary search.
+template <class Emit>
+__device__ __forceinline__ void gen_block_pairs(const uint4* __restrict__ packed,
+                                                const uint32_t* __restrict__ first, int part,
+                                                int64_t n, RecChunk& S, uint32_t* marks,
+                                                uint32_t* s_wave, Emit emit) {
+  const int t = threadIdx.x;
+  const uint32_t lo = (uint32_t)part * kSortTile;
+  const uint32_t hi = (uint32_t)min(n, (int64_t)lo + kSortTile);
+  const int nslots = (int)(hi - lo);
+  const uint32_t j0 = first[part], j1 = first[part + 1];
+  auto load_record = [&](uint32_t jj, int k) {
+    const uint4 q = packed[jj];
+    S.off[k] = q.x;
+    S.rec[k] = q.y;
+    S.base[k] = q.z;
+    S.wtx[k] = q.w;
+  };
+  auto tile_of_pair = [&](int k, uint32_t yy, uint32_t xx) -> uint32_t {
+    return S.base[k] + yy * (S.wtx[k] >> 16) + xx;
+  };
+  const uint32_t nrec = j1 - j0 + 1;
+  if (nrec <= 256) {
+    if ((uint32_t)t < nrec) load_record(j0 + t, t);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) marks[spad(16 * t + i)] = 0u;
+    __syncthreads();
+    if ((uint32_t)t < nrec) {
+      const uint32_t o = S.off[t];
+      const uint32_t s0 = (o > lo ? o : lo) - lo;
+      if (s0 < (uint32_t)nslots) marks[spad((int)s0)] = (uint32_t)t + 1u;
+    }
+    __syncthreads();
+    uint32_t m[16];
+    uint32_t run = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      run = max(run, marks[spad(16 * t + i)]);
+      m[i] = run;
+    }
+    const uint32_t pre = block_excl_max256(run, s_wave);
+    int kprev = -1;
+    uint32_t w = 1, xx = 0, yy = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int s = 16 * t + i;
+      if (s < nslots) {
+        const int k = (int)max(pre, m[i]) - 1;
+        if (k != kprev) {
+          w = S.wtx[k] & 0xffffu;
+          const uint32_t local = lo + (uint32_t)s - S.off[k];
+          yy = local / w;
+          xx = local - yy * w;
+          kprev = k;
+        } else if (++xx == w) {
+          xx = 0;
+          ++yy;
+        }
+        emit(s, tile_of_pair(k, yy, xx), S.rec[k]);
+      }
+    }
+    return;
   }
+  for (uint32_t c0 = j0; c0 <= j1; c0 += 256) {
+    const uint32_t clast = min(j1, c0 + 255u);
+    __syncthreads();  // the previous chunk is consumed
+    const uint32_t jj = c0 + t;
+    if (jj <= clast) load_record(jj, t);
+    // pairs of this chunk end where the next chunk's first record starts
+    // (the block's end for the last chunk)
+    if (t == 0) S.off[256] = clast < j1 ? packed[clast + 1].x : hi;
+    __syncthreads();
+    if (t > (int)(clast - c0)) S.off[t] = S.off[256];
+    __syncthreads();
+    const uint32_t beg = max(S.off[0], lo), end = min(S.off[256], hi);
+    for (uint32_t p = beg + t; p < end; p += 256) {
+      // last k with off[k] <= p
+      int a = 0, z = 255;
+      while (a < z) {
+        const int mid = (a + z + 1) >> 1;
+        if (S.off[mid] <= p) a = mid; else z = mid - 1;
+      }
+      const uint32_t local = p - S.off[a];
+      const uint32_t w = S.wtx[a] & 0xffffu;
+      const uint32_t yy = local / w;
+      emit((int)(p - lo), tile_of_pair(a, yy, local - yy * w), S.rec[a]);
+    }
+  }
+}
+
+// First-pass histogram (digit = low BITS bits of the tile id) of each sort
+// block, from regenerated pairs; counts digit-major like k_radix_hist.
+template <int BITS>
+__global__ __launch_bounds__(256) void k_pair_hist(const uint4* __restrict__ packed,
+                                                   const uint32_t* __restrict__ first,
+                                                   const int64_t* n_isect, int64_t cap,
+                                                   uint32_t* __restrict__ counts, int nblocks) {
+  constexpr int RADIX = 1 << BITS;
+  constexpr int COPIES = 8;
+  __shared__ RecChunk S;
+  __shared__ uint32_t marks[kSortTilePad];
+  __shared__ uint32_t s_wave[4];
+  __shared__ uint32_t h[COPIES][RADIX];
+  const int t = threadIdx.x;
+  for (int k = t; k < COPIES * RADIX; k += 256) (&h[0][0])[k] = 0;
+  const int64_t n = clamp_n(n_isect, cap);
+  const int part = xcd_swizzle(blockIdx.x, nblocks);
+  uint32_t* mine = h[t & (COPIES - 1)];
+  if ((int64_t)part * kSortTile < n)
+    gen_block_pairs(packed, first, part, n, S, marks, s_wave,
+                    [&](int, uint32_t tile, uint32_t) {
+                      atomicAdd(&mine[tile & (RADIX - 1)], 1u);
+                    });
+  __syncthreads();
+  if (t < RADIX) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < COPIES; ++k) c += h[k][t];
+    counts[(int64_t)t * nblocks + part] = c;
+  }
+}
+
+// First-pass scatter from regenerated pairs: the block's pairs are laid out
+// in LDS in pair order, then ranked and written exactly like k_radix_scatter
+// (digit = low BITS bits). With RANGES this is also the last pass.
+template <int BITS, bool RANGES, typename KO>
+__global__ __launch_bounds__(256) void k_pair_scatter(
+    const uint4* __restrict__ packed, const uint32_t* __restrict__ first, const int64_t* n_isect,
+    int64_t cap, const uint32_t* __restrict__ doff, int nblocks, KO* __restrict__ kout,
+    uint32_t* __restrict__ vout, int2* __restrict__ ranges) {
+  constexpr int RADIX = 1 << BITS;
+  __shared__ RecChunk S;
+  __shared__ uint32_t wcnt[kSortWaves][RADIX];
+  __shared__ uint32_t gbase[RADIX];
+  __shared__ uint32_t s_wave[4];
+  // pairs in slot order at spad(slot) (sval doubles as the generator's
+  // marks), then the ranked block in plain order
+  __shared__ uint32_t skey[kSortTilePad];
+  __shared__ uint32_t sval[kSortTilePad];
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int64_t n = clamp_n(n_isect, cap);
+  const int part = xcd_swizzle(blockIdx.x, nblocks);
+  const int64_t bbase = (int64_t)part * kSortTile;
+  if (bbase >= n) return;  // whole block beyond the list: no counts, nothing to write
+  const int nvalid = (int)min((int64_t)kSortTile, n - bbase);
+  for (int k = t; k < kSortWaves * RADIX; k += 256) (&wcnt[0][0])[k] = 0;
+  // the block's digit offsets do not depend on the pairs: fetch them early
+  const uint32_t my_off = t < RADIX ? doff[(int64_t)t * nblocks + part] : 0u;
+  gen_block_pairs(packed, first, part, n, S, sval, s_wave,
+                  [&](int slot, uint32_t tile, uint32_t rec) {
+                    skey[spad(slot)] = tile;
+                    sval[spad(slot)] = rec;
+                  });
+  __syncthreads();
+  const uint64_t lt = lanemask_lt();
+  uint32_t key[kSortItems], val[kSortItems], lofs[kSortItems];
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int slot = w * (64 * kSortItems) + j * 64 + lane;
+    const bool ok = slot < nvalid;
+    key[j] = ok ? skey[spad(slot)] : 0u;
+    val[j] = ok ? sval[spad(slot)] : 0u;
+    const uint32_t d = key[j] & (RADIX - 1);
+    const uint64_t m = match_digit<BITS>(d, ok);
+    const uint32_t before = wcnt[w][d];
+    lofs[j] = before + (uint32_t)__popcll(m & lt);
+    if (ok && (m & lt) == 0) wcnt[w][d] = before + (uint32_t)__popcll(m);
+  }
+  __syncthreads();
+  uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+  if (t < RADIX) {
+    c0 = wcnt[0][t];
+    c1 = wcnt[1][t];
+    c2 = wcnt[2][t];
+    c3 = wcnt[3][t];
+  }
+  const uint32_t start = block_excl_scan256(c0 + c1 + c2 + c3, s_wave, nullptr);
+  if (t < RADIX) {
+    gbase[t] = my_off - start;
+    wcnt[0][t] = start;
+    wcnt[1][t] = start + c0;
+    wcnt[2][t] = start + c0 + c1;
+    wcnt[3][t] = start + c0 + c1 + c2;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int slot = w * (64 * kSortItems) + j * 64 + lane;
+    if (slot < nvalid) {
+      const uint32_t pos = wcnt[w][key[j] & (RADIX - 1)] + lofs[j];
+      skey[pos] = key[j];
+      sval[pos] = val[j];
+    }
+  }
+  __syncthreads();
+  write_sorted<BITS, uint32_t, KO, RANGES>(skey, sval, gbase, nvalid, 0, kout, vout, ranges,
+                                           nullptr, nullptr);
 }
 
 // Digit width for sorting `bits` bits: 7 when that needs no more passes than
@@ -414,32 +721,48 @@ static inline int radix_passes(int bits) {
 template <int BITS, typename K>
 static hipError_t radix_pass(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const int64_t* n_dev,
                              int64_t cap, int nb, int shift, uint32_t* counts,
-                             uint64_t* partials, hipStream_t st) {
+                             uint64_t* partials, int2* ranges, const int32_t* aux_src,
+                             uint32_t* aux_dst, hipStream_t st) {
   hipLaunchKernelGGL((k_radix_hist<BITS, K>), dim3(nb), dim3(256), 0, st, k0, n_dev, cap, shift,
                      counts, nb);
   hipError_t e = device_scan(LoadArray{counts}, (int64_t)nb << BITS, counts, partials, nullptr, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_radix_scatter<BITS, K>), dim3(nb), dim3(256), 0, st, k0, v0, k1, v1, n_dev,
-                     cap, shift, counts, nb);
+  if (ranges)
+    hipLaunchKernelGGL((k_radix_scatter<BITS, K, true>), dim3(nb), dim3(256), 0, st, k0, v0, k1,
+                       v1, n_dev, cap, shift, counts, nb, ranges, aux_src, aux_dst);
+  else
+    hipLaunchKernelGGL((k_radix_scatter<BITS, K, false>), dim3(nb), dim3(256), 0, st, k0, v0, k1,
+                       v1, n_dev, cap, shift, counts, nb, (int2*)nullptr, aux_src, aux_dst);
   return hipGetLastError();
 }
 
 // Sorts (keys, vals) of length n_dev (<= cap) on bits [0, bits). The data
 // starts in (k0, v0) and ping-pongs with (k1, v1); returns via *k_out/*v_out
-// where it ended. grid_n bounds the number of keys (host known).
+// where it ended. grid_n bounds the number of keys (host known). The last
+// pass can build tile ranges and carry aux_src[value] into aux_dst.
 template <typename K>
 static hipError_t radix_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const int64_t* n_dev,
                              int64_t cap, int64_t grid_n, int bits, uint32_t* counts,
-                             uint64_t* partials, K** k_out, uint32_t** v_out, hipStream_t st) {
+                             uint64_t* partials, K** k_out, uint32_t** v_out, hipStream_t st,
+                             int first_shift = 0, int2* ranges = nullptr,
+                             bool keys_last = true, const int32_t* aux_src = nullptr,
+                             uint32_t* aux_dst = nullptr) {
   *k_out = k0;
   *v_out = v0;
   if (grid_n <= 0) return hipSuccess;
   const int nb = (int)((grid_n + kSortTile - 1) / kSortTile);
   const int dbits = radix_digit_bits(bits);
-  for (int shift = 0; shift < bits; shift += dbits) {
+  for (int shift = first_shift; shift < bits; shift += dbits) {
+    const bool last = shift + dbits >= bits;
+    int2* rg = last ? ranges : nullptr;
+    K* kdst = (last && !keys_last && ranges) ? nullptr : k1;
+    const int32_t* as = last ? aux_src : nullptr;
+    uint32_t* ad = last ? aux_dst : nullptr;
     hipError_t e = dbits == 7
-                       ? radix_pass<7, K>(k0, v0, k1, v1, n_dev, cap, nb, shift, counts, partials, st)
-                       : radix_pass<8, K>(k0, v0, k1, v1, n_dev, cap, nb, shift, counts, partials, st);
+                       ? radix_pass<7, K>(k0, v0, kdst, v1, n_dev, cap, nb, shift, counts, partials,
+                                          rg, as, ad, st)
+                       : radix_pass<8, K>(k0, v0, kdst, v1, n_dev, cap, nb, shift, counts, partials,
+                                          rg, as, ad, st);
     if (e != hipSuccess) return e;
     K* tk = k0; k0 = k1; k1 = tk;
     uint32_t* tv = v0; v0 = v1; v1 = tv;
@@ -480,8 +803,21 @@ __global__ void k_ranges(const K* __restrict__ keys, const int64_t* n_dev, int64
   }
 }
 
+// Ranges built by atomic min/max: start from (INT_MAX, 0), and give tiles
+// that received no pair the empty range (0, 0).
+__global__ void k_ranges_init(int2* ranges, int tiles) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < tiles) ranges[t] = make_int2(0x7fffffff, 0);
+}
+
+__global__ void k_ranges_fix(int2* ranges, int tiles) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < tiles && ranges[t].x == 0x7fffffff) ranges[t] = make_int2(0, 0);
+}
+
 // 64-bit output keys of the presort path: tile << 32 | depth bits.
-__global__ void k_make_keys64(const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ vals,
+template <typename KT>
+__global__ void k_make_keys64(const KT* __restrict__ tiles, const uint32_t* __restrict__ vals,
                               const float* __restrict__ depth, const int64_t* n_dev, int64_t cap,
                               uint64_t* __restrict__ keys) {
   const int64_t n = clamp_n(n_dev, cap);
@@ -519,6 +855,9 @@ struct BinWs {
   uint32_t* dkey[2];   // [n_rec]   (presort)
   uint32_t* perm[2];   // [n_rec]   (presort)
   uint32_t* tkey[2];   // [cap]     (presort)
+  uint32_t* first;     // [cap / kSortTile + 2]  (presort)
+  uint4* packed;       // [n_rec]   (presort)
+  uint32_t* tcs;       // [n_rec]   tile counts in depth order (presort)
   uint64_t* key64[2];  // [cap]     (full)
   size_t bytes;
 };
@@ -545,6 +884,9 @@ static BinWs bin_ws_layout(int64_t n_rec, int64_t cap, int64_t tiles, int sort_m
     for (int k = 0; k < 2; ++k) L.dkey[k] = (uint32_t*)take(4 * (size_t)std::max<int64_t>(n_rec, 1));
     for (int k = 0; k < 2; ++k) L.perm[k] = (uint32_t*)take(4 * (size_t)std::max<int64_t>(n_rec, 1));
     for (int k = 0; k < 2; ++k) L.tkey[k] = (uint32_t*)take(4 * (size_t)std::max<int64_t>(cap, 1));
+    L.first = (uint32_t*)take(4 * (size_t)(cap / kSortTile + 2));
+    L.packed = (uint4*)take(16 * (size_t)std::max<int64_t>(n_rec, 1));
+    L.tcs = (uint32_t*)take(4 * (size_t)std::max<int64_t>(n_rec, 1));
   } else {
     for (int k = 0; k < 2; ++k) L.key64[k] = (uint64_t*)take(8 * (size_t)std::max<int64_t>(cap, 1));
   }
@@ -574,10 +916,11 @@ hipError_t bin_phase1(const Batch& B, int sort_mode, const float* depth, const i
                        L.dkey[0], L.perm[0]);
     uint32_t *ko, *vo;
     hipError_t e = radix_sort<uint32_t>(L.dkey[0], L.perm[0], L.dkey[1], L.perm[1], nullptr, n_rec,
-                                        n_rec, 32, L.counts, L.partials, &ko, &vo, st);
+                                        n_rec, 32, L.counts, L.partials, &ko, &vo, st, 0, nullptr,
+                                        true, tc, L.tcs);
     if (e != hipSuccess) return e;
     *perm_out = vo;
-    return device_scan(LoadCountPerm{tc, vo}, n_rec, L.offsets, L.partials, n_isect, st);
+    return device_scan(LoadArray{L.tcs}, n_rec, L.offsets, L.partials, n_isect, st);
   }
   return device_scan(LoadCount{tc}, n_rec, L.offsets, L.partials, n_isect, st);
 }
@@ -608,6 +951,65 @@ static hipError_t tile_order_lpt(const Batch& B, const BinWs& L, const int2* ran
   return hipGetLastError();
 }
 
+static inline bool tiles_16bit(int64_t tiles) { return tiles <= 65536; }
+
+// Depth-presort path, after phase 1: replication fused into the first pass
+// of the tile-id sort, the remaining passes on tile keys of type KT (16 bits
+// when the tile ids fit), tile ranges built by the last pass. The pass
+// count's parity picks the first output buffer so the last pass lands in
+// the caller's vals.
+template <typename KT>
+static hipError_t pair_sort(const Batch& B, int tile_bits, const float* depth, const short4* rc,
+                            const uint32_t* perm, int64_t n_rec, int64_t cap, int64_t grid_n,
+                            const int64_t* n_isect, uint64_t* keys_out, uint32_t* vals_u,
+                            int2* ranges, const BinWs& L, hipStream_t st) {
+  const int dbits = radix_digit_bits(tile_bits);
+  const int passes = radix_passes(tile_bits);
+  const bool one = passes == 1;
+  uint32_t* v1 = (passes % 2 == 1) ? vals_u : L.vals_alt;
+  uint32_t* v2 = (passes % 2 == 1) ? L.vals_alt : vals_u;
+  KT* tk0 = reinterpret_cast<KT*>(L.tkey[0]);
+  KT* tk1 = reinterpret_cast<KT*>(L.tkey[1]);
+  const int tiles = B.total_tiles;
+  hipLaunchKernelGGL(k_ranges_init, dim3(grid1(tiles)), dim3(256), 0, st, ranges, tiles);
+  hipLaunchKernelGGL(k_pair_records, dim3(grid1(n_rec)), dim3(256), 0, st, B, rc, L.tcs, perm,
+                     L.offsets, n_rec, n_isect, cap, L.packed, L.first);
+  const int nb = (int)((grid_n + kSortTile - 1) / kSortTile);
+  KT* k1 = (one && !keys_out) ? nullptr : tk0;
+  if (dbits == 7)
+    hipLaunchKernelGGL(k_pair_hist<7>, dim3(nb), dim3(256), 0, st, L.packed, L.first, n_isect,
+                       cap, L.counts, nb);
+  else
+    hipLaunchKernelGGL(k_pair_hist<8>, dim3(nb), dim3(256), 0, st, L.packed, L.first, n_isect,
+                       cap, L.counts, nb);
+  hipError_t e =
+      device_scan(LoadArray{L.counts}, (int64_t)nb << dbits, L.counts, L.partials, nullptr, st);
+  if (e != hipSuccess) return e;
+#define XPR_PAIR_SCATTER(BITS, LAST)                                                        \
+  hipLaunchKernelGGL((k_pair_scatter<BITS, LAST, KT>), dim3(nb), dim3(256), 0, st, L.packed, \
+                     L.first, n_isect, cap, L.counts, nb, k1, v1,                           \
+                     LAST ? ranges : (int2*)nullptr)
+  if (dbits == 7) {
+    if (one) XPR_PAIR_SCATTER(7, true); else XPR_PAIR_SCATTER(7, false);
+  } else {
+    if (one) XPR_PAIR_SCATTER(8, true); else XPR_PAIR_SCATTER(8, false);
+  }
+#undef XPR_PAIR_SCATTER
+  KT* ko = tk0;
+  uint32_t* vo = v1;
+  if (!one) {
+    e = radix_sort<KT>(tk0, v1, tk1, v2, n_isect, cap, grid_n, tile_bits, L.counts, L.partials,
+                       &ko, &vo, st, dbits, ranges, keys_out != nullptr);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_ranges_fix, dim3(grid1(tiles)), dim3(256), 0, st, ranges, tiles);
+  if (keys_out)
+    hipLaunchKernelGGL(k_make_keys64<KT>, dim3(grid1(grid_n)), dim3(256), 0, st, ko, vo, depth,
+                       n_isect, cap, keys_out);
+  if (vo != vals_u) return hipErrorUnknown;  // the pass parity above guarantees vo == vals
+  return hipGetLastError();
+}
+
 hipError_t bin_phase2(const Batch& B, int sort_mode, int tile_bits, const float* depth,
                       const int16_t* rect, const int32_t* tc, const uint32_t* perm, int64_t n_rec,
                       int64_t cap, int64_t grid_n, const int64_t* n_isect, uint64_t* keys_out,
@@ -625,24 +1027,13 @@ hipError_t bin_phase2(const Batch& B, int sort_mode, int tile_bits, const float*
   uint32_t* vals_u = reinterpret_cast<uint32_t*>(vals);
   const int nbd = grid1(n_rec);
   if (sort_mode == XPR_SORT_PRESORT) {
-    const int passes = radix_passes(tile_bits);
-    // start so that the last pass lands in the caller's vals
-    uint32_t* v_start = (passes % 2 == 0) ? vals_u : L.vals_alt;
-    uint32_t* v_other = (passes % 2 == 0) ? L.vals_alt : vals_u;
-    hipLaunchKernelGGL((k_duplicate<true, false>), dim3(nbd), dim3(256), 0, st, B, rc, tc, depth,
-                       perm, L.offsets, n_rec, cap, (void*)L.tkey[0], v_start);
-    uint32_t *ko, *vo;
-    hipError_t e = radix_sort<uint32_t>(L.tkey[0], v_start, L.tkey[1], v_other, n_isect, cap,
-                                        grid_n, tile_bits, L.counts, L.partials, &ko, &vo, st);
+    const hipError_t e =
+        tiles_16bit(B.total_tiles)
+            ? pair_sort<uint16_t>(B, tile_bits, depth, rc, perm, n_rec, cap, grid_n, n_isect,
+                                  keys_out, vals_u, ranges, L, st)
+            : pair_sort<uint32_t>(B, tile_bits, depth, rc, perm, n_rec, cap, grid_n, n_isect,
+                                  keys_out, vals_u, ranges, L, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ranges<uint32_t>, dim3(grid1((grid_n + 3) / 4)), dim3(256), 0, st, ko,
-                       n_isect, cap, B.total_tiles, ranges);
-    if (keys_out)
-      hipLaunchKernelGGL(k_make_keys64, dim3(grid1(grid_n)), dim3(256), 0, st, ko, vo, depth,
-                         n_isect, cap, keys_out);
-    if (vo != vals_u)
-      hipLaunchKernelGGL(k_copy_u32, dim3(grid1(grid_n)), dim3(256), 0, st, vo, n_isect, cap,
-                         vals_u);
   } else {
     const int bits = 32 + tile_bits;
     const int passes = radix_passes(bits);

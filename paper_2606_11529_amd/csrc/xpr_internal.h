@@ -61,6 +61,20 @@ __device__ __forceinline__ int view_of_tile(const Batch& B, int g) {
   return v;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs of an MI355X
+// (workgroup b runs on XCD b % 8), and each XCD has its own L2. This
+// bijection of [0, n) gives XCD x a contiguous range of work items, so
+// neighbouring items (adjacent partitions of a sort, whose partial cache
+// lines at run boundaries then merge in one L2) share an L2. Only for blocks
+// of uniform cost: it hands each XCD one contiguous stretch of the work, so
+// uneven work (image tiles, records of very different footprint) would pile
+// up on some XCDs. Correct for any dispatch order; only locality changes.
+__device__ __forceinline__ int xcd_swizzle(int b, int n) {
+  const int x = b & 7, k = b >> 3;
+  const int per = n >> 3, rem = n & 7;
+  return x * per + min(x, rem) + k;
+}
+
 // Cross-lane helpers (wave64).
 template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf>
 __device__ __forceinline__ float dpp_f(float x) {
