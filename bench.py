@@ -54,6 +54,7 @@ def main():
     ap.add_argument("--fwd-ppt", type=int, default=None)
     ap.add_argument("--bwd-ppt", type=int, default=None)
     ap.add_argument("--bwd-lds-batch", type=int, default=None)
+    ap.add_argument("--schedule", choices=("index", "longest_first", "persistent"), default=None)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -77,6 +78,9 @@ def main():
     for k in ("fwd_ppt", "bwd_ppt", "bwd_lds_batch"):
         if getattr(args, k) is not None:
             cfg = dataclasses.replace(cfg, **{k: getattr(args, k)})
+    if args.schedule is not None:
+        cfg = dataclasses.replace(cfg, tile_order=args.schedule != "index",
+                                  persistent=args.schedule == "persistent")
     scene = R.Scene.from_host(sc, dev)
     tuned = None
     if not args.no_autotune:
@@ -87,7 +91,8 @@ def main():
         tuned = autotune(scene, cams, cfg, tiles=(args.tile,), reps=2)
         cfg = tuned.apply(cfg)
         log(f"[bench] autotune {time.time() - t0:.1f}s: sort {cfg.sort_mode}, fwd "
-            f"{cfg.lds_batch}x{cfg.fwd_ppt}, bwd {cfg.bwd_lds_batch}x{cfg.bwd_ppt}")
+            f"{cfg.lds_batch}x{cfg.fwd_ppt}, bwd {cfg.bwd_lds_batch}x{cfg.bwd_ppt}, "
+            f"schedule {tuned.schedule}")
     gen = torch.Generator(device=dev)
     gen.manual_seed(7)
     H, W = args.height, args.width
@@ -213,11 +218,13 @@ def main():
     }
     dom = "render_bwd" if mean["render_bwd"] >= mean["render_fwd"] else "render_fwd"
     ops = OPS_BWD * evals_bwd if dom == "render_bwd" else OPS_FWD * evals_fwd
+    pers = "true" if cfg.persistent else "false"
     if dom == "render_bwd":
         kname = (f"xpr::k_render_bwd<{args.tile},{args.tile},"
-                 f"{cfg.bwd_lds_batch or cfg.lds_batch},{cfg.bwd_ppt},false>")
+                 f"{cfg.bwd_lds_batch or cfg.lds_batch},{cfg.bwd_ppt},{pers}>")
     else:
-        kname = f"xpr::k_render_fwd<{args.tile},{args.tile},{cfg.lds_batch},{cfg.fwd_ppt},false>"
+        kname = (f"xpr::k_render_fwd<{args.tile},{args.tile},{cfg.lds_batch},{cfg.fwd_ppt},"
+                 f"{pers}>")
     # HBM bytes per launch from the committed counter record, only while the
     # kernel sources are the ones it was taken from
     from paper_2606_11529_amd.profiling import traffic_of
@@ -237,7 +244,10 @@ def main():
                    "sort": cfg.sort_mode, "fwd_lds_batch": cfg.lds_batch,
                    "fwd_ppt": cfg.fwd_ppt,
                    "bwd_lds_batch": cfg.bwd_lds_batch or cfg.lds_batch,
-                   "bwd_ppt": cfg.bwd_ppt, "autotuned": tuned is not None,
+                   "bwd_ppt": cfg.bwd_ppt,
+                   "schedule": ("persistent" if cfg.persistent else
+                                "longest_first" if cfg.tile_order else "index"),
+                   "autotuned": tuned is not None,
                    "pairs_per_frame": pairs},
         "stage_sum_ms": round(frame_ms, 4),
         "stages_ms_median": med,
@@ -281,7 +291,8 @@ def bench_batched(n=2_000_000, n_views=16, reps=5):
     targets = [torch.rand((3, c.height, c.width), generator=gen, device="cuda") for c in cams]
     pixels = sum(c.width * c.height for c in cams)
     log(f"[batch] scene {n}, {n_views} views, {pixels / 1e6:.1f} Mpx ({time.time() - t0:.1f}s)")
-    tuned = autotune(scene, cams, R.Config(persistent=True), tiles=(8, 16), reps=1)
+    tuned = autotune(scene, cams, R.Config(persistent=True), tiles=(8, 16), reps=1,
+                     schedules=("persistent",))
     cfg = tuned.apply(R.Config(persistent=True))
     log(f"[batch] autotuned tile {cfg.tile}, sort {cfg.sort_mode}, fwd {cfg.lds_batch}x"
         f"{cfg.fwd_ppt}, bwd {cfg.bwd_lds_batch}x{cfg.bwd_ppt}")
@@ -302,7 +313,7 @@ def bench_batched(n=2_000_000, n_views=16, reps=5):
     del br
     torch.cuda.empty_cache()
     # the same work as plain per-view launches (tile size as tuned)
-    pcfg = dataclasses.replace(cfg, persistent=False)
+    pcfg = dataclasses.replace(cfg, persistent=False, tile_order=False)
     ws = R.Workspace()
     states = [dict() for _ in cams]
     for v, cam in enumerate(cams):

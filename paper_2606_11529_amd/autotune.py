@@ -7,7 +7,11 @@ phases:
   1. tile size (8x8 or 16x16; this changes the pair lists, so the sort is
      re-profiled per tile size) and sort strategy (presort / full);
   2. forward compositing: LDS batch x pixels per thread;
-  3. backward compositing: LDS batch x pixels per thread.
+  3. backward compositing: LDS batch x pixels per thread;
+  4. tile schedule: tiles in index order, longest list first, or longest
+     first on a persistent grid (the analogue of the paper's trip-count
+     binning), timed as binning + forward + backward since the order is
+     built during binning.
 None of these knobs changes the rendered image except the tile size (the
 3-sigma rect is rounded out to whole tiles), which is only searched when the
 caller allows it. Results are cached in JSON keyed by device, scene size, SH
@@ -71,12 +75,15 @@ class TuneResult:
     bwd_lds: int
     bwd_ppt: int
     ms: dict
+    schedule: str = "index"  # "index" | "longest_first" | "persistent"
 
     def apply(self, cfg):
         """``cfg`` with the tuned knobs."""
         return dataclasses.replace(cfg, tile=self.tile, sort_mode=self.sort_mode,
                                    lds_batch=self.fwd_lds, fwd_ppt=self.fwd_ppt,
-                                   bwd_lds_batch=self.bwd_lds, bwd_ppt=self.bwd_ppt)
+                                   bwd_lds_batch=self.bwd_lds, bwd_ppt=self.bwd_ppt,
+                                   tile_order=self.schedule != "index",
+                                   persistent=self.schedule == "persistent")
 
 
 def _timer():
@@ -96,8 +103,12 @@ def _timer():
     return time_call
 
 
+SCHEDULES = ("index", "longest_first", "persistent")
+
+
 def autotune(scene, cams, cfg, tiles=(16,), lds_batches=LDS_BATCHES, ppts=PPTS, sorts=SORTS,
-             reps: int = 3, cache_path: Optional[str] = None, verbose: bool = False) -> TuneResult:
+             reps: int = 3, cache_path: Optional[str] = None, verbose: bool = False,
+             schedules: Sequence[str] = SCHEDULES) -> TuneResult:
     """Search the knobs on ``scene`` (a renderer.Scene) over ``cams``."""
     import torch
 
@@ -171,6 +182,40 @@ def autotune(scene, cams, cfg, tiles=(16,), lds_batches=LDS_BATCHES, ppts=PPTS, 
     best = min(tile_rows)
     res = TuneResult(tile=best[1], sort_mode=best[2], fwd_lds=best[3], fwd_ppt=best[4],
                      bwd_lds=best[5], bwd_ppt=best[6], ms=ms)
+    if len(schedules) == 1:
+        res.schedule = schedules[0]
+    else:
+        res.schedule = _tune_schedule(scene, cams, res.apply(cfg), schedules, reps, time_call, ws,
+                                      ms)
+        if verbose:
+            print(f"[autotune] schedule {res.schedule}", flush=True)
     cache[key] = dataclasses.asdict(res)
     save_cache(cache_path, cache)
     return res
+
+
+def _tune_schedule(scene, cams, cfg, schedules, reps, time_call, ws, ms) -> str:
+    """Phase 4: binning + forward + backward per tile schedule."""
+    import torch
+
+    from . import renderer as R
+
+    g2 = torch.empty((scene.n, 9), dtype=torch.float32, device=scene.means.device)
+    dimgs = [torch.randn(3 * c.width * c.height, device=scene.means.device) * 1e-6 for c in cams]
+    t = {}
+    for sch in schedules:
+        cs = dataclasses.replace(cfg, tile_order=sch != "index", persistent=sch == "persistent")
+        views = [R.Views([scene], [c], [0], cs) for c in cams]
+        projs = [R.xpr_project(v, cs) for v in views]
+        bins = [R.xpr_bin_sort(v, cs, p, ws=ws) for v, p in zip(views, projs)]
+        frames = [R.xpr_render_fwd(v, cs, p, b) for v, p, b in zip(views, projs, bins)]
+
+        def run(cs=cs, views=views, projs=projs, bins=bins, frames=frames):
+            for v, p, b, fr, d in zip(views, projs, bins, frames, dimgs):
+                R.xpr_bin_sort(v, cs, p, capacity=b.capacity, ws=ws, out=b)
+                R.xpr_render_fwd(v, cs, p, b, out=fr)
+                R.xpr_render_bwd(v, cs, p, b, fr, d, params=False, grad2d=g2, ws=ws)
+        run()
+        t[sch] = time_call(run, reps)
+    ms["schedule"] = {k: statistics.median(v) for k, v in t.items()}
+    return pick_best(t)

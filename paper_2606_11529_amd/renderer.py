@@ -36,6 +36,7 @@ class Config:
     bwd_ppt: int = 4            # pixels per thread, backward (16x16 tiles)
     bwd_lds_batch: int = 0      # LDS batch of the backward (0: lds_batch)
     persistent: bool = False    # persistent render grids over the tile order
+    tile_order: bool = False    # launch tiles longest list first (implied by persistent)
 
     def to_c(self) -> L.XprConfig:
         c = L.XprConfig()
@@ -241,10 +242,10 @@ def xpr_bin_sort(views: Views, cfg: Config, proj: Projected, capacity: Optional[
                  out: Optional[Bins] = None, want_order: Optional[bool] = None) -> Bins:
     """Binning with a host-side capacity retry on XPR_ERR_CAPACITY. The
     longest-first tile order is produced when ``want_order`` (default: when
-    the config is persistent)."""
+    the config asks for it or is persistent)."""
     ws = ws or _WS
     dev = proj.splat.device
-    want_order = cfg.persistent if want_order is None else want_order
+    want_order = (cfg.persistent or cfg.tile_order) if want_order is None else want_order
     cap = capacity if capacity is not None else max(1024, 16 * views.records)
     if out is not None and out.capacity >= cap:
         cap = out.capacity

@@ -27,3 +27,17 @@ def test_cache_roundtrip(tmp_path):
     cfg = back.apply(R.Config())
     assert (cfg.lds_batch, cfg.fwd_ppt, cfg.bwd_lds_batch, cfg.bwd_ppt) == (256, 2, 128, 4)
     assert cfg.to_c().bwd_lds_batch == 128
+
+
+def test_schedule_applies_order_and_persistence():
+    base = A.TuneResult(16, "presort", 256, 1, 64, 4, {})
+    assert base.schedule == "index"
+    c = base.apply(R.Config(persistent=True, tile_order=True))
+    assert not c.tile_order and not c.persistent and c.to_c().persistent == 0
+    lf = A.TuneResult(16, "presort", 256, 1, 64, 4, {}, schedule="longest_first").apply(R.Config())
+    assert lf.tile_order and not lf.persistent
+    ps = A.TuneResult(16, "presort", 256, 1, 64, 4, {}, schedule="persistent").apply(R.Config())
+    assert ps.tile_order and ps.persistent and ps.to_c().persistent == 1
+    # cache entries written before the schedule phase still load
+    old = {k: v for k, v in base.__dict__.items() if k != "schedule"}
+    assert A.TuneResult(**old).schedule == "index"
