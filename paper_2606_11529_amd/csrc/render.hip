@@ -67,52 +67,73 @@ __device__ __forceinline__ void fwd_tile(const Batch& B, int g, const float4* __
   const int2 rg = ranges[g];
   const float fpx = (float)px;
   const float amax = B.alpha_max, amin = B.alpha_min, tmin = B.t_min;
-  float T[PPT], C0[PPT], C1[PPT], C2[PPT];
+  float T[PPT], C0[PPT], C1[PPT], C2[PPT], lift[PPT];
   int last[PPT];
-  bool done[PPT];
-  int ndone = 0;
+  int nalive = 0;
 #pragma unroll
   for (int j = 0; j < PPT; ++j) {
     T[j] = 1.f;
     C0[j] = C1[j] = C2[j] = 0.f;
     last[j] = 0;
-    done[j] = !(px < V.W && py0 + j < V.H);
-    ndone += done[j];
+    const bool inside = px < V.W && py0 + j < V.H;
+    lift[j] = inside ? 0.f : __builtin_inff();
   }
   int walked = 0;
   for (int base = rg.x; base < rg.y; base += BATCH) {
-    if (__syncthreads_count(ndone < PPT) == 0) break;
+    nalive = 0;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) nalive += lift[j] == 0.f ? 1 : 0;
+    if (__syncthreads_count(nalive > 0) == 0) break;
     walked = min(BATCH, rg.y - base) + (base - rg.x);
     for (int k = threadIdx.x; k < BATCH; k += NT) {
       const int idx = base + k;
       if (idx < rg.y) stage_record(splat, (size_t)vals[idx], amin, s0[k], s1[k], s2[k]);
     }
     __syncthreads();
+    // The walk over the batch is branch-free per lane: a lane's decisions
+    // become selects, and only wave-uniform conditions branch (all lanes
+    // finished; no lane at or above the record's power threshold).
+    // Divergent branches would cost a scalar exec-mask sequence per
+    // condition per record, and the scalar unit has no more issue slots
+    // than the vector unit. A finished pixel adds +inf to every record's
+    // threshold (a live one adds 0), so it never passes the test again.
     const int nb = min(BATCH, rg.y - base);
-    for (int k = 0; k < nb && ndone < PPT; ++k) {
-      const float4 a = s0[k];
-      const float4 b = s1[k];
-      const float dx = __fsub_rn(fpx, a.x);
+    for (int k0 = 0; k0 < nb; k0 += 8) {
+      bool alive = false;
 #pragma unroll
-      for (int j = 0; j < PPT; ++j) {
-        if (done[j]) continue;
-        const float P2 = power2(dx, __fsub_rn((float)(py0 + j), a.y), a, b.x);
-        if (P2 < b.y) continue;
-        const float alpha = fminf(amax, __fmul_rn(b.z, __builtin_amdgcn_exp2f(P2)));
-        if (P2 > 0.f || alpha < amin) continue;
-        const float Tn = T[j] * (1.f - alpha);
-        if (Tn < tmin) {
-          done[j] = true;
-          ++ndone;
-          continue;
+      for (int j = 0; j < PPT; ++j) alive = alive || lift[j] == 0.f;
+      if (__ballot(alive) == 0) break;
+      const int kend = min(k0 + 8, nb);
+      for (int k = k0; k < kend; ++k) {
+        const float4 a = s0[k];
+        const float4 b = s1[k];
+        const float dx = __fsub_rn(fpx, a.x);
+        float P2[PPT];
+        bool anyp = false;
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+          P2[j] = power2(dx, __fsub_rn((float)(py0 + j), a.y), a, b.x);
+          anyp = anyp || P2[j] >= b.y + lift[j];
         }
-        const float w = alpha * T[j];
+        if (__ballot(anyp) == 0) continue;
         const float2 gb = s2[k];
-        C0[j] += b.w * w;
-        C1[j] += gb.x * w;
-        C2[j] += gb.y * w;
-        T[j] = Tn;
-        last[j] = base + k - rg.x + 1;
+        const int idx = base + k - rg.x + 1;
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+          // finished pixels and P2 > 0 get alpha 0, which fails alpha >= amin
+          float alpha = fminf(amax, __fmul_rn(b.z, __builtin_amdgcn_exp2f(P2[j])));
+          alpha = P2[j] + lift[j] > 0.f ? 0.f : alpha;
+          const bool use = alpha >= amin;
+          const float Tn = T[j] * (1.f - alpha);
+          const bool blend = use && Tn >= tmin;
+          const float w = blend ? alpha * T[j] : 0.f;
+          C0[j] += b.w * w;
+          C1[j] += gb.x * w;
+          C2[j] += gb.y * w;
+          T[j] = blend ? Tn : T[j];
+          last[j] = blend ? idx : last[j];
+          lift[j] = (use && !blend) ? __builtin_inff() : lift[j];
+        }
       }
     }
   }
@@ -238,23 +259,34 @@ __device__ __forceinline__ void bwd_tile(const Batch& B, int g, const float4* __
       if (__ballot(pos <= mylast) == 0) continue;
       const float4 a = s0[k];
       const float4 b = s1[k];
+      const float dx = __fsub_rn(fpx, a.x);
+      // Branch-free per lane, as in the forward: pixels past their last
+      // blended entry or below the record's threshold get alpha 0, which
+      // makes every update below exact no-ops (T * rcp(1) = T, S unchanged,
+      // all gradient terms 0).
+      float P2[PPT], dy[PPT];
+      bool anyp = false;
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        dy[j] = __fsub_rn((float)(py0 + j), a.y);
+        P2[j] = power2(dx, dy[j], a, b.x);
+        const float thr = pos <= last[j] ? b.y : __builtin_inff();
+        anyp = anyp || P2[j] >= thr;
+        P2[j] = P2[j] >= thr ? P2[j] : __builtin_inff();  // inf: not in play
+      }
+      if (__ballot(anyp) == 0) continue;
       const float2 c = s2[k];
       const float cr = b.w, cg = c.x, cb = c.y;
-      const float dx = __fsub_rn(fpx, a.x);
       float gu = 0.f, gv = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, go = 0.f;
       float gr = 0.f, gg = 0.f, gb = 0.f;
       bool any = false;
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
-        if (pos > last[j]) continue;
-        const float dy = __fsub_rn((float)(py0 + j), a.y);
-        const float P2 = power2(dx, dy, a, b.x);
-        if (P2 < b.y) continue;
-        const float eP = __builtin_amdgcn_exp2f(P2);
+        const float eP = __builtin_amdgcn_exp2f(P2[j]);
         const float raw = __fmul_rn(b.z, eP);
-        const float alpha = fminf(amax, raw);
-        if (P2 > 0.f || alpha < amin) continue;
-        any = true;
+        float alpha = fminf(amax, raw);
+        alpha = (P2[j] > 0.f || alpha < amin) ? 0.f : alpha;  // covers P2 = inf
+        any = any || alpha > 0.f;
         const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
         T[j] = T[j] * inv;
         const float w = alpha * T[j];
@@ -266,17 +298,16 @@ __device__ __forceinline__ void bwd_tile(const Batch& B, int g, const float4* __
         S0[j] = alpha * cr + (1.f - alpha) * S0[j];
         S1[j] = alpha * cg + (1.f - alpha) * S1[j];
         S2[j] = alpha * cb + (1.f - alpha) * S2[j];
-        if (raw <= amax) {
-          // dL/dP in natural-log units; the staged conic carries log2(e)
-          const float dP = alpha * da;
-          const float dPn = dP * kLn2;
-          go += eP * da;
-          gu -= dPn * (2.f * a.z * dx + a.w * dy);
-          gv -= dPn * (2.f * b.x * dy + a.w * dx);
-          gA += dP * dx * dx;
-          gB += dP * dx * dy;
-          gC += dP * dy * dy;
-        }
+        // dL/dP in natural-log units (zero when alpha is clamped); the
+        // staged conic carries log2(e)
+        const float dP = raw <= amax ? alpha * da : 0.f;
+        const float dPn = dP * kLn2;
+        go += raw <= amax && alpha > 0.f ? eP * da : 0.f;
+        gu -= dPn * (2.f * a.z * dx + a.w * dy[j]);
+        gv -= dPn * (2.f * b.x * dy[j] + a.w * dx);
+        gA += dP * dx * dx;
+        gB += dP * dx * dy[j];
+        gC += dP * dy[j] * dy[j];
       }
       if (__ballot(any) == 0) continue;
       gu = wave_sum_lane63(gu);
