@@ -196,6 +196,59 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_render_fwd(
 // sums them over its lanes with DPP and one lane adds them to
 // grad2d [record][9] with float atomics. Waves where no pixel uses the entry
 // skip both.
+// Sum over the 64 lanes of a wave of nine values for each of two records X
+// and Y, added to gx[0..8] and gy[0..8] with float atomics (a record whose
+// flag is false is skipped). The two records are reduced together with the
+// gfx950 lane swaps: permlane32 swaps of (X_i, Y_i) leave X_i folded to 32
+// lanes in the lower half and Y_i in the upper half of one register;
+// permlane16 swaps of register pairs then fold to one row of 16 lanes per
+// (record, value), so 5 registers hold all 18 values, a row of 16 lanes
+// each; four DPP steps sum each row, and lane 15 of row r issues that row's
+// atomics: row 0 X_0,2,4,6,8; row 1 X_1,3,5,7; row 2 Y_0,2,4,6,8; row 3
+// Y_1,3,5,7. 48 lane-parallel instructions instead of 2 x 9 full-wave
+// reductions.
+__device__ __forceinline__ float fold32(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float fold16(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float row_sum16(float x) {
+  x += dpp_f<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += dpp_f<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += dpp_f<0x141>(x);  // row_half_mirror
+  x += dpp_f<0x140>(x);  // row_mirror: every lane holds its row sum
+  return x;
+}
+
+__device__ __forceinline__ void reduce_pair(const float (&X)[9], const float (&Y)[9], bool ax,
+                                            bool ay, float* gx, float* gy) {
+  float Z[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Z[i] = fold32(X[i], Y[i]);
+  float W[5];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) W[m] = row_sum16(fold16(Z[2 * m], Z[2 * m + 1]));
+  W[4] = row_sum16(fold16(Z[8], 0.f));
+  const int lane = threadIdx.x & 63;
+  if ((lane & 15) == 15) {
+    const int row = lane >> 4;
+    const bool isy = row >= 2;
+    if (isy ? ay : ax) {
+      float* dst = (isy ? gy : gx) + (row & 1);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) atomicAdd(dst + 2 * m, W[m]);
+      if ((row & 1) == 0) atomicAdd(dst + 8, W[4]);
+    }
+  }
+}
+
 template <int TW, int TH, int BATCH, int PPT>
 __device__ __forceinline__ void bwd_tile(const Batch& B, int g, const float4* __restrict__ splat,
                                          const int32_t* __restrict__ vals,
@@ -217,7 +270,7 @@ __device__ __forceinline__ void bwd_tile(const Batch& B, int g, const float4* __
   const float amax = B.alpha_max, amin = B.alpha_min;
   const size_t WH = (size_t)V.W * V.H;
   const float* gi = dimg + 3 * (size_t)V.pix_off;
-  float T[PPT], Tf[PPT], G0[PPT], G1[PPT], G2[PPT], S0[PPT], S1[PPT], S2[PPT], bgG[PPT];
+  float T[PPT], TfbG[PPT], G0[PPT], G1[PPT], G2[PPT], S0[PPT], S1[PPT], S2[PPT];
   int last[PPT];
   int mylast = 0;
 #pragma unroll
@@ -234,9 +287,9 @@ __device__ __forceinline__ void bwd_tile(const Batch& B, int g, const float4* __
       G1[j] = gi[WH + p];
       G2[j] = gi[2 * WH + p];
     }
-    Tf[j] = T[j];
     S0[j] = S1[j] = S2[j] = 0.f;
-    bgG[j] = B.bg[0] * G0[j] + B.bg[1] * G1[j] + B.bg[2] * G2[j];
+    // T_final (bg . G), the background's share of dL/dalpha before 1/(1-alpha)
+    TfbG[j] = T[j] * (B.bg[0] * G0[j] + B.bg[1] * G1[j] + B.bg[2] * G2[j]);
     mylast = max(mylast, last[j]);
   }
   __syncthreads();
@@ -245,8 +298,67 @@ __device__ __forceinline__ void bwd_tile(const Batch& B, int g, const float4* __
   if (mylast > 0) atomicMax(&s_maxlast, mylast);
   __syncthreads();
   const int end = rg.x + min(s_maxlast, rg.y - rg.x);
+  int lo = 0;
+  // Per-lane sums of the nine gradient terms of staged record kk over this
+  // lane's PPT pixels, into g; returns whether any lane of the wave used it.
+  // Branch-free per lane, as in the forward: pixels past their last blended
+  // entry or below the record's threshold get alpha 0, which makes every
+  // update an exact no-op (T * rcp(1) = T, S unchanged, all terms 0).
+  auto contrib = [&](int kk, float (&g)[9]) -> bool {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) g[i] = 0.f;
+    const int pos = lo + kk - rg.x + 1;
+    if (__ballot(pos <= mylast) == 0) return false;
+    const float4 a = s0[kk];
+    const float4 b = s1[kk];
+    const float dx = __fsub_rn(fpx, a.x);
+    float P2[PPT], dy[PPT];
+    bool anyp = false;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      dy[j] = __fsub_rn((float)(py0 + j), a.y);
+      P2[j] = power2(dx, dy[j], a, b.x);
+      const float thr = pos <= last[j] ? b.y : __builtin_inff();
+      anyp = anyp || P2[j] >= thr;
+      P2[j] = P2[j] >= thr ? P2[j] : __builtin_inff();  // inf: not in play
+    }
+    if (__ballot(anyp) == 0) return false;
+    const float2 c = s2[kk];
+    const float cr = b.w, cg = c.x, cb = c.y;
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const float eP = __builtin_amdgcn_exp2f(P2[j]);
+      const float raw = __fmul_rn(b.z, eP);
+      float alpha = fminf(amax, raw);
+      alpha = (P2[j] > 0.f || alpha < amin) ? 0.f : alpha;  // covers P2 = inf
+      any = any || alpha > 0.f;
+      const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
+      T[j] = T[j] * inv;
+      const float w = alpha * T[j];
+      g[6] += w * G0[j];
+      g[7] += w * G1[j];
+      g[8] += w * G2[j];
+      const float da = T[j] * ((cr - S0[j]) * G0[j] + (cg - S1[j]) * G1[j] +
+                               (cb - S2[j]) * G2[j]) - TfbG[j] * inv;
+      S0[j] = alpha * cr + (1.f - alpha) * S0[j];
+      S1[j] = alpha * cg + (1.f - alpha) * S1[j];
+      S2[j] = alpha * cb + (1.f - alpha) * S2[j];
+      // dL/dP in natural-log units (zero when alpha is clamped); the staged
+      // conic carries log2(e)
+      const float dP = raw <= amax ? alpha * da : 0.f;
+      const float dPn = dP * kLn2;
+      g[5] += raw <= amax && alpha > 0.f ? eP * da : 0.f;
+      g[0] -= dPn * (2.f * a.z * dx + a.w * dy[j]);
+      g[1] -= dPn * (2.f * b.x * dy[j] + a.w * dx);
+      g[2] += dP * dx * dx;
+      g[3] += dP * dx * dy[j];
+      g[4] += dP * dy[j] * dy[j];
+    }
+    return __ballot(any) != 0;
+  };
   for (int hi = end; hi > rg.x; hi -= BATCH) {
-    const int lo = max(rg.x, hi - BATCH);
+    lo = max(rg.x, hi - BATCH);
     __syncthreads();
     for (int k = threadIdx.x; k < hi - lo; k += NT) {
       const int r = vals[lo + k];
@@ -254,83 +366,20 @@ __device__ __forceinline__ void bwd_tile(const Batch& B, int g, const float4* __
       stage_record(splat, (size_t)r, amin, s0[k], s1[k], s2[k]);
     }
     __syncthreads();
-    for (int k = hi - lo - 1; k >= 0; --k) {
-      const int pos = lo + k - rg.x + 1;
-      if (__ballot(pos <= mylast) == 0) continue;
-      const float4 a = s0[k];
-      const float4 b = s1[k];
-      const float dx = __fsub_rn(fpx, a.x);
-      // Branch-free per lane, as in the forward: pixels past their last
-      // blended entry or below the record's threshold get alpha 0, which
-      // makes every update below exact no-ops (T * rcp(1) = T, S unchanged,
-      // all gradient terms 0).
-      float P2[PPT], dy[PPT];
-      bool anyp = false;
+    // Records are taken two at a time (k, then k - 1: the reverse order
+    // the recovery of T needs) and their 2 x 9 per-lane sums reduced over
+    // the wave together (reduce_pair).
+    for (int k = hi - lo - 1; k >= 0; k -= 2) {
+      float X[9], Y[9];
+      const bool ax = contrib(k, X);
+      const bool ay = k >= 1 && contrib(k - 1, Y);
+      if (!ax && !ay) continue;
+      if (!ay) {
 #pragma unroll
-      for (int j = 0; j < PPT; ++j) {
-        dy[j] = __fsub_rn((float)(py0 + j), a.y);
-        P2[j] = power2(dx, dy[j], a, b.x);
-        const float thr = pos <= last[j] ? b.y : __builtin_inff();
-        anyp = anyp || P2[j] >= thr;
-        P2[j] = P2[j] >= thr ? P2[j] : __builtin_inff();  // inf: not in play
+        for (int i = 0; i < 9; ++i) Y[i] = 0.f;
       }
-      if (__ballot(anyp) == 0) continue;
-      const float2 c = s2[k];
-      const float cr = b.w, cg = c.x, cb = c.y;
-      float gu = 0.f, gv = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, go = 0.f;
-      float gr = 0.f, gg = 0.f, gb = 0.f;
-      bool any = false;
-#pragma unroll
-      for (int j = 0; j < PPT; ++j) {
-        const float eP = __builtin_amdgcn_exp2f(P2[j]);
-        const float raw = __fmul_rn(b.z, eP);
-        float alpha = fminf(amax, raw);
-        alpha = (P2[j] > 0.f || alpha < amin) ? 0.f : alpha;  // covers P2 = inf
-        any = any || alpha > 0.f;
-        const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
-        T[j] = T[j] * inv;
-        const float w = alpha * T[j];
-        gr += w * G0[j];
-        gg += w * G1[j];
-        gb += w * G2[j];
-        const float da = T[j] * ((cr - S0[j]) * G0[j] + (cg - S1[j]) * G1[j] +
-                                 (cb - S2[j]) * G2[j]) - Tf[j] * bgG[j] * inv;
-        S0[j] = alpha * cr + (1.f - alpha) * S0[j];
-        S1[j] = alpha * cg + (1.f - alpha) * S1[j];
-        S2[j] = alpha * cb + (1.f - alpha) * S2[j];
-        // dL/dP in natural-log units (zero when alpha is clamped); the
-        // staged conic carries log2(e)
-        const float dP = raw <= amax ? alpha * da : 0.f;
-        const float dPn = dP * kLn2;
-        go += raw <= amax && alpha > 0.f ? eP * da : 0.f;
-        gu -= dPn * (2.f * a.z * dx + a.w * dy[j]);
-        gv -= dPn * (2.f * b.x * dy[j] + a.w * dx);
-        gA += dP * dx * dx;
-        gB += dP * dx * dy[j];
-        gC += dP * dy[j] * dy[j];
-      }
-      if (__ballot(any) == 0) continue;
-      gu = wave_sum_lane63(gu);
-      gv = wave_sum_lane63(gv);
-      gA = wave_sum_lane63(gA);
-      gB = wave_sum_lane63(gB);
-      gC = wave_sum_lane63(gC);
-      go = wave_sum_lane63(go);
-      gr = wave_sum_lane63(gr);
-      gg = wave_sum_lane63(gg);
-      gb = wave_sum_lane63(gb);
-      if ((threadIdx.x & 63) == 63) {
-        float* dst = grad2d + 9 * (size_t)srec[k];
-        atomicAdd(dst + 0, gu);
-        atomicAdd(dst + 1, gv);
-        atomicAdd(dst + 2, gA);
-        atomicAdd(dst + 3, gB);
-        atomicAdd(dst + 4, gC);
-        atomicAdd(dst + 5, go);
-        atomicAdd(dst + 6, gr);
-        atomicAdd(dst + 7, gg);
-        atomicAdd(dst + 8, gb);
-      }
+      reduce_pair(X, Y, ax, ay, grad2d + 9 * (size_t)srec[k],
+                  grad2d + 9 * (size_t)srec[k >= 1 ? k - 1 : k]);
     }
   }
 }
