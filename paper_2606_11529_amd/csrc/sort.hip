@@ -94,12 +94,14 @@ template <class L>
 __global__ __launch_bounds__(256) void k_scan_reduce(L load, int64_t n, uint64_t* partials) {
   __shared__ uint64_t s_wave[4];
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  // all loads first (indices clamped, out-of-range items weighted 0)
+  uint32_t x[kScanItems];
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) x[j] = load(min(base + j * 256 + threadIdx.x, n - 1));
   uint64_t s = 0;
 #pragma unroll
-  for (int j = 0; j < kScanItems; ++j) {
-    const int64_t i = base + j * 256 + threadIdx.x;
-    if (i < n) s += load(i);
-  }
+  for (int j = 0; j < kScanItems; ++j)
+    if (base + j * 256 + threadIdx.x < n) s += x[j];
   s = block_sum256_u64(s, s_wave);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
@@ -147,10 +149,15 @@ __global__ __launch_bounds__(256) void k_scan_down(L load, int64_t n, const uint
   __shared__ uint32_t s_wave[4];
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
   const int t = threadIdx.x;
+  {
+    uint32_t y[kScanItems];
 #pragma unroll
-  for (int j = 0; j < kScanItems; ++j) {
-    const int i = j * 256 + t;
-    s[i + (i >> 4)] = (base + i < n) ? load(base + i) : 0u;
+    for (int j = 0; j < kScanItems; ++j) y[j] = load(min(base + j * 256 + t, n - 1));
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+      const int i = j * 256 + t;
+      s[i + (i >> 4)] = (base + i < n) ? y[j] : 0u;
+    }
   }
   __syncthreads();
   uint32_t x[kScanItems];
@@ -295,9 +302,12 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool active) {
   uint64_t m = __ballot(active);
 #pragma unroll
   for (int b = 0; b < BITS; ++b) {
-    const bool bit = (d >> b) & 1u;
-    const uint64_t bb = __ballot(bit);
-    m &= bit ? bb : ~bb;
+    const uint32_t bit = (d >> b) & 1u;
+    const uint64_t bb = __ballot(bit != 0u);
+    // lanes with the bit set keep the ballot, the others its complement:
+    // bb ^ (bit - 1) in each 32-bit half, no per-lane 64-bit select
+    const uint32_t flip = bit - 1u;
+    m &= ((uint64_t)((uint32_t)(bb >> 32) ^ flip) << 32) | ((uint32_t)bb ^ flip);
   }
   return m;
 }
@@ -324,10 +334,15 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys,
   const int part = xcd_swizzle(blockIdx.x, nblocks);
   const int64_t base = (int64_t)part * kSortTile;
   uint32_t* mine = h[t & (COPIES - 1)];
-#pragma unroll 4
-  for (int j = 0; j < kSortItems; ++j) {
-    const int64_t idx = base + j * 256 + t;
-    if (idx < n) atomicAdd(&mine[digit_of<BITS>(keys[idx], shift)], 1u);
+  if (base < n) {
+    // all loads first (indices clamped into the list), then the counting:
+    // a load-use pair per item would serialise the memory latencies
+    K kk[kSortItems];
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) kk[j] = keys[min(base + j * 256 + t, n - 1)];
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j)
+      if (base + j * 256 + t < n) atomicAdd(&mine[digit_of<BITS>(kk[j], shift)], 1u);
   }
   __syncthreads();
   if (t < RADIX) {
@@ -395,17 +410,22 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
   const int64_t n = clamp_n(n_dev, cap);
   const int part = xcd_swizzle(blockIdx.x, nblocks);
   const int64_t bbase = (int64_t)part * kSortTile;
+  if (bbase >= n) return;  // whole block beyond the list: no counts, nothing to write
   const int64_t base = bbase + w * (64 * kSortItems);
   const uint64_t lt = lanemask_lt();
   K key[kSortItems];
   uint32_t val[kSortItems];
   uint32_t lofs[kSortItems];
+  // all loads first (indices clamped into the list), then the ranking
 #pragma unroll
   for (int j = 0; j < kSortItems; ++j) {
-    const int64_t idx = base + j * 64 + lane;
-    const bool ok = idx < n;
-    key[j] = ok ? kin[idx] : (K)0;
-    val[j] = ok ? vin[idx] : 0u;
+    const int64_t idx = min(base + j * 64 + lane, n - 1);
+    key[j] = kin[idx];
+    val[j] = vin[idx];
+  }
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const bool ok = base + j * 64 + lane < n;
     const uint32_t d = digit_of<BITS>(key[j], shift);
     const uint64_t m = match_digit<BITS>(d, ok);
     const uint32_t before = wcnt[w][d];
@@ -550,25 +570,32 @@ __device__ __forceinline__ void gen_block_pairs(const uint4* __restrict__ packed
       m[i] = run;
     }
     const uint32_t pre = block_excl_max256(run, s_wave);
-    int kprev = -1;
-    uint32_t w = 1, xx = 0, yy = 0;
+    // Only the thread's first slot can fall inside a record; every record
+    // that starts later starts at a slot of its own with local index 0, so
+    // one division per thread places the first slot and the rest steps
+    // through the rects (branch-free).
+    int kprev = (int)max(pre, m[0]) - 1;
+    uint32_t xx = 0, yy = 0;
+    {
+      const uint32_t w0 = S.wtx[kprev] & 0xffffu;
+      const uint32_t local = lo + (uint32_t)(16 * t) - S.off[kprev];
+      yy = local / w0;
+      xx = local - yy * w0;
+    }
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int s = 16 * t + i;
-      if (s < nslots) {
-        const int k = (int)max(pre, m[i]) - 1;
-        if (k != kprev) {
-          w = S.wtx[k] & 0xffffu;
-          const uint32_t local = lo + (uint32_t)s - S.off[k];
-          yy = local / w;
-          xx = local - yy * w;
-          kprev = k;
-        } else if (++xx == w) {
-          xx = 0;
-          ++yy;
-        }
-        emit(s, tile_of_pair(k, yy, xx), S.rec[k]);
+      const int k = (int)max(pre, m[i]) - 1;
+      if (i > 0) {
+        const uint32_t w = S.wtx[k] & 0xffffu;
+        const bool nk = k != kprev;
+        const uint32_t x1 = xx + 1u;
+        const bool wrap = x1 == w;
+        xx = nk || wrap ? 0u : x1;
+        yy = nk ? 0u : (wrap ? yy + 1u : yy);
+        kprev = k;
       }
+      if (s < nslots) emit(s, tile_of_pair(k, yy, xx), S.rec[k]);
     }
     return;
   }
