@@ -104,6 +104,8 @@ def main():
     g2 = torch.empty((scene.n, 9), dtype=torch.float32, device=dev)
     grads = [scene.zeros_like_grads()]
     ws = R.Workspace()
+    loss_buf = torch.empty(1, dtype=torch.float32, device=dev)
+    dimg_buf = torch.empty(3 * H * W, dtype=torch.float32, device=dev)
 
     # A plain copy of known size (256 MiB read + 256 MiB written), so that
     # hardware byte counters of a profiled run can be calibrated against it.
@@ -141,13 +143,11 @@ def main():
         ev[2].record()
         frame = R.xpr_render_fwd(v, cfg, proj, bins, out=frame, tile_work=tw)
         ev[3].record()
-        img = v.image(frame.image, 0)
-        diff = img - targets[k % len(views)]
-        loss = diff.abs().mean()
-        dimg = torch.sign(diff) / diff.numel()
+        img = v.image(frame.image, 0).reshape(-1)
+        loss, dimg = R.xpr_l1_loss(img, targets[k % len(views)].reshape(-1), loss=loss_buf,
+                                   dimage=dimg_buf)
         ev[4].record()
-        R.xpr_render_bwd(v, cfg, proj, bins, frame, dimg.reshape(-1), params=False, grad2d=g2,
-                         ws=ws)
+        R.xpr_render_bwd(v, cfg, proj, bins, frame, dimg, params=False, grad2d=g2, ws=ws)
         ev[5].record()
         R.xpr_project_bwd(v, cfg, proj, g2, grads=grads)
         ev[6].record()

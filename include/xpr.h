@@ -258,6 +258,18 @@ xpr_status xpr_project_bwd(const xpr_views* views, const xpr_config* cfg, const 
                            const float* grad2d, const xpr_scene_grad* grads, int32_t accumulate,
                            hipStream_t stream);
 
+/* The training loss of the benchmarked step (the L1 photometric term of the
+ * 3DGS objective, Background section): over n colour values (3HW for one
+ * view, image and target laid out alike),
+ *   *loss = (1/n) sum |image - target|,
+ *   dL_dimage = sign(image - target) / n   (sign(0) = 0),
+ * ready to pass to xpr_render_bwd. loss is one device float (overwritten);
+ * all pointers are device memory, 4-byte aligned (16-byte alignment of all
+ * three arrays takes a vector path). The sum uses float atomics across
+ * workgroups, so its last bits vary from run to run; dL_dimage is exact. */
+xpr_status xpr_l1_loss(const float* image, const float* target, int64_t n, float* loss,
+                       float* dL_dimage, hipStream_t stream);
+
 /* Message of the last non-OK status on this thread ("" if none). */
 const char* xpr_last_error(void);
 

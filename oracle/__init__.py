@@ -212,3 +212,12 @@ def backward(scene, cam, cfg: OracleConfig, dimg, state=None):
     g = project_bwd(scene, cam, cfg, g9)
     g["grad9"] = g9
     return g
+
+
+def l1_loss(image: np.ndarray, target: np.ndarray):
+    """The photometric L1 term of the 3DGS training objective (Background
+    section), in float64: (mean |image - target|, sign(image - target) / n)
+    with sign(0) = 0 and n the number of values."""
+    d = np.asarray(image, np.float64) - np.asarray(target, np.float64)
+    n = d.size
+    return float(np.abs(d).sum() / n), np.sign(d) / n

@@ -33,6 +33,8 @@ hipError_t launch_render_bwd(const Batch& B, int lds_batch, int ppt, bool persis
                              int32_t* order, const float* dimg, const float* Tfin,
                              const int32_t* ncon, float* grad2d, hipStream_t st);
 hipError_t fill_zero_f32(float* p, int64_t n, hipStream_t st);
+hipError_t launch_l1_loss(const float* img, const float* tgt, int64_t n, float* loss,
+                          float* dimg, hipStream_t st);
 
 static thread_local char g_err[512];
 
@@ -402,6 +404,18 @@ xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const x
                             n_contrib, g2, stream));
   if (grads)
     XPR_HIP(launch_project_bwd(B, S.max_n, g2, proj->tiles_touched, G, accumulate ? 1 : 0, stream));
+  return XPR_OK;
+}
+
+xpr_status xpr_l1_loss(const float* image, const float* target, int64_t n, float* loss,
+                       float* dL_dimage, hipStream_t stream) {
+  g_err[0] = 0;
+  XPR_CHECK(n >= 0, "n < 0");
+  XPR_CHECK(loss && aligned(loss, 4), "loss NULL or misaligned");
+  XPR_CHECK(n == 0 || (image && target && dL_dimage), "image, target or dL_dimage is NULL");
+  XPR_CHECK(n == 0 || (aligned(image, 4) && aligned(target, 4) && aligned(dL_dimage, 4)),
+            "image, target or dL_dimage misaligned");
+  XPR_HIP(launch_l1_loss(image, target, n, loss, dL_dimage, stream));
   return XPR_OK;
 }
 

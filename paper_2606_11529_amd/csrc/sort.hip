@@ -78,8 +78,9 @@ __device__ __forceinline__ uint64_t block_sum256_u64(uint64_t x, uint64_t* s_wav
 }
 
 // ---------------------------------------------------------------------------
-// Device-wide exclusive scan of n uint32 values (n known on the host),
-// three kernels: block sums, scan of block sums, block scans + offset.
+// Device-wide exclusive scan of n uint32 values (n known on the host), two
+// kernels: block sums, then block scans, each block adding the sum of the
+// preceding block sums (the grand total, if wanted, from the last block).
 
 struct LoadArray {
   const uint32_t* p;
@@ -106,47 +107,14 @@ __global__ __launch_bounds__(256) void k_scan_reduce(L load, int64_t n, uint64_t
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-// Single block: in-place exclusive scan of the block sums; the grand total
-// goes to *total (if not null).
-__global__ __launch_bounds__(1024) void k_scan_partials(uint64_t* partials, int64_t nparts,
-                                                        int64_t* total) {
-  __shared__ uint64_t s_wave[16];
-  __shared__ uint64_t s_carry;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (threadIdx.x == 0) s_carry = 0;
-  __syncthreads();
-  for (int64_t base = 0; base < nparts; base += 1024) {
-    const int64_t i = base + threadIdx.x;
-    const uint64_t x = i < nparts ? partials[i] : 0;
-    uint64_t inc = x;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint64_t y = __shfl_up(inc, d, 64);
-      if (lane >= d) inc += y;
-    }
-    if (lane == 63) s_wave[w] = inc;
-    __syncthreads();
-    uint64_t off = s_carry;
-    for (int k = 0; k < w; ++k) off += s_wave[k];
-    if (i < nparts) partials[i] = off + inc - x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      uint64_t t = 0;
-      for (int k = 0; k < 16; ++k) t += s_wave[k];
-      s_carry += t;
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0 && total) *total = (int64_t)s_carry;
-}
-
 template <class L>
 __global__ __launch_bounds__(256) void k_scan_down(L load, int64_t n, const uint64_t* partials,
-                                                   uint32_t* out) {
+                                                   uint32_t* out, int64_t* total) {
   // 16 items per thread, staged through LDS with one pad word per 16 so the
   // per-thread contiguous reads are free of bank conflicts.
   __shared__ uint32_t s[kScanTile + kScanTile / 16];
   __shared__ uint32_t s_wave[4];
+  __shared__ uint64_t s_wave64[4];
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
   const int t = threadIdx.x;
   {
@@ -168,7 +136,14 @@ __global__ __launch_bounds__(256) void k_scan_down(L load, int64_t n, const uint
     run += x[j];
   }
   uint32_t excl = block_excl_scan256(run, s_wave, nullptr);
-  const uint32_t boff = (uint32_t)partials[blockIdx.x];
+  // this block's offset: the sum of the preceding blocks' totals (a few
+  // hundred at most), summed here instead of in a separate scan launch
+  uint64_t pre = 0;
+  for (int64_t b = t; b < (int64_t)blockIdx.x; b += 256) pre += partials[b];
+  const uint64_t boff64 = block_sum256_u64(pre, s_wave64);
+  if (total && t == 0 && blockIdx.x == gridDim.x - 1)
+    *total = (int64_t)(boff64 + partials[blockIdx.x]);
+  const uint32_t boff = (uint32_t)boff64;
 #pragma unroll
   for (int j = 0; j < kScanItems; ++j) {
     const uint32_t v = x[j];
@@ -191,8 +166,7 @@ static hipError_t device_scan(L load, int64_t n, uint32_t* out, uint64_t* partia
   }
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
   hipLaunchKernelGGL(k_scan_reduce<L>, dim3(nb), dim3(256), 0, st, load, n, partials);
-  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, partials, nb, total);
-  hipLaunchKernelGGL(k_scan_down<L>, dim3(nb), dim3(256), 0, st, load, n, partials, out);
+  hipLaunchKernelGGL(k_scan_down<L>, dim3(nb), dim3(256), 0, st, load, n, partials, out, total);
   return hipGetLastError();
 }
 

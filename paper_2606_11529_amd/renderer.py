@@ -329,6 +329,25 @@ def xpr_project_bwd(views: Views, cfg: Config, proj: Projected, grad2d: torch.Te
     return grads
 
 
+def xpr_l1_loss(image: torch.Tensor, target: torch.Tensor,
+                loss: Optional[torch.Tensor] = None,
+                dimage: Optional[torch.Tensor] = None):
+    """L1 loss mean |image - target| (one device float) and its gradient
+    sign(image - target) / n, in one kernel pass; image and target are
+    contiguous float32 tensors of the same size."""
+    if image.dtype != torch.float32 or target.dtype != torch.float32:
+        raise TypeError("image and target must be float32")
+    if not (image.is_contiguous() and target.is_contiguous()) or image.numel() != target.numel():
+        raise ValueError("image and target must be contiguous and of equal size")
+    n = image.numel()
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=image.device)
+    if dimage is None:
+        dimage = torch.empty_like(image)
+    L.xpr_l1_loss(_ptr(image), _ptr(target), n, _ptr(loss), _ptr(dimage), _stream())
+    return loss, dimage
+
+
 def render(scene: Scene, cam, cfg: Config, want_keys: bool = False):
     """One view: returns (image [3,H,W], state dict)."""
     views = Views([scene], [cam], [0], cfg)
