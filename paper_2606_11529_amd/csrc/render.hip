@@ -50,15 +50,75 @@ __device__ __forceinline__ float power2(float dx, float dy, float4 a, float c) {
                    __fmaf_rn(a.w, __fmul_rn(dx, dy), __fmul_rn(c, __fmul_rn(dy, dy))));
 }
 
+// Per-wave record lists. A record can only pass its threshold test at
+// pixels inside a box around its centre: for a negative definite base-2
+// power P2 = A' dx^2 + B' dx dy + C' dy^2, P2 >= thr (thr < 0) implies
+//   dx^2 <= thr / (A' - B'^2 / (4 C')),   dy^2 <= thr / (C' - B'^2 / (4 A')).
+// Each staged record gets a mask of the waves whose pixel rectangle meets
+// that box (computed in FP64 and widened by 1% + 0.05 px, far beyond the
+// rounding of the FP32 power; near-singular conics get every wave), and each
+// wave walks only its own records, in list order. The per-lane threshold
+// test still decides every pair, so this only skips (wave, record)
+// iterations in which no lane could pass.
+template <int BATCH, int NW>
+struct Stage {
+  float4 s0[BATCH];
+  float4 s1[BATCH];
+  float2 s2[BATCH];
+  uint8_t mask[BATCH];
+  uint16_t list[NW][BATCH];
+  int32_t rec[BATCH];
+};
+
+__device__ __forceinline__ uint32_t wave_mask(float4 a, float4 b, int x0, int x1, int y0, int rpw,
+                                              int nw) {
+  const uint32_t all = (1u << nw) - 1u;
+  const double A = a.z, Bc = a.w, C = b.x, thr = b.y;
+  if (thr >= 0.0) return 0u;  // o < alpha_min: no pixel can pass
+  if (!(thr < 0.0) || !(A < 0.0) || !(C < 0.0)) return all;
+  const double det4 = 4.0 * A * C - Bc * Bc;
+  if (!(det4 > 1e-3 * 4.0 * A * C)) return all;
+  const double ex = sqrt(thr * 4.0 * C / det4) * 1.01 + 0.05;
+  const double ey = sqrt(thr * 4.0 * A / det4) * 1.01 + 0.05;
+  if (!(a.x + ex >= (double)x0 && a.x - ex <= (double)x1)) return 0u;
+  uint32_t m = 0u;
+  for (int w = 0; w < nw; ++w) {
+    const double r0 = (double)(y0 + w * rpw), r1 = r0 + (double)(rpw - 1);
+    if (a.y + ey >= r0 && a.y - ey <= r1) m |= 1u << w;
+  }
+  return m;
+}
+
+// Builds this wave's ordered list of the staged records [0, nb) whose mask
+// has the wave's bit (and, for the backward, whose list position is within
+// the wave's walk); returns its length.
+template <int BATCH, int NW>
+__device__ __forceinline__ int build_wave_list(Stage<BATCH, NW>& S, int nb, int wv,
+                                               int max_k) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = lanemask_lt();
+  int cnt = 0;
+  for (int i0 = 0; i0 < nb; i0 += 64) {
+    const int k = i0 + lane;
+    const bool hit = k < nb && k <= max_k && ((S.mask[k] >> wv) & 1u);
+    const uint64_t m = __ballot(hit);
+    if (hit) S.list[wv][cnt + __popcll(m & lt)] = (uint16_t)k;
+    cnt += __popcll(m);
+  }
+  return cnt;
+}
+
 template <int TW, int TH, int BATCH, int PPT>
 __device__ __forceinline__ void fwd_tile(const Batch& B, int g, const float4* __restrict__ splat,
                                          const int32_t* __restrict__ vals,
                                          const int2* __restrict__ ranges,
                                          float* __restrict__ image, float* __restrict__ Tfin,
                                          int32_t* __restrict__ ncon,
-                                         int32_t* __restrict__ tile_work, float4* s0, float4* s1,
-                                         float2* s2) {
+                                         int32_t* __restrict__ tile_work,
+                                         Stage<BATCH, (TW * TH / PPT + 63) / 64>& S) {
   constexpr int NT = TW * TH / PPT;
+  constexpr int NW = (NT + 63) / 64;
+  constexpr int RPW = 64 * PPT / TW;  // pixel rows per wave
   const ViewDev& V = B.v[view_of_tile(B, g)];
   const int lt = g - V.tile_off;
   const int ty = lt / V.tiles_x, tx = lt - ty * V.tiles_x;
@@ -87,7 +147,11 @@ __device__ __forceinline__ void fwd_tile(const Batch& B, int g, const float4* __
     walked = min(BATCH, rg.y - base) + (base - rg.x);
     for (int k = threadIdx.x; k < BATCH; k += NT) {
       const int idx = base + k;
-      if (idx < rg.y) stage_record(splat, (size_t)vals[idx], amin, s0[k], s1[k], s2[k]);
+      if (idx < rg.y) {
+        stage_record(splat, (size_t)vals[idx], amin, S.s0[k], S.s1[k], S.s2[k]);
+        S.mask[k] = (uint8_t)wave_mask(S.s0[k], S.s1[k], tx * TW, tx * TW + TW - 1, ty * TH, RPW,
+                                       NW);
+      }
     }
     __syncthreads();
     // The walk over the batch is branch-free per lane: a lane's decisions
@@ -98,15 +162,19 @@ __device__ __forceinline__ void fwd_tile(const Batch& B, int g, const float4* __
     // than the vector unit. A finished pixel adds +inf to every record's
     // threshold (a live one adds 0), so it never passes the test again.
     const int nb = min(BATCH, rg.y - base);
-    for (int k0 = 0; k0 < nb; k0 += 8) {
+    const int wv = threadIdx.x >> 6;
+    const int cnt = build_wave_list(S, nb, wv, BATCH);
+    __syncthreads();
+    for (int i0 = 0; i0 < cnt; i0 += 8) {
       bool alive = false;
 #pragma unroll
       for (int j = 0; j < PPT; ++j) alive = alive || lift[j] == 0.f;
       if (__ballot(alive) == 0) break;
-      const int kend = min(k0 + 8, nb);
-      for (int k = k0; k < kend; ++k) {
-        const float4 a = s0[k];
-        const float4 b = s1[k];
+      const int iend = min(i0 + 8, cnt);
+      for (int i = i0; i < iend; ++i) {
+        const int k = S.list[wv][i];
+        const float4 a = S.s0[k];
+        const float4 b = S.s1[k];
         const float dx = __fsub_rn(fpx, a.x);
         float P2[PPT];
         bool anyp = false;
@@ -116,7 +184,7 @@ __device__ __forceinline__ void fwd_tile(const Batch& B, int g, const float4* __
           anyp = anyp || P2[j] >= b.y + lift[j];
         }
         if (__ballot(anyp) == 0) continue;
-        const float2 gb = s2[k];
+        const float2 gb = S.s2[k];
         const int idx = base + k - rg.x + 1;
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
@@ -170,19 +238,16 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_render_fwd(
     const int2* __restrict__ ranges, float* __restrict__ image, float* __restrict__ Tfin,
     int32_t* __restrict__ ncon, int32_t* __restrict__ tile_work, const int32_t* order,
     int32_t* qhead) {
-  __shared__ float4 s0[BATCH];
-  __shared__ float4 s1[BATCH];
-  __shared__ float2 s2[BATCH];
+  __shared__ Stage<BATCH, (TW * TH / PPT + 63) / 64> S;
   if (!PERSIST) {
     const int g = order ? order[blockIdx.x] : (int)blockIdx.x;
-    fwd_tile<TW, TH, BATCH, PPT>(B, g, splat, vals, ranges, image, Tfin, ncon, tile_work, s0, s1,
-                                 s2);
+    fwd_tile<TW, TH, BATCH, PPT>(B, g, splat, vals, ranges, image, Tfin, ncon, tile_work, S);
     return;
   }
   __shared__ int s_next;
   for (int q = next_tile(&s_next, qhead); q < B.total_tiles; q = next_tile(&s_next, qhead))
     fwd_tile<TW, TH, BATCH, PPT>(B, order[q], splat, vals, ranges, image, Tfin, ncon, tile_work,
-                                 s0, s1, s2);
+                                 S);
 }
 
 // Backward of the compositing. Each pixel walks its list in reverse from
@@ -256,9 +321,12 @@ __device__ __forceinline__ void bwd_tile(const Batch& B, int g, const float4* __
                                          const float* __restrict__ dimg,
                                          const float* __restrict__ Tfin,
                                          const int32_t* __restrict__ ncon,
-                                         float* __restrict__ grad2d, float4* s0, float4* s1,
-                                         float2* s2, int32_t* srec, int32_t* s_maxlast_p) {
+                                         float* __restrict__ grad2d,
+                                         Stage<BATCH, (TW * TH / PPT + 63) / 64>& S,
+                                         int32_t* s_maxlast_p) {
   constexpr int NT = TW * TH / PPT;
+  constexpr int NW = (NT + 63) / 64;
+  constexpr int RPW = 64 * PPT / TW;  // pixel rows per wave
   int32_t& s_maxlast = *s_maxlast_p;
   const ViewDev& V = B.v[view_of_tile(B, g)];
   const int lt = g - V.tile_off;
@@ -309,8 +377,8 @@ __device__ __forceinline__ void bwd_tile(const Batch& B, int g, const float4* __
     for (int i = 0; i < 9; ++i) g[i] = 0.f;
     const int pos = lo + kk - rg.x + 1;
     if (__ballot(pos <= mylast) == 0) return false;
-    const float4 a = s0[kk];
-    const float4 b = s1[kk];
+    const float4 a = S.s0[kk];
+    const float4 b = S.s1[kk];
     const float dx = __fsub_rn(fpx, a.x);
     float P2[PPT], dy[PPT];
     bool anyp = false;
@@ -323,7 +391,7 @@ __device__ __forceinline__ void bwd_tile(const Batch& B, int g, const float4* __
       P2[j] = P2[j] >= thr ? P2[j] : __builtin_inff();  // inf: not in play
     }
     if (__ballot(anyp) == 0) return false;
-    const float2 c = s2[kk];
+    const float2 c = S.s2[kk];
     const float cr = b.w, cg = c.x, cb = c.y;
     bool any = false;
 #pragma unroll
@@ -357,29 +425,39 @@ __device__ __forceinline__ void bwd_tile(const Batch& B, int g, const float4* __
     }
     return __ballot(any) != 0;
   };
+  // the last list position any pixel of this wave blended
+  int wlast = mylast;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) wlast = max(wlast, __shfl_xor(wlast, o, 64));
+  const int wv = threadIdx.x >> 6;
   for (int hi = end; hi > rg.x; hi -= BATCH) {
     lo = max(rg.x, hi - BATCH);
     __syncthreads();
     for (int k = threadIdx.x; k < hi - lo; k += NT) {
       const int r = vals[lo + k];
-      srec[k] = r;
-      stage_record(splat, (size_t)r, amin, s0[k], s1[k], s2[k]);
+      S.rec[k] = r;
+      stage_record(splat, (size_t)r, amin, S.s0[k], S.s1[k], S.s2[k]);
+      S.mask[k] = (uint8_t)wave_mask(S.s0[k], S.s1[k], tx * TW, tx * TW + TW - 1, ty * TH, RPW,
+                                     NW);
     }
     __syncthreads();
-    // Records are taken two at a time (k, then k - 1: the reverse order
-    // the recovery of T needs) and their 2 x 9 per-lane sums reduced over
-    // the wave together (reduce_pair).
-    for (int k = hi - lo - 1; k >= 0; k -= 2) {
+    const int cnt = build_wave_list(S, hi - lo, wv, wlast + rg.x - lo - 1);
+    __syncthreads();
+    // The wave's records, last first, two at a time (the reverse order the
+    // recovery of T needs); their 2 x 9 per-lane sums are reduced over the
+    // wave together (reduce_pair).
+    for (int i = cnt - 1; i >= 0; i -= 2) {
+      const int kx = S.list[wv][i];
+      const int ky = i >= 1 ? S.list[wv][i - 1] : kx;
       float X[9], Y[9];
-      const bool ax = contrib(k, X);
-      const bool ay = k >= 1 && contrib(k - 1, Y);
+      const bool ax = contrib(kx, X);
+      const bool ay = i >= 1 && contrib(ky, Y);
       if (!ax && !ay) continue;
       if (!ay) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) Y[i] = 0.f;
+        for (int q = 0; q < 9; ++q) Y[q] = 0.f;
       }
-      reduce_pair(X, Y, ax, ay, grad2d + 9 * (size_t)srec[k],
-                  grad2d + 9 * (size_t)srec[k >= 1 ? k - 1 : k]);
+      reduce_pair(X, Y, ax, ay, grad2d + 9 * (size_t)S.rec[kx], grad2d + 9 * (size_t)S.rec[ky]);
     }
   }
 }
@@ -390,21 +468,18 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_render_bwd(
     const int2* __restrict__ ranges, const float* __restrict__ dimg,
     const float* __restrict__ Tfin, const int32_t* __restrict__ ncon,
     float* __restrict__ grad2d, const int32_t* order, int32_t* qhead) {
-  __shared__ float4 s0[BATCH];
-  __shared__ float4 s1[BATCH];
-  __shared__ float2 s2[BATCH];
-  __shared__ int32_t srec[BATCH];
+  __shared__ Stage<BATCH, (TW * TH / PPT + 63) / 64> S;
   __shared__ int32_t s_maxlast;
   if (!PERSIST) {
     const int g = order ? order[blockIdx.x] : (int)blockIdx.x;
-    bwd_tile<TW, TH, BATCH, PPT>(B, g, splat, vals, ranges, dimg, Tfin, ncon, grad2d, s0, s1, s2,
-                                 srec, &s_maxlast);
+    bwd_tile<TW, TH, BATCH, PPT>(B, g, splat, vals, ranges, dimg, Tfin, ncon, grad2d, S,
+                                 &s_maxlast);
     return;
   }
   __shared__ int s_next;
   for (int q = next_tile(&s_next, qhead); q < B.total_tiles; q = next_tile(&s_next, qhead))
-    bwd_tile<TW, TH, BATCH, PPT>(B, order[q], splat, vals, ranges, dimg, Tfin, ncon, grad2d, s0,
-                                 s1, s2, srec, &s_maxlast);
+    bwd_tile<TW, TH, BATCH, PPT>(B, order[q], splat, vals, ranges, dimg, Tfin, ncon, grad2d, S,
+                                 &s_maxlast);
 }
 
 // Launchers ------------------------------------------------------------------
