@@ -62,6 +62,9 @@ typedef enum {
 /* Sort strategies of xpr_bin_sort; both produce the identical list. */
 #define XPR_SORT_PRESORT 0 /* sort Gaussians by depth, then pairs by tile */
 #define XPR_SORT_FULL 1    /* one radix sort of 64-bit (tile, depth) keys */
+#define XPR_SORT_BANDS 2   /* depth presort, then records binned per band of 16 tiles and
+                              placed per tile by counting (same output; falls back to
+                              XPR_SORT_PRESORT beyond 65536 bands or 2^23 records) */
 
 /* Pinhole camera, world -> camera x_c = R x_w + t (R row-major), camera axes
  * x right, y down, z forward. (cx, cy) is the principal point in continuous
@@ -86,7 +89,7 @@ typedef struct xpr_config {
   float z_near;           /* cull when camera-space z <= z_near (> 0; 0.2) */
   float fov_clip;         /* Jacobian clamp at fov_clip * W / (2 fx) (1.3; 0 = off) */
   float bg[3];            /* background colour (0, 0, 0) */
-  int32_t sort_mode;      /* XPR_SORT_PRESORT or XPR_SORT_FULL */
+  int32_t sort_mode;      /* XPR_SORT_PRESORT, XPR_SORT_FULL or XPR_SORT_BANDS */
   int32_t no_sync;        /* 1: never read back to the host (graph capture) */
   int32_t fwd_ppt;        /* pixels per thread in the forward: 1, 2 or 4 (16x16 tiles) */
   int32_t bwd_ppt;        /* pixels per thread in the backward: 1, 2 or 4 (16x16 tiles) */

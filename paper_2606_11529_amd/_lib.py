@@ -19,6 +19,7 @@ XPR_ERR_HIP = 3
 XPR_ERR_UNSUPPORTED = 4
 XPR_SORT_PRESORT = 0
 XPR_SORT_FULL = 1
+XPR_SORT_BANDS = 2
 XPR_MAX_VIEWS = 32
 XPR_MAX_SCENES = 8
 

@@ -27,7 +27,7 @@ from typing import Callable, Dict, Iterable, List, Optional, Sequence, Tuple
 
 LDS_BATCHES = (64, 128, 256, 512)
 PPTS = (1, 2, 4)
-SORTS = ("presort", "full")
+SORTS = ("bands", "presort", "full")
 
 
 def pick_best(timings: Dict[tuple, Sequence[float]], tie: float = 0.02) -> tuple:

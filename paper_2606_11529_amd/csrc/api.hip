@@ -87,7 +87,8 @@ static xpr_status check_config(const xpr_config* c) {
   XPR_CHECK(c->fov_clip >= 0.f && std::isfinite(c->fov_clip), "fov_clip must be >= 0");
   XPR_CHECK(std::isfinite(c->bg[0]) && std::isfinite(c->bg[1]) && std::isfinite(c->bg[2]),
             "bg must be finite");
-  XPR_CHECK(c->sort_mode == XPR_SORT_PRESORT || c->sort_mode == XPR_SORT_FULL,
+  XPR_CHECK(c->sort_mode == XPR_SORT_PRESORT || c->sort_mode == XPR_SORT_FULL ||
+                c->sort_mode == XPR_SORT_BANDS,
             "sort_mode %d unknown", c->sort_mode);
   XPR_CHECK(c->fwd_ppt == 1 || c->fwd_ppt == 2 || c->fwd_ppt == 4, "fwd_ppt %d not in {1,2,4}",
             c->fwd_ppt);

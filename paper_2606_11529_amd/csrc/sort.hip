@@ -319,11 +319,11 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys,
       if (base + j * 256 + t < n) atomicAdd(&mine[digit_of<BITS>(kk[j], shift)], 1u);
   }
   __syncthreads();
-  if (t < RADIX) {
+  for (int d = t; d < RADIX; d += 256) {
     uint32_t c = 0;
 #pragma unroll
-    for (int k = 0; k < COPIES; ++k) c += h[k][t];
-    counts[(int64_t)t * nblocks + part] = c;
+    for (int k = 0; k < COPIES; ++k) c += h[k][d];
+    counts[(int64_t)d * nblocks + part] = c;
   }
 }
 
@@ -479,12 +479,48 @@ __global__ void k_pair_records(Batch B, const short4* __restrict__ rect,
   if (e == n) first[(n + kSortTile - 1) / kSortTile] = (uint32_t)j;
 }
 
-// Up to 256 packed records of a sort block, staged in LDS.
+// Up to 256 packed records of a sort block, staged in LDS: the item offset
+// of each record and its three payload words.
 struct RecChunk {
   uint32_t off[257];
-  uint32_t rec[256];
-  uint32_t base[256];
-  uint32_t wtx[256];
+  uint32_t a[256];
+  uint32_t b[256];
+  uint32_t c[256];
+};
+
+// What a packed record generates. Items of a record form a grid of
+// width(k) columns in row-major order; item (yy, xx) gets a sort key and a
+// value. j is the record's depth-order position.
+//
+// Tile pairs: packed = (pair offset, record id, tile id of the rect's top-
+// left corner, rect width | tiles_x << 16); key = tile id, value = record.
+struct PairItems {
+  static __device__ __forceinline__ uint32_t width(uint4 q) { return q.w & 0xffffu; }
+  static __device__ __forceinline__ void item(uint4 q, uint32_t, uint32_t yy, uint32_t xx,
+                                              uint32_t& key, uint32_t& val) {
+    key = q.z + yy * (q.w >> 16) + xx;
+    val = q.y;
+  }
+};
+
+// Band entries (one per tile row of the rect and band of kBandWidth tile
+// columns it touches): packed = (entry offset, band id of the first entry,
+// bands per rect row | bands per view row << 16, x0 | x1 << 16 with the
+// rect's tile columns [x0, x1)); key = band id, value = j | xlo << 23 |
+// (xhi - 1) << 27 with [xlo, xhi) the rect's columns inside the band.
+constexpr int kBandWidth = 16;
+
+struct BandItems {
+  static __device__ __forceinline__ uint32_t width(uint4 q) { return q.z & 0xffffu; }
+  static __device__ __forceinline__ void item(uint4 q, uint32_t j, uint32_t yy, uint32_t xx,
+                                              uint32_t& key, uint32_t& val) {
+    key = q.y + yy * (q.z >> 16) + xx;
+    const int x0 = (int)(q.w & 0xffffu), x1 = (int)(q.w >> 16);
+    const int b0 = ((x0 / kBandWidth) + (int)xx) * kBandWidth;
+    const uint32_t xlo = (uint32_t)max(x0 - b0, 0);
+    const uint32_t xhi = (uint32_t)min(x1 - b0, kBandWidth);
+    val = j | (xlo << 23) | ((xhi - 1u) << 27);
+  }
 };
 
 // LDS position of slot s in the pair staging arrays: one pad word per 16
@@ -493,18 +529,18 @@ struct RecChunk {
 __device__ __forceinline__ int spad(int s) { return s + (s >> 4); }
 constexpr int kSortTilePad = kSortTile + kSortTile / 16;
 
-// Calls emit(slot, tile, record) once for every pair of sort block `part`
-// (slot = pair index - part T; pairs at or beyond n are skipped). Tiles of a
-// record are its rect in row-major order. Must be called by all threads of
-// the block. `marks` is LDS scratch of kSortTilePad words.
+// Calls emit(slot, key, value) once for every item of sort block `part`
+// (slot = item index - part T; items at or beyond n are skipped); Items says
+// what a record's grid of items is. Must be called by all threads of the
+// block. `marks` is LDS scratch of kSortTilePad words.
 //
-// Common case (at most 256 records in the block): each record marks the
-// slot of its first pair, and a block-wide running maximum over the slots
-// gives every slot its record; thread t then handles slots 16t .. 16t + 15,
-// stepping through its record's rect and dividing only when the record
-// changes. Otherwise the records go through LDS 256 at a time and each pair
-// finds its record by binary search.
-template <class Emit>
+// Each record marks the slot of its first item, and a block-wide running
+// maximum over the slots gives every slot its record; thread t then handles
+// slots 16t .. 16t + 15, stepping through its record's grid and dividing
+// only for its first slot (every later record change starts a record at
+// its first item). A block holds at most T + 1 records; up to 256 are staged
+// in LDS, beyond that they are read from the packed array (L2-resident).
+template <class Items, class Emit>
 __device__ __forceinline__ void gen_block_pairs(const uint4* __restrict__ packed,
                                                 const uint32_t* __restrict__ first, int part,
                                                 int64_t n, RecChunk& S, uint32_t* marks,
@@ -514,101 +550,75 @@ __device__ __forceinline__ void gen_block_pairs(const uint4* __restrict__ packed
   const uint32_t hi = (uint32_t)min(n, (int64_t)lo + kSortTile);
   const int nslots = (int)(hi - lo);
   const uint32_t j0 = first[part], j1 = first[part + 1];
-  auto load_record = [&](uint32_t jj, int k) {
-    const uint4 q = packed[jj];
-    S.off[k] = q.x;
-    S.rec[k] = q.y;
-    S.base[k] = q.z;
-    S.wtx[k] = q.w;
-  };
-  auto tile_of_pair = [&](int k, uint32_t yy, uint32_t xx) -> uint32_t {
-    return S.base[k] + yy * (S.wtx[k] >> 16) + xx;
-  };
   const uint32_t nrec = j1 - j0 + 1;
-  if (nrec <= 256) {
-    if ((uint32_t)t < nrec) load_record(j0 + t, t);
-#pragma unroll
-    for (int i = 0; i < 16; ++i) marks[spad(16 * t + i)] = 0u;
-    __syncthreads();
-    if ((uint32_t)t < nrec) {
-      const uint32_t o = S.off[t];
-      const uint32_t s0 = (o > lo ? o : lo) - lo;
-      if (s0 < (uint32_t)nslots) marks[spad((int)s0)] = (uint32_t)t + 1u;
-    }
-    __syncthreads();
-    uint32_t m[16];
-    uint32_t run = 0;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      run = max(run, marks[spad(16 * t + i)]);
-      m[i] = run;
-    }
-    const uint32_t pre = block_excl_max256(run, s_wave);
-    // Only the thread's first slot can fall inside a record; every record
-    // that starts later starts at a slot of its own with local index 0, so
-    // one division per thread places the first slot and the rest steps
-    // through the rects (branch-free).
-    int kprev = (int)max(pre, m[0]) - 1;
-    uint32_t xx = 0, yy = 0;
-    {
-      const uint32_t w0 = S.wtx[kprev] & 0xffffu;
-      const uint32_t local = lo + (uint32_t)(16 * t) - S.off[kprev];
-      yy = local / w0;
-      xx = local - yy * w0;
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int s = 16 * t + i;
-      const int k = (int)max(pre, m[i]) - 1;
-      if (i > 0) {
-        const uint32_t w = S.wtx[k] & 0xffffu;
-        const bool nk = k != kprev;
-        const uint32_t x1 = xx + 1u;
-        const bool wrap = x1 == w;
-        xx = nk || wrap ? 0u : x1;
-        yy = nk ? 0u : (wrap ? yy + 1u : yy);
-        kprev = k;
-      }
-      if (s < nslots) emit(s, tile_of_pair(k, yy, xx), S.rec[k]);
-    }
-    return;
+  const bool in_lds = nrec <= 256u;
+  if (in_lds && (uint32_t)t < nrec) {
+    const uint4 q = packed[j0 + t];
+    S.off[t] = q.x;
+    S.a[t] = q.y;
+    S.b[t] = q.z;
+    S.c[t] = q.w;
   }
-  for (uint32_t c0 = j0; c0 <= j1; c0 += 256) {
-    const uint32_t clast = min(j1, c0 + 255u);
-    __syncthreads();  // the previous chunk is consumed
-    const uint32_t jj = c0 + t;
-    if (jj <= clast) load_record(jj, t);
-    // pairs of this chunk end where the next chunk's first record starts
-    // (the block's end for the last chunk)
-    if (t == 0) S.off[256] = clast < j1 ? packed[clast + 1].x : hi;
-    __syncthreads();
-    if (t > (int)(clast - c0)) S.off[t] = S.off[256];
-    __syncthreads();
-    const uint32_t beg = max(S.off[0], lo), end = min(S.off[256], hi);
-    for (uint32_t p = beg + t; p < end; p += 256) {
-      // last k with off[k] <= p
-      int a = 0, z = 255;
-      while (a < z) {
-        const int mid = (a + z + 1) >> 1;
-        if (S.off[mid] <= p) a = mid; else z = mid - 1;
-      }
-      const uint32_t local = p - S.off[a];
-      const uint32_t w = S.wtx[a] & 0xffffu;
-      const uint32_t yy = local / w;
-      emit((int)(p - lo), tile_of_pair(a, yy, local - yy * w), S.rec[a]);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) marks[spad(16 * t + i)] = 0u;
+  __syncthreads();
+  for (uint32_t k = (uint32_t)t; k < nrec; k += 256u) {
+    const uint32_t o = in_lds ? S.off[k] : packed[j0 + k].x;
+    const uint32_t s0 = (o > lo ? o : lo) - lo;
+    if (s0 < (uint32_t)nslots) marks[spad((int)s0)] = k + 1u;
+  }
+  __syncthreads();
+  uint32_t m[16];
+  uint32_t run = 0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    run = max(run, marks[spad(16 * t + i)]);
+    m[i] = run;
+  }
+  const uint32_t pre = block_excl_max256(run, s_wave);
+  auto rec = [&](int k) -> uint4 {
+    return in_lds ? make_uint4(S.off[k], S.a[k], S.b[k], S.c[k]) : packed[j0 + (uint32_t)k];
+  };
+  int kprev = (int)max(pre, m[0]) - 1;
+  uint4 q = rec(kprev);
+  uint32_t xx = 0, yy = 0;
+  {
+    const uint32_t w0 = Items::width(q);
+    const uint32_t local = lo + (uint32_t)(16 * t) - q.x;
+    yy = local / w0;
+    xx = local - yy * w0;
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int s = 16 * t + i;
+    const int k = (int)max(pre, m[i]) - 1;
+    if (i > 0) {
+      const bool nk = k != kprev;
+      if (nk) q = rec(k);
+      const uint32_t w = Items::width(q);
+      const uint32_t x1 = xx + 1u;
+      const bool wrap = x1 == w;
+      xx = nk || wrap ? 0u : x1;
+      yy = nk ? 0u : (wrap ? yy + 1u : yy);
+      kprev = k;
+    }
+    if (s < nslots) {
+      uint32_t key, val;
+      Items::item(q, j0 + (uint32_t)k, yy, xx, key, val);
+      emit(s, key, val);
     }
   }
 }
 
 // First-pass histogram (digit = low BITS bits of the tile id) of each sort
 // block, from regenerated pairs; counts digit-major like k_radix_hist.
-template <int BITS>
+template <int BITS, class Items>
 __global__ __launch_bounds__(256) void k_pair_hist(const uint4* __restrict__ packed,
                                                    const uint32_t* __restrict__ first,
                                                    const int64_t* n_isect, int64_t cap,
                                                    uint32_t* __restrict__ counts, int nblocks) {
   constexpr int RADIX = 1 << BITS;
-  constexpr int COPIES = 8;
+  constexpr int COPIES = RADIX <= 256 ? 8 : 2;
   __shared__ RecChunk S;
   __shared__ uint32_t marks[kSortTilePad];
   __shared__ uint32_t s_wave[4];
@@ -619,23 +629,23 @@ __global__ __launch_bounds__(256) void k_pair_hist(const uint4* __restrict__ pac
   const int part = xcd_swizzle(blockIdx.x, nblocks);
   uint32_t* mine = h[t & (COPIES - 1)];
   if ((int64_t)part * kSortTile < n)
-    gen_block_pairs(packed, first, part, n, S, marks, s_wave,
-                    [&](int, uint32_t tile, uint32_t) {
-                      atomicAdd(&mine[tile & (RADIX - 1)], 1u);
-                    });
+    gen_block_pairs<Items>(packed, first, part, n, S, marks, s_wave,
+                           [&](int, uint32_t key, uint32_t) {
+                             atomicAdd(&mine[key & (RADIX - 1)], 1u);
+                           });
   __syncthreads();
-  if (t < RADIX) {
+  for (int d = t; d < RADIX; d += 256) {
     uint32_t c = 0;
 #pragma unroll
-    for (int k = 0; k < COPIES; ++k) c += h[k][t];
-    counts[(int64_t)t * nblocks + part] = c;
+    for (int k = 0; k < COPIES; ++k) c += h[k][d];
+    counts[(int64_t)d * nblocks + part] = c;
   }
 }
 
 // First-pass scatter from regenerated pairs: the block's pairs are laid out
 // in LDS in pair order, then ranked and written exactly like k_radix_scatter
 // (digit = low BITS bits). With RANGES this is also the last pass.
-template <int BITS, bool RANGES, typename KO>
+template <int BITS, bool RANGES, typename KO, class Items>
 __global__ __launch_bounds__(256) void k_pair_scatter(
     const uint4* __restrict__ packed, const uint32_t* __restrict__ first, const int64_t* n_isect,
     int64_t cap, const uint32_t* __restrict__ doff, int nblocks, KO* __restrict__ kout,
@@ -656,13 +666,20 @@ __global__ __launch_bounds__(256) void k_pair_scatter(
   if (bbase >= n) return;  // whole block beyond the list: no counts, nothing to write
   const int nvalid = (int)min((int64_t)kSortTile, n - bbase);
   for (int k = t; k < kSortWaves * RADIX; k += 256) (&wcnt[0][0])[k] = 0;
-  // the block's digit offsets do not depend on the pairs: fetch them early
-  const uint32_t my_off = t < RADIX ? doff[(int64_t)t * nblocks + part] : 0u;
-  gen_block_pairs(packed, first, part, n, S, sval, s_wave,
-                  [&](int slot, uint32_t tile, uint32_t rec) {
-                    skey[spad(slot)] = tile;
-                    sval[spad(slot)] = rec;
-                  });
+  // thread t owns digits [DPT t, DPT t + DPT); the block's digit offsets do
+  // not depend on the items: fetch them early
+  constexpr int DPT = (RADIX + 255) / 256;
+  uint32_t my_off[DPT];
+#pragma unroll
+  for (int i = 0; i < DPT; ++i) {
+    const int d = DPT * t + i;
+    my_off[i] = d < RADIX ? doff[(int64_t)d * nblocks + part] : 0u;
+  }
+  gen_block_pairs<Items>(packed, first, part, n, S, sval, s_wave,
+                         [&](int slot, uint32_t key, uint32_t val) {
+                           skey[spad(slot)] = key;
+                           sval[spad(slot)] = val;
+                         });
   __syncthreads();
   const uint64_t lt = lanemask_lt();
   uint32_t key[kSortItems], val[kSortItems], lofs[kSortItems];
@@ -679,20 +696,26 @@ __global__ __launch_bounds__(256) void k_pair_scatter(
     if (ok && (m & lt) == 0) wcnt[w][d] = before + (uint32_t)__popcll(m);
   }
   __syncthreads();
-  uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-  if (t < RADIX) {
-    c0 = wcnt[0][t];
-    c1 = wcnt[1][t];
-    c2 = wcnt[2][t];
-    c3 = wcnt[3][t];
+  uint32_t cw[DPT][4], tot = 0;
+#pragma unroll
+  for (int i = 0; i < DPT; ++i) {
+    const int d = DPT * t + i;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) cw[i][q] = d < RADIX ? wcnt[q][d] : 0u;
+    tot += cw[i][0] + cw[i][1] + cw[i][2] + cw[i][3];
   }
-  const uint32_t start = block_excl_scan256(c0 + c1 + c2 + c3, s_wave, nullptr);
-  if (t < RADIX) {
-    gbase[t] = my_off - start;
-    wcnt[0][t] = start;
-    wcnt[1][t] = start + c0;
-    wcnt[2][t] = start + c0 + c1;
-    wcnt[3][t] = start + c0 + c1 + c2;
+  uint32_t start = block_excl_scan256(tot, s_wave, nullptr);
+#pragma unroll
+  for (int i = 0; i < DPT; ++i) {
+    const int d = DPT * t + i;
+    if (d < RADIX) {
+      gbase[d] = my_off[i] - start;
+      wcnt[0][d] = start;
+      wcnt[1][d] = start + cw[i][0];
+      wcnt[2][d] = start + cw[i][0] + cw[i][1];
+      wcnt[3][d] = start + cw[i][0] + cw[i][1] + cw[i][2];
+    }
+    start += cw[i][0] + cw[i][1] + cw[i][2] + cw[i][3];
   }
   __syncthreads();
 #pragma unroll
@@ -846,6 +869,12 @@ __global__ void k_copy_u32(const uint32_t* __restrict__ a, const int64_t* n_dev,
 
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Band entries are distributed in chunks of kBandChunk entries of one band.
+constexpr int kBandChunk = 1024;
+static inline int64_t band_chunk_bound(int64_t cap, int64_t bands) {
+  return cap / kBandChunk + bands + 1;
+}
+
 struct BinWs {
   uint32_t* okey[2];   // [tiles]  (tile order)
   uint32_t* oval[2];   // [tiles]
@@ -859,6 +888,17 @@ struct BinWs {
   uint32_t* first;     // [cap / kSortTile + 2]  (presort)
   uint4* packed;       // [n_rec]   (presort)
   uint32_t* tcs;       // [n_rec]   tile counts in depth order (presort)
+  // band binning
+  int64_t* n_ent;      // [1] band entries
+  int64_t* n_chunk;    // [1] chunks
+  int2* branges;       // [tiles]   entry range per band
+  uint32_t* nch;       // [tiles]   chunks per band
+  uint32_t* cstart;    // [tiles]   first chunk of each band
+  int2* desc;          // [chunks]  (band, first entry)
+  uint32_t* ccnt;      // [chunks][16] per chunk and band column: covering entries
+  uint32_t* coff;      // [chunks][16] output offset of the chunk's entries per column
+  uint32_t* ttot;      // [tiles * 16] per band column: pairs
+  uint32_t* tbase;     // [tiles * 16] exclusive scan of ttot
   uint64_t* key64[2];  // [cap]     (full)
   size_t bytes;
 };
@@ -875,19 +915,35 @@ static BinWs bin_ws_layout(int64_t n_rec, int64_t cap, int64_t tiles, int sort_m
       (std::max(std::max(cap, n_rec), tiles) + kSortTile - 1) / kSortTile + 1;
   for (int k = 0; k < 2; ++k) L.okey[k] = (uint32_t*)take(4 * (size_t)std::max<int64_t>(tiles, 1));
   for (int k = 0; k < 2; ++k) L.oval[k] = (uint32_t*)take(4 * (size_t)std::max<int64_t>(tiles, 1));
-  const int64_t scan_n = std::max<int64_t>(256 * nb_max, n_rec);
+  // digit counts per sort block: up to 1024 digits in the band pass
+  const int64_t radix_max = sort_mode == XPR_SORT_BANDS ? 1024 : 256;
+  const int64_t scan_n = std::max<int64_t>(radix_max * nb_max, n_rec);
   const int64_t nparts = (scan_n + kScanTile - 1) / kScanTile + 1;
   L.offsets = (uint32_t*)take(4 * (size_t)std::max<int64_t>(n_rec, 1));
   L.partials = (uint64_t*)take(8 * (size_t)nparts);
-  L.counts = (uint32_t*)take(4 * (size_t)(256 * nb_max));
+  L.counts = (uint32_t*)take(4 * (size_t)(radix_max * nb_max));
   L.vals_alt = (uint32_t*)take(4 * (size_t)std::max<int64_t>(std::max(cap, n_rec), 1));
-  if (sort_mode == XPR_SORT_PRESORT) {
+  if (sort_mode == XPR_SORT_PRESORT || sort_mode == XPR_SORT_BANDS) {
     for (int k = 0; k < 2; ++k) L.dkey[k] = (uint32_t*)take(4 * (size_t)std::max<int64_t>(n_rec, 1));
     for (int k = 0; k < 2; ++k) L.perm[k] = (uint32_t*)take(4 * (size_t)std::max<int64_t>(n_rec, 1));
     for (int k = 0; k < 2; ++k) L.tkey[k] = (uint32_t*)take(4 * (size_t)std::max<int64_t>(cap, 1));
     L.first = (uint32_t*)take(4 * (size_t)(cap / kSortTile + 2));
     L.packed = (uint4*)take(16 * (size_t)std::max<int64_t>(n_rec, 1));
     L.tcs = (uint32_t*)take(4 * (size_t)std::max<int64_t>(n_rec, 1));
+    if (sort_mode == XPR_SORT_BANDS) {
+      const int64_t T1 = std::max<int64_t>(tiles, 1);
+      const int64_t nchunk = band_chunk_bound(cap, T1);
+      L.n_ent = (int64_t*)take(8);
+      L.n_chunk = (int64_t*)take(8);
+      L.branges = (int2*)take(8 * (size_t)T1);
+      L.nch = (uint32_t*)take(4 * (size_t)T1);
+      L.cstart = (uint32_t*)take(4 * (size_t)T1);
+      L.desc = (int2*)take(8 * (size_t)nchunk);
+      L.ccnt = (uint32_t*)take(4 * (size_t)nchunk * kBandWidth);
+      L.coff = (uint32_t*)take(4 * (size_t)nchunk * kBandWidth);
+      L.ttot = (uint32_t*)take(4 * (size_t)T1 * kBandWidth);
+      L.tbase = (uint32_t*)take(4 * (size_t)T1 * kBandWidth);
+    }
   } else {
     for (int k = 0; k < 2; ++k) L.key64[k] = (uint64_t*)take(8 * (size_t)std::max<int64_t>(cap, 1));
   }
@@ -912,7 +968,7 @@ hipError_t bin_phase1(const Batch& B, int sort_mode, const float* depth, const i
     hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, st, n_isect, (int64_t)0);
     return hipGetLastError();
   }
-  if (sort_mode == XPR_SORT_PRESORT) {
+  if (sort_mode == XPR_SORT_PRESORT || sort_mode == XPR_SORT_BANDS) {
     hipLaunchKernelGGL(k_depth_keys, dim3(grid1(n_rec)), dim3(256), 0, st, depth, tc, n_rec,
                        L.dkey[0], L.perm[0]);
     uint32_t *ko, *vo;
@@ -978,16 +1034,17 @@ static hipError_t pair_sort(const Batch& B, int tile_bits, const float* depth, c
   const int nb = (int)((grid_n + kSortTile - 1) / kSortTile);
   KT* k1 = (one && !keys_out) ? nullptr : tk0;
   if (dbits == 7)
-    hipLaunchKernelGGL(k_pair_hist<7>, dim3(nb), dim3(256), 0, st, L.packed, L.first, n_isect,
-                       cap, L.counts, nb);
+    hipLaunchKernelGGL((k_pair_hist<7, PairItems>), dim3(nb), dim3(256), 0, st, L.packed, L.first,
+                       n_isect, cap, L.counts, nb);
   else
-    hipLaunchKernelGGL(k_pair_hist<8>, dim3(nb), dim3(256), 0, st, L.packed, L.first, n_isect,
-                       cap, L.counts, nb);
+    hipLaunchKernelGGL((k_pair_hist<8, PairItems>), dim3(nb), dim3(256), 0, st, L.packed, L.first,
+                       n_isect, cap, L.counts, nb);
   hipError_t e =
       device_scan(LoadArray{L.counts}, (int64_t)nb << dbits, L.counts, L.partials, nullptr, st);
   if (e != hipSuccess) return e;
 #define XPR_PAIR_SCATTER(BITS, LAST)                                                        \
-  hipLaunchKernelGGL((k_pair_scatter<BITS, LAST, KT>), dim3(nb), dim3(256), 0, st, L.packed, \
+  hipLaunchKernelGGL((k_pair_scatter<BITS, LAST, KT, PairItems>), dim3(nb), dim3(256), 0, st,   \
+                     L.packed,                                                               \
                      L.first, n_isect, cap, L.counts, nb, k1, v1,                           \
                      LAST ? ranges : (int2*)nullptr)
   if (dbits == 7) {
@@ -1011,6 +1068,354 @@ static hipError_t pair_sort(const Batch& B, int tile_bits, const float* depth, c
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Band binning (depth-presort path, XPR_SORT_BANDS). The stable sort by
+// (tile id, depth) is done in two stages that exploit the rect shape of a
+// record's tiles. A band is one tile row by kBandWidth tile columns of one
+// view; band ids run in tile-id order (view, row, column band).
+//  1. Every record yields one entry per (row, band) of its rect, carrying
+//     its depth position j and its column range inside the band; the
+//     entries (about pairs / 4) are radix-sorted stably by band id, the
+//     replication fused into the first pass as for pairs.
+//  2. The entries of each band are cut into chunks of kBandChunk. Per chunk
+//     and band column, the covering entries are counted with one wave64
+//     ballot per (item, column); scans over (band, column) give each tile
+//     its output range and each chunk its offset inside it; then the same
+//     ballots rank the covering entries of every (wave, column) and they
+//     write their record ids, in depth order, as coalesced runs.
+// The result (vals, tile ranges, optional keys) is identical to the pair
+// sort's: the low 4 bits of the tile key are placed by the counting step
+// instead of a scatter pass, and 61M pairs are written once.
+
+__device__ __forceinline__ void view_bands(const Batch& B, int v, int& nbx, int& boff) {
+  boff = 0;
+  for (int q = 0; q < v; ++q)
+    boff += (int)B.v[q].tiles_y * (((int)B.v[q].tiles_x + kBandWidth - 1) / kBandWidth);
+  nbx = ((int)B.v[v].tiles_x + kBandWidth - 1) / kBandWidth;
+}
+
+// Packed band record and entry count per depth-ordered record. ne aliases
+// the tile counts it is computed from (read before written, same index).
+__global__ void k_band_records(Batch B, const short4* __restrict__ rect, const uint32_t* tcs,
+                               const uint32_t* __restrict__ perm, int64_t n_rec,
+                               uint4* __restrict__ packed, uint32_t* ne) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_rec) return;
+  if (tcs[j] == 0u) {
+    ne[j] = 0u;
+    return;
+  }
+  const uint32_t r = perm[j];
+  int v = 0;
+  for (int q = 1; q < B.n_views; ++q)
+    if ((int32_t)r >= B.v[q].rec_off) v = q;
+  const short4 rc = rect[r];
+  int nbx, boff;
+  view_bands(B, v, nbx, boff);
+  const int bx0 = rc.x / kBandWidth, bx1 = (rc.z - 1) / kBandWidth;
+  const uint32_t nbr = (uint32_t)(bx1 - bx0 + 1);
+  packed[j] = make_uint4(0u, (uint32_t)(boff + rc.y * nbx + bx0), nbr | ((uint32_t)nbx << 16),
+                         (uint32_t)rc.x | ((uint32_t)rc.z << 16));
+  ne[j] = (uint32_t)(rc.w - rc.y) * nbr;
+}
+
+// Entry offsets into the packed records and the sort-block map (as
+// k_pair_records does for pairs), n = min(entries, capacity).
+__global__ void k_band_first(const uint32_t* __restrict__ ne, const uint32_t* __restrict__ eoff,
+                             int64_t n_rec, const int64_t* n_ent, int64_t cap,
+                             uint4* __restrict__ packed, uint32_t* __restrict__ first) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_rec) return;
+  const int64_t n = clamp_n(n_ent, cap);
+  const int64_t o = eoff[j];
+  const int64_t e = min(o + (int64_t)ne[j], n);
+  if (e <= o) return;
+  packed[j].x = (uint32_t)o;
+  for (int64_t b = (o + kSortTile - 1) / kSortTile; b * kSortTile < e; ++b) first[b] = (uint32_t)j;
+  if (e == n) first[(n + kSortTile - 1) / kSortTile] = (uint32_t)j;
+}
+
+__global__ void k_band_nchunks(const int2* __restrict__ br, int nbk, uint32_t* __restrict__ nch) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nbk) nch[b] = (uint32_t)((br[b].y - br[b].x + kBandChunk - 1) / kBandChunk);
+}
+
+__global__ void k_band_desc(const int2* __restrict__ br, const uint32_t* __restrict__ nch,
+                            const uint32_t* __restrict__ cstart, int nbk,
+                            int2* __restrict__ desc) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbk) return;
+  const uint32_t c0 = cstart[b];
+  for (uint32_t i = 0; i < nch[b]; ++i)
+    desc[c0 + i] = make_int2(b, br[b].x + (int)i * kBandChunk);
+}
+
+// Chunk entry i = 256 w + 64 item + lane of wave w. The values of a
+// thread's 4 items and, per wave, the number of covering entries per band
+// column (lane-uniform).
+struct ChunkItems {
+  uint32_t xlo[4], xhi[4];
+  bool ok[4];
+};
+
+__device__ __forceinline__ void chunk_load(const uint32_t* __restrict__ ev, int first, int end,
+                                           ChunkItems& it, uint32_t* jpos) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint32_t v[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v[q] = ev[min(first + 256 * w + 64 * q + lane, end - 1)];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    it.ok[q] = first + 256 * w + 64 * q + lane < end;
+    it.xlo[q] = (v[q] >> 23) & 15u;
+    it.xhi[q] = ((v[q] >> 27) & 15u) + 1u;
+    if (jpos) jpos[q] = v[q] & 0x7fffffu;
+  }
+}
+
+__device__ __forceinline__ void chunk_wave_counts(const ChunkItems& it, uint32_t (&acc)[kBandWidth]) {
+#pragma unroll
+  for (int x = 0; x < kBandWidth; ++x) acc[x] = 0u;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int x = 0; x < kBandWidth; ++x)
+      acc[x] += (uint32_t)__popcll(__ballot(it.ok[q] && it.xlo[q] <= (uint32_t)x &&
+                                            (uint32_t)x < it.xhi[q]));
+}
+
+__global__ __launch_bounds__(256) void k_band_count(const int2* __restrict__ desc,
+                                                    const int64_t* n_chunk,
+                                                    const int2* __restrict__ br,
+                                                    const uint32_t* __restrict__ ev,
+                                                    uint32_t* __restrict__ ccnt) {
+  __shared__ uint32_t wc[4][kBandWidth];
+  const int c = blockIdx.x;
+  if ((int64_t)c >= *n_chunk) return;
+  const int2 d = desc[c];
+  const int end = min(d.y + kBandChunk, br[d.x].y);
+  ChunkItems it;
+  chunk_load(ev, d.y, end, it, nullptr);
+  uint32_t acc[kBandWidth];
+  chunk_wave_counts(it, acc);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int x = 0; x < kBandWidth; ++x) wc[w][x] = acc[x];
+  __syncthreads();
+  if (threadIdx.x < kBandWidth) {
+    const int x = threadIdx.x;
+    ccnt[(int64_t)c * kBandWidth + x] = wc[0][x] + wc[1][x] + wc[2][x] + wc[3][x];
+  }
+}
+
+// Per (band, column): pairs over the band's chunks.
+__global__ void k_band_totals(const uint32_t* __restrict__ cstart,
+                              const uint32_t* __restrict__ nch, int nbk,
+                              const uint32_t* __restrict__ ccnt, uint32_t* __restrict__ ttot) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nbk * kBandWidth) return;
+  const int b = id / kBandWidth, x = id - b * kBandWidth;
+  const uint32_t c0 = cstart[b], c1 = c0 + nch[b];
+  uint32_t s = 0;
+  for (uint32_t c = c0; c < c1; ++c) s += ccnt[(size_t)c * kBandWidth + x];
+  ttot[id] = s;
+}
+
+// Chunk offsets per column, and the tile ranges ((0, 0) when empty).
+__global__ void k_band_offsets(Batch B, const uint32_t* __restrict__ cstart,
+                               const uint32_t* __restrict__ nch, int nbk,
+                               const uint32_t* __restrict__ ccnt,
+                               const uint32_t* __restrict__ ttot,
+                               const uint32_t* __restrict__ tbase, uint32_t* __restrict__ coff,
+                               int2* __restrict__ ranges) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nbk * kBandWidth) return;
+  const int b = id / kBandWidth, x = id - b * kBandWidth;
+  uint32_t run = tbase[id];
+  const uint32_t c0 = cstart[b], c1 = c0 + nch[b];
+  for (uint32_t c = c0; c < c1; ++c) {
+    coff[(size_t)c * kBandWidth + x] = run;
+    run += ccnt[(size_t)c * kBandWidth + x];
+  }
+  int v = 0, boff = 0, nbx = 0;
+  for (;; ++v) {
+    nbx = ((int)B.v[v].tiles_x + kBandWidth - 1) / kBandWidth;
+    const int nv = (int)B.v[v].tiles_y * nbx;
+    if (b < boff + nv || v == B.n_views - 1) break;
+    boff += nv;
+  }
+  const int ty = (b - boff) / nbx, band = (b - boff) - ty * nbx;
+  const int tx = band * kBandWidth + x;
+  if (tx < (int)B.v[v].tiles_x) {
+    const int tile = B.v[v].tile_off + ty * (int)B.v[v].tiles_x + tx;
+    const uint32_t n = ttot[id];
+    ranges[tile] = n ? make_int2((int)tbase[id], (int)(tbase[id] + n)) : make_int2(0, 0);
+  }
+}
+
+// Writes each chunk's records into its tiles' lists: per (wave, item,
+// column) the covering lanes take consecutive slots after the chunk's
+// offset and the earlier waves' and items' counts.
+__global__ __launch_bounds__(256) void k_band_emit(Batch B, const int2* __restrict__ desc,
+                                                   const int64_t* n_chunk,
+                                                   const int2* __restrict__ br,
+                                                   const uint32_t* __restrict__ ev,
+                                                   const uint32_t* __restrict__ perm,
+                                                   const uint32_t* __restrict__ coff, int64_t cap,
+                                                   uint32_t* __restrict__ vals,
+                                                   uint64_t* __restrict__ keys,
+                                                   const float* __restrict__ depth) {
+  __shared__ uint32_t wc[4][kBandWidth];
+  const int c = blockIdx.x;
+  if ((int64_t)c >= *n_chunk) return;
+  const int2 d = desc[c];
+  const int end = min(d.y + kBandChunk, br[d.x].y);
+  ChunkItems it;
+  uint32_t jpos[4];
+  chunk_load(ev, d.y, end, it, jpos);
+  uint32_t rec[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) rec[q] = perm[jpos[q]];
+  uint32_t acc[kBandWidth];
+  chunk_wave_counts(it, acc);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int x = 0; x < kBandWidth; ++x) wc[w][x] = acc[x];
+  __syncthreads();
+  uint32_t pos[kBandWidth];
+#pragma unroll
+  for (int x = 0; x < kBandWidth; ++x) {
+    uint32_t p = coff[(size_t)c * kBandWidth + x];
+    for (int q = 0; q < w; ++q) p += wc[q][x];
+    pos[x] = p;
+  }
+  // tile id of column 0 of this band (for the optional 64-bit keys)
+  int tile0 = 0;
+  if (keys) {
+    int v = 0, boff = 0, nbx = 0;
+    for (;; ++v) {
+      nbx = ((int)B.v[v].tiles_x + kBandWidth - 1) / kBandWidth;
+      const int nv = (int)B.v[v].tiles_y * nbx;
+      if (d.x < boff + nv || v == B.n_views - 1) break;
+      boff += nv;
+    }
+    const int ty = (d.x - boff) / nbx, band = (d.x - boff) - ty * nbx;
+    tile0 = B.v[v].tile_off + ty * (int)B.v[v].tiles_x + band * kBandWidth;
+  }
+  const uint64_t lt = lanemask_lt();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int x = 0; x < kBandWidth; ++x) {
+      const bool cov = it.ok[q] && it.xlo[q] <= (uint32_t)x && (uint32_t)x < it.xhi[q];
+      const uint64_t m = __ballot(cov);
+      const uint32_t p = pos[x] + (uint32_t)__popcll(m & lt);
+      if (cov && (int64_t)p < cap) {
+        vals[p] = rec[q];
+        if (keys) keys[p] = ((uint64_t)(uint32_t)(tile0 + x) << 32) | __float_as_uint(depth[rec[q]]);
+      }
+      pos[x] += (uint32_t)__popcll(m);
+    }
+  }
+}
+
+static inline int bits_for(int64_t n) {
+  int b = 1;
+  while (((int64_t)1 << b) < n) ++b;
+  return b;
+}
+
+static int band_count(const Batch& B) {
+  int nbk = 0;
+  for (int v = 0; v < B.n_views; ++v)
+    nbk += (int)B.v[v].tiles_y * (((int)B.v[v].tiles_x + kBandWidth - 1) / kBandWidth);
+  return nbk;
+}
+
+static hipError_t band_sort(const Batch& B, const float* depth, const short4* rc,
+                            const uint32_t* perm, int64_t n_rec, int64_t cap, int64_t grid_n,
+                            uint64_t* keys_out, uint32_t* vals_u, int2* ranges, const BinWs& L,
+                            hipStream_t st) {
+  const int nbk = band_count(B);
+  // 1. entries per record, their offsets, the sort-block map
+  hipLaunchKernelGGL(k_band_records, dim3(grid1(n_rec)), dim3(256), 0, st, B, rc, L.tcs, perm,
+                     n_rec, L.packed, L.tcs);
+  hipError_t e = device_scan(LoadArray{L.tcs}, n_rec, L.offsets, L.partials, L.n_ent, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_band_first, dim3(grid1(n_rec)), dim3(256), 0, st, L.tcs, L.offsets, n_rec,
+                     (const int64_t*)L.n_ent, cap, L.packed, L.first);
+  // 2. entries sorted by band; the last pass leaves them in vals_alt (the
+  // caller's vals serve as the other buffer until the final write)
+  // up to 10 band bits in one pass (1024 buckets), else 7/8-bit digits
+  const int bits = bits_for(nbk);
+  const int dbits = bits <= 10 ? std::max(bits, 7) : radix_digit_bits(bits);
+  const int passes = bits <= 10 ? 1 : radix_passes(bits);
+  const bool one = passes == 1;
+  uint32_t* v1 = (passes % 2 == 1) ? L.vals_alt : vals_u;
+  uint32_t* v2 = (passes % 2 == 1) ? vals_u : L.vals_alt;
+  uint16_t* tk0 = reinterpret_cast<uint16_t*>(L.tkey[0]);
+  uint16_t* tk1 = reinterpret_cast<uint16_t*>(L.tkey[1]);
+  hipLaunchKernelGGL(k_ranges_init, dim3(grid1(nbk)), dim3(256), 0, st, L.branges, nbk);
+  const int nb = (int)((grid_n + kSortTile - 1) / kSortTile);
+#define XPR_BAND_HIST(BITS)                                                                   \
+  hipLaunchKernelGGL((k_pair_hist<BITS, BandItems>), dim3(nb), dim3(256), 0, st, L.packed,        \
+                     L.first, (const int64_t*)L.n_ent, cap, L.counts, nb)
+  switch (dbits) {
+    case 7: XPR_BAND_HIST(7); break;
+    case 8: XPR_BAND_HIST(8); break;
+    case 9: XPR_BAND_HIST(9); break;
+    default: XPR_BAND_HIST(10); break;
+  }
+#undef XPR_BAND_HIST
+  e = device_scan(LoadArray{L.counts}, (int64_t)nb << dbits, L.counts, L.partials, nullptr, st);
+  if (e != hipSuccess) return e;
+  uint16_t* k1 = one ? nullptr : tk0;
+#define XPR_BAND_SCATTER(BITS, LAST)                                                          \
+  hipLaunchKernelGGL((k_pair_scatter<BITS, LAST, uint16_t, BandItems>), dim3(nb), dim3(256), 0, \
+                     st, L.packed, L.first, (const int64_t*)L.n_ent, cap, L.counts, nb, k1, v1,  \
+                     LAST ? L.branges : (int2*)nullptr)
+  switch (dbits) {
+    case 7: if (one) XPR_BAND_SCATTER(7, true); else XPR_BAND_SCATTER(7, false); break;
+    case 8: if (one) XPR_BAND_SCATTER(8, true); else XPR_BAND_SCATTER(8, false); break;
+    case 9: XPR_BAND_SCATTER(9, true); break;
+    default: XPR_BAND_SCATTER(10, true); break;
+  }
+#undef XPR_BAND_SCATTER
+  uint16_t* ko = tk0;
+  uint32_t* vo = v1;
+  if (!one) {
+    e = radix_sort<uint16_t>(tk0, v1, tk1, v2, (const int64_t*)L.n_ent, cap, grid_n, bits,
+                             L.counts, L.partials, &ko, &vo, st, dbits, L.branges, false);
+    if (e != hipSuccess) return e;
+  }
+  if (vo != L.vals_alt) return hipErrorUnknown;  // the pass parity above guarantees it
+  hipLaunchKernelGGL(k_ranges_fix, dim3(grid1(nbk)), dim3(256), 0, st, L.branges, nbk);
+  // 3. chunks of each band's entries
+  hipLaunchKernelGGL(k_band_nchunks, dim3(grid1(nbk)), dim3(256), 0, st, L.branges, nbk, L.nch);
+  e = device_scan(LoadArray{L.nch}, nbk, L.cstart, L.partials, L.n_chunk, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_band_desc, dim3(grid1(nbk)), dim3(256), 0, st, L.branges, L.nch, L.cstart,
+                     nbk, L.desc);
+  const int64_t nch_bound = band_chunk_bound(grid_n, nbk);
+  hipLaunchKernelGGL(k_band_count, dim3(nch_bound), dim3(256), 0, st, L.desc,
+                     (const int64_t*)L.n_chunk, L.branges, L.vals_alt, L.ccnt);
+  // 4. tile ranges and chunk offsets
+  const int ncol = nbk * kBandWidth;
+  hipLaunchKernelGGL(k_band_totals, dim3(grid1(ncol)), dim3(256), 0, st, L.cstart, L.nch, nbk,
+                     L.ccnt, L.ttot);
+  e = device_scan(LoadArray{L.ttot}, ncol, L.tbase, L.partials, nullptr, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_band_offsets, dim3(grid1(ncol)), dim3(256), 0, st, B, L.cstart, L.nch, nbk,
+                     L.ccnt, L.ttot, L.tbase, L.coff, ranges);
+  // 5. the records into their tiles' lists
+  hipLaunchKernelGGL(k_band_emit, dim3(nch_bound), dim3(256), 0, st, B, L.desc,
+                     (const int64_t*)L.n_chunk, L.branges, L.vals_alt, perm, L.coff, cap, vals_u,
+                     keys_out, depth);
+  return hipGetLastError();
+}
+
 hipError_t bin_phase2(const Batch& B, int sort_mode, int tile_bits, const float* depth,
                       const int16_t* rect, const int32_t* tc, const uint32_t* perm, int64_t n_rec,
                       int64_t cap, int64_t grid_n, const int64_t* n_isect, uint64_t* keys_out,
@@ -1027,7 +1432,11 @@ hipError_t bin_phase2(const Batch& B, int sort_mode, int tile_bits, const float*
   const short4* rc = reinterpret_cast<const short4*>(rect);
   uint32_t* vals_u = reinterpret_cast<uint32_t*>(vals);
   const int nbd = grid1(n_rec);
-  if (sort_mode == XPR_SORT_PRESORT) {
+  if (sort_mode == XPR_SORT_BANDS && band_count(B) <= 65536 && n_rec < ((int64_t)1 << 23)) {
+    const hipError_t e = band_sort(B, depth, rc, perm, n_rec, cap, grid_n, keys_out, vals_u,
+                                   ranges, L, st);
+    if (e != hipSuccess) return e;
+  } else if (sort_mode == XPR_SORT_PRESORT || sort_mode == XPR_SORT_BANDS) {
     const hipError_t e =
         tiles_16bit(B.total_tiles)
             ? pair_sort<uint16_t>(B, tile_bits, depth, rc, perm, n_rec, cap, grid_n, n_isect,

@@ -54,7 +54,7 @@ def test_lds_batch_and_sort_mode_do_not_change_results():
     cam = camera_look_at((0.5, 0.5, -4.5), 120, 90)
     ref = None
     for lds in (64, 128, 256, 512):
-        for mode in ("presort", "full"):
+        for mode in ("presort", "full", "bands"):
             g = run_gpu(sc, cam, R.Config(lds_batch=lds, sort_mode=mode))
             if ref is None:
                 ref = g
@@ -93,10 +93,11 @@ def test_deterministic_and_order_invariant():
     assert np.array_equal(perm[c["vals"]], a["vals"])
 
 
-def test_capacity_error_and_retry():
+@pytest.mark.parametrize("mode", ["presort", "bands"])
+def test_capacity_error_and_retry(mode):
     sc = _small(3000, seed=6)
     cam = camera_look_at((0, 0, -4.0), 96, 64)
-    cfg = R.Config()
+    cfg = R.Config(sort_mode=mode)
     scene = R.Scene.from_host(sc)
     views = R.Views([scene], [cam], [0], cfg)
     proj = R.xpr_project(views, cfg)
@@ -117,7 +118,7 @@ def test_capacity_error_and_retry():
     assert int(n_isect.item()) == I
     assert "exceed" in L.xpr_last_error()
     # no-readback mode: status OK, the caller sees n_isect > capacity
-    cfg2 = R.Config(no_sync=True)
+    cfg2 = R.Config(no_sync=True, sort_mode=mode)
     views2 = R.Views([scene], [cam], [0], cfg2)
     st = L.xpr_bin_sort(views2.c, views2.cfg_c, proj.to_c(), bins, ctypes.c_void_p(ws.data_ptr()),
                         nb, R._stream())
@@ -130,12 +131,13 @@ def test_capacity_error_and_retry():
     assert torch.equal(small.vals[:I], full.vals[:I]) and torch.equal(small.ranges, full.ranges)
 
 
-def test_no_sync_mode_matches():
+@pytest.mark.parametrize("mode", ["presort", "bands"])
+def test_no_sync_mode_matches(mode):
     sc = _small(4000, seed=7)
     cam = camera_look_at((0.4, -0.2, -4.0), 111, 77)
     a = run_gpu(sc, cam, R.Config())
     scene = R.Scene.from_host(sc)
-    cfg = R.Config(no_sync=True)
+    cfg = R.Config(no_sync=True, sort_mode=mode)
     views = R.Views([scene], [cam], [0], cfg)
     proj = R.xpr_project(views, cfg)
     bins = R.xpr_bin_sort(views, cfg, proj, capacity=4 * a["I"])
@@ -145,10 +147,11 @@ def test_no_sync_mode_matches():
     assert np.array_equal(views.image(frame.image, 0).cpu().numpy(), a["image"][0])
 
 
-def test_batched_views_equal_single_views():
+@pytest.mark.parametrize("mode", ["presort", "bands"])
+def test_batched_views_equal_single_views(mode):
     sc = _small(6000, seed=8)
     cams = random_cameras(4, 3, [(64, 48), (97, 61), (128, 128), (40, 100)], radius=4.5)
-    cfg = R.Config()
+    cfg = R.Config(sort_mode=mode)
     rng = np.random.default_rng(0)
     dimgs = [rng.normal(size=(3, c.height, c.width)).astype(np.float32) for c in cams]
     batch = run_gpu(sc, cams, cfg, dimgs=dimgs)
@@ -166,10 +169,11 @@ def test_batched_views_equal_single_views():
         assert np.abs(batch["grads"][k] - gsum[k]).max() <= 1e-4 * scale, k
 
 
-def test_multi_scene_batch():
+@pytest.mark.parametrize("mode", ["presort", "bands"])
+def test_multi_scene_batch(mode):
     a, b = _small(2000, seed=10), _small(3000, seed=11, deg=3)
     cams = random_cameras(3, 5, (80, 60), radius=4.5)
-    cfg = R.Config()
+    cfg = R.Config(sort_mode=mode)
     sa, sb = R.Scene.from_host(a), R.Scene.from_host(b)
     views = R.Views([sa, sb], cams, [0, 1, 0], cfg)
     proj = R.xpr_project(views, cfg)
