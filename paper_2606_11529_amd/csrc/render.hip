@@ -393,6 +393,8 @@ __device__ __forceinline__ void bwd_tile(const Batch& B, int g, const float4* __
     if (__ballot(anyp) == 0) return false;
     const float2 c = S.s2[kk];
     const float cr = b.w, cg = c.x, cb = c.y;
+    // per-record terms of the conic gradient that do not depend on the row
+    const float hu = 2.f * a.z * dx, hv = a.w * dx, dx2 = dx * dx;
     bool any = false;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
@@ -407,19 +409,20 @@ __device__ __forceinline__ void bwd_tile(const Batch& B, int g, const float4* __
       g[6] += w * G0[j];
       g[7] += w * G1[j];
       g[8] += w * G2[j];
-      const float da = T[j] * ((cr - S0[j]) * G0[j] + (cg - S1[j]) * G1[j] +
-                               (cb - S2[j]) * G2[j]) - TfbG[j] * inv;
-      S0[j] = alpha * cr + (1.f - alpha) * S0[j];
-      S1[j] = alpha * cg + (1.f - alpha) * S1[j];
-      S2[j] = alpha * cb + (1.f - alpha) * S2[j];
+      // colour minus the colour behind; S_i = S_{i+1} + alpha (c - S_{i+1})
+      const float d0 = cr - S0[j], d1 = cg - S1[j], d2 = cb - S2[j];
+      const float da = T[j] * (d0 * G0[j] + d1 * G1[j] + d2 * G2[j]) - TfbG[j] * inv;
+      S0[j] += alpha * d0;
+      S1[j] += alpha * d1;
+      S2[j] += alpha * d2;
       // dL/dP in natural-log units (zero when alpha is clamped); the staged
       // conic carries log2(e)
       const float dP = raw <= amax ? alpha * da : 0.f;
       const float dPn = dP * kLn2;
       g[5] += raw <= amax && alpha > 0.f ? eP * da : 0.f;
-      g[0] -= dPn * (2.f * a.z * dx + a.w * dy[j]);
-      g[1] -= dPn * (2.f * b.x * dy[j] + a.w * dx);
-      g[2] += dP * dx * dx;
+      g[0] -= dPn * (hu + a.w * dy[j]);
+      g[1] -= dPn * (2.f * b.x * dy[j] + hv);
+      g[2] += dP * dx2;
       g[3] += dP * dx * dy[j];
       g[4] += dP * dy[j] * dy[j];
     }
