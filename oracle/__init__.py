@@ -11,8 +11,9 @@ Two independent forms of the same definition:
     no sort and no ranges, differentiable with torch autograd.
 
 Citations are to the paper (XPR, arxiv 2606.11529): Background section
-(blending), Listing "Implementation of XPR-3DGS" (project/evaluate), section
-"Rasterizer" (replicate, tile id, sort, bounds), Algorithm 1 (shader loop).
+(blending), Listing "Implementation of XPR-3DGS" (project/evaluate/
+tile_cull), section "Rasterizer" (replicate, tile id, sort, bounds),
+Algorithm 1 (shader loop).
 """
 from __future__ import annotations
 
@@ -39,6 +40,7 @@ class OracleConfig:
     z_near: float = 0.2
     fov_clip: float = 1.3           # Jacobian clamp at fov_clip*tan(fov/2)
     bg: tuple = (0.0, 0.0, 0.0)
+    tile_cull: bool = False         # per-(Gaussian, tile) cull of XPR-3DGS
 
     def proj_cfg(self):
         return np.array([self.lowpass, self.alpha_min, self.z_near, self.fov_clip],
@@ -62,8 +64,11 @@ def lib():
         L.orc_project.argtypes = [i64, P, P, P, P, P, i32, P, i32, i32, P, i32, i32, i32,
                                   P, P, P, P, P, P, P]
         L.orc_project.restype = None
-        L.orc_bin.argtypes = [i64, P, P, P, i32, i32, i64, P, P, P, P]
+        L.orc_bin.argtypes = [i64, P, P, P, i32, i32, i64, P, P, P, P, P, i32, i32, i32, i32,
+                              ctypes.c_double, P, P, P]
         L.orc_bin.restype = i64
+        L.orc_tile_cull.argtypes = [i64, P, P, i32, i32, i32, i32, ctypes.c_double, P, P, P, P]
+        L.orc_tile_cull.restype = None
         L.orc_render_fwd.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P, P, P, P]
         L.orc_render_fwd.restype = None
         L.orc_render_bwd.argtypes = [i32, i32, i32, i32, i64, P, P, P, P, P, P]
@@ -133,8 +138,14 @@ def project(scene, cam, cfg: OracleConfig):
     return out
 
 
-def bin_pairs(depth, rect, tc, tiles_x: int, tiles_y: int):
-    """Binning (section Rasterizer): offsets, I, keys, vals, ranges."""
+def bin_pairs(depth, rect, tc, tiles_x: int, tiles_y: int, cull=None):
+    """Binning (section Rasterizer): offsets, I, keys, vals, ranges.
+
+    ``cull`` = (rec [n][9], W, H, cfg) applies tile_cull (Listing XPR-3DGS)
+    to every replicated pair: culled pairs get the sentinel tile id
+    tiles_x*tiles_y and sort last, so the first ``I_kept`` entries of vals
+    and keys are the kept lists; ``pair_guard`` flags the pairs whose cull
+    decision is in the guard band, in sorted order."""
     depth = _f64(depth)
     rect = np.ascontiguousarray(rect, dtype=np.int32)
     tc = np.ascontiguousarray(tc, dtype=np.int32)
@@ -144,10 +155,37 @@ def bin_pairs(depth, rect, tc, tiles_x: int, tiles_y: int):
     keys = np.zeros(I, np.uint64)
     vals = np.zeros(I, np.int32)
     ranges = np.zeros((tiles_x * tiles_y, 2), np.int32)
+    kept = np.zeros(1, np.int64)
+    nguard = np.zeros(1, np.int64)
+    pguard = np.zeros(I, np.uint8)
+    crec, W, H, tw, th, amin = None, 0, 0, 0, 0, 0.0
+    if cull is not None:
+        rec, W, H, cfg = cull
+        crec = _f64(rec)
+        assert crec.shape == (n, 9)
+        tw, th, amin = cfg.tile_w, cfg.tile_h, cfg.alpha_min
     got = lib().orc_bin(n, _p(depth), _p(rect), _p(tc), tiles_x, tiles_y, I, _p(offsets),
-                        _p(keys), _p(vals), _p(ranges))
+                        _p(keys), _p(vals), _p(ranges), _p(crec), W, H, tw, th, amin,
+                        _p(kept), _p(nguard), _p(pguard))
     assert got == I
-    return dict(offsets=offsets, I=I, keys=keys, vals=vals, ranges=ranges)
+    return dict(offsets=offsets, I=I, keys=keys, vals=vals, ranges=ranges,
+                I_kept=int(kept[0]), n_guard=int(nguard[0]), pair_guard=pguard)
+
+
+def tile_cull(rec, txy, W: int, H: int, cfg: OracleConfig):
+    """tile_cull (Listing XPR-3DGS) of pairs rec[k] x tile txy[k]: keep,
+    smallest power over the tile, level log(o / alpha_min), guard."""
+    rec = _f64(rec).reshape(-1, 9)
+    txy = np.ascontiguousarray(txy, dtype=np.int32).reshape(-1, 2)
+    m = rec.shape[0]
+    assert txy.shape[0] == m
+    keep = np.zeros(m, np.uint8)
+    power = np.zeros(m)
+    level = np.zeros(m)
+    guard = np.zeros(m, np.uint8)
+    lib().orc_tile_cull(m, _p(rec), _p(txy), W, H, cfg.tile_w, cfg.tile_h, cfg.alpha_min,
+                        _p(keep), _p(power), _p(level), _p(guard))
+    return keep.astype(bool), power, level, guard.astype(bool)
 
 
 def render_fwd(rec, vals, ranges, W: int, H: int, cfg: OracleConfig):
@@ -199,7 +237,8 @@ def render(scene, cam, cfg: OracleConfig):
     """Whole forward pipeline in FP64: returns every intermediate."""
     pr = project(scene, cam, cfg)
     tx, ty = tiles(cam, cfg)
-    b = bin_pairs(pr["depth"], pr["rect"], pr["tc"], tx, ty)
+    cull = (pr["rec"], cam.width, cam.height, cfg) if cfg.tile_cull else None
+    b = bin_pairs(pr["depth"], pr["rect"], pr["tc"], tx, ty, cull)
     f = render_fwd(pr["rec"], b["vals"], b["ranges"], cam.width, cam.height, cfg)
     return dict(proj=pr, bins=b, fwd=f)
 

@@ -15,7 +15,9 @@
 //     -con01, -0.5*con11, o, c); function evaluate: power and alpha.
 //   * Section "Rasterizer": replicate by prefix sum, tile id
 //     t = y*W' + x with x = xmin + (r mod w), y = ymin + floor(r/w), sort by
-//     (tile id, depth), per-tile segment bounds.
+//     (tile id, depth), per-tile segment bounds; optionally tile_cull of the
+//     XPR-3DGS listing per replicated pair, culled pairs moved to a sentinel
+//     tile (the largest-response test the XPR-3DGS section describes).
 //   * Section "Shader", Algorithm 1: per-pixel front-to-back loop over the
 //     tile's list, gate and accumulate.
 // Readings where the paper is silent (pixel sample position, low-pass 0.3,
@@ -280,6 +282,59 @@ void project_one(int64_t i, int64_t n, const double* means, const double* scales
   (void)K;
 }
 
+// tile_cull of one (Gaussian, tile) pair (Listing "XPR-3DGS", tile_cull; the
+// XPR-3DGS section states the test): the largest contribution o G(x) over
+// the tile is reached at the point of the tile where the power
+// 0.5 (x - mu)^T conic (x - mu) is smallest, which is mu itself when mu lies
+// in the tile and otherwise a point on a tile edge facing mu; the pair is
+// kept iff that smallest power is at most log(o / alpha_min).
+//
+// Readings: the tile is the box spanned by its pixel samples,
+// [tx tw, tx tw + tw - 1] x [ty th, ty th + th - 1] clipped to the image
+// (pixel (i, j) is sampled at (i, j)); a conic that is not positive
+// definite (possible once rounded to float32) has no bounded footprint and
+// its pairs are kept. guard marks a smallest power within 1e-9 (relative)
+// of the level, where another float64 evaluation order may decide the other
+// way.
+struct CullTest {
+  bool keep, guard;
+  double power, level;
+};
+
+CullTest tile_cull_one(const double* rec, int tx, int ty, int W, int H, int tile_w, int tile_h,
+                       double alpha_min) {
+  const double X0 = (double)tx * tile_w, X1 = std::min(X0 + tile_w - 1, W - 1.0);
+  const double Y0 = (double)ty * tile_h, Y1 = std::min(Y0 + tile_h - 1, H - 1.0);
+  const double u = rec[0], v = rec[1];
+  // conic entries from the shader data (-0.5 con00, -con01, -0.5 con11)
+  const double a = -2.0 * rec[2], b = -rec[3], c = -2.0 * rec[4], o = rec[5];
+  CullTest r{true, false, 0.0, std::log(o / alpha_min)};
+  if (!(a > 0.0 && a * c - b * b > 0.0)) return r;
+  auto q = [&](double dx, double dy) { return a * dx * dx + 2.0 * b * dx * dy + c * dy * dy; };
+  auto clampd = [](double x, double lo, double hi) { return std::min(hi, std::max(lo, x)); };
+  const bool out_x = u < X0 || u > X1, out_y = v < Y0 || v > Y1;
+  double best = 0.0;
+  if (out_x || out_y) {
+    best = INFINITY;
+    if (out_x) {
+      // vertical edge facing mu: q along it is smallest at dy = -b dx / c
+      const double dx = (u < X0 ? X0 : X1) - u;
+      const double y = clampd(v - b * dx / c, Y0, Y1);
+      best = std::min(best, q(dx, y - v));
+    }
+    if (out_y) {
+      // horizontal edge facing mu: smallest at dx = -b dy / a
+      const double dy = (v < Y0 ? Y0 : Y1) - v;
+      const double x = clampd(u - b * dy / a, X0, X1);
+      best = std::min(best, q(x - u, dy));
+    }
+  }
+  r.power = 0.5 * best;
+  r.keep = r.power <= r.level;
+  r.guard = std::fabs(r.power - r.level) <= 1e-9 * std::max(1.0, std::fabs(r.level));
+  return r;
+}
+
 }  // namespace
 
 extern "C" {
@@ -344,16 +399,26 @@ void orc_project(int64_t n, const double* means, const double* scales, const dou
 //   offsets [n] (exclusive prefix sum of tc, may be NULL)
 //   keys [cap]: tile << 32 | float32 bits of depth (may be NULL)
 //   vals [cap]: Gaussian index, ranges [tiles_x*tiles_y][2]
+// With cull_rec [n][9] (shader data, may be NULL) every replicated pair
+// also goes through tile_cull (Listing "XPR-3DGS") and a culled pair gets
+// the sentinel tile id tiles_x*tiles_y, so it sorts after every real tile
+// and belongs to no range; *n_kept counts the pairs not culled, *n_guard the
+// pairs whose decision is in the guard band, pair_guard [cap] (may be NULL)
+// flags them in sorted order. W, H, tile_w, tile_h and alpha_min are only
+// read with cull_rec.
 // Returns I = sum tc; writes the lists only when I <= cap.
 int64_t orc_bin(int64_t n, const double* depth, const int32_t* rect, const int32_t* tc,
                 int tiles_x, int tiles_y, int64_t cap, int64_t* offsets, uint64_t* keys,
-                int32_t* vals, int32_t* ranges) {
+                int32_t* vals, int32_t* ranges, const double* cull_rec, int W, int H, int tile_w,
+                int tile_h, double alpha_min, int64_t* n_kept, int64_t* n_guard,
+                uint8_t* pair_guard) {
   std::vector<int64_t> off(n + 1, 0);
   for (int64_t i = 0; i < n; ++i) off[i + 1] = off[i] + tc[i];
   const int64_t I = off[n];
   if (offsets) for (int64_t i = 0; i < n; ++i) offsets[i] = off[i];
   if (I > cap) return I;
-  struct Pair { uint32_t tile; float depth; int32_t idx; };
+  const uint32_t sentinel = (uint32_t)tiles_x * (uint32_t)tiles_y;
+  struct Pair { uint32_t tile; float depth; int32_t idx; uint8_t guard; };
   std::vector<Pair> pairs(I);
 #pragma omp parallel for schedule(dynamic, 1024)
   for (int64_t i = 0; i < n; ++i) {
@@ -362,7 +427,14 @@ int64_t orc_bin(int64_t n, const double* depth, const int32_t* rect, const int32
     for (int64_t r = 0; r < tc[i]; ++r) {
       const int x = x0 + (int)(r % w);
       const int y = y0 + (int)(r / w);
-      pairs[off[i] + r] = Pair{(uint32_t)(y * tiles_x + x), (float)depth[i], (int32_t)i};
+      uint32_t tile = (uint32_t)(y * tiles_x + x);
+      uint8_t g = 0;
+      if (cull_rec) {
+        const CullTest t = tile_cull_one(cull_rec + 9 * i, x, y, W, H, tile_w, tile_h, alpha_min);
+        if (!t.keep) tile = sentinel;
+        g = t.guard ? 1 : 0;
+      }
+      pairs[off[i] + r] = Pair{tile, (float)depth[i], (int32_t)i, g};
     }
   }
   auto less = [](const Pair& p, const Pair& q) {
@@ -377,6 +449,7 @@ int64_t orc_bin(int64_t n, const double* depth, const int32_t* rect, const int32
 #endif
   const int64_t T = (int64_t)tiles_x * tiles_y;
   for (int64_t t = 0; t < 2 * T; ++t) ranges[t] = 0;
+  int64_t kept = 0, guards = 0;
   for (int64_t k = 0; k < I; ++k) {
     const Pair& p = pairs[k];
     if (keys) {
@@ -385,10 +458,32 @@ int64_t orc_bin(int64_t n, const double* depth, const int32_t* rect, const int32
       keys[k] = ((uint64_t)p.tile << 32) | bits;
     }
     vals[k] = p.idx;
+    if (pair_guard) pair_guard[k] = p.guard;
+    guards += p.guard;
+    if (p.tile == sentinel) continue;
+    ++kept;
     if (k == 0 || pairs[k - 1].tile != p.tile) ranges[2 * p.tile] = (int32_t)k;
     if (k == I - 1 || pairs[k + 1].tile != p.tile) ranges[2 * p.tile + 1] = (int32_t)(k + 1);
   }
+  if (n_kept) *n_kept = kept;
+  if (n_guard) *n_guard = guards;
   return I;
+}
+
+// tile_cull of m (Gaussian, tile) pairs: rec [m][9] shader data, txy [m][2]
+// tile coordinates; keep, power (smallest 0.5 q over the tile), level
+// (log(o / alpha_min)) and guard per pair (any output may be NULL).
+void orc_tile_cull(int64_t m, const double* rec, const int32_t* txy, int W, int H, int tile_w,
+                   int tile_h, double alpha_min, uint8_t* keep, double* power, double* level,
+                   uint8_t* guard) {
+  for (int64_t k = 0; k < m; ++k) {
+    const CullTest t =
+        tile_cull_one(rec + 9 * k, txy[2 * k], txy[2 * k + 1], W, H, tile_w, tile_h, alpha_min);
+    if (keep) keep[k] = t.keep ? 1 : 0;
+    if (power) power[k] = t.power;
+    if (level) level[k] = t.level;
+    if (guard) guard[k] = t.guard ? 1 : 0;
+  }
 }
 
 // Forward compositing (Algorithm 1 with the 3DGS evaluate): for pixel (x, y)
