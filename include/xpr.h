@@ -95,6 +95,7 @@ typedef struct xpr_config {
   int32_t bwd_ppt;        /* pixels per thread in the backward: 1, 2 or 4 (16x16 tiles) */
   int32_t bwd_lds_batch;  /* LDS batch of the backward (0: same as lds_batch) */
   int32_t persistent;     /* 1: persistent render grids pulling from tile_order */
+  int32_t tile_cull;      /* 1: per-(Gaussian, tile) cull in xpr_bin_sort (0) */
 } xpr_config;
 
 /* One scene of n Gaussians, structure of arrays with leading dimension ld:
@@ -200,6 +201,15 @@ xpr_status xpr_bin_sort_workspace(const xpr_views* views, const xpr_config* cfg,
  * row-major in the rect, stable sort by (tile id, depth) so that ties keep
  * the lower record index, per-tile [start, end), and (if requested) the
  * longest-list-first tile order.
+ * With cfg->tile_cull = 1 a pair is kept only if it passes tile_cull of the
+ * listing XPR-3DGS: the smallest power 0.5 d^T conic d over the tile's
+ * pixel-sample box [x tw, x tw + tw - 1] x [y th, y th + th - 1] (clipped
+ * to the image) is at most log(o / alpha_min), evaluated in float64 from the
+ * float32 splat (a conic that is not positive definite keeps its rect). The
+ * lists, ranges and *n_isect then hold the kept pairs only (the listing's
+ * sentinel tile for culled pairs is never materialised), the image is the
+ * same up to alpha values at the 1/255 threshold, and the presort strategy
+ * is used whatever cfg->sort_mode says.
  *   out     buffers as described at xpr_bins
  *   ws / ws_bytes   workspace of at least xpr_bin_sort_workspace() bytes
  * With cfg->no_sync == 0 the call reads I back (one stream sync) and returns

@@ -15,12 +15,14 @@ hipError_t launch_project(const Batch& B, int max_n, float* splat, float* depth,
                           int32_t* tc, hipStream_t st);
 hipError_t launch_project_bwd(const Batch& B, int max_n, const float* grad2d, const int32_t* tc,
                               const GradDev* G, int accumulate, hipStream_t st);
-size_t bin_workspace_bytes(int64_t n_rec, int64_t cap, int64_t tiles, int sort_mode);
-hipError_t bin_phase1(const Batch& B, int sort_mode, const float* depth, const int32_t* tc,
+size_t bin_workspace_bytes(int64_t n_rec, int64_t cap, int64_t tiles, int sort_mode, bool cull);
+hipError_t bin_phase1(const Batch& B, int sort_mode, bool cull, const float* splat,
+                      const int16_t* rect, const float* depth, const int32_t* tc,
                       int64_t n_rec, int64_t cap, int64_t* n_isect, void* ws, hipStream_t st,
                       const uint32_t** perm_out);
-hipError_t bin_phase2(const Batch& B, int sort_mode, int tile_bits, const float* depth,
-                      const int16_t* rect, const int32_t* tc, const uint32_t* perm, int64_t n_rec,
+hipError_t bin_phase2(const Batch& B, int sort_mode, bool cull, const float* splat,
+                      int tile_bits, const float* depth, const int16_t* rect, const int32_t* tc,
+                      const uint32_t* perm, int64_t n_rec,
                       int64_t cap, int64_t grid_n, const int64_t* n_isect, uint64_t* keys_out,
                       int32_t* vals, int2* ranges, int32_t* tile_order, void* ws, size_t ws_bytes,
                       hipStream_t st);
@@ -97,6 +99,7 @@ static xpr_status check_config(const xpr_config* c) {
   XPR_CHECK(c->bwd_lds_batch == 0 || c->bwd_lds_batch == 64 || c->bwd_lds_batch == 128 ||
                 c->bwd_lds_batch == 256 || c->bwd_lds_batch == 512,
             "bwd_lds_batch %d not in {0,64,128,256,512}", c->bwd_lds_batch);
+  XPR_CHECK(c->tile_cull == 0 || c->tile_cull == 1, "tile_cull must be 0 or 1");
   return XPR_OK;
 }
 
@@ -248,6 +251,7 @@ void xpr_config_default(xpr_config* c) {
   c->bwd_ppt = 4;
   c->bwd_lds_batch = 0;
   c->persistent = 0;
+  c->tile_cull = 0;
 }
 
 xpr_status xpr_batch_sizes(const xpr_views* views, const xpr_config* cfg, xpr_sizes* out) {
@@ -287,7 +291,8 @@ xpr_status xpr_bin_sort_workspace(const xpr_views* views, const xpr_config* cfg,
   XPR_CHECK(bytes != nullptr, "bytes is NULL");
   XPR_CHECK(isect_capacity >= 0 && isect_capacity < ((int64_t)1 << 31),
             "isect_capacity out of range");
-  *bytes = bin_workspace_bytes(S.records, isect_capacity, S.tiles, cfg->sort_mode);
+  *bytes = bin_workspace_bytes(S.records, isect_capacity, S.tiles, cfg->sort_mode,
+                               cfg->tile_cull != 0);
   return XPR_OK;
 }
 
@@ -309,13 +314,14 @@ xpr_status xpr_bin_sort(const xpr_views* views, const xpr_config* cfg, const xpr
                 (!out->keys || aligned(out->keys, 8)) && (!out->vals || aligned(out->vals, 4)) &&
                 (!out->tile_order || aligned(out->tile_order, 4)),
             "misaligned output buffer");
-  const size_t need = bin_workspace_bytes(S.records, cap, S.tiles, cfg->sort_mode);
+  const bool cull = cfg->tile_cull != 0;
+  const size_t need = bin_workspace_bytes(S.records, cap, S.tiles, cfg->sort_mode, cull);
   XPR_CHECK(ws_bytes >= need && (need == 0 || ws != nullptr),
             "workspace too small: %zu < %zu bytes", ws_bytes, need);
   XPR_CHECK(aligned(ws, 256), "workspace must be 256-byte aligned");
   const uint32_t* perm = nullptr;
-  XPR_HIP(bin_phase1(B, cfg->sort_mode, proj->depth, proj->tiles_touched, S.records, cap,
-                     out->n_isect, ws, stream, &perm));
+  XPR_HIP(bin_phase1(B, cfg->sort_mode, cull, proj->splat, proj->rect, proj->depth,
+                     proj->tiles_touched, S.records, cap, out->n_isect, ws, stream, &perm));
   int64_t grid_n = cap;
   if (!cfg->no_sync) {
     int64_t I = 0;
@@ -328,7 +334,7 @@ xpr_status xpr_bin_sort(const xpr_views* views, const xpr_config* cfg, const xpr
     }
     grid_n = I;
   }
-  XPR_HIP(bin_phase2(B, cfg->sort_mode, S.tile_bits, proj->depth, proj->rect,
+  XPR_HIP(bin_phase2(B, cfg->sort_mode, cull, proj->splat, S.tile_bits, proj->depth, proj->rect,
                      proj->tiles_touched, perm, S.records, cap, grid_n, out->n_isect, out->keys,
                      out->vals, reinterpret_cast<int2*>(out->tile_ranges), out->tile_order, ws,
                      ws_bytes, stream));

@@ -91,6 +91,12 @@ struct LoadCount {  // tile counts of records, in record order
   __device__ __forceinline__ uint32_t operator()(int64_t i) const { return (uint32_t)tc[i]; }
 };
 
+struct LoadGather {  // p[idx[i]]
+  const uint32_t* p;
+  const uint32_t* idx;
+  __device__ __forceinline__ uint32_t operator()(int64_t i) const { return p[idx[i]]; }
+};
+
 template <class L>
 __global__ __launch_bounds__(256) void k_scan_reduce(L load, int64_t n, uint64_t* partials) {
   __shared__ uint64_t s_wave[4];
@@ -477,6 +483,156 @@ __global__ void k_pair_records(Batch B, const short4* __restrict__ rect,
                          (uint32_t)(rc.z - rc.x) | (tx << 16));
   for (int64_t b = (o + kSortTile - 1) / kSortTile; b * kSortTile < e; ++b) first[b] = (uint32_t)j;
   if (e == n) first[(n + kSortTile - 1) / kSortTile] = (uint32_t)j;
+}
+
+// ---------------------------------------------------------------------------
+// Per-(Gaussian, tile) cull (tile_cull of XPR-3DGS, the StopThePop-style
+// test of the XPR-3DGS section): a pair is kept iff the power
+// 0.5 (x - mu)^T conic (x - mu), minimised over the tile's pixel-sample box
+// [tx tw, tx tw + tw - 1] x [ty th, ty th + th - 1] (clipped to the image),
+// is at most log(o / alpha_min).
+//
+// Equivalently, the tile meets the ellipse E = {q(d) <= 2 log(o / alpha_min)}
+// with q(d) = a dx^2 + 2 b dx dy + c dy^2. E is convex, so in each tile row
+// the kept tiles are the ones whose x range meets the x extent [xl, xr] of
+// E inside the row's y strip, a single run of columns found in closed form:
+// from (a dx + b dy)^2 = a q - det dy^2, the chord of E at height dy spans
+// dx = (-b dy -/+ sqrt(a lvl - det dy^2)) / a, its right end is concave in
+// dy with its peak at the rightmost point of E (dy = -b ex / c), so the
+// strip's xr is that end at the peak clamped into the strip (likewise xl).
+// Evaluated in float64 from the float32 shader data, without contracted
+// multiply-adds, so that the count and emit passes (separate kernels) take
+// bit-identical decisions; a conic that is not positive definite has no
+// bounded footprint and keeps its whole rect.
+
+struct CullShape {
+  double u, v, a, b, c;  // mean2D, quadratic form of the conic
+  double det, lvl;       // a c - b^2, 2 log(o / alpha_min)
+  double ex, ey;         // half extents of E
+  double inv_a;
+  int W, H, tw, th;
+  bool pd;
+};
+
+__device__ __forceinline__ CullShape cull_shape(const Batch& B, int v, const float4 s0,
+                                                const float4 s1) {
+#pragma clang fp contract(off)
+  CullShape S;
+  S.u = s0.x;
+  S.v = s0.y;
+  S.a = -2.0 * (double)s0.z;
+  S.b = -(double)s0.w;
+  S.c = -2.0 * (double)s1.x;
+  // a c and b^2 are exact products of float32 values, so the sign of det is
+  S.det = S.a * S.c - S.b * S.b;
+  S.pd = S.a > 0.0 && S.det > 0.0;
+  S.lvl = 2.0 * log((double)s1.y / (double)B.alpha_min);
+  const double id = 1.0 / S.det;
+  S.ex = S.pd ? sqrt(S.lvl * S.c * id) : 0.0;
+  S.ey = S.pd ? sqrt(S.lvl * S.a * id) : 0.0;
+  S.inv_a = 1.0 / S.a;
+  S.W = B.v[v].W;
+  S.H = B.v[v].H;
+  S.tw = B.tile_w;
+  S.th = B.tile_h;
+  return S;
+}
+
+// Kept columns [*lo, *hi) of rect row ty (rect columns [x0, x1)).
+__device__ __forceinline__ void cull_row(const CullShape& S, int ty, int x0, int x1, int* lo,
+                                         int* hi) {
+#pragma clang fp contract(off)
+  if (!S.pd) {
+    *lo = x0;
+    *hi = x1;
+    return;
+  }
+  const double y0 = (double)ty * S.th;
+  const double y1 = fmin(y0 + (S.th - 1), (double)(S.H - 1));
+  const double d0 = fmax(y0 - S.v, -S.ey), d1 = fmin(y1 - S.v, S.ey);
+  const double aq = S.a * S.lvl;
+  const double pk = S.b * S.ex / S.c;
+  const double dr = fmin(fmax(-pk, d0), d1), dl = fmin(fmax(pk, d0), d1);
+  const double xr = S.u + (-S.b * dr + sqrt(fmax(aq - S.det * dr * dr, 0.0))) * S.inv_a;
+  const double xl = S.u + (-S.b * dl - sqrt(fmax(aq - S.det * dl * dl, 0.0))) * S.inv_a;
+  // tile tx is kept iff tx tw <= xr and min(tx tw + tw - 1, W - 1) >= xl
+  const bool none = d0 > d1 || xl > (double)(S.W - 1) || xr < 0.0;
+  const double c_hi = floor(fmin(xr, 1e6) / S.tw) + 1.0;
+  const double c_lo = ceil((fmax(xl, -1e6) - (S.tw - 1)) / S.tw);
+  const int h = min(x1, (int)c_hi), l = max(x0, (int)c_lo);
+  *lo = l;
+  *hi = none ? l : max(l, h);
+}
+
+__device__ __forceinline__ int view_of_record(const Batch& B, int r) {
+  int v = 0;
+  for (int q = 1; q < B.n_views; ++q)
+    if (r >= B.v[q].rec_off) v = q;
+  return v;
+}
+
+// Count pass of the cull: kept pairs and kept rows per record, and the
+// depth-presort keys (records keeping no pair sort last).
+__global__ void k_cull_count(Batch B, const float4* __restrict__ splat,
+                             const short4* __restrict__ rect, const int32_t* __restrict__ tc,
+                             const float* __restrict__ depth, int64_t n, uint32_t* __restrict__ kc,
+                             uint32_t* __restrict__ nrow, uint32_t* __restrict__ key,
+                             uint32_t* __restrict__ perm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t cnt = 0, rows = 0;
+  if (tc[i] > 0) {
+    const short4 rc = rect[i];
+    const CullShape S = cull_shape(B, view_of_record(B, (int)i), splat[3 * i], splat[3 * i + 1]);
+    for (int ty = rc.y; ty < rc.w; ++ty) {
+      int lo, hi;
+      cull_row(S, ty, rc.x, rc.z, &lo, &hi);
+      cnt += (uint32_t)(hi - lo);
+      rows += hi > lo ? 1u : 0u;
+    }
+  }
+  kc[i] = cnt;
+  nrow[i] = rows;
+  key[i] = cnt > 0 ? __float_as_uint(depth[i]) : 0xffffffffu;
+  perm[i] = (uint32_t)i;
+}
+
+// Emit pass of the cull, one thread per record in depth order: one packed
+// record per kept row (pair offset, record id, tile id of the row's first
+// kept tile, run length), the rows of record j at roff[j].., and first[]
+// as k_pair_records writes it.
+__global__ void k_cull_records(Batch B, const float4* __restrict__ splat,
+                               const short4* __restrict__ rect, const uint32_t* __restrict__ kcs,
+                               const uint32_t* __restrict__ perm,
+                               const uint32_t* __restrict__ offsets,
+                               const uint32_t* __restrict__ roff, int64_t n_rec,
+                               const int64_t* n_isect, int64_t cap, uint4* __restrict__ packed,
+                               uint32_t* __restrict__ first) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_rec) return;
+  const int64_t n = clamp_n(n_isect, cap);
+  int64_t o = offsets[j];
+  const int64_t e = min(o + (int64_t)kcs[j], n);
+  if (e <= o) return;
+  const uint32_t r = perm[j];
+  const int v = view_of_record(B, (int)r);
+  const short4 rc = rect[r];
+  const CullShape S = cull_shape(B, v, splat[3 * (int64_t)r], splat[3 * (int64_t)r + 1]);
+  const uint32_t tx = (uint32_t)B.v[v].tiles_x;
+  const uint32_t toff = (uint32_t)B.v[v].tile_off;
+  uint32_t k = roff[j];
+  for (int ty = rc.y; ty < rc.w && o < e; ++ty) {
+    int lo, hi;
+    cull_row(S, ty, rc.x, rc.z, &lo, &hi);
+    if (hi <= lo) continue;
+    packed[k] = make_uint4((uint32_t)o, r, toff + (uint32_t)ty * tx + (uint32_t)lo,
+                           (uint32_t)(hi - lo) | (tx << 16));
+    const int64_t oe = min(o + (int64_t)(hi - lo), e);
+    for (int64_t b = (o + kSortTile - 1) / kSortTile; b * kSortTile < oe; ++b) first[b] = k;
+    if (oe == n) first[(n + kSortTile - 1) / kSortTile] = k;
+    o = oe;
+    ++k;
+  }
 }
 
 // Up to 256 packed records of a sort block, staged in LDS: the item offset
@@ -886,8 +1042,12 @@ struct BinWs {
   uint32_t* perm[2];   // [n_rec]   (presort)
   uint32_t* tkey[2];   // [cap]     (presort)
   uint32_t* first;     // [cap / kSortTile + 2]  (presort)
-  uint4* packed;       // [n_rec]   (presort)
+  uint4* packed;       // [n_rec]   (presort); [max(n_rec, cap)] row records with the cull
   uint32_t* tcs;       // [n_rec]   tile counts in depth order (presort)
+  // per-(Gaussian, tile) cull
+  uint32_t* kc;        // [n_rec]   kept pairs per record
+  uint32_t* nrow;      // [n_rec]   kept rows per record
+  uint32_t* roff;      // [n_rec]   first row record, depth order
   // band binning
   int64_t* n_ent;      // [1] band entries
   int64_t* n_chunk;    // [1] chunks
@@ -903,7 +1063,8 @@ struct BinWs {
   size_t bytes;
 };
 
-static BinWs bin_ws_layout(int64_t n_rec, int64_t cap, int64_t tiles, int sort_mode, char* base) {
+static BinWs bin_ws_layout(int64_t n_rec, int64_t cap, int64_t tiles, int sort_mode, bool cull,
+                           char* base) {
   BinWs L{};
   size_t off = 0;
   auto take = [&](size_t bytes) -> char* {
@@ -928,8 +1089,15 @@ static BinWs bin_ws_layout(int64_t n_rec, int64_t cap, int64_t tiles, int sort_m
     for (int k = 0; k < 2; ++k) L.perm[k] = (uint32_t*)take(4 * (size_t)std::max<int64_t>(n_rec, 1));
     for (int k = 0; k < 2; ++k) L.tkey[k] = (uint32_t*)take(4 * (size_t)std::max<int64_t>(cap, 1));
     L.first = (uint32_t*)take(4 * (size_t)(cap / kSortTile + 2));
-    L.packed = (uint4*)take(16 * (size_t)std::max<int64_t>(n_rec, 1));
+    // with the cull a record yields one packed record per kept row, and every
+    // kept row holds at least one of the <= cap pairs
+    L.packed = (uint4*)take(16 * (size_t)std::max<int64_t>(cull ? std::max(n_rec, cap) : n_rec, 1));
     L.tcs = (uint32_t*)take(4 * (size_t)std::max<int64_t>(n_rec, 1));
+    if (cull) {
+      L.kc = (uint32_t*)take(4 * (size_t)std::max<int64_t>(n_rec, 1));
+      L.nrow = (uint32_t*)take(4 * (size_t)std::max<int64_t>(n_rec, 1));
+      L.roff = (uint32_t*)take(4 * (size_t)std::max<int64_t>(n_rec, 1));
+    }
     if (sort_mode == XPR_SORT_BANDS) {
       const int64_t T1 = std::max<int64_t>(tiles, 1);
       const int64_t nchunk = band_chunk_bound(cap, T1);
@@ -951,33 +1119,46 @@ static BinWs bin_ws_layout(int64_t n_rec, int64_t cap, int64_t tiles, int sort_m
   return L;
 }
 
-size_t bin_workspace_bytes(int64_t n_rec, int64_t cap, int64_t tiles, int sort_mode) {
-  return bin_ws_layout(n_rec, cap, tiles, sort_mode, nullptr).bytes;
+size_t bin_workspace_bytes(int64_t n_rec, int64_t cap, int64_t tiles, int sort_mode, bool cull) {
+  return bin_ws_layout(n_rec, cap, tiles, cull ? XPR_SORT_PRESORT : sort_mode, cull, nullptr).bytes;
 }
 
 static inline int grid1(int64_t n, int bs = 256) { return (int)((n + bs - 1) / bs); }
 
 // Phase 1: everything up to a known I (the prefix sum of the counts, in
 // depth order for the presort path). Phase 2: replication, pair sort, ranges.
-hipError_t bin_phase1(const Batch& B, int sort_mode, const float* depth, const int32_t* tc,
-                      int64_t n_rec, int64_t cap, int64_t* n_isect, void* ws, hipStream_t st,
-                      const uint32_t** perm_out) {
-  BinWs L = bin_ws_layout(n_rec, cap, B.total_tiles, sort_mode, (char*)ws);
+hipError_t bin_phase1(const Batch& B, int sort_mode, bool cull, const float* splat,
+                      const int16_t* rect, const float* depth, const int32_t* tc,
+                      int64_t n_rec, int64_t cap,
+                      int64_t* n_isect, void* ws, hipStream_t st, const uint32_t** perm_out) {
+  if (cull) sort_mode = XPR_SORT_PRESORT;
+  BinWs L = bin_ws_layout(n_rec, cap, B.total_tiles, sort_mode, cull, (char*)ws);
   *perm_out = nullptr;
   if (n_rec == 0) {
     hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, st, n_isect, (int64_t)0);
     return hipGetLastError();
   }
   if (sort_mode == XPR_SORT_PRESORT || sort_mode == XPR_SORT_BANDS) {
-    hipLaunchKernelGGL(k_depth_keys, dim3(grid1(n_rec)), dim3(256), 0, st, depth, tc, n_rec,
-                       L.dkey[0], L.perm[0]);
+    const int32_t* counts = tc;
+    if (cull) {
+      hipLaunchKernelGGL(k_cull_count, dim3(grid1(n_rec)), dim3(256), 0, st, B,
+                         reinterpret_cast<const float4*>(splat),
+                         reinterpret_cast<const short4*>(rect), tc, depth, n_rec, L.kc,
+                         L.nrow, L.dkey[0], L.perm[0]);
+      counts = reinterpret_cast<const int32_t*>(L.kc);
+    } else {
+      hipLaunchKernelGGL(k_depth_keys, dim3(grid1(n_rec)), dim3(256), 0, st, depth, tc, n_rec,
+                         L.dkey[0], L.perm[0]);
+    }
     uint32_t *ko, *vo;
     hipError_t e = radix_sort<uint32_t>(L.dkey[0], L.perm[0], L.dkey[1], L.perm[1], nullptr, n_rec,
                                         n_rec, 32, L.counts, L.partials, &ko, &vo, st, 0, nullptr,
-                                        true, tc, L.tcs);
+                                        true, counts, L.tcs);
     if (e != hipSuccess) return e;
     *perm_out = vo;
-    return device_scan(LoadArray{L.tcs}, n_rec, L.offsets, L.partials, n_isect, st);
+    e = device_scan(LoadArray{L.tcs}, n_rec, L.offsets, L.partials, n_isect, st);
+    if (e != hipSuccess || !cull) return e;
+    return device_scan(LoadGather{L.nrow, vo}, n_rec, L.roff, L.partials, nullptr, st);
   }
   return device_scan(LoadCount{tc}, n_rec, L.offsets, L.partials, n_isect, st);
 }
@@ -1017,7 +1198,8 @@ static inline bool tiles_16bit(int64_t tiles) { return tiles <= 65536; }
 // the caller's vals.
 template <typename KT>
 static hipError_t pair_sort(const Batch& B, int tile_bits, const float* depth, const short4* rc,
-                            const uint32_t* perm, int64_t n_rec, int64_t cap, int64_t grid_n,
+                            const float* splat, const uint32_t* perm, int64_t n_rec, int64_t cap,
+                            int64_t grid_n,
                             const int64_t* n_isect, uint64_t* keys_out, uint32_t* vals_u,
                             int2* ranges, const BinWs& L, hipStream_t st) {
   const int dbits = radix_digit_bits(tile_bits);
@@ -1029,8 +1211,13 @@ static hipError_t pair_sort(const Batch& B, int tile_bits, const float* depth, c
   KT* tk1 = reinterpret_cast<KT*>(L.tkey[1]);
   const int tiles = B.total_tiles;
   hipLaunchKernelGGL(k_ranges_init, dim3(grid1(tiles)), dim3(256), 0, st, ranges, tiles);
-  hipLaunchKernelGGL(k_pair_records, dim3(grid1(n_rec)), dim3(256), 0, st, B, rc, L.tcs, perm,
-                     L.offsets, n_rec, n_isect, cap, L.packed, L.first);
+  if (splat)  // per-(Gaussian, tile) cull: one record per kept row
+    hipLaunchKernelGGL(k_cull_records, dim3(grid1(n_rec)), dim3(256), 0, st, B,
+                       reinterpret_cast<const float4*>(splat), rc, L.tcs, perm, L.offsets, L.roff,
+                       n_rec, n_isect, cap, L.packed, L.first);
+  else
+    hipLaunchKernelGGL(k_pair_records, dim3(grid1(n_rec)), dim3(256), 0, st, B, rc, L.tcs, perm,
+                       L.offsets, n_rec, n_isect, cap, L.packed, L.first);
   const int nb = (int)((grid_n + kSortTile - 1) / kSortTile);
   KT* k1 = (one && !keys_out) ? nullptr : tk0;
   if (dbits == 7)
@@ -1416,13 +1603,16 @@ static hipError_t band_sort(const Batch& B, const float* depth, const short4* rc
   return hipGetLastError();
 }
 
-hipError_t bin_phase2(const Batch& B, int sort_mode, int tile_bits, const float* depth,
-                      const int16_t* rect, const int32_t* tc, const uint32_t* perm, int64_t n_rec,
+hipError_t bin_phase2(const Batch& B, int sort_mode, bool cull, const float* splat,
+                      int tile_bits, const float* depth, const int16_t* rect, const int32_t* tc,
+                      const uint32_t* perm, int64_t n_rec,
                       int64_t cap, int64_t grid_n, const int64_t* n_isect, uint64_t* keys_out,
                       int32_t* vals, int2* ranges, int32_t* tile_order, void* ws, size_t ws_bytes,
                       hipStream_t st) {
   (void)ws_bytes;
-  BinWs L = bin_ws_layout(n_rec, cap, B.total_tiles, sort_mode, (char*)ws);
+  if (cull) sort_mode = XPR_SORT_PRESORT;
+  BinWs L = bin_ws_layout(n_rec, cap, B.total_tiles, sort_mode, cull, (char*)ws);
+  const float* cull_splat = cull ? splat : nullptr;
   hipLaunchKernelGGL(k_fill_u32, dim3(grid1(2 * (int64_t)B.total_tiles)), dim3(256), 0, st,
                      (uint32_t*)ranges, 2 * (int64_t)B.total_tiles, 0u);
   if (n_rec == 0 || grid_n == 0) {
@@ -1439,10 +1629,10 @@ hipError_t bin_phase2(const Batch& B, int sort_mode, int tile_bits, const float*
   } else if (sort_mode == XPR_SORT_PRESORT || sort_mode == XPR_SORT_BANDS) {
     const hipError_t e =
         tiles_16bit(B.total_tiles)
-            ? pair_sort<uint16_t>(B, tile_bits, depth, rc, perm, n_rec, cap, grid_n, n_isect,
-                                  keys_out, vals_u, ranges, L, st)
-            : pair_sort<uint32_t>(B, tile_bits, depth, rc, perm, n_rec, cap, grid_n, n_isect,
-                                  keys_out, vals_u, ranges, L, st);
+            ? pair_sort<uint16_t>(B, tile_bits, depth, rc, cull_splat, perm, n_rec, cap, grid_n,
+                                  n_isect, keys_out, vals_u, ranges, L, st)
+            : pair_sort<uint32_t>(B, tile_bits, depth, rc, cull_splat, perm, n_rec, cap, grid_n,
+                                  n_isect, keys_out, vals_u, ranges, L, st);
     if (e != hipSuccess) return e;
   } else {
     const int bits = 32 + tile_bits;

@@ -37,6 +37,7 @@ class Config:
     bwd_lds_batch: int = 0      # LDS batch of the backward (0: lds_batch)
     persistent: bool = False    # persistent render grids over the tile order
     tile_order: bool = False    # launch tiles longest list first (implied by persistent)
+    tile_cull: bool = False     # per-(Gaussian, tile) cull of XPR-3DGS in the binning
 
     def to_c(self) -> L.XprConfig:
         c = L.XprConfig()
@@ -60,6 +61,7 @@ class Config:
         c.bwd_ppt = int(self.bwd_ppt)
         c.bwd_lds_batch = int(self.bwd_lds_batch)
         c.persistent = 1 if self.persistent else 0
+        c.tile_cull = 1 if self.tile_cull else 0
         return c
 
 

@@ -142,6 +142,36 @@ def check_binning(gpu, tiles_x_total_tiles, rec_sel=None):
     return ref
 
 
+def check_binning_cull(gpu, cam, cfg, tiles_x_y):
+    """Binning with the per-(Gaussian, tile) cull: the oracle replicates the
+    GPU's rects, applies tile_cull to every pair on the GPU's float32 splat
+    (as float64) and sorts culled pairs to its sentinel tile; the GPU's lists
+    must be the oracle's kept pairs, bit-exact. A pair whose decision is in
+    the oracle's guard band may go either way: then every GPU pair must be
+    kept or guard, and all kept non-guard pairs must be there."""
+    tx, ty = tiles_x_y
+    oc = ocfg_of(cfg)
+    ref = oracle.bin_pairs(gpu["depth"].astype(np.float64), gpu["rect"], gpu["tc"], tx, ty,
+                           (rec9(gpu["splat"]), cam.width, cam.height, oc))
+    n = ref["I_kept"]
+    if ref["n_guard"] == 0:
+        assert gpu["I"] == n, (gpu["I"], n)
+        assert np.array_equal(gpu["vals"], ref["vals"][:n]), "vals differ"
+        if gpu["keys"] is not None:
+            assert np.array_equal(gpu["keys"], ref["keys"][:n]), "keys differ"
+        assert np.array_equal(gpu["ranges"], ref["ranges"]), "ranges differ"
+        return ref
+    lens = gpu["ranges"][:, 1] - gpu["ranges"][:, 0]
+    tid = np.repeat(np.arange(tx * ty), lens)
+    keep, _, _, g = oracle.tile_cull(rec9(gpu["splat"])[gpu["vals"]], np.stack([tid % tx, tid // tx], 1),
+                                     cam.width, cam.height, oc)
+    assert np.all(keep | g), "GPU kept a pair the oracle culls"
+    assert int((keep & ~g).sum()) == n - int(ref["pair_guard"][:n].sum())
+    if gpu["keys"] is not None:
+        assert np.all(gpu["keys"][1:] >= gpu["keys"][:-1])
+    return ref
+
+
 # ---- P3: forward compositing -------------------------------------------
 
 def check_forward(gpu, cam, cfg, v=0, ranges=None, pixel_mask=None):
