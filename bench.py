@@ -55,6 +55,9 @@ def main():
     ap.add_argument("--bwd-ppt", type=int, default=None)
     ap.add_argument("--bwd-lds-batch", type=int, default=None)
     ap.add_argument("--schedule", choices=("index", "longest_first", "persistent"), default=None)
+    ap.add_argument("--tile-cull", action="store_true",
+                    help="time the per-(Gaussian, tile) cull in the main line")
+    ap.add_argument("--no-cull-line", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -81,6 +84,8 @@ def main():
     if args.schedule is not None:
         cfg = dataclasses.replace(cfg, tile_order=args.schedule != "index",
                                   persistent=args.schedule == "persistent")
+    if args.tile_cull:
+        cfg = dataclasses.replace(cfg, tile_cull=True)
     scene = R.Scene.from_host(sc, dev)
     tuned = None
     if not args.no_autotune:
@@ -97,15 +102,6 @@ def main():
     gen.manual_seed(7)
     H, W = args.height, args.width
     targets = [torch.rand((3, H, W), generator=gen, device=dev) for _ in cams]
-    views = [R.Views([scene], [c], [0], cfg) for c in cams]
-    proj = R.empty_projected(scene.n, dev)
-    frame = None
-    tw = torch.zeros(views[0].tiles, dtype=torch.int32, device=dev)
-    g2 = torch.empty((scene.n, 9), dtype=torch.float32, device=dev)
-    grads = [scene.zeros_like_grads()]
-    ws = R.Workspace()
-    loss_buf = torch.empty(1, dtype=torch.float32, device=dev)
-    dimg_buf = torch.empty(3 * H * W, dtype=torch.float32, device=dev)
 
     # A plain copy of known size (256 MiB read + 256 MiB written), so that
     # hardware byte counters of a profiled run can be calibrated against it.
@@ -115,80 +111,10 @@ def main():
     torch.cuda.synchronize()
     del calib, calib_dst
 
-    # Capacity for the pair list: one pass over the cameras, +10%.
-    cap = 0
-    for v in views:
-        R.xpr_project(v, cfg, out=proj)
-        b = R.xpr_bin_sort(v, cfg, proj, ws=ws)
-        cap = max(cap, b.count)
-    cap = int(cap * 1.1) + 4096
-    bins = R.xpr_bin_sort(views[0], cfg, proj, capacity=cap, ws=ws)
-    log(f"[bench] pair capacity {cap}")
-
     names = ["project", "bin_sort", "render_fwd", "loss", "render_bwd", "project_bwd"]
-    n_ev = len(names) + 1
-    ev_all = [[torch.cuda.Event(enable_timing=True) for _ in range(n_ev)]
-              for _ in range(args.steps + 1)]
-    ev = ev_all[-1]
-    stage_ms = {k: [] for k in names}
-    work = {"fwd": [], "bwd": [], "pairs": [], "visible": []}
-
-    def step(k, ev):
-        nonlocal bins, frame
-        v = views[k % len(views)]
-        ev[0].record()
-        R.xpr_project(v, cfg, out=proj)
-        ev[1].record()
-        bins = R.xpr_bin_sort(v, cfg, proj, capacity=cap, ws=ws, out=bins)
-        ev[2].record()
-        frame = R.xpr_render_fwd(v, cfg, proj, bins, out=frame, tile_work=tw)
-        ev[3].record()
-        img = v.image(frame.image, 0).reshape(-1)
-        loss, dimg = R.xpr_l1_loss(img, targets[k % len(views)].reshape(-1), loss=loss_buf,
-                                   dimage=dimg_buf)
-        ev[4].record()
-        R.xpr_render_bwd(v, cfg, proj, bins, frame, dimg, params=False, grad2d=g2, ws=ws)
-        ev[5].record()
-        R.xpr_project_bwd(v, cfg, proj, g2, grads=grads)
-        ev[6].record()
-        return loss
-
-    for k in range(args.warmup):
-        step(k, ev)
-    torch.cuda.synchronize()
-    log(f"[bench] warmup done ({args.warmup} steps)")
-
-    # Timed region: exactly K steps bracketed by device synchronisation.
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        step(args.warmup + k, ev_all[k])
-    torch.cuda.synchronize()
-    t_end = time.perf_counter()
-    for k in range(args.steps):
-        for i, name in enumerate(names):
-            stage_ms[name].append(ev_all[k][i].elapsed_time(ev_all[k][i + 1]))
-    log(f"[bench] timed {args.steps} steps")
-    ms_wall = (t_end - t_start) * 1e3 / args.steps
-
-    # Work per camera (deterministic), outside the timed region.
-    tiles_x = (W + args.tile - 1) // args.tile
-    tiles_y = (H + args.tile - 1) // args.tile
-    npx = args.tile * args.tile
-    for k in range(len(views)):
-        v = views[k]
-        R.xpr_project(v, cfg, out=proj)
-        bins = R.xpr_bin_sort(v, cfg, proj, capacity=cap, ws=ws, out=bins)
-        frame = R.xpr_render_fwd(v, cfg, proj, bins, out=frame, tile_work=tw)
-        nc = v.plane(frame.n_contrib, 0)
-        pad = torch.zeros((tiles_y * args.tile, tiles_x * args.tile), dtype=torch.int32, device=dev)
-        pad[:H, :W] = nc
-        tmax = pad.view(tiles_y, args.tile, tiles_x, args.tile).amax(dim=(1, 3))
-        work["fwd"].append(float(tw.sum().item()) * npx)
-        work["bwd"].append(float(tmax.sum().item()) * npx)
-        work["pairs"].append(bins.count)
-        work["visible"].append(int((proj.tc[:scene.n] > 0).sum().item()))
-    order = [(args.warmup + k) % len(views) for k in range(args.steps)]
+    run = timed_frames(scene, cams, cfg, targets, args.steps, args.warmup, args.tile, names)
+    ms_wall, stage_ms, work = run["ms_wall"], run["stage_ms"], run["work"]
+    order = [(args.warmup + k) % len(cams) for k in range(args.steps)]
     evals_fwd = float(np.mean([work["fwd"][c] for c in order]))
     evals_bwd = float(np.mean([work["bwd"][c] for c in order]))
     pairs = float(np.mean([work["pairs"][c] for c in order]))
@@ -248,6 +174,7 @@ def main():
                    "schedule": ("persistent" if cfg.persistent else
                                 "longest_first" if cfg.tile_order else "index"),
                    "autotuned": tuned is not None,
+                   "tile_cull": cfg.tile_cull,
                    "pairs_per_frame": pairs},
         "stage_sum_ms": round(frame_ms, 4),
         "stages_ms_median": med,
@@ -256,7 +183,21 @@ def main():
     }
     log(f"[bench] frame {frame_ms:.3f} ms (stage sum), wall {ms_wall:.3f} ms/step")
 
-    del scene, proj, bins, frame, g2, grads, targets, views
+    if not args.no_cull_line and not cfg.tile_cull:
+        # the paper's per-(Gaussian, tile) cull (opt-in) on the same frames
+        ccfg = dataclasses.replace(cfg, tile_cull=True)
+        cr = timed_frames(scene, cams, ccfg, targets, args.steps, args.warmup, args.tile, names)
+        cmean = {k: float(np.mean(v)) for k, v in cr["stage_ms"].items()}
+        cpairs = float(np.mean([cr["work"]["pairs"][c] for c in order]))
+        out["tile_cull"] = {"ms_per_step": round(cr["ms_wall"], 4),
+                            "stage_sum_ms": round(float(np.mean(np.sum(
+                                [cr["stage_ms"][k] for k in names], axis=0))), 4),
+                            "stages_ms_mean": cmean, "pairs_per_frame": cpairs,
+                            "pairs_kept_frac": cpairs / pairs,
+                            "speedup": ms_wall / cr["ms_wall"]}
+        log(f"[bench] tile_cull: {cr['ms_wall']:.3f} ms/step, pairs {cpairs:.0f} "
+            f"({cpairs / pairs:.3f} of {pairs:.0f})")
+    del scene, targets
     torch.cuda.empty_cache()
     if not args.no_batch:
         out["batched"] = bench_batched()
@@ -267,6 +208,104 @@ def main():
     if tuned is not None:
         out["autotune_ms"] = tuned.ms
     print(json.dumps(out), flush=True)
+
+
+def timed_frames(scene, cams, cfg, targets, steps, warmup, tile, names):
+    """K timed frames (after W untimed ones) cycling over the cameras, each
+    project -> bin_sort -> render_fwd -> L1 loss -> render_bwd -> project_bwd
+    with buffers allocated beforehand; per-stage HIP-event times and the
+    deterministic work of each camera (outside the timed region)."""
+    import torch
+
+    from paper_2606_11529_amd import renderer as R
+
+    dev = torch.device("cuda:0")
+    H, W = targets[0].shape[1], targets[0].shape[2]
+    views = [R.Views([scene], [c], [0], cfg) for c in cams]
+    proj = R.empty_projected(scene.n, dev)
+    frame = None
+    tw = torch.zeros(views[0].tiles, dtype=torch.int32, device=dev)
+    g2 = torch.empty((scene.n, 9), dtype=torch.float32, device=dev)
+    grads = [scene.zeros_like_grads()]
+    ws = R.Workspace()
+    loss_buf = torch.empty(1, dtype=torch.float32, device=dev)
+    dimg_buf = torch.empty(3 * H * W, dtype=torch.float32, device=dev)
+
+    # Capacity for the pair list: one pass over the cameras, +10%.
+    cap = 0
+    for v in views:
+        R.xpr_project(v, cfg, out=proj)
+        b = R.xpr_bin_sort(v, cfg, proj, ws=ws)
+        cap = max(cap, b.count)
+    cap = int(cap * 1.1) + 4096
+    bins = R.xpr_bin_sort(views[0], cfg, proj, capacity=cap, ws=ws)
+    log(f"[bench] pair capacity {cap}")
+
+    n_ev = len(names) + 1
+    ev_all = [[torch.cuda.Event(enable_timing=True) for _ in range(n_ev)]
+              for _ in range(steps + 1)]
+    ev = ev_all[-1]
+    stage_ms = {k: [] for k in names}
+    work = {"fwd": [], "bwd": [], "pairs": [], "visible": []}
+
+    def step(k, ev):
+        nonlocal bins, frame
+        v = views[k % len(views)]
+        ev[0].record()
+        R.xpr_project(v, cfg, out=proj)
+        ev[1].record()
+        bins = R.xpr_bin_sort(v, cfg, proj, capacity=cap, ws=ws, out=bins)
+        ev[2].record()
+        frame = R.xpr_render_fwd(v, cfg, proj, bins, out=frame, tile_work=tw)
+        ev[3].record()
+        img = v.image(frame.image, 0).reshape(-1)
+        loss, dimg = R.xpr_l1_loss(img, targets[k % len(views)].reshape(-1), loss=loss_buf,
+                                   dimage=dimg_buf)
+        ev[4].record()
+        R.xpr_render_bwd(v, cfg, proj, bins, frame, dimg, params=False, grad2d=g2, ws=ws)
+        ev[5].record()
+        R.xpr_project_bwd(v, cfg, proj, g2, grads=grads)
+        ev[6].record()
+        return loss
+
+    for k in range(warmup):
+        step(k, ev)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup done ({warmup} steps)")
+
+    # Timed region: exactly K steps bracketed by device synchronisation.
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(steps):
+        step(warmup + k, ev_all[k])
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    for k in range(steps):
+        for i, name in enumerate(names):
+            stage_ms[name].append(ev_all[k][i].elapsed_time(ev_all[k][i + 1]))
+    log(f"[bench] timed {steps} steps")
+    ms_wall = (t_end - t_start) * 1e3 / steps
+
+    # Work per camera (deterministic), outside the timed region.
+    tiles_x = (W + tile - 1) // tile
+    tiles_y = (H + tile - 1) // tile
+    npx = tile * tile
+    for k in range(len(views)):
+        v = views[k]
+        R.xpr_project(v, cfg, out=proj)
+        bins = R.xpr_bin_sort(v, cfg, proj, capacity=cap, ws=ws, out=bins)
+        frame = R.xpr_render_fwd(v, cfg, proj, bins, out=frame, tile_work=tw)
+        nc = v.plane(frame.n_contrib, 0)
+        pad = torch.zeros((tiles_y * tile, tiles_x * tile), dtype=torch.int32, device=dev)
+        pad[:H, :W] = nc
+        tmax = pad.view(tiles_y, tile, tiles_x, tile).amax(dim=(1, 3))
+        work["fwd"].append(float(tw.sum().item()) * npx)
+        work["bwd"].append(float(tmax.sum().item()) * npx)
+        work["pairs"].append(bins.count)
+        work["visible"].append(int((proj.tc[:scene.n] > 0).sum().item()))
+    del proj, bins, frame, g2, grads, views, ws
+    torch.cuda.empty_cache()
+    return dict(ms_wall=ms_wall, stage_ms=stage_ms, work=work, cap=cap)
 
 
 def bench_batched(n=2_000_000, n_views=16, reps=5):

@@ -34,6 +34,28 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
   return x;
 }
 
+// Inclusive scan over the 64 lanes with DPP (no LDS crossbar): prefix sums
+// inside each row of 16 lanes (row_shr 1, 2, 4, 8, sources outside the row
+// read 0), then row 0's total into row 1 and row 2's into row 3
+// (row_bcast:15), then the total of rows 0-1 into rows 2 and 3
+// (row_bcast:31). Every lane must be active.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ uint32_t dpp_u(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xf, true);
+}
+__device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t x) {
+  x += dpp_u<0x111>(x);
+  x += dpp_u<0x112>(x);
+  x += dpp_u<0x114>(x);
+  x += dpp_u<0x118>(x);
+  x += dpp_u<0x142, 0xa>(x);
+  x += dpp_u<0x143, 0xc>(x);
+  return x;
+}
+__device__ __forceinline__ uint32_t lane63_u(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
 // Exclusive scan of one value per thread over a 256-thread block.
 __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t* s_wave,
                                                        uint32_t* total) {
@@ -91,6 +113,16 @@ struct LoadCount {  // tile counts of records, in record order
   __device__ __forceinline__ uint32_t operator()(int64_t i) const { return (uint32_t)tc[i]; }
 };
 
+struct LoadMask {  // p[i] & m
+  const uint32_t* p;
+  uint32_t m;
+  __device__ __forceinline__ uint32_t operator()(int64_t i) const { return p[i] & m; }
+};
+struct LoadShift {  // p[i] >> s
+  const uint32_t* p;
+  int s;
+  __device__ __forceinline__ uint32_t operator()(int64_t i) const { return p[i] >> s; }
+};
 struct LoadGather {  // p[idx[i]]
   const uint32_t* p;
   const uint32_t* idx;
@@ -505,65 +537,6 @@ __global__ void k_pair_records(Batch B, const short4* __restrict__ rect,
 // bit-identical decisions; a conic that is not positive definite has no
 // bounded footprint and keeps its whole rect.
 
-struct CullShape {
-  double u, v, a, b, c;  // mean2D, quadratic form of the conic
-  double det, lvl;       // a c - b^2, 2 log(o / alpha_min)
-  double ex, ey;         // half extents of E
-  double inv_a;
-  int W, H, tw, th;
-  bool pd;
-};
-
-__device__ __forceinline__ CullShape cull_shape(const Batch& B, int v, const float4 s0,
-                                                const float4 s1) {
-#pragma clang fp contract(off)
-  CullShape S;
-  S.u = s0.x;
-  S.v = s0.y;
-  S.a = -2.0 * (double)s0.z;
-  S.b = -(double)s0.w;
-  S.c = -2.0 * (double)s1.x;
-  // a c and b^2 are exact products of float32 values, so the sign of det is
-  S.det = S.a * S.c - S.b * S.b;
-  S.pd = S.a > 0.0 && S.det > 0.0;
-  S.lvl = 2.0 * log((double)s1.y / (double)B.alpha_min);
-  const double id = 1.0 / S.det;
-  S.ex = S.pd ? sqrt(S.lvl * S.c * id) : 0.0;
-  S.ey = S.pd ? sqrt(S.lvl * S.a * id) : 0.0;
-  S.inv_a = 1.0 / S.a;
-  S.W = B.v[v].W;
-  S.H = B.v[v].H;
-  S.tw = B.tile_w;
-  S.th = B.tile_h;
-  return S;
-}
-
-// Kept columns [*lo, *hi) of rect row ty (rect columns [x0, x1)).
-__device__ __forceinline__ void cull_row(const CullShape& S, int ty, int x0, int x1, int* lo,
-                                         int* hi) {
-#pragma clang fp contract(off)
-  if (!S.pd) {
-    *lo = x0;
-    *hi = x1;
-    return;
-  }
-  const double y0 = (double)ty * S.th;
-  const double y1 = fmin(y0 + (S.th - 1), (double)(S.H - 1));
-  const double d0 = fmax(y0 - S.v, -S.ey), d1 = fmin(y1 - S.v, S.ey);
-  const double aq = S.a * S.lvl;
-  const double pk = S.b * S.ex / S.c;
-  const double dr = fmin(fmax(-pk, d0), d1), dl = fmin(fmax(pk, d0), d1);
-  const double xr = S.u + (-S.b * dr + sqrt(fmax(aq - S.det * dr * dr, 0.0))) * S.inv_a;
-  const double xl = S.u + (-S.b * dl - sqrt(fmax(aq - S.det * dl * dl, 0.0))) * S.inv_a;
-  // tile tx is kept iff tx tw <= xr and min(tx tw + tw - 1, W - 1) >= xl
-  const bool none = d0 > d1 || xl > (double)(S.W - 1) || xr < 0.0;
-  const double c_hi = floor(fmin(xr, 1e6) / S.tw) + 1.0;
-  const double c_lo = ceil((fmax(xl, -1e6) - (S.tw - 1)) / S.tw);
-  const int h = min(x1, (int)c_hi), l = max(x0, (int)c_lo);
-  *lo = l;
-  *hi = none ? l : max(l, h);
-}
-
 __device__ __forceinline__ int view_of_record(const Batch& B, int r) {
   int v = 0;
   for (int q = 1; q < B.n_views; ++q)
@@ -571,77 +544,218 @@ __device__ __forceinline__ int view_of_record(const Batch& B, int r) {
   return v;
 }
 
-// Count pass of the cull: kept pairs and kept rows per record, and the
-// depth-presort keys (records keeping no pair sort last).
-__global__ void k_cull_count(Batch B, const float4* __restrict__ splat,
-                             const short4* __restrict__ rect, const int32_t* __restrict__ tc,
-                             const float* __restrict__ depth, int64_t n, uint32_t* __restrict__ kc,
-                             uint32_t* __restrict__ nrow, uint32_t* __restrict__ key,
-                             uint32_t* __restrict__ perm) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  uint32_t cnt = 0, rows = 0;
-  if (tc[i] > 0) {
-    const short4 rc = rect[i];
-    const CullShape S = cull_shape(B, view_of_record(B, (int)i), splat[3 * i], splat[3 * i + 1]);
-    for (int ty = rc.y; ty < rc.w; ++ty) {
-      int lo, hi;
-      cull_row(S, ty, rc.x, rc.z, &lo, &hi);
-      cnt += (uint32_t)(hi - lo);
-      rows += hi > lo ? 1u : 0u;
-    }
+struct RowGeom {
+  double u, v, b, det;  // mean2D, conic entry b, det = a c - b^2
+  double aq, pk, ey;    // a lvl, b ex / c, half height of E
+  double inv_a;
+  int32_t x0, x1, y0, pd;  // rect columns [x0, x1), first rect row, positive definite
+  int32_t wm1, hm1;        // W - 1, H - 1 of the view
+  int32_t rec, tile0;      // record id, tile id of the view's tile (0, 0)
+  int32_t tiles_x, pad;
+};
+
+// Cull constants of one record (lvl = 2 log(o / alpha_min), ex the half
+// width of E).
+__device__ __forceinline__ RowGeom row_geom(const Batch& B, int r, const float4 s0,
+                                            const float4 s1, const short4 rc) {
+#pragma clang fp contract(off)
+  RowGeom G;
+  const int v = view_of_record(B, r);
+  const double a = -2.0 * (double)s0.z, b = -(double)s0.w, c = -2.0 * (double)s1.x;
+  G.u = s0.x;
+  G.v = s0.y;
+  G.b = b;
+  // a c and b^2 are exact products of float32 values, so the sign of det is
+  G.det = a * c - b * b;
+  G.pd = a > 0.0 && G.det > 0.0 ? 1 : 0;
+  const double lvl = 2.0 * log((double)s1.y / (double)B.alpha_min);
+  const double id = 1.0 / G.det;
+  const double ex = G.pd ? sqrt(lvl * c * id) : 0.0;
+  G.ey = G.pd ? sqrt(lvl * a * id) : 0.0;
+  G.aq = a * lvl;
+  G.pk = b * ex / c;
+  G.inv_a = 1.0 / a;
+  G.x0 = rc.x;
+  G.x1 = rc.z;
+  G.y0 = rc.y;
+  G.wm1 = B.v[v].W - 1;
+  G.hm1 = B.v[v].H - 1;
+  G.rec = r;
+  G.tile0 = B.v[v].tile_off;
+  G.tiles_x = B.v[v].tiles_x;
+  G.pad = 0;
+  return G;
+}
+
+// Kept columns [*lo, *hi) of rect row ty. Tile sizes are powers of two, so
+// the scalings by 1 / tw are exact.
+__device__ __forceinline__ void cull_row(const RowGeom& G, int ty, int tw, int th, double inv_tw,
+                                         int* lo, int* hi) {
+#pragma clang fp contract(off)
+  if (!G.pd) {
+    *lo = G.x0;
+    *hi = G.x1;
+    return;
   }
-  kc[i] = cnt;
-  nrow[i] = rows;
-  key[i] = cnt > 0 ? __float_as_uint(depth[i]) : 0xffffffffu;
+  const double y0 = (double)ty * th;
+  const double y1 = fmin(y0 + (th - 1), (double)G.hm1);
+  const double d0 = fmax(y0 - G.v, -G.ey), d1 = fmin(y1 - G.v, G.ey);
+  const double dr = fmin(fmax(-G.pk, d0), d1), dl = fmin(fmax(G.pk, d0), d1);
+  const double xr = G.u + (-G.b * dr + sqrt(fmax(G.aq - G.det * dr * dr, 0.0))) * G.inv_a;
+  const double xl = G.u + (-G.b * dl - sqrt(fmax(G.aq - G.det * dl * dl, 0.0))) * G.inv_a;
+  // tile tx is kept iff tx tw <= xr and min(tx tw + tw - 1, W - 1) >= xl
+  const bool none = d0 > d1 || xl > (double)G.wm1 || xr < 0.0;
+  const double c_hi = floor(fmin(xr, 1e6) * inv_tw) + 1.0;
+  const double c_lo = ceil((fmax(xl, -1e6) - (tw - 1)) * inv_tw);
+  const int h = min(G.x1, (int)c_hi), l = max(G.x0, (int)c_lo);
+  *lo = l;
+  *hi = none ? l : max(l, h);
+}
+
+// The rows of the rects of a wave's 64 records, spread over its lanes: lane
+// l's record has h rows (0 when it keeps nothing), pre = the wave's
+// exclusive scan of h, and item q of the flattened row sequence belongs to
+// the last record g with pre[g] <= q. Calls f(g, ty, lo, hi) for every item
+// of every chunk of 64 (valid = false past the end, then lo = hi); the loop
+// is wave-uniform. geo / pre are this wave's 64 LDS entries.
+template <class F>
+__device__ __forceinline__ void wave_rows(const RowGeom* geo, const uint32_t* pre, uint32_t total,
+                                          int tw, int th, F f) {
+  const int lane = threadIdx.x & 63;
+  const double inv_tw = 1.0 / tw;
+  for (uint32_t base = 0; base < total; base += 64) {
+    const uint32_t q = base + (uint32_t)lane;
+    int g = 0, lo = 0, hi = 0, ty = 0;
+    const bool valid = q < total;
+    if (valid) {
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1)
+        if (pre[g + step] <= q) g += step;
+      ty = geo[g].y0 + (int)(q - pre[g]);
+      cull_row(geo[g], ty, tw, th, inv_tw, &lo, &hi);
+    }
+    f(valid, g, ty, lo, hi);
+  }
+}
+
+// Count pass of the cull (record order): kept pairs kc and kept rows per
+// record, written as kc | rows << pack_bits (pack_bits > 0) or to two arrays,
+// and the depth-presort keys (records keeping no pair sort last).
+__global__ __launch_bounds__(256) void k_cull_count(Batch B, const float4* __restrict__ splat,
+                                                    const short4* __restrict__ rect,
+                                                    const int32_t* __restrict__ tc,
+                                                    const float* __restrict__ depth, int64_t n,
+                                                    int pack_bits, uint32_t* __restrict__ kc,
+                                                    uint32_t* __restrict__ nrow,
+                                                    uint32_t* __restrict__ key,
+                                                    uint32_t* __restrict__ perm) {
+  __shared__ RowGeom geo[256];
+  __shared__ uint32_t pre[256], s_kc[256], s_nr[256];
+  const int t = threadIdx.x, wb = t & ~63;
+  const int64_t i = (int64_t)blockIdx.x * 256 + t;
+  uint32_t h = 0;
+  if (i < n && tc[i] > 0) {
+    const short4 rc = rect[i];
+    geo[t] = row_geom(B, (int)i, splat[3 * i], splat[3 * i + 1], rc);
+    h = (uint32_t)(rc.w - rc.y);
+  }
+  s_kc[t] = 0;
+  s_nr[t] = 0;
+  const uint32_t inc = wave_incl_scan_dpp(h);
+  pre[t] = inc - h;
+  const uint32_t total = lane63_u(inc);
+  __syncthreads();
+  wave_rows(geo + wb, pre + wb, total, B.tile_w, B.tile_h,
+            [&](bool valid, int g, int, int lo, int hi) {
+              if (valid && hi > lo) {
+                atomicAdd(&s_kc[wb + g], (uint32_t)(hi - lo));
+                atomicAdd(&s_nr[wb + g], 1u);
+              }
+            });
+  __syncthreads();
+  if (i >= n) return;
+  const uint32_t c = s_kc[t], rows = s_nr[t];
+  if (pack_bits > 0) {
+    kc[i] = c | (rows << pack_bits);
+  } else {
+    kc[i] = c;
+    nrow[i] = rows;
+  }
+  key[i] = c > 0 ? __float_as_uint(depth[i]) : 0xffffffffu;
   perm[i] = (uint32_t)i;
 }
 
-// Emit pass of the cull, one thread per record in depth order: one packed
-// record per kept row (pair offset, record id, tile id of the row's first
-// kept tile, run length), the rows of record j at roff[j].., and first[]
-// as k_pair_records writes it.
-__global__ void k_cull_records(Batch B, const float4* __restrict__ splat,
-                               const short4* __restrict__ rect, const uint32_t* __restrict__ kcs,
-                               const uint32_t* __restrict__ perm,
-                               const uint32_t* __restrict__ offsets,
-                               const uint32_t* __restrict__ roff, int64_t n_rec,
-                               const int64_t* n_isect, int64_t cap, uint4* __restrict__ packed,
-                               uint32_t* __restrict__ first) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n_rec) return;
-  const int64_t n = clamp_n(n_isect, cap);
-  int64_t o = offsets[j];
-  const int64_t e = min(o + (int64_t)kcs[j], n);
-  if (e <= o) return;
-  const uint32_t r = perm[j];
-  const int v = view_of_record(B, (int)r);
-  const short4 rc = rect[r];
-  const CullShape S = cull_shape(B, v, splat[3 * (int64_t)r], splat[3 * (int64_t)r + 1]);
-  const uint32_t tx = (uint32_t)B.v[v].tiles_x;
-  const uint32_t toff = (uint32_t)B.v[v].tile_off;
-  uint32_t k = roff[j];
-  for (int ty = rc.y; ty < rc.w && o < e; ++ty) {
-    int lo, hi;
-    cull_row(S, ty, rc.x, rc.z, &lo, &hi);
-    if (hi <= lo) continue;
-    packed[k] = make_uint4((uint32_t)o, r, toff + (uint32_t)ty * tx + (uint32_t)lo,
-                           (uint32_t)(hi - lo) | (tx << 16));
-    const int64_t oe = min(o + (int64_t)(hi - lo), e);
-    for (int64_t b = (o + kSortTile - 1) / kSortTile; b * kSortTile < oe; ++b) first[b] = k;
-    if (oe == n) first[(n + kSortTile - 1) / kSortTile] = k;
-    o = oe;
-    ++k;
+// Emit pass of the cull (depth order): one packed record per kept row (pair
+// offset, record id, tile id of the row's first kept tile, run length |
+// tiles_x << 16), and first[] as k_pair_records writes it. A wave's rows are
+// flattened in depth order, so their pair offsets and record slots are the
+// wave's bases (offsets / roff at its first position) plus running sums.
+__global__ __launch_bounds__(256) void k_cull_emit(Batch B, const float4* __restrict__ splat,
+                                                   const short4* __restrict__ rect,
+                                                   const uint32_t* __restrict__ kcs,
+                                                   const uint32_t* __restrict__ perm,
+                                                   const uint32_t* __restrict__ offsets,
+                                                   const uint32_t* __restrict__ roff,
+                                                   uint32_t kc_mask, int64_t n_rec,
+                                                   const int64_t* n_isect, int64_t cap,
+                                                   uint4* __restrict__ packed,
+                                                   uint32_t* __restrict__ first) {
+  __shared__ RowGeom geo[256];
+  __shared__ uint32_t pre[256];
+  const int t = threadIdx.x, lane = t & 63, wb = t & ~63;
+  const int64_t j = (int64_t)blockIdx.x * 256 + t;
+  const int64_t jw = (int64_t)blockIdx.x * 256 + wb;
+  uint32_t h = 0;
+  if (j < n_rec && (kcs[j] & kc_mask) > 0) {
+    const uint32_t r = perm[j];
+    const short4 rc = rect[r];
+    geo[t] = row_geom(B, (int)r, splat[3 * (int64_t)r], splat[3 * (int64_t)r + 1], rc);
+    h = (uint32_t)(rc.w - rc.y);
   }
+  const uint32_t inc = wave_incl_scan_dpp(h);
+  pre[t] = inc - h;
+  const uint32_t total = lane63_u(inc);
+  __syncthreads();
+  if (jw >= n_rec || total == 0) return;
+  const int64_t n = clamp_n(n_isect, cap);
+  int64_t pbase = offsets[jw];
+  uint32_t rbase = roff[jw];
+  wave_rows(geo + wb, pre + wb, total, B.tile_w, B.tile_h,
+            [&](bool valid, int g, int ty, int lo, int hi) {
+              // run length (<= 2048 tile columns, so a chunk's sum < 2^20)
+              // and kept flag, scanned together
+              const uint32_t w = valid ? (uint32_t)(hi - lo) : 0u;
+              const uint32_t x = w | (w > 0 ? 1u << 20 : 0u);
+              const uint32_t ix = wave_incl_scan_dpp(x);
+              const uint32_t iw = ix & 0xfffffu, ir = ix >> 20;
+              const int64_t o = pbase + (int64_t)(iw - w);
+              if (w > 0 && o < n) {
+                const RowGeom& G = geo[wb + g];
+                const uint32_t k = rbase + ir - 1u;
+                packed[k] = make_uint4((uint32_t)o, (uint32_t)G.rec,
+                                       (uint32_t)(G.tile0 + ty * G.tiles_x + lo),
+                                       w | ((uint32_t)G.tiles_x << 16));
+                const int64_t oe = min(o + (int64_t)w, n);
+                for (int64_t b = (o + kSortTile - 1) / kSortTile; b * kSortTile < oe; ++b)
+                  first[b] = k;
+                if (oe == n) first[(n + kSortTile - 1) / kSortTile] = k;
+              }
+              const uint32_t tot = lane63_u(ix);
+              pbase += tot & 0xfffffu;
+              rbase += tot >> 20;
+            });
+  (void)lane;
 }
 
-// Up to 256 packed records of a sort block, staged in LDS: the item offset
-// of each record and its three payload words.
+// Up to N packed records of a sort block, staged in LDS: the item offset of
+// each record and its payload words (the third one only when the record
+// kind reads it).
+template <int N, bool C>
 struct RecChunk {
-  uint32_t off[257];
-  uint32_t a[256];
-  uint32_t b[256];
-  uint32_t c[256];
+  uint32_t off[N + 1];
+  uint32_t a[N];
+  uint32_t b[N];
+  uint32_t c[C ? N : 1];
 };
 
 // What a packed record generates. Items of a record form a grid of
@@ -651,6 +765,8 @@ struct RecChunk {
 // Tile pairs: packed = (pair offset, record id, tile id of the rect's top-
 // left corner, rect width | tiles_x << 16); key = tile id, value = record.
 struct PairItems {
+  using Chunk = RecChunk<256, true>;
+  static constexpr int kStage = 256;
   static __device__ __forceinline__ uint32_t width(uint4 q) { return q.w & 0xffffu; }
   static __device__ __forceinline__ void item(uint4 q, uint32_t, uint32_t yy, uint32_t xx,
                                               uint32_t& key, uint32_t& val) {
@@ -667,6 +783,8 @@ struct PairItems {
 constexpr int kBandWidth = 16;
 
 struct BandItems {
+  using Chunk = RecChunk<256, true>;
+  static constexpr int kStage = 256;
   static __device__ __forceinline__ uint32_t width(uint4 q) { return q.z & 0xffffu; }
   static __device__ __forceinline__ void item(uint4 q, uint32_t j, uint32_t yy, uint32_t xx,
                                               uint32_t& key, uint32_t& val) {
@@ -676,6 +794,22 @@ struct BandItems {
     const uint32_t xlo = (uint32_t)max(x0 - b0, 0);
     const uint32_t xhi = (uint32_t)min(x1 - b0, kBandWidth);
     val = j | (xlo << 23) | ((xhi - 1u) << 27);
+  }
+};
+
+// Kept rows of the per-(Gaussian, tile) cull: packed = (pair offset, record
+// id, tile id of the row's first kept tile, -); a one-row grid, so no width
+// is needed (any width beyond the row keeps xx = item - offset). Records
+// average a few pairs, so a sort block holds about a thousand: up to 2048
+// are staged in LDS.
+struct RowItems {
+  using Chunk = RecChunk<2048, false>;
+  static constexpr int kStage = 2048;
+  static __device__ __forceinline__ uint32_t width(uint4) { return 1u << 30; }
+  static __device__ __forceinline__ void item(uint4 q, uint32_t, uint32_t, uint32_t xx,
+                                              uint32_t& key, uint32_t& val) {
+    key = q.z + xx;
+    val = q.y;
   }
 };
 
@@ -699,7 +833,8 @@ constexpr int kSortTilePad = kSortTile + kSortTile / 16;
 template <class Items, class Emit>
 __device__ __forceinline__ void gen_block_pairs(const uint4* __restrict__ packed,
                                                 const uint32_t* __restrict__ first, int part,
-                                                int64_t n, RecChunk& S, uint32_t* marks,
+                                                int64_t n, typename Items::Chunk& S,
+                                                uint32_t* marks,
                                                 uint32_t* s_wave, Emit emit) {
   const int t = threadIdx.x;
   const uint32_t lo = (uint32_t)part * kSortTile;
@@ -707,13 +842,27 @@ __device__ __forceinline__ void gen_block_pairs(const uint4* __restrict__ packed
   const int nslots = (int)(hi - lo);
   const uint32_t j0 = first[part], j1 = first[part + 1];
   const uint32_t nrec = j1 - j0 + 1;
-  const bool in_lds = nrec <= 256u;
-  if (in_lds && (uint32_t)t < nrec) {
-    const uint4 q = packed[j0 + t];
-    S.off[t] = q.x;
-    S.a[t] = q.y;
-    S.b[t] = q.z;
-    S.c[t] = q.w;
+  constexpr bool kC = sizeof(S.c) > sizeof(uint32_t);
+  const bool in_lds = nrec <= (uint32_t)Items::kStage;
+  if (in_lds) {
+    // all loads first, then the LDS stores
+    constexpr int R = Items::kStage / 256;
+    uint4 q[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t k = (uint32_t)(t + 256 * r);
+      if (k < nrec) q[r] = packed[j0 + k];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t k = (uint32_t)(t + 256 * r);
+      if (k < nrec) {
+        S.off[k] = q[r].x;
+        S.a[k] = q[r].y;
+        S.b[k] = q[r].z;
+        if (kC) S.c[k] = q[r].w;
+      }
+    }
   }
 #pragma unroll
   for (int i = 0; i < 16; ++i) marks[spad(16 * t + i)] = 0u;
@@ -733,7 +882,8 @@ __device__ __forceinline__ void gen_block_pairs(const uint4* __restrict__ packed
   }
   const uint32_t pre = block_excl_max256(run, s_wave);
   auto rec = [&](int k) -> uint4 {
-    return in_lds ? make_uint4(S.off[k], S.a[k], S.b[k], S.c[k]) : packed[j0 + (uint32_t)k];
+    return in_lds ? make_uint4(S.off[k], S.a[k], S.b[k], kC ? S.c[k] : 0u)
+                  : packed[j0 + (uint32_t)k];
   };
   int kprev = (int)max(pre, m[0]) - 1;
   uint4 q = rec(kprev);
@@ -775,7 +925,7 @@ __global__ __launch_bounds__(256) void k_pair_hist(const uint4* __restrict__ pac
                                                    uint32_t* __restrict__ counts, int nblocks) {
   constexpr int RADIX = 1 << BITS;
   constexpr int COPIES = RADIX <= 256 ? 8 : 2;
-  __shared__ RecChunk S;
+  __shared__ typename Items::Chunk S;
   __shared__ uint32_t marks[kSortTilePad];
   __shared__ uint32_t s_wave[4];
   __shared__ uint32_t h[COPIES][RADIX];
@@ -807,7 +957,7 @@ __global__ __launch_bounds__(256) void k_pair_scatter(
     int64_t cap, const uint32_t* __restrict__ doff, int nblocks, KO* __restrict__ kout,
     uint32_t* __restrict__ vout, int2* __restrict__ ranges) {
   constexpr int RADIX = 1 << BITS;
-  __shared__ RecChunk S;
+  __shared__ typename Items::Chunk S;
   __shared__ uint32_t wcnt[kSortWaves][RADIX];
   __shared__ uint32_t gbase[RADIX];
   __shared__ uint32_t s_wave[4];
@@ -1125,6 +1275,21 @@ size_t bin_workspace_bytes(int64_t n_rec, int64_t cap, int64_t tiles, int sort_m
 
 static inline int grid1(int64_t n, int bs = 256) { return (int)((n + bs - 1) / bs); }
 
+// Kept pairs and kept rows of a record travel through the depth presort as
+// one word, kc | rows << bits, when both fit (kc <= tiles of the view, rows
+// <= its tile rows); 0 = they do not, rows are then gathered separately.
+static int cull_pack_bits(const Batch& B) {
+  int64_t tiles = 1, ty = 1;
+  for (int v = 0; v < B.n_views; ++v) {
+    tiles = std::max<int64_t>(tiles, (int64_t)B.v[v].tiles_x * B.v[v].tiles_y);
+    ty = std::max<int64_t>(ty, B.v[v].tiles_y);
+  }
+  int kb = 1, rb = 1;
+  while (((int64_t)1 << kb) <= tiles) ++kb;
+  while (((int64_t)1 << rb) <= ty) ++rb;
+  return kb + rb <= 32 ? kb : 0;
+}
+
 // Phase 1: everything up to a known I (the prefix sum of the counts, in
 // depth order for the presort path). Phase 2: replication, pair sort, ranges.
 hipError_t bin_phase1(const Batch& B, int sort_mode, bool cull, const float* splat,
@@ -1140,10 +1305,11 @@ hipError_t bin_phase1(const Batch& B, int sort_mode, bool cull, const float* spl
   }
   if (sort_mode == XPR_SORT_PRESORT || sort_mode == XPR_SORT_BANDS) {
     const int32_t* counts = tc;
+    const int pb = cull ? cull_pack_bits(B) : 0;
     if (cull) {
       hipLaunchKernelGGL(k_cull_count, dim3(grid1(n_rec)), dim3(256), 0, st, B,
                          reinterpret_cast<const float4*>(splat),
-                         reinterpret_cast<const short4*>(rect), tc, depth, n_rec, L.kc,
+                         reinterpret_cast<const short4*>(rect), tc, depth, n_rec, pb, L.kc,
                          L.nrow, L.dkey[0], L.perm[0]);
       counts = reinterpret_cast<const int32_t*>(L.kc);
     } else {
@@ -1156,8 +1322,14 @@ hipError_t bin_phase1(const Batch& B, int sort_mode, bool cull, const float* spl
                                         true, counts, L.tcs);
     if (e != hipSuccess) return e;
     *perm_out = vo;
+    if (!cull) return device_scan(LoadArray{L.tcs}, n_rec, L.offsets, L.partials, n_isect, st);
+    if (pb > 0) {
+      e = device_scan(LoadMask{L.tcs, (1u << pb) - 1u}, n_rec, L.offsets, L.partials, n_isect, st);
+      if (e != hipSuccess) return e;
+      return device_scan(LoadShift{L.tcs, pb}, n_rec, L.roff, L.partials, nullptr, st);
+    }
     e = device_scan(LoadArray{L.tcs}, n_rec, L.offsets, L.partials, n_isect, st);
-    if (e != hipSuccess || !cull) return e;
+    if (e != hipSuccess) return e;
     return device_scan(LoadGather{L.nrow, vo}, n_rec, L.roff, L.partials, nullptr, st);
   }
   return device_scan(LoadCount{tc}, n_rec, L.offsets, L.partials, n_isect, st);
@@ -1211,34 +1383,45 @@ static hipError_t pair_sort(const Batch& B, int tile_bits, const float* depth, c
   KT* tk1 = reinterpret_cast<KT*>(L.tkey[1]);
   const int tiles = B.total_tiles;
   hipLaunchKernelGGL(k_ranges_init, dim3(grid1(tiles)), dim3(256), 0, st, ranges, tiles);
-  if (splat)  // per-(Gaussian, tile) cull: one record per kept row
-    hipLaunchKernelGGL(k_cull_records, dim3(grid1(n_rec)), dim3(256), 0, st, B,
+  if (splat) {  // per-(Gaussian, tile) cull: one record per kept row
+    const int pb = cull_pack_bits(B);
+    hipLaunchKernelGGL(k_cull_emit, dim3(grid1(n_rec)), dim3(256), 0, st, B,
                        reinterpret_cast<const float4*>(splat), rc, L.tcs, perm, L.offsets, L.roff,
-                       n_rec, n_isect, cap, L.packed, L.first);
-  else
+                       pb > 0 ? (1u << pb) - 1u : 0xffffffffu, n_rec, n_isect, cap, L.packed,
+                       L.first);
+  } else
     hipLaunchKernelGGL(k_pair_records, dim3(grid1(n_rec)), dim3(256), 0, st, B, rc, L.tcs, perm,
                        L.offsets, n_rec, n_isect, cap, L.packed, L.first);
   const int nb = (int)((grid_n + kSortTile - 1) / kSortTile);
   KT* k1 = (one && !keys_out) ? nullptr : tk0;
-  if (dbits == 7)
-    hipLaunchKernelGGL((k_pair_hist<7, PairItems>), dim3(nb), dim3(256), 0, st, L.packed, L.first,
-                       n_isect, cap, L.counts, nb);
-  else
-    hipLaunchKernelGGL((k_pair_hist<8, PairItems>), dim3(nb), dim3(256), 0, st, L.packed, L.first,
-                       n_isect, cap, L.counts, nb);
+#define XPR_PAIR_HIST(BITS, ITEMS)                                                          \
+  hipLaunchKernelGGL((k_pair_hist<BITS, ITEMS>), dim3(nb), dim3(256), 0, st, L.packed, L.first, \
+                     n_isect, cap, L.counts, nb)
+  if (dbits == 7) {
+    if (splat) XPR_PAIR_HIST(7, RowItems); else XPR_PAIR_HIST(7, PairItems);
+  } else {
+    if (splat) XPR_PAIR_HIST(8, RowItems); else XPR_PAIR_HIST(8, PairItems);
+  }
+#undef XPR_PAIR_HIST
   hipError_t e =
       device_scan(LoadArray{L.counts}, (int64_t)nb << dbits, L.counts, L.partials, nullptr, st);
   if (e != hipSuccess) return e;
-#define XPR_PAIR_SCATTER(BITS, LAST)                                                        \
-  hipLaunchKernelGGL((k_pair_scatter<BITS, LAST, KT, PairItems>), dim3(nb), dim3(256), 0, st,   \
+#define XPR_PAIR_SCATTER(BITS, LAST, ITEMS)                                                 \
+  hipLaunchKernelGGL((k_pair_scatter<BITS, LAST, KT, ITEMS>), dim3(nb), dim3(256), 0, st,       \
                      L.packed,                                                               \
                      L.first, n_isect, cap, L.counts, nb, k1, v1,                           \
                      LAST ? ranges : (int2*)nullptr)
+#define XPR_PAIR_SCATTER_I(BITS, LAST)                                                      \
+  do {                                                                                      \
+    if (splat) XPR_PAIR_SCATTER(BITS, LAST, RowItems);                                      \
+    else XPR_PAIR_SCATTER(BITS, LAST, PairItems);                                           \
+  } while (0)
   if (dbits == 7) {
-    if (one) XPR_PAIR_SCATTER(7, true); else XPR_PAIR_SCATTER(7, false);
+    if (one) XPR_PAIR_SCATTER_I(7, true); else XPR_PAIR_SCATTER_I(7, false);
   } else {
-    if (one) XPR_PAIR_SCATTER(8, true); else XPR_PAIR_SCATTER(8, false);
+    if (one) XPR_PAIR_SCATTER_I(8, true); else XPR_PAIR_SCATTER_I(8, false);
   }
+#undef XPR_PAIR_SCATTER_I
 #undef XPR_PAIR_SCATTER
   KT* ko = tk0;
   uint32_t* vo = v1;
