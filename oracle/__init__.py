@@ -41,10 +41,11 @@ class OracleConfig:
     fov_clip: float = 1.3           # Jacobian clamp at fov_clip*tan(fov/2)
     bg: tuple = (0.0, 0.0, 0.0)
     tile_cull: bool = False         # per-(Gaussian, tile) cull of XPR-3DGS
+    opacity_extents: bool = False   # rect from the alpha >= alpha_min ellipse (not 3 sigma)
 
     def proj_cfg(self):
-        return np.array([self.lowpass, self.alpha_min, self.z_near, self.fov_clip],
-                        dtype=np.float64)
+        return np.array([self.lowpass, self.alpha_min, self.z_near, self.fov_clip,
+                         1.0 if self.opacity_extents else 0.0], dtype=np.float64)
 
     def render_cfg(self):
         return np.array([self.alpha_min, self.alpha_max, self.t_min, *self.bg],

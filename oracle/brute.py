@@ -88,15 +88,23 @@ def project_torch(means, scales, quats, opac, sh, cam, cfg: OracleConfig):
     u = cam.fx * tx / tz + cam.cx - 0.5
     v = cam.fy * ty / tz + cam.cy - 0.5
     with torch.no_grad():
-        mid = 0.5 * (a + c)
-        lam = mid + torch.sqrt(torch.clamp(mid * mid - det, min=0.0))
-        r = torch.ceil(3 * torch.sqrt(lam))
+        if cfg.opacity_extents:
+            # half-widths of the ellipse where o G = alpha_min
+            lvl = 2 * torch.log(opac / cfg.alpha_min)
+            ex = torch.where(lvl > 0, torch.sqrt(torch.clamp(lvl * a, min=0.0)), torch.zeros_like(a))
+            ey = torch.where(lvl > 0, torch.sqrt(torch.clamp(lvl * c, min=0.0)), torch.zeros_like(c))
+            r = torch.maximum(ex, ey)
+        else:
+            mid = 0.5 * (a + c)
+            lam = mid + torch.sqrt(torch.clamp(mid * mid - det, min=0.0))
+            r = torch.ceil(3 * torch.sqrt(lam))
+            ex = ey = r
         txn = (cam.width + cfg.tile_w - 1) // cfg.tile_w
         tyn = (cam.height + cfg.tile_h - 1) // cfg.tile_h
-        x0 = torch.clamp(torch.floor((u - r) / cfg.tile_w), 0, txn)
-        x1 = torch.clamp(torch.floor((u + r) / cfg.tile_w) + 1, 0, txn)
-        y0 = torch.clamp(torch.floor((v - r) / cfg.tile_h), 0, tyn)
-        y1 = torch.clamp(torch.floor((v + r) / cfg.tile_h) + 1, 0, tyn)
+        x0 = torch.clamp(torch.floor((u - ex) / cfg.tile_w), 0, txn)
+        x1 = torch.clamp(torch.floor((u + ex) / cfg.tile_w) + 1, 0, txn)
+        y0 = torch.clamp(torch.floor((v - ey) / cfg.tile_h), 0, tyn)
+        y1 = torch.clamp(torch.floor((v + ey) / cfg.tile_h) + 1, 0, tyn)
         tc = (x1 - x0) * (y1 - y0)
         visible = (tz > cfg.z_near) & (det > 0) & (opac >= cfg.alpha_min) & (r > 0) & (tc > 0)
     campos = -(Rw.T @ tw)

@@ -171,6 +171,7 @@ void project_one(int64_t i, int64_t n, const double* means, const double* scales
                  const double* quats, const double* opac, const double* sh, int K,
                  const Cam& cam, const double* cfg, int tile_w, int tile_h, int deg, Proj& P) {
   const double lowpass = cfg[0], alpha_min = cfg[1], z_near = cfg[2], fov_clip = cfg[3];
+  const bool opacity_extents = cfg[4] != 0.0;
   const int tiles_x = (cam.W + tile_w - 1) / tile_w;
   const int tiles_y = (cam.H + tile_h - 1) / tile_h;
   std::memset(&P, 0, sizeof(P));
@@ -232,16 +233,29 @@ void project_one(int64_t i, int64_t n, const double* means, const double* scales
     // point f*X/Z + c is shifted by one half pixel.
     P.u = cam.fx * tx / tz + cam.cx - 0.5;
     P.v = cam.fy * ty / tz + cam.cy - 0.5;
-    // 3-sigma radius of the largest eigenvalue.
+    // Extents (compute_extents of the listing): the 3-sigma radius of the
+    // largest eigenvalue in both directions, or, opacity-aware, the
+    // half-widths of the ellipse 0.5 d^T conic d = log(o / alpha_min) where
+    // o G falls to alpha_min: sqrt(2 log(o / alpha_min) cov_xx) and likewise
+    // with cov_yy (the extreme x of that ellipse); the radius is their
+    // maximum (compute_radius).
     const double mid = 0.5 * (P.a + P.c);
     P.lambda = mid + std::sqrt(std::max(0.0, mid * mid - P.det));
     const double r3 = 3.0 * std::sqrt(P.lambda);
-    P.radius = std::ceil(r3);
+    double ex, ey;
+    if (opacity_extents) {
+      const double lvl = 2.0 * std::log(o / alpha_min);
+      ex = lvl > 0.0 ? std::sqrt(lvl * P.a) : 0.0;
+      ey = lvl > 0.0 ? std::sqrt(lvl * P.c) : 0.0;
+      P.radius = std::max(ex, ey);
+    } else {
+      P.radius = std::ceil(r3);
+      ex = ey = P.radius;
+    }
     // Tile-space bounding box, half-open: covers every pixel sample within
-    // the L-infinity box of half-width r around mean2D.
-    const double r = P.radius;
-    const double fx0 = (P.u - r) / tile_w, fx1 = (P.u + r) / tile_w;
-    const double fy0 = (P.v - r) / tile_h, fy1 = (P.v + r) / tile_h;
+    // the box of half-widths (ex, ey) around mean2D.
+    const double fx0 = (P.u - ex) / tile_w, fx1 = (P.u + ex) / tile_w;
+    const double fy0 = (P.v - ey) / tile_h, fy1 = (P.v + ey) / tile_h;
     auto clampi = [](double x, int lo, int hi) {
       return (int)std::min<double>(hi, std::max<double>(lo, x));
     };
@@ -254,7 +268,8 @@ void project_one(int64_t i, int64_t n, const double* means, const double* scales
     // 1e-9 (relative) of an integer, where a float64 computation in another
     // operation order may round the other way.
     const double g = 1e-9;
-    if (near_int(r3, g * std::max(1.0, r3)) || near_int(fx0, g * std::max(1.0, std::fabs(fx0))) ||
+    if ((!opacity_extents && near_int(r3, g * std::max(1.0, r3))) ||
+        near_int(fx0, g * std::max(1.0, std::fabs(fx0))) ||
         near_int(fx1, g * std::max(1.0, std::fabs(fx1))) ||
         near_int(fy0, g * std::max(1.0, std::fabs(fy0))) ||
         near_int(fy1, g * std::max(1.0, std::fabs(fy1))))
