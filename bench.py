@@ -57,7 +57,10 @@ def main():
     ap.add_argument("--schedule", choices=("index", "longest_first", "persistent"), default=None)
     ap.add_argument("--tile-cull", action="store_true",
                     help="time the per-(Gaussian, tile) cull in the main line")
-    ap.add_argument("--no-cull-line", action="store_true")
+    ap.add_argument("--opacity-extents", action="store_true",
+                    help="time the opacity-aware extents in the main line")
+    ap.add_argument("--no-cull-line", action="store_true",
+                    help="skip the tile_cull / opacity_extents variant lines")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -86,6 +89,8 @@ def main():
                                   persistent=args.schedule == "persistent")
     if args.tile_cull:
         cfg = dataclasses.replace(cfg, tile_cull=True)
+    if args.opacity_extents:
+        cfg = dataclasses.replace(cfg, opacity_extents=True)
     scene = R.Scene.from_host(sc, dev)
     tuned = None
     if not args.no_autotune:
@@ -175,6 +180,7 @@ def main():
                                 "longest_first" if cfg.tile_order else "index"),
                    "autotuned": tuned is not None,
                    "tile_cull": cfg.tile_cull,
+                   "opacity_extents": cfg.opacity_extents,
                    "pairs_per_frame": pairs},
         "stage_sum_ms": round(frame_ms, 4),
         "stages_ms_median": med,
@@ -183,20 +189,26 @@ def main():
     }
     log(f"[bench] frame {frame_ms:.3f} ms (stage sum), wall {ms_wall:.3f} ms/step")
 
-    if not args.no_cull_line and not cfg.tile_cull:
-        # the paper's per-(Gaussian, tile) cull (opt-in) on the same frames
-        ccfg = dataclasses.replace(cfg, tile_cull=True)
-        cr = timed_frames(scene, cams, ccfg, targets, args.steps, args.warmup, args.tile, names)
-        cmean = {k: float(np.mean(v)) for k, v in cr["stage_ms"].items()}
-        cpairs = float(np.mean([cr["work"]["pairs"][c] for c in order]))
-        out["tile_cull"] = {"ms_per_step": round(cr["ms_wall"], 4),
-                            "stage_sum_ms": round(float(np.mean(np.sum(
-                                [cr["stage_ms"][k] for k in names], axis=0))), 4),
-                            "stages_ms_mean": cmean, "pairs_per_frame": cpairs,
-                            "pairs_kept_frac": cpairs / pairs,
-                            "speedup": ms_wall / cr["ms_wall"]}
-        log(f"[bench] tile_cull: {cr['ms_wall']:.3f} ms/step, pairs {cpairs:.0f} "
-            f"({cpairs / pairs:.3f} of {pairs:.0f})")
+    if not args.no_cull_line and not cfg.tile_cull and not cfg.opacity_extents:
+        # the paper's per-(Gaussian, tile) cull and opacity-aware extents
+        # (opt-in options of the method) on the same frames and knobs
+        for key, opts in (("tile_cull", {"tile_cull": True}),
+                          ("opacity_extents", {"opacity_extents": True}),
+                          ("opacity_extents_tile_cull", {"tile_cull": True,
+                                                         "opacity_extents": True})):
+            vcfg = dataclasses.replace(cfg, **opts)
+            cr = timed_frames(scene, cams, vcfg, targets, args.steps, args.warmup, args.tile,
+                              names)
+            cmean = {k: float(np.mean(v)) for k, v in cr["stage_ms"].items()}
+            cpairs = float(np.mean([cr["work"]["pairs"][c] for c in order]))
+            out[key] = {"ms_per_step": round(cr["ms_wall"], 4),
+                        "stage_sum_ms": round(float(np.mean(np.sum(
+                            [cr["stage_ms"][k] for k in names], axis=0))), 4),
+                        "stages_ms_mean": cmean, "pairs_per_frame": cpairs,
+                        "pairs_vs_plain": cpairs / pairs,
+                        "speedup": ms_wall / cr["ms_wall"]}
+            log(f"[bench] {key}: {cr['ms_wall']:.3f} ms/step, pairs {cpairs:.0f} "
+                f"({cpairs / pairs:.3f} of {pairs:.0f})")
     del scene, targets
     torch.cuda.empty_cache()
     if not args.no_batch:

@@ -96,6 +96,7 @@ typedef struct xpr_config {
   int32_t bwd_lds_batch;  /* LDS batch of the backward (0: same as lds_batch) */
   int32_t persistent;     /* 1: persistent render grids pulling from tile_order */
   int32_t tile_cull;      /* 1: per-(Gaussian, tile) cull in xpr_bin_sort (0) */
+  int32_t opacity_extents; /* 1: rect from the alpha >= alpha_min extents, not 3 sigma (0) */
 } xpr_config;
 
 /* One scene of n Gaussians, structure of arrays with leading dimension ld:
@@ -167,7 +168,14 @@ xpr_status xpr_batch_sizes(const xpr_views* views, const xpr_config* cfg, xpr_si
  * Jacobian at the clamped direction; conic = inverse; mean2D = f X/Z + c - 1/2;
  * radius ceil(3 sqrt(lambda_max)); tile rect [floor((u-r)/tw),
  * floor((u+r)/tw)+1) clamped to the grid (likewise v); visibility
- * det > 0, o >= alpha_min, r > 0, area > 0, z > z_near; colour
+ * det > 0, o >= alpha_min, r > 0, area > 0, z > z_near. With
+ * cfg->opacity_extents = 1 the extents are opacity-aware (compute_extents of
+ * the listing takes the opacity): the half-widths of the ellipse where
+ * o G = alpha_min, ex = sqrt(2 ln(o / alpha_min) cov_xx) and
+ * ey = sqrt(2 ln(o / alpha_min) cov_yy) (cov with the low-pass), the rect is
+ * [floor((u-ex)/tw), floor((u+ex)/tw)+1) x [floor((v-ey)/th),
+ * floor((v+ey)/th)+1) and r = max(ex, ey); every pixel whose alpha can pass
+ * the alpha_min gate then lies in the rect. Colour
  * max(0, 0.5 + sum_lm sh_lm Y_lm(dir)) with the real SH basis (Condon-Shortley
  * phase) and dir = (mu - campos) / |mu - campos|. Writes every field of
  * *out for all records (invisible: tiles_touched = 0). */

@@ -100,6 +100,7 @@ static xpr_status check_config(const xpr_config* c) {
                 c->bwd_lds_batch == 256 || c->bwd_lds_batch == 512,
             "bwd_lds_batch %d not in {0,64,128,256,512}", c->bwd_lds_batch);
   XPR_CHECK(c->tile_cull == 0 || c->tile_cull == 1, "tile_cull must be 0 or 1");
+  XPR_CHECK(c->opacity_extents == 0 || c->opacity_extents == 1, "opacity_extents must be 0 or 1");
   return XPR_OK;
 }
 
@@ -173,6 +174,7 @@ static xpr_status build_batch(const xpr_views* vw, const xpr_config* c, Batch* B
   B->tile_w = c->tile_w;
   B->tile_h = c->tile_h;
   B->sh_degree = c->sh_degree;
+  B->opacity_extents = c->opacity_extents;
   B->lowpass = c->lowpass;
   B->alpha_min = c->alpha_min;
   B->alpha_max = c->alpha_max;
@@ -252,6 +254,7 @@ void xpr_config_default(xpr_config* c) {
   c->bwd_lds_batch = 0;
   c->persistent = 0;
   c->tile_cull = 0;
+  c->opacity_extents = 0;
 }
 
 xpr_status xpr_batch_sizes(const xpr_views* views, const xpr_config* cfg, xpr_sizes* out) {

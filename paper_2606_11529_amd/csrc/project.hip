@@ -194,18 +194,29 @@ __device__ __forceinline__ void project_core(const Batch& B, const ViewDev& V, c
   P.u = fx * tx / tz + (double)V.cx - 0.5;
   P.v = fy * ty / tz + (double)V.cy - 0.5;
 
-  // 3-sigma radius of the largest eigenvalue, tile rect, tile count.
-  const double mid = 0.5 * (P.a + P.c);
-  const double lam = mid + sqrt(fmax(0.0, mid * mid - P.det));
-  const double rad = ceil(3.0 * sqrt(lam));
+  // Extents, radius, tile rect, tile count: the 3-sigma radius of the
+  // largest eigenvalue, or (opacity-aware) the half-widths of the ellipse
+  // where o G = alpha_min.
+  const float o = S.opac[i];
+  double ex, ey, rad;
+  if (B.opacity_extents) {
+    const double lvl = 2.0 * log((double)o / (double)B.alpha_min);
+    ex = lvl > 0.0 ? sqrt(lvl * P.a) : 0.0;
+    ey = lvl > 0.0 ? sqrt(lvl * P.c) : 0.0;
+    rad = fmax(ex, ey);
+  } else {
+    const double mid = 0.5 * (P.a + P.c);
+    const double lam = mid + sqrt(fmax(0.0, mid * mid - P.det));
+    rad = ceil(3.0 * sqrt(lam));
+    ex = ey = rad;
+  }
   const double tw = B.tile_w, th = B.tile_h;
   const double txn = V.tiles_x, tyn = V.tiles_y;
-  P.rect[0] = (int)fmin(txn, fmax(0.0, floor((P.u - rad) / tw)));
-  P.rect[1] = (int)fmin(tyn, fmax(0.0, floor((P.v - rad) / th)));
-  P.rect[2] = (int)fmin(txn, fmax(0.0, floor((P.u + rad) / tw) + 1.0));
-  P.rect[3] = (int)fmin(tyn, fmax(0.0, floor((P.v + rad) / th) + 1.0));
+  P.rect[0] = (int)fmin(txn, fmax(0.0, floor((P.u - ex) / tw)));
+  P.rect[1] = (int)fmin(tyn, fmax(0.0, floor((P.v - ey) / th)));
+  P.rect[2] = (int)fmin(txn, fmax(0.0, floor((P.u + ex) / tw) + 1.0));
+  P.rect[3] = (int)fmin(tyn, fmax(0.0, floor((P.v + ey) / th) + 1.0));
   const int area = (P.rect[2] - P.rect[0]) * (P.rect[3] - P.rect[1]);
-  const float o = S.opac[i];
   const bool visible = tz > (double)B.z_near && P.det > 0.0 && o >= B.alpha_min && rad > 0.0 &&
                        area > 0;
   P.tc = visible ? area : 0;

@@ -37,7 +37,7 @@ struct Batch {
   int32_t n_views, n_scenes;
   int32_t total_rec, total_tiles;
   int32_t tile_w, tile_h;
-  int32_t sh_degree, pad;
+  int32_t sh_degree, opacity_extents;
   float lowpass, alpha_min, alpha_max, t_min, z_near, fov_clip;
   float bg[3], pad2;
 };

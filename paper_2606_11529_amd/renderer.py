@@ -38,6 +38,7 @@ class Config:
     persistent: bool = False    # persistent render grids over the tile order
     tile_order: bool = False    # launch tiles longest list first (implied by persistent)
     tile_cull: bool = False     # per-(Gaussian, tile) cull of XPR-3DGS in the binning
+    opacity_extents: bool = False  # rect from the alpha >= alpha_min ellipse, not 3 sigma
 
     def to_c(self) -> L.XprConfig:
         c = L.XprConfig()
@@ -62,6 +63,7 @@ class Config:
         c.bwd_lds_batch = int(self.bwd_lds_batch)
         c.persistent = 1 if self.persistent else 0
         c.tile_cull = 1 if self.tile_cull else 0
+        c.opacity_extents = 1 if self.opacity_extents else 0
         return c
 
 

@@ -38,7 +38,8 @@ def ocfg_of(cfg: R.Config) -> oracle.OracleConfig:
                                lowpass=f(cfg.lowpass), alpha_min=f(cfg.alpha_min),
                                alpha_max=f(cfg.alpha_max), t_min=f(cfg.t_min),
                                z_near=f(cfg.z_near), fov_clip=f(cfg.fov_clip),
-                               bg=tuple(f(b) for b in cfg.bg))
+                               bg=tuple(f(b) for b in cfg.bg), tile_cull=cfg.tile_cull,
+                               opacity_extents=cfg.opacity_extents)
 
 
 def run_gpu(sc, cams, cfg: R.Config, dimgs=None, want_keys=True, want_grad2d=True,
