@@ -42,9 +42,14 @@ class OracleConfig:
     bg: tuple = (0.0, 0.0, 0.0)
     tile_cull: bool = False         # per-(Gaussian, tile) cull of XPR-3DGS
     opacity_extents: bool = False   # rect from the alpha >= alpha_min ellipse (not 3 sigma)
+    method: str = "3dgs"            # "3dgs" (EWA) or "3dgut" (unscented transform, ray evaluate)
 
     def proj_cfg(self):
         return np.array([self.lowpass, self.alpha_min, self.z_near, self.fov_clip,
+                         1.0 if self.opacity_extents else 0.0], dtype=np.float64)
+
+    def gut_cfg(self):
+        return np.array([self.lowpass, self.alpha_min, self.z_near,
                          1.0 if self.opacity_extents else 0.0], dtype=np.float64)
 
     def render_cfg(self):
@@ -66,9 +71,10 @@ def lib():
                                   P, P, P, P, P, P, P]
         L.orc_project.restype = None
         L.orc_bin.argtypes = [i64, P, P, P, i32, i32, i64, P, P, P, P, P, i32, i32, i32, i32,
-                              ctypes.c_double, P, P, P]
+                              i32, i32, ctypes.c_double, P, P, P]
         L.orc_bin.restype = i64
-        L.orc_tile_cull.argtypes = [i64, P, P, i32, i32, i32, i32, ctypes.c_double, P, P, P, P]
+        L.orc_tile_cull.argtypes = [i64, P, P, i32, i32, i32, i32, ctypes.c_double, i32, P, P, P,
+                                    P]
         L.orc_tile_cull.restype = None
         L.orc_render_fwd.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P, P, P, P]
         L.orc_render_fwd.restype = None
@@ -77,6 +83,13 @@ def lib():
         L.orc_project_bwd.argtypes = [i64, P, P, P, P, P, i32, P, i32, i32, P, i32, i32, i32,
                                       P, P, P, P, P, P]
         L.orc_project_bwd.restype = None
+        L.orc_project_gut.argtypes = [i64, P, P, P, P, P, P, i32, i32, P, i32, i32, i32,
+                                      P, P, P, P, P, P]
+        L.orc_project_gut.restype = None
+        L.orc_render_fwd_gut.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P, P, P, P, P]
+        L.orc_render_fwd_gut.restype = None
+        L.orc_gut_response.argtypes = [i64, P, P, P, i32, i32, P]
+        L.orc_gut_response.restype = None
         L.orc_sh_basis.argtypes = [i32, P, P, P]
         L.orc_sh_basis.restype = None
         L.orc_num_threads.restype = i32
@@ -123,7 +136,11 @@ def _scene_arrays(scene):
 
 
 def project(scene, cam, cfg: OracleConfig):
-    """Projection of every Gaussian (Listing XPR-3DGS, project)."""
+    """Projection of every Gaussian (Listing XPR-3DGS, project; with
+    cfg.method == "3dgut" the unscented transform of Listing XPR-3DGUT,
+    then rec has 21 columns: the 9 of 3DGS, ro, M)."""
+    if cfg.method == "3dgut":
+        return project_gut(scene, cam, cfg)
     m, s, q, o, sh = _scene_arrays(scene)
     n = o.shape[0]
     K = sh.shape[0]
@@ -136,6 +153,31 @@ def project(scene, cam, cfg: OracleConfig):
                       cam.height, _p(pc), cfg.tile_w, cfg.tile_h, cfg.sh_degree,
                       _p(out["rec"]), _p(out["cov"]), _p(out["depth"]), _p(out["rect"]),
                       _p(out["tc"]), _p(out["radius"]), _p(out["guard"]))
+    return out
+
+
+def project_gut(scene, cam, cfg: OracleConfig):
+    """3DGUT projection (Listing XPR-3DGUT, project)."""
+    m, s, q, o, sh = _scene_arrays(scene)
+    n = o.shape[0]
+    out = dict(rec=np.zeros((n, 21)), cov=np.zeros((n, 3)), depth=np.zeros(n),
+               rect=np.zeros((n, 4), np.int32), tc=np.zeros(n, np.int32),
+               guard=np.zeros(n, np.uint8))
+    lib().orc_project_gut(n, _p(m), _p(s), _p(q), _p(o), _p(sh), _p(cam_vec(cam)), cam.width,
+                          cam.height, _p(cfg.gut_cfg()), cfg.tile_w, cfg.tile_h, cfg.sh_degree,
+                          _p(out["rec"]), _p(out["cov"]), _p(out["depth"]), _p(out["rect"]),
+                          _p(out["tc"]), _p(out["guard"]))
+    return out
+
+
+def gut_response(rec21, pxy, cam):
+    """3DGUT evaluate: the response along the ray of pixel pxy[k] for
+    record rec21[k]."""
+    rec21 = _f64(rec21).reshape(-1, 21)
+    pxy = np.ascontiguousarray(pxy, np.int32).reshape(-1, 2)
+    out = np.zeros(rec21.shape[0])
+    lib().orc_gut_response(rec21.shape[0], _p(rec21), _p(pxy), _p(cam_vec(cam)), cam.width,
+                           cam.height, _p(out))
     return out
 
 
@@ -159,14 +201,16 @@ def bin_pairs(depth, rect, tc, tiles_x: int, tiles_y: int, cull=None):
     kept = np.zeros(1, np.int64)
     nguard = np.zeros(1, np.int64)
     pguard = np.zeros(I, np.uint8)
-    crec, W, H, tw, th, amin = None, 0, 0, 0, 0, 0.0
+    crec, stride, ext, W, H, tw, th, amin = None, 9, 0, 0, 0, 0, 0, 0.0
     if cull is not None:
         rec, W, H, cfg = cull
         crec = _f64(rec)
-        assert crec.shape == (n, 9)
+        assert crec.shape[0] == n and crec.shape[1] in (9, 21)
+        stride = crec.shape[1]
+        ext = 1 if cfg.method == "3dgut" else 0
         tw, th, amin = cfg.tile_w, cfg.tile_h, cfg.alpha_min
     got = lib().orc_bin(n, _p(depth), _p(rect), _p(tc), tiles_x, tiles_y, I, _p(offsets),
-                        _p(keys), _p(vals), _p(ranges), _p(crec), W, H, tw, th, amin,
+                        _p(keys), _p(vals), _p(ranges), _p(crec), stride, ext, W, H, tw, th, amin,
                         _p(kept), _p(nguard), _p(pguard))
     assert got == I
     return dict(offsets=offsets, I=I, keys=keys, vals=vals, ranges=ranges,
@@ -184,14 +228,18 @@ def tile_cull(rec, txy, W: int, H: int, cfg: OracleConfig):
     power = np.zeros(m)
     level = np.zeros(m)
     guard = np.zeros(m, np.uint8)
-    lib().orc_tile_cull(m, _p(rec), _p(txy), W, H, cfg.tile_w, cfg.tile_h, cfg.alpha_min,
+    ext = 1 if cfg.method == "3dgut" else 0
+    lib().orc_tile_cull(m, _p(rec), _p(txy), W, H, cfg.tile_w, cfg.tile_h, cfg.alpha_min, ext,
                         _p(keep), _p(power), _p(level), _p(guard))
     return keep.astype(bool), power, level, guard.astype(bool)
 
 
-def render_fwd(rec, vals, ranges, W: int, H: int, cfg: OracleConfig):
-    """Compositing (Algorithm 1 with the 3DGS evaluate)."""
+def render_fwd(rec, vals, ranges, W: int, H: int, cfg: OracleConfig, cam=None):
+    """Compositing (Algorithm 1 with the 3DGS evaluate, or with the 3DGUT
+    pixel_info and evaluate when rec has 21 columns; cam is then needed)."""
     rec = _f64(rec)
+    if rec.shape[1] == 21:
+        return render_fwd_gut(rec, vals, ranges, cam, cfg)
     vals = np.ascontiguousarray(vals, np.int32)
     ranges = np.ascontiguousarray(ranges, np.int32)
     out = dict(img=np.zeros((3, H, W)), Tfinal=np.zeros((H, W)),
@@ -201,6 +249,23 @@ def render_fwd(rec, vals, ranges, W: int, H: int, cfg: OracleConfig):
     lib().orc_render_fwd(W, H, cfg.tile_w, cfg.tile_h, _p(rec), _p(vals), _p(ranges), _p(rc),
                          _p(out["img"]), _p(out["Tfinal"]), _p(out["ncontrib"]),
                          _p(out["nblend"]), _p(out["guard"]))
+    return out
+
+
+def render_fwd_gut(rec, vals, ranges, cam, cfg: OracleConfig):
+    """3DGUT compositing (Algorithm 1 with the XPR-3DGUT pixel_info and
+    evaluate)."""
+    rec = _f64(rec)
+    W, H = cam.width, cam.height
+    vals = np.ascontiguousarray(vals, np.int32)
+    ranges = np.ascontiguousarray(ranges, np.int32)
+    out = dict(img=np.zeros((3, H, W)), Tfinal=np.zeros((H, W)),
+               ncontrib=np.zeros((H, W), np.int32), nblend=np.zeros((H, W), np.int32),
+               guard=np.zeros((H, W), np.uint8))
+    lib().orc_render_fwd_gut(W, H, cfg.tile_w, cfg.tile_h, _p(rec), _p(vals), _p(ranges),
+                             _p(cam_vec(cam)), _p(cfg.render_cfg()), _p(out["img"]),
+                             _p(out["Tfinal"]), _p(out["ncontrib"]), _p(out["nblend"]),
+                             _p(out["guard"]))
     return out
 
 
@@ -240,12 +305,15 @@ def render(scene, cam, cfg: OracleConfig):
     tx, ty = tiles(cam, cfg)
     cull = (pr["rec"], cam.width, cam.height, cfg) if cfg.tile_cull else None
     b = bin_pairs(pr["depth"], pr["rect"], pr["tc"], tx, ty, cull)
-    f = render_fwd(pr["rec"], b["vals"], b["ranges"], cam.width, cam.height, cfg)
+    f = render_fwd(pr["rec"], b["vals"], b["ranges"], cam.width, cam.height, cfg, cam)
     return dict(proj=pr, bins=b, fwd=f)
 
 
 def backward(scene, cam, cfg: OracleConfig, dimg, state=None):
-    """Analytic gradient of <dimg, image> with respect to the scene."""
+    """Analytic gradient of <dimg, image> with respect to the scene (3DGS
+    only: the 3DGUT path is forward only)."""
+    if cfg.method != "3dgs":
+        raise NotImplementedError("the oracle's backward covers 3DGS only")
     st = render(scene, cam, cfg) if state is None else state
     g9 = render_bwd(st["proj"]["rec"], st["bins"]["vals"], st["bins"]["ranges"],
                     cam.width, cam.height, cfg, dimg)

@@ -172,3 +172,97 @@ def render(scene, cam, cfg: OracleConfig):
     with torch.no_grad():
         img, T = render_torch(*scene_tensors(scene), cam, cfg)
     return img.numpy(), T.numpy()
+
+
+def render_gut(scene, cam, cfg: OracleConfig):
+    """Per-pixel brute force of 3DGUT (Listing "Implementation of
+    XPR-3DGUT"), forward only, in torch float64: unscented-transform
+    projection (rect, visibility, adjusted opacity), then for every pixel the
+    ray response of every visible Gaussian whose rect contains the pixel's
+    tile, in (float32 depth, index) order, with the validity threshold and
+    the gates of the 3DGS path. No pairs, no sort, no tile ranges."""
+    means, scales, quats, opac, sh = scene_tensors(scene)
+    G = opac.shape[0]
+    Rw = torch.as_tensor(np.asarray(cam.R), dtype=torch.float64)
+    tw = torch.as_tensor(np.asarray(cam.t), dtype=torch.float64)
+    Rq = _quat_rot(quats)                                    # [G, 3, 3]
+    k = math.sqrt(3.0)
+    # sigma points [G, 7, 3]: centre, then mu +- sqrt(3) s_j Rq[:, j]
+    cols = Rq.transpose(1, 2) * scales[:, :, None]           # row j = s_j Rq[:, j]
+    pts = [means]
+    for j in range(3):
+        pts += [means + k * cols[:, j], means - k * cols[:, j]]
+    X = torch.stack(pts, 1)
+    Y = X @ Rw.T + tw
+    z = Y[..., 2]
+    front = (z > cfg.z_near).all(1)
+    P2 = torch.stack([cam.fx * Y[..., 0] / z + cam.cx, cam.fy * Y[..., 1] / z + cam.cy], -1)
+    wm = torch.tensor([0.0] + [1 / 6] * 6, dtype=torch.float64)
+    wc = torch.tensor([2.0] + [1 / 6] * 6, dtype=torch.float64)
+    m2 = (wm[None, :, None] * P2).sum(1)
+    D = P2 - m2[:, None, :]
+    cxx = (wc * D[..., 0] * D[..., 0]).sum(1)
+    cxy = (wc * D[..., 0] * D[..., 1]).sum(1)
+    cyy = (wc * D[..., 1] * D[..., 1]).sum(1)
+    det0 = cxx * cyy - cxy * cxy
+    a, b, c = cxx + cfg.lowpass, cxy, cyy + cfg.lowpass
+    det = a * c - b * b
+    o2 = opac * torch.sqrt(torch.clamp(det0, min=0.0) / det)
+    u, v = m2[:, 0] - 0.5, m2[:, 1] - 0.5
+    if cfg.opacity_extents:
+        lvl = 2 * torch.log(o2 / cfg.alpha_min)
+        ex = torch.where(lvl > 0, torch.sqrt(torch.clamp(lvl * a, min=0.0)), torch.zeros_like(a))
+        ey = torch.where(lvl > 0, torch.sqrt(torch.clamp(lvl * c, min=0.0)), torch.zeros_like(c))
+        r = torch.maximum(ex, ey)
+    else:
+        mid = 0.5 * (a + c)
+        r = torch.ceil(3 * torch.sqrt(mid + torch.sqrt(torch.clamp(mid * mid - det, min=0.0))))
+        ex = ey = r
+    txn = (cam.width + cfg.tile_w - 1) // cfg.tile_w
+    tyn = (cam.height + cfg.tile_h - 1) // cfg.tile_h
+    x0 = torch.clamp(torch.floor((u - ex) / cfg.tile_w), 0, txn)
+    x1 = torch.clamp(torch.floor((u + ex) / cfg.tile_w) + 1, 0, txn)
+    y0 = torch.clamp(torch.floor((v - ey) / cfg.tile_h), 0, tyn)
+    y1 = torch.clamp(torch.floor((v + ey) / cfg.tile_h) + 1, 0, tyn)
+    visible = front & (det > 0) & (o2 > cfg.alpha_min) & (r > 0) & ((x1 - x0) * (y1 - y0) > 0)
+    # shader data: camera position and ray directions in each Gaussian's frame
+    campos = -(Rw.T @ tw)
+    Minv = Rq.transpose(1, 2) / scales[:, :, None]          # S^-1 R^T
+    ro = (Minv @ (campos[None, :] - means)[:, :, None])[..., 0]
+    dirs = (means - campos) / (means - campos).norm(dim=1, keepdim=True)
+    nb = (cfg.sh_degree + 1) ** 2
+    colour = torch.clamp(0.5 + torch.einsum("gj,gjc->gc", _sh_real(cfg.sh_degree, dirs),
+                                            sh[:, :nb, :]), min=0.0)
+    W, H = cam.width, cam.height
+    ys, xs = torch.meshgrid(torch.arange(H, dtype=torch.float64),
+                            torch.arange(W, dtype=torch.float64), indexing="ij")
+    xs, ys = xs.reshape(-1), ys.reshape(-1)
+    dc = torch.stack([(xs + 0.5 - cam.cx) / cam.fx, (ys + 0.5 - cam.cy) / cam.fy,
+                      torch.ones_like(xs)], 1)
+    dc = dc / dc.norm(dim=1, keepdim=True)
+    rd = dc @ Rw                                             # R^T dc per row
+    ptx = (xs // cfg.tile_w).long()
+    pty = (ys // cfg.tile_h).long()
+    order = np.lexsort((np.arange(G), Y[:, 0, 2].to(torch.float32).numpy()))
+    img = torch.zeros(3, H * W, dtype=torch.float64)
+    T = torch.ones(H * W, dtype=torch.float64)
+    done = torch.zeros(H * W, dtype=torch.bool)
+    for g in order.tolist():
+        if not bool(visible[g]):
+            continue
+        inside = (ptx >= int(x0[g])) & (ptx < int(x1[g])) & (pty >= int(y0[g])) & (pty < int(y1[g]))
+        rdc = rd @ Minv[g].T
+        tau = -(rdc @ ro[g]) / (rdc * rdc).sum(1)
+        p = ro[g][None, :] + tau[:, None] * rdc
+        resp = torch.exp(-0.5 * (p * p).sum(1))
+        alpha = torch.clamp(o2[g] * resp, max=cfg.alpha_max)
+        live = inside & ~done & (resp > 0.0113) & (alpha >= cfg.alpha_min)
+        Tn = T * (1 - alpha)
+        stop = live & (Tn < cfg.t_min)
+        done = done | stop
+        blend = live & ~stop
+        a_ = torch.where(blend, alpha, torch.zeros_like(alpha))
+        img = img + colour[g][:, None] * (a_ * T)[None, :]
+        T = T * (1 - a_)
+    img = img + T[None, :] * torch.as_tensor(cfg.bg, dtype=torch.float64)[:, None]
+    return img.view(3, H, W).numpy(), T.view(H, W).numpy()

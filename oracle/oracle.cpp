@@ -20,6 +20,9 @@
 //     tile (the largest-response test the XPR-3DGS section describes).
 //   * Section "Shader", Algorithm 1: per-pixel front-to-back loop over the
 //     tile's list, gate and accumulate.
+//   * Listing "Implementation of XPR-3DGUT" (forward only): unscented-
+//     transform projection, pixel_info (ray direction) and the ray-based
+//     evaluate at tau_max; tile_cull with the extended tile bounds.
 // Readings where the paper is silent (pixel sample position, low-pass 0.3,
 // 3-sigma radius from the largest eigenvalue, conservative rect rounding,
 // alpha clamp 0.99, stop at T < 1e-4 before blending, ties by index, SH
@@ -317,9 +320,11 @@ struct CullTest {
 };
 
 CullTest tile_cull_one(const double* rec, int tx, int ty, int W, int H, int tile_w, int tile_h,
-                       double alpha_min) {
-  const double X0 = (double)tx * tile_w, X1 = std::min(X0 + tile_w - 1, W - 1.0);
-  const double Y0 = (double)ty * tile_h, Y1 = std::min(Y0 + tile_h - 1, H - 1.0);
+                       double alpha_min, int ext = 0) {
+  // ext = 1 for 3DGUT: its tile_cull first moves tile_max out by one pixel
+  // in x and y (the ray offset adjustment of Listing "XPR-3DGUT")
+  const double X0 = (double)tx * tile_w, X1 = std::min(X0 + tile_w - 1, W - 1.0) + ext;
+  const double Y0 = (double)ty * tile_h, Y1 = std::min(Y0 + tile_h - 1, H - 1.0) + ext;
   const double u = rec[0], v = rec[1];
   // conic entries from the shader data (-0.5 con00, -con01, -0.5 con11)
   const double a = -2.0 * rec[2], b = -rec[3], c = -2.0 * rec[4], o = rec[5];
@@ -348,6 +353,185 @@ CullTest tile_cull_one(const double* rec, int tx, int ty, int W, int H, int tile
   r.keep = r.power <= r.level;
   r.guard = std::fabs(r.power - r.level) <= 1e-9 * std::max(1.0, std::fabs(r.level));
   return r;
+}
+
+// ----------------------------------------------------------------------------
+// 3DGUT (Listing "Implementation of XPR-3DGUT"): unscented-transform
+// projection and per-pixel ray evaluation.
+//
+// Readings: the unscented transform of n = 3 dimensions with alpha = 1,
+// beta = 2, kappa = 0, so lambda = 0: sigma points mu and
+// mu +- sqrt(3) s_j R e_j (j = 0..2), mean weights 0 (centre) and 1/6,
+// covariance weights 2 (centre) and 1/6; the 2D points are the pinhole
+// projections f X / Z + c; a Gaussian with a sigma point at camera depth
+// <= z_near is not visible (the projection is undefined there); the opacity
+// compensation of the low-pass (Mip-Splatting) is sqrt(det_orig / det).
+// ----------------------------------------------------------------------------
+struct GutProj {
+  double u, v, A, B, C, o;  // 2D cull data (mean2D - 1/2, scaled conic), adjusted opacity
+  double colour[3];
+  double ro[3], M[9];       // canonical ray origin, M = S^-1 R^T (row-major)
+  double a, b, c;           // low-passed 2D covariance
+  double depth;
+  int rect[4];
+  int tc;
+  bool guard;
+};
+
+void project_gut_one(int64_t i, int64_t n, const double* means, const double* scales,
+                     const double* quats, const double* opac, const double* sh, const Cam& cam,
+                     const double* cfg, int tile_w, int tile_h, int deg, GutProj& G) {
+  const double lowpass = cfg[0], alpha_min = cfg[1], z_near = cfg[2];
+  const bool opacity_extents = cfg[3] != 0.0;
+  const int tiles_x = (cam.W + tile_w - 1) / tile_w;
+  const int tiles_y = (cam.H + tile_h - 1) / tile_h;
+  std::memset(&G, 0, sizeof(G));
+  const double mu[3] = {means[i], means[n + i], means[2 * n + i]};
+  const double q[4] = {quats[i], quats[n + i], quats[2 * n + i], quats[3 * n + i]};
+  const double qn = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  const double qu[4] = {q[0] / qn, q[1] / qn, q[2] / qn, q[3] / qn};
+  double Rq[9];
+  quat_to_rot(qu, Rq);
+  const double s[3] = {scales[i], scales[n + i], scales[2 * n + i]};
+  // sigma points: centre, then +- sqrt(3) s_j times column j of Rq
+  double X[7][3];
+  for (int c = 0; c < 3; ++c) X[0][c] = mu[c];
+  const double k = std::sqrt(3.0);
+  for (int j = 0; j < 3; ++j)
+    for (int sg = 0; sg < 2; ++sg)
+      for (int c = 0; c < 3; ++c)
+        X[1 + 2 * j + sg][c] = mu[c] + (sg ? -1.0 : 1.0) * k * s[j] * Rq[3 * c + j];
+  const double wm[7] = {0.0, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
+  const double wc[7] = {2.0, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
+  double P2[7][2];
+  bool front = true;
+  double zc = 0.0;
+  for (int p = 0; p < 7; ++p) {
+    double y[3];
+    for (int r = 0; r < 3; ++r)
+      y[r] = cam.R[3 * r] * X[p][0] + cam.R[3 * r + 1] * X[p][1] + cam.R[3 * r + 2] * X[p][2] +
+             cam.t[r];
+    if (p == 0) zc = y[2];
+    if (!(y[2] > z_near)) front = false;
+    if (std::fabs(y[2] - z_near) <= 1e-9 * std::max(1.0, z_near)) G.guard = true;
+    P2[p][0] = cam.fx * y[0] / y[2] + cam.cx;
+    P2[p][1] = cam.fy * y[1] / y[2] + cam.cy;
+  }
+  G.depth = zc;
+  double m2[2] = {0.0, 0.0};
+  for (int p = 0; p < 7; ++p) {
+    m2[0] += wm[p] * P2[p][0];
+    m2[1] += wm[p] * P2[p][1];
+  }
+  double cxx = 0.0, cxy = 0.0, cyy = 0.0;
+  for (int p = 0; p < 7; ++p) {
+    const double dx = P2[p][0] - m2[0], dy = P2[p][1] - m2[1];
+    cxx += wc[p] * dx * dx;
+    cxy += wc[p] * dx * dy;
+    cyy += wc[p] * dy * dy;
+  }
+  const double det_orig = cxx * cyy - cxy * cxy;
+  G.a = cxx + lowpass;
+  G.b = cxy;
+  G.c = cyy + lowpass;
+  const double det = G.a * G.c - G.b * G.b;
+  if (std::fabs(det) <= 1e-9 * G.a * G.c) G.guard = true;
+  double con[3] = {0.0, 0.0, 0.0};
+  if (det > 0) {
+    con[0] = G.c / det;
+    con[1] = -G.b / det;
+    con[2] = G.a / det;
+  }
+  const double o = opac[i] * (det > 0 ? std::sqrt(std::max(det_orig, 0.0) / det) : 0.0);
+  G.o = o;
+  if (std::fabs(o - alpha_min) <= 1e-9 * alpha_min) G.guard = true;
+  // the bounding box is placed at mean2D - 1/2 (ray offset): pixel (i, j)
+  // is the ray through (i + 1/2, j + 1/2)
+  G.u = m2[0] - 0.5;
+  G.v = m2[1] - 0.5;
+  G.A = -0.5 * con[0];
+  G.B = -con[1];
+  G.C = -0.5 * con[2];
+  double ex, ey, rad;
+  if (opacity_extents) {
+    const double lvl = o > 0 ? 2.0 * std::log(o / alpha_min) : -1.0;
+    ex = lvl > 0.0 ? std::sqrt(lvl * G.a) : 0.0;
+    ey = lvl > 0.0 ? std::sqrt(lvl * G.c) : 0.0;
+    rad = std::max(ex, ey);
+  } else {
+    const double mid = 0.5 * (G.a + G.c);
+    const double lam = mid + std::sqrt(std::max(0.0, mid * mid - det));
+    const double r3 = 3.0 * std::sqrt(lam);
+    if (near_int(r3, 1e-9 * std::max(1.0, r3))) G.guard = true;
+    rad = std::ceil(r3);
+    ex = ey = rad;
+  }
+  const double fx0 = (G.u - ex) / tile_w, fx1 = (G.u + ex) / tile_w;
+  const double fy0 = (G.v - ey) / tile_h, fy1 = (G.v + ey) / tile_h;
+  auto clampi = [](double x, int lo, int hi) {
+    return (int)std::min<double>(hi, std::max<double>(lo, x));
+  };
+  G.rect[0] = clampi(std::floor(fx0), 0, tiles_x);
+  G.rect[1] = clampi(std::floor(fy0), 0, tiles_y);
+  G.rect[2] = clampi(std::floor(fx1) + 1, 0, tiles_x);
+  G.rect[3] = clampi(std::floor(fy1) + 1, 0, tiles_y);
+  const double g = 1e-9;
+  if (near_int(fx0, g * std::max(1.0, std::fabs(fx0))) ||
+      near_int(fx1, g * std::max(1.0, std::fabs(fx1))) ||
+      near_int(fy0, g * std::max(1.0, std::fabs(fy0))) ||
+      near_int(fy1, g * std::max(1.0, std::fabs(fy1))))
+    G.guard = true;
+  const int area = (G.rect[2] - G.rect[0]) * (G.rect[3] - G.rect[1]);
+  const bool visible = front && det > 0 && o > alpha_min && rad > 0 && area > 0;
+  G.tc = visible ? area : 0;
+  // shader data: M = S^-1 R^T and the camera position in canonical space
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) G.M[3 * r + c] = Rq[3 * c + r] / s[r];
+  const double cp[3] = {
+      -(cam.R[0] * cam.t[0] + cam.R[3] * cam.t[1] + cam.R[6] * cam.t[2]),
+      -(cam.R[1] * cam.t[0] + cam.R[4] * cam.t[1] + cam.R[7] * cam.t[2]),
+      -(cam.R[2] * cam.t[0] + cam.R[5] * cam.t[1] + cam.R[8] * cam.t[2])};
+  for (int r = 0; r < 3; ++r)
+    G.ro[r] = G.M[3 * r] * (cp[0] - mu[0]) + G.M[3 * r + 1] * (cp[1] - mu[1]) +
+              G.M[3 * r + 2] * (cp[2] - mu[2]);
+  // view-dependent colour, as for 3DGS
+  double dv[3] = {mu[0] - cp[0], mu[1] - cp[1], mu[2] - cp[2]};
+  const double dn = std::sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+  for (int c = 0; c < 3; ++c) dv[c] /= dn;
+  double Y[16];
+  sh_basis(deg, dv, Y, nullptr);
+  const int nb = (deg + 1) * (deg + 1);
+  for (int ch = 0; ch < 3; ++ch) {
+    double acc = 0.5;
+    for (int j = 0; j < nb; ++j) acc += sh[(int64_t)(j * 3 + ch) * n + i] * Y[j];
+    G.colour[ch] = std::max(0.0, acc);
+  }
+}
+
+// pixel_info of 3DGUT: the world-space unit direction of the ray through
+// pixel (px, py), i.e. through (px + 1/2, py + 1/2).
+void gut_ray(const Cam& cam, int px, int py, double rd[3]) {
+  double dc[3] = {(px + 0.5 - cam.cx) / cam.fx, (py + 0.5 - cam.cy) / cam.fy, 1.0};
+  const double nn = std::sqrt(dc[0] * dc[0] + dc[1] * dc[1] + dc[2] * dc[2]);
+  for (int c = 0; c < 3; ++c) dc[c] /= nn;
+  for (int c = 0; c < 3; ++c)
+    rd[c] = cam.R[c] * dc[0] + cam.R[3 + c] * dc[1] + cam.R[6 + c] * dc[2];
+}
+
+// evaluate of 3DGUT: the largest response of the canonical Gaussian
+// exp(-|x|^2 / 2) along the ray ro + tau M rd, reached at
+// tau_max = -(ro . rdc) / (rdc . rdc).
+double gut_response(const double* ro, const double* M, const double rd[3]) {
+  double rdc[3];
+  for (int r = 0; r < 3; ++r) rdc[r] = M[3 * r] * rd[0] + M[3 * r + 1] * rd[1] + M[3 * r + 2] * rd[2];
+  const double tau = -(ro[0] * rdc[0] + ro[1] * rdc[1] + ro[2] * rdc[2]) /
+                     (rdc[0] * rdc[0] + rdc[1] * rdc[1] + rdc[2] * rdc[2]);
+  double d2 = 0.0;
+  for (int r = 0; r < 3; ++r) {
+    const double x = ro[r] + tau * rdc[r];
+    d2 += x * x;
+  }
+  return std::exp(-0.5 * d2);
 }
 
 }  // namespace
@@ -414,19 +598,20 @@ void orc_project(int64_t n, const double* means, const double* scales, const dou
 //   offsets [n] (exclusive prefix sum of tc, may be NULL)
 //   keys [cap]: tile << 32 | float32 bits of depth (may be NULL)
 //   vals [cap]: Gaussian index, ranges [tiles_x*tiles_y][2]
-// With cull_rec [n][9] (shader data, may be NULL) every replicated pair
+// With cull_rec [n][rec_stride] (shader data, may be NULL) every replicated pair
 // also goes through tile_cull (Listing "XPR-3DGS") and a culled pair gets
 // the sentinel tile id tiles_x*tiles_y, so it sorts after every real tile
 // and belongs to no range; *n_kept counts the pairs not culled, *n_guard the
 // pairs whose decision is in the guard band, pair_guard [cap] (may be NULL)
 // flags them in sorted order. W, H, tile_w, tile_h and alpha_min are only
-// read with cull_rec.
+// read with cull_rec; rec_stride is 9 (3DGS) or 21 (3DGUT, whose cull uses
+// tile bounds extended by ext = 1).
 // Returns I = sum tc; writes the lists only when I <= cap.
 int64_t orc_bin(int64_t n, const double* depth, const int32_t* rect, const int32_t* tc,
                 int tiles_x, int tiles_y, int64_t cap, int64_t* offsets, uint64_t* keys,
-                int32_t* vals, int32_t* ranges, const double* cull_rec, int W, int H, int tile_w,
-                int tile_h, double alpha_min, int64_t* n_kept, int64_t* n_guard,
-                uint8_t* pair_guard) {
+                int32_t* vals, int32_t* ranges, const double* cull_rec, int rec_stride, int ext,
+                int W, int H, int tile_w, int tile_h, double alpha_min, int64_t* n_kept,
+                int64_t* n_guard, uint8_t* pair_guard) {
   std::vector<int64_t> off(n + 1, 0);
   for (int64_t i = 0; i < n; ++i) off[i + 1] = off[i] + tc[i];
   const int64_t I = off[n];
@@ -445,7 +630,8 @@ int64_t orc_bin(int64_t n, const double* depth, const int32_t* rect, const int32
       uint32_t tile = (uint32_t)(y * tiles_x + x);
       uint8_t g = 0;
       if (cull_rec) {
-        const CullTest t = tile_cull_one(cull_rec + 9 * i, x, y, W, H, tile_w, tile_h, alpha_min);
+        const CullTest t = tile_cull_one(cull_rec + (int64_t)rec_stride * i, x, y, W, H, tile_w,
+                                         tile_h, alpha_min, ext);
         if (!t.keep) tile = sentinel;
         g = t.guard ? 1 : 0;
       }
@@ -486,14 +672,15 @@ int64_t orc_bin(int64_t n, const double* depth, const int32_t* rect, const int32
 }
 
 // tile_cull of m (Gaussian, tile) pairs: rec [m][9] shader data, txy [m][2]
-// tile coordinates; keep, power (smallest 0.5 q over the tile), level
-// (log(o / alpha_min)) and guard per pair (any output may be NULL).
+// tile coordinates, ext the tile-bound extension (0 for 3DGS, 1 for 3DGUT);
+// keep, power (smallest 0.5 q over the tile), level (log(o / alpha_min))
+// and guard per pair (any output may be NULL).
 void orc_tile_cull(int64_t m, const double* rec, const int32_t* txy, int W, int H, int tile_w,
-                   int tile_h, double alpha_min, uint8_t* keep, double* power, double* level,
-                   uint8_t* guard) {
+                   int tile_h, double alpha_min, int ext, uint8_t* keep, double* power,
+                   double* level, uint8_t* guard) {
   for (int64_t k = 0; k < m; ++k) {
-    const CullTest t =
-        tile_cull_one(rec + 9 * k, txy[2 * k], txy[2 * k + 1], W, H, tile_w, tile_h, alpha_min);
+    const CullTest t = tile_cull_one(rec + 9 * k, txy[2 * k], txy[2 * k + 1], W, H, tile_w,
+                                     tile_h, alpha_min, ext);
     if (keep) keep[k] = t.keep ? 1 : 0;
     if (power) power[k] = t.power;
     if (level) level[k] = t.level;
@@ -553,6 +740,101 @@ void orc_render_fwd(int W, int H, int tile_w, int tile_h, const double* rec, con
         if (nblend) nblend[p] = count;
         if (guard) guard[p] = g ? 1 : 0;
       }
+  }
+}
+
+// 3DGUT projection of n Gaussians (Listing "XPR-3DGUT", project).
+//   cfg: lowpass, alpha_min, z_near, opacity_extents (0/1)
+// Outputs (any may be NULL): rec [n][21] = u, v, A, B, C, o', r, g, b
+// (2D cull data and colour, laid out like the 3DGS shader data), ro (3),
+// M (9, row-major); cov [n][3]; depth [n]; rect [n][4]; tc [n]; guard [n].
+void orc_project_gut(int64_t n, const double* means, const double* scales, const double* quats,
+                     const double* opac, const double* sh, const double* camv, int W, int H,
+                     const double* cfg, int tile_w, int tile_h, int deg, double* rec, double* cov,
+                     double* depth, int32_t* rect, int32_t* tc, uint8_t* guard) {
+  const Cam cam = read_cam(camv, W, H);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    GutProj G;
+    project_gut_one(i, n, means, scales, quats, opac, sh, cam, cfg, tile_w, tile_h, deg, G);
+    if (rec) {
+      double* r = rec + 21 * i;
+      const double v9[9] = {G.u, G.v, G.A, G.B, G.C, G.o, G.colour[0], G.colour[1], G.colour[2]};
+      for (int c = 0; c < 9; ++c) r[c] = v9[c];
+      for (int c = 0; c < 3; ++c) r[9 + c] = G.ro[c];
+      for (int c = 0; c < 9; ++c) r[12 + c] = G.M[c];
+    }
+    if (cov) { cov[3 * i] = G.a; cov[3 * i + 1] = G.b; cov[3 * i + 2] = G.c; }
+    if (depth) depth[i] = G.depth;
+    if (rect) for (int c = 0; c < 4; ++c) rect[4 * i + c] = G.rect[c];
+    if (tc) tc[i] = G.tc;
+    if (guard) guard[i] = G.guard ? 1 : 0;
+  }
+}
+
+// 3DGUT forward compositing (Algorithm 1 with the 3DGUT pixel_info and
+// evaluate): per pixel the ray direction rd; per listed record the response
+// along the ray, alpha = o' response, skipped unless response > 0.0113
+// (the listing's validity threshold) and, as for 3DGS, alpha =
+// min(alpha_max, alpha) >= alpha_min; same stop rule and blending.
+//   rec [n][21], vals / ranges from orc_bin, camv the camera (pixel_info)
+//   cfg: alpha_min, alpha_max, t_min, bg0, bg1, bg2; outputs as orc_render_fwd
+void orc_render_fwd_gut(int W, int H, int tile_w, int tile_h, const double* rec,
+                        const int32_t* vals, const int32_t* ranges, const double* camv,
+                        const double* cfg, double* img, double* Tfinal, int32_t* ncontrib,
+                        int32_t* nblend, uint8_t* guard) {
+  const Cam cam = read_cam(camv, W, H);
+  const double alpha_min = cfg[0], alpha_max = cfg[1], t_min = cfg[2];
+  const double bg[3] = {cfg[3], cfg[4], cfg[5]};
+  const double valid_min = 0.0113;
+  const int tiles_x = (W + tile_w - 1) / tile_w;
+  const int tiles_y = (H + tile_h - 1) / tile_h;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int t = 0; t < tiles_x * tiles_y; ++t) {
+    const int tx = t % tiles_x, ty = t / tiles_x;
+    const int32_t start = ranges[2 * t], end = ranges[2 * t + 1];
+    for (int py = ty * tile_h; py < std::min(H, (ty + 1) * tile_h); ++py)
+      for (int px = tx * tile_w; px < std::min(W, (tx + 1) * tile_w); ++px) {
+        double rd[3];
+        gut_ray(cam, px, py, rd);
+        double T = 1.0, C[3] = {0, 0, 0};
+        int32_t last = 0, count = 0;
+        bool g = false;
+        for (int32_t k = start; k < end; ++k) {
+          const double* r = rec + 21 * (int64_t)vals[k];
+          const double resp = gut_response(r + 9, r + 12, rd);
+          if (std::fabs(resp - valid_min) <= 1e-6 * valid_min) g = true;
+          if (!(resp > valid_min)) continue;
+          const double alpha = std::min(alpha_max, r[5] * resp);
+          if (std::fabs(alpha - alpha_min) <= 1e-4 * alpha_min) g = true;
+          if (alpha < alpha_min) continue;
+          const double Tn = T * (1.0 - alpha);
+          if (std::fabs(Tn - t_min) <= 1e-3 * t_min) g = true;
+          if (Tn < t_min) break;
+          for (int c = 0; c < 3; ++c) C[c] += r[6 + c] * alpha * T;
+          T = Tn;
+          last = k - start + 1;
+          ++count;
+        }
+        const int64_t p = (int64_t)py * W + px;
+        for (int c = 0; c < 3; ++c) img[(int64_t)c * W * H + p] = C[c] + T * bg[c];
+        if (Tfinal) Tfinal[p] = T;
+        if (ncontrib) ncontrib[p] = last;
+        if (nblend) nblend[p] = count;
+        if (guard) guard[p] = g ? 1 : 0;
+      }
+  }
+}
+
+// The 3DGUT response along the ray through pixel (px, py) for m records
+// rec [m][21] (one pixel per record): out [m].
+void orc_gut_response(int64_t m, const double* rec, const int32_t* pxy, const double* camv,
+                      int W, int H, double* out) {
+  const Cam cam = read_cam(camv, W, H);
+  for (int64_t k = 0; k < m; ++k) {
+    double rd[3];
+    gut_ray(cam, pxy[2 * k], pxy[2 * k + 1], rd);
+    out[k] = gut_response(rec + 21 * k + 9, rec + 21 * k + 12, rd);
   }
 }
 
