@@ -59,6 +59,10 @@ typedef enum {
   XPR_ERR_UNSUPPORTED = 4
 } xpr_status;
 
+/* Methods (listings "Implementation of XPR-3DGS" and "...XPR-3DGUT"). */
+#define XPR_METHOD_3DGS 0  /* EWA projection, 2D Gaussian evaluate; forward and backward */
+#define XPR_METHOD_3DGUT 1 /* unscented-transform projection, ray evaluate; forward only */
+
 /* Sort strategies of xpr_bin_sort; both produce the identical list. */
 #define XPR_SORT_PRESORT 0 /* sort Gaussians by depth, then pairs by tile */
 #define XPR_SORT_FULL 1    /* one radix sort of 64-bit (tile, depth) keys */
@@ -97,6 +101,7 @@ typedef struct xpr_config {
   int32_t persistent;     /* 1: persistent render grids pulling from tile_order */
   int32_t tile_cull;      /* 1: per-(Gaussian, tile) cull in xpr_bin_sort (0) */
   int32_t opacity_extents; /* 1: rect from the alpha >= alpha_min extents, not 3 sigma (0) */
+  int32_t method;         /* XPR_METHOD_3DGS (0) or XPR_METHOD_3DGUT */
 } xpr_config;
 
 /* One scene of n Gaussians, structure of arrays with leading dimension ld:
@@ -139,7 +144,12 @@ typedef struct xpr_views {
  * one record per (view, Gaussian)). The paper's ProjectResult:
  *   splat [total][12] float: u, v, A, B | C, o, r, g | b, 0, 0, 0 where
  *         (u, v) is mean2D and A = -0.5 con00, B = -con01, C = -0.5 con11
- *         the scaled conic (the listing's shader data), (r, g, b) the colour
+ *         the scaled conic (the listing's shader data), (r, g, b) the colour;
+ *         with XPR_METHOD_3DGUT [total][24] float: the same 9 values (o the
+ *         adjusted opacity o', (u, v) = UT mean2D - 1/2 and the conic of the
+ *         UT covariance: the listing's tile cull data), then ro (3), the
+ *         camera position in the Gaussian's canonical frame, M = S^-1 R^T
+ *         (9, row-major) and 3 zeros (the listing's shader data)
  *   depth [total] float: camera-space z
  *   rect  [total][4] int16: tile-space box x0, y0, x1, y1 (half-open)
  *   tiles_touched [total] int32: (x1-x0)(y1-y0) if visible else 0 */
@@ -175,7 +185,14 @@ xpr_status xpr_batch_sizes(const xpr_views* views, const xpr_config* cfg, xpr_si
  * ey = sqrt(2 ln(o / alpha_min) cov_yy) (cov with the low-pass), the rect is
  * [floor((u-ex)/tw), floor((u+ex)/tw)+1) x [floor((v-ey)/th),
  * floor((v+ey)/th)+1) and r = max(ex, ey); every pixel whose alpha can pass
- * the alpha_min gate then lies in the rect. Colour
+ * the alpha_min gate then lies in the rect.
+ * With cfg->method = XPR_METHOD_3DGUT (listing XPR-3DGUT, project): the
+ * unscented transform of n = 3 with alpha = 1, beta = 2, kappa = 0 (sigma
+ * points mu and mu +- sqrt(3) s_j R e_j; mean weights 0 and 1/6, covariance
+ * weights 2 and 1/6) through the pinhole projection; invisible when a sigma
+ * point has z <= z_near; cov2D + lowpass I; o' = o sqrt(det_orig / det);
+ * rect as above around (u, v) = mean2D - 1/2; visibility also needs
+ * o' > alpha_min; ro and M as in the record layout above. Colour
  * max(0, 0.5 + sum_lm sh_lm Y_lm(dir)) with the real SH basis (Condon-Shortley
  * phase) and dir = (mu - campos) / |mu - campos|. Writes every field of
  * *out for all records (invisible: tiles_touched = 0). */
@@ -217,7 +234,9 @@ xpr_status xpr_bin_sort_workspace(const xpr_views* views, const xpr_config* cfg,
  * lists, ranges and *n_isect then hold the kept pairs only (the listing's
  * sentinel tile for culled pairs is never materialised), the image is the
  * same up to alpha values at the 1/255 threshold, and the presort strategy
- * is used whatever cfg->sort_mode says.
+ * is used whatever cfg->sort_mode says. For XPR_METHOD_3DGUT the tile box
+ * is first extended by one pixel in x and y (tile_max += 1 of its
+ * tile_cull).
  *   out     buffers as described at xpr_bins
  *   ws / ws_bytes   workspace of at least xpr_bin_sort_workspace() bytes
  * With cfg->no_sync == 0 the call reads I back (one stream sync) and returns
@@ -242,7 +261,14 @@ xpr_status xpr_bin_sort(const xpr_views* views, const xpr_config* cfg, const xpr
  *   workgroup evaluated before every pixel was done (the lockstep work).
  * Tiles are scheduled in tile_order when given; with cfg->persistent a grid
  * sized to fill the device pulls tiles from that order through an atomic
- * counter (then tile_order is required). */
+ * counter (then tile_order is required).
+ * XPR_METHOD_3DGUT (pixel_info and evaluate of listing XPR-3DGUT): per pixel
+ * the world ray direction through (x + 1/2, y + 1/2); per entry the largest
+ * response exp(-d^2 / 2) of the Gaussian along that ray, d^2 the squared
+ * canonical distance at tau_max; skipped unless the response > 0.0113; then
+ * alpha = min(alpha_max, o' response) with the gates, stop rule and
+ * blending above. Evaluated with d^2 in float64. cfg->lds_batch, fwd_ppt
+ * and persistent do not apply (256 / 64 threads per 16x16 / 8x8 tile). */
 xpr_status xpr_render_fwd(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
                           const xpr_bins* bins, float* image, float* T_final, int32_t* n_contrib,
                           int32_t* tile_work, hipStream_t stream);
@@ -263,7 +289,7 @@ xpr_status xpr_render_bwd_workspace(const xpr_views* views, const xpr_config* cf
  * The compositing backward walks each pixel's list in reverse from its last
  * blended entry (T_i recovered as T_{i+1} / (1 - a_i)); tiles are scheduled
  * as in xpr_render_fwd. Gradient sums use float atomics, so the last bits
- * vary from run to run. */
+ * vary from run to run. XPR_METHOD_3DGS only (XPR_ERR_UNSUPPORTED otherwise). */
 xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
                           const xpr_bins* bins, const float* dL_dimage, const float* T_final,
                           const int32_t* n_contrib, const xpr_scene_grad* grads,
@@ -274,7 +300,7 @@ xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const x
  * xpr_render_bwd) to the parameter gradients of every scene, summed over the
  * views that render it (one thread per Gaussian loops over those views, so
  * the sum is deterministic). Records with tiles_touched == 0 contribute
- * nothing. grads and accumulate as in xpr_render_bwd. */
+ * nothing. grads and accumulate as in xpr_render_bwd. XPR_METHOD_3DGS only. */
 xpr_status xpr_project_bwd(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
                            const float* grad2d, const xpr_scene_grad* grads, int32_t accumulate,
                            hipStream_t stream);

@@ -20,6 +20,8 @@ XPR_ERR_UNSUPPORTED = 4
 XPR_SORT_PRESORT = 0
 XPR_SORT_FULL = 1
 XPR_SORT_BANDS = 2
+XPR_METHOD_3DGS = 0
+XPR_METHOD_3DGUT = 1
 XPR_MAX_VIEWS = 32
 XPR_MAX_SCENES = 8
 
@@ -40,7 +42,7 @@ class XprConfig(ctypes.Structure):
                 ("z_near", _f), ("fov_clip", _f), ("bg", _f * 3), ("sort_mode", _i32),
                 ("no_sync", _i32), ("fwd_ppt", _i32), ("bwd_ppt", _i32),
                 ("bwd_lds_batch", _i32), ("persistent", _i32), ("tile_cull", _i32),
-                ("opacity_extents", _i32)]
+                ("opacity_extents", _i32), ("method", _i32)]
 
 
 class XprScene(ctypes.Structure):

@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libxpr.so")
 BUILD_DIR = os.path.join(PKG, "_build")
-SOURCES = ["api.hip", "project.hip", "sort.hip", "render.hip", "loss.hip"]
+SOURCES = ["api.hip", "project.hip", "sort.hip", "render.hip", "render_gut.hip", "loss.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -26,6 +26,9 @@ hipError_t bin_phase2(const Batch& B, int sort_mode, bool cull, const float* spl
                       int64_t cap, int64_t grid_n, const int64_t* n_isect, uint64_t* keys_out,
                       int32_t* vals, int2* ranges, int32_t* tile_order, void* ws, size_t ws_bytes,
                       hipStream_t st);
+hipError_t launch_render_fwd_gut(const Batch& B, const float* splat, const int32_t* vals,
+                                 const int32_t* ranges, const int32_t* order, float* image,
+                                 float* Tfin, int32_t* ncon, int32_t* tile_work, hipStream_t st);
 hipError_t launch_render_fwd(const Batch& B, int lds_batch, int ppt, bool persistent,
                              const float* splat, const int32_t* vals, const int32_t* ranges,
                              int32_t* order, float* image, float* Tfin, int32_t* ncon,
@@ -101,6 +104,8 @@ static xpr_status check_config(const xpr_config* c) {
             "bwd_lds_batch %d not in {0,64,128,256,512}", c->bwd_lds_batch);
   XPR_CHECK(c->tile_cull == 0 || c->tile_cull == 1, "tile_cull must be 0 or 1");
   XPR_CHECK(c->opacity_extents == 0 || c->opacity_extents == 1, "opacity_extents must be 0 or 1");
+  XPR_CHECK(c->method == XPR_METHOD_3DGS || c->method == XPR_METHOD_3DGUT, "method %d unknown",
+            c->method);
   return XPR_OK;
 }
 
@@ -175,6 +180,7 @@ static xpr_status build_batch(const xpr_views* vw, const xpr_config* c, Batch* B
   B->tile_h = c->tile_h;
   B->sh_degree = c->sh_degree;
   B->opacity_extents = c->opacity_extents;
+  B->method = c->method;
   B->lowpass = c->lowpass;
   B->alpha_min = c->alpha_min;
   B->alpha_max = c->alpha_max;
@@ -255,6 +261,7 @@ void xpr_config_default(xpr_config* c) {
   c->persistent = 0;
   c->tile_cull = 0;
   c->opacity_extents = 0;
+  c->method = XPR_METHOD_3DGS;
 }
 
 xpr_status xpr_batch_sizes(const xpr_views* views, const xpr_config* cfg, xpr_sizes* out) {
@@ -360,6 +367,11 @@ xpr_status xpr_render_fwd(const xpr_views* views, const xpr_config* cfg, const x
                 aligned(n_contrib, 4) && (!bins->vals || aligned(bins->vals, 4)) &&
                 (!tile_work || aligned(tile_work, 4)),
             "misaligned buffer");
+  if (cfg->method == XPR_METHOD_3DGUT) {
+    XPR_HIP(launch_render_fwd_gut(B, proj->splat, bins->vals, bins->tile_ranges, bins->tile_order,
+                                  image, T_final, n_contrib, tile_work, stream));
+    return XPR_OK;
+  }
   XPR_HIP(launch_render_fwd(B, cfg->lds_batch, cfg->fwd_ppt, cfg->persistent != 0, proj->splat,
                             bins->vals, bins->tile_ranges, bins->tile_order, image, T_final,
                             n_contrib, tile_work, stream));
@@ -389,6 +401,10 @@ xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const x
   if (st != XPR_OK) return st;
   st = check_proj(proj, S);
   if (st != XPR_OK) return st;
+  if (cfg->method != XPR_METHOD_3DGS) {
+    set_error("the backward is built for XPR_METHOD_3DGS only");
+    return XPR_ERR_UNSUPPORTED;
+  }
   XPR_CHECK(bins && bins->tile_ranges && dL_dimage && T_final && n_contrib, "NULL buffer");
   XPR_CHECK(grads || grad2d, "grads and grad2d both NULL");
   XPR_CHECK(!cfg->persistent || bins->tile_order, "persistent needs bins->tile_order");
@@ -439,6 +455,10 @@ xpr_status xpr_project_bwd(const xpr_views* views, const xpr_config* cfg, const 
   if (st != XPR_OK) return st;
   st = check_proj(proj, S);
   if (st != XPR_OK) return st;
+  if (cfg->method != XPR_METHOD_3DGS) {
+    set_error("the backward is built for XPR_METHOD_3DGS only");
+    return XPR_ERR_UNSUPPORTED;
+  }
   XPR_CHECK(grads != nullptr, "grads is NULL");
   XPR_CHECK(S.records == 0 || (grad2d && aligned(grad2d, 4)), "grad2d NULL or misaligned");
   GradDev G[XPR_MAX_SCENES];

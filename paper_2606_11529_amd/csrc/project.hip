@@ -459,6 +459,144 @@ __global__ __launch_bounds__(256) void k_project_bwd(Batch B, const float* __res
   }
 }
 
+// 3DGUT projection (listing "Implementation of XPR-3DGUT", project), one
+// thread per (view, Gaussian), in FP64 like the EWA path. The unscented
+// transform of the 3D Gaussian (n = 3, alpha = 1, beta = 2, kappa = 0, so
+// lambda = 0): sigma points mu and mu +- sqrt(3) s_j R e_j, mean weights 0
+// (centre) and 1/6, covariance weights 2 (centre) and 1/6, each point taken
+// through the pinhole projection f X / Z + c; a Gaussian with a sigma point
+// at camera depth <= z_near is not visible. The 2D covariance gets the
+// low-pass, the opacity the Mip-Splatting factor sqrt(det_orig / det), and
+// the bounding box is placed at mean2D - 1/2 (pixel (i, j) is the ray
+// through (i + 1/2, j + 1/2)). Record layout (24 floats):
+//   (u, v, A, B) (C, o', r, g) (b, ro) (M00 M01 M02 M10) (M11 M12 M20 M21)
+//   (M22, 0, 0, 0)
+// with (u, v) = mean2D - 1/2, (A, B, C) the scaled conic as for 3DGS, ro the
+// camera position in the Gaussian's canonical frame and M = S^-1 R^T.
+template <int DEG>
+__global__ __launch_bounds__(256) void k_project_gut(Batch B, float4* __restrict__ splat,
+                                                     float* __restrict__ depth,
+                                                     short4* __restrict__ rect,
+                                                     int32_t* __restrict__ tc) {
+  const ViewDev& V = B.v[blockIdx.y];
+  const SceneDev& S = B.s[V.scene];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= S.n) return;
+  const double mu[3] = {S.means[i], S.means[S.ld + i], S.means[2 * S.ld + i]};
+  double R[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) R[k] = V.R[k];
+  const double qw = S.quats[i], qx = S.quats[S.ld + i], qy = S.quats[2 * S.ld + i],
+               qz = S.quats[3 * S.ld + i];
+  const double qinv = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  const double w = qw * qinv, x = qx * qinv, y = qy * qinv, z = qz * qinv;
+  const double Q[9] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y),
+                       2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x),
+                       2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)};
+  const double s[3] = {S.scales[i], S.scales[S.ld + i], S.scales[2 * S.ld + i]};
+  const double fx = V.fx, fy = V.fy, cx = V.cx, cy = V.cy;
+  const double k3 = 1.7320508075688772;  // sqrt(3)
+  // sigma points in camera space: centre, then +-sqrt(3) s_j (R column j)
+  bool front = true;
+  double zc = 0.0, px[7], py[7];
+#pragma unroll
+  for (int p = 0; p < 7; ++p) {
+    double X[3] = {mu[0], mu[1], mu[2]};
+    if (p > 0) {
+      const int j = (p - 1) >> 1;
+      const double sg = ((p - 1) & 1) ? -k3 : k3;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) X[c] += sg * s[j] * Q[3 * c + j];
+    }
+    const double cxp = R[0] * X[0] + R[1] * X[1] + R[2] * X[2] + (double)V.t[0];
+    const double cyp = R[3] * X[0] + R[4] * X[1] + R[5] * X[2] + (double)V.t[1];
+    const double czp = R[6] * X[0] + R[7] * X[1] + R[8] * X[2] + (double)V.t[2];
+    if (p == 0) zc = czp;
+    front = front && czp > (double)B.z_near;
+    px[p] = fx * cxp / czp + cx;
+    py[p] = fy * cyp / czp + cy;
+  }
+  double mx = 0.0, my = 0.0;
+#pragma unroll
+  for (int p = 1; p < 7; ++p) {
+    mx += px[p] / 6.0;
+    my += py[p] / 6.0;
+  }
+  double cxx = 0.0, cxy = 0.0, cyy = 0.0;
+#pragma unroll
+  for (int p = 0; p < 7; ++p) {
+    const double wc = p == 0 ? 2.0 : 1.0 / 6.0;
+    const double dx = px[p] - mx, dy = py[p] - my;
+    cxx += wc * dx * dx;
+    cxy += wc * dx * dy;
+    cyy += wc * dy * dy;
+  }
+  const double det0 = cxx * cyy - cxy * cxy;
+  const double a = cxx + (double)B.lowpass, b = cxy, c = cyy + (double)B.lowpass;
+  const double det = a * c - b * b;
+  const double dinv = det > 0.0 ? 1.0 / det : 0.0;
+  const double o = det > 0.0 ? (double)S.opac[i] * sqrt(fmax(det0, 0.0) * dinv) : 0.0;
+  const double u = mx - 0.5, v = my - 0.5;
+  double ex, ey, rad;
+  if (B.opacity_extents) {
+    const double lvl = o > 0.0 ? 2.0 * log(o / (double)B.alpha_min) : -1.0;
+    ex = lvl > 0.0 ? sqrt(lvl * a) : 0.0;
+    ey = lvl > 0.0 ? sqrt(lvl * c) : 0.0;
+    rad = fmax(ex, ey);
+  } else {
+    const double mid = 0.5 * (a + c);
+    rad = ceil(3.0 * sqrt(mid + sqrt(fmax(0.0, mid * mid - det))));
+    ex = ey = rad;
+  }
+  const double tw = B.tile_w, th = B.tile_h;
+  const double txn = V.tiles_x, tyn = V.tiles_y;
+  const int x0 = (int)fmin(txn, fmax(0.0, floor((u - ex) / tw)));
+  const int y0 = (int)fmin(tyn, fmax(0.0, floor((v - ey) / th)));
+  const int x1 = (int)fmin(txn, fmax(0.0, floor((u + ex) / tw) + 1.0));
+  const int y1 = (int)fmin(tyn, fmax(0.0, floor((v + ey) / th) + 1.0));
+  const int area = (x1 - x0) * (y1 - y0);
+  const bool visible = front && det > 0.0 && o > (double)B.alpha_min && rad > 0.0 && area > 0;
+  // shader data: M = S^-1 R^T (row r = column r of R over s_r), camera
+  // position in the canonical frame
+  double M[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) M[3 * r + k] = Q[3 * k + r] / s[r];
+  const double cpx = -(R[0] * V.t[0] + R[3] * V.t[1] + R[6] * V.t[2]);
+  const double cpy = -(R[1] * V.t[0] + R[4] * V.t[1] + R[7] * V.t[2]);
+  const double cpz = -(R[2] * V.t[0] + R[5] * V.t[1] + R[8] * V.t[2]);
+  const double d0 = cpx - mu[0], d1 = cpy - mu[1], d2 = cpz - mu[2];
+  const double ro0 = M[0] * d0 + M[1] * d1 + M[2] * d2;
+  const double ro1 = M[3] * d0 + M[4] * d1 + M[5] * d2;
+  const double ro2 = M[6] * d0 + M[7] * d1 + M[8] * d2;
+  // view-dependent colour, as for 3DGS
+  const double dn = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+  float Y[16];
+  sh_basis<DEG>((float)(-d0 * dn), (float)(-d1 * dn), (float)(-d2 * dn), Y);
+  constexpr int NB = (DEG + 1) * (DEG + 1);
+  float col[3];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    float acc = 0.5f;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc += S.sh[(size_t)(3 * j + ch) * S.ld + i] * Y[j];
+    col[ch] = fmaxf(0.f, acc);
+  }
+  const size_t r = (size_t)V.rec_off + i;
+  float4* out = splat + 6 * r;
+  out[0] = make_float4((float)u, (float)v, (float)(-0.5 * c * dinv), (float)(b * dinv));
+  out[1] = make_float4((float)(-0.5 * a * dinv), (float)o, col[0], col[1]);
+  out[2] = make_float4(col[2], (float)ro0, (float)ro1, (float)ro2);
+  out[3] = make_float4((float)M[0], (float)M[1], (float)M[2], (float)M[3]);
+  out[4] = make_float4((float)M[4], (float)M[5], (float)M[6], (float)M[7]);
+  out[5] = make_float4((float)M[8], 0.f, 0.f, 0.f);
+  depth[r] = (float)zc;
+  rect[r] = visible ? make_short4((short)x0, (short)y0, (short)x1, (short)y1)
+                    : make_short4(0, 0, 0, 0);
+  tc[r] = visible ? area : 0;
+}
+
 // Launchers ------------------------------------------------------------------
 
 hipError_t launch_project(const Batch& B, int max_n, float* splat, float* depth, int16_t* rect,
@@ -467,6 +605,15 @@ hipError_t launch_project(const Batch& B, int max_n, float* splat, float* depth,
   dim3 grid((max_n + 255) / 256, B.n_views);
   float4* sp = reinterpret_cast<float4*>(splat);
   short4* rc = reinterpret_cast<short4*>(rect);
+  if (B.method == XPR_METHOD_3DGUT) {
+    switch (B.sh_degree) {
+      case 0: hipLaunchKernelGGL(k_project_gut<0>, grid, dim3(256), 0, st, B, sp, depth, rc, tc); break;
+      case 1: hipLaunchKernelGGL(k_project_gut<1>, grid, dim3(256), 0, st, B, sp, depth, rc, tc); break;
+      case 2: hipLaunchKernelGGL(k_project_gut<2>, grid, dim3(256), 0, st, B, sp, depth, rc, tc); break;
+      default: hipLaunchKernelGGL(k_project_gut<3>, grid, dim3(256), 0, st, B, sp, depth, rc, tc); break;
+    }
+    return hipGetLastError();
+  }
   switch (B.sh_degree) {
     case 0: hipLaunchKernelGGL(k_project<0>, grid, dim3(256), 0, st, B, sp, depth, rc, tc); break;
     case 1: hipLaunchKernelGGL(k_project<1>, grid, dim3(256), 0, st, B, sp, depth, rc, tc); break;

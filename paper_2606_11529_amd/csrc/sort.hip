@@ -522,7 +522,8 @@ __global__ void k_pair_records(Batch B, const short4* __restrict__ rect,
 // test of the XPR-3DGS section): a pair is kept iff the power
 // 0.5 (x - mu)^T conic (x - mu), minimised over the tile's pixel-sample box
 // [tx tw, tx tw + tw - 1] x [ty th, ty th + th - 1] (clipped to the image),
-// is at most log(o / alpha_min).
+// is at most log(o / alpha_min). For 3DGUT (tile_cull of XPR-3DGUT) the box
+// is first extended by one pixel in x and y, on the UT footprint and o'.
 //
 // Equivalently, the tile meets the ellipse E = {q(d) <= 2 log(o / alpha_min)}
 // with q(d) = a dx^2 + 2 b dx dy + c dy^2. E is convex, so in each tile row
@@ -551,7 +552,7 @@ struct RowGeom {
   int32_t x0, x1, y0, pd;  // rect columns [x0, x1), first rect row, positive definite
   int32_t wm1, hm1;        // W - 1, H - 1 of the view
   int32_t rec, tile0;      // record id, tile id of the view's tile (0, 0)
-  int32_t tiles_x, pad;
+  int32_t tiles_x, ext;     // ext: tile boxes extended by one pixel (3DGUT)
 };
 
 // Cull constants of one record (lvl = 2 log(o / alpha_min), ex the half
@@ -583,7 +584,7 @@ __device__ __forceinline__ RowGeom row_geom(const Batch& B, int r, const float4 
   G.rec = r;
   G.tile0 = B.v[v].tile_off;
   G.tiles_x = B.v[v].tiles_x;
-  G.pad = 0;
+  G.ext = B.method == XPR_METHOD_3DGUT ? 1 : 0;
   return G;
 }
 
@@ -598,15 +599,15 @@ __device__ __forceinline__ void cull_row(const RowGeom& G, int ty, int tw, int t
     return;
   }
   const double y0 = (double)ty * th;
-  const double y1 = fmin(y0 + (th - 1), (double)G.hm1);
+  const double y1 = fmin(y0 + (th - 1), (double)G.hm1) + G.ext;
   const double d0 = fmax(y0 - G.v, -G.ey), d1 = fmin(y1 - G.v, G.ey);
   const double dr = fmin(fmax(-G.pk, d0), d1), dl = fmin(fmax(G.pk, d0), d1);
   const double xr = G.u + (-G.b * dr + sqrt(fmax(G.aq - G.det * dr * dr, 0.0))) * G.inv_a;
   const double xl = G.u + (-G.b * dl - sqrt(fmax(G.aq - G.det * dl * dl, 0.0))) * G.inv_a;
-  // tile tx is kept iff tx tw <= xr and min(tx tw + tw - 1, W - 1) >= xl
-  const bool none = d0 > d1 || xl > (double)G.wm1 || xr < 0.0;
+  // tile tx is kept iff tx tw <= xr and min(tx tw + tw - 1, W - 1) + ext >= xl
+  const bool none = d0 > d1 || xl > (double)(G.wm1 + G.ext) || xr < 0.0;
   const double c_hi = floor(fmin(xr, 1e6) * inv_tw) + 1.0;
-  const double c_lo = ceil((fmax(xl, -1e6) - (tw - 1)) * inv_tw);
+  const double c_lo = ceil((fmax(xl, -1e6) - (tw - 1) - G.ext) * inv_tw);
   const int h = min(G.x1, (int)c_hi), l = max(G.x0, (int)c_lo);
   *lo = l;
   *hi = none ? l : max(l, h);
@@ -656,7 +657,8 @@ __global__ __launch_bounds__(256) void k_cull_count(Batch B, const float4* __res
   uint32_t h = 0;
   if (i < n && tc[i] > 0) {
     const short4 rc = rect[i];
-    geo[t] = row_geom(B, (int)i, splat[3 * i], splat[3 * i + 1], rc);
+    const int64_t sr = (int64_t)splat_stride4(B) * i;
+    geo[t] = row_geom(B, (int)i, splat[sr], splat[sr + 1], rc);
     h = (uint32_t)(rc.w - rc.y);
   }
   s_kc[t] = 0;
@@ -709,7 +711,8 @@ __global__ __launch_bounds__(256) void k_cull_emit(Batch B, const float4* __rest
   if (j < n_rec && (kcs[j] & kc_mask) > 0) {
     const uint32_t r = perm[j];
     const short4 rc = rect[r];
-    geo[t] = row_geom(B, (int)r, splat[3 * (int64_t)r], splat[3 * (int64_t)r + 1], rc);
+    const int64_t sr = (int64_t)splat_stride4(B) * r;
+    geo[t] = row_geom(B, (int)r, splat[sr], splat[sr + 1], rc);
     h = (uint32_t)(rc.w - rc.y);
   }
   const uint32_t inc = wave_incl_scan_dpp(h);

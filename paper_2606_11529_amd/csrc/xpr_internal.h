@@ -39,7 +39,8 @@ struct Batch {
   int32_t tile_w, tile_h;
   int32_t sh_degree, opacity_extents;
   float lowpass, alpha_min, alpha_max, t_min, z_near, fov_clip;
-  float bg[3], pad2;
+  float bg[3];
+  int32_t method;  // XPR_METHOD_3DGS or XPR_METHOD_3DGUT
 };
 // Gradient destinations of every scene (project backward).
 struct GradDev {
@@ -52,6 +53,11 @@ struct GradDev {
 // Kernel arguments stay below the 4 KiB kernarg limit.
 static_assert(sizeof(Batch) + sizeof(GradDev) * XPR_MAX_SCENES + 64 <= 4096,
               "kernel argument block too large");
+
+// Splat record stride in float4 units: 12 floats for 3DGS, 24 for 3DGUT.
+__device__ __host__ __forceinline__ int splat_stride4(const Batch& B) {
+  return B.method == XPR_METHOD_3DGUT ? 6 : 3;
+}
 
 // View owning global tile g (views are few; a scalar linear scan).
 __device__ __forceinline__ int view_of_tile(const Batch& B, int g) {

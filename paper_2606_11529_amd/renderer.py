@@ -39,6 +39,7 @@ class Config:
     tile_order: bool = False    # launch tiles longest list first (implied by persistent)
     tile_cull: bool = False     # per-(Gaussian, tile) cull of XPR-3DGS in the binning
     opacity_extents: bool = False  # rect from the alpha >= alpha_min ellipse, not 3 sigma
+    method: str = "3dgs"        # "3dgs" or "3dgut" (forward only)
 
     def to_c(self) -> L.XprConfig:
         c = L.XprConfig()
@@ -64,6 +65,10 @@ class Config:
         c.persistent = 1 if self.persistent else 0
         c.tile_cull = 1 if self.tile_cull else 0
         c.opacity_extents = 1 if self.opacity_extents else 0
+        methods = {"3dgs": L.XPR_METHOD_3DGS, "3dgut": L.XPR_METHOD_3DGUT}
+        if self.method not in methods:
+            raise ValueError(f"unknown method {self.method!r}")
+        c.method = methods[self.method]
         return c
 
 
@@ -178,7 +183,7 @@ class Views:
 
 @dataclasses.dataclass
 class Projected:
-    splat: torch.Tensor   # [R, 12] f32
+    splat: torch.Tensor   # [R, 12] f32 (3DGS) or [R, 24] (3DGUT)
     depth: torch.Tensor   # [R] f32
     rect: torch.Tensor    # [R, 4] i16
     tc: torch.Tensor      # [R] i32
@@ -212,9 +217,14 @@ class Frame:
     n_contrib: torch.Tensor  # [pixels] i32
 
 
-def empty_projected(n: int, device) -> Projected:
+def splat_floats(cfg: "Config") -> int:
+    """Floats per projected record: 12 for 3DGS, 24 for 3DGUT."""
+    return 24 if cfg.method == "3dgut" else 12
+
+
+def empty_projected(n: int, device, floats: int = 12) -> Projected:
     n1 = max(n, 1)
-    return Projected(torch.empty((n1, 12), dtype=torch.float32, device=device),
+    return Projected(torch.empty((n1, floats), dtype=torch.float32, device=device),
                      torch.empty(n1, dtype=torch.float32, device=device),
                      torch.empty((n1, 4), dtype=torch.int16, device=device),
                      torch.empty(n1, dtype=torch.int32, device=device))
@@ -222,7 +232,10 @@ def empty_projected(n: int, device) -> Projected:
 
 def xpr_project(views: Views, cfg: Config, out: Optional[Projected] = None) -> Projected:
     dev = views.scenes[0].means.device
-    out = out or empty_projected(views.records, dev)
+    nf = splat_floats(cfg)
+    if out is not None and (out.splat.shape[1] != nf or out.splat.shape[0] < views.records):
+        raise ValueError(f"out.splat must be [>= {views.records}, {nf}] for method {cfg.method}")
+    out = out or empty_projected(views.records, dev, nf)
     L.xpr_project(views.c, views.cfg_c, out.to_c(), _stream())
     return out
 

@@ -39,7 +39,7 @@ def ocfg_of(cfg: R.Config) -> oracle.OracleConfig:
                                alpha_max=f(cfg.alpha_max), t_min=f(cfg.t_min),
                                z_near=f(cfg.z_near), fov_clip=f(cfg.fov_clip),
                                bg=tuple(f(b) for b in cfg.bg), tile_cull=cfg.tile_cull,
-                               opacity_extents=cfg.opacity_extents)
+                               opacity_extents=cfg.opacity_extents, method=cfg.method)
 
 
 def run_gpu(sc, cams, cfg: R.Config, dimgs=None, want_keys=True, want_grad2d=True,
@@ -152,8 +152,10 @@ def check_binning_cull(gpu, cam, cfg, tiles_x_y):
     kept or guard, and all kept non-guard pairs must be there."""
     tx, ty = tiles_x_y
     oc = ocfg_of(cfg)
+    nrec = 21 if cfg.method == "3dgut" else 9
+    crec = gpu["splat"][:, :nrec].astype(np.float64)
     ref = oracle.bin_pairs(gpu["depth"].astype(np.float64), gpu["rect"], gpu["tc"], tx, ty,
-                           (rec9(gpu["splat"]), cam.width, cam.height, oc))
+                           (crec, cam.width, cam.height, oc))
     n = ref["I_kept"]
     if ref["n_guard"] == 0:
         assert gpu["I"] == n, (gpu["I"], n)
