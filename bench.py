@@ -209,6 +209,18 @@ def main():
                         "speedup": ms_wall / cr["ms_wall"]}
             log(f"[bench] {key}: {cr['ms_wall']:.3f} ms/step, pairs {cpairs:.0f} "
                 f"({cpairs / pairs:.3f} of {pairs:.0f})")
+    if not args.no_cull_line and cfg.method == "3dgs":
+        # the 3DGUT method (forward only) on the same frames, against the
+        # forward stages of the 3DGS frame above
+        gcfg = dataclasses.replace(cfg, method="3dgut")
+        gr = timed_forward(scene, cams, gcfg, args.steps, args.warmup)
+        fwd3 = mean["project"] + mean["bin_sort"] + mean["render_fwd"]
+        out["3dgut_forward"] = {"ms_per_step": round(gr["ms_wall"], 4),
+                                "stages_ms_mean": gr["stage_ms"],
+                                "pairs_per_frame": gr["pairs"],
+                                "3dgs_forward_stage_sum_ms": round(fwd3, 4)}
+        log(f"[bench] 3dgut forward: {gr['ms_wall']:.3f} ms/frame (3DGS forward stages "
+            f"{fwd3:.3f} ms), pairs {gr['pairs']:.0f}")
     del scene, targets
     torch.cuda.empty_cache()
     if not args.no_batch:
@@ -318,6 +330,55 @@ def timed_frames(scene, cams, cfg, targets, steps, warmup, tile, names):
     del proj, bins, frame, g2, grads, views, ws
     torch.cuda.empty_cache()
     return dict(ms_wall=ms_wall, stage_ms=stage_ms, work=work, cap=cap)
+
+
+def timed_forward(scene, cams, cfg, steps, warmup):
+    """K timed forward frames (project -> bin_sort -> render_fwd) cycling
+    over the cameras, after W untimed ones; per-stage HIP-event means."""
+    import numpy as np
+    import torch
+
+    from paper_2606_11529_amd import renderer as R
+
+    views = [R.Views([scene], [c], [0], cfg) for c in cams]
+    proj = None
+    ws = R.Workspace()
+    cap = 0
+    for v in views:
+        proj = R.xpr_project(v, cfg, out=proj)
+        cap = max(cap, R.xpr_bin_sort(v, cfg, proj, ws=ws).count)
+    cap = int(cap * 1.1) + 4096
+    bins = R.xpr_bin_sort(views[0], cfg, proj, capacity=cap, ws=ws)
+    frame = None
+    names = ["project", "bin_sort", "render_fwd"]
+    ev_all = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps + 1)]
+    pairs = []
+
+    def step(k, ev):
+        nonlocal bins, frame, proj
+        v = views[k % len(views)]
+        ev[0].record()
+        proj = R.xpr_project(v, cfg, out=proj)
+        ev[1].record()
+        bins = R.xpr_bin_sort(v, cfg, proj, capacity=cap, ws=ws, out=bins)
+        ev[2].record()
+        frame = R.xpr_render_fwd(v, cfg, proj, bins, out=frame)
+        ev[3].record()
+
+    for k in range(warmup):
+        step(k, ev_all[-1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(warmup + k, ev_all[k])
+        pairs.append(bins.count)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    st = {n: float(np.mean([ev_all[k][i].elapsed_time(ev_all[k][i + 1]) for k in range(steps)]))
+          for i, n in enumerate(names)}
+    del proj, bins, frame, views, ws
+    torch.cuda.empty_cache()
+    return dict(ms_wall=ms, stage_ms=st, pairs=float(np.mean(pairs)))
 
 
 def bench_batched(n=2_000_000, n_views=16, reps=5):

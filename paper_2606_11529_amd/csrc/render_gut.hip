@@ -8,13 +8,30 @@
 // M = S^-1 R^T from the record); its closest approach to the centre,
 // at tau_max = -(ro . rdc) / (rdc . rdc) with rdc = M rd, has squared
 // distance d^2 = |ro|^2 - (ro . rdc)^2 / (rdc . rdc), and the response is
-// exp(-d^2 / 2). For small Gaussians seen from afar |ro| is in the
-// thousands while the d^2 that matters is a few units, so d^2 is formed in
+// exp(-d^2 / 2), evaluated as ro . rdc = (M^T ro) . rd and
+// rdc . rdc = rd^T (M^T M) rd with M^T ro and M^T M formed once per staged
+// record and the six products of rd's components once per pixel (9
+// multiply-adds per entry instead of 15). For small Gaussians seen from
+// afar |ro| is in the thousands while the d^2 that matters is a few units,
+// so d^2 is formed in
 // float64 (a float32 ray direction alone would move it by ~1e-4); the
 // exponential, the gates and the blending are float32 as for 3DGS:
 // skipped unless the response exceeds 0.0113 (the listing's validity
 // threshold, d^2 < 8.97), alpha = min(alpha_max, o' response) >= alpha_min,
 // stop before blending when T (1 - alpha) < t_min.
+//
+// Per-wave record lists: a ray can only come within d^2 <= 9 of the centre
+// if it meets the ellipsoid (x - mu)^T Sigma^-1 (x - mu) <= 9, whose image
+// is bounded by the tangent planes through the camera centre. In camera
+// coordinates the ellipsoid is {x : (x - c)^T E^-1 (x - c) <= 1} with
+// E = 9 N N^T and c = -N ro for N = R_cam M^-1, and the plane X = a Z
+// touches it iff K00 - 2 a K02 + a^2 K22 = 0 for K = E - c c^T
+// = N (9 I - ro ro^T) N^T (likewise Y = b Z with K11, K12, K22), so the
+// image of the ellipsoid lies in x in fx [a1, a2] + cx (and y alike) when
+// K22 < 0 (the ellipsoid in front of the camera plane). Each staged record
+// gets the mask of the waves whose pixel rows meet that box (float64,
+// widened by 1% + 0.05 px; every wave when K22 >= 0), and each wave walks
+// only its records, in list order; the per-lane test still decides.
 #include "xpr_internal.h"
 
 namespace xpr {
@@ -26,13 +43,74 @@ constexpr float kGutHalfLog2e = 0.72134752044448170f;  // log2(e) / 2
 // 8.966, with margin for the float32 rounding of the response)
 constexpr double kGutD2Max = 9.0;
 
-struct GutStage {
-  float4 g0[kGutBatch];    // ro, o'
-  float4 g1[kGutBatch];    // M00 M01 M02 M10
-  float4 g2[kGutBatch];    // M11 M12 M20 M21
-  float4 g3[kGutBatch];    // M22, r, g, b
-  double ro2[kGutBatch];   // |ro|^2
+struct GutRec {
+  double w[3];   // M^T ro
+  double q[6];   // M^T M: 00 11 22 01 02 12
+  double ro2;    // |ro|^2
+  float o, r, g, b;
 };
+
+template <int NW>
+struct GutStage {
+  GutRec rec[kGutBatch];
+  uint8_t mask[kGutBatch];
+  uint16_t list[NW][kGutBatch];
+};
+
+// Mask of the waves (rows of RPW pixels from y0) whose pixel rays can meet
+// the record's 3-sigma ellipsoid; x0 .. x1 are the tile's pixel columns.
+__device__ __forceinline__ uint32_t gut_wave_mask(const double* m, const double* ro,
+                                                  const ViewDev& V, int x0, int x1, int y0,
+                                                  int rpw, int nw) {
+  const uint32_t all = (1u << nw) - 1u;
+  // M^-1 by the adjugate
+  const double c00 = m[4] * m[8] - m[5] * m[7], c01 = m[5] * m[6] - m[3] * m[8],
+               c02 = m[3] * m[7] - m[4] * m[6];
+  const double det = m[0] * c00 + m[1] * c01 + m[2] * c02;
+  if (!(fabs(det) > 0.0)) return all;
+  const double id = 1.0 / det;
+  const double inv[9] = {c00 * id, (m[2] * m[7] - m[1] * m[8]) * id,
+                         (m[1] * m[5] - m[2] * m[4]) * id, c01 * id,
+                         (m[0] * m[8] - m[2] * m[6]) * id, (m[2] * m[3] - m[0] * m[5]) * id,
+                         c02 * id, (m[1] * m[6] - m[0] * m[7]) * id,
+                         (m[0] * m[4] - m[1] * m[3]) * id};
+  double N[9];  // R_cam M^-1
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      N[3 * r + c] = (double)V.R[3 * r] * inv[c] + (double)V.R[3 * r + 1] * inv[3 + c] +
+                     (double)V.R[3 * r + 2] * inv[6 + c];
+  // K = N (9 I - ro ro^T) N^T: entries 00, 02, 22, 11, 12
+  double Nro[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+    Nro[r] = N[3 * r] * ro[0] + N[3 * r + 1] * ro[1] + N[3 * r + 2] * ro[2];
+  auto kk = [&](int i, int j) {
+    return 9.0 * (N[3 * i] * N[3 * j] + N[3 * i + 1] * N[3 * j + 1] + N[3 * i + 2] * N[3 * j + 2]) -
+           Nro[i] * Nro[j];
+  };
+  const double k22 = kk(2, 2);
+  if (!(k22 < 0.0)) return all;
+  const double k00 = kk(0, 0), k02 = kk(0, 2), k11 = kk(1, 1), k12 = kk(1, 2);
+  const double dx = fmax(k02 * k02 - k00 * k22, 0.0), dy = fmax(k12 * k12 - k11 * k22, 0.0);
+  // roots of K00 - 2 a K02 + a^2 K22 = 0: (K02 -/+ sqrt(dx)) / K22
+  const double ax0 = (k02 + sqrt(dx)) / k22, ax1 = (k02 - sqrt(dx)) / k22;
+  const double ay0 = (k12 + sqrt(dy)) / k22, ay1 = (k12 - sqrt(dy)) / k22;
+  // image box of the ray points x + 1/2, widened
+  const double ux0 = (double)V.fx * fmin(ax0, ax1) + (double)V.cx,
+               ux1 = (double)V.fx * fmax(ax0, ax1) + (double)V.cx;
+  const double uy0 = (double)V.fy * fmin(ay0, ay1) + (double)V.cy,
+               uy1 = (double)V.fy * fmax(ay0, ay1) + (double)V.cy;
+  const double wx = 0.01 * (ux1 - ux0) + 0.05, wy = 0.01 * (uy1 - uy0) + 0.05;
+  if (!(ux1 + wx >= (double)x0 + 0.5 && ux0 - wx <= (double)x1 + 0.5)) return 0u;
+  uint32_t msk = 0u;
+  for (int w = 0; w < nw; ++w) {
+    const double r0 = (double)(y0 + w * rpw) + 0.5, r1 = r0 + (double)(rpw - 1);
+    if (uy1 + wy >= r0 && uy0 - wy <= r1) msk |= 1u << w;
+  }
+  return msk;
+}
 
 template <int TW, int TH>
 __global__ __launch_bounds__(TW* TH) void k_render_fwd_gut(
@@ -40,7 +118,9 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd_gut(
     const int2* __restrict__ ranges, float* __restrict__ image, float* __restrict__ Tfin,
     int32_t* __restrict__ ncon, int32_t* __restrict__ tile_work, const int32_t* order) {
   constexpr int NT = TW * TH;
-  __shared__ GutStage S;
+  constexpr int NW = (NT + 63) / 64;
+  constexpr int RPW = 64 / TW;  // pixel rows per wave
+  __shared__ GutStage<NW> S;
   const int g = order ? order[blockIdx.x] : (int)blockIdx.x;
   const ViewDev& V = B.v[view_of_tile(B, g)];
   const int lt = g - V.tile_off;
@@ -50,6 +130,7 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd_gut(
   const bool inside = px < V.W && py < V.H;
   const int2 rg = ranges[g];
   const float amax = B.alpha_max, amin = B.alpha_min, tmin = B.t_min;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // pixel_info: world ray direction through the pixel centre, R^T dc
   double rd0, rd1, rd2;
   {
@@ -61,6 +142,8 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd_gut(
     rd1 = (double)V.R[1] * ex + (double)V.R[4] * ey + (double)V.R[7] * ez;
     rd2 = (double)V.R[2] * ex + (double)V.R[5] * ey + (double)V.R[8] * ez;
   }
+  const double p00 = rd0 * rd0, p11 = rd1 * rd1, p22 = rd2 * rd2;
+  const double p01 = 2.0 * rd0 * rd1, p02 = 2.0 * rd0 * rd2, p12 = 2.0 * rd1 * rd2;
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   int last = 0;
   bool done = !inside;
@@ -73,35 +156,57 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd_gut(
     for (int k = threadIdx.x; k < nb; k += NT) {
       const float4* q = splat + (size_t)stride * (size_t)vals[base + k];
       const float4 q1 = q[1], q2 = q[2], q3 = q[3], q4 = q[4], q5 = q[5];
-      S.g0[k] = make_float4(q2.y, q2.z, q2.w, q1.y);
-      S.g1[k] = q3;
-      S.g2[k] = q4;
-      S.g3[k] = make_float4(q5.x, q1.z, q1.w, q2.x);
-      S.ro2[k] = (double)q2.y * q2.y + (double)q2.z * q2.z + (double)q2.w * q2.w;
+      const double m[9] = {q3.x, q3.y, q3.z, q3.w, q4.x, q4.y, q4.z, q4.w, q5.x};
+      const double ro[3] = {q2.y, q2.z, q2.w};
+      GutRec& G = S.rec[k];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) G.w[c] = m[c] * ro[0] + m[3 + c] * ro[1] + m[6 + c] * ro[2];
+      auto mm = [&](int a, int b) { return m[a] * m[b] + m[3 + a] * m[3 + b] + m[6 + a] * m[6 + b]; };
+      G.q[0] = mm(0, 0); G.q[1] = mm(1, 1); G.q[2] = mm(2, 2);
+      G.q[3] = mm(0, 1); G.q[4] = mm(0, 2); G.q[5] = mm(1, 2);
+      G.ro2 = ro[0] * ro[0] + ro[1] * ro[1] + ro[2] * ro[2];
+      G.o = q1.y; G.r = q1.z; G.g = q1.w; G.b = q2.x;
+      S.mask[k] = (uint8_t)gut_wave_mask(m, ro, V, tx * TW, tx * TW + TW - 1, ty * TH, RPW, NW);
     }
     __syncthreads();
-    for (int i0 = 0; i0 < nb; i0 += 8) {
+    // this wave's records of the batch, in list order
+    int cnt = 0;
+    {
+      const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+      for (int i0 = 0; i0 < nb; i0 += 64) {
+        const int k = i0 + lane;
+        const bool hit = k < nb && ((S.mask[k] >> wv) & 1u);
+        const uint64_t m = __ballot(hit);
+        if (hit) S.list[wv][cnt + __popcll(m & lt_mask)] = (uint16_t)k;
+        cnt += __popcll(m);
+      }
+    }
+    __syncthreads();
+    for (int i0 = 0; i0 < cnt; i0 += 8) {
       if (__ballot(!done) == 0) break;
-      const int iend = min(i0 + 8, nb);
-      for (int k = i0; k < iend; ++k) {
-        const float4 a = S.g0[k], m1 = S.g1[k], m2 = S.g2[k], m3 = S.g3[k];
-        const double r0 = (double)m1.x * rd0 + (double)m1.y * rd1 + (double)m1.z * rd2;
-        const double r1 = (double)m1.w * rd0 + (double)m2.x * rd1 + (double)m2.y * rd2;
-        const double r2 = (double)m2.z * rd0 + (double)m2.w * rd1 + (double)m3.x * rd2;
-        const double dot = (double)a.x * r0 + (double)a.y * r1 + (double)a.z * r2;
-        const double nrm = r0 * r0 + r1 * r1 + r2 * r2;
-        const double d2 = fmax(S.ro2[k] - dot * dot / nrm, 0.0);
+      const int iend = min(i0 + 8, cnt);
+      for (int i = i0; i < iend; ++i) {
+        const int k = S.list[wv][i];
+        const GutRec& G = S.rec[k];
+        const double dot = G.w[0] * rd0 + G.w[1] * rd1 + G.w[2] * rd2;
+        const double nrm = G.q[0] * p00 + G.q[1] * p11 + G.q[2] * p22 + G.q[3] * p01 +
+                           G.q[4] * p02 + G.q[5] * p12;
+        // 1 / nrm: hardware reciprocal, then two Newton steps
+        double rn = __builtin_amdgcn_rcp(nrm);
+        rn = fma(rn, fma(-nrm, rn, 1.0), rn);
+        rn = fma(rn, fma(-nrm, rn, 1.0), rn);
+        const double d2 = fmax(G.ro2 - dot * dot * rn, 0.0);
         const bool near = !done && d2 < kGutD2Max;
         if (__ballot(near) == 0) continue;
         const float resp = __builtin_amdgcn_exp2f(-kGutHalfLog2e * (float)d2);
-        const float alpha = fminf(amax, __fmul_rn(a.w, resp));
+        const float alpha = fminf(amax, __fmul_rn(G.o, resp));
         const bool use = near && resp > kGutValid && alpha >= amin;
         const float Tn = T * (1.f - alpha);
         const bool blend = use && Tn >= tmin;
         const float w = blend ? alpha * T : 0.f;
-        C0 += m3.y * w;
-        C1 += m3.z * w;
-        C2 += m3.w * w;
+        C0 += G.r * w;
+        C1 += G.g * w;
+        C2 += G.b * w;
         T = blend ? Tn : T;
         last = blend ? base + k - rg.x + 1 : last;
         done = done || (use && !blend);
