@@ -343,11 +343,11 @@ def timed_forward(scene, cams, cfg, steps, warmup):
     views = [R.Views([scene], [c], [0], cfg) for c in cams]
     proj = None
     ws = R.Workspace()
-    cap = 0
+    counts = []
     for v in views:
         proj = R.xpr_project(v, cfg, out=proj)
-        cap = max(cap, R.xpr_bin_sort(v, cfg, proj, ws=ws).count)
-    cap = int(cap * 1.1) + 4096
+        counts.append(R.xpr_bin_sort(v, cfg, proj, ws=ws).count)
+    cap = int(max(counts) * 1.1) + 4096
     bins = R.xpr_bin_sort(views[0], cfg, proj, capacity=cap, ws=ws)
     frame = None
     names = ["project", "bin_sort", "render_fwd"]
@@ -371,7 +371,7 @@ def timed_forward(scene, cams, cfg, steps, warmup):
     t0 = time.perf_counter()
     for k in range(steps):
         step(warmup + k, ev_all[k])
-        pairs.append(bins.count)
+        pairs.append(counts[(warmup + k) % len(views)])
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     st = {n: float(np.mean([ev_all[k][i].elapsed_time(ev_all[k][i + 1]) for k in range(steps)]))

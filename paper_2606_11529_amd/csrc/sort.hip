@@ -1091,11 +1091,22 @@ static hipError_t radix_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const int
     K* kdst = (last && !keys_last && ranges) ? nullptr : k1;
     const int32_t* as = last ? aux_src : nullptr;
     uint32_t* ad = last ? aux_dst : nullptr;
-    hipError_t e = dbits == 7
-                       ? radix_pass<7, K>(k0, v0, kdst, v1, n_dev, cap, nb, shift, counts, partials,
-                                          rg, as, ad, st)
-                       : radix_pass<8, K>(k0, v0, kdst, v1, n_dev, cap, nb, shift, counts, partials,
-                                          rg, as, ad, st);
+    // each pass ranks exactly the bits it places (the last one may have
+    // fewer than dbits left: one ballot per bit saved per key)
+    const int pb = std::min(dbits, bits - shift);
+    hipError_t e;
+    switch (pb) {
+      case 8: e = radix_pass<8, K>(k0, v0, kdst, v1, n_dev, cap, nb, shift, counts, partials, rg,
+                                   as, ad, st); break;
+      case 7: e = radix_pass<7, K>(k0, v0, kdst, v1, n_dev, cap, nb, shift, counts, partials, rg,
+                                   as, ad, st); break;
+      case 6: e = radix_pass<6, K>(k0, v0, kdst, v1, n_dev, cap, nb, shift, counts, partials, rg,
+                                   as, ad, st); break;
+      case 5: e = radix_pass<5, K>(k0, v0, kdst, v1, n_dev, cap, nb, shift, counts, partials, rg,
+                                   as, ad, st); break;
+      default: e = radix_pass<4, K>(k0, v0, kdst, v1, n_dev, cap, nb, shift, counts, partials, rg,
+                                    as, ad, st); break;
+    }
     if (e != hipSuccess) return e;
     K* tk = k0; k0 = k1; k1 = tk;
     uint32_t* tv = v0; v0 = v1; v1 = tv;

@@ -200,8 +200,16 @@ class Bins:
     n_isect: torch.Tensor  # [1] i64 (device)
     keys: Optional[torch.Tensor] = None  # [cap] i64 (bits of uint64)
     capacity: int = 0
-    count: int = -1        # host copy of n_isect when known
+    count_cache: int = -1  # host copy of n_isect once read (-1: not read yet)
     tile_order: Optional[torch.Tensor] = None  # [tiles + 1] i32
+
+    @property
+    def count(self) -> int:
+        """Host copy of n_isect, read (one stream sync) the first time it is
+        asked for after a binning, so a frame that never asks does not wait."""
+        if self.count_cache < 0:
+            self.count_cache = int(self.n_isect.item())
+        return self.count_cache
 
     def to_c(self) -> L.XprBins:
         return L.XprBins(self.keys.data_ptr() if self.keys is not None else None,
@@ -291,8 +299,7 @@ def xpr_bin_sort(views: Views, cfg: Config, proj: Projected, capacity: Optional[
         st = L.xpr_bin_sort(views.c, views.cfg_c, proj.to_c(), bc, _ptr(wsb), wsb.numel(),
                             _stream())
         if st == L.XPR_OK:
-            if not cfg.no_sync:
-                out.count = int(out.n_isect.item())
+            out.count_cache = -1
             return out
         need = int(out.n_isect.item())
         cap = int(need * 1.125) + 1024
