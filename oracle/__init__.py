@@ -42,7 +42,8 @@ class OracleConfig:
     bg: tuple = (0.0, 0.0, 0.0)
     tile_cull: bool = False         # per-(Gaussian, tile) cull of XPR-3DGS
     opacity_extents: bool = False   # rect from the alpha >= alpha_min ellipse (not 3 sigma)
-    method: str = "3dgs"            # "3dgs" (EWA) or "3dgut" (unscented transform, ray evaluate)
+    method: str = "3dgs"            # "3dgs" (EWA), "3dgut" (unscented transform, ray evaluate)
+    #                                 or "linprim" (octahedra, slab chords, Beer-Lambert)
 
     def proj_cfg(self):
         return np.array([self.lowpass, self.alpha_min, self.z_near, self.fov_clip,
@@ -90,6 +91,13 @@ def lib():
         L.orc_render_fwd_gut.restype = None
         L.orc_gut_response.argtypes = [i64, P, P, P, i32, i32, P]
         L.orc_gut_response.restype = None
+        L.orc_project_lin.argtypes = [i64, P, P, P, P, P, P, i32, i32, P, i32, i32, i32,
+                                      P, P, P, P, P]
+        L.orc_project_lin.restype = None
+        L.orc_lin_chord.argtypes = [i64, P, P, P]
+        L.orc_lin_chord.restype = None
+        L.orc_render_fwd_lin.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P, P, P, P]
+        L.orc_render_fwd_lin.restype = None
         L.orc_sh_basis.argtypes = [i32, P, P, P]
         L.orc_sh_basis.restype = None
         L.orc_num_threads.restype = i32
@@ -141,6 +149,8 @@ def project(scene, cam, cfg: OracleConfig):
     then rec has 21 columns: the 9 of 3DGS, ro, M)."""
     if cfg.method == "3dgut":
         return project_gut(scene, cam, cfg)
+    if cfg.method == "linprim":
+        return project_lin(scene, cam, cfg)
     m, s, q, o, sh = _scene_arrays(scene)
     n = o.shape[0]
     K = sh.shape[0]
@@ -167,6 +177,44 @@ def project_gut(scene, cam, cfg: OracleConfig):
                           cam.height, _p(cfg.gut_cfg()), cfg.tile_w, cfg.tile_h, cfg.sh_degree,
                           _p(out["rec"]), _p(out["cov"]), _p(out["depth"]), _p(out["rect"]),
                           _p(out["tc"]), _p(out["guard"]))
+    return out
+
+
+def project_lin(scene, cam, cfg: OracleConfig):
+    """LinPrim projection (Listing XPR-LinPrim, project); rec has 17
+    columns: u, v (mu_2D - 1/2), sigma, colour, ex, ey, c0, c1, c2."""
+    m, s, q, o, sh = _scene_arrays(scene)
+    n = o.shape[0]
+    out = dict(rec=np.zeros((n, 17)), depth=np.zeros(n), rect=np.zeros((n, 4), np.int32),
+               tc=np.zeros(n, np.int32), guard=np.zeros(n, np.uint8))
+    lib().orc_project_lin(n, _p(m), _p(s), _p(q), _p(o), _p(sh), _p(cam_vec(cam)), cam.width,
+                          cam.height, _p(cfg.proj_cfg()), cfg.tile_w, cfg.tile_h, cfg.sh_degree,
+                          _p(out["rec"]), _p(out["depth"]), _p(out["rect"]), _p(out["tc"]),
+                          _p(out["guard"]))
+    return out
+
+
+def lin_chord(rec17, pxy):
+    """LinPrim slab intersection: chord length of pixel pxy[k]'s ray in
+    record rec17[k] (<= 0: no intersection)."""
+    rec17 = _f64(rec17).reshape(-1, 17)
+    pxy = np.ascontiguousarray(pxy, np.int32).reshape(-1, 2)
+    out = np.zeros(rec17.shape[0])
+    lib().orc_lin_chord(rec17.shape[0], _p(rec17), _p(pxy), _p(out))
+    return out
+
+
+def render_fwd_lin(rec, vals, ranges, W: int, H: int, cfg: OracleConfig):
+    """LinPrim compositing (Algorithm 1 with the XPR-LinPrim evaluate)."""
+    rec = _f64(rec)
+    vals = np.ascontiguousarray(vals, np.int32)
+    ranges = np.ascontiguousarray(ranges, np.int32)
+    out = dict(img=np.zeros((3, H, W)), Tfinal=np.zeros((H, W)),
+               ncontrib=np.zeros((H, W), np.int32), nblend=np.zeros((H, W), np.int32),
+               guard=np.zeros((H, W), np.uint8))
+    lib().orc_render_fwd_lin(W, H, cfg.tile_w, cfg.tile_h, _p(rec), _p(vals), _p(ranges),
+                             _p(cfg.render_cfg()), _p(out["img"]), _p(out["Tfinal"]),
+                             _p(out["ncontrib"]), _p(out["nblend"]), _p(out["guard"]))
     return out
 
 
@@ -240,6 +288,8 @@ def render_fwd(rec, vals, ranges, W: int, H: int, cfg: OracleConfig, cam=None):
     rec = _f64(rec)
     if rec.shape[1] == 21:
         return render_fwd_gut(rec, vals, ranges, cam, cfg)
+    if rec.shape[1] == 17:
+        return render_fwd_lin(rec, vals, ranges, W, H, cfg)
     vals = np.ascontiguousarray(vals, np.int32)
     ranges = np.ascontiguousarray(ranges, np.int32)
     out = dict(img=np.zeros((3, H, W)), Tfinal=np.zeros((H, W)),
@@ -303,6 +353,8 @@ def render(scene, cam, cfg: OracleConfig):
     """Whole forward pipeline in FP64: returns every intermediate."""
     pr = project(scene, cam, cfg)
     tx, ty = tiles(cam, cfg)
+    if cfg.tile_cull and cfg.method == "linprim":
+        raise NotImplementedError("the LinPrim tile cull is not built")
     cull = (pr["rec"], cam.width, cam.height, cfg) if cfg.tile_cull else None
     b = bin_pairs(pr["depth"], pr["rect"], pr["tc"], tx, ty, cull)
     f = render_fwd(pr["rec"], b["vals"], b["ranges"], cam.width, cam.height, cfg, cam)

@@ -23,6 +23,8 @@
 //   * Listing "Implementation of XPR-3DGUT" (forward only): unscented-
 //     transform projection, pixel_info (ray direction) and the ray-based
 //     evaluate at tau_max; tile_cull with the extended tile bounds.
+//   * Listing "Implementation of XPR-LinPrim" (forward): the linear map A of
+//     each octahedron, slab-pair ray intersection, Beer-Lambert opacity.
 // Readings where the paper is silent (pixel sample position, low-pass 0.3,
 // 3-sigma radius from the largest eigenvalue, conservative rect rounding,
 // alpha clamp 0.99, stop at T < 1e-4 before blending, ties by index, SH
@@ -534,6 +536,144 @@ double gut_response(const double* ro, const double* M, const double rd[3]) {
   return std::exp(-0.5 * d2);
 }
 
+// ----------------------------------------------------------------------------
+// LinPrim (Listing "Implementation of XPR-LinPrim", forward): octahedra
+// {mu + R diag(s) u : |u|_1 <= 1} with homogeneous density, projected by
+// the linear map A = J3 R_w2c R diag(s) to (x_px, y_px, tau) (tau the
+// Euclidean depth relative to the centre), evaluated by intersecting the
+// pixel ray with the four slab pairs |n_i . (dx, dy, tau)| <= 1,
+// n_i = c0 +- c1 +- c2 (c_k the rows of A^-1), opacity by Beer-Lambert.
+//
+// Readings: J3 stacks the perspective Jacobian rows (fx/z, 0, -fx x/z^2),
+// (0, fy/z, -fy y/z^2) on the unit viewing direction mu_c / |mu_c| (the
+// derivative of the Euclidean distance); the extents are the largest
+// |A_0k| and |A_1k| (the projected vertices mu_2D +- A e_k bound the
+// footprint) and compute_radius their maximum; the depth is |mu_c|; a
+// primitive is visible only if its centre is in front (z_c > z_near), A is
+// invertible and s_min > 0; a slab with |n_z| < 1e-10 does not constrain
+// tau where |n_x dx + n_y dy| <= 1 and excludes the pixel elsewhere.
+// ----------------------------------------------------------------------------
+struct LinProj {
+  double u2, v2;     // mu_2D (f x / z + c)
+  double c[9];       // rows of A^-1
+  double sigma, ex, ey, depth;
+  double colour[3];
+  int rect[4];
+  int tc;
+  bool guard;
+};
+
+bool inv3(const double* m, double* inv) {
+  const double c00 = m[4] * m[8] - m[5] * m[7], c01 = m[5] * m[6] - m[3] * m[8],
+               c02 = m[3] * m[7] - m[4] * m[6];
+  const double det = m[0] * c00 + m[1] * c01 + m[2] * c02;
+  if (!(std::fabs(det) > 0.0) || !std::isfinite(det)) return false;
+  const double id = 1.0 / det;
+  inv[0] = c00 * id; inv[1] = (m[2] * m[7] - m[1] * m[8]) * id; inv[2] = (m[1] * m[5] - m[2] * m[4]) * id;
+  inv[3] = c01 * id; inv[4] = (m[0] * m[8] - m[2] * m[6]) * id; inv[5] = (m[2] * m[3] - m[0] * m[5]) * id;
+  inv[6] = c02 * id; inv[7] = (m[1] * m[6] - m[0] * m[7]) * id; inv[8] = (m[0] * m[4] - m[1] * m[3]) * id;
+  return true;
+}
+
+void project_lin_one(int64_t i, int64_t n, const double* means, const double* scales,
+                     const double* quats, const double* opac, const double* sh, const Cam& cam,
+                     const double* cfg, int tile_w, int tile_h, int deg, LinProj& L) {
+  const double z_near = cfg[2];
+  const int tiles_x = (cam.W + tile_w - 1) / tile_w;
+  const int tiles_y = (cam.H + tile_h - 1) / tile_h;
+  std::memset(&L, 0, sizeof(L));
+  const double mu[3] = {means[i], means[n + i], means[2 * n + i]};
+  double mc[3];
+  for (int r = 0; r < 3; ++r)
+    mc[r] = cam.R[3 * r] * mu[0] + cam.R[3 * r + 1] * mu[1] + cam.R[3 * r + 2] * mu[2] + cam.t[r];
+  const double x = mc[0], y = mc[1], z = mc[2];
+  const double d = std::sqrt(x * x + y * y + z * z);
+  L.depth = d;
+  if (std::fabs(z - z_near) <= 1e-9 * std::max(1.0, z_near)) L.guard = true;
+  const double q[4] = {quats[i], quats[n + i], quats[2 * n + i], quats[3 * n + i]};
+  const double qn = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  const double qu[4] = {q[0] / qn, q[1] / qn, q[2] / qn, q[3] / qn};
+  double Rq[9];
+  quat_to_rot(qu, Rq);
+  const double s[3] = {scales[i], scales[n + i], scales[2 * n + i]};
+  const double smin = std::min(s[0], std::min(s[1], s[2]));
+  // A = J3 R_w2c Rq diag(s)
+  const double J[9] = {cam.fx / z, 0.0, -cam.fx * x / (z * z), 0.0, cam.fy / z,
+                       -cam.fy * y / (z * z), x / d, y / d, z / d};
+  double W[9], A[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      W[3 * r + c] = cam.R[3 * r] * Rq[c] + cam.R[3 * r + 1] * Rq[3 + c] + cam.R[3 * r + 2] * Rq[6 + c];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      A[3 * r + c] = (J[3 * r] * W[c] + J[3 * r + 1] * W[3 + c] + J[3 * r + 2] * W[6 + c]) * s[c];
+  const bool inv_ok = z > z_near && smin > 0.0 && inv3(A, L.c);
+  L.u2 = cam.fx * x / z + cam.cx;
+  L.v2 = cam.fy * y / z + cam.cy;
+  L.ex = std::max(std::fabs(A[0]), std::max(std::fabs(A[1]), std::fabs(A[2])));
+  L.ey = std::max(std::fabs(A[3]), std::max(std::fabs(A[4]), std::fabs(A[5])));
+  const double r = std::max(L.ex, L.ey);
+  const double o = std::min(0.999, std::max(0.0, opac[i]));
+  L.sigma = smin > 0.0 ? -std::log1p(-0.99 * o) / (2.0 * smin) : 0.0;
+  const double u = L.u2 - 0.5, v = L.v2 - 0.5;
+  const double fx0 = (u - L.ex) / tile_w, fx1 = (u + L.ex) / tile_w;
+  const double fy0 = (v - L.ey) / tile_h, fy1 = (v + L.ey) / tile_h;
+  auto clampi = [](double t, int lo, int hi) {
+    return (int)std::min<double>(hi, std::max<double>(lo, t));
+  };
+  L.rect[0] = clampi(std::floor(fx0), 0, tiles_x);
+  L.rect[1] = clampi(std::floor(fy0), 0, tiles_y);
+  L.rect[2] = clampi(std::floor(fx1) + 1, 0, tiles_x);
+  L.rect[3] = clampi(std::floor(fy1) + 1, 0, tiles_y);
+  const double g = 1e-9;
+  if (near_int(fx0, g * std::max(1.0, std::fabs(fx0))) ||
+      near_int(fx1, g * std::max(1.0, std::fabs(fx1))) ||
+      near_int(fy0, g * std::max(1.0, std::fabs(fy0))) ||
+      near_int(fy1, g * std::max(1.0, std::fabs(fy1))))
+    L.guard = true;
+  const int area = (L.rect[2] - L.rect[0]) * (L.rect[3] - L.rect[1]);
+  const bool visible = inv_ok && r > 0 && area > 0 && d > z_near;
+  L.tc = visible ? area : 0;
+  double dv[3] = {mu[0], mu[1], mu[2]};
+  const double cp[3] = {
+      -(cam.R[0] * cam.t[0] + cam.R[3] * cam.t[1] + cam.R[6] * cam.t[2]),
+      -(cam.R[1] * cam.t[0] + cam.R[4] * cam.t[1] + cam.R[7] * cam.t[2]),
+      -(cam.R[2] * cam.t[0] + cam.R[5] * cam.t[1] + cam.R[8] * cam.t[2])};
+  for (int k = 0; k < 3; ++k) dv[k] -= cp[k];
+  const double dn = std::sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+  for (int k = 0; k < 3; ++k) dv[k] /= dn;
+  double Y[16];
+  sh_basis(deg, dv, Y, nullptr);
+  const int nb = (deg + 1) * (deg + 1);
+  for (int ch = 0; ch < 3; ++ch) {
+    double acc = 0.5;
+    for (int j = 0; j < nb; ++j) acc += sh[(int64_t)(j * 3 + ch) * n + i] * Y[j];
+    L.colour[ch] = std::max(0.0, acc);
+  }
+}
+
+// Chord of the ray through pixel-centre offset (dx, dy) inside the slabs:
+// [enter, exit] = intersection over i of {tau : |n_i . (dx, dy, tau)| <= 1};
+// returns exit - enter, or a value <= 0 when empty.
+double lin_chord(const double* c, double dx, double dy) {
+  double enter = -INFINITY, exit_ = INFINITY;
+  for (int i = 0; i < 4; ++i) {
+    const double e1 = (i & 2) ? -1.0 : 1.0, e2 = (i & 1) ? -1.0 : 1.0;
+    const double nx = c[0] + e1 * c[3] + e2 * c[6];
+    const double ny = c[1] + e1 * c[4] + e2 * c[7];
+    const double nz = c[2] + e1 * c[5] + e2 * c[8];
+    const double w = nx * dx + ny * dy;
+    if (std::fabs(nz) >= 1e-10) {
+      const double m = -w / nz, h = 1.0 / std::fabs(nz);
+      enter = std::max(enter, m - h);
+      exit_ = std::min(exit_, m + h);
+    } else if (std::fabs(w) > 1.0) {
+      return -1.0;
+    }
+  }
+  return exit_ - enter;
+}
+
 }  // namespace
 
 extern "C" {
@@ -835,6 +975,88 @@ void orc_gut_response(int64_t m, const double* rec, const int32_t* pxy, const do
     double rd[3];
     gut_ray(cam, pxy[2 * k], pxy[2 * k + 1], rd);
     out[k] = gut_response(rec + 21 * k + 9, rec + 21 * k + 12, rd);
+  }
+}
+
+// LinPrim projection of n octahedra (Listing "XPR-LinPrim", project).
+//   cfg: lowpass (unused), alpha_min, z_near, unused
+// rec [n][17] = u, v (mu_2D - 1/2), sigma, r, g, b, ex, ey, c0 (3), c1 (3),
+// c2 (3); depth [n] (Euclidean); rect [n][4]; tc [n]; guard [n].
+void orc_project_lin(int64_t n, const double* means, const double* scales, const double* quats,
+                     const double* opac, const double* sh, const double* camv, int W, int H,
+                     const double* cfg, int tile_w, int tile_h, int deg, double* rec,
+                     double* depth, int32_t* rect, int32_t* tc, uint8_t* guard) {
+  const Cam cam = read_cam(camv, W, H);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    LinProj L;
+    project_lin_one(i, n, means, scales, quats, opac, sh, cam, cfg, tile_w, tile_h, deg, L);
+    if (rec) {
+      double* r = rec + 17 * i;
+      const double v8[8] = {L.u2 - 0.5, L.v2 - 0.5, L.sigma, L.colour[0], L.colour[1],
+                            L.colour[2], L.ex, L.ey};
+      for (int k = 0; k < 8; ++k) r[k] = v8[k];
+      for (int k = 0; k < 9; ++k) r[8 + k] = L.c[k];
+    }
+    if (depth) depth[i] = L.depth;
+    if (rect) for (int k = 0; k < 4; ++k) rect[4 * i + k] = L.rect[k];
+    if (tc) tc[i] = L.tc;
+    if (guard) guard[i] = L.guard ? 1 : 0;
+  }
+}
+
+// Chord lengths for m (record, pixel) pairs: rec [m][17], pxy [m][2].
+void orc_lin_chord(int64_t m, const double* rec, const int32_t* pxy, double* out) {
+  for (int64_t k = 0; k < m; ++k) {
+    const double* r = rec + 17 * k;
+    // pixel centre px + 1/2 minus mu_2D = px - u with u = mu_2D - 1/2
+    out[k] = lin_chord(r + 8, pxy[2 * k] - r[0], pxy[2 * k + 1] - r[1]);
+  }
+}
+
+// LinPrim forward compositing (Algorithm 1 with the XPR-LinPrim evaluate):
+// per listed record alpha = 1 - exp(-sigma chord) for a positive chord
+// (valid always), then alpha = min(alpha_max, alpha) >= alpha_min, the stop
+// rule and blending of the 3DGS path.
+void orc_render_fwd_lin(int W, int H, int tile_w, int tile_h, const double* rec,
+                        const int32_t* vals, const int32_t* ranges, const double* cfg,
+                        double* img, double* Tfinal, int32_t* ncontrib, int32_t* nblend,
+                        uint8_t* guard) {
+  const double alpha_min = cfg[0], alpha_max = cfg[1], t_min = cfg[2];
+  const double bg[3] = {cfg[3], cfg[4], cfg[5]};
+  const int tiles_x = (W + tile_w - 1) / tile_w;
+  const int tiles_y = (H + tile_h - 1) / tile_h;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int t = 0; t < tiles_x * tiles_y; ++t) {
+    const int tx = t % tiles_x, ty = t / tiles_x;
+    const int32_t start = ranges[2 * t], end = ranges[2 * t + 1];
+    for (int py = ty * tile_h; py < std::min(H, (ty + 1) * tile_h); ++py)
+      for (int px = tx * tile_w; px < std::min(W, (tx + 1) * tile_w); ++px) {
+        double T = 1.0, C[3] = {0, 0, 0};
+        int32_t last = 0, count = 0;
+        bool g = false;
+        for (int32_t k = start; k < end; ++k) {
+          const double* r = rec + 17 * (int64_t)vals[k];
+          const double ch = lin_chord(r + 8, px - r[0], py - r[1]);
+          if (!(ch > 0.0)) continue;
+          const double alpha = std::min(alpha_max, -std::expm1(-r[2] * ch));
+          if (std::fabs(alpha - alpha_min) <= 1e-4 * alpha_min) g = true;
+          if (alpha < alpha_min) continue;
+          const double Tn = T * (1.0 - alpha);
+          if (std::fabs(Tn - t_min) <= 1e-3 * t_min) g = true;
+          if (Tn < t_min) break;
+          for (int c = 0; c < 3; ++c) C[c] += r[3 + c] * alpha * T;
+          T = Tn;
+          last = k - start + 1;
+          ++count;
+        }
+        const int64_t p = (int64_t)py * W + px;
+        for (int c = 0; c < 3; ++c) img[(int64_t)c * W * H + p] = C[c] + T * bg[c];
+        if (Tfinal) Tfinal[p] = T;
+        if (ncontrib) ncontrib[p] = last;
+        if (nblend) nblend[p] = count;
+        if (guard) guard[p] = g ? 1 : 0;
+      }
   }
 }
 
