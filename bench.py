@@ -221,6 +221,15 @@ def main():
                                 "3dgs_forward_stage_sum_ms": round(fwd3, 4)}
         log(f"[bench] 3dgut forward: {gr['ms_wall']:.3f} ms/frame (3DGS forward stages "
             f"{fwd3:.3f} ms), pairs {gr['pairs']:.0f}")
+        # LinPrim (forward only): the same scene's parameters read as octahedra
+        # (scales as half-extents)
+        lcfg = dataclasses.replace(cfg, method="linprim")
+        lr = timed_forward(scene, cams, lcfg, args.steps, args.warmup)
+        out["linprim_forward"] = {"ms_per_step": round(lr["ms_wall"], 4),
+                                  "stages_ms_mean": lr["stage_ms"],
+                                  "pairs_per_frame": lr["pairs"],
+                                  "3dgs_forward_stage_sum_ms": round(fwd3, 4)}
+        log(f"[bench] linprim forward: {lr['ms_wall']:.3f} ms/frame, pairs {lr['pairs']:.0f}")
     del scene, targets
     torch.cuda.empty_cache()
     if not args.no_batch:

@@ -62,6 +62,8 @@ typedef enum {
 /* Methods (listings "Implementation of XPR-3DGS" and "...XPR-3DGUT"). */
 #define XPR_METHOD_3DGS 0  /* EWA projection, 2D Gaussian evaluate; forward and backward */
 #define XPR_METHOD_3DGUT 1 /* unscented-transform projection, ray evaluate; forward only */
+#define XPR_METHOD_LINPRIM 2 /* octahedra (scales = half-extents), slab chords, Beer-Lambert;
+                                forward only, no tile_cull */
 
 /* Sort strategies of xpr_bin_sort; both produce the identical list. */
 #define XPR_SORT_PRESORT 0 /* sort Gaussians by depth, then pairs by tile */
@@ -101,7 +103,7 @@ typedef struct xpr_config {
   int32_t persistent;     /* 1: persistent render grids pulling from tile_order */
   int32_t tile_cull;      /* 1: per-(Gaussian, tile) cull in xpr_bin_sort (0) */
   int32_t opacity_extents; /* 1: rect from the alpha >= alpha_min extents, not 3 sigma (0) */
-  int32_t method;         /* XPR_METHOD_3DGS (0) or XPR_METHOD_3DGUT */
+  int32_t method;         /* XPR_METHOD_3DGS (0), XPR_METHOD_3DGUT or XPR_METHOD_LINPRIM */
 } xpr_config;
 
 /* One scene of n Gaussians, structure of arrays with leading dimension ld:
@@ -149,7 +151,10 @@ typedef struct xpr_views {
  *         adjusted opacity o', (u, v) = UT mean2D - 1/2 and the conic of the
  *         UT covariance: the listing's tile cull data), then ro (3), the
  *         camera position in the Gaussian's canonical frame, M = S^-1 R^T
- *         (9, row-major) and 3 zeros (the listing's shader data)
+ *         (9, row-major) and 3 zeros (the listing's shader data);
+ *         with XPR_METHOD_LINPRIM [total][20] float: u, v (mu_2D - 1/2),
+ *         sigma, r | g, b, ex, ey | c0 (3), c1 (3), c2 (3), 3 zeros with
+ *         c_k the rows of A^-1 (the listing's shader data)
  *   depth [total] float: camera-space z
  *   rect  [total][4] int16: tile-space box x0, y0, x1, y1 (half-open)
  *   tiles_touched [total] int32: (x1-x0)(y1-y0) if visible else 0 */
@@ -192,7 +197,15 @@ xpr_status xpr_batch_sizes(const xpr_views* views, const xpr_config* cfg, xpr_si
  * weights 2 and 1/6) through the pinhole projection; invisible when a sigma
  * point has z <= z_near; cov2D + lowpass I; o' = o sqrt(det_orig / det);
  * rect as above around (u, v) = mean2D - 1/2; visibility also needs
- * o' > alpha_min; ro and M as in the record layout above. Colour
+ * o' > alpha_min; ro and M as in the record layout above.
+ * With cfg->method = XPR_METHOD_LINPRIM (listing XPR-LinPrim, project; the
+ * scene's scales are the octahedra's half-extents): A = J3 R_w2c R diag(s)
+ * with J3 the perspective Jacobian rows over mu_c / |mu_c|; c_k the rows of
+ * A^-1; ex = max_k |A_0k|, ey = max_k |A_1k|; rect around (u, v) = mu_2D -
+ * 1/2 from (ex, ey) with the rounding above; depth = |mu_c|;
+ * sigma = -log(1 - 0.99 o) / (2 s_min), o clipped to [0, 0.999]; visible
+ * when z > z_near, A is invertible, s_min > 0 and the rect is not empty.
+ * Colour
  * max(0, 0.5 + sum_lm sh_lm Y_lm(dir)) with the real SH basis (Condon-Shortley
  * phase) and dir = (mu - campos) / |mu - campos|. Writes every field of
  * *out for all records (invisible: tiles_touched = 0). */
@@ -234,7 +247,8 @@ xpr_status xpr_bin_sort_workspace(const xpr_views* views, const xpr_config* cfg,
  * lists, ranges and *n_isect then hold the kept pairs only (the listing's
  * sentinel tile for culled pairs is never materialised), the image is the
  * same up to alpha values at the 1/255 threshold, and the presort strategy
- * is used whatever cfg->sort_mode says. For XPR_METHOD_3DGUT the tile box
+ * is used whatever cfg->sort_mode says (XPR_ERR_UNSUPPORTED with
+ * XPR_METHOD_LINPRIM, whose cull is not built). For XPR_METHOD_3DGUT the tile box
  * is first extended by one pixel in x and y (tile_max += 1 of its
  * tile_cull).
  *   out     buffers as described at xpr_bins
@@ -268,7 +282,12 @@ xpr_status xpr_bin_sort(const xpr_views* views, const xpr_config* cfg, const xpr
  * canonical distance at tau_max; skipped unless the response > 0.0113; then
  * alpha = min(alpha_max, o' response) with the gates, stop rule and
  * blending above. Evaluated with d^2 in float64. cfg->lds_batch, fwd_ppt
- * and persistent do not apply (256 / 64 threads per 16x16 / 8x8 tile). */
+ * and persistent do not apply (256 / 64 threads per 16x16 / 8x8 tile).
+ * XPR_METHOD_LINPRIM (evaluate of listing XPR-LinPrim): the chord of the
+ * ray through (x + 1/2, y + 1/2) inside the slabs |n_i . (dx, dy, tau)|
+ * <= 1, n_i = c0 +- c1 +- c2, alpha = 1 - exp(-sigma chord) for a
+ * positive chord, then the gates, stop rule and blending above (chord in
+ * float64; same launch shape as 3DGUT). */
 xpr_status xpr_render_fwd(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
                           const xpr_bins* bins, float* image, float* T_final, int32_t* n_contrib,
                           int32_t* tile_work, hipStream_t stream);

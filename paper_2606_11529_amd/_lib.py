@@ -22,6 +22,7 @@ XPR_SORT_FULL = 1
 XPR_SORT_BANDS = 2
 XPR_METHOD_3DGS = 0
 XPR_METHOD_3DGUT = 1
+XPR_METHOD_LINPRIM = 2
 XPR_MAX_VIEWS = 32
 XPR_MAX_SCENES = 8
 

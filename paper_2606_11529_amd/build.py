@@ -17,7 +17,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libxpr.so")
 BUILD_DIR = os.path.join(PKG, "_build")
-SOURCES = ["api.hip", "project.hip", "sort.hip", "render.hip", "render_gut.hip", "loss.hip"]
+SOURCES = ["api.hip", "project.hip", "sort.hip", "render.hip", "render_gut.hip", "render_lin.hip",
+           "loss.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

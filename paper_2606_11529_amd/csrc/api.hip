@@ -29,6 +29,9 @@ hipError_t bin_phase2(const Batch& B, int sort_mode, bool cull, const float* spl
 hipError_t launch_render_fwd_gut(const Batch& B, const float* splat, const int32_t* vals,
                                  const int32_t* ranges, const int32_t* order, float* image,
                                  float* Tfin, int32_t* ncon, int32_t* tile_work, hipStream_t st);
+hipError_t launch_render_fwd_lin(const Batch& B, const float* splat, const int32_t* vals,
+                                 const int32_t* ranges, const int32_t* order, float* image,
+                                 float* Tfin, int32_t* ncon, int32_t* tile_work, hipStream_t st);
 hipError_t launch_render_fwd(const Batch& B, int lds_batch, int ppt, bool persistent,
                              const float* splat, const int32_t* vals, const int32_t* ranges,
                              int32_t* order, float* image, float* Tfin, int32_t* ncon,
@@ -104,8 +107,9 @@ static xpr_status check_config(const xpr_config* c) {
             "bwd_lds_batch %d not in {0,64,128,256,512}", c->bwd_lds_batch);
   XPR_CHECK(c->tile_cull == 0 || c->tile_cull == 1, "tile_cull must be 0 or 1");
   XPR_CHECK(c->opacity_extents == 0 || c->opacity_extents == 1, "opacity_extents must be 0 or 1");
-  XPR_CHECK(c->method == XPR_METHOD_3DGS || c->method == XPR_METHOD_3DGUT, "method %d unknown",
-            c->method);
+  XPR_CHECK(c->method == XPR_METHOD_3DGS || c->method == XPR_METHOD_3DGUT ||
+                c->method == XPR_METHOD_LINPRIM,
+            "method %d unknown", c->method);
   return XPR_OK;
 }
 
@@ -325,6 +329,10 @@ xpr_status xpr_bin_sort(const xpr_views* views, const xpr_config* cfg, const xpr
                 (!out->tile_order || aligned(out->tile_order, 4)),
             "misaligned output buffer");
   const bool cull = cfg->tile_cull != 0;
+  if (cull && cfg->method == XPR_METHOD_LINPRIM) {
+    set_error("tile_cull is not built for XPR_METHOD_LINPRIM");
+    return XPR_ERR_UNSUPPORTED;
+  }
   const size_t need = bin_workspace_bytes(S.records, cap, S.tiles, cfg->sort_mode, cull);
   XPR_CHECK(ws_bytes >= need && (need == 0 || ws != nullptr),
             "workspace too small: %zu < %zu bytes", ws_bytes, need);
@@ -367,6 +375,11 @@ xpr_status xpr_render_fwd(const xpr_views* views, const xpr_config* cfg, const x
                 aligned(n_contrib, 4) && (!bins->vals || aligned(bins->vals, 4)) &&
                 (!tile_work || aligned(tile_work, 4)),
             "misaligned buffer");
+  if (cfg->method == XPR_METHOD_LINPRIM) {
+    XPR_HIP(launch_render_fwd_lin(B, proj->splat, bins->vals, bins->tile_ranges, bins->tile_order,
+                                  image, T_final, n_contrib, tile_work, stream));
+    return XPR_OK;
+  }
   if (cfg->method == XPR_METHOD_3DGUT) {
     XPR_HIP(launch_render_fwd_gut(B, proj->splat, bins->vals, bins->tile_ranges, bins->tile_order,
                                   image, T_final, n_contrib, tile_work, stream));

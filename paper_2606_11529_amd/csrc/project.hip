@@ -597,6 +597,111 @@ __global__ __launch_bounds__(256) void k_project_gut(Batch B, float4* __restrict
   tc[r] = visible ? area : 0;
 }
 
+// LinPrim projection (listing "Implementation of XPR-LinPrim", project),
+// one thread per (view, Gaussian slot holding an octahedron: scales are its
+// half-extents), in FP64. A = J3 R_w2c R diag(s) maps the octahedron's
+// local frame to (x_px, y_px, tau) with tau the Euclidean depth from the
+// centre; J3 stacks the perspective Jacobian rows on the unit viewing
+// direction. The footprint lies in mu_2D +- (ex, ey) with ex = max_k |A_0k|,
+// ey = max_k |A_1k| (the projected vertices), the sort depth is |mu_c|,
+// sigma = -log(1 - 0.99 o) / (2 s_min) with o clipped to [0, 0.999], and
+// the rows c_k of A^-1 are the slab data. Visible: centre in front
+// (z > z_near), A invertible, s_min > 0, footprint on the tile grid.
+// Record layout (20 floats):
+//   (u, v, sigma, r) (g, b, ex, ey) (c00 c01 c02 c10) (c11 c12 c20 c21)
+//   (c22, 0, 0, 0)    with (u, v) = mu_2D - 1/2
+template <int DEG>
+__global__ __launch_bounds__(256) void k_project_lin(Batch B, float4* __restrict__ splat,
+                                                     float* __restrict__ depth,
+                                                     short4* __restrict__ rect,
+                                                     int32_t* __restrict__ tc) {
+  const ViewDev& V = B.v[blockIdx.y];
+  const SceneDev& S = B.s[V.scene];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= S.n) return;
+  const double mu[3] = {S.means[i], S.means[S.ld + i], S.means[2 * S.ld + i]};
+  double R[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) R[k] = V.R[k];
+  const double x = R[0] * mu[0] + R[1] * mu[1] + R[2] * mu[2] + (double)V.t[0];
+  const double y = R[3] * mu[0] + R[4] * mu[1] + R[5] * mu[2] + (double)V.t[1];
+  const double z = R[6] * mu[0] + R[7] * mu[1] + R[8] * mu[2] + (double)V.t[2];
+  const double d = sqrt(x * x + y * y + z * z);
+  const double qw = S.quats[i], qx = S.quats[S.ld + i], qy = S.quats[2 * S.ld + i],
+               qz = S.quats[3 * S.ld + i];
+  const double qinv = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  const double w = qw * qinv, a = qx * qinv, b = qy * qinv, c = qz * qinv;
+  const double Q[9] = {1.0 - 2.0 * (b * b + c * c), 2.0 * (a * b - w * c), 2.0 * (a * c + w * b),
+                       2.0 * (a * b + w * c), 1.0 - 2.0 * (a * a + c * c), 2.0 * (b * c - w * a),
+                       2.0 * (a * c - w * b), 2.0 * (b * c + w * a), 1.0 - 2.0 * (a * a + b * b)};
+  const double s[3] = {S.scales[i], S.scales[S.ld + i], S.scales[2 * S.ld + i]};
+  const double smin = fmin(s[0], fmin(s[1], s[2]));
+  const double fx = V.fx, fy = V.fy;
+  const double J[9] = {fx / z, 0.0, -fx * x / (z * z), 0.0, fy / z, -fy * y / (z * z),
+                       x / d, y / d, z / d};
+  double A[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      // (J R_w2c Rq)[r][k] s[k]
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+        acc += J[3 * r + m] * (R[3 * m] * Q[k] + R[3 * m + 1] * Q[3 + k] + R[3 * m + 2] * Q[6 + k]);
+      A[3 * r + k] = acc * s[k];
+    }
+  const double c00 = A[4] * A[8] - A[5] * A[7], c01 = A[5] * A[6] - A[3] * A[8],
+               c02 = A[3] * A[7] - A[4] * A[6];
+  const double det = A[0] * c00 + A[1] * c01 + A[2] * c02;
+  const bool inv_ok = z > (double)B.z_near && smin > 0.0 && fabs(det) > 0.0 && isfinite(det);
+  const double id = inv_ok ? 1.0 / det : 0.0;
+  const double C[9] = {c00 * id, (A[2] * A[7] - A[1] * A[8]) * id, (A[1] * A[5] - A[2] * A[4]) * id,
+                       c01 * id, (A[0] * A[8] - A[2] * A[6]) * id, (A[2] * A[3] - A[0] * A[5]) * id,
+                       c02 * id, (A[1] * A[6] - A[0] * A[7]) * id, (A[0] * A[4] - A[1] * A[3]) * id};
+  const double ex = fmax(fabs(A[0]), fmax(fabs(A[1]), fabs(A[2])));
+  const double ey = fmax(fabs(A[3]), fmax(fabs(A[4]), fabs(A[5])));
+  const double o = fmin(0.999, fmax(0.0, (double)S.opac[i]));
+  const double sigma = smin > 0.0 ? -log1p(-0.99 * o) / (2.0 * smin) : 0.0;
+  const double u = fx * x / z + (double)V.cx - 0.5, v = fy * y / z + (double)V.cy - 0.5;
+  const double tw = B.tile_w, th = B.tile_h;
+  const double txn = V.tiles_x, tyn = V.tiles_y;
+  const int x0 = (int)fmin(txn, fmax(0.0, floor((u - ex) / tw)));
+  const int y0 = (int)fmin(tyn, fmax(0.0, floor((v - ey) / th)));
+  const int x1 = (int)fmin(txn, fmax(0.0, floor((u + ex) / tw) + 1.0));
+  const int y1 = (int)fmin(tyn, fmax(0.0, floor((v + ey) / th) + 1.0));
+  const int area = (x1 - x0) * (y1 - y0);
+  const bool visible = inv_ok && fmax(ex, ey) > 0.0 && area > 0 && d > (double)B.z_near;
+  // view-dependent colour, as for 3DGS
+  const double cpx = -(R[0] * V.t[0] + R[3] * V.t[1] + R[6] * V.t[2]);
+  const double cpy = -(R[1] * V.t[0] + R[4] * V.t[1] + R[7] * V.t[2]);
+  const double cpz = -(R[2] * V.t[0] + R[5] * V.t[1] + R[8] * V.t[2]);
+  const double dx = mu[0] - cpx, dy = mu[1] - cpy, dz = mu[2] - cpz;
+  const double dn = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+  float Y[16];
+  sh_basis<DEG>((float)(dx * dn), (float)(dy * dn), (float)(dz * dn), Y);
+  constexpr int NB = (DEG + 1) * (DEG + 1);
+  float col[3];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    float acc = 0.5f;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc += S.sh[(size_t)(3 * j + ch) * S.ld + i] * Y[j];
+    col[ch] = fmaxf(0.f, acc);
+  }
+  const size_t r = (size_t)V.rec_off + i;
+  float4* out = splat + 5 * r;
+  out[0] = make_float4((float)u, (float)v, (float)sigma, col[0]);
+  out[1] = make_float4(col[1], col[2], (float)ex, (float)ey);
+  out[2] = make_float4((float)C[0], (float)C[1], (float)C[2], (float)C[3]);
+  out[3] = make_float4((float)C[4], (float)C[5], (float)C[6], (float)C[7]);
+  out[4] = make_float4((float)C[8], 0.f, 0.f, 0.f);
+  depth[r] = (float)d;
+  rect[r] = visible ? make_short4((short)x0, (short)y0, (short)x1, (short)y1)
+                    : make_short4(0, 0, 0, 0);
+  tc[r] = visible ? area : 0;
+}
+
 // Launchers ------------------------------------------------------------------
 
 hipError_t launch_project(const Batch& B, int max_n, float* splat, float* depth, int16_t* rect,
@@ -605,6 +710,15 @@ hipError_t launch_project(const Batch& B, int max_n, float* splat, float* depth,
   dim3 grid((max_n + 255) / 256, B.n_views);
   float4* sp = reinterpret_cast<float4*>(splat);
   short4* rc = reinterpret_cast<short4*>(rect);
+  if (B.method == XPR_METHOD_LINPRIM) {
+    switch (B.sh_degree) {
+      case 0: hipLaunchKernelGGL(k_project_lin<0>, grid, dim3(256), 0, st, B, sp, depth, rc, tc); break;
+      case 1: hipLaunchKernelGGL(k_project_lin<1>, grid, dim3(256), 0, st, B, sp, depth, rc, tc); break;
+      case 2: hipLaunchKernelGGL(k_project_lin<2>, grid, dim3(256), 0, st, B, sp, depth, rc, tc); break;
+      default: hipLaunchKernelGGL(k_project_lin<3>, grid, dim3(256), 0, st, B, sp, depth, rc, tc); break;
+    }
+    return hipGetLastError();
+  }
   if (B.method == XPR_METHOD_3DGUT) {
     switch (B.sh_degree) {
       case 0: hipLaunchKernelGGL(k_project_gut<0>, grid, dim3(256), 0, st, B, sp, depth, rc, tc); break;

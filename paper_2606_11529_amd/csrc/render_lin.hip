@@ -1,0 +1,183 @@
+// Forward compositing of LinPrim: Algorithm 1 of the paper with the
+// evaluate of the listing "Implementation of XPR-LinPrim".
+//
+// One workgroup per tile, one thread per pixel (256 threads for 16x16
+// tiles, 64 for 8x8). For pixel (x, y) the offset from the record's
+// projected centre is (dx, dy) = (x + 1/2 - mu_2D) = (x - u, y - v). The
+// octahedron is the intersection of the slabs |n_i . (dx, dy, tau)| <= 1,
+// n_i = c0 +- c1 +- c2 (c_k the rows of A^-1): slab i holds
+// tau in [m_i - h_i, m_i + h_i] with m_i = -(n_ix dx + n_iy dy) / n_iz and
+// h_i = 1 / |n_iz|, so the ray's chord is min_i (m_i + h_i) -
+// max_i (m_i - h_i) when positive; a slab with |n_iz| < 1e-10 does not
+// bound tau and excludes the pixel when |n_ix dx + n_iy dy| > 1. The slope
+// coefficients -n_ix / n_iz, -n_iy / n_iz and h_i are formed in float64
+// once per staged record, the chord per pixel in float64 (anisotropic
+// octahedra make the float32 chord lose ~1e-5 of alpha), Beer-Lambert
+// alpha = 1 - exp(-sigma chord) and the gates, stop rule and blending of the
+// 3DGS path in float32.
+//
+// Per-wave lists: the footprint lies in |dx| <= ex, |dy| <= ey (the
+// projected vertices of the octahedron), so each staged record gets the
+// mask of the waves whose pixel rows meet that box (widened by 0.05 px) and
+// each wave walks only its records, in list order.
+#include "xpr_internal.h"
+
+namespace xpr {
+
+constexpr int kLinBatch = 128;
+constexpr float kLog2eLin = 1.4426950408889634f;
+
+struct LinRec {
+  double a[4], b[4], h[4];  // m_i = a_i dx + b_i dy; h_i < 0 marks a slab with n_z ~ 0
+  double u, v;
+  float sigma, r, g, bl;
+};
+
+template <int NW>
+struct LinStage {
+  LinRec rec[kLinBatch];
+  uint8_t mask[kLinBatch];
+  uint16_t list[NW][kLinBatch];
+};
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW* TH) void k_render_fwd_lin(
+    Batch B, const float4* __restrict__ splat, const int32_t* __restrict__ vals,
+    const int2* __restrict__ ranges, float* __restrict__ image, float* __restrict__ Tfin,
+    int32_t* __restrict__ ncon, int32_t* __restrict__ tile_work, const int32_t* order) {
+  constexpr int NT = TW * TH;
+  constexpr int NW = (NT + 63) / 64;
+  constexpr int RPW = 64 / TW;  // pixel rows per wave
+  __shared__ LinStage<NW> S;
+  const int g = order ? order[blockIdx.x] : (int)blockIdx.x;
+  const ViewDev& V = B.v[view_of_tile(B, g)];
+  const int lt = g - V.tile_off;
+  const int ty = lt / V.tiles_x, tx = lt - ty * V.tiles_x;
+  const int px = tx * TW + (int)(threadIdx.x % TW);
+  const int py = ty * TH + (int)(threadIdx.x / TW);
+  const bool inside = px < V.W && py < V.H;
+  const int2 rg = ranges[g];
+  const float amax = B.alpha_max, amin = B.alpha_min, tmin = B.t_min;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const double fpx = (double)px, fpy = (double)py;
+  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+  int last = 0;
+  bool done = !inside;
+  int walked = 0;
+  const int stride = splat_stride4(B);
+  const int x0 = tx * TW, x1 = tx * TW + TW - 1, y0 = ty * TH;
+  for (int base = rg.x; base < rg.y; base += kLinBatch) {
+    if (__syncthreads_count(!done) == 0) break;
+    const int nb = min(kLinBatch, rg.y - base);
+    walked = nb + (base - rg.x);
+    for (int k = threadIdx.x; k < nb; k += NT) {
+      const float4* q = splat + (size_t)stride * (size_t)vals[base + k];
+      const float4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3], q4 = q[4];
+      const double c[9] = {q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w, q4.x};
+      LinRec& L = S.rec[k];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double e1 = (i & 2) ? -1.0 : 1.0, e2 = (i & 1) ? -1.0 : 1.0;
+        const double nx = c[0] + e1 * c[3] + e2 * c[6];
+        const double ny = c[1] + e1 * c[4] + e2 * c[7];
+        const double nz = c[2] + e1 * c[5] + e2 * c[8];
+        const bool flat = !(fabs(nz) >= 1e-10);
+        L.a[i] = flat ? nx : -nx / nz;
+        L.b[i] = flat ? ny : -ny / nz;
+        L.h[i] = flat ? -1.0 : 1.0 / fabs(nz);
+      }
+      L.u = q0.x;
+      L.v = q0.y;
+      L.sigma = q0.z;
+      L.r = q0.w;
+      L.g = q1.x;
+      L.bl = q1.y;
+      // waves whose pixel rows meet the footprint box
+      const double ex = (double)q1.z + 0.05, ey = (double)q1.w + 0.05;
+      uint32_t msk = 0u;
+      if (L.u + ex >= (double)x0 && L.u - ex <= (double)x1) {
+        for (int w = 0; w < NW; ++w) {
+          const double r0 = (double)(y0 + w * RPW), r1 = r0 + (double)(RPW - 1);
+          if (L.v + ey >= r0 && L.v - ey <= r1) msk |= 1u << w;
+        }
+      }
+      S.mask[k] = (uint8_t)msk;
+    }
+    __syncthreads();
+    int cnt = 0;
+    {
+      const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+      for (int i0 = 0; i0 < nb; i0 += 64) {
+        const int k = i0 + lane;
+        const bool hit = k < nb && ((S.mask[k] >> wv) & 1u);
+        const uint64_t m = __ballot(hit);
+        if (hit) S.list[wv][cnt + __popcll(m & lt_mask)] = (uint16_t)k;
+        cnt += __popcll(m);
+      }
+    }
+    __syncthreads();
+    for (int i0 = 0; i0 < cnt; i0 += 8) {
+      if (__ballot(!done) == 0) break;
+      const int iend = min(i0 + 8, cnt);
+      for (int i = i0; i < iend; ++i) {
+        const int k = S.list[wv][i];
+        const LinRec& L = S.rec[k];
+        const double dx = fpx - L.u, dy = fpy - L.v;
+        double enter = -INFINITY, exit_ = INFINITY;
+        bool miss = false;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const double m = L.a[j] * dx + L.b[j] * dy, h = L.h[j];
+          const bool flat = h < 0.0;
+          enter = flat ? enter : fmax(enter, m - h);
+          exit_ = flat ? exit_ : fmin(exit_, m + h);
+          miss = miss || (flat && fabs(m) > 1.0);
+        }
+        const double chord = miss ? -1.0 : exit_ - enter;
+        const bool hitp = !done && chord > 0.0;
+        if (__ballot(hitp) == 0) continue;
+        const float alpha =
+            fminf(amax, 1.f - __builtin_amdgcn_exp2f(-L.sigma * kLog2eLin * (float)chord));
+        const bool use = hitp && alpha >= amin;
+        const float Tn = T * (1.f - alpha);
+        const bool blend = use && Tn >= tmin;
+        const float w = blend ? alpha * T : 0.f;
+        C0 += L.r * w;
+        C1 += L.g * w;
+        C2 += L.bl * w;
+        T = blend ? Tn : T;
+        last = blend ? base + k - rg.x + 1 : last;
+        done = done || (use && !blend);
+      }
+    }
+  }
+  if (inside) {
+    const size_t WH = (size_t)V.W * V.H;
+    const size_t p = (size_t)py * V.W + px;
+    float* img = image + 3 * (size_t)V.pix_off;
+    img[p] = C0 + T * B.bg[0];
+    img[WH + p] = C1 + T * B.bg[1];
+    img[2 * WH + p] = C2 + T * B.bg[2];
+    Tfin[(size_t)V.pix_off + p] = T;
+    ncon[(size_t)V.pix_off + p] = last;
+  }
+  if (tile_work && threadIdx.x == 0) tile_work[g] = walked;
+}
+
+hipError_t launch_render_fwd_lin(const Batch& B, const float* splat, const int32_t* vals,
+                                 const int32_t* ranges, const int32_t* order, float* image,
+                                 float* Tfin, int32_t* ncon, int32_t* tile_work, hipStream_t st) {
+  if (B.total_tiles <= 0) return hipSuccess;
+  const float4* sp = reinterpret_cast<const float4*>(splat);
+  const int2* rg = reinterpret_cast<const int2*>(ranges);
+  const dim3 grid(B.total_tiles);
+  if (B.tile_w == 8)
+    hipLaunchKernelGGL((k_render_fwd_lin<8, 8>), grid, dim3(64), 0, st, B, sp, vals, rg, image,
+                       Tfin, ncon, tile_work, order);
+  else
+    hipLaunchKernelGGL((k_render_fwd_lin<16, 16>), grid, dim3(256), 0, st, B, sp, vals, rg,
+                       image, Tfin, ncon, tile_work, order);
+  return hipGetLastError();
+}
+
+}  // namespace xpr

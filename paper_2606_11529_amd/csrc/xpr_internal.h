@@ -40,7 +40,7 @@ struct Batch {
   int32_t sh_degree, opacity_extents;
   float lowpass, alpha_min, alpha_max, t_min, z_near, fov_clip;
   float bg[3];
-  int32_t method;  // XPR_METHOD_3DGS or XPR_METHOD_3DGUT
+  int32_t method;  // XPR_METHOD_3DGS, XPR_METHOD_3DGUT or XPR_METHOD_LINPRIM
 };
 // Gradient destinations of every scene (project backward).
 struct GradDev {
@@ -54,9 +54,10 @@ struct GradDev {
 static_assert(sizeof(Batch) + sizeof(GradDev) * XPR_MAX_SCENES + 64 <= 4096,
               "kernel argument block too large");
 
-// Splat record stride in float4 units: 12 floats for 3DGS, 24 for 3DGUT.
+// Splat record stride in float4 units: 12 floats for 3DGS, 24 for 3DGUT,
+// 20 for LinPrim.
 __device__ __host__ __forceinline__ int splat_stride4(const Batch& B) {
-  return B.method == XPR_METHOD_3DGUT ? 6 : 3;
+  return B.method == XPR_METHOD_3DGUT ? 6 : (B.method == XPR_METHOD_LINPRIM ? 5 : 3);
 }
 
 // View owning global tile g (views are few; a scalar linear scan).

@@ -39,7 +39,7 @@ class Config:
     tile_order: bool = False    # launch tiles longest list first (implied by persistent)
     tile_cull: bool = False     # per-(Gaussian, tile) cull of XPR-3DGS in the binning
     opacity_extents: bool = False  # rect from the alpha >= alpha_min ellipse, not 3 sigma
-    method: str = "3dgs"        # "3dgs" or "3dgut" (forward only)
+    method: str = "3dgs"        # "3dgs", "3dgut" or "linprim" (the last two forward only)
 
     def to_c(self) -> L.XprConfig:
         c = L.XprConfig()
@@ -65,7 +65,8 @@ class Config:
         c.persistent = 1 if self.persistent else 0
         c.tile_cull = 1 if self.tile_cull else 0
         c.opacity_extents = 1 if self.opacity_extents else 0
-        methods = {"3dgs": L.XPR_METHOD_3DGS, "3dgut": L.XPR_METHOD_3DGUT}
+        methods = {"3dgs": L.XPR_METHOD_3DGS, "3dgut": L.XPR_METHOD_3DGUT,
+                   "linprim": L.XPR_METHOD_LINPRIM}
         if self.method not in methods:
             raise ValueError(f"unknown method {self.method!r}")
         c.method = methods[self.method]
@@ -183,7 +184,7 @@ class Views:
 
 @dataclasses.dataclass
 class Projected:
-    splat: torch.Tensor   # [R, 12] f32 (3DGS) or [R, 24] (3DGUT)
+    splat: torch.Tensor   # [R, 12] f32 (3DGS), [R, 24] (3DGUT) or [R, 20] (LinPrim)
     depth: torch.Tensor   # [R] f32
     rect: torch.Tensor    # [R, 4] i16
     tc: torch.Tensor      # [R] i32
@@ -226,8 +227,8 @@ class Frame:
 
 
 def splat_floats(cfg: "Config") -> int:
-    """Floats per projected record: 12 for 3DGS, 24 for 3DGUT."""
-    return 24 if cfg.method == "3dgut" else 12
+    """Floats per projected record: 12 for 3DGS, 24 for 3DGUT, 20 for LinPrim."""
+    return {"3dgut": 24, "linprim": 20}.get(cfg.method, 12)
 
 
 def empty_projected(n: int, device, floats: int = 12) -> Projected:

@@ -1,0 +1,122 @@
+"""Parity of the LinPrim forward path (listing "Implementation of
+XPR-LinPrim") on the HIP path with the FP64 oracle, through the C-ABI: the
+projection (floats within rounding bounds, rects and tile counts bit-exact
+outside the guard band), binning bit-exact on the Euclidean depth,
+compositing within 1e-5 max-abs with n_contrib exact, and the entry points
+refusing what is not built (the LinPrim cull, the backward)."""
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import cam32, check_binning, log, ocfg_of, run_gpu, TOL_PIXEL
+from paper_2606_11529_amd import _lib as L
+from paper_2606_11529_amd import renderer as R
+from synth import camera_config1, camera_look_at, random_cameras, scene_clusters, scene_config1
+
+pytestmark = pytest.mark.gpu
+
+ULP = 2.0 ** -23
+
+
+def _case(name):
+    if name == "c1_10k_256":
+        return scene_config1(10_000, 0), camera_config1(256, 256), R.Config(sh_degree=0)
+    if name == "ragged_t8":
+        sc = scene_clusters(3000, seed=5, n_clusters=6, box=1.2, lo=0.005, hi=0.4)
+        return sc, camera_look_at((0.7, -0.4, -3.2), 77, 45), R.Config(tile=8, sh_degree=3)
+    if name == "ragged_t16":
+        sc = scene_clusters(3000, seed=6, n_clusters=6, box=1.2, lo=0.005, hi=0.4, sh_degree=1)
+        return sc, camera_look_at((-0.3, 0.5, -3.9), 101, 67), R.Config(sh_degree=1)
+    if name == "c2_1M_1297x840":
+        sc = scene_clusters(1_000_000, seed=0)
+        return sc, random_cameras(1, 0, (1297, 840))[0], R.Config(sh_degree=3)
+    raise KeyError(name)
+
+
+CASES = ["c1_10k_256", "ragged_t8", "ragged_t16", "c2_1M_1297x840"]
+
+
+@functools.lru_cache(maxsize=1)
+def _run(name):
+    sc, cam, cfg = _case(name)
+    cfg.method = "linprim"
+    log(f"[gpu linprim] case={name} n={sc.n} {cam.width}x{cam.height} tile={cfg.tile}")
+    return sc, cam, cfg, run_gpu(sc, cam, cfg)
+
+
+def _check_projection(sc, cam, cfg, g, idx):
+    ref = oracle.project(sc.subset(idx), cam32(cam), ocfg_of(cfg))
+    got = g["splat"][idx, :17].astype(np.float64)
+    ok = ~ref["guard"].astype(bool)
+    assert np.array_equal(g["tc"][idx][ok], ref["tc"][ok]), "tc mismatch"
+    vr = ok & (ref["tc"] > 0)
+    assert np.array_equal(g["rect"][idx][vr], ref["rect"][vr]), "rect mismatch"
+    m = (ref["tc"] > 0) & (g["tc"][idx] > 0)
+    rr, gg = ref["rec"][m], got[m]
+    for cols, name, k in (((0, 1), "mean2D", 1), ((2,), "sigma", 4), ((6, 7), "extents", 2)):
+        c = list(cols)
+        scale = np.maximum(1.0, np.abs(rr[:, c]))
+        err = (np.abs(gg[:, c] - rr[:, c]) / scale).max(initial=0)
+        assert err <= k * ULP, f"{name} error {err}"
+    assert np.abs(gg[:, 3:6] - rr[:, 3:6]).max(initial=0) <= 1e-6, "colour"
+    c = rr[:, 8:17].reshape(-1, 3, 3)
+    rowmax = np.abs(c).max(axis=2, keepdims=True)
+    lim = 2 * ULP * np.abs(c) + 1e-10 * rowmax
+    worst = (np.abs(gg[:, 8:17].reshape(-1, 3, 3) - c) / lim).max(initial=0)
+    assert worst <= 1.0, f"slab rows error {worst} x bound"
+    d_err = np.abs(g["depth"][idx][m] - ref["depth"][m]) / np.maximum(1.0, ref["depth"][m])
+    assert d_err.max(initial=0) <= ULP
+    return int((~ok).sum())
+
+
+def _check_forward(g, cam, cfg):
+    oc = ocfg_of(cfg)
+    rec = g["splat"][:, :17].astype(np.float64)
+    ref = oracle.render_fwd_lin(rec, g["vals"], g["ranges"], cam.width, cam.height, oc)
+    sel = ~ref["guard"].astype(bool)
+    emax = float(np.abs(g["image"][0] - ref["img"])[:, sel].max(initial=0))
+    assert emax <= TOL_PIXEL, f"pixel max-abs {emax}"
+    assert np.array_equal(g["ncontrib"][0][sel], ref["ncontrib"][sel]), "n_contrib differs"
+    terr = np.abs(g["Tfinal"][0][sel] - ref["Tfinal"][sel]).max(initial=0)
+    assert terr <= TOL_PIXEL, f"T_final {terr}"
+    if (~sel).any():
+        assert np.abs(g["image"][0] - ref["img"])[:, ~sel].max() <= 1e-2
+    return emax, int((~sel).sum())
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_linprim_projection_binning_forward(name):
+    sc, cam, cfg, g = _run(name)
+    idx = np.arange(sc.n)
+    if sc.n > 200_000:
+        idx = np.sort(np.random.default_rng(2).choice(sc.n, 200_000, replace=False))
+    ng = _check_projection(sc, cam, cfg, g, idx)
+    tx, ty = oracle.tiles(cam, ocfg_of(cfg))
+    check_binning(g, (tx, ty))
+    emax, gp = _check_forward(g, cam, cfg)
+    log(f"[L1] {name}: {idx.size} projected ({ng} guard), I={g['I']} bit-exact, "
+        f"max-abs {emax:.2e}, guard pixels {gp}, lit {(g['ncontrib'][0] > 0).mean():.3f}")
+
+
+def test_linprim_refuses_cull_and_backward():
+    sc = scene_clusters(500, seed=4, n_clusters=2, box=1.0, lo=0.01, hi=0.2)
+    cam = camera_look_at((0.1, 0.2, -4.0), 48, 32)
+    cfg = R.Config(method="linprim")
+    scene = R.Scene.from_host(sc)
+    views = R.Views([scene], [cam], [0], cfg)
+    proj = R.xpr_project(views, cfg)
+    assert proj.splat.shape[1] == 20
+    bins = R.xpr_bin_sort(views, cfg, proj)
+    frame = R.xpr_render_fwd(views, cfg, proj, bins)
+    dimg = torch.zeros(3 * views.pixels, dtype=torch.float32, device="cuda")
+    with pytest.raises(L.XprError) as e:
+        R.xpr_render_bwd(views, cfg, proj, bins, frame, dimg)
+    assert e.value.status == L.XPR_ERR_UNSUPPORTED
+    ccfg = R.Config(method="linprim", tile_cull=True)
+    cviews = R.Views([scene], [cam], [0], ccfg)
+    with pytest.raises(L.XprError) as e:
+        R.xpr_bin_sort(cviews, ccfg, proj)
+    assert e.value.status == L.XPR_ERR_UNSUPPORTED
