@@ -31,6 +31,7 @@ struct LinRec {
   double a[4], b[4], h[4];  // m_i = a_i dx + b_i dy; h_i < 0 marks a slab with n_z ~ 0
   double u, v;
   float sigma, r, g, bl;
+  int32_t flat, pad;  // flat: some slab has n_z ~ 0 (the general chord below)
 };
 
 template <int NW>
@@ -75,6 +76,7 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd_lin(
       const float4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3], q4 = q[4];
       const double c[9] = {q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w, q4.x};
       LinRec& L = S.rec[k];
+      int flat_any = 0;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const double e1 = (i & 2) ? -1.0 : 1.0, e2 = (i & 1) ? -1.0 : 1.0;
@@ -85,7 +87,9 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd_lin(
         L.a[i] = flat ? nx : -nx / nz;
         L.b[i] = flat ? ny : -ny / nz;
         L.h[i] = flat ? -1.0 : 1.0 / fabs(nz);
+        flat_any |= flat ? 1 : 0;
       }
+      L.flat = flat_any;
       L.u = q0.x;
       L.v = q0.y;
       L.sigma = q0.z;
@@ -123,17 +127,30 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd_lin(
         const int k = S.list[wv][i];
         const LinRec& L = S.rec[k];
         const double dx = fpx - L.u, dy = fpy - L.v;
-        double enter = -INFINITY, exit_ = INFINITY;
-        bool miss = false;
+        double chord;
+        if (!L.flat) {  // one record per wave step: a uniform branch
+          double m = L.a[0] * dx + L.b[0] * dy;
+          double enter = m - L.h[0], exit_ = m + L.h[0];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const double m = L.a[j] * dx + L.b[j] * dy, h = L.h[j];
-          const bool flat = h < 0.0;
-          enter = flat ? enter : fmax(enter, m - h);
-          exit_ = flat ? exit_ : fmin(exit_, m + h);
-          miss = miss || (flat && fabs(m) > 1.0);
+          for (int j = 1; j < 4; ++j) {
+            m = L.a[j] * dx + L.b[j] * dy;
+            enter = fmax(enter, m - L.h[j]);
+            exit_ = fmin(exit_, m + L.h[j]);
+          }
+          chord = exit_ - enter;
+        } else {
+          double enter = -INFINITY, exit_ = INFINITY;
+          bool miss = false;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const double m = L.a[j] * dx + L.b[j] * dy, h = L.h[j];
+            const bool fl = h < 0.0;
+            enter = fl ? enter : fmax(enter, m - h);
+            exit_ = fl ? exit_ : fmin(exit_, m + h);
+            miss = miss || (fl && fabs(m) > 1.0);
+          }
+          chord = miss ? -1.0 : exit_ - enter;
         }
-        const double chord = miss ? -1.0 : exit_ - enter;
         const bool hitp = !done && chord > 0.0;
         if (__ballot(hitp) == 0) continue;
         const float alpha =
