@@ -74,8 +74,8 @@ def lib():
         L.orc_bin.argtypes = [i64, P, P, P, i32, i32, i64, P, P, P, P, P, i32, i32, i32, i32,
                               i32, i32, ctypes.c_double, P, P, P]
         L.orc_bin.restype = i64
-        L.orc_tile_cull.argtypes = [i64, P, P, i32, i32, i32, i32, ctypes.c_double, i32, P, P, P,
-                                    P]
+        L.orc_tile_cull.argtypes = [i64, P, i32, P, i32, i32, i32, i32, ctypes.c_double, i32, P,
+                                    P, P, P]
         L.orc_tile_cull.restype = None
         L.orc_render_fwd.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P, P, P, P]
         L.orc_render_fwd.restype = None
@@ -232,8 +232,9 @@ def gut_response(rec21, pxy, cam):
 def bin_pairs(depth, rect, tc, tiles_x: int, tiles_y: int, cull=None):
     """Binning (section Rasterizer): offsets, I, keys, vals, ranges.
 
-    ``cull`` = (rec [n][9], W, H, cfg) applies tile_cull (Listing XPR-3DGS)
-    to every replicated pair: culled pairs get the sentinel tile id
+    ``cull`` = (rec, W, H, cfg) applies tile_cull to every replicated pair
+    (Listing XPR-3DGS with rec [n][9], XPR-3DGUT with [n][21], XPR-LinPrim
+    with [n][17]): culled pairs get the sentinel tile id
     tiles_x*tiles_y and sort last, so the first ``I_kept`` entries of vals
     and keys are the kept lists; ``pair_guard`` flags the pairs whose cull
     decision is in the guard band, in sorted order."""
@@ -253,7 +254,7 @@ def bin_pairs(depth, rect, tc, tiles_x: int, tiles_y: int, cull=None):
     if cull is not None:
         rec, W, H, cfg = cull
         crec = _f64(rec)
-        assert crec.shape[0] == n and crec.shape[1] in (9, 21)
+        assert crec.shape[0] == n and crec.shape[1] in (9, 17, 21)
         stride = crec.shape[1]
         ext = 1 if cfg.method == "3dgut" else 0
         tw, th, amin = cfg.tile_w, cfg.tile_h, cfg.alpha_min
@@ -266,9 +267,15 @@ def bin_pairs(depth, rect, tc, tiles_x: int, tiles_y: int, cull=None):
 
 
 def tile_cull(rec, txy, W: int, H: int, cfg: OracleConfig):
-    """tile_cull (Listing XPR-3DGS) of pairs rec[k] x tile txy[k]: keep,
-    smallest power over the tile, level log(o / alpha_min), guard."""
-    rec = _f64(rec).reshape(-1, 9)
+    """tile_cull of pairs rec[k] x tile txy[k]: keep, power, level, guard.
+
+    3DGS / 3DGUT (Listing XPR-3DGS; rec [m][9]): power is the smallest
+    0.5 q over the tile, level log(o / alpha_min). LinPrim (Listing
+    XPR-LinPrim; rec [m][17] and cfg.method "linprim"): power is sigma times
+    the per-tile chord bound, level -log(1 - alpha_min); kept iff
+    power >= level."""
+    stride = 17 if cfg.method == "linprim" else 9
+    rec = _f64(rec).reshape(-1, stride)
     txy = np.ascontiguousarray(txy, dtype=np.int32).reshape(-1, 2)
     m = rec.shape[0]
     assert txy.shape[0] == m
@@ -277,8 +284,8 @@ def tile_cull(rec, txy, W: int, H: int, cfg: OracleConfig):
     level = np.zeros(m)
     guard = np.zeros(m, np.uint8)
     ext = 1 if cfg.method == "3dgut" else 0
-    lib().orc_tile_cull(m, _p(rec), _p(txy), W, H, cfg.tile_w, cfg.tile_h, cfg.alpha_min, ext,
-                        _p(keep), _p(power), _p(level), _p(guard))
+    lib().orc_tile_cull(m, _p(rec), stride, _p(txy), W, H, cfg.tile_w, cfg.tile_h, cfg.alpha_min,
+                        ext, _p(keep), _p(power), _p(level), _p(guard))
     return keep.astype(bool), power, level, guard.astype(bool)
 
 
@@ -353,8 +360,6 @@ def render(scene, cam, cfg: OracleConfig):
     """Whole forward pipeline in FP64: returns every intermediate."""
     pr = project(scene, cam, cfg)
     tx, ty = tiles(cam, cfg)
-    if cfg.tile_cull and cfg.method == "linprim":
-        raise NotImplementedError("the LinPrim tile cull is not built")
     cull = (pr["rec"], cam.width, cam.height, cfg) if cfg.tile_cull else None
     b = bin_pairs(pr["depth"], pr["rect"], pr["tc"], tx, ty, cull)
     f = render_fwd(pr["rec"], b["vals"], b["ranges"], cam.width, cam.height, cfg, cam)

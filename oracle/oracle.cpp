@@ -24,7 +24,8 @@
 //     transform projection, pixel_info (ray direction) and the ray-based
 //     evaluate at tau_max; tile_cull with the extended tile bounds.
 //   * Listing "Implementation of XPR-LinPrim" (forward): the linear map A of
-//     each octahedron, slab-pair ray intersection, Beer-Lambert opacity.
+//     each octahedron, slab-pair ray intersection, Beer-Lambert opacity, and
+//     tile_cull with the per-tile chord bound of the XPR-LinPrim section.
 // Readings where the paper is silent (pixel sample position, low-pass 0.3,
 // 3-sigma radius from the largest eigenvalue, conservative rect rounding,
 // alpha clamp 0.99, stop at T < 1e-4 before blending, ties by index, SH
@@ -674,6 +675,55 @@ double lin_chord(const double* c, double dx, double dy) {
   return exit_ - enter;
 }
 
+// tile_cull of one (octahedron, tile) pair (Listing "XPR-LinPrim",
+// tile_cull; the per-tile upper bound and cull predicate of the XPR-LinPrim
+// section). Every chord over the tile is at most
+//   bound = max(0, min over ordered slab pairs (i, j) of
+//               [max over the box corners of (m_i - m_j) + h_i + h_j])
+// with m_i = -(n_ix dx + n_iy dy) / n_iz and h_i = 1 / |n_iz| at each corner
+// (dx, dy) = corner - u; a slab with |n_iz| < 1e-10 leaves tau free and is
+// dropped from the minimum (its gaps are +infinity). The pair is culled iff
+// sigma bound < -log(1 - alpha_min).
+//
+// Readings: the box is the pixel-sample box of the 3DGS cull,
+// [tx tw, min(tx tw + tw - 1, W - 1)] x [ty th, min(ty th + th - 1, H - 1)],
+// with the sample of pixel x at x + 1/2, so that its offset from mu_2D is
+// x - u (u = mu_2D - 1/2). power holds sigma bound, level the threshold;
+// guard marks sigma bound within 1e-9 (relative) of the threshold.
+CullTest lin_cull_one(const double* rec, int tx, int ty, int W, int H, int tile_w, int tile_h,
+                      double alpha_min) {
+  const double X0 = (double)tx * tile_w, X1 = std::min(X0 + tile_w - 1, W - 1.0);
+  const double Y0 = (double)ty * tile_h, Y1 = std::min(Y0 + tile_h - 1, H - 1.0);
+  const double u = rec[0], v = rec[1], sigma = rec[2];
+  const double* c = rec + 8;  // rows c0, c1, c2 of A^-1
+  const double cx[4] = {X0 - u, X0 - u, X1 - u, X1 - u};
+  const double cy[4] = {Y0 - v, Y1 - v, Y0 - v, Y1 - v};
+  double m[4][4], h[4];
+  bool flat[4];
+  for (int i = 0; i < 4; ++i) {
+    const double e1 = (i & 2) ? -1.0 : 1.0, e2 = (i & 1) ? -1.0 : 1.0;
+    const double nx = c[0] + e1 * c[3] + e2 * c[6];
+    const double ny = c[1] + e1 * c[4] + e2 * c[7];
+    const double nz = c[2] + e1 * c[5] + e2 * c[8];
+    flat[i] = !(std::fabs(nz) >= 1e-10);
+    h[i] = flat[i] ? INFINITY : 1.0 / std::fabs(nz);
+    for (int k = 0; k < 4; ++k) m[i][k] = flat[i] ? 0.0 : -(nx * cx[k] + ny * cy[k]) / nz;
+  }
+  double best = INFINITY;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      if (flat[i] || flat[j]) continue;
+      double mx = -INFINITY;
+      for (int k = 0; k < 4; ++k) mx = std::max(mx, m[i][k] - m[j][k]);
+      best = std::min(best, mx + h[i] + h[j]);
+    }
+  const double bound = std::max(0.0, best);
+  CullTest r{true, false, sigma * bound, -std::log(1.0 - alpha_min)};
+  r.keep = r.power >= r.level;
+  r.guard = std::fabs(r.power - r.level) <= 1e-9 * r.level;
+  return r;
+}
+
 }  // namespace
 
 extern "C" {
@@ -744,8 +794,8 @@ void orc_project(int64_t n, const double* means, const double* scales, const dou
 // and belongs to no range; *n_kept counts the pairs not culled, *n_guard the
 // pairs whose decision is in the guard band, pair_guard [cap] (may be NULL)
 // flags them in sorted order. W, H, tile_w, tile_h and alpha_min are only
-// read with cull_rec; rec_stride is 9 (3DGS) or 21 (3DGUT, whose cull uses
-// tile bounds extended by ext = 1).
+// read with cull_rec; rec_stride is 9 (3DGS), 21 (3DGUT, whose cull uses
+// tile bounds extended by ext = 1) or 17 (LinPrim, the chord bound).
 // Returns I = sum tc; writes the lists only when I <= cap.
 int64_t orc_bin(int64_t n, const double* depth, const int32_t* rect, const int32_t* tc,
                 int tiles_x, int tiles_y, int64_t cap, int64_t* offsets, uint64_t* keys,
@@ -770,8 +820,10 @@ int64_t orc_bin(int64_t n, const double* depth, const int32_t* rect, const int32
       uint32_t tile = (uint32_t)(y * tiles_x + x);
       uint8_t g = 0;
       if (cull_rec) {
-        const CullTest t = tile_cull_one(cull_rec + (int64_t)rec_stride * i, x, y, W, H, tile_w,
-                                         tile_h, alpha_min, ext);
+        const double* cr = cull_rec + (int64_t)rec_stride * i;
+        const CullTest t = rec_stride == 17
+                               ? lin_cull_one(cr, x, y, W, H, tile_w, tile_h, alpha_min)
+                               : tile_cull_one(cr, x, y, W, H, tile_w, tile_h, alpha_min, ext);
         if (!t.keep) tile = sentinel;
         g = t.guard ? 1 : 0;
       }
@@ -811,16 +863,21 @@ int64_t orc_bin(int64_t n, const double* depth, const int32_t* rect, const int32
   return I;
 }
 
-// tile_cull of m (Gaussian, tile) pairs: rec [m][9] shader data, txy [m][2]
-// tile coordinates, ext the tile-bound extension (0 for 3DGS, 1 for 3DGUT);
-// keep, power (smallest 0.5 q over the tile), level (log(o / alpha_min))
-// and guard per pair (any output may be NULL).
-void orc_tile_cull(int64_t m, const double* rec, const int32_t* txy, int W, int H, int tile_w,
-                   int tile_h, double alpha_min, int ext, uint8_t* keep, double* power,
-                   double* level, uint8_t* guard) {
+// tile_cull of m (primitive, tile) pairs: rec [m][rec_stride] shader data
+// (9: 3DGS/3DGUT cull columns, 17: LinPrim), txy [m][2] tile coordinates,
+// ext the tile-bound extension (0 for 3DGS, 1 for 3DGUT); keep, power
+// (3DGS: smallest 0.5 q over the tile, level log(o / alpha_min); LinPrim:
+// sigma times the chord bound, level -log(1 - alpha_min)) and guard per pair
+// (any output may be NULL).
+void orc_tile_cull(int64_t m, const double* rec, int rec_stride, const int32_t* txy, int W,
+                   int H, int tile_w, int tile_h, double alpha_min, int ext, uint8_t* keep,
+                   double* power, double* level, uint8_t* guard) {
   for (int64_t k = 0; k < m; ++k) {
-    const CullTest t = tile_cull_one(rec + 9 * k, txy[2 * k], txy[2 * k + 1], W, H, tile_w,
-                                     tile_h, alpha_min, ext);
+    const double* r = rec + (int64_t)rec_stride * k;
+    const CullTest t =
+        rec_stride == 17
+            ? lin_cull_one(r, txy[2 * k], txy[2 * k + 1], W, H, tile_w, tile_h, alpha_min)
+            : tile_cull_one(r, txy[2 * k], txy[2 * k + 1], W, H, tile_w, tile_h, alpha_min, ext);
     if (keep) keep[k] = t.keep ? 1 : 0;
     if (power) power[k] = t.power;
     if (level) level[k] = t.level;
