@@ -230,6 +230,14 @@ def main():
                                   "pairs_per_frame": lr["pairs"],
                                   "3dgs_forward_stage_sum_ms": round(fwd3, 4)}
         log(f"[bench] linprim forward: {lr['ms_wall']:.3f} ms/frame, pairs {lr['pairs']:.0f}")
+        lccfg = dataclasses.replace(lcfg, tile_cull=True)
+        lc = timed_forward(scene, cams, lccfg, args.steps, args.warmup)
+        out["linprim_forward_tile_cull"] = {"ms_per_step": round(lc["ms_wall"], 4),
+                                            "stages_ms_mean": lc["stage_ms"],
+                                            "pairs_per_frame": lc["pairs"],
+                                            "pairs_vs_uncut": lc["pairs"] / lr["pairs"]}
+        log(f"[bench] linprim forward + tile_cull: {lc['ms_wall']:.3f} ms/frame, pairs "
+            f"{lc['pairs']:.0f} ({lc['pairs'] / lr['pairs']:.3f} of {lr['pairs']:.0f})")
     del scene, targets
     torch.cuda.empty_cache()
     if not args.no_batch:

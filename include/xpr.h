@@ -247,10 +247,15 @@ xpr_status xpr_bin_sort_workspace(const xpr_views* views, const xpr_config* cfg,
  * lists, ranges and *n_isect then hold the kept pairs only (the listing's
  * sentinel tile for culled pairs is never materialised), the image is the
  * same up to alpha values at the 1/255 threshold, and the presort strategy
- * is used whatever cfg->sort_mode says (XPR_ERR_UNSUPPORTED with
- * XPR_METHOD_LINPRIM, whose cull is not built). For XPR_METHOD_3DGUT the tile box
+ * is used whatever cfg->sort_mode says. For XPR_METHOD_3DGUT the tile box
  * is first extended by one pixel in x and y (tile_max += 1 of its
- * tile_cull).
+ * tile_cull). For XPR_METHOD_LINPRIM the test is the tile_cull of the
+ * listing XPR-LinPrim: with the slab data (h_i = 1 / |n_iz|, m_i the slab
+ * midpoint in tau at a pixel) the longest chord over the same pixel-sample
+ * box is bounded by max(0, min over ordered slab pairs (i, j) of
+ * [max over the box corners of (m_i - m_j) + h_i + h_j]) (slabs with
+ * |n_iz| < 1e-10 dropped), and the pair is kept iff sigma times that bound
+ * is at least -log(1 - alpha_min).
  *   out     buffers as described at xpr_bins
  *   ws / ws_bytes   workspace of at least xpr_bin_sort_workspace() bytes
  * With cfg->no_sync == 0 the call reads I back (one stream sync) and returns

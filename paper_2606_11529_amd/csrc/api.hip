@@ -329,10 +329,6 @@ xpr_status xpr_bin_sort(const xpr_views* views, const xpr_config* cfg, const xpr
                 (!out->tile_order || aligned(out->tile_order, 4)),
             "misaligned output buffer");
   const bool cull = cfg->tile_cull != 0;
-  if (cull && cfg->method == XPR_METHOD_LINPRIM) {
-    set_error("tile_cull is not built for XPR_METHOD_LINPRIM");
-    return XPR_ERR_UNSUPPORTED;
-  }
   const size_t need = bin_workspace_bytes(S.records, cap, S.tiles, cfg->sort_mode, cull);
   XPR_CHECK(ws_bytes >= need && (need == 0 || ws != nullptr),
             "workspace too small: %zu < %zu bytes", ws_bytes, need);

@@ -10,6 +10,7 @@
 // rank among lanes holding the same digit) and writes them out in digit
 // order, so global stores are contiguous runs per digit.
 #include <algorithm>
+#include <cmath>
 
 #include "xpr_internal.h"
 
@@ -556,11 +557,11 @@ struct RowGeom {
 };
 
 // Cull constants of one record (lvl = 2 log(o / alpha_min), ex the half
-// width of E).
-__device__ __forceinline__ RowGeom row_geom(const Batch& B, int r, const float4 s0,
-                                            const float4 s1, const short4 rc) {
+// width of E); q is the record's splat data.
+__device__ __forceinline__ void make_geom(RowGeom& G, const Batch& B, int r,
+                                          const float4* __restrict__ q, const short4 rc, double) {
 #pragma clang fp contract(off)
-  RowGeom G;
+  const float4 s0 = q[0], s1 = q[1];
   const int v = view_of_record(B, r);
   const double a = -2.0 * (double)s0.z, b = -(double)s0.w, c = -2.0 * (double)s1.x;
   G.u = s0.x;
@@ -585,7 +586,6 @@ __device__ __forceinline__ RowGeom row_geom(const Batch& B, int r, const float4 
   G.tile0 = B.v[v].tile_off;
   G.tiles_x = B.v[v].tiles_x;
   G.ext = B.method == XPR_METHOD_3DGUT ? 1 : 0;
-  return G;
 }
 
 // Kept columns [*lo, *hi) of rect row ty. Tile sizes are powers of two, so
@@ -613,14 +613,148 @@ __device__ __forceinline__ void cull_row(const RowGeom& G, int ty, int tw, int t
   *hi = none ? l : max(l, h);
 }
 
+// LinPrim (tile_cull of XPR-LinPrim, the per-tile chord bound of the
+// XPR-LinPrim section): a pair is kept iff sigma * bound >= -log(1 -
+// alpha_min), with
+//   bound = max(0, min over ordered slab pairs (i, j) of
+//               [max over the box corners of (m_i - m_j) + h_i + h_j]),
+// m_i = a_i dx + b_i dy (a_i = -n_ix / n_iz, b_i = -n_iy / n_iz),
+// h_i = 1 / |n_iz|, on the pixel-sample box of the 3DGS cull; a slab with
+// |n_iz| < 1e-10 is dropped (h = +inf, a = b = 0). With lam = req / sigma
+// the test is: 2 min h_i >= lam and every off-diagonal gap >= lam.
+//
+// The corners form the product {dx0, dx1} x {dy0, dy1}, so the gap of
+// (i, j) is max(D dx0, D dx1) + max(Bd dy0, Bd dy1) + h_i + h_j with
+// D = a_i - a_j, Bd = b_i - b_j, and (j, i) has the negated slopes. In a
+// tile row dy0, dy1 are fixed and dx1 = dx0 + tw - 1 with dx0 = X0 - u (X0
+// the tile's first pixel column), so for D != 0 the two gaps of a slab pair
+// (the one with positive x slope reaches its maximum at dx1, the other at
+// dx0) are >= lam exactly when, with th = lam - h_i - h_j and q = 1 / D,
+//   X0 >= lc - max(bq dy0, bq dy1),  lc = (u - tw + 1) + th |q|,
+//   X0 <= uc - min(bq dy0, bq dy1),  uc = u - th |q|,   bq = Bd q,
+// whatever the sign of D: a row keeps the tiles whose X0 lies in the
+// intersection of these intervals (one run; the gaps are affine in X0).
+// A pair with D = 0 is a yes/no condition on the row (max(Bd dy) >= th and
+// -min(Bd dy) >= th). A last tile column clipped by the image border has
+// dx1 = W - 1 - u: its lower bounds are checked at X0 = W - tw.
+struct LinGeom {
+  double lc[6], uc[6], bq[6];  // slab pairs i < j with a_i != a_j
+  double zb[6], zt[6];         // pairs with a_i == a_j: Bd and th (read when zm != 0)
+  double v;                    // mu_2D.y - 1/2
+  int32_t zm, none;            // mask of the a_i == a_j pairs; 2 min h < lam
+  int32_t x0, x1, y0, wm1;     // rect columns [x0, x1), first rect row, W - 1
+  int32_t hm1, rec;            // H - 1, record id
+  int32_t tile0, tiles_x;      // tile id of the view's tile (0, 0), tiles per row
+};
+
+// 1 / d from the hardware reciprocal and two Newton-Raphson steps (about one
+// ulp; d finite and normal).
+__device__ __forceinline__ double rcp_nr(double d) {
+  double x = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, x, 1.0);
+  x = fma(x, e, x);
+  e = fma(-d, x, 1.0);
+  return fma(x, e, x);
+}
+
+__device__ __forceinline__ void make_geom(LinGeom& G, const Batch& B, int r,
+                                          const float4* __restrict__ q, const short4 rc,
+                                          double req) {
+#pragma clang fp contract(off)
+  const float4 q0 = q[0], q2 = q[2], q3 = q[3], q4 = q[4];
+  const double c[9] = {q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w, q4.x};
+  const int v = view_of_record(B, r);
+  const double u = q0.x, sigma = q0.z;
+  G.v = q0.y;
+  const double lam = sigma > 0.0 ? req * rcp_nr(sigma) : INFINITY;
+  double a[4], b[4], h[4], hm = INFINITY;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double e1 = (i & 2) ? -1.0 : 1.0, e2 = (i & 1) ? -1.0 : 1.0;
+    const double nx = c[0] + e1 * c[3] + e2 * c[6];
+    const double ny = c[1] + e1 * c[4] + e2 * c[7];
+    const double nz = c[2] + e1 * c[5] + e2 * c[8];
+    const bool flat = !(fabs(nz) >= 1e-10);
+    const double rz = rcp_nr(flat ? 1.0 : nz);
+    a[i] = flat ? 0.0 : -nx * rz;
+    b[i] = flat ? 0.0 : -ny * rz;
+    h[i] = flat ? INFINITY : fabs(rz);
+    hm = fmin(hm, h[i]);
+  }
+  G.none = hm + hm >= lam ? 0 : 1;
+  const double ul = u - (double)(B.tile_w - 1);
+  int zm = 0, p = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = i + 1; j < 4; ++j, ++p) {
+      const double D = a[i] - a[j], Bd = b[i] - b[j];
+      const double th = lam - (h[i] + h[j]);
+      const bool z = D == 0.0;
+      const double qd = rcp_nr(z ? 1.0 : D), aq = fabs(qd);
+      G.lc[p] = z ? -1e300 : ul + th * aq;
+      G.uc[p] = z ? 1e300 : u - th * aq;
+      G.bq[p] = z ? 0.0 : Bd * qd;
+      G.zb[p] = Bd;
+      G.zt[p] = th;
+      zm |= z ? 1 << p : 0;
+    }
+  G.zm = zm;
+  G.x0 = rc.x;
+  G.x1 = rc.z;
+  G.y0 = rc.y;
+  G.wm1 = B.v[v].W - 1;
+  G.hm1 = B.v[v].H - 1;
+  G.rec = r;
+  G.tile0 = B.v[v].tile_off;
+  G.tiles_x = B.v[v].tiles_x;
+}
+
+// The LinPrim cull threshold -log(1 - alpha_min), formed on the host.
+inline double lin_req(const Batch& B) { return -std::log(1.0 - (double)B.alpha_min); }
+
+// Kept columns [*lo, *hi) of rect row ty.
+__device__ __forceinline__ void cull_row(const LinGeom& G, int ty, int tw, int th, double inv_tw,
+                                         int* lo, int* hi) {
+#pragma clang fp contract(off)
+  const double dy0 = (double)ty * th - G.v;
+  const double dy1 = fmin((double)ty * th + (th - 1), (double)G.hm1) - G.v;
+  double xl = -1e9, xr = 1e9;  // X0 must lie in [xl, xr]
+#pragma unroll
+  for (int p = 0; p < 6; ++p) {
+    const double t0 = G.bq[p] * dy0, t1 = G.bq[p] * dy1;
+    xl = fmax(xl, G.lc[p] - fmax(t0, t1));
+    xr = fmin(xr, G.uc[p] - fmin(t0, t1));
+  }
+  bool none = G.none != 0;
+  if (G.zm != 0) {
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+      const double t0 = G.zb[p] * dy0, t1 = G.zb[p] * dy1;
+      const bool bad = fmax(t0, t1) < G.zt[p] || -fmin(t0, t1) < G.zt[p];
+      none = none || (((G.zm >> p) & 1) && bad);
+    }
+  }
+  const int c_lo = (int)ceil(fmin(fmax(xl, -1e9), 1e9) * inv_tw);
+  const int c_hi = (int)floor(fmin(fmax(xr, -1e9), 1e9) * inv_tw) + 1;
+  const int l = max(G.x0, c_lo);
+  int h = none ? l : max(l, min(G.x1, c_hi));
+  // the last tile column, if the image border clips its box
+  if (h > l && h == G.tiles_x && (h - 1) * tw + (tw - 1) > G.wm1 &&
+      !((double)(G.wm1 - (tw - 1)) >= xl))
+    --h;
+  *lo = l;
+  *hi = h;
+}
+
 // The rows of the rects of a wave's 64 records, spread over its lanes: lane
 // l's record has h rows (0 when it keeps nothing), pre = the wave's
 // exclusive scan of h, and item q of the flattened row sequence belongs to
 // the last record g with pre[g] <= q. Calls f(g, ty, lo, hi) for every item
 // of every chunk of 64 (valid = false past the end, then lo = hi); the loop
 // is wave-uniform. geo / pre are this wave's 64 LDS entries.
-template <class F>
-__device__ __forceinline__ void wave_rows(const RowGeom* geo, const uint32_t* pre, uint32_t total,
+template <class Geo, class F>
+__device__ __forceinline__ void wave_rows(const Geo* geo, const uint32_t* pre, uint32_t total,
                                           int tw, int th, F f) {
   const int lane = threadIdx.x & 63;
   const double inv_tw = 1.0 / tw;
@@ -642,6 +776,7 @@ __device__ __forceinline__ void wave_rows(const RowGeom* geo, const uint32_t* pr
 // Count pass of the cull (record order): kept pairs kc and kept rows per
 // record, written as kc | rows << pack_bits (pack_bits > 0) or to two arrays,
 // and the depth-presort keys (records keeping no pair sort last).
+template <class Geo>
 __global__ __launch_bounds__(256) void k_cull_count(Batch B, const float4* __restrict__ splat,
                                                     const short4* __restrict__ rect,
                                                     const int32_t* __restrict__ tc,
@@ -649,16 +784,15 @@ __global__ __launch_bounds__(256) void k_cull_count(Batch B, const float4* __res
                                                     int pack_bits, uint32_t* __restrict__ kc,
                                                     uint32_t* __restrict__ nrow,
                                                     uint32_t* __restrict__ key,
-                                                    uint32_t* __restrict__ perm) {
-  __shared__ RowGeom geo[256];
+                                                    uint32_t* __restrict__ perm, double req) {
+  __shared__ Geo geo[256];
   __shared__ uint32_t pre[256], s_kc[256], s_nr[256];
   const int t = threadIdx.x, wb = t & ~63;
   const int64_t i = (int64_t)blockIdx.x * 256 + t;
   uint32_t h = 0;
   if (i < n && tc[i] > 0) {
     const short4 rc = rect[i];
-    const int64_t sr = (int64_t)splat_stride4(B) * i;
-    geo[t] = row_geom(B, (int)i, splat[sr], splat[sr + 1], rc);
+    make_geom(geo[t], B, (int)i, splat + (int64_t)splat_stride4(B) * i, rc, req);
     h = (uint32_t)(rc.w - rc.y);
   }
   s_kc[t] = 0;
@@ -692,6 +826,7 @@ __global__ __launch_bounds__(256) void k_cull_count(Batch B, const float4* __res
 // tiles_x << 16), and first[] as k_pair_records writes it. A wave's rows are
 // flattened in depth order, so their pair offsets and record slots are the
 // wave's bases (offsets / roff at its first position) plus running sums.
+template <class Geo>
 __global__ __launch_bounds__(256) void k_cull_emit(Batch B, const float4* __restrict__ splat,
                                                    const short4* __restrict__ rect,
                                                    const uint32_t* __restrict__ kcs,
@@ -701,8 +836,8 @@ __global__ __launch_bounds__(256) void k_cull_emit(Batch B, const float4* __rest
                                                    uint32_t kc_mask, int64_t n_rec,
                                                    const int64_t* n_isect, int64_t cap,
                                                    uint4* __restrict__ packed,
-                                                   uint32_t* __restrict__ first) {
-  __shared__ RowGeom geo[256];
+                                                   uint32_t* __restrict__ first, double req) {
+  __shared__ Geo geo[256];
   __shared__ uint32_t pre[256];
   const int t = threadIdx.x, lane = t & 63, wb = t & ~63;
   const int64_t j = (int64_t)blockIdx.x * 256 + t;
@@ -711,8 +846,7 @@ __global__ __launch_bounds__(256) void k_cull_emit(Batch B, const float4* __rest
   if (j < n_rec && (kcs[j] & kc_mask) > 0) {
     const uint32_t r = perm[j];
     const short4 rc = rect[r];
-    const int64_t sr = (int64_t)splat_stride4(B) * r;
-    geo[t] = row_geom(B, (int)r, splat[sr], splat[sr + 1], rc);
+    make_geom(geo[t], B, (int)r, splat + (int64_t)splat_stride4(B) * r, rc, req);
     h = (uint32_t)(rc.w - rc.y);
   }
   const uint32_t inc = wave_incl_scan_dpp(h);
@@ -733,7 +867,7 @@ __global__ __launch_bounds__(256) void k_cull_emit(Batch B, const float4* __rest
               const uint32_t iw = ix & 0xfffffu, ir = ix >> 20;
               const int64_t o = pbase + (int64_t)(iw - w);
               if (w > 0 && o < n) {
-                const RowGeom& G = geo[wb + g];
+                const Geo& G = geo[wb + g];
                 const uint32_t k = rbase + ir - 1u;
                 packed[k] = make_uint4((uint32_t)o, (uint32_t)G.rec,
                                        (uint32_t)(G.tile0 + ty * G.tiles_x + lo),
@@ -748,6 +882,80 @@ __global__ __launch_bounds__(256) void k_cull_emit(Batch B, const float4* __rest
               rbase += tot >> 20;
             });
   (void)lane;
+}
+
+// The LinPrim cull passes, one record per lane: octahedron rects span few
+// tile rows (about two on average) and the row test is a closed form, so a
+// lane walks its own record's rows with the slab data in registers (no LDS
+// staging, no cross-lane search). Same outputs as k_cull_count /
+// k_cull_emit.
+__global__ __launch_bounds__(256) void k_cull_count_lin(Batch B, const float4* __restrict__ splat,
+                                                        const short4* __restrict__ rect,
+                                                        const int32_t* __restrict__ tc,
+                                                        const float* __restrict__ depth,
+                                                        int64_t n, int pack_bits,
+                                                        uint32_t* __restrict__ kc,
+                                                        uint32_t* __restrict__ nrow,
+                                                        uint32_t* __restrict__ key,
+                                                        uint32_t* __restrict__ perm, double req) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  uint32_t c = 0, rows = 0;
+  if (tc[i] > 0) {
+    const short4 rc = rect[i];
+    LinGeom G;
+    make_geom(G, B, (int)i, splat + (int64_t)splat_stride4(B) * i, rc, req);
+    const double inv_tw = ldexp(1.0, -__builtin_ctz(B.tile_w));  // tile sizes are powers of 2
+    for (int ty = rc.y; ty < rc.w; ++ty) {
+      int lo, hi;
+      cull_row(G, ty, B.tile_w, B.tile_h, inv_tw, &lo, &hi);
+      c += (uint32_t)(hi - lo);
+      rows += hi > lo ? 1u : 0u;
+    }
+  }
+  if (pack_bits > 0) {
+    kc[i] = c | (rows << pack_bits);
+  } else {
+    kc[i] = c;
+    nrow[i] = rows;
+  }
+  key[i] = c > 0 ? __float_as_uint(depth[i]) : 0xffffffffu;
+  perm[i] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(256) void k_cull_emit_lin(Batch B, const float4* __restrict__ splat,
+                                                       const short4* __restrict__ rect,
+                                                       const uint32_t* __restrict__ kcs,
+                                                       const uint32_t* __restrict__ perm,
+                                                       const uint32_t* __restrict__ offsets,
+                                                       const uint32_t* __restrict__ roff,
+                                                       uint32_t kc_mask, int64_t n_rec,
+                                                       const int64_t* n_isect, int64_t cap,
+                                                       uint4* __restrict__ packed,
+                                                       uint32_t* __restrict__ first, double req) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n_rec || (kcs[j] & kc_mask) == 0) return;
+  const uint32_t r = perm[j];
+  const short4 rc = rect[r];
+  LinGeom G;
+  make_geom(G, B, (int)r, splat + (int64_t)splat_stride4(B) * r, rc, req);
+  const double inv_tw = ldexp(1.0, -__builtin_ctz(B.tile_w));
+  const int64_t n = clamp_n(n_isect, cap);
+  int64_t o = offsets[j];
+  uint32_t k = roff[j];
+  for (int ty = rc.y; ty < rc.w && o < n; ++ty) {
+    int lo, hi;
+    cull_row(G, ty, B.tile_w, B.tile_h, inv_tw, &lo, &hi);
+    const uint32_t w = (uint32_t)(hi - lo);
+    if (w == 0) continue;
+    packed[k] = make_uint4((uint32_t)o, r, (uint32_t)(G.tile0 + ty * G.tiles_x + lo),
+                           w | ((uint32_t)G.tiles_x << 16));
+    const int64_t oe = min(o + (int64_t)w, n);
+    for (int64_t b = (o + kSortTile - 1) / kSortTile; b * kSortTile < oe; ++b) first[b] = k;
+    if (oe == n) first[(n + kSortTile - 1) / kSortTile] = k;
+    o += w;
+    ++k;
+  }
 }
 
 // Up to N packed records of a sort block, staged in LDS: the item offset of
@@ -1321,10 +1529,16 @@ hipError_t bin_phase1(const Batch& B, int sort_mode, bool cull, const float* spl
     const int32_t* counts = tc;
     const int pb = cull ? cull_pack_bits(B) : 0;
     if (cull) {
-      hipLaunchKernelGGL(k_cull_count, dim3(grid1(n_rec)), dim3(256), 0, st, B,
-                         reinterpret_cast<const float4*>(splat),
-                         reinterpret_cast<const short4*>(rect), tc, depth, n_rec, pb, L.kc,
-                         L.nrow, L.dkey[0], L.perm[0]);
+      if (B.method == XPR_METHOD_LINPRIM)
+        hipLaunchKernelGGL(k_cull_count_lin, dim3(grid1(n_rec)), dim3(256), 0, st, B,
+                           reinterpret_cast<const float4*>(splat),
+                           reinterpret_cast<const short4*>(rect), tc, depth, n_rec, pb, L.kc,
+                           L.nrow, L.dkey[0], L.perm[0], lin_req(B));
+      else
+        hipLaunchKernelGGL(k_cull_count<RowGeom>, dim3(grid1(n_rec)), dim3(256), 0, st, B,
+                           reinterpret_cast<const float4*>(splat),
+                           reinterpret_cast<const short4*>(rect), tc, depth, n_rec, pb, L.kc,
+                           L.nrow, L.dkey[0], L.perm[0], lin_req(B));
       counts = reinterpret_cast<const int32_t*>(L.kc);
     } else {
       hipLaunchKernelGGL(k_depth_keys, dim3(grid1(n_rec)), dim3(256), 0, st, depth, tc, n_rec,
@@ -1399,10 +1613,15 @@ static hipError_t pair_sort(const Batch& B, int tile_bits, const float* depth, c
   hipLaunchKernelGGL(k_ranges_init, dim3(grid1(tiles)), dim3(256), 0, st, ranges, tiles);
   if (splat) {  // per-(Gaussian, tile) cull: one record per kept row
     const int pb = cull_pack_bits(B);
-    hipLaunchKernelGGL(k_cull_emit, dim3(grid1(n_rec)), dim3(256), 0, st, B,
-                       reinterpret_cast<const float4*>(splat), rc, L.tcs, perm, L.offsets, L.roff,
-                       pb > 0 ? (1u << pb) - 1u : 0xffffffffu, n_rec, n_isect, cap, L.packed,
-                       L.first);
+    const uint32_t kmask = pb > 0 ? (1u << pb) - 1u : 0xffffffffu;
+    if (B.method == XPR_METHOD_LINPRIM)
+      hipLaunchKernelGGL(k_cull_emit_lin, dim3(grid1(n_rec)), dim3(256), 0, st, B,
+                         reinterpret_cast<const float4*>(splat), rc, L.tcs, perm, L.offsets,
+                         L.roff, kmask, n_rec, n_isect, cap, L.packed, L.first, lin_req(B));
+    else
+      hipLaunchKernelGGL(k_cull_emit<RowGeom>, dim3(grid1(n_rec)), dim3(256), 0, st, B,
+                         reinterpret_cast<const float4*>(splat), rc, L.tcs, perm, L.offsets,
+                         L.roff, kmask, n_rec, n_isect, cap, L.packed, L.first, lin_req(B));
   } else
     hipLaunchKernelGGL(k_pair_records, dim3(grid1(n_rec)), dim3(256), 0, st, B, rc, L.tcs, perm,
                        L.offsets, n_rec, n_isect, cap, L.packed, L.first);

@@ -152,7 +152,7 @@ def check_binning_cull(gpu, cam, cfg, tiles_x_y):
     kept or guard, and all kept non-guard pairs must be there."""
     tx, ty = tiles_x_y
     oc = ocfg_of(cfg)
-    nrec = 21 if cfg.method == "3dgut" else 9
+    nrec = {"3dgut": 21, "linprim": 17}.get(cfg.method, 9)
     crec = gpu["splat"][:, :nrec].astype(np.float64)
     ref = oracle.bin_pairs(gpu["depth"].astype(np.float64), gpu["rect"], gpu["tc"], tx, ty,
                            (crec, cam.width, cam.height, oc))
@@ -166,7 +166,8 @@ def check_binning_cull(gpu, cam, cfg, tiles_x_y):
         return ref
     lens = gpu["ranges"][:, 1] - gpu["ranges"][:, 0]
     tid = np.repeat(np.arange(tx * ty), lens)
-    keep, _, _, g = oracle.tile_cull(rec9(gpu["splat"])[gpu["vals"]], np.stack([tid % tx, tid // tx], 1),
+    trec = crec[:, :17] if cfg.method == "linprim" else crec[:, :9]
+    keep, _, _, g = oracle.tile_cull(trec[gpu["vals"]], np.stack([tid % tx, tid // tx], 1),
                                      cam.width, cam.height, oc)
     assert np.all(keep | g), "GPU kept a pair the oracle culls"
     assert int((keep & ~g).sum()) == n - int(ref["pair_guard"][:n].sum())

@@ -2,8 +2,10 @@
 XPR-LinPrim") on the HIP path with the FP64 oracle, through the C-ABI: the
 projection (floats within rounding bounds, rects and tile counts bit-exact
 outside the guard band), binning bit-exact on the Euclidean depth,
-compositing within 1e-5 max-abs with n_contrib exact, and the entry points
-refusing what is not built (the LinPrim cull, the backward)."""
+compositing within 1e-5 max-abs with n_contrib exact; with tile_cull the
+lists equal the oracle's kept pairs (its per-tile chord bound) bit-exactly
+outside the guard band and the images stay within the tolerance of the uncut
+ones; the backward entry points refuse LinPrim (not built)."""
 import functools
 
 import numpy as np
@@ -11,9 +13,11 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import cam32, check_binning, log, ocfg_of, run_gpu, TOL_PIXEL
+from gpu_util import (cam32, check_binning, check_binning_cull, log, ocfg_of, run_gpu,
+                      TOL_PIXEL)
 from paper_2606_11529_amd import _lib as L
 from paper_2606_11529_amd import renderer as R
+from helpers import axis_camera, hand_scene
 from synth import camera_config1, camera_look_at, random_cameras, scene_clusters, scene_config1
 
 pytestmark = pytest.mark.gpu
@@ -30,20 +34,30 @@ def _case(name):
     if name == "ragged_t16":
         sc = scene_clusters(3000, seed=6, n_clusters=6, box=1.2, lo=0.005, hi=0.4, sh_degree=1)
         return sc, camera_look_at((-0.3, 0.5, -3.9), 101, 67), R.Config(sh_degree=1)
+    if name == "axis_grid_t8":
+        # axis-aligned octahedra in front of an axis camera: the ones on the
+        # horizontal axis have slab pairs with equal x slopes (a_i == a_j)
+        g = np.stack(np.meshgrid(np.linspace(-1, 1, 9), np.linspace(-0.6, 0.6, 7), [4.0]),
+                     -1).reshape(-1, 3)
+        g[:, 0] += 0.013
+        sc = hand_scene(g, [[0.12, 0.09, 0.05]], opac=0.8)
+        return sc, axis_camera(150, 97, f=120.0), R.Config(tile=8, sh_degree=0)
     if name == "c2_1M_1297x840":
         sc = scene_clusters(1_000_000, seed=0)
         return sc, random_cameras(1, 0, (1297, 840))[0], R.Config(sh_degree=3)
     raise KeyError(name)
 
 
-CASES = ["c1_10k_256", "ragged_t8", "ragged_t16", "c2_1M_1297x840"]
+CASES = ["c1_10k_256", "ragged_t8", "ragged_t16", "axis_grid_t8", "c2_1M_1297x840"]
 
 
 @functools.lru_cache(maxsize=1)
-def _run(name):
+def _run(name, cull=False):
     sc, cam, cfg = _case(name)
     cfg.method = "linprim"
-    log(f"[gpu linprim] case={name} n={sc.n} {cam.width}x{cam.height} tile={cfg.tile}")
+    cfg.tile_cull = cull
+    log(f"[gpu linprim] case={name} n={sc.n} {cam.width}x{cam.height} tile={cfg.tile} "
+        f"cull={cull}")
     return sc, cam, cfg, run_gpu(sc, cam, cfg)
 
 
@@ -101,7 +115,23 @@ def test_linprim_projection_binning_forward(name):
         f"max-abs {emax:.2e}, guard pixels {gp}, lit {(g['ncontrib'][0] > 0).mean():.3f}")
 
 
-def test_linprim_refuses_cull_and_backward():
+@pytest.mark.parametrize("name", CASES)
+def test_linprim_cull(name):
+    _, _, _, g0 = _run(name)
+    img0, n0 = g0["image"][0].copy(), g0["I"]
+    sc, cam, cfg, g = _run(name, cull=True)
+    tx, ty = oracle.tiles(cam, ocfg_of(cfg))
+    ref = check_binning_cull(g, cam, cfg, (tx, ty))
+    assert ref["I"] == n0 and g["I"] < n0
+    emax, gp = _check_forward(g, cam, cfg)
+    # culled pairs have alpha < 1/255 at every pixel: the image is the uncut one
+    dmax = float(np.abs(g["image"][0] - img0).max())
+    assert dmax <= TOL_PIXEL, f"cull changed the image by {dmax}"
+    log(f"[L2] {name}: kept {g['I']} of {n0} ({g['I'] / n0:.3f}), guard pairs "
+        f"{ref['n_guard']}, max-abs {emax:.2e}, vs uncut {dmax:.1e}")
+
+
+def test_linprim_refuses_backward():
     sc = scene_clusters(500, seed=4, n_clusters=2, box=1.0, lo=0.01, hi=0.2)
     cam = camera_look_at((0.1, 0.2, -4.0), 48, 32)
     cfg = R.Config(method="linprim")
@@ -114,9 +144,4 @@ def test_linprim_refuses_cull_and_backward():
     dimg = torch.zeros(3 * views.pixels, dtype=torch.float32, device="cuda")
     with pytest.raises(L.XprError) as e:
         R.xpr_render_bwd(views, cfg, proj, bins, frame, dimg)
-    assert e.value.status == L.XPR_ERR_UNSUPPORTED
-    ccfg = R.Config(method="linprim", tile_cull=True)
-    cviews = R.Views([scene], [cam], [0], ccfg)
-    with pytest.raises(L.XprError) as e:
-        R.xpr_bin_sort(cviews, ccfg, proj)
     assert e.value.status == L.XPR_ERR_UNSUPPORTED
