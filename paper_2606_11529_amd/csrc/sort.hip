@@ -888,7 +888,11 @@ __global__ __launch_bounds__(256) void k_cull_emit(Batch B, const float4* __rest
 // tile rows (about two on average) and the row test is a closed form, so a
 // lane walks its own record's rows with the slab data in registers (no LDS
 // staging, no cross-lane search). Same outputs as k_cull_count /
-// k_cull_emit.
+// k_cull_emit. The count pass also keeps, in record order, the runs of a
+// record whose kept rows are at most 3 consecutive ones: runs[i] = (first
+// kept row | rows << 16, lo | hi << 16 of each row), else (0xffffffff, ...);
+// the emit pass (depth order) then gathers those 16 bytes instead of the
+// splat and rect, and rebuilds the runs only for the other records.
 __global__ __launch_bounds__(256) void k_cull_count_lin(Batch B, const float4* __restrict__ splat,
                                                         const short4* __restrict__ rect,
                                                         const int32_t* __restrict__ tc,
@@ -897,10 +901,13 @@ __global__ __launch_bounds__(256) void k_cull_count_lin(Batch B, const float4* _
                                                         uint32_t* __restrict__ kc,
                                                         uint32_t* __restrict__ nrow,
                                                         uint32_t* __restrict__ key,
-                                                        uint32_t* __restrict__ perm, double req) {
+                                                        uint32_t* __restrict__ perm,
+                                                        uint4* __restrict__ runs, double req) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
-  uint32_t c = 0, rows = 0;
+  uint32_t c = 0, rows = 0, first_row = 0;
+  uint32_t rw0 = 0, rw1 = 0, rw2 = 0;
+  bool gap = false;
   if (tc[i] > 0) {
     const short4 rc = rect[i];
     LinGeom G;
@@ -909,10 +916,19 @@ __global__ __launch_bounds__(256) void k_cull_count_lin(Batch B, const float4* _
     for (int ty = rc.y; ty < rc.w; ++ty) {
       int lo, hi;
       cull_row(G, ty, B.tile_w, B.tile_h, inv_tw, &lo, &hi);
+      if (hi <= lo) continue;
+      const uint32_t w = (uint32_t)lo | ((uint32_t)hi << 16);
+      if (rows == 0) first_row = (uint32_t)ty;
+      gap = gap || (uint32_t)ty != first_row + rows;
+      rw0 = rows == 0 ? w : rw0;
+      rw1 = rows == 1 ? w : rw1;
+      rw2 = rows == 2 ? w : rw2;
       c += (uint32_t)(hi - lo);
-      rows += hi > lo ? 1u : 0u;
+      ++rows;
     }
   }
+  runs[i] = rows > 0 && rows <= 3 && !gap ? make_uint4(first_row | (rows << 16), rw0, rw1, rw2)
+                                          : make_uint4(0xffffffffu, 0u, 0u, 0u);
   if (pack_bits > 0) {
     kc[i] = c | (rows << pack_bits);
   } else {
@@ -931,30 +947,44 @@ __global__ __launch_bounds__(256) void k_cull_emit_lin(Batch B, const float4* __
                                                        const uint32_t* __restrict__ roff,
                                                        uint32_t kc_mask, int64_t n_rec,
                                                        const int64_t* n_isect, int64_t cap,
+                                                       const uint4* __restrict__ runs,
                                                        uint4* __restrict__ packed,
                                                        uint32_t* __restrict__ first, double req) {
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= n_rec || (kcs[j] & kc_mask) == 0) return;
   const uint32_t r = perm[j];
-  const short4 rc = rect[r];
-  LinGeom G;
-  make_geom(G, B, (int)r, splat + (int64_t)splat_stride4(B) * r, rc, req);
-  const double inv_tw = ldexp(1.0, -__builtin_ctz(B.tile_w));
   const int64_t n = clamp_n(n_isect, cap);
   int64_t o = offsets[j];
   uint32_t k = roff[j];
-  for (int ty = rc.y; ty < rc.w && o < n; ++ty) {
-    int lo, hi;
-    cull_row(G, ty, B.tile_w, B.tile_h, inv_tw, &lo, &hi);
+  const int v = view_of_record(B, (int)r);
+  const int tile0 = B.v[v].tile_off, tiles_x = B.v[v].tiles_x;
+  auto put = [&](int ty, int lo, int hi) {
     const uint32_t w = (uint32_t)(hi - lo);
-    if (w == 0) continue;
-    packed[k] = make_uint4((uint32_t)o, r, (uint32_t)(G.tile0 + ty * G.tiles_x + lo),
-                           w | ((uint32_t)G.tiles_x << 16));
+    packed[k] = make_uint4((uint32_t)o, r, (uint32_t)(tile0 + ty * tiles_x + lo),
+                           w | ((uint32_t)tiles_x << 16));
     const int64_t oe = min(o + (int64_t)w, n);
     for (int64_t b = (o + kSortTile - 1) / kSortTile; b * kSortTile < oe; ++b) first[b] = k;
     if (oe == n) first[(n + kSortTile - 1) / kSortTile] = k;
     o += w;
     ++k;
+  };
+  const uint4 ru = runs[r];
+  if (ru.x != 0xffffffffu) {
+    const int ty0 = (int)(ru.x & 0xffffu), rows = (int)(ru.x >> 16);
+    const uint32_t rw[3] = {ru.y, ru.z, ru.w};
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      if (q < rows && o < n) put(ty0 + q, (int)(rw[q] & 0xffffu), (int)(rw[q] >> 16));
+    return;
+  }
+  const short4 rc = rect[r];
+  LinGeom G;
+  make_geom(G, B, (int)r, splat + (int64_t)splat_stride4(B) * r, rc, req);
+  const double inv_tw = ldexp(1.0, -__builtin_ctz(B.tile_w));
+  for (int ty = rc.y; ty < rc.w && o < n; ++ty) {
+    int lo, hi;
+    cull_row(G, ty, B.tile_w, B.tile_h, inv_tw, &lo, &hi);
+    if (hi > lo) put(ty, lo, hi);
   }
 }
 
@@ -1420,6 +1450,7 @@ struct BinWs {
   uint32_t* kc;        // [n_rec]   kept pairs per record
   uint32_t* nrow;      // [n_rec]   kept rows per record
   uint32_t* roff;      // [n_rec]   first row record, depth order
+  uint4* runs;         // [n_rec]   kept runs of up to 3 rows (the LinPrim count pass)
   // band binning
   int64_t* n_ent;      // [1] band entries
   int64_t* n_chunk;    // [1] chunks
@@ -1469,6 +1500,7 @@ static BinWs bin_ws_layout(int64_t n_rec, int64_t cap, int64_t tiles, int sort_m
       L.kc = (uint32_t*)take(4 * (size_t)std::max<int64_t>(n_rec, 1));
       L.nrow = (uint32_t*)take(4 * (size_t)std::max<int64_t>(n_rec, 1));
       L.roff = (uint32_t*)take(4 * (size_t)std::max<int64_t>(n_rec, 1));
+      L.runs = (uint4*)take(16 * (size_t)std::max<int64_t>(n_rec, 1));
     }
     if (sort_mode == XPR_SORT_BANDS) {
       const int64_t T1 = std::max<int64_t>(tiles, 1);
@@ -1533,7 +1565,7 @@ hipError_t bin_phase1(const Batch& B, int sort_mode, bool cull, const float* spl
         hipLaunchKernelGGL(k_cull_count_lin, dim3(grid1(n_rec)), dim3(256), 0, st, B,
                            reinterpret_cast<const float4*>(splat),
                            reinterpret_cast<const short4*>(rect), tc, depth, n_rec, pb, L.kc,
-                           L.nrow, L.dkey[0], L.perm[0], lin_req(B));
+                           L.nrow, L.dkey[0], L.perm[0], L.runs, lin_req(B));
       else
         hipLaunchKernelGGL(k_cull_count<RowGeom>, dim3(grid1(n_rec)), dim3(256), 0, st, B,
                            reinterpret_cast<const float4*>(splat),
@@ -1617,7 +1649,8 @@ static hipError_t pair_sort(const Batch& B, int tile_bits, const float* depth, c
     if (B.method == XPR_METHOD_LINPRIM)
       hipLaunchKernelGGL(k_cull_emit_lin, dim3(grid1(n_rec)), dim3(256), 0, st, B,
                          reinterpret_cast<const float4*>(splat), rc, L.tcs, perm, L.offsets,
-                         L.roff, kmask, n_rec, n_isect, cap, L.packed, L.first, lin_req(B));
+                         L.roff, kmask, n_rec, n_isect, cap, L.runs, L.packed, L.first,
+                         lin_req(B));
     else
       hipLaunchKernelGGL(k_cull_emit<RowGeom>, dim3(grid1(n_rec)), dim3(256), 0, st, B,
                          reinterpret_cast<const float4*>(splat), rc, L.tcs, perm, L.offsets,
