@@ -88,6 +88,8 @@ def test_linear_map_rows_are_the_derivatives():
             h = 1e-5
             fd = (f(mu + h * e) - f(mu - h * e)) / (2 * h)
             np.testing.assert_allclose(A[:, k], fd, rtol=1e-6, atol=1e-8)
+        # the sort depth is the Euclidean distance that tau measures
+        assert pr["depth"][i] == pytest.approx(f(mu)[2], rel=1e-13)
 
 
 def test_chord_matches_linear_programming():
