@@ -181,6 +181,9 @@ def main():
                    "autotuned": tuned is not None,
                    "tile_cull": cfg.tile_cull,
                    "opacity_extents": cfg.opacity_extents,
+                   "pair_capacity": run["cap"],
+                   "binning": "no mid-frame readback (grids sized from the capacity of an "
+                              "untimed pass, +10%; counts checked after)",
                    "pairs_per_frame": pairs},
         "stage_sum_ms": round(frame_ms, 4),
         "stages_ms_median": med,
@@ -272,7 +275,10 @@ def timed_frames(scene, cams, cfg, targets, steps, warmup, tile, names):
     loss_buf = torch.empty(1, dtype=torch.float32, device=dev)
     dimg_buf = torch.empty(3 * H * W, dtype=torch.float32, device=dev)
 
-    # Capacity for the pair list: one pass over the cameras, +10%.
+    # Capacity for the pair list: one pass over the cameras, +10%. The timed
+    # frames then bin without reading the pair count back mid-frame (grids
+    # sized from the capacity); every camera's count is checked against the
+    # capacity after the timed region.
     cap = 0
     for v in views:
         R.xpr_project(v, cfg, out=proj)
@@ -281,6 +287,8 @@ def timed_frames(scene, cams, cfg, targets, steps, warmup, tile, names):
     cap = int(cap * 1.1) + 4096
     bins = R.xpr_bin_sort(views[0], cfg, proj, capacity=cap, ws=ws)
     log(f"[bench] pair capacity {cap}")
+    cfg = dataclasses.replace(cfg, no_sync=True)
+    views = [R.Views([scene], [c], [0], cfg) for c in cams]
 
     n_ev = len(names) + 1
     ev_all = [[torch.cuda.Event(enable_timing=True) for _ in range(n_ev)]
@@ -342,6 +350,8 @@ def timed_frames(scene, cams, cfg, targets, steps, warmup, tile, names):
         tmax = pad.view(tiles_y, tile, tiles_x, tile).amax(dim=(1, 3))
         work["fwd"].append(float(tw.sum().item()) * npx)
         work["bwd"].append(float(tmax.sum().item()) * npx)
+        if bins.count > cap:
+            raise RuntimeError(f"camera {k}: {bins.count} pairs exceed the capacity {cap}")
         work["pairs"].append(bins.count)
         work["visible"].append(int((proj.tc[:scene.n] > 0).sum().item()))
     del proj, bins, frame, g2, grads, views, ws
@@ -366,6 +376,10 @@ def timed_forward(scene, cams, cfg, steps, warmup):
         counts.append(R.xpr_bin_sort(v, cfg, proj, ws=ws).count)
     cap = int(max(counts) * 1.1) + 4096
     bins = R.xpr_bin_sort(views[0], cfg, proj, capacity=cap, ws=ws)
+    # timed frames bin without the mid-frame readback (as in timed_frames);
+    # the counts above are deterministic per camera and below the capacity
+    cfg = dataclasses.replace(cfg, no_sync=True)
+    views = [R.Views([scene], [c], [0], cfg) for c in cams]
     frame = None
     names = ["project", "bin_sort", "render_fwd"]
     ev_all = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps + 1)]

@@ -330,6 +330,17 @@ __device__ __forceinline__ int64_t clamp_n(const int64_t* n_dev, int64_t cap) {
   return n < cap ? n : cap;
 }
 
+// Partition of sort block b when the grid holds nblocks blocks but only the
+// first ceil(n / kSortTile) hold items (a grid sized from a capacity): the
+// live blocks are XCD-swizzled among themselves, so every XCD gets its share
+// of the real work, and the rest map to themselves (their digit counts are
+// zero).
+__device__ __forceinline__ int live_swizzle(int b, int nblocks, int64_t n) {
+  const int64_t need = (n + kSortTile - 1) / kSortTile;
+  const int live = need < nblocks ? (int)need : nblocks;
+  return b < live ? xcd_swizzle(b, live) : b;
+}
+
 // Digit counts of one block of kSortTile keys, written digit-major
 // (counts[d * nblocks + b]) for the scan. Eight lane-indexed copies of the
 // histogram keep LDS atomic collisions at most 8-way.
@@ -344,7 +355,7 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys,
   for (int k = t; k < COPIES * RADIX; k += 256) (&h[0][0])[k] = 0;
   __syncthreads();
   const int64_t n = clamp_n(n_dev, cap);
-  const int part = xcd_swizzle(blockIdx.x, nblocks);
+  const int part = live_swizzle(blockIdx.x, nblocks, n);
   const int64_t base = (int64_t)part * kSortTile;
   uint32_t* mine = h[t & (COPIES - 1)];
   if (base < n) {
@@ -421,7 +432,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
   for (int k = t; k < kSortWaves * RADIX; k += 256) (&wcnt[0][0])[k] = 0;
   __syncthreads();
   const int64_t n = clamp_n(n_dev, cap);
-  const int part = xcd_swizzle(blockIdx.x, nblocks);
+  const int part = live_swizzle(blockIdx.x, nblocks, n);
   const int64_t bbase = (int64_t)part * kSortTile;
   if (bbase >= n) return;  // whole block beyond the list: no counts, nothing to write
   const int64_t base = bbase + w * (64 * kSortItems);
@@ -1173,7 +1184,7 @@ __global__ __launch_bounds__(256) void k_pair_hist(const uint4* __restrict__ pac
   const int t = threadIdx.x;
   for (int k = t; k < COPIES * RADIX; k += 256) (&h[0][0])[k] = 0;
   const int64_t n = clamp_n(n_isect, cap);
-  const int part = xcd_swizzle(blockIdx.x, nblocks);
+  const int part = live_swizzle(blockIdx.x, nblocks, n);
   uint32_t* mine = h[t & (COPIES - 1)];
   if ((int64_t)part * kSortTile < n)
     gen_block_pairs<Items>(packed, first, part, n, S, marks, s_wave,
@@ -1208,7 +1219,7 @@ __global__ __launch_bounds__(256) void k_pair_scatter(
   __shared__ uint32_t sval[kSortTilePad];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int64_t n = clamp_n(n_isect, cap);
-  const int part = xcd_swizzle(blockIdx.x, nblocks);
+  const int part = live_swizzle(blockIdx.x, nblocks, n);
   const int64_t bbase = (int64_t)part * kSortTile;
   if (bbase >= n) return;  // whole block beyond the list: no counts, nothing to write
   const int nvalid = (int)min((int64_t)kSortTile, n - bbase);

@@ -131,6 +131,28 @@ def test_capacity_error_and_retry(mode):
     assert torch.equal(small.vals[:I], full.vals[:I]) and torch.equal(small.ranges, full.ranges)
 
 
+@pytest.mark.parametrize("method,cull", [("3dgs", True), ("3dgut", False), ("linprim", False),
+                                         ("linprim", True)])
+def test_no_sync_mode_matches_per_method(method, cull):
+    # a grid sized from 4x the pair count: the live sort blocks are spread over
+    # the XCDs among themselves, the rest only write zero counts
+    sc = _small(4000, seed=8)
+    cam = camera_look_at((-0.3, 0.4, -3.8), 123, 81)
+    a = run_gpu(sc, cam, R.Config(method=method, tile_cull=cull))
+    scene = R.Scene.from_host(sc)
+    cfg = R.Config(no_sync=True, method=method, tile_cull=cull)
+    views = R.Views([scene], [cam], [0], cfg)
+    proj = R.xpr_project(views, cfg)
+    bins = R.xpr_bin_sort(views, cfg, proj, capacity=4 * a["I"])
+    frame = R.xpr_render_fwd(views, cfg, proj, bins)
+    torch.cuda.synchronize()
+    I = int(bins.n_isect.item())
+    assert I == a["I"]
+    assert np.array_equal(bins.vals[:I].cpu().numpy(), a["vals"])
+    assert np.array_equal(bins.ranges[:views.tiles].cpu().numpy(), a["ranges"])
+    assert np.array_equal(views.image(frame.image, 0).cpu().numpy(), a["image"][0])
+
+
 @pytest.mark.parametrize("mode", ["presort", "bands"])
 def test_no_sync_mode_matches(mode):
     sc = _small(4000, seed=7)
