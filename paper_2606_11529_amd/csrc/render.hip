@@ -366,6 +366,17 @@ __device__ __forceinline__ void bwd_tile(const Batch& B, int g, const float4* __
   if (mylast > 0) atomicMax(&s_maxlast, mylast);
   __syncthreads();
   const int end = rg.x + min(s_maxlast, rg.y - rg.x);
+  // A tile whose walk is much longer than the typical few hundred entries
+  // would finish last while sharing its SIMD with lighter waves: its waves
+  // get a higher issue priority (per wave, reset at the end of the tile).
+  // The walk is known here (the last blended position over the tile).
+  const int walk = end - rg.x;
+  if (walk >= 3072)
+    __builtin_amdgcn_s_setprio(3);
+  else if (walk >= 1536)
+    __builtin_amdgcn_s_setprio(2);
+  else if (walk >= 768)
+    __builtin_amdgcn_s_setprio(1);
   int lo = 0;
   // Per-lane sums of the nine gradient terms of staged record kk over this
   // lane's PPT pixels, into g; returns whether any lane of the wave used it.
@@ -463,6 +474,7 @@ __device__ __forceinline__ void bwd_tile(const Batch& B, int g, const float4* __
       reduce_pair(X, Y, ax, ay, grad2d + 9 * (size_t)S.rec[kx], grad2d + 9 * (size_t)S.rec[ky]);
     }
   }
+  __builtin_amdgcn_s_setprio(0);
 }
 
 template <int TW, int TH, int BATCH, int PPT, bool PERSIST>
