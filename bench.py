@@ -158,11 +158,16 @@ def main():
                  f"{pers}>")
     # HBM bytes per launch from the committed counter record, only while the
     # kernel sources are the ones it was taken from
-    from paper_2606_11529_amd.profiling import traffic_of
+    from paper_2606_11529_amd.profiling import traffic_of, valu_busy_of
     traffic = traffic_of(os.path.join(ROOT, "profiles", "hbm_traffic_c3.txt"), kname)
+    # The lockstep evaluation count overstates what the per-wave lists leave
+    # to evaluate, so frac can exceed 1; the hardware counters' VALU busy
+    # fraction of the same kernel (committed summary) is the utilisation.
+    busy = valu_busy_of(os.path.join(ROOT, "profiles", "compositing_sq_c3.md"), kname)
     roof = {"kernel": kname, "bound": "alu", "achieved": stages[dom]["TOP/s"],
             "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": stages[dom]["frac"],
-            "traffic": traffic, "ops_per_launch": ops, "launch_ms": mean[dom]}
+            "traffic": traffic, "ops_per_launch": ops, "launch_ms": mean[dom],
+            "valu_busy_counters": busy}
 
     out = {
         "metric": METRIC, "value": round(ms_wall, 4), "unit": "ms/frame", "n_gpus": 1,

@@ -163,6 +163,38 @@ def traffic_of(path: str, kernel: str) -> Optional[float]:
     return None
 
 
+def valu_busy_of(path: str, kernel: str) -> Optional[float]:
+    """The counter-based VALU busy fraction of ``kernel`` (template arguments
+    without spaces) from a committed instruction-mix summary (a markdown
+    table with a "VALU busy" column), or None when the file is missing, has
+    no such row, or was taken from other kernel sources than the current
+    ones (its ``sources_sha256:`` line)."""
+    try:
+        with open(path) as f:
+            lines = f.read().splitlines()
+    except OSError:
+        return None
+    digest = next((ln.split(":", 1)[1].strip() for ln in lines
+                   if ln.startswith("sources_sha256:")), None)
+    if digest != sources_digest():
+        return None
+    header = None
+    key = kernel.replace(" ", "")
+    for ln in lines:
+        if not ln.startswith("|"):
+            continue
+        cells = [c.strip() for c in ln.strip("|").split("|")]
+        if "VALU busy" in cells:
+            header = cells
+            continue
+        if header and cells and cells[0].strip("`").replace(" ", "") == key:
+            try:
+                return float(cells[header.index("VALU busy")])
+            except (ValueError, IndexError):
+                return None
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
