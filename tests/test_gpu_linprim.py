@@ -145,3 +145,45 @@ def test_linprim_refuses_backward():
     with pytest.raises(L.XprError) as e:
         R.xpr_render_bwd(views, cfg, proj, bins, frame, dimg)
     assert e.value.status == L.XPR_ERR_UNSUPPORTED
+
+
+def test_linprim_cull_empty_and_everything_culled():
+    from synth import scene_config1
+    cam = camera_look_at((0, 0, -4.0), 64, 48)
+    g = run_gpu(scene_config1(10, 0).subset(np.arange(0)), cam,
+                R.Config(method="linprim", tile_cull=True, sh_degree=0))
+    assert g["I"] == 0
+    # a density this low keeps sigma * chord below -log(1 - 1/255) everywhere
+    sc = scene_config1(300, 2)
+    sc.opacities[:] = np.float32(1e-4)
+    cfg = R.Config(method="linprim", tile_cull=True, sh_degree=0)
+    g = run_gpu(sc, cam, cfg)
+    g0 = run_gpu(sc, cam, R.Config(method="linprim", sh_degree=0))
+    assert g0["I"] > 0 and g["I"] == 0
+    check_binning_cull(g, cam, cfg, oracle.tiles(cam, ocfg_of(cfg)))
+    assert np.array_equal(g["image"][0], g0["image"][0])
+
+
+@pytest.mark.parametrize("tile", [8, 16])
+def test_linprim_cull_tile_sizes(tile):
+    sc = scene_clusters(2500, seed=9, n_clusters=5, box=1.2, lo=0.004, hi=0.35)
+    cam = camera_look_at((0.6, 0.3, -3.6), 149, 93)
+    cfg = R.Config(method="linprim", tile_cull=True, tile=tile, sh_degree=1)
+    g = run_gpu(sc, cam, cfg)
+    g0 = run_gpu(sc, cam, R.Config(method="linprim", tile=tile, sh_degree=1))
+    ref = check_binning_cull(g, cam, cfg, oracle.tiles(cam, ocfg_of(cfg)))
+    assert ref["I"] == g0["I"] and g["I"] < g0["I"]
+    _check_forward(g, cam, cfg)
+    assert float(np.abs(g["image"][0] - g0["image"][0]).max()) <= TOL_PIXEL
+    log(f"[L3] tile {tile}: kept {g['I']} of {g0['I']}")
+
+
+def test_linprim_cull_batched_views_equal_single_views():
+    sc = scene_clusters(4000, seed=10, n_clusters=6, box=1.2, lo=0.004, hi=0.3)
+    cams = random_cameras(3, 4, [(64, 48), (97, 61), (128, 96)], radius=4.5)
+    cfg = R.Config(method="linprim", tile_cull=True, sh_degree=1)
+    batch = run_gpu(sc, cams, cfg)
+    for v, cam in enumerate(cams):
+        one = run_gpu(sc, cam, cfg)
+        assert np.array_equal(batch["image"][v], one["image"][0]), v
+        assert np.array_equal(batch["ncontrib"][v], one["ncontrib"][0]), v
