@@ -64,7 +64,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "bench.py runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
@@ -159,11 +159,11 @@ def main():
     # HBM bytes per launch from the committed counter record, only while the
     # kernel sources are the ones it was taken from
     from paper_2606_11529_amd.profiling import traffic_of, valu_busy_of
-    traffic = traffic_of(os.path.join(ROOT, "profiles", "hbm_traffic_c3.txt"), kname)
+    traffic = traffic_of(os.path.join(ROOT, "profiles", "hbm_traffic_3dgs_3M_1600x1064.txt"), kname)
     # The lockstep evaluation count overstates what the per-wave lists leave
     # to evaluate, so frac can exceed 1; the hardware counters' VALU busy
     # fraction of the same kernel (committed summary) is the utilisation.
-    busy = valu_busy_of(os.path.join(ROOT, "profiles", "compositing_sq_c3.md"), kname)
+    busy = valu_busy_of(os.path.join(ROOT, "profiles", "compositing_sq_3dgs_3M_1600x1064.md"), kname)
     roof = {"kernel": kname, "bound": "alu", "achieved": stages[dom]["TOP/s"],
             "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": stages[dom]["frac"],
             "traffic": traffic, "ops_per_launch": ops, "launch_ms": mean[dom],
@@ -431,7 +431,7 @@ def bench_batched(n=2_000_000, n_views=16, reps=5):
 
     t0 = time.time()
     sc = scene_clusters(n, seed=0)
-    cams = random_cameras(n_views, 0, CONFIGS["c4"]["res_set"])
+    cams = random_cameras(n_views, 0, CONFIGS["batched_2M_16views"]["res_set"])
     scene = R.Scene.from_host(sc)
     del sc
     gen = torch.Generator(device="cuda")
@@ -496,7 +496,7 @@ def bench_serving(n_requests=1000):
     from paper_2606_11529_amd import serve as S
     from synth import CONFIGS, request_stream, scene_clusters
 
-    c5 = CONFIGS["c5"]
+    c5 = CONFIGS["serving_4scenes"]
     scenes = {k: R.Scene.from_host(scene_clusters(n, seed=k)) for k, n in enumerate(c5["scenes"])}
     arrivals = request_stream(n_requests + 100, c5["rate_hz"], len(scenes), c5["res_set"])
     cfg = R.Config()

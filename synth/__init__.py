@@ -7,9 +7,9 @@ from .scenes import (  # noqa: F401
     Camera,
     Scene,
     camera_look_at,
-    camera_config1,
+    camera_front,
     random_cameras,
-    scene_config1,
+    scene_uniform_cube,
     scene_clusters,
     request_stream,
     CONFIGS,

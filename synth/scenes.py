@@ -129,7 +129,7 @@ def _finish(rng, means, n, lo, hi, sigma_o, sh_degree, rgb_dc):
     )
 
 
-def scene_config1(n: int = 10_000, seed: int = 0) -> Scene:
+def scene_uniform_cube(n: int = 10_000, seed: int = 0) -> Scene:
     """Means U[-1,1]^3, log-scales U[ln .005, ln .05], opacity sigmoid(N(0,1)),
     RGB U[0,1] as SH degree 0."""
     rng = np.random.default_rng(seed)
@@ -174,7 +174,7 @@ def camera_look_at(pos, width: int, height: int, fov_deg: float = 60.0,
                   width=int(width), height=int(height))
 
 
-def camera_config1(width: int = 256, height: int = 256) -> Camera:
+def camera_front(width: int = 256, height: int = 256) -> Camera:
     return camera_look_at((0.0, 0.0, -4.0), width, height)
 
 
@@ -215,13 +215,13 @@ def request_stream(n_requests: int, rate_hz: float, n_scenes: int,
 
 # The benchmark configurations (sizes only; see the generators above).
 CONFIGS = {
-    "c1": dict(n=10_000, res=(256, 256), sh_degree=0, tile=16),
-    "c2": dict(n=1_000_000, res=(1297, 840), sh_degree=3, tile=16),
-    "c3": dict(n=3_000_000, res=(1600, 1064), sh_degree=3, tile=16, cameras=8),
-    "c4": dict(n=2_000_000, sh_degree=3, cameras=16,
+    "cube_10k_256": dict(n=10_000, res=(256, 256), sh_degree=0, tile=16),
+    "clusters_1M_1297x840": dict(n=1_000_000, res=(1297, 840), sh_degree=3, tile=16),
+    "clusters_3M_1600x1064": dict(n=3_000_000, res=(1600, 1064), sh_degree=3, tile=16, cameras=8),
+    "batched_2M_16views": dict(n=2_000_000, sh_degree=3, cameras=16,
                res_set=[(256, 256), (640, 480), (1297, 840), (1600, 1064),
                         (1920, 1080)]),
-    "c5": dict(scenes=[100_000, 500_000, 1_500_000, 3_000_000], sh_degree=3,
+    "serving_4scenes": dict(scenes=[100_000, 500_000, 1_500_000, 3_000_000], sh_degree=3,
                rate_hz=200.0,
                res_set=[(512, 512), (1280, 720), (1920, 1080)]),
 }

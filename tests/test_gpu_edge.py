@@ -14,7 +14,7 @@ from gpu_util import check_forward, log, ocfg_of, rec9, run_gpu
 from helpers import axis_camera, hand_scene
 from paper_2606_11529_amd import _lib as L
 from paper_2606_11529_amd import renderer as R
-from synth import camera_look_at, random_cameras, scene_clusters, scene_config1
+from synth import camera_look_at, random_cameras, scene_clusters, scene_uniform_cube
 
 pytestmark = pytest.mark.gpu
 
@@ -24,7 +24,7 @@ def _small(n=4000, seed=3, deg=3):
 
 
 def test_empty_scene():
-    sc = scene_config1(10, 0).subset(np.arange(0))
+    sc = scene_uniform_cube(10, 0).subset(np.arange(0))
     cam = camera_look_at((0, 0, -4.0), 40, 30)
     cfg = R.Config(sh_degree=0, bg=(0.25, 0.5, 0.75))
     g = run_gpu(sc, cam, cfg, dimgs=[np.ones((3, 30, 40), np.float32)])

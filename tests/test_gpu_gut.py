@@ -14,7 +14,7 @@ from gpu_util import (cam32, check_binning, check_binning_cull, log, ocfg_of, ru
                       TOL_PIXEL)
 from paper_2606_11529_amd import _lib as L
 from paper_2606_11529_amd import renderer as R
-from synth import camera_config1, camera_look_at, random_cameras, scene_clusters, scene_config1
+from synth import camera_front, camera_look_at, random_cameras, scene_clusters, scene_uniform_cube
 
 pytestmark = pytest.mark.gpu
 
@@ -22,8 +22,8 @@ ULP = 2.0 ** -23
 
 
 def _case(name):
-    if name == "c1_10k_256":
-        return scene_config1(10_000, 0), camera_config1(256, 256), R.Config(sh_degree=0)
+    if name == "cube_10k_256":
+        return scene_uniform_cube(10_000, 0), camera_front(256, 256), R.Config(sh_degree=0)
     if name == "ragged_t8":
         sc = scene_clusters(3000, seed=5, n_clusters=6, box=1.2, lo=0.005, hi=0.4)
         return sc, camera_look_at((0.7, -0.4, -3.2), 77, 45), R.Config(tile=8, sh_degree=3)
@@ -31,13 +31,13 @@ def _case(name):
         sc = scene_clusters(3000, seed=6, n_clusters=6, box=1.2, lo=0.005, hi=0.4, sh_degree=1)
         return (sc, camera_look_at((-0.3, 0.5, -3.9), 101, 67),
                 R.Config(sh_degree=1, opacity_extents=True))
-    if name == "c2_1M_1297x840":
+    if name == "clusters_1M_1297x840":
         sc = scene_clusters(1_000_000, seed=0)
         return sc, random_cameras(1, 0, (1297, 840))[0], R.Config(sh_degree=3)
     raise KeyError(name)
 
 
-CASES = ["c1_10k_256", "ragged_t8", "ragged_t16_ext", "c2_1M_1297x840"]
+CASES = ["cube_10k_256", "ragged_t8", "ragged_t16_ext", "clusters_1M_1297x840"]
 
 
 @functools.lru_cache(maxsize=2)
@@ -121,7 +121,7 @@ def test_gut_binning_and_forward(name):
     log(f"[G2] {name}: I={g['I']} bit-exact, max-abs {emax:.2e}, guard pixels {ng}")
 
 
-@pytest.mark.parametrize("name", ["ragged_t8", "ragged_t16_ext", "c1_10k_256"])
+@pytest.mark.parametrize("name", ["ragged_t8", "ragged_t16_ext", "cube_10k_256"])
 def test_gut_with_cull(name):
     sc, cam, cfg, g = _run(name, cull=True)
     tx, ty = oracle.tiles(cam, ocfg_of(cfg))

@@ -18,7 +18,7 @@ from gpu_util import (cam32, check_binning, check_binning_cull, log, ocfg_of, ru
 from paper_2606_11529_amd import _lib as L
 from paper_2606_11529_amd import renderer as R
 from helpers import axis_camera, hand_scene
-from synth import camera_config1, camera_look_at, random_cameras, scene_clusters, scene_config1
+from synth import camera_front, camera_look_at, random_cameras, scene_clusters, scene_uniform_cube
 
 pytestmark = pytest.mark.gpu
 
@@ -26,8 +26,8 @@ ULP = 2.0 ** -23
 
 
 def _case(name):
-    if name == "c1_10k_256":
-        return scene_config1(10_000, 0), camera_config1(256, 256), R.Config(sh_degree=0)
+    if name == "cube_10k_256":
+        return scene_uniform_cube(10_000, 0), camera_front(256, 256), R.Config(sh_degree=0)
     if name == "ragged_t8":
         sc = scene_clusters(3000, seed=5, n_clusters=6, box=1.2, lo=0.005, hi=0.4)
         return sc, camera_look_at((0.7, -0.4, -3.2), 77, 45), R.Config(tile=8, sh_degree=3)
@@ -42,13 +42,13 @@ def _case(name):
         g[:, 0] += 0.013
         sc = hand_scene(g, [[0.12, 0.09, 0.05]], opac=0.8)
         return sc, axis_camera(150, 97, f=120.0), R.Config(tile=8, sh_degree=0)
-    if name == "c2_1M_1297x840":
+    if name == "clusters_1M_1297x840":
         sc = scene_clusters(1_000_000, seed=0)
         return sc, random_cameras(1, 0, (1297, 840))[0], R.Config(sh_degree=3)
     raise KeyError(name)
 
 
-CASES = ["c1_10k_256", "ragged_t8", "ragged_t16", "axis_grid_t8", "c2_1M_1297x840"]
+CASES = ["cube_10k_256", "ragged_t8", "ragged_t16", "axis_grid_t8", "clusters_1M_1297x840"]
 
 
 @functools.lru_cache(maxsize=1)
@@ -148,13 +148,13 @@ def test_linprim_refuses_backward():
 
 
 def test_linprim_cull_empty_and_everything_culled():
-    from synth import scene_config1
+    from synth import scene_uniform_cube
     cam = camera_look_at((0, 0, -4.0), 64, 48)
-    g = run_gpu(scene_config1(10, 0).subset(np.arange(0)), cam,
+    g = run_gpu(scene_uniform_cube(10, 0).subset(np.arange(0)), cam,
                 R.Config(method="linprim", tile_cull=True, sh_degree=0))
     assert g["I"] == 0
     # a density this low keeps sigma * chord below -log(1 - 1/255) everywhere
-    sc = scene_config1(300, 2)
+    sc = scene_uniform_cube(300, 2)
     sc.opacities[:] = np.float32(1e-4)
     cfg = R.Config(method="linprim", tile_cull=True, sh_degree=0)
     g = run_gpu(sc, cam, cfg)

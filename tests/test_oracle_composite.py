@@ -11,7 +11,7 @@ import pytest
 import oracle
 import oracle.brute as brute
 from helpers import axis_camera, hand_scene
-from synth import camera_look_at, scene_clusters, scene_config1
+from synth import camera_look_at, scene_clusters, scene_uniform_cube
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -86,7 +86,7 @@ def test_two_gaussian_order_closed_form():
 
 
 def _white_scene(n, seed):
-    sc = scene_config1(n, seed)
+    sc = scene_uniform_cube(n, seed)
     sc.sh[0] = np.float32(0.5 / (0.5 / math.sqrt(math.pi)))  # colour exactly ~1
     return sc
 
@@ -121,7 +121,7 @@ def test_bounds_and_invariants():
 def test_tile_size_invariance_low_opacity():
     # (f) with every o < e^4.5/255 the image does not depend on the tile size
     # (alpha >= 1/255 then forces Mahalanobis^2 < 9, inside the 3-sigma rect).
-    sc = scene_config1(600, 3)
+    sc = scene_uniform_cube(600, 3)
     sc.opacities = np.minimum(sc.opacities, np.float32(0.35))
     cam = camera_look_at((0.2, 0.1, -4.0), 70, 52)
     imgs = []
