@@ -146,11 +146,14 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd_gut(
   const double p01 = 2.0 * rd0 * rd1, p02 = 2.0 * rd0 * rd2, p12 = 2.0 * rd1 * rd2;
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   int last = 0;
-  bool done = !inside;
+  // a finished pixel (or one outside the image) carries lift = +inf, which
+  // fails every later test; kept in a vector register (a carried boolean
+  // becomes a lane mask updated by scalar instructions on every record)
+  float lift = inside ? 0.f : __builtin_inff();
   int walked = 0;
   const int stride = splat_stride4(B);
   for (int base = rg.x; base < rg.y; base += kGutBatch) {
-    if (__syncthreads_count(!done) == 0) break;
+    if (__syncthreads_count(lift == 0.f) == 0) break;
     const int nb = min(kGutBatch, rg.y - base);
     walked = nb + (base - rg.x);
     for (int k = threadIdx.x; k < nb; k += NT) {
@@ -183,10 +186,14 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd_gut(
     }
     __syncthreads();
     for (int i0 = 0; i0 < cnt; i0 += 8) {
-      if (__ballot(!done) == 0) break;
+      if (__ballot(lift == 0.f) == 0) break;
       const int iend = min(i0 + 8, cnt);
+      int knext = S.list[wv][i0];
       for (int i = i0; i < iend; ++i) {
-        const int k = S.list[wv][i];
+        // the next list entry is read one step ahead, so the record's reads
+        // do not wait behind the read of its index
+        const int k = knext;
+        if (i + 1 < iend) knext = S.list[wv][i + 1];
         const GutRec& G = S.rec[k];
         const double dot = G.w[0] * rd0 + G.w[1] * rd1 + G.w[2] * rd2;
         const double nrm = G.q[0] * p00 + G.q[1] * p11 + G.q[2] * p22 + G.q[3] * p01 +
@@ -196,7 +203,7 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd_gut(
         rn = fma(rn, fma(-nrm, rn, 1.0), rn);
         rn = fma(rn, fma(-nrm, rn, 1.0), rn);
         const double d2 = fmax(G.ro2 - dot * dot * rn, 0.0);
-        const bool near = !done && d2 < kGutD2Max;
+        const bool near = d2 + (double)lift < kGutD2Max;
         if (__ballot(near) == 0) continue;
         const float resp = __builtin_amdgcn_exp2f(-kGutHalfLog2e * (float)d2);
         const float alpha = fminf(amax, __fmul_rn(G.o, resp));
@@ -209,7 +216,7 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd_gut(
         C2 += G.b * w;
         T = blend ? Tn : T;
         last = blend ? base + k - rg.x + 1 : last;
-        done = done || (use && !blend);
+        lift = (use && !blend) ? __builtin_inff() : lift;
       }
     }
   }

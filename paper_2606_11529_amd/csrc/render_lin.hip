@@ -63,12 +63,15 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd_lin(
   const double fpx = (double)px, fpy = (double)py;
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   int last = 0;
-  bool done = !inside;
+  // a finished pixel (or one outside the image) carries lift = +inf, which
+  // fails every later test; kept in a vector register (a carried boolean
+  // becomes a lane mask updated by scalar instructions on every record)
+  float lift = inside ? 0.f : __builtin_inff();
   int walked = 0;
   const int stride = splat_stride4(B);
   const int x0 = tx * TW, x1 = tx * TW + TW - 1, y0 = ty * TH;
   for (int base = rg.x; base < rg.y; base += kLinBatch) {
-    if (__syncthreads_count(!done) == 0) break;
+    if (__syncthreads_count(lift == 0.f) == 0) break;
     const int nb = min(kLinBatch, rg.y - base);
     walked = nb + (base - rg.x);
     for (int k = threadIdx.x; k < nb; k += NT) {
@@ -121,10 +124,14 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd_lin(
     }
     __syncthreads();
     for (int i0 = 0; i0 < cnt; i0 += 8) {
-      if (__ballot(!done) == 0) break;
+      if (__ballot(lift == 0.f) == 0) break;
       const int iend = min(i0 + 8, cnt);
+      int knext = S.list[wv][i0];
       for (int i = i0; i < iend; ++i) {
-        const int k = S.list[wv][i];
+        // the next list entry is read one step ahead, so the record's reads
+        // do not wait behind the read of its index
+        const int k = knext;
+        if (i + 1 < iend) knext = S.list[wv][i + 1];
         const LinRec& L = S.rec[k];
         const double dx = fpx - L.u, dy = fpy - L.v;
         double chord;
@@ -151,7 +158,7 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd_lin(
           }
           chord = miss ? -1.0 : exit_ - enter;
         }
-        const bool hitp = !done && chord > 0.0;
+        const bool hitp = chord - (double)lift > 0.0;
         if (__ballot(hitp) == 0) continue;
         const float alpha =
             fminf(amax, 1.f - __builtin_amdgcn_exp2f(-L.sigma * kLog2eLin * (float)chord));
@@ -164,7 +171,7 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd_lin(
         C2 += L.bl * w;
         T = blend ? Tn : T;
         last = blend ? base + k - rg.x + 1 : last;
-        done = done || (use && !blend);
+        lift = (use && !blend) ? __builtin_inff() : lift;
       }
     }
   }
