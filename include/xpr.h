@@ -85,7 +85,7 @@ typedef struct xpr_camera {
 
 /* Method constants and tuning knobs. Defaults: xpr_config_default(). */
 typedef struct xpr_config {
-  int32_t tile_w, tile_h; /* 8x8 or 16x16 */
+  int32_t tile_w, tile_h; /* 8x8, 16x16 or 32x32 */
   int32_t lds_batch;      /* Gaussians staged per LDS batch (forward): 64,128,256,512 */
   int32_t sh_degree;      /* 0..3 */
   float lowpass;          /* added to both diagonal entries of cov2D (0.3) */
@@ -97,8 +97,10 @@ typedef struct xpr_config {
   float bg[3];            /* background colour (0, 0, 0) */
   int32_t sort_mode;      /* XPR_SORT_PRESORT, XPR_SORT_FULL or XPR_SORT_BANDS */
   int32_t no_sync;        /* 1: never read back to the host (graph capture) */
-  int32_t fwd_ppt;        /* pixels per thread in the forward: 1, 2 or 4 (16x16 tiles) */
-  int32_t bwd_ppt;        /* pixels per thread in the backward: 1, 2 or 4 (16x16 tiles) */
+  int32_t fwd_ppt;        /* pixels per thread in the forward: 1, 2 or 4 (16x16 tiles;
+                           * 8x8 tiles use 1, 32x32 tiles 4) */
+  int32_t bwd_ppt;        /* pixels per thread in the backward: 1, 2 or 4 (16x16 tiles;
+                           * 8x8 tiles use 1, 32x32 tiles 4) */
   int32_t bwd_lds_batch;  /* LDS batch of the backward (0: same as lds_batch) */
   int32_t persistent;     /* 1: persistent render grids pulling from tile_order */
   int32_t tile_cull;      /* 1: per-(Gaussian, tile) cull in xpr_bin_sort (0) */
@@ -287,7 +289,8 @@ xpr_status xpr_bin_sort(const xpr_views* views, const xpr_config* cfg, const xpr
  * canonical distance at tau_max; skipped unless the response > 0.0113; then
  * alpha = min(alpha_max, o' response) with the gates, stop rule and
  * blending above. Evaluated with d^2 in float64. cfg->lds_batch, fwd_ppt
- * and persistent do not apply (256 / 64 threads per 16x16 / 8x8 tile).
+ * and persistent do not apply (256 / 64 / 1024 threads per 16x16 / 8x8 /
+ * 32x32 tile).
  * XPR_METHOD_LINPRIM (evaluate of listing XPR-LinPrim): the chord of the
  * ray through (x + 1/2, y + 1/2) inside the slabs |n_i . (dx, dy, tau)|
  * <= 1, n_i = c0 +- c1 +- c2, alpha = 1 - exp(-sigma chord) for a

@@ -81,8 +81,8 @@ struct Sizes {
 
 static xpr_status check_config(const xpr_config* c) {
   XPR_CHECK(c != nullptr, "config is NULL");
-  XPR_CHECK((c->tile_w == 8 && c->tile_h == 8) || (c->tile_w == 16 && c->tile_h == 16),
-            "tile size %dx%d not supported (8x8 or 16x16)", c->tile_w, c->tile_h);
+  XPR_CHECK(c->tile_w == c->tile_h && (c->tile_w == 8 || c->tile_w == 16 || c->tile_w == 32),
+            "tile size %dx%d not supported (8x8, 16x16 or 32x32)", c->tile_w, c->tile_h);
   XPR_CHECK(c->lds_batch == 64 || c->lds_batch == 128 || c->lds_batch == 256 || c->lds_batch == 512,
             "lds_batch %d not in {64,128,256,512}", c->lds_batch);
   XPR_CHECK(c->sh_degree >= 0 && c->sh_degree <= 3, "sh_degree %d not in 0..3", c->sh_degree);

@@ -577,6 +577,10 @@ static void launch_render(const Batch& B, int lds_batch, int ppt, const RenderAr
     launch_batch<8, 8, 1>(B, lds_batch, A, bwd, st);
     return;
   }
+  if (B.tile_w == 32) {  // 4 pixels per thread: 256 threads, 4 waves of 8 rows
+    launch_batch<32, 32, 4>(B, lds_batch, A, bwd, st);
+    return;
+  }
   switch (ppt) {
     case 2: launch_batch<16, 16, 2>(B, lds_batch, A, bwd, st); break;
     case 4: launch_batch<16, 16, 4>(B, lds_batch, A, bwd, st); break;

@@ -2,7 +2,7 @@
 // pixel_info and evaluate of the listing "Implementation of XPR-3DGUT".
 //
 // One workgroup per tile, one thread per pixel (256 threads for 16x16
-// tiles, 64 for 8x8). pixel_info: the world-space unit direction rd of the
+// tiles, 64 for 8x8, 1024 for 32x32). pixel_info: the world-space unit direction rd of the
 // ray through (x + 1/2, y + 1/2), once per pixel. evaluate, per list entry:
 // in the Gaussian's canonical frame the ray is ro + tau M rd (ro and
 // M = S^-1 R^T from the record); its closest approach to the centre,
@@ -52,8 +52,10 @@ struct GutRec {
 
 template <int NW>
 struct GutStage {
+  // one bit per wave: 4 waves at 16x16 tiles, 16 at 32x32
+  using mask_t = std::conditional_t<(NW > 8), uint16_t, uint8_t>;
   GutRec rec[kGutBatch];
-  uint8_t mask[kGutBatch];
+  mask_t mask[kGutBatch];
   uint16_t list[NW][kGutBatch];
 };
 
@@ -169,7 +171,8 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd_gut(
       G.q[3] = mm(0, 1); G.q[4] = mm(0, 2); G.q[5] = mm(1, 2);
       G.ro2 = ro[0] * ro[0] + ro[1] * ro[1] + ro[2] * ro[2];
       G.o = q1.y; G.r = q1.z; G.g = q1.w; G.b = q2.x;
-      S.mask[k] = (uint8_t)gut_wave_mask(m, ro, V, tx * TW, tx * TW + TW - 1, ty * TH, RPW, NW);
+      S.mask[k] = (typename GutStage<NW>::mask_t)gut_wave_mask(m, ro, V, tx * TW, tx * TW + TW - 1,
+                                                               ty * TH, RPW, NW);
     }
     __syncthreads();
     // this wave's records of the batch, in list order
@@ -243,6 +246,9 @@ hipError_t launch_render_fwd_gut(const Batch& B, const float* splat, const int32
   if (B.tile_w == 8)
     hipLaunchKernelGGL((k_render_fwd_gut<8, 8>), grid, dim3(64), 0, st, B, sp, vals, rg, image,
                        Tfin, ncon, tile_work, order);
+  else if (B.tile_w == 32)
+    hipLaunchKernelGGL((k_render_fwd_gut<32, 32>), grid, dim3(1024), 0, st, B, sp, vals, rg,
+                       image, Tfin, ncon, tile_work, order);
   else
     hipLaunchKernelGGL((k_render_fwd_gut<16, 16>), grid, dim3(256), 0, st, B, sp, vals, rg,
                        image, Tfin, ncon, tile_work, order);

@@ -2,7 +2,7 @@
 // evaluate of the listing "Implementation of XPR-LinPrim".
 //
 // One workgroup per tile, one thread per pixel (256 threads for 16x16
-// tiles, 64 for 8x8). For pixel (x, y) the offset from the record's
+// tiles, 64 for 8x8, 1024 for 32x32). For pixel (x, y) the offset from the record's
 // projected centre is (dx, dy) = (x + 1/2 - mu_2D) = (x - u, y - v). The
 // octahedron is the intersection of the slabs |n_i . (dx, dy, tau)| <= 1,
 // n_i = c0 +- c1 +- c2 (c_k the rows of A^-1): slab i holds
@@ -37,7 +37,9 @@ struct LinRec {
 template <int NW>
 struct LinStage {
   LinRec rec[kLinBatch];
-  uint8_t mask[kLinBatch];
+  // one bit per wave: 4 waves at 16x16 tiles, 16 at 32x32
+  using mask_t = std::conditional_t<(NW > 8), uint16_t, uint8_t>;
+  mask_t mask[kLinBatch];
   uint16_t list[NW][kLinBatch];
 };
 
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd_lin(
           if (L.v + ey >= r0 && L.v - ey <= r1) msk |= 1u << w;
         }
       }
-      S.mask[k] = (uint8_t)msk;
+      S.mask[k] = (typename LinStage<NW>::mask_t)msk;
     }
     __syncthreads();
     int cnt = 0;
@@ -198,6 +200,9 @@ hipError_t launch_render_fwd_lin(const Batch& B, const float* splat, const int32
   if (B.tile_w == 8)
     hipLaunchKernelGGL((k_render_fwd_lin<8, 8>), grid, dim3(64), 0, st, B, sp, vals, rg, image,
                        Tfin, ncon, tile_work, order);
+  else if (B.tile_w == 32)
+    hipLaunchKernelGGL((k_render_fwd_lin<32, 32>), grid, dim3(1024), 0, st, B, sp, vals, rg,
+                       image, Tfin, ncon, tile_work, order);
   else
     hipLaunchKernelGGL((k_render_fwd_lin<16, 16>), grid, dim3(256), 0, st, B, sp, vals, rg,
                        image, Tfin, ncon, tile_work, order);

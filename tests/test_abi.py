@@ -84,6 +84,13 @@ def test_batch_sizes():
     c.tile_w = c.tile_h = 8
     s = L.xpr_batch_sizes(v, c)
     assert s.tiles == 3 * 9 * 5
+    c.tile_w = c.tile_h = 32
+    s = L.xpr_batch_sizes(v, c)
+    assert s.tiles == 3 * 3 * 2
+    c.tile_h = 16
+    with pytest.raises(L.XprError) as e:
+        L.xpr_batch_sizes(v, c)
+    assert e.value.status == L.XPR_ERR_INVALID_ARG
 
 
 @pytest.mark.parametrize("field,value", [

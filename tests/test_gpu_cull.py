@@ -30,6 +30,9 @@ def _case(name):
     if name == "ragged_t16_b64":
         sc = scene_clusters(3000, seed=6, n_clusters=6, box=1.2, lo=0.005, hi=0.4, sh_degree=1)
         return sc, camera_look_at((-0.3, 0.5, -3.9), 101, 67), R.Config(sh_degree=1, lds_batch=64)
+    if name == "ragged_t32":
+        sc = scene_clusters(4000, seed=7, n_clusters=6, box=1.2, lo=0.005, hi=0.4, sh_degree=2)
+        return sc, camera_look_at((0.4, 0.3, -4.0), 150, 97), R.Config(tile=32, sh_degree=2)
     if name == "clusters_1M_1297x840":
         sc = scene_clusters(1_000_000, seed=0)
         cam = random_cameras(1, 0, (1297, 840))[0]
@@ -37,7 +40,7 @@ def _case(name):
     raise KeyError(name)
 
 
-CASES = ["cube_10k_256", "ragged_t8", "ragged_t16_b64", "clusters_1M_1297x840"]
+CASES = ["cube_10k_256", "ragged_t8", "ragged_t16_b64", "ragged_t32", "clusters_1M_1297x840"]
 
 
 @functools.lru_cache(maxsize=4)

@@ -70,7 +70,9 @@ def test_tile_size_invariance_low_opacity():
     cam = camera_look_at((0.2, -0.4, -4.0), 100, 75)
     a = run_gpu(sc, cam, R.Config(tile=8))
     b = run_gpu(sc, cam, R.Config(tile=16))
+    c = run_gpu(sc, cam, R.Config(tile=32))
     assert np.array_equal(a["image"][0], b["image"][0])
+    assert np.array_equal(a["image"][0], c["image"][0])
 
 
 def test_deterministic_and_order_invariant():

@@ -84,7 +84,9 @@ def test_extents_tile_size_invariance(opaque):
     cam = camera_look_at((0.2, -0.4, -4.0), 100, 75)
     a = run_gpu(sc, cam, R.Config(tile=8, opacity_extents=True))
     b = run_gpu(sc, cam, R.Config(tile=16, opacity_extents=True))
+    c = run_gpu(sc, cam, R.Config(tile=32, opacity_extents=True))
     assert np.array_equal(a["image"][0], b["image"][0])
+    assert np.array_equal(a["image"][0], c["image"][0])
 
 
 def test_extents_with_cull():

@@ -31,13 +31,16 @@ def _case(name):
         sc = scene_clusters(3000, seed=6, n_clusters=6, box=1.2, lo=0.005, hi=0.4, sh_degree=1)
         return (sc, camera_look_at((-0.3, 0.5, -3.9), 101, 67),
                 R.Config(sh_degree=1, opacity_extents=True))
+    if name == "ragged_t32":
+        sc = scene_clusters(4000, seed=7, n_clusters=6, box=1.2, lo=0.005, hi=0.4, sh_degree=2)
+        return sc, camera_look_at((0.4, 0.3, -4.0), 150, 97), R.Config(tile=32, sh_degree=2)
     if name == "clusters_1M_1297x840":
         sc = scene_clusters(1_000_000, seed=0)
         return sc, random_cameras(1, 0, (1297, 840))[0], R.Config(sh_degree=3)
     raise KeyError(name)
 
 
-CASES = ["cube_10k_256", "ragged_t8", "ragged_t16_ext", "clusters_1M_1297x840"]
+CASES = ["cube_10k_256", "ragged_t8", "ragged_t16_ext", "ragged_t32", "clusters_1M_1297x840"]
 
 
 @functools.lru_cache(maxsize=2)
@@ -121,7 +124,7 @@ def test_gut_binning_and_forward(name):
     log(f"[G2] {name}: I={g['I']} bit-exact, max-abs {emax:.2e}, guard pixels {ng}")
 
 
-@pytest.mark.parametrize("name", ["ragged_t8", "ragged_t16_ext", "cube_10k_256"])
+@pytest.mark.parametrize("name", ["ragged_t8", "ragged_t16_ext", "ragged_t32", "cube_10k_256"])
 def test_gut_with_cull(name):
     sc, cam, cfg, g = _run(name, cull=True)
     tx, ty = oracle.tiles(cam, ocfg_of(cfg))

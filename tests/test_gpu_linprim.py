@@ -164,7 +164,7 @@ def test_linprim_cull_empty_and_everything_culled():
     assert np.array_equal(g["image"][0], g0["image"][0])
 
 
-@pytest.mark.parametrize("tile", [8, 16])
+@pytest.mark.parametrize("tile", [8, 16, 32])
 def test_linprim_cull_tile_sizes(tile):
     sc = scene_clusters(2500, seed=9, n_clusters=5, box=1.2, lo=0.004, hi=0.35)
     cam = camera_look_at((0.6, 0.3, -3.6), 149, 93)

@@ -1,8 +1,8 @@
 """Stage-wise parity of the HIP path (through the C-ABI) with the FP64 oracle:
 P1 projection, P2 binning (bit-exact), P3 forward compositing (1e-5
 max-abs), P4 gradients (1e-3 relative), on the small benchmark workload
-(10k Gaussians, 256x256, SH degree 0), ragged images with 8x8 and 16x16
-tiles, and the 1M-Gaussian 1297x840 SH-degree-3 workload."""
+(10k Gaussians, 256x256, SH degree 0), ragged images with 8x8, 16x16 and
+32x32 tiles, and the 1M-Gaussian 1297x840 SH-degree-3 workload."""
 import functools
 
 import numpy as np
@@ -26,6 +26,9 @@ def _case(name):
     if name == "ragged_t16_b64":
         sc = scene_clusters(3000, seed=6, n_clusters=6, box=1.2, lo=0.005, hi=0.2, sh_degree=1)
         return sc, camera_look_at((-0.3, 0.5, -3.9), 101, 67), R.Config(sh_degree=1, lds_batch=64)
+    if name == "ragged_t32":
+        sc = scene_clusters(4000, seed=7, n_clusters=6, box=1.2, lo=0.005, hi=0.4, sh_degree=2)
+        return sc, camera_look_at((0.4, 0.3, -4.0), 150, 97), R.Config(tile=32, sh_degree=2)
     if name == "clusters_1M_1297x840":
         sc = scene_clusters(1_000_000, seed=0)
         cam = random_cameras(1, 0, (1297, 840))[0]
@@ -33,7 +36,7 @@ def _case(name):
     raise KeyError(name)
 
 
-CASES = ["cube_10k_256", "ragged_t8", "ragged_t16_b64", "clusters_1M_1297x840"]
+CASES = ["cube_10k_256", "ragged_t8", "ragged_t16_b64", "ragged_t32", "clusters_1M_1297x840"]
 
 
 @functools.lru_cache(maxsize=2)
