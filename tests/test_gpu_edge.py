@@ -229,14 +229,15 @@ def test_multi_scene_batch(mode):
         assert np.array_equal(views.image(frame.image, v).cpu().numpy(), one["image"][0]), v
 
 
+@pytest.mark.parametrize("tile", [16, 32])
 @pytest.mark.parametrize("persistent", [False, True])
-def test_tile_order_and_persistent_grids_match(persistent):
+def test_tile_order_and_persistent_grids_match(persistent, tile):
     sc = _small(6000, seed=12)
     cams = random_cameras(3, 9, [(96, 64), (130, 77), (48, 48)], radius=4.5)
     rng = np.random.default_rng(0)
     dimgs = [rng.normal(size=(3, c.height, c.width)).astype(np.float32) for c in cams]
-    ref = run_gpu(sc, cams, R.Config(), dimgs=dimgs)
-    cfg = R.Config(persistent=persistent)
+    ref = run_gpu(sc, cams, R.Config(tile=tile), dimgs=dimgs)
+    cfg = R.Config(persistent=persistent, tile=tile)
     scene = R.Scene.from_host(sc)
     views = R.Views([scene], cams, [0] * len(cams), cfg)
     proj = R.xpr_project(views, cfg)
