@@ -383,3 +383,18 @@ def render(scene: Scene, cam, cfg: Config, want_keys: bool = False):
     bins = xpr_bin_sort(views, cfg, proj, want_keys=want_keys)
     frame = xpr_render_fwd(views, cfg, proj, bins)
     return views.image(frame.image, 0), dict(views=views, proj=proj, bins=bins, frame=frame)
+
+
+def render_batch(scene, cams, cfg: Config, view_scene=None):
+    """Many views, one launch per stage: ``scene`` is a Scene or a list of
+    them and view v renders scene ``view_scene[v]`` (default 0), cameras of
+    any sizes. Returns ([image [3,H,W] per view], state dict)."""
+    scenes = list(scene) if isinstance(scene, (list, tuple)) else [scene]
+    cams = list(cams)
+    vs = [0] * len(cams) if view_scene is None else [int(i) for i in view_scene]
+    views = Views(scenes, cams, vs, cfg)
+    proj = xpr_project(views, cfg)
+    bins = xpr_bin_sort(views, cfg, proj)
+    frame = xpr_render_fwd(views, cfg, proj, bins)
+    images = [views.image(frame.image, v) for v in range(len(cams))]
+    return images, dict(views=views, proj=proj, bins=bins, frame=frame)

@@ -73,3 +73,20 @@ def test_overflow_detected_and_resize():
     br.step()
     torch.cuda.synchronize()
     assert not br.overflowed() and int(br.bins.n_isect.item()) == need
+
+
+@pytest.mark.parametrize("tile", [16, 32])
+def test_render_batch_equals_single_views(tile):
+    # two scenes, views of four sizes; every view equals its own render()
+    sa = R.Scene.from_host(scene_clusters(6000, seed=21, n_clusters=6, box=1.4))
+    sb = R.Scene.from_host(scene_clusters(3000, seed=22, n_clusters=4, box=1.0, sh_degree=1))
+    cams = random_cameras(5, 23, [(64, 64), (160, 120), (97, 53), (200, 150)], radius=4.5)
+    vs = [0, 1, 0, 1, 1]
+    cfg = R.Config(tile=tile, sh_degree=1)
+    images, st = R.render_batch([sa, sb], cams, cfg, view_scene=vs)
+    assert len(images) == len(cams)
+    for v, cam in enumerate(cams):
+        one, _ = R.render([sa, sb][vs[v]], cam, cfg)
+        assert images[v].shape == (3, cam.height, cam.width)
+        assert torch.equal(images[v], one), v
+    log(f"[batch] render_batch tile {tile}: {len(cams)} views, I={st['bins'].count}")
