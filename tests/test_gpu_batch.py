@@ -1,6 +1,7 @@
 """Batched multi-view rendering: the graph-captured step replays to the eager
 result (several replays with eager work and synchronisation in between), the
-batch equals per-view plain launches, and the overflow check works."""
+batch equals per-view plain launches, render_batch over two scenes equals
+render() per view (16 and 32 tiles), and the overflow check works."""
 import numpy as np
 import pytest
 import torch
