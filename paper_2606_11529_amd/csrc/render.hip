@@ -3,10 +3,11 @@
 //
 // One workgroup per tile. Each thread owns PPT vertically adjacent pixels of
 // its tile column (a 16x16 tile is 256/PPT threads: four wave64s at PPT=1,
-// one wave64 covering the whole tile at PPT=4). The tile's depth-sorted list
-// is walked in batches of BATCH splat records staged in LDS; every thread
-// reads each record once (an LDS broadcast) and applies it to its PPT
-// pixels, so LDS reads, loop control and, in the backward, the cross-lane
+// one wave64 covering the whole tile at PPT=4; an 8x8 tile is one wave64 at
+// PPT=1, a 32x32 tile four wave64s of 8 rows at PPT=4). The tile's
+// depth-sorted list is walked in batches of BATCH splat records staged in
+// LDS; every thread reads each record once (an LDS broadcast) and applies it
+// to its PPT pixels, so LDS reads, loop control and, in the backward, the cross-lane
 // gradient reduction are shared by PPT pixel evaluations. The workgroup
 // leaves the loop as soon as no pixel is still active, checked once per batch
 // (the batch-boundary exit check of Algorithm 1). The loop body is plain FP32

@@ -217,6 +217,13 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
   if (i < n) p[i] = v;
 }
 
+// Zero fill in 16-byte stores (the backward's gradient buffer: 9 floats per
+// record, a pure write stream).
+__global__ void k_zero_x4(uint4* p, int64_t n4) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n4) p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 __global__ void k_set_i64(int64_t* p, int64_t v) {
   if (threadIdx.x == 0) *p = v;
 }
@@ -2121,7 +2128,15 @@ hipError_t bin_phase2(const Batch& B, int sort_mode, bool cull, const float* spl
 
 hipError_t fill_zero_f32(float* p, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_u32, dim3(grid1(n)), dim3(256), 0, st, (uint32_t*)p, n, 0u);
+  // 16-byte stores over the aligned multiple of 4 floats, then the rest
+  const int64_t n4 = ((uintptr_t)p & 15u) == 0 ? n / 4 : 0;
+  if (n4 > 0)
+    hipLaunchKernelGGL(k_zero_x4, dim3(grid1(n4)), dim3(256), 0, st, reinterpret_cast<uint4*>(p),
+                       n4);
+  const int64_t rest = n - 4 * n4;
+  if (rest > 0)
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid1(rest)), dim3(256), 0, st,
+                       reinterpret_cast<uint32_t*>(p + 4 * n4), rest, 0u);
   return hipGetLastError();
 }
 
