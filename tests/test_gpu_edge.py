@@ -254,3 +254,32 @@ def test_tile_order_and_persistent_grids_match(persistent, tile):
         assert np.array_equal(views.image(frame.image, v).cpu().numpy(), ref["image"][v])
     g2 = g2.cpu().numpy()[:views.records]
     np.testing.assert_allclose(g2, ref["grad2d"], rtol=1e-4, atol=1e-6 * np.abs(ref["grad2d"]).max())
+
+
+@pytest.mark.parametrize("offset", [0, 1, 2, 3])
+def test_backward_gradient_buffer_any_alignment(offset):
+    # grad2d given by the caller at every 4-byte offset from a 16-byte
+    # boundary and prefilled with NaN, over a record count whose 9 floats per
+    # record leave a tail: the backward's zero fill covers the buffer exactly
+    # and the gradients equal those in its own aligned buffer
+    sc = _small(2999, seed=13)
+    cam = camera_look_at((0.3, -0.2, -4.0), 90, 70)
+    cfg = R.Config()
+    scene = R.Scene.from_host(sc)
+    views = R.Views([scene], [cam], [0], cfg)
+    proj = R.xpr_project(views, cfg)
+    bins = R.xpr_bin_sort(views, cfg, proj)
+    frame = R.xpr_render_fwd(views, cfg, proj, bins)
+    dimg = torch.from_numpy(np.random.default_rng(2).normal(
+        size=3 * views.pixels).astype(np.float32)).cuda()
+    _, ref = R.xpr_render_bwd(views, cfg, proj, bins, frame, dimg, params=False)
+    n = views.records
+    assert (9 * n) % 4 != 0
+    buf = torch.full((9 * n + 8,), float("nan"), dtype=torch.float32, device="cuda")
+    g2 = buf[offset:offset + 9 * n].view(n, 9)
+    R.xpr_render_bwd(views, cfg, proj, bins, frame, dimg, params=False, grad2d=g2)
+    torch.cuda.synchronize()
+    assert torch.isfinite(g2).all()
+    assert torch.isnan(buf[:offset]).all() and torch.isnan(buf[offset + 9 * n:]).all()
+    np.testing.assert_allclose(g2.cpu().numpy(), ref[:n].cpu().numpy(), rtol=1e-5,
+                               atol=1e-6 * float(ref.abs().max()))
