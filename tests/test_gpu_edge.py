@@ -1,8 +1,9 @@
 """Edge cases and invariances of the HIP path through the C-ABI: empty and
 fully culled scenes, background colour, LDS batch size and sort strategy
 independence, tile-size invariance at low opacity, determinism, order
-invariance, capacity handling (host retry and the no-readback mode), and
-batched views against single views."""
+invariance, capacity handling (host retry and the no-readback mode),
+batched views against single views, longest-first and persistent launches
+at 16 and 32 tiles, and caller gradient buffers at any 4-byte alignment."""
 import ctypes
 
 import numpy as np
