@@ -77,7 +77,7 @@ def lib():
         L.orc_tile_cull.argtypes = [i64, P, i32, P, i32, i32, i32, i32, ctypes.c_double, i32, P,
                                     P, P, P]
         L.orc_tile_cull.restype = None
-        L.orc_render_fwd.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P, P, P, P]
+        L.orc_render_fwd.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_render_fwd.restype = None
         L.orc_render_bwd.argtypes = [i32, i32, i32, i32, i64, P, P, P, P, P, P]
         L.orc_render_bwd.restype = None
@@ -101,6 +101,8 @@ def lib():
         L.orc_sh_basis.argtypes = [i32, P, P, P]
         L.orc_sh_basis.restype = None
         L.orc_num_threads.restype = i32
+        L.orc_set_num_threads.argtypes = [i32]
+        L.orc_set_num_threads.restype = None
         _LIB = L
     return _LIB
 
@@ -127,6 +129,11 @@ def tiles(cam, cfg: OracleConfig):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of the oracle's later parallel loops."""
+    lib().orc_set_num_threads(int(n))
 
 
 def sh_basis(deg: int, d, grad: bool = False):
@@ -291,7 +298,16 @@ def tile_cull(rec, txy, W: int, H: int, cfg: OracleConfig):
 
 def render_fwd(rec, vals, ranges, W: int, H: int, cfg: OracleConfig, cam=None):
     """Compositing (Algorithm 1 with the 3DGS evaluate, or with the 3DGUT
-    pixel_info and evaluate when rec has 21 columns; cam is then needed)."""
+    pixel_info and evaluate when rec has 21 columns; cam is then needed).
+
+    3DGS also returns, per pixel: ``neval`` the list entries it evaluates
+    (up to and including the one that stops it, else the whole list);
+    ``tsens`` the sensitivity of T_final to a float32 evaluation, in units
+    of 2^-24 (1 plus, per blended entry, alpha/(1-alpha) (7 S + 3) + 2 with S
+    the sum of the absolute power terms; a clamped alpha adds 2 only);
+    ``amb`` [2][H][W] the ambiguous contribution of guard pixels: the
+    largest colour change, and the T change, summed over re-walks that each
+    invert one guard-band decision (0 elsewhere)."""
     rec = _f64(rec)
     if rec.shape[1] == 21:
         return render_fwd_gut(rec, vals, ranges, cam, cfg)
@@ -301,11 +317,13 @@ def render_fwd(rec, vals, ranges, W: int, H: int, cfg: OracleConfig, cam=None):
     ranges = np.ascontiguousarray(ranges, np.int32)
     out = dict(img=np.zeros((3, H, W)), Tfinal=np.zeros((H, W)),
                ncontrib=np.zeros((H, W), np.int32), nblend=np.zeros((H, W), np.int32),
-               guard=np.zeros((H, W), np.uint8))
+               guard=np.zeros((H, W), np.uint8), neval=np.zeros((H, W), np.int32),
+               tsens=np.zeros((H, W)), amb=np.zeros((2, H, W)))
     rc = cfg.render_cfg()
     lib().orc_render_fwd(W, H, cfg.tile_w, cfg.tile_h, _p(rec), _p(vals), _p(ranges), _p(rc),
                          _p(out["img"]), _p(out["Tfinal"]), _p(out["ncontrib"]),
-                         _p(out["nblend"]), _p(out["guard"]))
+                         _p(out["nblend"]), _p(out["guard"]), _p(out["neval"]),
+                         _p(out["tsens"]), _p(out["amb"]))
     return out
 
 

@@ -738,6 +738,15 @@ int orc_num_threads(void) {
 #endif
 }
 
+// Threads of the later parallel regions (n >= 1).
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n < 1 ? 1 : n);
+#else
+  (void)n;
+#endif
+}
+
 // Real SH basis values (and gradients w.r.t. the direction if dY != NULL) at
 // a unit direction d. Y has (deg+1)^2 entries, dY 3 per entry.
 void orc_sh_basis(int deg, const double* d, double* Y, double* dY) {
@@ -892,50 +901,109 @@ void orc_tile_cull(int64_t m, const double* rec, int rec_stride, const int32_t* 
 //   stop (without blending) if T (1 - alpha) < t_min; else C += c alpha T,
 //   T *= 1 - alpha.
 // Output C + T bg.
-//   rec [n][9], vals, ranges as produced by orc_bin
-//   cfg: alpha_min, alpha_max, t_min, bg0, bg1, bg2
+//
+// A decision is in the guard band when its operand lies within a small band
+// of its threshold (|P| <= 1e-6, |alpha - alpha_min| <= 1e-4 alpha_min,
+// |T (1 - alpha) - t_min| <= 1e-3 t_min): a float32 evaluation may take it
+// either way. For a pixel with such decisions the walk is repeated once per
+// decision with that decision alone inverted; the largest change of any
+// colour channel (and of T) summed over these walks is the pixel's
+// ambiguous contribution.
+struct PixelWalk {
+  double C[3], T;
+  int32_t last, count, neval, nguard;
+  double tsens;  // sum over blended entries of alpha/(1-alpha) (7 S + 3) + 2
+};
+
+// flip: ordinal of the guard decision to invert (-1: none).
+static PixelWalk walk_pixel(int px, int py, const double* rec, const int32_t* vals, int32_t start,
+                     int32_t end, double alpha_min, double alpha_max, double t_min, int flip) {
+  PixelWalk w{{0, 0, 0}, 1.0, 0, 0, 0, 0, 1.0};
+  auto decide = [&](bool near, bool value) {
+    if (!near) return value;
+    return (w.nguard++ == flip) ? !value : value;
+  };
+  w.neval = end - start;
+  for (int32_t k = start; k < end; ++k) {
+    const double* r = rec + 9 * (int64_t)vals[k];
+    const double dx = px - r[0], dy = py - r[1];
+    const double t0 = r[2] * dx * dx, t1 = r[3] * dx * dy, t2 = r[4] * dy * dy;
+    const double P = t0 + t1 + t2;
+    if (decide(std::fabs(P) <= 1e-6, P > 0)) continue;
+    const double raw = r[5] * std::exp(P);
+    const double alpha = std::min(alpha_max, raw);
+    if (decide(std::fabs(alpha - alpha_min) <= 1e-4 * alpha_min, alpha < alpha_min)) continue;
+    const double Tn = w.T * (1.0 - alpha);
+    if (decide(std::fabs(Tn - t_min) <= 1e-3 * t_min, Tn < t_min)) {
+      w.neval = k - start + 1;
+      break;
+    }
+    for (int c = 0; c < 3; ++c) w.C[c] += r[6 + c] * alpha * w.T;
+    // Sensitivity of T to float32 evaluation (in units of the float32 unit
+    // roundoff u = 2^-24): alpha carries a relative error of at most about
+    // 7u times the sum of the absolute power terms plus 3u (the roundings of
+    // dx, dy, the products and sums of the power, exp and the opacity
+    // product), amplified by alpha / (1 - alpha) in 1 - alpha; the update of
+    // T adds two roundings. A clamped alpha is the constant alpha_max.
+    const double S = std::fabs(t0) + std::fabs(t1) + std::fabs(t2);
+    w.tsens += (raw >= alpha_max ? 0.0 : alpha / (1.0 - alpha) * (7.0 * S + 3.0)) + 2.0;
+    w.T = Tn;
+    w.last = k - start + 1;
+    ++w.count;
+  }
+  return w;
+}
+
+// rec [n][9], vals, ranges as produced by orc_bin
+// cfg: alpha_min, alpha_max, t_min, bg0, bg1, bg2
+// Outputs (all but img may be NULL):
 //   img [3][H][W], Tfinal [H][W], ncontrib [H][W] (1-based position of the
 //   last blended entry, 0 if none), nblend [H][W] (number blended),
-//   guard [H][W] (1 where a decision sits within the guard band; may be NULL)
+//   guard [H][W] (1 where a decision sits within the guard band),
+//   neval [H][W] (list entries the pixel evaluates: the position of the
+//   entry that stops it, else the list length),
+//   tsens [H][W] (the sensitivity above, in units of 2^-24),
+//   amb [2][H][W] (ambiguous contribution: colour, then T; 0 off the guard
+//   band).
 void orc_render_fwd(int W, int H, int tile_w, int tile_h, const double* rec, const int32_t* vals,
                     const int32_t* ranges, const double* cfg, double* img, double* Tfinal,
-                    int32_t* ncontrib, int32_t* nblend, uint8_t* guard) {
+                    int32_t* ncontrib, int32_t* nblend, uint8_t* guard, int32_t* neval,
+                    double* tsens, double* amb) {
   const double alpha_min = cfg[0], alpha_max = cfg[1], t_min = cfg[2];
   const double bg[3] = {cfg[3], cfg[4], cfg[5]};
   const int tiles_x = (W + tile_w - 1) / tile_w;
   const int tiles_y = (H + tile_h - 1) / tile_h;
+  const int64_t WH = (int64_t)W * H;
 #pragma omp parallel for schedule(dynamic, 1)
   for (int t = 0; t < tiles_x * tiles_y; ++t) {
     const int tx = t % tiles_x, ty = t / tiles_x;
     const int32_t start = ranges[2 * t], end = ranges[2 * t + 1];
     for (int py = ty * tile_h; py < std::min(H, (ty + 1) * tile_h); ++py)
       for (int px = tx * tile_w; px < std::min(W, (tx + 1) * tile_w); ++px) {
-        double T = 1.0, C[3] = {0, 0, 0};
-        int32_t last = 0, count = 0;
-        bool g = false;
-        for (int32_t k = start; k < end; ++k) {
-          const double* r = rec + 9 * (int64_t)vals[k];
-          const double dx = px - r[0], dy = py - r[1];
-          const double P = r[2] * dx * dx + r[3] * dx * dy + r[4] * dy * dy;
-          if (std::fabs(P) <= 1e-6) g = true;
-          if (P > 0) continue;
-          const double alpha = std::min(alpha_max, r[5] * std::exp(P));
-          if (std::fabs(alpha - alpha_min) <= 1e-4 * alpha_min) g = true;
-          if (alpha < alpha_min) continue;
-          const double Tn = T * (1.0 - alpha);
-          if (std::fabs(Tn - t_min) <= 1e-3 * t_min) g = true;
-          if (Tn < t_min) break;
-          for (int c = 0; c < 3; ++c) C[c] += r[6 + c] * alpha * T;
-          T = Tn;
-          last = k - start + 1;
-          ++count;
-        }
+        const PixelWalk w =
+            walk_pixel(px, py, rec, vals, start, end, alpha_min, alpha_max, t_min, -1);
         const int64_t p = (int64_t)py * W + px;
-        for (int c = 0; c < 3; ++c) img[(int64_t)c * W * H + p] = C[c] + T * bg[c];
-        if (Tfinal) Tfinal[p] = T;
-        if (ncontrib) ncontrib[p] = last;
-        if (nblend) nblend[p] = count;
-        if (guard) guard[p] = g ? 1 : 0;
+        for (int c = 0; c < 3; ++c) img[(int64_t)c * WH + p] = w.C[c] + w.T * bg[c];
+        if (Tfinal) Tfinal[p] = w.T;
+        if (ncontrib) ncontrib[p] = w.last;
+        if (nblend) nblend[p] = w.count;
+        if (guard) guard[p] = w.nguard > 0 ? 1 : 0;
+        if (neval) neval[p] = w.neval;
+        if (tsens) tsens[p] = w.tsens;
+        if (amb) {
+          double ac = 0.0, at = 0.0;
+          for (int f = 0; f < w.nguard; ++f) {
+            const PixelWalk v =
+                walk_pixel(px, py, rec, vals, start, end, alpha_min, alpha_max, t_min, f);
+            double d = 0.0;
+            for (int c = 0; c < 3; ++c)
+              d = std::max(d, std::fabs((v.C[c] + v.T * bg[c]) - (w.C[c] + w.T * bg[c])));
+            ac += d;
+            at += std::fabs(v.T - w.T);
+          }
+          amb[p] = ac;
+          amb[WH + p] = at;
+        }
       }
   }
 }
