@@ -303,7 +303,18 @@ xpr_status xpr_render_fwd(const xpr_views* views, const xpr_config* cfg, const x
 /* Workspace bytes xpr_render_bwd needs (per-record 2D gradients). */
 xpr_status xpr_render_bwd_workspace(const xpr_views* views, const xpr_config* cfg, size_t* bytes);
 
-/* Backward of compositing and projection. Given dL/dimage (laid out like
+/* Backward of compositing and projection: the derivative of the blending
+ * sum of the Background section, c(x, y) = sum_i c_i a_i T_i with
+ * T_i = prod_{j<i} (1 - a_j), through evaluate and project of the listing
+ * "Implementation of XPR-3DGS". The paper obtains this derivative by
+ * automatic differentiation of its four interface functions (section Key
+ * Interfaces: gradients flow through project, tile_cull, pixel_info and
+ * evaluate); here it is written out, with the gates, the stop rule and the
+ * rect rounding piecewise constant (zero derivative) and the clamps
+ * (alpha <= alpha_max, colour >= 0, the Jacobian clamp) differentiated on
+ * the side they take, which is what automatic differentiation of the
+ * forward gives.
+ * Given dL/dimage (laid out like
  * image) and the forward's T_final and n_contrib, accumulates the gradient of
  * L with respect to every scene's parameters, summed over the views that
  * render it:
@@ -323,7 +334,11 @@ xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const x
                           int32_t accumulate, float* grad2d, void* ws, size_t ws_bytes,
                           hipStream_t stream);
 
-/* Backward of the projection alone: from grad2d [records][9] (as written by
+/* Backward of the projection alone (the derivative of project of the listing
+ * "Implementation of XPR-3DGS" -- world to camera, R(q) S^2 R(q)^T, the EWA
+ * covariance with its low-pass, the conic, mean2D and the SH colour of the
+ * Background section -- obtained in the paper by automatic differentiation,
+ * section Key Interfaces): from grad2d [records][9] (as written by
  * xpr_render_bwd) to the parameter gradients of every scene, summed over the
  * views that render it (one thread per Gaussian loops over those views, so
  * the sum is deterministic). Records with tiles_touched == 0 contribute
