@@ -87,7 +87,7 @@ def lib():
         L.orc_project_gut.argtypes = [i64, P, P, P, P, P, P, i32, i32, P, i32, i32, i32,
                                       P, P, P, P, P, P]
         L.orc_project_gut.restype = None
-        L.orc_render_fwd_gut.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P, P, P, P, P]
+        L.orc_render_fwd_gut.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_render_fwd_gut.restype = None
         L.orc_gut_response.argtypes = [i64, P, P, P, i32, i32, P]
         L.orc_gut_response.restype = None
@@ -96,7 +96,7 @@ def lib():
         L.orc_project_lin.restype = None
         L.orc_lin_chord.argtypes = [i64, P, P, P]
         L.orc_lin_chord.restype = None
-        L.orc_render_fwd_lin.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P, P, P, P]
+        L.orc_render_fwd_lin.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P, P, P, P, P]
         L.orc_render_fwd_lin.restype = None
         L.orc_sh_basis.argtypes = [i32, P, P, P]
         L.orc_sh_basis.restype = None
@@ -212,16 +212,18 @@ def lin_chord(rec17, pxy):
 
 
 def render_fwd_lin(rec, vals, ranges, W: int, H: int, cfg: OracleConfig):
-    """LinPrim compositing (Algorithm 1 with the XPR-LinPrim evaluate)."""
+    """LinPrim compositing (Algorithm 1 with the XPR-LinPrim evaluate);
+    ``neval`` as for 3DGS."""
     rec = _f64(rec)
     vals = np.ascontiguousarray(vals, np.int32)
     ranges = np.ascontiguousarray(ranges, np.int32)
     out = dict(img=np.zeros((3, H, W)), Tfinal=np.zeros((H, W)),
                ncontrib=np.zeros((H, W), np.int32), nblend=np.zeros((H, W), np.int32),
-               guard=np.zeros((H, W), np.uint8))
+               guard=np.zeros((H, W), np.uint8), neval=np.zeros((H, W), np.int32))
     lib().orc_render_fwd_lin(W, H, cfg.tile_w, cfg.tile_h, _p(rec), _p(vals), _p(ranges),
                              _p(cfg.render_cfg()), _p(out["img"]), _p(out["Tfinal"]),
-                             _p(out["ncontrib"]), _p(out["nblend"]), _p(out["guard"]))
+                             _p(out["ncontrib"]), _p(out["nblend"]), _p(out["guard"]),
+                             _p(out["neval"]))
     return out
 
 
@@ -329,18 +331,18 @@ def render_fwd(rec, vals, ranges, W: int, H: int, cfg: OracleConfig, cam=None):
 
 def render_fwd_gut(rec, vals, ranges, cam, cfg: OracleConfig):
     """3DGUT compositing (Algorithm 1 with the XPR-3DGUT pixel_info and
-    evaluate)."""
+    evaluate); ``neval`` as for 3DGS."""
     rec = _f64(rec)
     W, H = cam.width, cam.height
     vals = np.ascontiguousarray(vals, np.int32)
     ranges = np.ascontiguousarray(ranges, np.int32)
     out = dict(img=np.zeros((3, H, W)), Tfinal=np.zeros((H, W)),
                ncontrib=np.zeros((H, W), np.int32), nblend=np.zeros((H, W), np.int32),
-               guard=np.zeros((H, W), np.uint8))
+               guard=np.zeros((H, W), np.uint8), neval=np.zeros((H, W), np.int32))
     lib().orc_render_fwd_gut(W, H, cfg.tile_w, cfg.tile_h, _p(rec), _p(vals), _p(ranges),
                              _p(cam_vec(cam)), _p(cfg.render_cfg()), _p(out["img"]),
                              _p(out["Tfinal"]), _p(out["ncontrib"]), _p(out["nblend"]),
-                             _p(out["guard"]))
+                             _p(out["guard"]), _p(out["neval"]))
     return out
 
 

@@ -1047,7 +1047,7 @@ void orc_project_gut(int64_t n, const double* means, const double* scales, const
 void orc_render_fwd_gut(int W, int H, int tile_w, int tile_h, const double* rec,
                         const int32_t* vals, const int32_t* ranges, const double* camv,
                         const double* cfg, double* img, double* Tfinal, int32_t* ncontrib,
-                        int32_t* nblend, uint8_t* guard) {
+                        int32_t* nblend, uint8_t* guard, int32_t* neval) {
   const Cam cam = read_cam(camv, W, H);
   const double alpha_min = cfg[0], alpha_max = cfg[1], t_min = cfg[2];
   const double bg[3] = {cfg[3], cfg[4], cfg[5]};
@@ -1063,7 +1063,7 @@ void orc_render_fwd_gut(int W, int H, int tile_w, int tile_h, const double* rec,
         double rd[3];
         gut_ray(cam, px, py, rd);
         double T = 1.0, C[3] = {0, 0, 0};
-        int32_t last = 0, count = 0;
+        int32_t last = 0, count = 0, ne = end - start;
         bool g = false;
         for (int32_t k = start; k < end; ++k) {
           const double* r = rec + 21 * (int64_t)vals[k];
@@ -1075,7 +1075,10 @@ void orc_render_fwd_gut(int W, int H, int tile_w, int tile_h, const double* rec,
           if (alpha < alpha_min) continue;
           const double Tn = T * (1.0 - alpha);
           if (std::fabs(Tn - t_min) <= 1e-3 * t_min) g = true;
-          if (Tn < t_min) break;
+          if (Tn < t_min) {
+            ne = k - start + 1;
+            break;
+          }
           for (int c = 0; c < 3; ++c) C[c] += r[6 + c] * alpha * T;
           T = Tn;
           last = k - start + 1;
@@ -1087,6 +1090,7 @@ void orc_render_fwd_gut(int W, int H, int tile_w, int tile_h, const double* rec,
         if (ncontrib) ncontrib[p] = last;
         if (nblend) nblend[p] = count;
         if (guard) guard[p] = g ? 1 : 0;
+        if (neval) neval[p] = ne;
       }
   }
 }
@@ -1146,7 +1150,7 @@ void orc_lin_chord(int64_t m, const double* rec, const int32_t* pxy, double* out
 void orc_render_fwd_lin(int W, int H, int tile_w, int tile_h, const double* rec,
                         const int32_t* vals, const int32_t* ranges, const double* cfg,
                         double* img, double* Tfinal, int32_t* ncontrib, int32_t* nblend,
-                        uint8_t* guard) {
+                        uint8_t* guard, int32_t* neval) {
   const double alpha_min = cfg[0], alpha_max = cfg[1], t_min = cfg[2];
   const double bg[3] = {cfg[3], cfg[4], cfg[5]};
   const int tiles_x = (W + tile_w - 1) / tile_w;
@@ -1158,7 +1162,7 @@ void orc_render_fwd_lin(int W, int H, int tile_w, int tile_h, const double* rec,
     for (int py = ty * tile_h; py < std::min(H, (ty + 1) * tile_h); ++py)
       for (int px = tx * tile_w; px < std::min(W, (tx + 1) * tile_w); ++px) {
         double T = 1.0, C[3] = {0, 0, 0};
-        int32_t last = 0, count = 0;
+        int32_t last = 0, count = 0, ne = end - start;
         bool g = false;
         for (int32_t k = start; k < end; ++k) {
           const double* r = rec + 17 * (int64_t)vals[k];
@@ -1169,7 +1173,10 @@ void orc_render_fwd_lin(int W, int H, int tile_w, int tile_h, const double* rec,
           if (alpha < alpha_min) continue;
           const double Tn = T * (1.0 - alpha);
           if (std::fabs(Tn - t_min) <= 1e-3 * t_min) g = true;
-          if (Tn < t_min) break;
+          if (Tn < t_min) {
+            ne = k - start + 1;
+            break;
+          }
           for (int c = 0; c < 3; ++c) C[c] += r[3 + c] * alpha * T;
           T = Tn;
           last = k - start + 1;
@@ -1181,6 +1188,7 @@ void orc_render_fwd_lin(int W, int H, int tile_w, int tile_h, const double* rec,
         if (ncontrib) ncontrib[p] = last;
         if (nblend) nblend[p] = count;
         if (guard) guard[p] = g ? 1 : 0;
+        if (neval) neval[p] = ne;
       }
   }
 }
