@@ -14,6 +14,8 @@ from paper_2606_11529_amd import renderer as R
 
 TOL_PIXEL = 1e-5     # max-abs on FP32 pixel colours
 TOL_GRAD = 1e-3      # relative on gradients
+U32 = 2.0 ** -24     # float32 unit roundoff
+T_SAFETY = 2.0      # slack on the first-order T_final rounding bound
 
 
 def log(*a):
@@ -191,14 +193,26 @@ def check_forward(gpu, cam, cfg, v=0, ranges=None, pixel_mask=None):
     emax = float(err.max(initial=0))
     assert emax <= TOL_PIXEL, f"pixel max-abs {emax} > {TOL_PIXEL}"
     assert np.array_equal(gpu["ncontrib"][v][sel], ref["ncontrib"][sel]), "n_contrib differs"
-    # absolute, like the colour: after a Gaussian with alpha near alpha_max the
-    # relative error of T is amplified by 1 / (1 - alpha) ~ 100
-    terr = np.abs(gpu["Tfinal"][v][sel] - ref["Tfinal"][sel])
-    assert terr.max(initial=0) <= TOL_PIXEL, f"T_final abs err {terr.max()}"
+    # T_final relative to the oracle's per-pixel float32 sensitivity (its
+    # tsens, in units of 2^-24: the alpha roundings amplified by
+    # alpha / (1 - alpha), plus two roundings per update), with a factor
+    # T_SAFETY for the rounding of the staged base-2 conic and second-order
+    # terms; relative, so a T near t_min is held to the same precision.
+    tref = ref["Tfinal"][sel]
+    tb = T_SAFETY * ref["tsens"][sel] * U32 * tref
+    tr = np.abs(gpu["Tfinal"][v][sel] - tref) / tb
+    assert tr.max(initial=0) <= 1.0, f"T_final error {tr.max()} x its rounding bound"
     gsel = guard if pixel_mask is None else (guard & pixel_mask)
     if gsel.any():
-        gerr = np.abs(img - ref["img"])[:, gsel].max()
-        assert gerr <= 1e-2, f"guard pixel error {gerr}"
+        # a guard pixel may take any of its ambiguous decisions either way:
+        # its colour and T may move by its ambiguous contribution (summed
+        # over single flips) on top of the non-guard tolerance
+        gerr = np.abs(img - ref["img"])[:, gsel].max(axis=0)
+        gb = ref["amb"][0][gsel] + TOL_PIXEL
+        assert np.all(gerr <= gb), f"guard pixel error {(gerr / gb).max()} x its ambiguous bound"
+        terr = np.abs(gpu["Tfinal"][v][gsel] - ref["Tfinal"][gsel])
+        tgb = ref["amb"][1][gsel] + T_SAFETY * ref["tsens"][gsel] * U32 * ref["Tfinal"][gsel]
+        assert np.all(terr <= tgb), f"guard pixel T error {(terr / tgb).max()} x bound"
     return emax, int(gsel.sum()), ref
 
 
