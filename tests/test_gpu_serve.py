@@ -1,12 +1,17 @@
 """Serving on the GPU: requests of several scenes and resolutions batched by
-the continuous-batching server (overlapping on two streams, admitted under a
-memory budget) return exactly the image each request gets when rendered
-alone."""
+the continuous-batching server (overlapping on two streams, admitted from a
+budget pool) return exactly the image each request gets when rendered
+alone, and every served image matches the FP64 oracle run on the records
+and pair lists its batch rendered it from (projection P1, binning P2
+bit-exact, compositing P3). The server's device memory stays within the
+resident scenes plus its budget, also when pair lists outgrow their
+estimate and batches run again."""
 import numpy as np
 import pytest
 import torch
 
-from gpu_util import log
+import oracle
+from gpu_util import check_forward, check_projection, log, ocfg_of
 from paper_2606_11529_amd import renderer as R
 from paper_2606_11529_amd import serve as S
 from synth import random_cameras, scene_clusters
@@ -14,16 +19,12 @@ from synth import random_cameras, scene_clusters
 pytestmark = pytest.mark.gpu
 
 
-def test_each_result_same_alone_and_in_the_mix():
+def _scenes():
     hosts = {0: scene_clusters(20_000, seed=0, n_clusters=8), 1: scene_clusters(60_000, seed=1)}
-    scenes = {k: R.Scene.from_host(v) for k, v in hosts.items()}
-    cfg = R.Config()
-    rng = np.random.default_rng(3)
-    res = [(128, 96), (200, 120), (96, 160), (64, 64)]
-    cams = random_cameras(24, 11, res)
-    sids = rng.integers(0, 2, size=len(cams)).tolist()
-    budget = 64 << 20   # forces several batches
-    srv = S.Server(scenes, cfg, budget, max_views=6, slots=2)
+    return hosts, {k: R.Scene.from_host(v) for k, v in hosts.items()}
+
+
+def _requests(srv, cams, sids):
     reqs = []
     for k, (sid, cam) in enumerate(zip(sids, cams)):
         reqs.append(srv.submit(sid, cam))
@@ -31,10 +32,67 @@ def test_each_result_same_alone_and_in_the_mix():
             srv.poll()      # later requests arrive while earlier batches run
     srv.drain()
     torch.cuda.synchronize()
+    return reqs
+
+
+@pytest.mark.parametrize("policy", ["size_class", "fifo"])
+def test_each_result_same_alone_and_in_the_mix_and_equal_to_the_oracle(policy):
+    hosts, scenes = _scenes()
+    cfg = R.Config()
+    rng = np.random.default_rng(3)
+    res = [(128, 96), (200, 120), (96, 160), (64, 64)]
+    cams = random_cameras(24, 11, res)
+    sids = rng.integers(0, 2, size=len(cams)).tolist()
+    budget = 64 << 20   # forces several batches
+    srv = S.Server(scenes, cfg, budget, max_views=6, slots=2, policy=policy, keep_state=True)
+    reqs = _requests(srv, cams, sids)
     assert len(srv.done) == len(reqs) and not srv.sched.rejected
+    oc = ocfg_of(cfg)
+    worst = 0.0
     for r in reqs:
         img, _ = R.render(scenes[r.scene_id], r.cam, cfg)
         torch.cuda.synchronize()
-        assert torch.equal(r.image, img), r.rid
-    st = S.latency_stats(srv.done)
-    log(f"[serve] {st}")
+        assert torch.equal(r.image, img.cpu()), r.rid
+        st = r.state
+        g = dict(splat=st["splat"], depth=st["depth"], rect=st["rect"].astype(np.int32),
+                 tc=st["tc"], vals=st["vals"].astype(np.int32),
+                 ranges=st["ranges"].astype(np.int32), image=[r.image.numpy()],
+                 Tfinal=[st["T_final"]], ncontrib=[st["n_contrib"]])
+        check_projection(hosts[r.scene_id], r.cam, cfg, g)
+        tx, ty = oracle.tiles(r.cam, oc)
+        ref = oracle.bin_pairs(g["depth"].astype(np.float64), g["rect"], g["tc"], tx, ty)
+        assert ref["I"] == r.pairs == g["vals"].size, (r.rid, ref["I"], r.pairs)
+        assert np.array_equal(g["vals"], ref["vals"]) and np.array_equal(g["ranges"], ref["ranges"])
+        emax, _, _ = check_forward(g, r.cam, cfg)
+        worst = max(worst, emax)
+    log(f"[serve] {policy}: {len(reqs)} requests equal alone and to the oracle "
+        f"(max-abs {worst:.2e}); {S.latency_stats(srv.done)}")
+
+
+def test_device_memory_within_scenes_plus_budget():
+    hosts, scenes = _scenes()
+    cfg = R.Config()
+    rng = np.random.default_rng(5)
+    cams = random_cameras(30, 12, [(256, 256), (640, 360), (960, 540)])
+    sids = rng.integers(0, 2, size=len(cams)).tolist()
+    budget = 96 << 20
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()
+    base = torch.cuda.memory_allocated()
+    # a prior far below the scenes' pair rates: the first batches outgrow
+    # their pair lists and run again with the exact count
+    est = S.PairEstimator(prior_per_pixel=0.5, margin=1.0)
+    srv = S.Server(scenes, cfg, budget, max_views=6, slots=2, estimator=est)
+    reqs = _requests(srv, cams, sids)
+    peak = torch.cuda.max_memory_allocated()
+    assert len(srv.done) == len(reqs) and not srv.sched.rejected
+    assert srv.sched.used == 0 and srv.sched.n_reruns > 0
+    # the pool is the only device allocation of the serving loop (torch's
+    # allocator rounds it up to 512 bytes)
+    assert peak - base <= -(-budget // 512) * 512, (peak - base, budget)
+    for r in reqs[:6]:
+        img, _ = R.render(scenes[r.scene_id], r.cam, cfg)
+        assert torch.equal(r.image, img.cpu()), r.rid
+    log(f"[serve] peak {peak - base} B over the resident scenes, budget {budget} B, "
+        f"{srv.sched.n_reruns} batches run again with their exact pair count")

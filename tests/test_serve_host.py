@@ -1,8 +1,9 @@
-"""Host logic of the serving loop (admission by memory budget, batching,
-slots, FIFO order, continuous admission, capacity re-run), driven by a
-host-side executor with a simulated clock: no GPU involved."""
+"""Host logic of the serving loop (the budget pool, admission by memory,
+FIFO and size-class batching, slots, continuous admission, capacity re-run),
+driven by a host-side executor with a simulated clock: no GPU involved."""
 import dataclasses
 
+import numpy as np
 import pytest
 
 from paper_2606_11529_amd import serve as S
@@ -54,11 +55,11 @@ class FakeScene:
     n: int
 
 
-def _server(budget, max_views=4, slots=2, **kw):
+def _server(budget, max_views=4, slots=2, policy="fifo", **kw):
     clock = Clock()
     ex = FakeExec(clock, **kw)
     srv = S.Server({0: FakeScene(1000), 1: FakeScene(50_000)}, None, budget,
-                   max_views=max_views, slots=slots, executor=ex, clock=clock)
+                   max_views=max_views, slots=slots, executor=ex, clock=clock, policy=policy)
     return srv, ex, clock
 
 
@@ -83,7 +84,8 @@ def test_batches_respect_view_limit_and_fifo():
 def test_memory_budget_admission_and_release():
     srv, ex, clock = _server(budget=10**9, max_views=8, slots=2)
     one = srv.sched.request_bytes(S.Request(0, 1, Cam(512, 512), 0.0))
-    srv.sched.budget = int(2.5 * one)          # two requests fit, the third waits
+    srv, ex, clock = _server(budget=int(2.5 * one), max_views=8, slots=2)
+    # two requests fit, the third waits
     for _ in range(3):
         srv.submit(1, Cam(512, 512))
     srv.poll()
@@ -156,3 +158,81 @@ def test_replay_drives_arrivals():
     S.replay(srv, arrivals, spin=0)
     assert len(srv.done) == 20
     assert all(r.t_done >= r.t_arrival for r in srv.done)
+
+
+def test_pool_first_fit_alignment_and_coalescing():
+    p = S.Pool(10 * S.ALIGN + 17)
+    assert p.size == 10 * S.ALIGN and p.largest_free() == p.size
+    a = p.alloc(1)
+    b = p.alloc(3 * S.ALIGN - 5)
+    c = p.alloc(2 * S.ALIGN)
+    assert (a, b, c) == (0, S.ALIGN, 4 * S.ALIGN)
+    assert p.used == 6 * S.ALIGN and p.largest_free() == 4 * S.ALIGN
+    assert p.alloc(5 * S.ALIGN) is None
+    p.release(b)                       # hole of 3 blocks between a and c
+    assert p.alloc(3 * S.ALIGN) == S.ALIGN
+    p.release(S.ALIGN)
+    p.release(a)
+    p.release(c)                       # everything coalesces back
+    assert p.free == [[0, p.size]] and p.used == 0
+
+
+def test_size_class_batches_equal_resolutions_first():
+    srv, ex, clock = _server(budget=10**10, max_views=4, slots=1, policy="size_class")
+    sizes = [(512, 512), (1920, 1080), (512, 512), (1920, 1080), (512, 512)]
+    for w, h in sizes:
+        srv.submit(0, Cam(w, h))
+    srv.poll()
+    assert ex.launched == [[0, 2, 4]]   # the head's class, skipping the others
+    clock.t = 1.0
+    srv.poll()
+    assert ex.launched[-1] == [1, 3]
+    clock.t = 2.0
+    srv.poll()
+    assert srv.idle() and len(srv.done) == 5
+
+
+def test_rerun_larger_than_the_pool_is_rejected():
+    srv, ex, clock = _server(budget=10**9, overflow_once=True)
+    one = srv.sched.request_bytes(S.Request(0, 0, Cam(64, 64), 0.0))
+    srv, ex, clock = _server(budget=2 * one, overflow_once=True)
+    ex_collect = ex.collect
+
+    def collect(job, h):    # the pair list needs far more than the pool
+        ok = ex_collect(job, h)
+        if not ok:
+            job.capacity = 10**9
+        return ok
+    ex.collect = collect
+    r = srv.submit(0, Cam(64, 64))
+    srv.poll()
+    clock.t = 1.0
+    srv.poll()
+    assert r.failed and r in srv.sched.rejected and srv.idle() and srv.sched.used == 0
+
+
+@pytest.mark.parametrize("policy", ["fifo", "size_class"])
+def test_pool_never_overcommitted(policy):
+    # random arrivals, sizes, scenes and latencies; overflows now and then:
+    # after every poll the live blocks are disjoint and within the budget
+    rng = np.random.default_rng(11)
+    srv, ex, clock = _server(budget=60 << 20, max_views=6, slots=3, policy=policy)
+    res = [(512, 512), (1280, 720), (1920, 1080), (64, 64)]
+    for step in range(400):
+        for _ in range(rng.poisson(0.8)):
+            w, h = res[rng.integers(0, len(res))]
+            srv.submit(int(rng.integers(0, 2)), Cam(w, h))
+        if rng.uniform() < 0.05:
+            ex.overflow_once = True
+        ex.latency = float(rng.uniform(0.001, 0.01))
+        clock.t += 0.002
+        srv.poll()
+        p = srv.sched.pool
+        blocks = sorted(p.live.items())
+        assert all(o1 + n1 <= o2 for (o1, n1), (o2, _) in zip(blocks, blocks[1:]))
+        assert p.used <= p.size <= 60 << 20
+        assert p.used == sum(j.bytes for j in srv.sched.in_flight)
+    while not srv.idle():
+        clock.t += 0.01
+        srv.poll()
+    assert srv.sched.used == 0 and len(srv.done) + len(srv.sched.rejected) == srv._rid
