@@ -24,11 +24,21 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fwd+bwd ms/frame @3M Gaussians 1600x1064; served frames/s + p99 latency"
 HBM_PEAK_GBS = 8000.0
-# FP32 VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (no packed math).
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# Algorithmic VALU lane-operations per pixel-Gaussian evaluation.
-OPS_FWD = 22
-OPS_BWD = 40
+# MI355X published FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x
+# 2 flops per FMA x 2 (packed FP32), in TFLOP/s. Without packed FP32 (these
+# kernels are built without it) the issue ceiling is half of it.
+FP32_PEAK_TFLOPS = 157.3
+FP32_UNPACKED_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+# Algorithmic flops of the compositing definition (an FMA counts 2, exp 1):
+# every evaluated list entry forms dx, dy, the power (3 products of the
+# offsets, 3 by the conic, 2 sums), e^P and o e^P: 12; a blended entry adds
+# 1 - alpha, T (1 - alpha), alpha T and three colour FMAs in the forward (9),
+# and in the backward T / (1 - alpha), 1 - alpha, alpha T, dL/dc (3),
+# dL/dalpha (11), the colour-behind update (9), dL/do and dL/dP (2), the
+# mean and conic gradients (11) and their 9 sums over pixels: 48.
+FLOP_EVAL = 12
+FLOP_BLEND_FWD = 9
+FLOP_BLEND_BWD = 48
 
 
 def log(msg):
@@ -120,9 +130,19 @@ def main():
     run = timed_frames(scene, cams, cfg, targets, args.steps, args.warmup, args.tile, names)
     ms_wall, stage_ms, work = run["ms_wall"], run["stage_ms"], run["work"]
     order = [(args.warmup + k) % len(cams) for k in range(args.steps)]
-    evals_fwd = float(np.mean([work["fwd"][c] for c in order]))
-    evals_bwd = float(np.mean([work["bwd"][c] for c in order]))
+    evals_fwd = float(np.mean([work["fwd_evals"][c] for c in order]))
+    blend = float(np.mean([work["blended"][c] for c in order]))
+    walk_bwd = float(np.mean([work["bwd_walked"][c] for c in order]))
+    flop_fwd = float(np.mean([work["fwd_evals"][c] * FLOP_EVAL + work["blended"][c] * FLOP_BLEND_FWD
+                              for c in order]))
+    flop_bwd = float(np.mean([work["bwd_walked"][c] * FLOP_EVAL + work["blended"][c] * FLOP_BLEND_BWD
+                              for c in order]))
     pairs = float(np.mean([work["pairs"][c] for c in order]))
+    # backward time per camera: mean over its timed frames, and the worst
+    per_cam = {}
+    for k, c in enumerate(order):
+        per_cam.setdefault(c, []).append(stage_ms["render_bwd"][k])
+    bwd_cam = {int(c): float(np.mean(v)) for c, v in sorted(per_cam.items())}
 
     med = {k: float(np.median(v)) for k, v in stage_ms.items()}
     mean = {k: float(np.mean(v)) for k, v in stage_ms.items()}
@@ -131,24 +151,29 @@ def main():
     nG = scene.n
     proj_bytes = nG * (236 + 64)
     pbwd_bytes = nG * (236 + 36 + 4 + 236)
-    fwd_tops = evals_fwd * OPS_FWD / (mean["render_fwd"] * 1e-3) / 1e12
-    bwd_tops = evals_bwd * OPS_BWD / (mean["render_bwd"] * 1e-3) / 1e12
+    fwd_tf = flop_fwd / (mean["render_fwd"] * 1e-3) / 1e12
+    bwd_tf = flop_bwd / (mean["render_bwd"] * 1e-3) / 1e12
     stages = {
         "project": {"ms": mean["project"], "bound": "hbm",
                     "GB/s": proj_bytes / (mean["project"] * 1e-3) / 1e9,
                     "frac": proj_bytes / (mean["project"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "bin_sort": {"ms": mean["bin_sort"], "pairs": pairs},
         "render_fwd": {"ms": mean["render_fwd"], "bound": "alu", "evals": evals_fwd,
-                       "TOP/s": fwd_tops, "frac": fwd_tops / VALU_PEAK_TOPS},
+                       "blended": blend, "GFLOP": flop_fwd / 1e9, "TFLOP/s": fwd_tf,
+                       "frac": fwd_tf / FP32_PEAK_TFLOPS},
         "loss": {"ms": mean["loss"]},
-        "render_bwd": {"ms": mean["render_bwd"], "bound": "alu", "evals": evals_bwd,
-                       "TOP/s": bwd_tops, "frac": bwd_tops / VALU_PEAK_TOPS},
+        "render_bwd": {"ms": mean["render_bwd"], "bound": "alu", "walked": walk_bwd,
+                       "blended": blend, "GFLOP": flop_bwd / 1e9, "TFLOP/s": bwd_tf,
+                       "frac": bwd_tf / FP32_PEAK_TFLOPS, "ms_per_camera": bwd_cam,
+                       "ms_worst_camera": max(bwd_cam.values()),
+                       "worst_over_mean": max(bwd_cam.values()) / float(np.mean(
+                           list(bwd_cam.values())))},
         "project_bwd": {"ms": mean["project_bwd"], "bound": "hbm",
                         "GB/s": pbwd_bytes / (mean["project_bwd"] * 1e-3) / 1e9,
                         "frac": pbwd_bytes / (mean["project_bwd"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
     dom = "render_bwd" if mean["render_bwd"] >= mean["render_fwd"] else "render_fwd"
-    ops = OPS_BWD * evals_bwd if dom == "render_bwd" else OPS_FWD * evals_fwd
+    flops = flop_bwd if dom == "render_bwd" else flop_fwd
     pers = "true" if cfg.persistent else "false"
     if dom == "render_bwd":
         kname = (f"xpr::k_render_bwd<{args.tile},{args.tile},"
@@ -160,13 +185,16 @@ def main():
     # kernel sources are the ones it was taken from
     from paper_2606_11529_amd.profiling import traffic_of, valu_busy_of
     traffic = traffic_of(os.path.join(ROOT, "profiles", "hbm_traffic_3dgs_3M_1600x1064.txt"), kname)
-    # The lockstep evaluation count overstates what the per-wave lists leave
-    # to evaluate, so frac can exceed 1; the hardware counters' VALU busy
-    # fraction of the same kernel (committed summary) is the utilisation.
+    # The achieved figure counts the definition's flops (the evaluations the
+    # pixels make until they stop, and the blended entries), not the
+    # instructions the kernel issues; beside it, the hardware counters' VALU
+    # busy fraction of the same kernel (committed summary) and the ceiling
+    # without packed FP32.
     busy = valu_busy_of(os.path.join(ROOT, "profiles", "compositing_sq_3dgs_3M_1600x1064.md"), kname)
-    roof = {"kernel": kname, "bound": "alu", "achieved": stages[dom]["TOP/s"],
-            "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": stages[dom]["frac"],
-            "traffic": traffic, "ops_per_launch": ops, "launch_ms": mean[dom],
+    roof = {"kernel": kname, "bound": "alu", "achieved": stages[dom]["TFLOP/s"],
+            "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": stages[dom]["frac"],
+            "traffic": traffic, "flop_per_launch": flops, "launch_ms": mean[dom],
+            "frac_of_unpacked_fp32": stages[dom]["TFLOP/s"] / FP32_UNPACKED_TFLOPS,
             "valu_busy_counters": busy}
 
     out = {
@@ -273,7 +301,7 @@ def timed_frames(scene, cams, cfg, targets, steps, warmup, tile, names):
     views = [R.Views([scene], [c], [0], cfg) for c in cams]
     proj = R.empty_projected(scene.n, dev)
     frame = None
-    tw = torch.zeros(views[0].tiles, dtype=torch.int32, device=dev)
+    tw = torch.zeros((views[0].tiles, 2), dtype=torch.int32, device=dev)
     g2 = torch.empty((scene.n, 9), dtype=torch.float32, device=dev)
     grads = [scene.zeros_like_grads()]
     ws = R.Workspace()
@@ -300,7 +328,7 @@ def timed_frames(scene, cams, cfg, targets, steps, warmup, tile, names):
               for _ in range(steps + 1)]
     ev = ev_all[-1]
     stage_ms = {k: [] for k in names}
-    work = {"fwd": [], "bwd": [], "pairs": [], "visible": []}
+    work = {"fwd_evals": [], "blended": [], "bwd_walked": [], "pairs": [], "visible": []}
 
     def step(k, ev):
         nonlocal bins, frame
@@ -310,7 +338,7 @@ def timed_frames(scene, cams, cfg, targets, steps, warmup, tile, names):
         ev[1].record()
         bins = R.xpr_bin_sort(v, cfg, proj, capacity=cap, ws=ws, out=bins)
         ev[2].record()
-        frame = R.xpr_render_fwd(v, cfg, proj, bins, out=frame, tile_work=tw)
+        frame = R.xpr_render_fwd(v, cfg, proj, bins, out=frame)
         ev[3].record()
         img = v.image(frame.image, 0).reshape(-1)
         loss, dimg = R.xpr_l1_loss(img, targets[k % len(views)].reshape(-1), loss=loss_buf,
@@ -340,21 +368,19 @@ def timed_frames(scene, cams, cfg, targets, steps, warmup, tile, names):
     log(f"[bench] timed {steps} steps")
     ms_wall = (t_end - t_start) * 1e3 / steps
 
-    # Work per camera (deterministic), outside the timed region.
-    tiles_x = (W + tile - 1) // tile
-    tiles_y = (H + tile - 1) // tile
-    npx = tile * tile
+    # Work per camera (deterministic), outside the timed region: the
+    # counting forward gives, per tile, the list entries its pixels evaluate
+    # before they stop and the entries they blend; the backward walks every
+    # pixel's list down from its last blended entry (n_contrib).
     for k in range(len(views)):
         v = views[k]
         R.xpr_project(v, cfg, out=proj)
         bins = R.xpr_bin_sort(v, cfg, proj, capacity=cap, ws=ws, out=bins)
         frame = R.xpr_render_fwd(v, cfg, proj, bins, out=frame, tile_work=tw)
-        nc = v.plane(frame.n_contrib, 0)
-        pad = torch.zeros((tiles_y * tile, tiles_x * tile), dtype=torch.int32, device=dev)
-        pad[:H, :W] = nc
-        tmax = pad.view(tiles_y, tile, tiles_x, tile).amax(dim=(1, 3))
-        work["fwd"].append(float(tw.sum().item()) * npx)
-        work["bwd"].append(float(tmax.sum().item()) * npx)
+        tws = tw.to(torch.int64).sum(dim=0).tolist()
+        work["fwd_evals"].append(float(tws[0]))
+        work["blended"].append(float(tws[1]))
+        work["bwd_walked"].append(float(v.plane(frame.n_contrib, 0).to(torch.int64).sum().item()))
         if bins.count > cap:
             raise RuntimeError(f"camera {k}: {bins.count} pairs exceed the capacity {cap}")
         work["pairs"].append(bins.count)
@@ -525,12 +551,15 @@ def bench_serving(n_requests=1000):
 def cpu_baseline(sc, cam, cfg):
     """The FP64 oracle on one full frame of the same workload (camera 0):
     projection, binning, compositing forward and backward, projection
-    backward, on all host cores."""
+    backward, on all host cores; beside it the small 10k-Gaussian 256x256
+    forward on one core."""
     import numpy as np
 
     import oracle
+    from synth import camera_front, scene_uniform_cube
     oc = oracle.OracleConfig(tile_w=cfg.tile, tile_h=cfg.tile, sh_degree=cfg.sh_degree)
-    log(f"[bench] cpu baseline: oracle on {oracle.num_threads()} threads")
+    threads = oracle.num_threads()
+    log(f"[bench] cpu baseline: oracle on {threads} threads")
     t0 = time.perf_counter()
     st = oracle.render(sc, cam, oc)
     target = np.random.default_rng(7).uniform(size=(3, cam.height, cam.width))
@@ -548,11 +577,25 @@ def cpu_baseline(sc, cam, cfg):
     except OSError:
         pass
     log(f"[bench] cpu baseline {dt:.1f}s")
-    return {"value": round(dt * 1e3, 1), "unit": "ms/frame", "cores": oracle.num_threads(),
-            "kind": "oracle", "cpu": cpu,
+    # one core: the 10k-Gaussian, 256x256, SH degree 0 forward (median of 3)
+    small, scam = scene_uniform_cube(10_000, seed=0), camera_front(256, 256)
+    soc = oracle.OracleConfig(tile_w=16, tile_h=16, sh_degree=0)
+    oracle.set_num_threads(1)
+    try:
+        one = []
+        for _ in range(3):
+            t1 = time.perf_counter()
+            oracle.render(small, scam, soc)
+            one.append(time.perf_counter() - t1)
+    finally:
+        oracle.set_num_threads(threads)
+    log(f"[bench] cpu baseline 1 core, 10k forward: {np.median(one) * 1e3:.1f} ms")
+    return {"value": round(dt * 1e3, 1), "unit": "ms/frame", "cores": threads,
+            "kind": "oracle", "cpu": cpu, "host_cpus": os.cpu_count(),
             "sample": "one full frame (camera 0 of 8): FP64 projection of all Gaussians, "
                       "binning, compositing forward and backward over every pixel, "
-                      "projection backward"}
+                      "projection backward",
+            "one_core_10k_256x256_forward_ms": round(float(np.median(one)) * 1e3, 2)}
 
 
 if __name__ == "__main__":

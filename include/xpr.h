@@ -278,8 +278,12 @@ xpr_status xpr_bin_sort(const xpr_views* views, const xpr_config* cfg, const xpr
  *   T_final [H][W] per view: final transmittance
  *   n_contrib [H][W] per view: 1-based list position of the last blended
  *   entry (0 if none), used by the backward;
- *   tile_work [tiles] int32 (may be NULL): list entries each tile's
- *   workgroup evaluated before every pixel was done (the lockstep work).
+ *   tile_work [tiles][2] int32 (may be NULL): the work the definition
+ *   performs in each tile, summed over its pixels: the list entries a pixel
+ *   evaluates (up to and including the one that stops it, else the whole
+ *   list), then the entries it blends. Given, the call runs a counting
+ *   instantiation in index order (tile_order, persistent and the
+ *   lds_batch / fwd_ppt knobs are then ignored; the outputs are the same).
  * Tiles are scheduled in tile_order when given; with cfg->persistent a grid
  * sized to fill the device pulls tiles from that order through an atomic
  * counter (then tile_order is required).

@@ -109,14 +109,19 @@ __device__ __forceinline__ int build_wave_list(Stage<BATCH, NW>& S, int nb, int 
   return cnt;
 }
 
-template <int TW, int TH, int BATCH, int PPT>
+// With COUNT the tile also counts the work the definition performs: per
+// pixel the list entries it evaluates (up to and including the one that
+// stops it, else the whole list) and the entries it blends, summed over the
+// tile's pixels into tile_work [g][2] (s_cnt: two ints of LDS).
+template <int TW, int TH, int BATCH, int PPT, bool COUNT>
 __device__ __forceinline__ void fwd_tile(const Batch& B, int g, const float4* __restrict__ splat,
                                          const int32_t* __restrict__ vals,
                                          const int2* __restrict__ ranges,
                                          float* __restrict__ image, float* __restrict__ Tfin,
                                          int32_t* __restrict__ ncon,
                                          int32_t* __restrict__ tile_work,
-                                         Stage<BATCH, (TW * TH / PPT + 63) / 64>& S) {
+                                         Stage<BATCH, (TW * TH / PPT + 63) / 64>& S,
+                                         int32_t* s_cnt) {
   constexpr int NT = TW * TH / PPT;
   constexpr int NW = (NT + 63) / 64;
   constexpr int RPW = 64 * PPT / TW;  // pixel rows per wave
@@ -130,22 +135,22 @@ __device__ __forceinline__ void fwd_tile(const Batch& B, int g, const float4* __
   const float amax = B.alpha_max, amin = B.alpha_min, tmin = B.t_min;
   float T[PPT], C0[PPT], C1[PPT], C2[PPT], lift[PPT];
   int last[PPT];
+  int stop[PPT], nbl[PPT];  // COUNT only: stopping position, entries blended
   int nalive = 0;
 #pragma unroll
   for (int j = 0; j < PPT; ++j) {
     T[j] = 1.f;
     C0[j] = C1[j] = C2[j] = 0.f;
     last[j] = 0;
+    stop[j] = nbl[j] = 0;
     const bool inside = px < V.W && py0 + j < V.H;
     lift[j] = inside ? 0.f : __builtin_inff();
   }
-  int walked = 0;
   for (int base = rg.x; base < rg.y; base += BATCH) {
     nalive = 0;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) nalive += lift[j] == 0.f ? 1 : 0;
     if (__syncthreads_count(nalive > 0) == 0) break;
-    walked = min(BATCH, rg.y - base) + (base - rg.x);
     for (int k = threadIdx.x; k < BATCH; k += NT) {
       const int idx = base + k;
       if (idx < rg.y) {
@@ -201,6 +206,10 @@ __device__ __forceinline__ void fwd_tile(const Batch& B, int g, const float4* __
           C2[j] += gb.y * w;
           T[j] = blend ? Tn : T[j];
           last[j] = blend ? idx : last[j];
+          if (COUNT) {
+            stop[j] = (use && !blend) ? idx : stop[j];
+            nbl[j] += blend ? 1 : 0;
+          }
           lift[j] = (use && !blend) ? __builtin_inff() : lift[j];
         }
       }
@@ -220,7 +229,17 @@ __device__ __forceinline__ void fwd_tile(const Batch& B, int g, const float4* __
       ncon[(size_t)V.pix_off + p] = last[j];
     }
   }
-  if (tile_work && threadIdx.x == 0) tile_work[g] = walked;
+  if (COUNT) {
+    int ev = 0, bl = 0;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      if (px < V.W && py0 + j < V.H) {
+        ev += stop[j] > 0 ? stop[j] : rg.y - rg.x;
+        bl += nbl[j];
+      }
+    }
+    store_tile_work(ev, bl, s_cnt, tile_work, g);
+  }
 }
 
 // Tile scheduling: with PERSIST the grid is sized to the device and each
@@ -233,22 +252,24 @@ __device__ __forceinline__ int next_tile(int* s_next, int32_t* qhead) {
   return *s_next;
 }
 
-template <int TW, int TH, int BATCH, int PPT, bool PERSIST>
+template <int TW, int TH, int BATCH, int PPT, bool PERSIST, bool COUNT = false>
 __global__ __launch_bounds__(TW* TH / PPT) void k_render_fwd(
     Batch B, const float4* __restrict__ splat, const int32_t* __restrict__ vals,
     const int2* __restrict__ ranges, float* __restrict__ image, float* __restrict__ Tfin,
     int32_t* __restrict__ ncon, int32_t* __restrict__ tile_work, const int32_t* order,
     int32_t* qhead) {
   __shared__ Stage<BATCH, (TW * TH / PPT + 63) / 64> S;
+  __shared__ int32_t s_cnt[2];
   if (!PERSIST) {
     const int g = order ? order[blockIdx.x] : (int)blockIdx.x;
-    fwd_tile<TW, TH, BATCH, PPT>(B, g, splat, vals, ranges, image, Tfin, ncon, tile_work, S);
+    fwd_tile<TW, TH, BATCH, PPT, COUNT>(B, g, splat, vals, ranges, image, Tfin, ncon, tile_work,
+                                        S, s_cnt);
     return;
   }
   __shared__ int s_next;
   for (int q = next_tile(&s_next, qhead); q < B.total_tiles; q = next_tile(&s_next, qhead))
-    fwd_tile<TW, TH, BATCH, PPT>(B, order[q], splat, vals, ranges, image, Tfin, ncon, tile_work,
-                                 S);
+    fwd_tile<TW, TH, BATCH, PPT, COUNT>(B, order[q], splat, vals, ranges, image, Tfin, ncon,
+                                        tile_work, S, s_cnt);
 }
 
 // Backward of the compositing. Each pixel walks its list in reverse from
@@ -572,8 +593,31 @@ static void launch_batch(const Batch& B, int lds_batch, const RenderArgs& A, boo
   }
 }
 
+// The counting forward: index order, LDS batch 256, one pixel per thread
+// (four per thread at 32x32); the work counts and the image do not depend
+// on the launch shape.
+static void launch_count(const Batch& B, const RenderArgs& A, hipStream_t st) {
+  const dim3 grid(B.total_tiles);
+  if (B.tile_w == 8)
+    hipLaunchKernelGGL((k_render_fwd<8, 8, 256, 1, false, true>), grid, dim3(64), 0, st, B,
+                       A.splat, A.vals, A.ranges, A.image, A.Tfin, A.ncon, A.tile_work,
+                       nullptr, nullptr);
+  else if (B.tile_w == 32)
+    hipLaunchKernelGGL((k_render_fwd<32, 32, 256, 4, false, true>), grid, dim3(256), 0, st, B,
+                       A.splat, A.vals, A.ranges, A.image, A.Tfin, A.ncon, A.tile_work,
+                       nullptr, nullptr);
+  else
+    hipLaunchKernelGGL((k_render_fwd<16, 16, 256, 1, false, true>), grid, dim3(256), 0, st, B,
+                       A.splat, A.vals, A.ranges, A.image, A.Tfin, A.ncon, A.tile_work,
+                       nullptr, nullptr);
+}
+
 static void launch_render(const Batch& B, int lds_batch, int ppt, const RenderArgs& A, bool bwd,
                           hipStream_t st) {
+  if (!bwd && A.tile_work) {
+    launch_count(B, A, st);
+    return;
+  }
   if (B.tile_w == 8) {
     launch_batch<8, 8, 1>(B, lds_batch, A, bwd, st);
     return;

@@ -43,7 +43,10 @@ struct LinStage {
   uint16_t list[NW][kLinBatch];
 };
 
-template <int TW, int TH>
+// With COUNT the tile also counts the definition's work into tile_work
+// [g][2]: per pixel the entries evaluated (up to and including the one that
+// stops it, else the whole list) and the entries blended.
+template <int TW, int TH, bool COUNT = false>
 __global__ __launch_bounds__(TW* TH) void k_render_fwd_lin(
     Batch B, const float4* __restrict__ splat, const int32_t* __restrict__ vals,
     const int2* __restrict__ ranges, float* __restrict__ image, float* __restrict__ Tfin,
@@ -65,17 +68,16 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd_lin(
   const double fpx = (double)px, fpy = (double)py;
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   int last = 0;
+  int stop = 0, nbl = 0;  // COUNT only
   // a finished pixel (or one outside the image) carries lift = +inf, which
   // fails every later test; kept in a vector register (a carried boolean
   // becomes a lane mask updated by scalar instructions on every record)
   float lift = inside ? 0.f : __builtin_inff();
-  int walked = 0;
   const int stride = splat_stride4(B);
   const int x0 = tx * TW, x1 = tx * TW + TW - 1, y0 = ty * TH;
   for (int base = rg.x; base < rg.y; base += kLinBatch) {
     if (__syncthreads_count(lift == 0.f) == 0) break;
     const int nb = min(kLinBatch, rg.y - base);
-    walked = nb + (base - rg.x);
     for (int k = threadIdx.x; k < nb; k += NT) {
       const float4* q = splat + (size_t)stride * (size_t)vals[base + k];
       const float4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3], q4 = q[4];
@@ -173,6 +175,10 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd_lin(
         C2 += L.bl * w;
         T = blend ? Tn : T;
         last = blend ? base + k - rg.x + 1 : last;
+        if (COUNT) {
+          stop = (use && !blend) ? base + k - rg.x + 1 : stop;
+          nbl += blend ? 1 : 0;
+        }
         lift = (use && !blend) ? __builtin_inff() : lift;
       }
     }
@@ -187,7 +193,11 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd_lin(
     Tfin[(size_t)V.pix_off + p] = T;
     ncon[(size_t)V.pix_off + p] = last;
   }
-  if (tile_work && threadIdx.x == 0) tile_work[g] = walked;
+  if (COUNT) {
+    __shared__ int32_t s_cnt[2];
+    store_tile_work(inside ? (stop > 0 ? stop : rg.y - rg.x) : 0, inside ? nbl : 0, s_cnt,
+                    tile_work, g);
+  }
 }
 
 hipError_t launch_render_fwd_lin(const Batch& B, const float* splat, const int32_t* vals,
@@ -197,15 +207,27 @@ hipError_t launch_render_fwd_lin(const Batch& B, const float* splat, const int32
   const float4* sp = reinterpret_cast<const float4*>(splat);
   const int2* rg = reinterpret_cast<const int2*>(ranges);
   const dim3 grid(B.total_tiles);
+  if (tile_work) {
+    if (B.tile_w == 8)
+      hipLaunchKernelGGL((k_render_fwd_lin<8, 8, true>), grid, dim3(64), 0, st, B, sp, vals, rg, image,
+                         Tfin, ncon, tile_work, order);
+    else if (B.tile_w == 32)
+      hipLaunchKernelGGL((k_render_fwd_lin<32, 32, true>), grid, dim3(1024), 0, st, B, sp, vals, rg,
+                         image, Tfin, ncon, tile_work, order);
+    else
+      hipLaunchKernelGGL((k_render_fwd_lin<16, 16, true>), grid, dim3(256), 0, st, B, sp, vals, rg,
+                         image, Tfin, ncon, tile_work, order);
+    return hipGetLastError();
+  }
   if (B.tile_w == 8)
     hipLaunchKernelGGL((k_render_fwd_lin<8, 8>), grid, dim3(64), 0, st, B, sp, vals, rg, image,
-                       Tfin, ncon, tile_work, order);
+                       Tfin, ncon, nullptr, order);
   else if (B.tile_w == 32)
     hipLaunchKernelGGL((k_render_fwd_lin<32, 32>), grid, dim3(1024), 0, st, B, sp, vals, rg,
-                       image, Tfin, ncon, tile_work, order);
+                       image, Tfin, ncon, nullptr, order);
   else
     hipLaunchKernelGGL((k_render_fwd_lin<16, 16>), grid, dim3(256), 0, st, B, sp, vals, rg,
-                       image, Tfin, ncon, tile_work, order);
+                       image, Tfin, ncon, nullptr, order);
   return hipGetLastError();
 }
 

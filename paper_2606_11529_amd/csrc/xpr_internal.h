@@ -116,4 +116,21 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 // Host-side launch helpers (api.hip).
 const char* set_error(const char* fmt, ...);
 
+// Work counts of the counting forward: the workgroup's sums of its
+// threads' evaluated and blended list entries go to tile_work [g][2]
+// (s_cnt: two ints of LDS). Every thread of the workgroup calls it.
+__device__ __forceinline__ void store_tile_work(int ev, int bl, int32_t* s_cnt,
+                                                int32_t* tile_work, int g) {
+  __syncthreads();
+  if (threadIdx.x == 0) s_cnt[0] = s_cnt[1] = 0;
+  __syncthreads();
+  atomicAdd(&s_cnt[0], ev);
+  atomicAdd(&s_cnt[1], bl);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    tile_work[2 * (size_t)g] = s_cnt[0];
+    tile_work[2 * (size_t)g + 1] = s_cnt[1];
+  }
+}
+
 }  // namespace xpr
