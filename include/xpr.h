@@ -338,6 +338,24 @@ xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const x
                           int32_t accumulate, float* grad2d, void* ws, size_t ws_bytes,
                           hipStream_t stream);
 
+/* xpr_render_bwd for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation with grads required and grad2d / the workspace
+ * replaced by a file-scope static device array of 64 MiB per device (the
+ * per-record 2D gradients, 36 bytes per record: at most 1,864,135 records;
+ * more fail with XPR_ERR_CAPACITY before anything is enqueued). Calls no
+ * hipMalloc, hipFree or other allocating routine; the caller still owns
+ * every input and the gradient buffers. Every call on a device shares that
+ * device's array, which is zero-filled at the start of each call by a
+ * kernel on the given stream: calls that overlap on one device (different
+ * streams, or threads) race on it and must be serialised by the caller.
+ * The array's address is looked up once per device on its first call. */
+xpr_status xpr_render_bwd_noalloc(const xpr_views* views, const xpr_config* cfg,
+                                  const xpr_projected* proj, const xpr_bins* bins,
+                                  const float* dL_dimage, const float* T_final,
+                                  const int32_t* n_contrib, const xpr_scene_grad* grads,
+                                  int32_t accumulate, hipStream_t stream);
+
 /* Backward of the projection alone (the derivative of project of the listing
  * "Implementation of XPR-3DGS" -- world to camera, R(q) S^2 R(q)^T, the EWA
  * covariance with its low-pass, the conic, mean2D and the SH colour of the

@@ -93,6 +93,8 @@ SIGNATURES = {
     "xpr_render_bwd_workspace": (_i32, [_P(XprViews), _P(XprConfig), _P(ctypes.c_size_t)]),
     "xpr_render_bwd": (_i32, [_P(XprViews), _P(XprConfig), _P(XprProjected), _P(XprBins), _vp,
                               _vp, _vp, _P(XprSceneGrad), _i32, _vp, _vp, ctypes.c_size_t, _vp]),
+    "xpr_render_bwd_noalloc": (_i32, [_P(XprViews), _P(XprConfig), _P(XprProjected), _P(XprBins),
+                                      _vp, _vp, _vp, _P(XprSceneGrad), _i32, _vp]),
     "xpr_l1_loss": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
     "xpr_last_error": (ctypes.c_char_p, []),
     "xpr_version": (_i32, []),
@@ -188,6 +190,14 @@ def xpr_render_bwd(views, cfg, proj, bins, dimage, T_final, n_contrib, grads, ac
     check(lib().xpr_render_bwd(ctypes.byref(views), ctypes.byref(cfg), ctypes.byref(proj),
                                ctypes.byref(bins), dimage, T_final, n_contrib, grads, accumulate,
                                grad2d, ws, ws_bytes, stream), "xpr_render_bwd")
+
+
+def xpr_render_bwd_noalloc(views, cfg, proj, bins, dimage, T_final, n_contrib, grads,
+                           accumulate, stream) -> None:
+    check(lib().xpr_render_bwd_noalloc(ctypes.byref(views), ctypes.byref(cfg),
+                                       ctypes.byref(proj), ctypes.byref(bins), dimage, T_final,
+                                       n_contrib, grads, accumulate, stream),
+          "xpr_render_bwd_noalloc")
 
 
 def xpr_l1_loss(image, target, n: int, loss, dimage, stream) -> None:

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "xpr_internal.h"
 
@@ -398,12 +399,16 @@ xpr_status xpr_render_bwd_workspace(const xpr_views* views, const xpr_config* cf
   return XPR_OK;
 }
 
-xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
-                          const xpr_bins* bins, const float* dL_dimage, const float* T_final,
-                          const int32_t* n_contrib, const xpr_scene_grad* grads,
-                          int32_t accumulate, float* grad2d, void* ws, size_t ws_bytes,
-                          hipStream_t stream) {
-  g_err[0] = 0;
+}  // extern "C"
+
+// The backward given the per-record 2D gradient buffer g2 (or NULL: then
+// grad2d, else the workspace ws of ws_bytes holds it).
+static xpr_status render_bwd_impl(const xpr_views* views, const xpr_config* cfg,
+                                  const xpr_projected* proj, const xpr_bins* bins,
+                                  const float* dL_dimage, const float* T_final,
+                                  const int32_t* n_contrib, const xpr_scene_grad* grads,
+                                  int32_t accumulate, float* grad2d, void* ws, size_t ws_bytes,
+                                  float* g2, int64_t g2_max_records, hipStream_t stream) {
   Batch B;
   Sizes S;
   xpr_status st = build_batch(views, cfg, &B, &S);
@@ -420,7 +425,17 @@ xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const x
   XPR_CHECK(aligned(dL_dimage, 4) && aligned(T_final, 4) && aligned(n_contrib, 4) &&
                 aligned(bins->tile_ranges, 8) && (!grad2d || aligned(grad2d, 4)),
             "misaligned buffer");
-  float* g2 = grad2d;
+  if (g2) {
+    if (S.records > g2_max_records) {
+      set_error("%lld records need %lld bytes of 2D gradients; the static scratch holds %lld "
+                "(%lld records)",
+                (long long)S.records, (long long)S.records * 36, (long long)g2_max_records * 36,
+                (long long)g2_max_records);
+      return XPR_ERR_CAPACITY;
+    }
+  } else {
+    g2 = grad2d;
+  }
   if (!g2) {
     const size_t need = (size_t)9 * sizeof(float) * (size_t)std::max<int64_t>(S.records, 1);
     XPR_CHECK(ws && ws_bytes >= need, "workspace too small: %zu < %zu bytes", ws_bytes, need);
@@ -440,6 +455,74 @@ xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const x
   if (grads)
     XPR_HIP(launch_project_bwd(B, S.max_n, g2, proj->tiles_touched, G, accumulate ? 1 : 0, stream));
   return XPR_OK;
+}
+
+// File-scope scratch of xpr_render_bwd_noalloc: the per-record 2D gradients
+// (9 floats per record). Each device holds its own copy for the life of the
+// process. In host code ``scratch`` names a host-side stand-in, never the
+// device memory: kernels and fills get the address hipGetSymbolAddress
+// returns on each device.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int64_t kScratchRecords = (int64_t)(kScratchBytes / (9 * sizeof(float)));
+static __device__ __align__(256) float scratch[kScratchBytes / sizeof(float)];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static float* g_scratch_ptr[kMaxDevices];
+
+// The current device's address of ``scratch`` (looked up once per device,
+// with that device current).
+static xpr_status scratch_of_current_device(float** out) {
+  int dev = -1;
+  XPR_HIP(hipGetDevice(&dev));
+  XPR_CHECK(dev >= 0 && dev < kMaxDevices, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    XPR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    XPR_CHECK(p != nullptr && aligned(p, 256), "scratch symbol address invalid");
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return XPR_OK;
+}
+
+extern "C" {
+
+xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
+                          const xpr_bins* bins, const float* dL_dimage, const float* T_final,
+                          const int32_t* n_contrib, const xpr_scene_grad* grads,
+                          int32_t accumulate, float* grad2d, void* ws, size_t ws_bytes,
+                          hipStream_t stream) {
+  g_err[0] = 0;
+  return render_bwd_impl(views, cfg, proj, bins, dL_dimage, T_final, n_contrib, grads,
+                         accumulate, grad2d, ws, ws_bytes, nullptr, 0, stream);
+}
+
+xpr_status xpr_render_bwd_noalloc(const xpr_views* views, const xpr_config* cfg,
+                                  const xpr_projected* proj, const xpr_bins* bins,
+                                  const float* dL_dimage, const float* T_final,
+                                  const int32_t* n_contrib, const xpr_scene_grad* grads,
+                                  int32_t accumulate, hipStream_t stream) {
+  g_err[0] = 0;
+  XPR_CHECK(grads != nullptr, "grads is NULL");
+  // the size check needs no device: it comes before anything else
+  Batch B;
+  Sizes S;
+  xpr_status st = build_batch(views, cfg, &B, &S);
+  if (st != XPR_OK) return st;
+  if (S.records > kScratchRecords) {
+    set_error("%lld records need %lld bytes of 2D gradients; the static scratch holds %lld "
+              "(%lld records)",
+              (long long)S.records, (long long)S.records * 36, (long long)kScratchRecords * 36,
+              (long long)kScratchRecords);
+    return XPR_ERR_CAPACITY;
+  }
+  float* g2 = nullptr;
+  st = scratch_of_current_device(&g2);
+  if (st != XPR_OK) return st;
+  return render_bwd_impl(views, cfg, proj, bins, dL_dimage, T_final, n_contrib, grads,
+                         accumulate, nullptr, nullptr, 0, g2, kScratchRecords, stream);
 }
 
 xpr_status xpr_l1_loss(const float* image, const float* target, int64_t n, float* loss,

@@ -348,6 +348,17 @@ def xpr_render_bwd(views: Views, cfg: Config, proj: Projected, bins: Bins, frame
     return (grads if params else None), grad2d
 
 
+def xpr_render_bwd_noalloc(views: Views, cfg: Config, proj: Projected, bins: Bins, frame: Frame,
+                           dimage: torch.Tensor, grads: List[dict], accumulate: bool = False):
+    """The backward into caller-owned parameter gradients with the library's
+    static device scratch for the 2D gradients: nothing is allocated (the
+    caller passes every buffer)."""
+    L.xpr_render_bwd_noalloc(views.c, views.cfg_c, proj.to_c(), bins.to_c(), _ptr(dimage),
+                             _ptr(frame.T_final), _ptr(frame.n_contrib), _grads_c(grads),
+                             1 if accumulate else 0, _stream())
+    return grads
+
+
 def xpr_project_bwd(views: Views, cfg: Config, proj: Projected, grad2d: torch.Tensor,
                     grads: Optional[List[dict]] = None, accumulate: bool = False):
     if grads is None:

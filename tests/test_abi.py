@@ -157,3 +157,20 @@ def test_bin_sort_rejects_small_workspace():
                               ctypes.byref(bins), 4096, 16, None)
     assert st == L.XPR_ERR_INVALID_ARG
     assert "workspace" in L.xpr_last_error()
+
+
+def test_noalloc_backward_rejects_more_records_than_its_scratch():
+    # 1,864,135 records fit the 64 MiB static scratch (36 bytes each); one
+    # more view of a 1M scene is refused on the host, before any device call
+    c = L.xpr_config_default()
+    grads = (L.XprSceneGrad * 1)(L.XprSceneGrad(4096, 4096, 4096, 4096, 4096))
+    args = (L.XprProjected(4096, 4096, 4096, 4096), L.XprBins(None, 4096, 4096, 4096, None, 10))
+    v = _views(n=1_000_000, n_views=2)
+    st = L.lib().xpr_render_bwd_noalloc(ctypes.byref(v), ctypes.byref(c), ctypes.byref(args[0]),
+                                        ctypes.byref(args[1]), 4096, 4096, 4096, grads, 0, None)
+    assert st == L.XPR_ERR_CAPACITY
+    msg = L.xpr_last_error()
+    assert "2000000 records" in msg and "1864135 records" in msg
+    st = L.lib().xpr_render_bwd_noalloc(ctypes.byref(v), ctypes.byref(c), ctypes.byref(args[0]),
+                                        ctypes.byref(args[1]), 4096, 4096, 4096, None, 0, None)
+    assert st == L.XPR_ERR_INVALID_ARG and "grads" in L.xpr_last_error()
