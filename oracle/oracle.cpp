@@ -902,13 +902,18 @@ void orc_tile_cull(int64_t m, const double* rec, int rec_stride, const int32_t* 
 //   T *= 1 - alpha.
 // Output C + T bg.
 //
-// A decision is in the guard band when its operand lies within a small band
-// of its threshold (|P| <= 1e-6, |alpha - alpha_min| <= 1e-4 alpha_min,
-// |T (1 - alpha) - t_min| <= 1e-3 t_min): a float32 evaluation may take it
-// either way. For a pixel with such decisions the walk is repeated once per
-// decision with that decision alone inverted; the largest change of any
-// colour channel (and of T) summed over these walks is the pixel's
-// ambiguous contribution.
+// A decision is in the guard band when its operand lies within the float32
+// rounding bound of its threshold, so that a float32 evaluation may take it
+// either way. With u = 2^-24 and S the sum of the absolute power terms
+// (the power's rounding grows with S, not with |P|: a needle-like conic
+// cancels large terms): the P > 0 gate when |P| <= max(1e-6, 2 * 7 S u);
+// the alpha gate when |alpha - alpha_min| <= max(1e-4 alpha_min,
+// 2 (7 S + 3) u alpha); the stop rule when |T (1 - alpha) - t_min| <=
+// max(1e-3, 2 s u) t_min, s the T sensitivity below including this entry.
+// For a pixel with such decisions the walk is repeated once per decision
+// with that decision alone inverted; the largest change of any colour
+// channel (and of T) summed over these walks is the pixel's ambiguous
+// contribution.
 struct PixelWalk {
   double C[3], T;
   int32_t last, count, neval, nguard;
@@ -929,24 +934,29 @@ static PixelWalk walk_pixel(int px, int py, const double* rec, const int32_t* va
     const double dx = px - r[0], dy = py - r[1];
     const double t0 = r[2] * dx * dx, t1 = r[3] * dx * dy, t2 = r[4] * dy * dy;
     const double P = t0 + t1 + t2;
-    if (decide(std::fabs(P) <= 1e-6, P > 0)) continue;
+    const double S = std::fabs(t0) + std::fabs(t1) + std::fabs(t2);
+    const double u = 0x1p-24;
+    if (decide(std::fabs(P) <= std::max(1e-6, 14.0 * S * u), P > 0)) continue;
     const double raw = r[5] * std::exp(P);
     const double alpha = std::min(alpha_max, raw);
-    if (decide(std::fabs(alpha - alpha_min) <= 1e-4 * alpha_min, alpha < alpha_min)) continue;
+    if (decide(std::fabs(alpha - alpha_min) <=
+                   std::max(1e-4 * alpha_min, 2.0 * (7.0 * S + 3.0) * u * alpha),
+               alpha < alpha_min))
+      continue;
+    // Sensitivity of T to float32 evaluation (in units of u): alpha carries
+    // a relative error of at most about 7u S plus 3u (the roundings of dx,
+    // dy, the products and sums of the power, exp and the opacity product),
+    // amplified by alpha / (1 - alpha) in 1 - alpha; the update of T adds
+    // two roundings. A clamped alpha is the constant alpha_max.
+    const double sens =
+        w.tsens + (raw >= alpha_max ? 0.0 : alpha / (1.0 - alpha) * (7.0 * S + 3.0)) + 2.0;
     const double Tn = w.T * (1.0 - alpha);
-    if (decide(std::fabs(Tn - t_min) <= 1e-3 * t_min, Tn < t_min)) {
+    if (decide(std::fabs(Tn - t_min) <= std::max(1e-3, 2.0 * sens * u) * t_min, Tn < t_min)) {
       w.neval = k - start + 1;
       break;
     }
     for (int c = 0; c < 3; ++c) w.C[c] += r[6 + c] * alpha * w.T;
-    // Sensitivity of T to float32 evaluation (in units of the float32 unit
-    // roundoff u = 2^-24): alpha carries a relative error of at most about
-    // 7u times the sum of the absolute power terms plus 3u (the roundings of
-    // dx, dy, the products and sums of the power, exp and the opacity
-    // product), amplified by alpha / (1 - alpha) in 1 - alpha; the update of
-    // T adds two roundings. A clamped alpha is the constant alpha_max.
-    const double S = std::fabs(t0) + std::fabs(t1) + std::fabs(t2);
-    w.tsens += (raw >= alpha_max ? 0.0 : alpha / (1.0 - alpha) * (7.0 * S + 3.0)) + 2.0;
+    w.tsens = sens;
     w.T = Tn;
     w.last = k - start + 1;
     ++w.count;

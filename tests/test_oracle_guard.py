@@ -134,3 +134,31 @@ def test_amb_sums_over_decisions():
     drop1 = np.array(cols[0]) * a
     want = np.abs(full - drop0).max() + np.abs(full - drop1).max()
     assert r["amb"][0, 7, 9] == pytest.approx(want, rel=1e-6)
+
+
+@pytest.mark.parametrize("needle,guard", [(True, 1), (False, 0)])
+def test_alpha_gate_band_follows_the_power_terms(needle, guard):
+    # alpha at pixel (7, 7) sits 5e-4 (relative) below alpha_min. For a
+    # needle-like conic whose power terms cancel (|A| = |C| = 500, B just
+    # below 1000, S about 2000) the float32 rounding of the power moves alpha
+    # by about 2 (7 S + 3) 2^-24 = 1.7e-3 relative: the decision is in the
+    # guard band and the ambiguous contribution is the record's colour times
+    # alpha. For an isotropic conic reaching the same alpha (S = |P|) it is
+    # decided: not a guard pixel, nothing ambiguous.
+    o = 0.5
+    a = A_MIN * (1 - 5e-4)
+    P = math.log(a / o)      # at dx = dy = 1
+    if needle:
+        A = C = -500.0
+        B = P + 1000.0       # -A - C + B = P
+    else:
+        A = C = P / 2
+        B = 0.0
+    col = (0.7, 0.3, 0.5)
+    r = _render([[6.0, 6.0, A, B, C, o, *col]])
+    assert (r["guard"][7, 7], r["nblend"][7, 7]) == (guard, 0)
+    if guard:
+        assert r["amb"][0, 7, 7] == pytest.approx(max(col) * a, rel=1e-6)
+        assert r["amb"][1, 7, 7] == pytest.approx(a, rel=1e-6)
+    else:
+        assert r["amb"][:, 7, 7].max() == 0.0
