@@ -53,10 +53,7 @@ def _run(name, sort_mode="presort"):
 @pytest.mark.parametrize("name", CASES)
 def test_projection(name):
     sc, cam, cfg, _, g = _run(name)
-    idx = None
-    if sc.n > 200_000:
-        idx = np.sort(np.random.default_rng(2).choice(sc.n, 200_000, replace=False))
-    nguard, n = check_projection(sc, cam, cfg, g, idx=idx)
+    nguard, n = check_projection(sc, cam, cfg, g)
     log(f"[P1] {name}: {n} Gaussians checked, {nguard} in the guard band")
 
 
