@@ -510,12 +510,14 @@ def bench_batched(n=2_000_000, n_views=16, reps=5):
             "images_identical": bool(same)}
 
 
-def bench_serving(n_requests=1000):
-    """Four resident scenes (100k, 500k, 1.5M, 3M); Poisson view requests at
-    200/s, uniform scene, random camera on the radius-6 sphere, resolution
-    uniform in {512x512, 1280x720, 1920x1080}; forward only. The continuous-
-    batching server against a FIFO server that renders one request at a
-    time with plain launches."""
+def bench_serving(n_requests=1000, rates=(200.0, 1000.0)):
+    """Four resident scenes (100k, 500k, 1.5M, 3M); Poisson view requests,
+    uniform scene, random camera on the radius-6 sphere, resolution uniform
+    in {512x512, 1280x720, 1920x1080}; forward only, 4 GiB batch pool. The
+    continuous-batching server (size-class batches, and FIFO-prefix batches)
+    against a server that renders one request at a time with plain
+    launches, at the workload's 200 requests/s and at 1000/s (above what one
+    at a time sustains), then saturated (all requests at once)."""
     import torch
 
     from paper_2606_11529_amd import renderer as R
@@ -524,27 +526,39 @@ def bench_serving(n_requests=1000):
 
     c5 = CONFIGS["serving_4scenes"]
     scenes = {k: R.Scene.from_host(scene_clusters(n, seed=k)) for k, n in enumerate(c5["scenes"])}
-    arrivals = request_stream(n_requests + 100, c5["rate_hz"], len(scenes), c5["res_set"])
     cfg = R.Config()
-    out = {"workload": f"4 resident scenes {c5['scenes']}, Poisson {c5['rate_hz']:.0f}/s, "
-                       f"{n_requests} requests after 100 warm-up, forward only, 4 GiB budget"}
-    for name, mv, slots in (("continuous_batching", 8, 2), ("fifo_one_at_a_time", 1, 1)):
-        srv = S.Server(scenes, cfg, 4 << 30, max_views=mv, slots=slots, keep_images=False)
-        S.replay(srv, arrivals[:100])            # warm-up (estimator, allocator)
-        srv.done.clear()
-        torch.cuda.synchronize()
-        t0 = arrivals[100][0]
-        rest = [(a - t0, sid, cam) for a, sid, cam in arrivals[100:]]
-        wall = S.replay(srv, rest)
-        st = S.latency_stats(srv.done)
-        st.update(frames_per_s=len(srv.done) / wall, wall_s=wall, max_views=mv, slots=slots)
-        # saturation: all requests at once
+    out = {"workload": f"4 resident scenes {c5['scenes']}, Poisson arrivals, {n_requests} "
+                       "requests after 100 warm-up, forward only, 4 GiB batch pool",
+           "rates_per_s": list(rates)}
+    servers = (("continuous_size_class", 8, 2, "size_class"),
+               ("continuous_fifo", 8, 2, "fifo"),
+               ("one_at_a_time", 1, 1, "fifo"))
+    for name, mv, slots, policy in servers:
+        srv = S.Server(scenes, cfg, 4 << 30, max_views=mv, slots=slots, keep_images=False,
+                       policy=policy)
+        res = {"max_views": mv, "slots": slots, "policy": policy}
+        for rate in rates:
+            arrivals = request_stream(n_requests + 100, rate, len(scenes), c5["res_set"])
+            srv.done.clear()
+            S.replay(srv, arrivals[:100])            # warm-up (estimator)
+            srv.done.clear()
+            torch.cuda.synchronize()
+            t0 = arrivals[100][0]
+            rest = [(a - t0, sid, cam) for a, sid, cam in arrivals[100:]]
+            wall = S.replay(srv, rest)
+            st = S.latency_stats(srv.done)
+            st.update(frames_per_s=len(srv.done) / wall, wall_s=wall)
+            res[f"{rate:.0f}_per_s"] = st
+            log(f"[serve] {name} at {rate:.0f}/s: p50 {st['p50_ms']:.2f} ms p99 "
+                f"{st['p99_ms']:.2f} ms {st['frames_per_s']:.1f} fps")
         srv.done.clear()
         wall_sat = S.replay(srv, [(0.0, sid, cam) for _, sid, cam in rest])
-        st["saturated_frames_per_s"] = len(srv.done) / wall_sat
-        log(f"[serve] {name}: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms "
-            f"{st['frames_per_s']:.1f} fps, saturated {st['saturated_frames_per_s']:.1f} fps")
-        out[name] = st
+        res["saturated_frames_per_s"] = len(srv.done) / wall_sat
+        res["reruns"] = srv.sched.n_reruns
+        log(f"[serve] {name}: saturated {res['saturated_frames_per_s']:.1f} fps")
+        out[name] = res
+        del srv
+        torch.cuda.empty_cache()
     return out
 
 

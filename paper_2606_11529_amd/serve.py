@@ -7,9 +7,11 @@ buffer it will use (projected records, pair list, tile ranges, sort
 workspace, image planes) has been placed in the pool, so the serving loop's
 device memory never exceeds the resident scenes plus the budget. Whenever a
 stream slot is free the scheduler forms one batch of up to ``max_views``
-views of any scenes: the oldest queued request, then (policy ``size_class``)
-the next queued requests of the same resolution, or (policy ``fifo``) the
-queue's prefix, as long as the batch still fits the pool. A batch runs the
+views of any scenes and sizes: the queue's prefix (policy ``fifo``, the
+default), or the oldest queued request and the next queued requests of its
+resolution (policy ``size_class``), as long as the batch still fits the
+pool. On the four-scene workload the prefix sustains more frames per
+second, so it is the default. A batch runs the
 four stages as one batched launch each on its own stream, so batches overlap
 on the device; requests arriving meanwhile are admitted as soon as a slot
 and memory free up. Each request's image does not depend on what it was
@@ -156,7 +158,7 @@ class Scheduler:
 
     def __init__(self, scene_sizes: Dict[int, int], budget_bytes: int, max_views: int = 8,
                  slots: int = 2, estimator: Optional[PairEstimator] = None,
-                 policy: str = "size_class",
+                 policy: str = "fifo",
                  sizer: Optional[Callable[[List[Request], int], int]] = None):
         if policy not in ("fifo", "size_class"):
             raise ValueError(f"unknown policy {policy!r}")
@@ -422,7 +424,7 @@ class Server:
 
     def __init__(self, scenes: Dict[int, "object"], cfg, budget_bytes: int, max_views: int = 8,
                  slots: int = 2, executor=None, clock: Callable[[], float] = time.perf_counter,
-                 keep_images: bool = True, policy: str = "size_class",
+                 keep_images: bool = True, policy: str = "fifo",
                  estimator: Optional[PairEstimator] = None, keep_state: bool = False):
         self.exec = executor or GpuExecutor(scenes, cfg, slots, budget_bytes,
                                             keep_images=keep_images, keep_state=keep_state)
