@@ -71,6 +71,11 @@ typedef enum {
 #define XPR_SORT_BANDS 2   /* depth presort, then records binned per band of 16 tiles and
                               placed per tile by counting (same output; falls back to
                               XPR_SORT_PRESORT beyond 65536 bands or 2^23 records) */
+#define XPR_SORT_ONESWEEP 3 /* XPR_SORT_PRESORT with single-pass radix passes: digit counts
+                              of every pass taken up front, each pass one kernel whose
+                              blocks find their digit offsets by decoupled look-back (same
+                              output; XPR_SORT_PRESORT with tile_cull or for capacities of
+                              2^30 pairs or more) */
 
 /* Pinhole camera, world -> camera x_c = R x_w + t (R row-major), camera axes
  * x right, y down, z forward. (cx, cy) is the principal point in continuous
@@ -95,7 +100,7 @@ typedef struct xpr_config {
   float z_near;           /* cull when camera-space z <= z_near (> 0; 0.2) */
   float fov_clip;         /* Jacobian clamp at fov_clip * W / (2 fx) (1.3; 0 = off) */
   float bg[3];            /* background colour (0, 0, 0) */
-  int32_t sort_mode;      /* XPR_SORT_PRESORT, XPR_SORT_FULL or XPR_SORT_BANDS */
+  int32_t sort_mode;      /* XPR_SORT_PRESORT, _FULL, _BANDS or _ONESWEEP */
   int32_t no_sync;        /* 1: never read back to the host (graph capture) */
   int32_t fwd_ppt;        /* pixels per thread in the forward: 1, 2 or 4 (16x16 tiles;
                            * 8x8 tiles use 1, 32x32 tiles 4) */

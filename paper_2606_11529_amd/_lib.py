@@ -20,6 +20,7 @@ XPR_ERR_UNSUPPORTED = 4
 XPR_SORT_PRESORT = 0
 XPR_SORT_FULL = 1
 XPR_SORT_BANDS = 2
+XPR_SORT_ONESWEEP = 3
 XPR_METHOD_3DGS = 0
 XPR_METHOD_3DGUT = 1
 XPR_METHOD_LINPRIM = 2

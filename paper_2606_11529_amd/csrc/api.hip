@@ -97,7 +97,7 @@ static xpr_status check_config(const xpr_config* c) {
   XPR_CHECK(std::isfinite(c->bg[0]) && std::isfinite(c->bg[1]) && std::isfinite(c->bg[2]),
             "bg must be finite");
   XPR_CHECK(c->sort_mode == XPR_SORT_PRESORT || c->sort_mode == XPR_SORT_FULL ||
-                c->sort_mode == XPR_SORT_BANDS,
+                c->sort_mode == XPR_SORT_BANDS || c->sort_mode == XPR_SORT_ONESWEEP,
             "sort_mode %d unknown", c->sort_mode);
   XPR_CHECK(c->fwd_ppt == 1 || c->fwd_ppt == 2 || c->fwd_ppt == 4, "fwd_ppt %d not in {1,2,4}",
             c->fwd_ppt);
@@ -353,6 +353,16 @@ xpr_status xpr_bin_sort(const xpr_views* views, const xpr_config* cfg, const xpr
                      proj->tiles_touched, perm, S.records, cap, grid_n, out->n_isect, out->keys,
                      out->vals, reinterpret_cast<int2*>(out->tile_ranges), out->tile_order, ws,
                      ws_bytes, stream));
+  if (!cfg->no_sync && cfg->sort_mode == XPR_SORT_ONESWEEP && !cull) {
+    // a look-back wait past its limit poisons the pair count
+    int64_t I2 = 0;
+    XPR_HIP(hipMemcpyAsync(&I2, out->n_isect, sizeof(I2), hipMemcpyDeviceToHost, stream));
+    XPR_HIP(hipStreamSynchronize(stream));
+    if (I2 > cap) {
+      set_error("binning failed: a look-back wait of the single-pass sort hit its limit");
+      return XPR_ERR_HIP;
+    }
+  }
   return XPR_OK;
 }
 

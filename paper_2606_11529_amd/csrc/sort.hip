@@ -1297,6 +1297,421 @@ __global__ __launch_bounds__(256) void k_pair_scatter(
                                            nullptr, nullptr);
 }
 
+// ---------------------------------------------------------------------------
+// Single-pass ("onesweep") radix passes with decoupled look-back
+// (XPR_SORT_ONESWEEP). The digit counts of every pass are taken up front in
+// one pass over the data (for the tile passes, from the records' rects
+// without generating the pairs), so no pass needs a histogram kernel or a
+// device-wide scan of block counts. A block takes the next partition id from
+// an atomic counter (ids follow the order in which blocks start, so a block
+// only ever waits for partitions held by blocks already running), ranks its
+// 4096 keys in LDS as in k_radix_scatter, publishes its per-digit counts,
+// and finds, per digit, the count of the same digit in all earlier
+// partitions by walking back over their published words until one holds an
+// inclusive prefix; it then publishes its own inclusive prefix and writes its
+// keys at digit start + prefix + rank. A status word is flag << 30 | count
+// (0 = not yet published, 1 = the partition's own count, 2 = inclusive
+// prefix), so one 32-bit atomic load reads both. Waits are bounded: past the
+// limit the block records an error and goes on, and the driver turns the
+// error into a failed binning instead of a hang.
+constexpr uint32_t kLbAgg = 1u << 30;
+constexpr uint32_t kLbInc = 2u << 30;
+constexpr uint32_t kLbCount = kLbAgg - 1u;
+constexpr int kLbSpinLimit = 1 << 22;
+constexpr int kSweepMaxPasses = 4;
+
+struct Sweep {
+  uint32_t* status;      // [partitions][RADIX] look-back words, zero before the pass
+  uint32_t* counter;     // partition counter, zero before the pass
+  const uint32_t* hist;  // [RADIX] digit counts of the pass over the whole list
+  uint32_t* err;         // nonzero after a look-back wait hit its limit
+};
+
+__device__ __forceinline__ uint32_t lb_load(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void lb_store(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The block's partition id (all threads).
+__device__ __forceinline__ int sweep_part(uint32_t* counter, int* s_part) {
+  if (threadIdx.x == 0) *s_part = (int)atomicAdd(counter, 1u);
+  __syncthreads();
+  return *s_part;
+}
+
+// Publishes the block's count of digit t (thread t < RADIX): as an
+// inclusive prefix for partition 0, else as its own count. Called as soon
+// as the counts are known, so that later partitions find it early.
+template <int RADIX>
+__device__ __forceinline__ void sweep_publish(const Sweep& sw, int part, uint32_t tot) {
+  const int t = threadIdx.x;
+  if (t < RADIX) lb_store(sw.status + (size_t)part * RADIX + t, (part == 0 ? kLbInc : kLbAgg) | tot);
+}
+
+// Called by all threads after sweep_publish: returns, for thread t <
+// RADIX, where the block's run of digit t starts in the output (digit start
+// over the whole list plus the count of digit t in earlier partitions), and
+// publishes the inclusive prefix. The walk back reads kLbWindow earlier
+// partitions' words at once (independent loads), then takes them in order.
+constexpr int kLbWindow = 4;
+template <int RADIX>
+__device__ __forceinline__ uint32_t sweep_offset(const Sweep& sw, int part, uint32_t tot,
+                                                 uint32_t* s_wave) {
+  const int t = threadIdx.x;
+  const uint32_t dstart = block_excl_scan256(t < RADIX ? sw.hist[t] : 0u, s_wave, nullptr);
+  if (t >= RADIX || part == 0) return t < RADIX ? dstart : 0u;
+  uint32_t excl = 0u;
+  int p = part - 1;
+  int spins = 0;
+  bool done = false;
+  while (!done && p >= 0) {
+    uint32_t w[kLbWindow];
+#pragma unroll
+    for (int i = 0; i < kLbWindow; ++i)
+      w[i] = p - i >= 0 ? lb_load(sw.status + (size_t)(p - i) * RADIX + t) : (kLbInc | 0u);
+#pragma unroll
+    for (int i = 0; i < kLbWindow; ++i) {
+      if (done) break;
+      const uint32_t flag = w[i] >> 30;
+      if (flag == 0u) break;  // not yet published: read again from p
+      excl += w[i] & kLbCount;
+      --p;
+      if (flag == 2u) done = true;
+    }
+    if (!done && p >= 0 && (lb_load(sw.status + (size_t)p * RADIX + t) >> 30) == 0u) {
+      if (++spins > kLbSpinLimit) {
+        atomicOr(sw.err, 1u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  lb_store(sw.status + (size_t)part * RADIX + t, kLbInc | ((excl + tot) & kLbCount));
+  return dstart + excl;
+}
+
+// write_sorted with a bound: with a pair list larger than its capacity the
+// digit starts can point past it, and nothing may be written there.
+template <int BITS, typename KS, typename KO, bool RANGES>
+__device__ __forceinline__ void write_sorted_capped(const KS* skey, const uint32_t* sval,
+                                                    const uint32_t* gbase, int nvalid, int shift,
+                                                    int64_t cap, KO* __restrict__ kout,
+                                                    uint32_t* __restrict__ vout,
+                                                    int2* __restrict__ ranges,
+                                                    const int32_t* __restrict__ aux_src,
+                                                    uint32_t* __restrict__ aux_dst) {
+  for (int k = threadIdx.x; k < nvalid; k += 256) {
+    const KS kk = skey[k];
+    const uint32_t g = gbase[digit_of<BITS>(kk, shift)] + (uint32_t)k;
+    if ((int64_t)g >= cap) continue;
+    if (!RANGES || kout) kout[g] = (KO)kk;
+    const uint32_t v = sval[k];
+    vout[g] = v;
+    if (aux_dst) aux_dst[g] = (uint32_t)aux_src[v];
+    if (RANGES) {
+      const uint32_t tile = (uint32_t)kk;
+      if (k == 0 || (uint32_t)skey[k - 1] != tile) atomicMin(&ranges[tile].x, (int)g);
+      if (k == nvalid - 1 || (uint32_t)skey[k + 1] != tile) atomicMax(&ranges[tile].y, (int)g + 1);
+    }
+  }
+}
+
+// One onesweep pass over keys in memory: k_radix_scatter with the digit
+// offsets from the look-back.
+template <int BITS, typename K, bool RANGES>
+__global__ __launch_bounds__(256) void k_sweep_scatter(const K* __restrict__ kin,
+                                                       const uint32_t* __restrict__ vin,
+                                                       K* __restrict__ kout,
+                                                       uint32_t* __restrict__ vout,
+                                                       const int64_t* n_dev, int64_t cap,
+                                                       int shift, Sweep sw,
+                                                       int2* __restrict__ ranges,
+                                                       const int32_t* __restrict__ aux_src,
+                                                       uint32_t* __restrict__ aux_dst) {
+  constexpr int RADIX = 1 << BITS;
+  __shared__ uint32_t wcnt[kSortWaves][RADIX];
+  __shared__ uint32_t gbase[RADIX];
+  __shared__ uint32_t s_wave[4];
+  __shared__ int s_part;
+  __shared__ K skey[kSortTile];
+  __shared__ uint32_t sval[kSortTile];
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int part = sweep_part(sw.counter, &s_part);
+  const int64_t n = clamp_n(n_dev, cap);
+  const int64_t bbase = (int64_t)part * kSortTile;
+  if (bbase >= n) return;  // partitions past the list: nobody waits for them
+  for (int k = t; k < kSortWaves * RADIX; k += 256) (&wcnt[0][0])[k] = 0;
+  for (int k = t; k < RADIX; k += 256) gbase[k] = 0u;
+  const int64_t base = bbase + w * (64 * kSortItems);
+  const uint64_t lt = lanemask_lt();
+  K key[kSortItems];
+  uint32_t val[kSortItems];
+  uint32_t lofs[kSortItems];
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int64_t idx = min(base + j * 64 + lane, n - 1);
+    key[j] = kin[idx];
+    val[j] = vin[idx];
+  }
+  __syncthreads();
+  // the block's digit counts first, published before the ranking
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j)
+    if (base + j * 64 + lane < n) atomicAdd(&gbase[digit_of<BITS>(key[j], shift)], 1u);
+  __syncthreads();
+  sweep_publish<RADIX>(sw, part, t < RADIX ? gbase[t] : 0u);
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const bool ok = base + j * 64 + lane < n;
+    const uint32_t d = digit_of<BITS>(key[j], shift);
+    const uint64_t m = match_digit<BITS>(d, ok);
+    const uint32_t before = wcnt[w][d];
+    lofs[j] = before + (uint32_t)__popcll(m & lt);
+    if (ok && (m & lt) == 0) wcnt[w][d] = before + (uint32_t)__popcll(m);
+  }
+  __syncthreads();
+  uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+  if (t < RADIX) {
+    c0 = wcnt[0][t];
+    c1 = wcnt[1][t];
+    c2 = wcnt[2][t];
+    c3 = wcnt[3][t];
+  }
+  const uint32_t tot = c0 + c1 + c2 + c3;
+  const uint32_t start = block_excl_scan256(tot, s_wave, nullptr);
+  const uint32_t gofs = sweep_offset<RADIX>(sw, part, tot, s_wave);
+  if (t < RADIX) {
+    gbase[t] = gofs - start;
+    wcnt[0][t] = start;
+    wcnt[1][t] = start + c0;
+    wcnt[2][t] = start + c0 + c1;
+    wcnt[3][t] = start + c0 + c1 + c2;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int64_t idx = base + j * 64 + lane;
+    if (idx < n) {
+      const uint32_t pos = wcnt[w][digit_of<BITS>(key[j], shift)] + lofs[j];
+      skey[pos] = key[j];
+      sval[pos] = val[j];
+    }
+  }
+  __syncthreads();
+  const int64_t rem = n - bbase;
+  const int nvalid = rem < kSortTile ? (int)rem : kSortTile;
+  write_sorted_capped<BITS, K, K, RANGES>(skey, sval, gbase, nvalid, shift, cap, kout, vout,
+                                          ranges, aux_src, aux_dst);
+}
+
+// First tile pass of the onesweep path: k_pair_scatter with the digit
+// offsets from the look-back.
+template <int BITS, bool RANGES, typename KO>
+__global__ __launch_bounds__(256) void k_sweep_pair_scatter(
+    const uint4* __restrict__ packed, const uint32_t* __restrict__ first, const int64_t* n_isect,
+    int64_t cap, Sweep sw, KO* __restrict__ kout, uint32_t* __restrict__ vout,
+    int2* __restrict__ ranges) {
+  constexpr int RADIX = 1 << BITS;
+  __shared__ typename PairItems::Chunk S;
+  __shared__ uint32_t wcnt[kSortWaves][RADIX];
+  __shared__ uint32_t gbase[RADIX];
+  __shared__ uint32_t s_wave[4];
+  __shared__ int s_part;
+  __shared__ uint32_t skey[kSortTilePad];
+  __shared__ uint32_t sval[kSortTilePad];
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int part = sweep_part(sw.counter, &s_part);
+  const int64_t n = clamp_n(n_isect, cap);
+  const int64_t bbase = (int64_t)part * kSortTile;
+  if (bbase >= n) return;
+  const int nvalid = (int)min((int64_t)kSortTile, n - bbase);
+  for (int k = t; k < kSortWaves * RADIX; k += 256) (&wcnt[0][0])[k] = 0;
+  for (int k = t; k < RADIX; k += 256) gbase[k] = 0u;
+  gen_block_pairs<PairItems>(packed, first, part, n, S, sval, s_wave,
+                             [&](int slot, uint32_t key, uint32_t val) {
+                               skey[spad(slot)] = key;
+                               sval[spad(slot)] = val;
+                               atomicAdd(&gbase[key & (RADIX - 1)], 1u);
+                             });
+  __syncthreads();
+  sweep_publish<RADIX>(sw, part, t < RADIX ? gbase[t] : 0u);
+  const uint64_t lt = lanemask_lt();
+  uint32_t key[kSortItems], val[kSortItems], lofs[kSortItems];
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int slot = w * (64 * kSortItems) + j * 64 + lane;
+    const bool ok = slot < nvalid;
+    key[j] = ok ? skey[spad(slot)] : 0u;
+    val[j] = ok ? sval[spad(slot)] : 0u;
+    const uint32_t d = key[j] & (RADIX - 1);
+    const uint64_t m = match_digit<BITS>(d, ok);
+    const uint32_t before = wcnt[w][d];
+    lofs[j] = before + (uint32_t)__popcll(m & lt);
+    if (ok && (m & lt) == 0) wcnt[w][d] = before + (uint32_t)__popcll(m);
+  }
+  __syncthreads();
+  uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+  if (t < RADIX) {
+    c0 = wcnt[0][t];
+    c1 = wcnt[1][t];
+    c2 = wcnt[2][t];
+    c3 = wcnt[3][t];
+  }
+  const uint32_t tot = c0 + c1 + c2 + c3;
+  const uint32_t start = block_excl_scan256(tot, s_wave, nullptr);
+  const uint32_t gofs = sweep_offset<RADIX>(sw, part, tot, s_wave);
+  if (t < RADIX) {
+    gbase[t] = gofs - start;
+    wcnt[0][t] = start;
+    wcnt[1][t] = start + c0;
+    wcnt[2][t] = start + c0 + c1;
+    wcnt[3][t] = start + c0 + c1 + c2;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int slot = w * (64 * kSortItems) + j * 64 + lane;
+    if (slot < nvalid) {
+      const uint32_t pos = wcnt[w][key[j] & (RADIX - 1)] + lofs[j];
+      skey[pos] = key[j];
+      sval[pos] = val[j];
+    }
+  }
+  __syncthreads();
+  write_sorted_capped<BITS, uint32_t, KO, RANGES>(skey, sval, gbase, nvalid, 0, cap, kout, vout,
+                                                  ranges, nullptr, nullptr);
+}
+
+// Depth-presort keys (as k_depth_keys) for 16 records per thread, with the
+// digit counts of the four 8-bit passes over all of them added to
+// hist [4][256] (zero before).
+__global__ __launch_bounds__(256) void k_depth_keys_hist(const float* __restrict__ depth,
+                                                         const int32_t* __restrict__ tc,
+                                                         int64_t n, uint32_t* __restrict__ key,
+                                                         uint32_t* __restrict__ perm,
+                                                         uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[4][256];
+  const int t = threadIdx.x;
+  for (int k = t; k < 4 * 256; k += 256) (&h[0][0])[k] = 0u;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll 4
+  for (int j = 0; j < kSortItems; ++j) {
+    const int64_t i = base + j * 256 + t;
+    if (i < n) {
+      const uint32_t k = tc[i] > 0 ? __float_as_uint(depth[i]) : 0xffffffffu;
+      key[i] = k;
+      perm[i] = (uint32_t)i;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) atomicAdd(&h[p][(k >> (8 * p)) & 255u], 1u);
+    }
+  }
+  __syncthreads();
+  for (int k = t; k < 4 * 256; k += 256) {
+    const uint32_t c = (&h[0][0])[k];
+    if (c) atomicAdd(hist + k, c);
+  }
+}
+
+// Digit counts of the tile keys of the pairs [a, a + len) of one rect row
+// (consecutive tile ids), pairs of the list only; hist rows of 256 per pass.
+// The first pass's digits of a run of consecutive ids are consecutive
+// modulo the radix: a difference array (diff, RADIX + 1 words) takes the
+// run in two updates (plus full cycles in `cyc`); later passes change digit
+// at most once per 2^shift ids.
+__device__ __forceinline__ void hist_run(uint32_t a, uint32_t len, int dbits, int passes,
+                                         int* diff, uint32_t* cyc, uint32_t* h) {
+  const uint32_t radix = 1u << dbits, mask = radix - 1u;
+  const uint32_t full = len >> dbits, rem = len & mask;
+  if (full) atomicAdd(cyc, full);
+  if (rem) {
+    const uint32_t lo = a & mask, hi = lo + rem;
+    atomicAdd(&diff[lo], 1);
+    if (hi <= radix) {
+      atomicAdd(&diff[hi], -1);
+    } else {
+      atomicAdd(&diff[radix], -1);
+      atomicAdd(&diff[0], 1);
+      atomicAdd(&diff[hi - radix], -1);
+    }
+  }
+  for (int p = 1; p < passes; ++p) {
+    const int sh = p * dbits;
+    uint32_t x = a;
+    const uint32_t e = a + len;
+    while (x < e) {
+      const uint32_t seg = min(e, ((x >> sh) + 1u) << sh);
+      atomicAdd(&h[p * 256 + ((x >> sh) & mask)], seg - x);
+      x = seg;
+    }
+  }
+}
+
+// k_pair_records for 16 records per thread, adding the digit counts of all
+// tile passes over the list's pairs to hist [passes][256] (zero before).
+__global__ __launch_bounds__(256) void k_pair_records_hist(
+    Batch B, const short4* __restrict__ rect, const uint32_t* __restrict__ tc_sorted,
+    const uint32_t* __restrict__ perm, const uint32_t* __restrict__ offsets, int64_t n_rec,
+    const int64_t* n_isect, int64_t cap, int dbits, int passes, uint4* __restrict__ packed,
+    uint32_t* __restrict__ first, uint32_t* __restrict__ hist) {
+  __shared__ int diff[257];
+  __shared__ uint32_t cyc;
+  __shared__ uint32_t h[kSweepMaxPasses * 256];
+  const int t = threadIdx.x;
+  for (int k = t; k < 257; k += 256) diff[k] = 0;
+  for (int k = t; k < kSweepMaxPasses * 256; k += 256) h[k] = 0u;
+  if (t == 0) cyc = 0u;
+  __syncthreads();
+  const int64_t n = clamp_n(n_isect, cap);
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int jj = 0; jj < kSortItems; ++jj) {
+    const int64_t j = base + jj * 256 + t;
+    if (j >= n_rec) break;
+    const int64_t o = offsets[j];
+    const int64_t e = min(o + (int64_t)tc_sorted[j], n);
+    if (e <= o) continue;
+    const uint32_t r = perm[j];
+    int v = 0;
+    for (int q = 1; q < B.n_views; ++q)
+      if ((int32_t)r >= B.v[q].rec_off) v = q;
+    const short4 rc = rect[r];
+    const uint32_t tx = (uint32_t)B.v[v].tiles_x;
+    const uint32_t t0 = (uint32_t)B.v[v].tile_off + (uint32_t)rc.y * tx + (uint32_t)rc.x;
+    const uint32_t wdt = (uint32_t)(rc.z - rc.x);
+    packed[j] = make_uint4((uint32_t)o, r, t0, wdt | (tx << 16));
+    for (int64_t b = (o + kSortTile - 1) / kSortTile; b * kSortTile < e; ++b)
+      first[b] = (uint32_t)j;
+    if (e == n) first[(n + kSortTile - 1) / kSortTile] = (uint32_t)j;
+    // the record's pairs in the list: whole rows, then part of one
+    const int64_t cnt = e - o;
+    const uint32_t rows = (uint32_t)(cnt / wdt), last = (uint32_t)(cnt - (int64_t)rows * wdt);
+    for (uint32_t y = 0; y < rows; ++y) hist_run(t0 + y * tx, wdt, dbits, passes, diff, &cyc, h);
+    if (last) hist_run(t0 + rows * tx, last, dbits, passes, diff, &cyc, h);
+  }
+  __syncthreads();
+  // first pass: prefix sum of the difference array, plus the full cycles
+  const uint32_t radix = 1u << dbits;
+  int run = 0;
+  if (t < (int)radix) {
+    for (int k = 0; k <= t; ++k) run += diff[k];
+    h[t] = (uint32_t)run + cyc;
+  }
+  __syncthreads();
+  for (int k = t; k < passes * 256; k += 256) {
+    const uint32_t c = h[k];
+    if (c && (k & 255) < (int)radix) atomicAdd(hist + k, c);
+  }
+}
+
+// A failed look-back poisons the pair count, so the caller's capacity check
+// (which every caller makes) reports it; the synchronous entry point also
+// reads err itself.
+__global__ void k_sweep_check(const uint32_t* err, int64_t* n_isect) {
+  if (threadIdx.x == 0 && *err != 0u) *n_isect = (int64_t)1 << 62;
+}
+
 // Digit width for sorting `bits` bits: 7 when that needs no more passes than
 // 8 (longer per-digit runs in the scatter, one ballot fewer per key).
 static inline int radix_digit_bits(int bits) { return (bits + 6) / 7 == (bits + 7) / 8 ? 7 : 8; }
@@ -1481,8 +1896,25 @@ struct BinWs {
   uint32_t* ttot;      // [tiles * 16] per band column: pairs
   uint32_t* tbase;     // [tiles * 16] exclusive scan of ttot
   uint64_t* key64[2];  // [cap]     (full)
+  // onesweep passes (zeroed together at the start of the binning)
+  uint32_t* sweep;     // start of the zeroed region
+  size_t sweep_bytes;
+  uint32_t* hist_d;    // [4][256]  depth passes
+  uint32_t* hist_t;    // [4][256]  tile passes
+  uint32_t* counters;  // [16]      partition counters (depth 0..3, tile 4..7)
+  uint32_t* err;       // [1]
+  uint32_t* status_d;  // [4][parts of n_rec][256]
+  uint32_t* status_t;  // [passes][parts of cap][2^dbits]
+  int64_t parts_d, parts_t;
+  int t_radix;
   size_t bytes;
 };
+
+static inline int tile_id_bits(int64_t tiles) {
+  int bits = 1;
+  while (bits < 31 && ((int64_t)1 << bits) < tiles) ++bits;
+  return bits;
+}
 
 static BinWs bin_ws_layout(int64_t n_rec, int64_t cap, int64_t tiles, int sort_mode, bool cull,
                            char* base) {
@@ -1505,7 +1937,8 @@ static BinWs bin_ws_layout(int64_t n_rec, int64_t cap, int64_t tiles, int sort_m
   L.partials = (uint64_t*)take(8 * (size_t)nparts);
   L.counts = (uint32_t*)take(4 * (size_t)(radix_max * nb_max));
   L.vals_alt = (uint32_t*)take(4 * (size_t)std::max<int64_t>(std::max(cap, n_rec), 1));
-  if (sort_mode == XPR_SORT_PRESORT || sort_mode == XPR_SORT_BANDS) {
+  if (sort_mode == XPR_SORT_PRESORT || sort_mode == XPR_SORT_BANDS ||
+      sort_mode == XPR_SORT_ONESWEEP) {
     for (int k = 0; k < 2; ++k) L.dkey[k] = (uint32_t*)take(4 * (size_t)std::max<int64_t>(n_rec, 1));
     for (int k = 0; k < 2; ++k) L.perm[k] = (uint32_t*)take(4 * (size_t)std::max<int64_t>(n_rec, 1));
     for (int k = 0; k < 2; ++k) L.tkey[k] = (uint32_t*)take(4 * (size_t)std::max<int64_t>(cap, 1));
@@ -1537,12 +1970,42 @@ static BinWs bin_ws_layout(int64_t n_rec, int64_t cap, int64_t tiles, int sort_m
   } else {
     for (int k = 0; k < 2; ++k) L.key64[k] = (uint64_t*)take(8 * (size_t)std::max<int64_t>(cap, 1));
   }
+  if (sort_mode == XPR_SORT_ONESWEEP) {
+    const int tb = tile_id_bits(std::max<int64_t>(tiles, 1));
+    L.parts_d = (n_rec + kSortTile - 1) / kSortTile + 1;
+    L.parts_t = (cap + kSortTile - 1) / kSortTile + 1;
+    L.t_radix = 1 << radix_digit_bits(tb);
+    const size_t head = 4 * (4 * 256 + 4 * 256 + 16 + 64);
+    const size_t sd = 4 * (size_t)4 * L.parts_d * 256;
+    const size_t st = 4 * (size_t)radix_passes(tb) * L.parts_t * L.t_radix;
+    char* r = take(head + sd + st);
+    L.sweep = (uint32_t*)r;
+    L.sweep_bytes = align256(head + sd + st);
+    if (r) {
+      L.hist_d = (uint32_t*)r;
+      L.hist_t = L.hist_d + 4 * 256;
+      L.counters = L.hist_t + 4 * 256;
+      L.err = L.counters + 16;
+      L.status_d = L.err + 64;
+      L.status_t = L.status_d + (size_t)4 * L.parts_d * 256;
+    }
+  }
   L.bytes = off;
   return L;
 }
 
+// The onesweep look-back words hold counts below 2^30.
+static inline int effective_mode(int sort_mode, bool cull, int64_t cap, int64_t n_rec) {
+  if (cull) return XPR_SORT_PRESORT;
+  if (sort_mode == XPR_SORT_ONESWEEP &&
+      (cap >= ((int64_t)1 << 30) || n_rec >= ((int64_t)1 << 30)))
+    return XPR_SORT_PRESORT;
+  return sort_mode;
+}
+
 size_t bin_workspace_bytes(int64_t n_rec, int64_t cap, int64_t tiles, int sort_mode, bool cull) {
-  return bin_ws_layout(n_rec, cap, tiles, cull ? XPR_SORT_PRESORT : sort_mode, cull, nullptr).bytes;
+  return bin_ws_layout(n_rec, cap, tiles, effective_mode(sort_mode, cull, cap, n_rec), cull,
+                       nullptr).bytes;
 }
 
 static inline int grid1(int64_t n, int bs = 256) { return (int)((n + bs - 1) / bs); }
@@ -1568,12 +2031,33 @@ hipError_t bin_phase1(const Batch& B, int sort_mode, bool cull, const float* spl
                       const int16_t* rect, const float* depth, const int32_t* tc,
                       int64_t n_rec, int64_t cap,
                       int64_t* n_isect, void* ws, hipStream_t st, const uint32_t** perm_out) {
-  if (cull) sort_mode = XPR_SORT_PRESORT;
+  sort_mode = effective_mode(sort_mode, cull, cap, n_rec);
   BinWs L = bin_ws_layout(n_rec, cap, B.total_tiles, sort_mode, cull, (char*)ws);
   *perm_out = nullptr;
   if (n_rec == 0) {
     hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, st, n_isect, (int64_t)0);
     return hipGetLastError();
+  }
+  if (sort_mode == XPR_SORT_ONESWEEP) {
+    // zero the histograms, counters, error word and look-back words of
+    // every pass (a fill kernel: the step may be captured in a graph)
+    hipLaunchKernelGGL(k_zero_x4, dim3(grid1((int64_t)(L.sweep_bytes / 16))), dim3(256), 0, st,
+                       reinterpret_cast<uint4*>(L.sweep), (int64_t)(L.sweep_bytes / 16));
+    hipLaunchKernelGGL(k_depth_keys_hist, dim3((int)((n_rec + kSortTile - 1) / kSortTile)),
+                       dim3(256), 0, st, depth, tc, n_rec, L.dkey[0], L.perm[0], L.hist_d);
+    const int nb = (int)((n_rec + kSortTile - 1) / kSortTile);
+    uint32_t *k0 = L.dkey[0], *v0 = L.perm[0], *k1 = L.dkey[1], *v1 = L.perm[1];
+    for (int p = 0; p < 4; ++p) {
+      const Sweep sw{L.status_d + (size_t)p * L.parts_d * 256, L.counters + p,
+                     L.hist_d + 256 * p, L.err};
+      hipLaunchKernelGGL((k_sweep_scatter<8, uint32_t, false>), dim3(nb), dim3(256), 0, st, k0,
+                         v0, k1, v1, (const int64_t*)nullptr, n_rec, 8 * p, sw, (int2*)nullptr,
+                         p == 3 ? tc : nullptr, p == 3 ? L.tcs : nullptr);
+      std::swap(k0, k1);
+      std::swap(v0, v1);
+    }
+    *perm_out = v0;
+    return device_scan(LoadArray{L.tcs}, n_rec, L.offsets, L.partials, n_isect, st);
   }
   if (sort_mode == XPR_SORT_PRESORT || sort_mode == XPR_SORT_BANDS) {
     const int32_t* counts = tc;
@@ -1719,6 +2203,90 @@ static hipError_t pair_sort(const Batch& B, int tile_bits, const float* depth, c
     hipLaunchKernelGGL(k_make_keys64<KT>, dim3(grid1(grid_n)), dim3(256), 0, st, ko, vo, depth,
                        n_isect, cap, keys_out);
   if (vo != vals_u) return hipErrorUnknown;  // the pass parity above guarantees vo == vals
+  return hipGetLastError();
+}
+
+// Onesweep path after phase 1 (XPR_SORT_ONESWEEP): the records' pass over
+// the depth order also takes the digit counts of every tile pass, the first
+// pass generates the pairs in LDS (as k_pair_scatter), each pass is one
+// kernel, the last writes the ranges.
+template <typename KT>
+static hipError_t pair_sort_sweep(const Batch& B, int tile_bits, const float* depth,
+                                  const short4* rc, const uint32_t* perm, int64_t n_rec,
+                                  int64_t cap, int64_t grid_n, const int64_t* n_isect,
+                                  uint64_t* keys_out, uint32_t* vals_u, int2* ranges,
+                                  const BinWs& L, hipStream_t st) {
+  const int dbits = radix_digit_bits(tile_bits);
+  const int passes = radix_passes(tile_bits);
+  if (passes > kSweepMaxPasses || (1 << dbits) != L.t_radix) return hipErrorInvalidValue;
+  uint32_t* v1 = (passes % 2 == 1) ? vals_u : L.vals_alt;
+  uint32_t* v2 = (passes % 2 == 1) ? L.vals_alt : vals_u;
+  KT* tk0 = reinterpret_cast<KT*>(L.tkey[0]);
+  KT* tk1 = reinterpret_cast<KT*>(L.tkey[1]);
+  const int tiles = B.total_tiles;
+  hipLaunchKernelGGL(k_ranges_init, dim3(grid1(tiles)), dim3(256), 0, st, ranges, tiles);
+  hipLaunchKernelGGL(k_pair_records_hist, dim3((int)((n_rec + kSortTile - 1) / kSortTile)),
+                     dim3(256), 0, st, B, rc, L.tcs, perm, L.offsets, n_rec, n_isect, cap, dbits,
+                     passes, L.packed, L.first, L.hist_t);
+  const int nb = (int)((grid_n + kSortTile - 1) / kSortTile);
+  auto sweep_of = [&](int p) {
+    return Sweep{L.status_t + (size_t)p * L.parts_t * L.t_radix, L.counters + 4 + p,
+                 L.hist_t + 256 * p, L.err};
+  };
+  const bool one = passes == 1;
+  KT* k1 = (one && !keys_out) ? nullptr : tk0;
+#define XPR_SWEEP_PAIR(BITS, LAST)                                                          \
+  hipLaunchKernelGGL((k_sweep_pair_scatter<BITS, LAST, KT>), dim3(nb), dim3(256), 0, st,    \
+                     L.packed, L.first, n_isect, cap, sweep_of(0), k1, v1,                  \
+                     LAST ? ranges : (int2*)nullptr)
+  if (dbits == 7) {
+    if (one) XPR_SWEEP_PAIR(7, true); else XPR_SWEEP_PAIR(7, false);
+  } else {
+    if (one) XPR_SWEEP_PAIR(8, true); else XPR_SWEEP_PAIR(8, false);
+  }
+#undef XPR_SWEEP_PAIR
+  KT* ka = tk0;
+  KT* kb = tk1;
+  uint32_t* va = v1;
+  uint32_t* vb = v2;
+  for (int p = 1; p < passes; ++p) {
+    const int shift = p * dbits;
+    const bool last = p == passes - 1;
+    const int pb = std::min(dbits, tile_bits - shift);
+    KT* kdst = (last && !keys_out) ? nullptr : kb;
+    int2* rg = last ? ranges : nullptr;
+    const Sweep sw = sweep_of(p);
+#define XPR_SWEEP(BITS)                                                                     \
+  do {                                                                                      \
+    if (last)                                                                               \
+      hipLaunchKernelGGL((k_sweep_scatter<BITS, KT, true>), dim3(nb), dim3(256), 0, st, ka, \
+                         va, kdst, vb, n_isect, cap, shift, sw, rg, (const int32_t*)nullptr, \
+                         (uint32_t*)nullptr);                                               \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_sweep_scatter<BITS, KT, false>), dim3(nb), dim3(256), 0, st,    \
+                         ka, va, kdst, vb, n_isect, cap, shift, sw, rg,                     \
+                         (const int32_t*)nullptr, (uint32_t*)nullptr);                      \
+  } while (0)
+    switch (pb) {
+      case 8: XPR_SWEEP(8); break;
+      case 7: XPR_SWEEP(7); break;
+      case 6: XPR_SWEEP(6); break;
+      case 5: XPR_SWEEP(5); break;
+      case 4: XPR_SWEEP(4); break;
+      case 3: XPR_SWEEP(3); break;
+      case 2: XPR_SWEEP(2); break;
+      default: XPR_SWEEP(1); break;
+    }
+#undef XPR_SWEEP
+    std::swap(ka, kb);
+    std::swap(va, vb);
+  }
+  hipLaunchKernelGGL(k_ranges_fix, dim3(grid1(tiles)), dim3(256), 0, st, ranges, tiles);
+  if (keys_out)
+    hipLaunchKernelGGL(k_make_keys64<KT>, dim3(grid1(grid_n)), dim3(256), 0, st, ka, va, depth,
+                       n_isect, cap, keys_out);
+  hipLaunchKernelGGL(k_sweep_check, dim3(1), dim3(64), 0, st, L.err, (int64_t*)n_isect);
+  if (va != vals_u) return hipErrorUnknown;  // the pass parity above guarantees va == vals
   return hipGetLastError();
 }
 
@@ -2077,7 +2645,7 @@ hipError_t bin_phase2(const Batch& B, int sort_mode, bool cull, const float* spl
                       int32_t* vals, int2* ranges, int32_t* tile_order, void* ws, size_t ws_bytes,
                       hipStream_t st) {
   (void)ws_bytes;
-  if (cull) sort_mode = XPR_SORT_PRESORT;
+  sort_mode = effective_mode(sort_mode, cull, cap, n_rec);
   BinWs L = bin_ws_layout(n_rec, cap, B.total_tiles, sort_mode, cull, (char*)ws);
   const float* cull_splat = cull ? splat : nullptr;
   hipLaunchKernelGGL(k_fill_u32, dim3(grid1(2 * (int64_t)B.total_tiles)), dim3(256), 0, st,
@@ -2089,7 +2657,16 @@ hipError_t bin_phase2(const Batch& B, int sort_mode, bool cull, const float* spl
   const short4* rc = reinterpret_cast<const short4*>(rect);
   uint32_t* vals_u = reinterpret_cast<uint32_t*>(vals);
   const int nbd = grid1(n_rec);
-  if (sort_mode == XPR_SORT_BANDS && band_count(B) <= 65536 && n_rec < ((int64_t)1 << 23)) {
+  if (sort_mode == XPR_SORT_ONESWEEP) {
+    const hipError_t e =
+        tiles_16bit(B.total_tiles)
+            ? pair_sort_sweep<uint16_t>(B, tile_bits, depth, rc, perm, n_rec, cap, grid_n,
+                                        n_isect, keys_out, vals_u, ranges, L, st)
+            : pair_sort_sweep<uint32_t>(B, tile_bits, depth, rc, perm, n_rec, cap, grid_n,
+                                        n_isect, keys_out, vals_u, ranges, L, st);
+    if (e != hipSuccess) return e;
+  } else if (sort_mode == XPR_SORT_BANDS && band_count(B) <= 65536 &&
+             n_rec < ((int64_t)1 << 23)) {
     const hipError_t e = band_sort(B, depth, rc, perm, n_rec, cap, grid_n, keys_out, vals_u,
                                    ranges, L, st);
     if (e != hipSuccess) return e;

@@ -30,7 +30,7 @@ class Config:
     z_near: float = 0.2
     fov_clip: float = 1.3
     bg: tuple = (0.0, 0.0, 0.0)
-    sort_mode: str = "presort"  # "presort", "full" or "bands"
+    sort_mode: str = "presort"  # "presort", "full", "bands" or "onesweep"
     no_sync: bool = False
     fwd_ppt: int = 2            # pixels per thread, forward (16x16 tiles)
     bwd_ppt: int = 4            # pixels per thread, backward (16x16 tiles)
@@ -54,7 +54,8 @@ class Config:
         c.fov_clip = self.fov_clip
         for k in range(3):
             c.bg[k] = float(self.bg[k])
-        modes = {"presort": L.XPR_SORT_PRESORT, "full": L.XPR_SORT_FULL, "bands": L.XPR_SORT_BANDS}
+        modes = {"presort": L.XPR_SORT_PRESORT, "full": L.XPR_SORT_FULL, "bands": L.XPR_SORT_BANDS,
+                 "onesweep": L.XPR_SORT_ONESWEEP}
         if self.sort_mode not in modes:
             raise ValueError(f"unknown sort_mode {self.sort_mode!r}")
         c.sort_mode = modes[self.sort_mode]

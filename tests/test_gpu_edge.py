@@ -55,7 +55,7 @@ def test_lds_batch_and_sort_mode_do_not_change_results():
     cam = camera_look_at((0.5, 0.5, -4.5), 120, 90)
     ref = None
     for lds in (64, 128, 256, 512):
-        for mode in ("presort", "full", "bands"):
+        for mode in ("presort", "full", "bands", "onesweep"):
             g = run_gpu(sc, cam, R.Config(lds_batch=lds, sort_mode=mode))
             if ref is None:
                 ref = g
@@ -117,7 +117,7 @@ def test_deterministic_and_order_invariant_per_method(method, cull):
     assert np.array_equal(perm[c["vals"]], a["vals"])
 
 
-@pytest.mark.parametrize("mode", ["presort", "bands"])
+@pytest.mark.parametrize("mode", ["presort", "bands", "onesweep"])
 def test_capacity_error_and_retry(mode):
     sc = _small(3000, seed=6)
     cam = camera_look_at((0, 0, -4.0), 96, 64)
@@ -177,7 +177,7 @@ def test_no_sync_mode_matches_per_method(method, cull):
     assert np.array_equal(views.image(frame.image, 0).cpu().numpy(), a["image"][0])
 
 
-@pytest.mark.parametrize("mode", ["presort", "bands"])
+@pytest.mark.parametrize("mode", ["presort", "bands", "onesweep"])
 def test_no_sync_mode_matches(mode):
     sc = _small(4000, seed=7)
     cam = camera_look_at((0.4, -0.2, -4.0), 111, 77)
@@ -193,7 +193,7 @@ def test_no_sync_mode_matches(mode):
     assert np.array_equal(views.image(frame.image, 0).cpu().numpy(), a["image"][0])
 
 
-@pytest.mark.parametrize("mode", ["presort", "bands"])
+@pytest.mark.parametrize("mode", ["presort", "bands", "onesweep"])
 def test_batched_views_equal_single_views(mode):
     sc = _small(6000, seed=8)
     cams = random_cameras(4, 3, [(64, 48), (97, 61), (128, 128), (40, 100)], radius=4.5)
@@ -215,7 +215,7 @@ def test_batched_views_equal_single_views(mode):
         assert np.abs(batch["grads"][k] - gsum[k]).max() <= 1e-4 * scale, k
 
 
-@pytest.mark.parametrize("mode", ["presort", "bands"])
+@pytest.mark.parametrize("mode", ["presort", "bands", "onesweep"])
 def test_multi_scene_batch(mode):
     a, b = _small(2000, seed=10), _small(3000, seed=11, deg=3)
     cams = random_cameras(3, 5, (80, 60), radius=4.5)

@@ -57,7 +57,7 @@ def test_projection(name):
     log(f"[P1] {name}: {n} Gaussians checked, {nguard} in the guard band")
 
 
-@pytest.mark.parametrize("sort_mode", ["presort", "full", "bands"])
+@pytest.mark.parametrize("sort_mode", ["presort", "full", "bands", "onesweep"])
 @pytest.mark.parametrize("name", CASES)
 def test_binning(name, sort_mode):
     sc, cam, cfg, _, g = _run(name, sort_mode)
