@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--fwd-ppt", type=int, default=None)
     ap.add_argument("--bwd-ppt", type=int, default=None)
     ap.add_argument("--bwd-lds-batch", type=int, default=None)
+    ap.add_argument("--bwd-split-walk", type=int, default=None,
+                    help="backward: split tiles whose walk reaches this (0: never)")
     ap.add_argument("--schedule", choices=("index", "longest_first", "persistent"), default=None)
     ap.add_argument("--tile-cull", action="store_true",
                     help="time the per-(Gaussian, tile) cull in the main line")
@@ -91,7 +93,7 @@ def main():
     cams = random_cameras(8, 0, (args.width, args.height))
     log(f"[bench] scene {args.n} generated in {time.time() - t0:.1f}s")
     cfg = R.Config(tile=args.tile, lds_batch=args.lds_batch, sh_degree=3, sort_mode=args.sort)
-    for k in ("fwd_ppt", "bwd_ppt", "bwd_lds_batch"):
+    for k in ("fwd_ppt", "bwd_ppt", "bwd_lds_batch", "bwd_split_walk"):
         if getattr(args, k) is not None:
             cfg = dataclasses.replace(cfg, **{k: getattr(args, k)})
     if args.schedule is not None:
@@ -176,8 +178,12 @@ def main():
     flops = flop_bwd if dom == "render_bwd" else flop_fwd
     pers = "true" if cfg.persistent else "false"
     if dom == "render_bwd":
-        kname = (f"xpr::k_render_bwd<{args.tile},{args.tile},"
-                 f"{cfg.bwd_lds_batch or cfg.lds_batch},{cfg.bwd_ppt},{pers}>")
+        if (cfg.bwd_split_walk > 0 and args.tile == 16 and cfg.bwd_ppt == 4
+                and not cfg.persistent):
+            kname = f"xpr::k_render_bwd_split<{cfg.bwd_lds_batch or cfg.lds_batch}>"
+        else:
+            kname = (f"xpr::k_render_bwd<{args.tile},{args.tile},"
+                     f"{cfg.bwd_lds_batch or cfg.lds_batch},{cfg.bwd_ppt},{pers}>")
     else:
         kname = (f"xpr::k_render_fwd<{args.tile},{args.tile},{cfg.lds_batch},{cfg.fwd_ppt},"
                  f"{pers}>")
@@ -209,6 +215,7 @@ def main():
                    "fwd_ppt": cfg.fwd_ppt,
                    "bwd_lds_batch": cfg.bwd_lds_batch or cfg.lds_batch,
                    "bwd_ppt": cfg.bwd_ppt,
+                   "bwd_split_walk": cfg.bwd_split_walk,
                    "schedule": ("persistent" if cfg.persistent else
                                 "longest_first" if cfg.tile_order else "index"),
                    "autotuned": tuned is not None,

@@ -111,6 +111,10 @@ typedef struct xpr_config {
   int32_t tile_cull;      /* 1: per-(Gaussian, tile) cull in xpr_bin_sort (0) */
   int32_t opacity_extents; /* 1: rect from the alpha >= alpha_min extents, not 3 sigma (0) */
   int32_t method;         /* XPR_METHOD_3DGS (0), XPR_METHOD_3DGUT or XPR_METHOD_LINPRIM */
+  int32_t bwd_split_walk; /* 16x16 tiles, bwd_ppt 4, not persistent: a tile whose walk (its
+                           * largest n_contrib) reaches this is walked backward as four
+                           * 16x4 bands by four workgroups, one pixel per lane (at most 64
+                           * tiles per call); 0 = never (default 2048) */
 } xpr_config;
 
 /* One scene of n Gaussians, structure of arrays with leading dimension ld:
@@ -309,7 +313,9 @@ xpr_status xpr_render_fwd(const xpr_views* views, const xpr_config* cfg, const x
                           const xpr_bins* bins, float* image, float* T_final, int32_t* n_contrib,
                           int32_t* tile_work, hipStream_t stream);
 
-/* Workspace bytes xpr_render_bwd needs (per-record 2D gradients). */
+/* Workspace bytes xpr_render_bwd needs: the tile data of the split backward
+ * (bwd_split_walk; 4 bytes per tile plus 512) followed by the per-record 2D
+ * gradients (36 bytes per record, used when grad2d is NULL). */
 xpr_status xpr_render_bwd_workspace(const xpr_views* views, const xpr_config* cfg, size_t* bytes);
 
 /* Backward of compositing and projection: the derivative of the blending
@@ -346,9 +352,10 @@ xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const x
 /* xpr_render_bwd for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * the same computation with grads required and grad2d / the workspace
- * replaced by a file-scope static device array of 64 MiB per device (the
- * per-record 2D gradients, 36 bytes per record: at most 1,864,135 records;
- * more fail with XPR_ERR_CAPACITY before anything is enqueued). Calls no
+ * replaced by a file-scope static device array of 64 MiB per device (1 MiB
+ * of split-backward tile data, used for batches of up to 200,000 tiles,
+ * then the per-record 2D gradients, 36 bytes per record: at most 1,835,008
+ * records; more fail with XPR_ERR_CAPACITY before anything is enqueued). Calls no
  * hipMalloc, hipFree or other allocating routine; the caller still owns
  * every input and the gradient buffers. Every call on a device shares that
  * device's array, which is zero-filled at the start of each call by a

@@ -44,7 +44,7 @@ class XprConfig(ctypes.Structure):
                 ("z_near", _f), ("fov_clip", _f), ("bg", _f * 3), ("sort_mode", _i32),
                 ("no_sync", _i32), ("fwd_ppt", _i32), ("bwd_ppt", _i32),
                 ("bwd_lds_batch", _i32), ("persistent", _i32), ("tile_cull", _i32),
-                ("opacity_extents", _i32), ("method", _i32)]
+                ("opacity_extents", _i32), ("method", _i32), ("bwd_split_walk", _i32)]
 
 
 class XprScene(ctypes.Structure):

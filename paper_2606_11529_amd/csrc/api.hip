@@ -38,9 +38,11 @@ hipError_t launch_render_fwd(const Batch& B, int lds_batch, int ppt, bool persis
                              int32_t* order, float* image, float* Tfin, int32_t* ncon,
                              int32_t* tile_work, hipStream_t st);
 hipError_t launch_render_bwd(const Batch& B, int lds_batch, int ppt, bool persistent,
-                             const float* splat, const int32_t* vals, const int32_t* ranges,
-                             int32_t* order, const float* dimg, const float* Tfin,
-                             const int32_t* ncon, float* grad2d, hipStream_t st);
+                             int split_walk, int32_t* split_meta, const float* splat,
+                             const int32_t* vals, const int32_t* ranges, int32_t* order,
+                             const float* dimg, const float* Tfin, const int32_t* ncon,
+                             float* grad2d, hipStream_t st);
+size_t split_meta_bytes(int64_t tiles);
 hipError_t fill_zero_f32(float* p, int64_t n, hipStream_t st);
 hipError_t launch_l1_loss(const float* img, const float* tgt, int64_t n, float* loss,
                           float* dimg, hipStream_t st);
@@ -103,6 +105,7 @@ static xpr_status check_config(const xpr_config* c) {
             c->fwd_ppt);
   XPR_CHECK(c->bwd_ppt == 1 || c->bwd_ppt == 2 || c->bwd_ppt == 4, "bwd_ppt %d not in {1,2,4}",
             c->bwd_ppt);
+  XPR_CHECK(c->bwd_split_walk >= 0, "bwd_split_walk < 0");
   XPR_CHECK(c->bwd_lds_batch == 0 || c->bwd_lds_batch == 64 || c->bwd_lds_batch == 128 ||
                 c->bwd_lds_batch == 256 || c->bwd_lds_batch == 512,
             "bwd_lds_batch %d not in {0,64,128,256,512}", c->bwd_lds_batch);
@@ -262,6 +265,7 @@ void xpr_config_default(xpr_config* c) {
   c->no_sync = 0;
   c->fwd_ppt = 2;
   c->bwd_ppt = 4;
+  c->bwd_split_walk = 2048;
   c->bwd_lds_batch = 0;
   c->persistent = 0;
   c->tile_cull = 0;
@@ -405,7 +409,7 @@ xpr_status xpr_render_bwd_workspace(const xpr_views* views, const xpr_config* cf
   xpr_status st = build_batch(views, cfg, &B, &S);
   if (st != XPR_OK) return st;
   XPR_CHECK(bytes != nullptr, "bytes is NULL");
-  *bytes = (size_t)9 * sizeof(float) * (size_t)std::max<int64_t>(S.records, 1);
+  *bytes = split_meta_bytes(S.tiles) + (size_t)9 * sizeof(float) * (size_t)std::max<int64_t>(S.records, 1);
   return XPR_OK;
 }
 
@@ -418,7 +422,8 @@ static xpr_status render_bwd_impl(const xpr_views* views, const xpr_config* cfg,
                                   const float* dL_dimage, const float* T_final,
                                   const int32_t* n_contrib, const xpr_scene_grad* grads,
                                   int32_t accumulate, float* grad2d, void* ws, size_t ws_bytes,
-                                  float* g2, int64_t g2_max_records, hipStream_t stream) {
+                                  float* g2, int64_t g2_max_records, int32_t* split_meta,
+                                  hipStream_t stream) {
   Batch B;
   Sizes S;
   xpr_status st = build_batch(views, cfg, &B, &S);
@@ -435,6 +440,9 @@ static xpr_status render_bwd_impl(const xpr_views* views, const xpr_config* cfg,
   XPR_CHECK(aligned(dL_dimage, 4) && aligned(T_final, 4) && aligned(n_contrib, 4) &&
                 aligned(bins->tile_ranges, 8) && (!grad2d || aligned(grad2d, 4)),
             "misaligned buffer");
+  // workspace: [split metadata][2D gradients unless grad2d is given]; the
+  // static scratch path passes both parts itself
+  const size_t meta_bytes = split_meta_bytes(S.tiles);
   if (g2) {
     if (S.records > g2_max_records) {
       set_error("%lld records need %lld bytes of 2D gradients; the static scratch holds %lld "
@@ -445,12 +453,14 @@ static xpr_status render_bwd_impl(const xpr_views* views, const xpr_config* cfg,
     }
   } else {
     g2 = grad2d;
+    if (ws) XPR_CHECK(aligned(ws, 16), "workspace misaligned");
+    if (ws && ws_bytes >= meta_bytes) split_meta = static_cast<int32_t*>(ws);
   }
   if (!g2) {
-    const size_t need = (size_t)9 * sizeof(float) * (size_t)std::max<int64_t>(S.records, 1);
+    const size_t need =
+        meta_bytes + (size_t)9 * sizeof(float) * (size_t)std::max<int64_t>(S.records, 1);
     XPR_CHECK(ws && ws_bytes >= need, "workspace too small: %zu < %zu bytes", ws_bytes, need);
-    XPR_CHECK(aligned(ws, 16), "workspace misaligned");
-    g2 = static_cast<float*>(ws);
+    g2 = reinterpret_cast<float*>(static_cast<char*>(ws) + meta_bytes);
   }
   GradDev G[XPR_MAX_SCENES];
   if (grads) {
@@ -459,9 +469,9 @@ static xpr_status render_bwd_impl(const xpr_views* views, const xpr_config* cfg,
   }
   XPR_HIP(fill_zero_f32(g2, 9 * S.records, stream));
   const int bwd_lds = cfg->bwd_lds_batch ? cfg->bwd_lds_batch : cfg->lds_batch;
-  XPR_HIP(launch_render_bwd(B, bwd_lds, cfg->bwd_ppt, cfg->persistent != 0, proj->splat,
-                            bins->vals, bins->tile_ranges, bins->tile_order, dL_dimage, T_final,
-                            n_contrib, g2, stream));
+  XPR_HIP(launch_render_bwd(B, bwd_lds, cfg->bwd_ppt, cfg->persistent != 0, cfg->bwd_split_walk,
+                            split_meta, proj->splat, bins->vals, bins->tile_ranges,
+                            bins->tile_order, dL_dimage, T_final, n_contrib, g2, stream));
   if (grads)
     XPR_HIP(launch_project_bwd(B, S.max_n, g2, proj->tiles_touched, G, accumulate ? 1 : 0, stream));
   return XPR_OK;
@@ -473,7 +483,12 @@ static xpr_status render_bwd_impl(const xpr_views* views, const xpr_config* cfg,
 // device memory: kernels and fills get the address hipGetSymbolAddress
 // returns on each device.
 constexpr size_t kScratchBytes = (size_t)64 << 20;
-constexpr int64_t kScratchRecords = (int64_t)(kScratchBytes / (9 * sizeof(float)));
+// the first 1 MiB holds the split backward's tile data (its size for
+// kScratchTiles tiles is 800,768 bytes; larger batches are walked unsplit)
+constexpr size_t kScratchMetaBytes = (size_t)1 << 20;
+constexpr int64_t kScratchTiles = 200000;
+constexpr int64_t kScratchRecords =
+    (int64_t)((kScratchBytes - kScratchMetaBytes) / (9 * sizeof(float)));
 static __device__ __align__(256) float scratch[kScratchBytes / sizeof(float)];
 
 constexpr int kMaxDevices = 64;
@@ -506,7 +521,7 @@ xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const x
                           hipStream_t stream) {
   g_err[0] = 0;
   return render_bwd_impl(views, cfg, proj, bins, dL_dimage, T_final, n_contrib, grads,
-                         accumulate, grad2d, ws, ws_bytes, nullptr, 0, stream);
+                         accumulate, grad2d, ws, ws_bytes, nullptr, 0, nullptr, stream);
 }
 
 xpr_status xpr_render_bwd_noalloc(const xpr_views* views, const xpr_config* cfg,
@@ -528,11 +543,13 @@ xpr_status xpr_render_bwd_noalloc(const xpr_views* views, const xpr_config* cfg,
               (long long)kScratchRecords);
     return XPR_ERR_CAPACITY;
   }
-  float* g2 = nullptr;
-  st = scratch_of_current_device(&g2);
+  float* base = nullptr;
+  st = scratch_of_current_device(&base);
   if (st != XPR_OK) return st;
+  int32_t* meta = S.tiles <= kScratchTiles ? reinterpret_cast<int32_t*>(base) : nullptr;
+  float* g2 = base + kScratchMetaBytes / sizeof(float);
   return render_bwd_impl(views, cfg, proj, bins, dL_dimage, T_final, n_contrib, grads,
-                         accumulate, nullptr, nullptr, 0, g2, kScratchRecords, stream);
+                         accumulate, nullptr, nullptr, 0, g2, kScratchRecords, meta, stream);
 }
 
 xpr_status xpr_l1_loss(const float* image, const float* target, int64_t n, float* loss,

@@ -336,17 +336,20 @@ __device__ __forceinline__ void reduce_pair(const float (&X)[9], const float (&Y
   }
 }
 
-template <int TW, int TH, int BATCH, int PPT>
-__device__ __forceinline__ void bwd_tile(const Batch& B, int g, const float4* __restrict__ splat,
+// The backward of the pixel rows [y_off, y_off + TROWS) of tile g (TROWS =
+// TH: the whole tile).
+template <int TW, int TH, int TROWS, int BATCH, int PPT>
+__device__ __forceinline__ void bwd_tile(const Batch& B, int g, int y_off,
+                                         const float4* __restrict__ splat,
                                          const int32_t* __restrict__ vals,
                                          const int2* __restrict__ ranges,
                                          const float* __restrict__ dimg,
                                          const float* __restrict__ Tfin,
                                          const int32_t* __restrict__ ncon,
                                          float* __restrict__ grad2d,
-                                         Stage<BATCH, (TW * TH / PPT + 63) / 64>& S,
+                                         Stage<BATCH, (TW * TROWS / PPT + 63) / 64>& S,
                                          int32_t* s_maxlast_p) {
-  constexpr int NT = TW * TH / PPT;
+  constexpr int NT = TW * TROWS / PPT;
   constexpr int NW = (NT + 63) / 64;
   constexpr int RPW = 64 * PPT / TW;  // pixel rows per wave
   int32_t& s_maxlast = *s_maxlast_p;
@@ -354,7 +357,7 @@ __device__ __forceinline__ void bwd_tile(const Batch& B, int g, const float4* __
   const int lt = g - V.tile_off;
   const int ty = lt / V.tiles_x, tx = lt - ty * V.tiles_x;
   const int px = tx * TW + (int)(threadIdx.x % TW);
-  const int py0 = ty * TH + (int)(threadIdx.x / TW) * PPT;
+  const int py0 = ty * TH + y_off + (int)(threadIdx.x / TW) * PPT;
   const int2 rg = ranges[g];
   const float fpx = (float)px;
   const float amax = B.alpha_max, amin = B.alpha_min;
@@ -473,8 +476,8 @@ __device__ __forceinline__ void bwd_tile(const Batch& B, int g, const float4* __
       const int r = vals[lo + k];
       S.rec[k] = r;
       stage_record(splat, (size_t)r, amin, S.s0[k], S.s1[k], S.s2[k]);
-      S.mask[k] = (uint8_t)wave_mask(S.s0[k], S.s1[k], tx * TW, tx * TW + TW - 1, ty * TH, RPW,
-                                     NW);
+      S.mask[k] = (uint8_t)wave_mask(S.s0[k], S.s1[k], tx * TW, tx * TW + TW - 1,
+                                     ty * TH + y_off, RPW, NW);
     }
     __syncthreads();
     const int cnt = build_wave_list(S, hi - lo, wv, wlast + rg.x - lo - 1);
@@ -509,14 +512,94 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_render_bwd(
   __shared__ int32_t s_maxlast;
   if (!PERSIST) {
     const int g = order ? order[blockIdx.x] : (int)blockIdx.x;
-    bwd_tile<TW, TH, BATCH, PPT>(B, g, splat, vals, ranges, dimg, Tfin, ncon, grad2d, S,
-                                 &s_maxlast);
+    bwd_tile<TW, TH, TH, BATCH, PPT>(B, g, 0, splat, vals, ranges, dimg, Tfin, ncon, grad2d, S,
+                                     &s_maxlast);
     return;
   }
   __shared__ int s_next;
   for (int q = next_tile(&s_next, qhead); q < B.total_tiles; q = next_tile(&s_next, qhead))
-    bwd_tile<TW, TH, BATCH, PPT>(B, order[q], splat, vals, ranges, dimg, Tfin, ncon, grad2d, S,
-                                 &s_maxlast);
+    bwd_tile<TW, TH, TH, BATCH, PPT>(B, order[q], 0, splat, vals, ranges, dimg, Tfin, ncon,
+                                     grad2d, S, &s_maxlast);
+}
+
+// Backward with heavy tiles split (16x16 tiles). A first kernel finds each
+// tile's walk -- the largest n_contrib over its pixels -- and gives the
+// tiles whose walk reaches split_walk a slot in a short list (at most
+// kSplitMaxHeavy; tiles beyond it stay whole). Such a tile is walked as four
+// 16x4 bands at one pixel per lane, by four one-wave workgroups each with
+// its own walk and record list, instead of by one wave at four pixels per
+// lane: its waves would otherwise walk thousands of entries long after the
+// other tiles are done. The grid is 3 kSplitMaxHeavy workgroups for bands
+// 1..3 of the listed tiles (first, so they start early; those past the
+// list's length return at once), then one per tile: band 0 of a listed
+// tile, else the whole tile. Split metadata (int32): [0] list length,
+// [kSplitHeavyOff + h] the listed tiles, [kSplitSlotOff + g] tile g's slot
+// or -1.
+constexpr int kSplitMaxHeavy = 64;
+constexpr int kSplitHeavyOff = 64;
+constexpr int kSplitSlotOff = kSplitHeavyOff + kSplitMaxHeavy;
+
+__global__ __launch_bounds__(256) void k_tile_walks(Batch B, const int32_t* __restrict__ ncon,
+                                                    int split_walk, int32_t* __restrict__ meta) {
+  const int g = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  if (g >= B.total_tiles) return;
+  const int lane = (int)(threadIdx.x & 63u);
+  const ViewDev& V = B.v[view_of_tile(B, g)];
+  const int lt = g - V.tile_off;
+  const int ty = lt / V.tiles_x, tx = lt - ty * V.tiles_x;
+  const int px = tx * 16 + (lane & 15);
+  const int py0 = ty * 16 + (lane >> 4) * 4;
+  int walk = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (px < V.W && py0 + j < V.H)
+      walk = max(walk, ncon[(size_t)V.pix_off + (size_t)(py0 + j) * V.W + px]);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) walk = max(walk, __shfl_xor(walk, o, 64));
+  if (lane == 0) {
+    int slot = -1;
+    if (walk >= split_walk) {
+      const int h = atomicAdd(&meta[0], 1);
+      if (h < kSplitMaxHeavy) {
+        meta[kSplitHeavyOff + h] = g;
+        slot = h;
+      }
+    }
+    meta[kSplitSlotOff + g] = slot;
+  }
+}
+
+template <int BATCH>
+__global__ __launch_bounds__(64) void k_render_bwd_split(
+    Batch B, const float4* __restrict__ splat, const int32_t* __restrict__ vals,
+    const int2* __restrict__ ranges, const float* __restrict__ dimg,
+    const float* __restrict__ Tfin, const int32_t* __restrict__ ncon,
+    float* __restrict__ grad2d, const int32_t* order, const int32_t* __restrict__ meta) {
+  __shared__ Stage<BATCH, 1> S;
+  __shared__ int32_t s_maxlast;
+  constexpr int NX = 3 * kSplitMaxHeavy;
+  int g, band;
+  if ((int)blockIdx.x < NX) {
+    const int h = (int)blockIdx.x / 3;
+    if (h >= min(meta[0], kSplitMaxHeavy)) return;
+    g = meta[kSplitHeavyOff + h];
+    band = 1 + (int)blockIdx.x % 3;
+  } else {
+    const int q = (int)blockIdx.x - NX;
+    g = order ? order[q] : q;
+    if (meta[kSplitSlotOff + g] < 0) {
+      bwd_tile<16, 16, 16, BATCH, 4>(B, g, 0, splat, vals, ranges, dimg, Tfin, ncon, grad2d, S,
+                                     &s_maxlast);
+      return;
+    }
+    band = 0;
+  }
+  bwd_tile<16, 16, 4, BATCH, 1>(B, g, 4 * band, splat, vals, ranges, dimg, Tfin, ncon, grad2d, S,
+                                &s_maxlast);
+}
+
+size_t split_meta_bytes(int64_t tiles) {
+  return (((size_t)(kSplitSlotOff + tiles) * sizeof(int32_t)) + 255) & ~(size_t)255;
 }
 
 // Launchers ------------------------------------------------------------------
@@ -653,10 +736,18 @@ hipError_t launch_render_fwd(const Batch& B, int lds_batch, int ppt, bool persis
   return hipGetLastError();
 }
 
+template <int BATCH>
+static void launch_bwd_split(const Batch& B, const RenderArgs& A, int32_t* meta, hipStream_t st) {
+  hipLaunchKernelGGL((k_render_bwd_split<BATCH>), dim3(3 * kSplitMaxHeavy + B.total_tiles),
+                     dim3(64), 0, st, B, A.splat, A.vals, A.ranges, A.dimg, A.Tfin_in, A.ncon_in,
+                     A.grad2d, A.order, meta);
+}
+
 hipError_t launch_render_bwd(const Batch& B, int lds_batch, int ppt, bool persistent,
-                             const float* splat, const int32_t* vals, const int32_t* ranges,
-                             int32_t* order, const float* dimg, const float* Tfin,
-                             const int32_t* ncon, float* grad2d, hipStream_t st) {
+                             int split_walk, int32_t* split_meta, const float* splat,
+                             const int32_t* vals, const int32_t* ranges, int32_t* order,
+                             const float* dimg, const float* Tfin, const int32_t* ncon,
+                             float* grad2d, hipStream_t st) {
   if (B.total_tiles <= 0) return hipSuccess;
   RenderArgs A{};
   A.splat = reinterpret_cast<const float4*>(splat);
@@ -669,6 +760,18 @@ hipError_t launch_render_bwd(const Batch& B, int lds_batch, int ppt, bool persis
   A.order = order;
   A.qhead = order ? order + B.total_tiles : nullptr;
   A.persistent = persistent && order;
+  if (split_walk > 0 && split_meta && !A.persistent && B.tile_w == 16 && ppt == 4) {
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, split_meta);
+    hipLaunchKernelGGL(k_tile_walks, dim3((B.total_tiles + 3) / 4), dim3(256), 0, st, B,
+                       A.ncon_in, split_walk, split_meta);
+    switch (lds_batch) {
+      case 64: launch_bwd_split<64>(B, A, split_meta, st); break;
+      case 128: launch_bwd_split<128>(B, A, split_meta, st); break;
+      case 512: launch_bwd_split<512>(B, A, split_meta, st); break;
+      default: launch_bwd_split<256>(B, A, split_meta, st); break;
+    }
+    return hipGetLastError();
+  }
   launch_render(B, lds_batch, ppt, A, true, st);
   return hipGetLastError();
 }

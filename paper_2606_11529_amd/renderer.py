@@ -40,6 +40,7 @@ class Config:
     tile_cull: bool = False     # per-(Gaussian, tile) cull of XPR-3DGS in the binning
     opacity_extents: bool = False  # rect from the alpha >= alpha_min ellipse, not 3 sigma
     method: str = "3dgs"        # "3dgs", "3dgut" or "linprim" (the last two forward only)
+    bwd_split_walk: int = 2048  # backward: tiles whose walk reaches this go as four bands
 
     def to_c(self) -> L.XprConfig:
         c = L.XprConfig()
@@ -71,6 +72,7 @@ class Config:
         if self.method not in methods:
             raise ValueError(f"unknown method {self.method!r}")
         c.method = methods[self.method]
+        c.bwd_split_walk = int(self.bwd_split_walk)
         return c
 
 

@@ -143,7 +143,10 @@ def test_workspace_queries_host_only():
     assert 0 < a < b
     c.sort_mode = L.XPR_SORT_FULL
     assert L.xpr_bin_sort_workspace(v, c, 100_000) > 0
-    assert L.xpr_render_bwd_workspace(v, c) == 9 * 4 * 1000
+    # the split backward's tile data (128 words + 1 per tile, in 256-byte
+    # units), then 36 bytes per record
+    meta = -(-(128 + 12) * 4 // 256) * 256
+    assert L.xpr_render_bwd_workspace(v, c) == meta + 9 * 4 * 1000
     with pytest.raises(L.XprError):
         L.xpr_bin_sort_workspace(v, c, -1)
 
@@ -160,8 +163,9 @@ def test_bin_sort_rejects_small_workspace():
 
 
 def test_noalloc_backward_rejects_more_records_than_its_scratch():
-    # 1,864,135 records fit the 64 MiB static scratch (36 bytes each); one
-    # more view of a 1M scene is refused on the host, before any device call
+    # 1,835,008 records fit the 63 MiB of the static scratch left after the
+    # split backward's tile data (36 bytes each); a second view of a 1M
+    # scene is refused on the host, before any device call
     c = L.xpr_config_default()
     grads = (L.XprSceneGrad * 1)(L.XprSceneGrad(4096, 4096, 4096, 4096, 4096))
     args = (L.XprProjected(4096, 4096, 4096, 4096), L.XprBins(None, 4096, 4096, 4096, None, 10))
@@ -170,7 +174,7 @@ def test_noalloc_backward_rejects_more_records_than_its_scratch():
                                         ctypes.byref(args[1]), 4096, 4096, 4096, grads, 0, None)
     assert st == L.XPR_ERR_CAPACITY
     msg = L.xpr_last_error()
-    assert "2000000 records" in msg and "1864135 records" in msg
+    assert "2000000 records" in msg and "1835008 records" in msg
     st = L.lib().xpr_render_bwd_noalloc(ctypes.byref(v), ctypes.byref(c), ctypes.byref(args[0]),
                                         ctypes.byref(args[1]), 4096, 4096, 4096, None, 0, None)
     assert st == L.XPR_ERR_INVALID_ARG and "grads" in L.xpr_last_error()
