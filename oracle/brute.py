@@ -176,12 +176,19 @@ def render(scene, cam, cfg: OracleConfig):
 
 def render_gut(scene, cam, cfg: OracleConfig):
     """Per-pixel brute force of 3DGUT (Listing "Implementation of
-    XPR-3DGUT"), forward only, in torch float64: unscented-transform
-    projection (rect, visibility, adjusted opacity), then for every pixel the
-    ray response of every visible Gaussian whose rect contains the pixel's
-    tile, in (float32 depth, index) order, with the validity threshold and
-    the gates of the 3DGS path. No pairs, no sort, no tile ranges."""
-    means, scales, quats, opac, sh = scene_tensors(scene)
+    XPR-3DGUT") in torch float64: unscented-transform projection (rect,
+    visibility, adjusted opacity), then for every pixel the ray response of
+    every visible Gaussian whose rect contains the pixel's tile, in (float32
+    depth, index) order, with the validity threshold and the gates of the
+    3DGS path. No pairs, no sort, no tile ranges. Returns numpy arrays."""
+    with torch.no_grad():
+        img, T = render_gut_torch(*scene_tensors(scene), cam, cfg)
+    return img.numpy(), T.numpy()
+
+
+def render_gut_torch(means, scales, quats, opac, sh, cam, cfg: OracleConfig):
+    """render_gut on tensors, differentiable (decisions on detached values):
+    returns image [3, H, W] and T_final [H, W] tensors."""
     G = opac.shape[0]
     Rw = torch.as_tensor(np.asarray(cam.R), dtype=torch.float64)
     tw = torch.as_tensor(np.asarray(cam.t), dtype=torch.float64)
@@ -243,7 +250,7 @@ def render_gut(scene, cam, cfg: OracleConfig):
     rd = dc @ Rw                                             # R^T dc per row
     ptx = (xs // cfg.tile_w).long()
     pty = (ys // cfg.tile_h).long()
-    order = np.lexsort((np.arange(G), Y[:, 0, 2].to(torch.float32).numpy()))
+    order = np.lexsort((np.arange(G), Y[:, 0, 2].detach().to(torch.float32).numpy()))
     img = torch.zeros(3, H * W, dtype=torch.float64)
     T = torch.ones(H * W, dtype=torch.float64)
     done = torch.zeros(H * W, dtype=torch.bool)
@@ -256,16 +263,17 @@ def render_gut(scene, cam, cfg: OracleConfig):
         p = ro[g][None, :] + tau[:, None] * rdc
         resp = torch.exp(-0.5 * (p * p).sum(1))
         alpha = torch.clamp(o2[g] * resp, max=cfg.alpha_max)
-        live = inside & ~done & (resp > 0.0113) & (alpha >= cfg.alpha_min)
-        Tn = T * (1 - alpha)
-        stop = live & (Tn < cfg.t_min)
-        done = done | stop
-        blend = live & ~stop
+        with torch.no_grad():
+            live = inside & ~done & (resp > 0.0113) & (alpha >= cfg.alpha_min)
+            Tn = T * (1 - alpha)
+            stop = live & (Tn < cfg.t_min)
+            done = done | stop
+            blend = live & ~stop
         a_ = torch.where(blend, alpha, torch.zeros_like(alpha))
         img = img + colour[g][:, None] * (a_ * T)[None, :]
         T = T * (1 - a_)
     img = img + T[None, :] * torch.as_tensor(cfg.bg, dtype=torch.float64)[:, None]
-    return img.view(3, H, W).numpy(), T.view(H, W).numpy()
+    return img.view(3, H, W), T.view(H, W)
 
 
 def render_lin(scene, cam, cfg: OracleConfig):

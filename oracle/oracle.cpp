@@ -1412,4 +1412,260 @@ void orc_project_bwd(int64_t n, const double* means, const double* scales, const
   }
 }
 
+
+// ----------------------------------------------------------------------------
+// 3DGUT backward. The forward (Listing XPR-3DGUT: the unscented-transform
+// project, pixel_info and evaluate, blended by Algorithm 1) differentiated
+// by hand, as the paper obtains it by automatic differentiation (section Key
+// Interfaces). The shader data's derivative is taken with respect to the 16
+// values the evaluation reads: the adjusted opacity o', the colour (3), the
+// canonical ray origin ro (3) and M = S^-1 R^T (9, row-major); the 2D mean
+// and conic of the record only place the rect, which is piecewise constant.
+// ----------------------------------------------------------------------------
+
+// dL/d(o', r, g, b, ro, M) per record [n][16] from dL/dimage [3][H][W]:
+// per pixel the blended entries are found front to back (as in
+// orc_render_fwd_gut), then walked back with the colour behind S, as in
+// orc_render_bwd. With resp = exp(-d2 / 2), d2 = |ro|^2 - (ro . w)^2 / |w|^2
+// and w = M rd (rd the pixel's world ray): dL/do' = resp dL/dalpha,
+// dL/dd2 = -resp o' dL/dalpha / 2, and the chain to ro and w, then M.
+void orc_render_bwd_gut(int W, int H, int tile_w, int tile_h, int64_t n, const double* rec,
+                        const int32_t* vals, const int32_t* ranges, const double* camv,
+                        const double* cfg, const double* dimg, double* grad) {
+  const Cam cam = read_cam(camv, W, H);
+  const double alpha_min = cfg[0], alpha_max = cfg[1], t_min = cfg[2];
+  const double bg[3] = {cfg[3], cfg[4], cfg[5]};
+  const double valid_min = 0.0113;
+  const int tiles_x = (W + tile_w - 1) / tile_w;
+  const int tiles_y = (H + tile_h - 1) / tile_h;
+  int nthreads = 1;
+#ifdef _OPENMP
+  nthreads = omp_get_max_threads();
+#endif
+  std::vector<std::vector<double>> part(nthreads);
+#pragma omp parallel
+  {
+    int tid = 0;
+#ifdef _OPENMP
+    tid = omp_get_thread_num();
+#endif
+    std::vector<double>& acc = part[tid];
+    acc.assign((size_t)n * 16, 0.0);
+    struct Step { int64_t g; double alpha, T, resp; bool clamped; };
+    std::vector<Step> steps;
+#pragma omp for schedule(dynamic, 1)
+    for (int t = 0; t < tiles_x * tiles_y; ++t) {
+      const int tx = t % tiles_x, ty = t / tiles_x;
+      const int32_t start = ranges[2 * t], end = ranges[2 * t + 1];
+      for (int py = ty * tile_h; py < std::min(H, (ty + 1) * tile_h); ++py)
+        for (int px = tx * tile_w; px < std::min(W, (tx + 1) * tile_w); ++px) {
+          double rd[3];
+          gut_ray(cam, px, py, rd);
+          steps.clear();
+          double T = 1.0;
+          for (int32_t k = start; k < end; ++k) {
+            const int64_t gi = vals[k];
+            const double* r = rec + 21 * gi;
+            const double resp = gut_response(r + 9, r + 12, rd);
+            if (!(resp > valid_min)) continue;
+            const double raw = r[5] * resp;
+            const double alpha = std::min(alpha_max, raw);
+            if (alpha < alpha_min) continue;
+            const double Tn = T * (1.0 - alpha);
+            if (Tn < t_min) break;
+            steps.push_back(Step{gi, alpha, T, resp, raw > alpha_max});
+            T = Tn;
+          }
+          const double Tfin = T;
+          const int64_t p = (int64_t)py * W + px;
+          const double G[3] = {dimg[p], dimg[(int64_t)W * H + p], dimg[2 * (int64_t)W * H + p]};
+          const double bgG = bg[0] * G[0] + bg[1] * G[1] + bg[2] * G[2];
+          double S[3] = {0, 0, 0};
+          for (int si = (int)steps.size() - 1; si >= 0; --si) {
+            const Step& st = steps[si];
+            const double* r = rec + 21 * st.g;
+            double* ga = acc.data() + 16 * st.g;
+            double dalpha = 0;
+            for (int c = 0; c < 3; ++c) {
+              ga[1 + c] += st.alpha * st.T * G[c];
+              dalpha += st.T * (r[6 + c] - S[c]) * G[c];
+            }
+            dalpha -= Tfin * bgG / (1.0 - st.alpha);
+            for (int c = 0; c < 3; ++c) S[c] = st.alpha * r[6 + c] + (1.0 - st.alpha) * S[c];
+            if (st.clamped) continue;
+            ga[0] += st.resp * dalpha;
+            const double dd2 = -0.5 * st.resp * r[5] * dalpha;
+            const double* ro = r + 9;
+            const double* M = r + 12;
+            double w[3];
+            for (int a = 0; a < 3; ++a) w[a] = M[3 * a] * rd[0] + M[3 * a + 1] * rd[1] + M[3 * a + 2] * rd[2];
+            const double rw = ro[0] * w[0] + ro[1] * w[1] + ro[2] * w[2];
+            const double ww = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+            for (int a = 0; a < 3; ++a) {
+              ga[4 + a] += dd2 * (2.0 * ro[a] - 2.0 * rw / ww * w[a]);
+              const double gw = dd2 * (-2.0 * rw / ww * ro[a] + 2.0 * rw * rw / (ww * ww) * w[a]);
+              for (int b = 0; b < 3; ++b) ga[7 + 3 * a + b] += gw * rd[b];
+            }
+          }
+        }
+    }
+  }
+  for (int64_t k = 0; k < n * 16; ++k) {
+    double s = 0;
+    for (int th = 0; th < nthreads; ++th)
+      if (!part[th].empty()) s += part[th][k];
+    grad[k] = s;
+  }
+}
+
+// Backward of the 3DGUT projection: from dL/d(o', colour, ro, M) [n][16] to
+// the gradients of the inputs (activated scales and opacity, raw
+// quaternion), [k][n] like the inputs, overwritten. Through o' = o comp,
+// comp = sqrt(det_orig / det), the unscented transform's 2D covariance and
+// its seven projected sigma points; through ro = M (campos - mu) and
+// M = S^-1 R^T; through the colour as for 3DGS. Gaussians that are not
+// visible get zero.
+void orc_project_bwd_gut(int64_t n, const double* means, const double* scales,
+                         const double* quats, const double* opac, const double* sh, int K,
+                         const double* camv, int W, int H, const double* cfg, int tile_w,
+                         int tile_h, int deg, const double* grad, double* g_means,
+                         double* g_scales, double* g_quats, double* g_opac, double* g_sh) {
+  const Cam cam = read_cam(camv, W, H);
+  const double lowpass = cfg[0];
+  const int nb = (deg + 1) * (deg + 1);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    for (int c = 0; c < 3; ++c) { g_means[c * n + i] = 0; g_scales[c * n + i] = 0; }
+    for (int c = 0; c < 4; ++c) g_quats[c * n + i] = 0;
+    g_opac[i] = 0;
+    for (int j = 0; j < K; ++j)
+      for (int ch = 0; ch < 3; ++ch) g_sh[(int64_t)(j * 3 + ch) * n + i] = 0;
+    GutProj Gp;
+    project_gut_one(i, n, means, scales, quats, opac, sh, cam, cfg, tile_w, tile_h, deg, Gp);
+    if (Gp.tc == 0) continue;
+    const double* g = grad + 16 * i;
+    const double mu[3] = {means[i], means[n + i], means[2 * n + i]};
+    const double q[4] = {quats[i], quats[n + i], quats[2 * n + i], quats[3 * n + i]};
+    const double qnorm = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const double qn[4] = {q[0] / qnorm, q[1] / qnorm, q[2] / qnorm, q[3] / qnorm};
+    double Rq[9];
+    quat_to_rot(qn, Rq);
+    const double s[3] = {scales[i], scales[n + i], scales[2 * n + i]};
+    const double cp[3] = {
+        -(cam.R[0] * cam.t[0] + cam.R[3] * cam.t[1] + cam.R[6] * cam.t[2]),
+        -(cam.R[1] * cam.t[0] + cam.R[4] * cam.t[1] + cam.R[7] * cam.t[2]),
+        -(cam.R[2] * cam.t[0] + cam.R[5] * cam.t[1] + cam.R[8] * cam.t[2])};
+    double gmu[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+
+    // colour = max(0, 0.5 + sum_j sh_j Y_j(dir)), dir = (mu - campos) / |.|
+    double dv[3] = {mu[0] - cp[0], mu[1] - cp[1], mu[2] - cp[2]};
+    const double dn = std::sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+    for (int c = 0; c < 3; ++c) dv[c] /= dn;
+    double Y[16], dY[16][3];
+    sh_basis(deg, dv, Y, dY);
+    double gdir[3] = {0, 0, 0};
+    for (int ch = 0; ch < 3; ++ch) {
+      double raw = 0.5;
+      for (int j = 0; j < nb; ++j) raw += sh[(int64_t)(j * 3 + ch) * n + i] * Y[j];
+      const double gr = raw > 0 ? g[1 + ch] : 0.0;
+      for (int j = 0; j < nb; ++j) {
+        g_sh[(int64_t)(j * 3 + ch) * n + i] = Y[j] * gr;
+        const double wgt = sh[(int64_t)(j * 3 + ch) * n + i] * gr;
+        for (int c = 0; c < 3; ++c) gdir[c] += wgt * dY[j][c];
+      }
+    }
+    const double dd = dv[0] * gdir[0] + dv[1] * gdir[1] + dv[2] * gdir[2];
+    for (int c = 0; c < 3; ++c) gmu[c] += (gdir[c] - dv[c] * dd) / dn;
+
+    // ro = M (campos - mu), then M[r][c] = Rq[c][r] / s[r]
+    double gM[9];
+    for (int k = 0; k < 9; ++k) gM[k] = g[7 + k];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        gM[3 * r + c] += g[4 + r] * (cp[c] - mu[c]);
+        gmu[c] -= Gp.M[3 * r + c] * g[4 + r];
+      }
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        gR[3 * c + r] += gM[3 * r + c] / s[r];
+        gs[r] -= gM[3 * r + c] * Rq[3 * c + r] / (s[r] * s[r]);
+      }
+
+    // o' = o comp, comp = sqrt(max(det_orig, 0) / det) over the sigma points
+    const double k3 = std::sqrt(3.0);
+    double X[7][3];
+    for (int c = 0; c < 3; ++c) X[0][c] = mu[c];
+    for (int j = 0; j < 3; ++j)
+      for (int sg = 0; sg < 2; ++sg)
+        for (int c = 0; c < 3; ++c)
+          X[1 + 2 * j + sg][c] = mu[c] + (sg ? -1.0 : 1.0) * k3 * s[j] * Rq[3 * c + j];
+    const double wm[7] = {0.0, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
+    const double wc[7] = {2.0, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
+    double Yc[7][3], P2[7][2];
+    for (int p = 0; p < 7; ++p) {
+      for (int r = 0; r < 3; ++r)
+        Yc[p][r] = cam.R[3 * r] * X[p][0] + cam.R[3 * r + 1] * X[p][1] + cam.R[3 * r + 2] * X[p][2] +
+                   cam.t[r];
+      P2[p][0] = cam.fx * Yc[p][0] / Yc[p][2] + cam.cx;
+      P2[p][1] = cam.fy * Yc[p][1] / Yc[p][2] + cam.cy;
+    }
+    double m2[2] = {0, 0};
+    for (int p = 0; p < 7; ++p) { m2[0] += wm[p] * P2[p][0]; m2[1] += wm[p] * P2[p][1]; }
+    double D[7][2], cxx = 0, cxy = 0, cyy = 0;
+    for (int p = 0; p < 7; ++p) {
+      D[p][0] = P2[p][0] - m2[0];
+      D[p][1] = P2[p][1] - m2[1];
+      cxx += wc[p] * D[p][0] * D[p][0];
+      cxy += wc[p] * D[p][0] * D[p][1];
+      cyy += wc[p] * D[p][1] * D[p][1];
+    }
+    const double det0 = cxx * cyy - cxy * cxy;
+    const double det = (cxx + lowpass) * (cyy + lowpass) - cxy * cxy;
+    const double comp = det > 0 ? std::sqrt(std::max(det0, 0.0) / det) : 0.0;
+    g_opac[i] = comp * g[0];
+    if (det0 > 0 && det > 0) {
+      const double gcomp = opac[i] * g[0];
+      const double gdet0 = gcomp * comp / (2.0 * det0), gdet = -gcomp * comp / (2.0 * det);
+      const double gxx = gdet0 * cyy + gdet * (cyy + lowpass);
+      const double gyy = gdet0 * cxx + gdet * (cxx + lowpass);
+      const double gxy = -2.0 * cxy * (gdet0 + gdet);
+      double gD[7][2], sD[2] = {0, 0};
+      for (int p = 0; p < 7; ++p) {
+        gD[p][0] = wc[p] * (2.0 * D[p][0] * gxx + D[p][1] * gxy);
+        gD[p][1] = wc[p] * (2.0 * D[p][1] * gyy + D[p][0] * gxy);
+        sD[0] += gD[p][0];
+        sD[1] += gD[p][1];
+      }
+      for (int p = 0; p < 7; ++p) {
+        const double gPx = gD[p][0] - wm[p] * sD[0], gPy = gD[p][1] - wm[p] * sD[1];
+        const double z = Yc[p][2];
+        const double gy[3] = {cam.fx / z * gPx, cam.fy / z * gPy,
+                              -(cam.fx * Yc[p][0] * gPx + cam.fy * Yc[p][1] * gPy) / (z * z)};
+        double gX[3];
+        for (int c = 0; c < 3; ++c)
+          gX[c] = cam.R[c] * gy[0] + cam.R[3 + c] * gy[1] + cam.R[6 + c] * gy[2];
+        for (int c = 0; c < 3; ++c) gmu[c] += gX[c];
+        if (p == 0) continue;
+        const int j = (p - 1) / 2;
+        const double sign = ((p - 1) % 2) ? -1.0 : 1.0;
+        for (int c = 0; c < 3; ++c) {
+          gs[j] += sign * k3 * gX[c] * Rq[3 * c + j];
+          gR[3 * c + j] += sign * k3 * s[j] * gX[c];
+        }
+      }
+    }
+    for (int c = 0; c < 3; ++c) {
+      g_means[c * n + i] = gmu[c];
+      g_scales[c * n + i] = gs[c];
+    }
+    double dR[9][4];
+    quat_to_rot_jac(qn, dR);
+    double gqn[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 9; ++k)
+      for (int c = 0; c < 4; ++c) gqn[c] += gR[k] * dR[k][c];
+    const double qd = qn[0] * gqn[0] + qn[1] * gqn[1] + qn[2] * gqn[2] + qn[3] * gqn[3];
+    for (int c = 0; c < 4; ++c) g_quats[c * n + i] = (gqn[c] - qn[c] * qd) / qnorm;
+  }
+}
+
 }  // extern "C"
