@@ -186,9 +186,11 @@ def render_gut(scene, cam, cfg: OracleConfig):
     return img.numpy(), T.numpy()
 
 
-def render_gut_torch(means, scales, quats, opac, sh, cam, cfg: OracleConfig):
+def render_gut_torch(means, scales, quats, opac, sh, cam, cfg: OracleConfig, keep=None):
     """render_gut on tensors, differentiable (decisions on detached values):
-    returns image [3, H, W] and T_final [H, W] tensors."""
+    returns image [3, H, W] and T_final [H, W] tensors. With a dict ``keep``
+    the shader data o' [G], colour [G, 3], ro [G, 3] and M [G, 3, 3] and the
+    camera position are stored in it, their gradients retained."""
     G = opac.shape[0]
     Rw = torch.as_tensor(np.asarray(cam.R), dtype=torch.float64)
     tw = torch.as_tensor(np.asarray(cam.t), dtype=torch.float64)
@@ -240,6 +242,12 @@ def render_gut_torch(means, scales, quats, opac, sh, cam, cfg: OracleConfig):
     nb = (cfg.sh_degree + 1) ** 2
     colour = torch.clamp(0.5 + torch.einsum("gj,gjc->gc", _sh_real(cfg.sh_degree, dirs),
                                             sh[:, :nb, :]), min=0.0)
+    if keep is not None:
+        for name, v in (("o2", o2), ("colour", colour), ("ro", ro), ("M", Minv)):
+            if v.requires_grad:
+                v.retain_grad()
+            keep[name] = v
+        keep["campos"] = campos
     W, H = cam.width, cam.height
     ys, xs = torch.meshgrid(torch.arange(H, dtype=torch.float64),
                             torch.arange(W, dtype=torch.float64), indexing="ij")

@@ -1421,14 +1421,24 @@ void orc_project_bwd(int64_t n, const double* means, const double* scales, const
 // values the evaluation reads: the adjusted opacity o', the colour (3), the
 // canonical ray origin ro (3) and M = S^-1 R^T (9, row-major); the 2D mean
 // and conic of the record only place the rect, which is piecewise constant.
+// The derivative with respect to M holds the Gaussian's centre fixed, i.e.
+// ro = M d moves with M for d = M^-1 ro (the camera position minus the
+// centre): dL/dM|centre = dL/dM|ro + dL/dro d^T. The two terms on the right
+// are each about |d| / |x| times larger than their sum (x below), so
+// forming the sum per pixel in float64 keeps the scale and rotation
+// gradients that follow from it well conditioned when the per-record sums
+// are stored in float32.
 // ----------------------------------------------------------------------------
 
-// dL/d(o', r, g, b, ro, M) per record [n][16] from dL/dimage [3][H][W]:
-// per pixel the blended entries are found front to back (as in
+// dL/d(o', r, g, b, ro, M|centre) per record [n][16] from dL/dimage
+// [3][H][W]: per pixel the blended entries are found front to back (as in
 // orc_render_fwd_gut), then walked back with the colour behind S, as in
-// orc_render_bwd. With resp = exp(-d2 / 2), d2 = |ro|^2 - (ro . w)^2 / |w|^2
-// and w = M rd (rd the pixel's world ray): dL/do' = resp dL/dalpha,
-// dL/dd2 = -resp o' dL/dalpha / 2, and the chain to ro and w, then M.
+// orc_render_bwd. With resp = exp(-d2 / 2), d2 = |p|^2 for p = ro - t w,
+// w = M rd (rd the pixel's world ray) and t = (ro . w) / |w|^2 (p is the
+// canonical offset of the ray's closest point from the centre, and t is
+// stationary there): dL/do' = resp dL/dalpha, dL/dd2 = -resp o' dL/dalpha
+// / 2, dd2/dro = 2 p, and with the centre fixed p = M x for the world
+// offset x = d - t rd of the closest point, so dd2/dM = 2 p x^T.
 void orc_render_bwd_gut(int W, int H, int tile_w, int tile_h, int64_t n, const double* rec,
                         const int32_t* vals, const int32_t* ranges, const double* camv,
                         const double* cfg, const double* dimg, double* grad) {
@@ -1497,14 +1507,18 @@ void orc_render_bwd_gut(int W, int H, int tile_w, int tile_h, int64_t n, const d
             const double dd2 = -0.5 * st.resp * r[5] * dalpha;
             const double* ro = r + 9;
             const double* M = r + 12;
-            double w[3];
+            double w[3], Minv[9], d[3], x[3], pv[3];
             for (int a = 0; a < 3; ++a) w[a] = M[3 * a] * rd[0] + M[3 * a + 1] * rd[1] + M[3 * a + 2] * rd[2];
             const double rw = ro[0] * w[0] + ro[1] * w[1] + ro[2] * w[2];
             const double ww = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+            const double t = rw / ww;
+            if (!inv3(M, Minv)) continue;  // not reached: a blended record has M invertible
+            for (int a = 0; a < 3; ++a) d[a] = Minv[3 * a] * ro[0] + Minv[3 * a + 1] * ro[1] + Minv[3 * a + 2] * ro[2];
+            for (int a = 0; a < 3; ++a) x[a] = d[a] - t * rd[a];
+            for (int a = 0; a < 3; ++a) pv[a] = M[3 * a] * x[0] + M[3 * a + 1] * x[1] + M[3 * a + 2] * x[2];
             for (int a = 0; a < 3; ++a) {
-              ga[4 + a] += dd2 * (2.0 * ro[a] - 2.0 * rw / ww * w[a]);
-              const double gw = dd2 * (-2.0 * rw / ww * ro[a] + 2.0 * rw * rw / (ww * ww) * w[a]);
-              for (int b = 0; b < 3; ++b) ga[7 + 3 * a + b] += gw * rd[b];
+              ga[4 + a] += 2.0 * dd2 * pv[a];
+              for (int b = 0; b < 3; ++b) ga[7 + 3 * a + b] += 2.0 * dd2 * pv[a] * x[b];
             }
           }
         }
@@ -1518,13 +1532,14 @@ void orc_render_bwd_gut(int W, int H, int tile_w, int tile_h, int64_t n, const d
   }
 }
 
-// Backward of the 3DGUT projection: from dL/d(o', colour, ro, M) [n][16] to
-// the gradients of the inputs (activated scales and opacity, raw
-// quaternion), [k][n] like the inputs, overwritten. Through o' = o comp,
-// comp = sqrt(det_orig / det), the unscented transform's 2D covariance and
-// its seven projected sigma points; through ro = M (campos - mu) and
-// M = S^-1 R^T; through the colour as for 3DGS. Gaussians that are not
-// visible get zero.
+// Backward of the 3DGUT projection: from dL/d(o', colour, ro, M|centre)
+// [n][16] (as orc_render_bwd_gut writes it) to the gradients of the inputs
+// (activated scales and opacity, raw quaternion), [k][n] like the inputs,
+// overwritten. Through o' = o comp, comp = sqrt(det_orig / det), the
+// unscented transform's 2D covariance and its seven projected sigma points;
+// through ro = M (campos - mu) at fixed M (dL/dmu = -M^T dL/dro) and
+// M = S^-1 R^T with the centre fixed (the dL/dM given); through the colour
+// as for 3DGS. Gaussians that are not visible get zero.
 void orc_project_bwd_gut(int64_t n, const double* means, const double* scales,
                          const double* quats, const double* opac, const double* sh, int K,
                          const double* camv, int W, int H, const double* cfg, int tile_w,
@@ -1577,14 +1592,12 @@ void orc_project_bwd_gut(int64_t n, const double* means, const double* scales,
     const double dd = dv[0] * gdir[0] + dv[1] * gdir[1] + dv[2] * gdir[2];
     for (int c = 0; c < 3; ++c) gmu[c] += (gdir[c] - dv[c] * dd) / dn;
 
-    // ro = M (campos - mu), then M[r][c] = Rq[c][r] / s[r]
+    // ro = M (campos - mu) at fixed M; then M[r][c] = Rq[c][r] / s[r], whose
+    // derivative (the centre fixed) the record gradient holds
     double gM[9];
     for (int k = 0; k < 9; ++k) gM[k] = g[7 + k];
     for (int r = 0; r < 3; ++r)
-      for (int c = 0; c < 3; ++c) {
-        gM[3 * r + c] += g[4 + r] * (cp[c] - mu[c]);
-        gmu[c] -= Gp.M[3 * r + c] * g[4 + r];
-      }
+      for (int c = 0; c < 3; ++c) gmu[c] -= Gp.M[3 * r + c] * g[4 + r];
     for (int r = 0; r < 3; ++r)
       for (int c = 0; c < 3; ++c) {
         gR[3 * c + r] += gM[3 * r + c] / s[r];

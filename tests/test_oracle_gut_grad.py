@@ -2,8 +2,9 @@
 pixel_info and evaluate of Listing XPR-3DGUT, blended by Algorithm 1,
 differentiated by hand as the paper's pipeline is by automatic
 differentiation, section Key Interfaces): torch float64 autograd of the
-independent per-pixel brute force, and central finite differences of the
-tiled FP64 forward. Decisions (validity, gates, stop, rect) are piecewise
+independent per-pixel brute force (for the parameter gradients and for the
+16 per-record shader-data gradients), and central finite differences of
+the tiled FP64 forward. Decisions (validity, gates, stop, rect) are piecewise
 constant."""
 import dataclasses
 
@@ -65,6 +66,42 @@ def test_gut_analytic_matches_autograd_of_brute_force(name, sc, cam):
         scale = max(np.abs(ref[f]).max(), 1e-12)
         assert np.abs(g[f] - ref[f]).max() <= 1e-7 * scale, f
         assert np.abs(ref[f]).max() > 0, f
+
+
+@pytest.mark.parametrize("name,sc,cam", list(_scenes()), ids=lambda x: x if isinstance(x, str) else "")
+def test_gut_record_gradient_matches_autograd_of_brute_force(name, sc, cam):
+    """The 16 per-record values of orc_render_bwd_gut against autograd of the
+    brute force at its own shader data: dL/do', dL/dcolour, dL/dro (M
+    fixed) and dL/dM with the centre fixed -- the brute force forms ro from
+    M and the centre, so autograd's dL/dM is that derivative. It differs
+    from dL/dM at fixed ro by dL/dro (campos - mu)^T, which must not be
+    zero here (the definition is then pinned, not only the sum)."""
+    cfg = _cfg()
+    dimg = np.random.default_rng(2).normal(size=(3, cam.height, cam.width))
+    st = oracle.render(sc, cam, cfg)
+    g16 = oracle.render_bwd_gut(st["proj"]["rec"], st["bins"]["vals"], st["bins"]["ranges"], cam,
+                                cfg, dimg)
+    ts = brute.scene_tensors(sc, requires_grad=True)
+    keep = {}
+    img, _ = brute.render_gut_torch(*ts, cam, cfg, keep=keep)
+    (img * torch.as_tensor(dimg)).sum().backward()
+    d = (keep["campos"][None, :] - ts[0]).detach().numpy()
+    gro = keep["ro"].grad.numpy()
+    gM = keep["M"].grad.numpy()
+    ref = np.concatenate([keep["o2"].grad.numpy()[:, None], keep["colour"].grad.numpy(), gro,
+                          gM.reshape(-1, 9)], axis=1)
+    vis = st["proj"]["tc"] > 0
+    assert vis.sum() >= 3
+    shift = np.abs(gro[:, :, None] * d[:, None, :])[vis].max()
+    assert shift > 0.1 * np.abs(gM[vis]).max()
+    for cols, what in ((slice(0, 1), "o'"), (slice(1, 4), "colour"), (slice(4, 7), "ro"),
+                       (slice(7, 16), "M")):
+        r, x = ref[vis, cols], g16[vis, cols]
+        scale = max(np.abs(r).max(), 1e-12)
+        assert np.abs(x - r).max() <= 1e-8 * scale, what
+        assert np.abs(r).max() > 0, what
+    # invisible records receive nothing
+    assert np.all(g16[~vis] == 0)
 
 
 def test_gut_clamp_scene_exercises_clamps():
