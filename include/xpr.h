@@ -61,7 +61,8 @@ typedef enum {
 
 /* Methods (listings "Implementation of XPR-3DGS" and "...XPR-3DGUT"). */
 #define XPR_METHOD_3DGS 0  /* EWA projection, 2D Gaussian evaluate; forward and backward */
-#define XPR_METHOD_3DGUT 1 /* unscented-transform projection, ray evaluate; forward only */
+#define XPR_METHOD_3DGUT 1 /* unscented-transform projection, ray evaluate; forward and
+                              backward */
 #define XPR_METHOD_LINPRIM 2 /* octahedra (scales = half-extents), slab chords, Beer-Lambert;
                                 forward only, no tile_cull */
 
@@ -314,8 +315,9 @@ xpr_status xpr_render_fwd(const xpr_views* views, const xpr_config* cfg, const x
                           int32_t* tile_work, hipStream_t stream);
 
 /* Workspace bytes xpr_render_bwd needs: the tile data of the split backward
- * (bwd_split_walk; 4 bytes per tile plus 512) followed by the per-record 2D
- * gradients (36 bytes per record, used when grad2d is NULL). */
+ * (bwd_split_walk; 4 bytes per tile plus 512) followed by the per-record
+ * shader-data gradients (36 bytes per record for XPR_METHOD_3DGS, 64 for
+ * XPR_METHOD_3DGUT; used when grad2d is NULL). */
 xpr_status xpr_render_bwd_workspace(const xpr_views* views, const xpr_config* cfg, size_t* bytes);
 
 /* Backward of compositing and projection: the derivative of the blending
@@ -336,13 +338,20 @@ xpr_status xpr_render_bwd_workspace(const xpr_views* views, const xpr_config* cf
  *   grads [n_scenes] host array of device gradient buffers, or NULL to stop
  *   after the compositing backward (then grad2d is required);
  *   accumulate 0: overwrite, 1: add to the existing contents;
- *   grad2d [records][9] float (may be NULL): receives dL/d(u, v, A, B, C, o,
- *   r, g, b) per record, the derivative with respect to the shader data;
- *   when NULL the workspace holds it.
+ *   grad2d float (may be NULL): receives the derivative with respect to the
+ *   shader data per record, [records][9] dL/d(u, v, A, B, C, o, r, g, b)
+ *   for XPR_METHOD_3DGS, [records][16] dL/d(o', r, g, b, ro (3), M (9,
+ *   row-major)) for XPR_METHOD_3DGUT (the values its evaluate reads; the
+ *   2D mean and conic only place the rect); when NULL the workspace holds it.
  * The compositing backward walks each pixel's list in reverse from its last
  * blended entry (T_i recovered as T_{i+1} / (1 - a_i)); tiles are scheduled
  * as in xpr_render_fwd. Gradient sums use float atomics, so the last bits
- * vary from run to run. XPR_METHOD_3DGS only (XPR_ERR_UNSUPPORTED otherwise). */
+ * vary from run to run. For XPR_METHOD_3DGUT the same derivative is taken
+ * through evaluate and project of the listing "Implementation of XPR-3DGUT"
+ * (the response along the ray, the unscented transform's 2D covariance in
+ * the Mip-Splatting opacity factor, ro and M = S^-1 R^T); cfg->lds_batch,
+ * bwd_ppt, persistent and bwd_split_walk do not apply to it (one thread per
+ * pixel). XPR_METHOD_LINPRIM gives XPR_ERR_UNSUPPORTED. */
 xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
                           const xpr_bins* bins, const float* dL_dimage, const float* T_final,
                           const int32_t* n_contrib, const xpr_scene_grad* grads,
@@ -354,8 +363,10 @@ xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const x
  * the same computation with grads required and grad2d / the workspace
  * replaced by a file-scope static device array of 64 MiB per device (1 MiB
  * of split-backward tile data, used for batches of up to 200,000 tiles,
- * then the per-record 2D gradients, 36 bytes per record: at most 1,835,008
- * records; more fail with XPR_ERR_CAPACITY before anything is enqueued). Calls no
+ * then the per-record shader-data gradients, 36 bytes per record for
+ * XPR_METHOD_3DGS, at most 1,835,008 records, 64 for XPR_METHOD_3DGUT, at
+ * most 1,032,192; more fail with XPR_ERR_CAPACITY before anything is
+ * enqueued). Calls no
  * hipMalloc, hipFree or other allocating routine; the caller still owns
  * every input and the gradient buffers. Every call on a device shares that
  * device's array, which is zero-filled at the start of each call by a
@@ -376,7 +387,12 @@ xpr_status xpr_render_bwd_noalloc(const xpr_views* views, const xpr_config* cfg,
  * xpr_render_bwd) to the parameter gradients of every scene, summed over the
  * views that render it (one thread per Gaussian loops over those views, so
  * the sum is deterministic). Records with tiles_touched == 0 contribute
- * nothing. grads and accumulate as in xpr_render_bwd. XPR_METHOD_3DGS only. */
+ * nothing. grads and accumulate as in xpr_render_bwd. For XPR_METHOD_3DGUT
+ * grad2d is [records][16] and the derivative is that of the listing
+ * "Implementation of XPR-3DGUT", project: ro = M (campos - mu),
+ * M = S^-1 R(q)^T, the opacity factor sqrt(det_orig / det) through the
+ * seven projected sigma points, and the SH colour. XPR_METHOD_LINPRIM gives
+ * XPR_ERR_UNSUPPORTED. */
 xpr_status xpr_project_bwd(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
                            const float* grad2d, const xpr_scene_grad* grads, int32_t accumulate,
                            hipStream_t stream);

@@ -67,7 +67,7 @@ class BatchRenderer:
         self.frame = R.Frame(torch.empty(3 * v.pixels, device=self.dev),
                              torch.empty(v.pixels, device=self.dev),
                              torch.empty(v.pixels, dtype=torch.int32, device=self.dev))
-        self.grad2d = torch.empty((max(v.records, 1), 9), device=self.dev)
+        self.grad2d = torch.empty((max(v.records, 1), R.grad2d_floats(self.cfg)), device=self.dev)
         self.grads = [s.zeros_like_grads() for s in self.scenes]
         self.graph = None
 
@@ -140,7 +140,8 @@ def per_view_step(scene: R.Scene, cam, cfg: R.Config, target: torch.Tensor,
     frame = R.xpr_render_fwd(views, cfg, proj, bins, out=state.get("frame"))
     dimg = torch.sign(frame.image - target.reshape(-1)) / frame.image.numel()
     if "grad2d" not in state:
-        state["grad2d"] = torch.empty((max(scene.n, 1), 9), device=scene.means.device)
+        state["grad2d"] = torch.empty((max(scene.n, 1), R.grad2d_floats(cfg)),
+                                      device=scene.means.device)
         state["grads"] = [scene.zeros_like_grads()]
     R.xpr_render_bwd(views, cfg, proj, bins, frame, dimg, params=False, grad2d=state["grad2d"],
                      ws=ws)

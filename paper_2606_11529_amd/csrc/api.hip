@@ -42,6 +42,10 @@ hipError_t launch_render_bwd(const Batch& B, int lds_batch, int ppt, bool persis
                              const int32_t* vals, const int32_t* ranges, int32_t* order,
                              const float* dimg, const float* Tfin, const int32_t* ncon,
                              float* grad2d, hipStream_t st);
+hipError_t launch_render_bwd_gut(const Batch& B, const float* splat, const int32_t* vals,
+                                 const int32_t* ranges, const int32_t* order, const float* dimg,
+                                 const float* Tfin, const int32_t* ncon, float* grad,
+                                 hipStream_t st);
 size_t split_meta_bytes(int64_t tiles);
 hipError_t fill_zero_f32(float* p, int64_t n, hipStream_t st);
 hipError_t launch_l1_loss(const float* img, const float* tgt, int64_t n, float* loss,
@@ -238,6 +242,24 @@ static xpr_status check_grads(const xpr_views* views, const xpr_scene_grad* grad
   return XPR_OK;
 }
 
+// Floats per record of the backward's shader-data gradient: 9 for 3DGS
+// (mean2D, conic, opacity, colour), 16 for 3DGUT (o', colour, ro, M).
+static size_t grad_width(int method) { return method == XPR_METHOD_3DGUT ? 16 : 9; }
+
+// Refuses a batch whose shader-data gradients (gw floats per record) do not
+// fit in cap bytes of static scratch.
+static xpr_status scratch_capacity_check(int64_t records, size_t gw, size_t cap) {
+  const int64_t max_records = (int64_t)(cap / (gw * sizeof(float)));
+  if (records > max_records) {
+    set_error("%lld records need %lld bytes of 2D gradients; the static scratch holds %lld "
+              "(%lld records)",
+              (long long)records, (long long)(records * (int64_t)(gw * sizeof(float))),
+              (long long)(max_records * (int64_t)(gw * sizeof(float))), (long long)max_records);
+    return XPR_ERR_CAPACITY;
+  }
+  return XPR_OK;
+}
+
 }  // namespace xpr
 
 using namespace xpr;
@@ -409,7 +431,8 @@ xpr_status xpr_render_bwd_workspace(const xpr_views* views, const xpr_config* cf
   xpr_status st = build_batch(views, cfg, &B, &S);
   if (st != XPR_OK) return st;
   XPR_CHECK(bytes != nullptr, "bytes is NULL");
-  *bytes = split_meta_bytes(S.tiles) + (size_t)9 * sizeof(float) * (size_t)std::max<int64_t>(S.records, 1);
+  *bytes = split_meta_bytes(S.tiles) + grad_width(cfg->method) * sizeof(float) *
+                                           (size_t)std::max<int64_t>(S.records, 1);
   return XPR_OK;
 }
 
@@ -422,7 +445,7 @@ static xpr_status render_bwd_impl(const xpr_views* views, const xpr_config* cfg,
                                   const float* dL_dimage, const float* T_final,
                                   const int32_t* n_contrib, const xpr_scene_grad* grads,
                                   int32_t accumulate, float* grad2d, void* ws, size_t ws_bytes,
-                                  float* g2, int64_t g2_max_records, int32_t* split_meta,
+                                  float* g2, size_t g2_bytes, int32_t* split_meta,
                                   hipStream_t stream) {
   Batch B;
   Sizes S;
@@ -430,10 +453,11 @@ static xpr_status render_bwd_impl(const xpr_views* views, const xpr_config* cfg,
   if (st != XPR_OK) return st;
   st = check_proj(proj, S);
   if (st != XPR_OK) return st;
-  if (cfg->method != XPR_METHOD_3DGS) {
-    set_error("the backward is built for XPR_METHOD_3DGS only");
+  if (cfg->method == XPR_METHOD_LINPRIM) {
+    set_error("the backward is built for XPR_METHOD_3DGS and XPR_METHOD_3DGUT");
     return XPR_ERR_UNSUPPORTED;
   }
+  const size_t gw = grad_width(cfg->method);
   XPR_CHECK(bins && bins->tile_ranges && dL_dimage && T_final && n_contrib, "NULL buffer");
   XPR_CHECK(grads || grad2d, "grads and grad2d both NULL");
   XPR_CHECK(!cfg->persistent || bins->tile_order, "persistent needs bins->tile_order");
@@ -444,13 +468,8 @@ static xpr_status render_bwd_impl(const xpr_views* views, const xpr_config* cfg,
   // static scratch path passes both parts itself
   const size_t meta_bytes = split_meta_bytes(S.tiles);
   if (g2) {
-    if (S.records > g2_max_records) {
-      set_error("%lld records need %lld bytes of 2D gradients; the static scratch holds %lld "
-                "(%lld records)",
-                (long long)S.records, (long long)S.records * 36, (long long)g2_max_records * 36,
-                (long long)g2_max_records);
-      return XPR_ERR_CAPACITY;
-    }
+    st = scratch_capacity_check(S.records, gw, g2_bytes);
+    if (st != XPR_OK) return st;
   } else {
     g2 = grad2d;
     if (ws) XPR_CHECK(aligned(ws, 16), "workspace misaligned");
@@ -458,7 +477,7 @@ static xpr_status render_bwd_impl(const xpr_views* views, const xpr_config* cfg,
   }
   if (!g2) {
     const size_t need =
-        meta_bytes + (size_t)9 * sizeof(float) * (size_t)std::max<int64_t>(S.records, 1);
+        meta_bytes + gw * sizeof(float) * (size_t)std::max<int64_t>(S.records, 1);
     XPR_CHECK(ws && ws_bytes >= need, "workspace too small: %zu < %zu bytes", ws_bytes, need);
     g2 = reinterpret_cast<float*>(static_cast<char*>(ws) + meta_bytes);
   }
@@ -467,7 +486,15 @@ static xpr_status render_bwd_impl(const xpr_views* views, const xpr_config* cfg,
     st = check_grads(views, grads, G);
     if (st != XPR_OK) return st;
   }
-  XPR_HIP(fill_zero_f32(g2, 9 * S.records, stream));
+  XPR_HIP(fill_zero_f32(g2, (int64_t)gw * S.records, stream));
+  if (cfg->method == XPR_METHOD_3DGUT) {
+    XPR_HIP(launch_render_bwd_gut(B, proj->splat, bins->vals, bins->tile_ranges, bins->tile_order,
+                                  dL_dimage, T_final, n_contrib, g2, stream));
+    if (grads)
+      XPR_HIP(launch_project_bwd(B, S.max_n, g2, proj->tiles_touched, G, accumulate ? 1 : 0,
+                                 stream));
+    return XPR_OK;
+  }
   const int bwd_lds = cfg->bwd_lds_batch ? cfg->bwd_lds_batch : cfg->lds_batch;
   XPR_HIP(launch_render_bwd(B, bwd_lds, cfg->bwd_ppt, cfg->persistent != 0, cfg->bwd_split_walk,
                             split_meta, proj->splat, bins->vals, bins->tile_ranges,
@@ -477,8 +504,8 @@ static xpr_status render_bwd_impl(const xpr_views* views, const xpr_config* cfg,
   return XPR_OK;
 }
 
-// File-scope scratch of xpr_render_bwd_noalloc: the per-record 2D gradients
-// (9 floats per record). Each device holds its own copy for the life of the
+// File-scope scratch of xpr_render_bwd_noalloc: the per-record shader-data
+// gradients (9 floats per record for 3DGS, 16 for 3DGUT). Each device holds its own copy for the life of the
 // process. In host code ``scratch`` names a host-side stand-in, never the
 // device memory: kernels and fills get the address hipGetSymbolAddress
 // returns on each device.
@@ -487,8 +514,7 @@ constexpr size_t kScratchBytes = (size_t)64 << 20;
 // kScratchTiles tiles is 800,768 bytes; larger batches are walked unsplit)
 constexpr size_t kScratchMetaBytes = (size_t)1 << 20;
 constexpr int64_t kScratchTiles = 200000;
-constexpr int64_t kScratchRecords =
-    (int64_t)((kScratchBytes - kScratchMetaBytes) / (9 * sizeof(float)));
+constexpr size_t kScratchGradBytes = kScratchBytes - kScratchMetaBytes;
 static __device__ __align__(256) float scratch[kScratchBytes / sizeof(float)];
 
 constexpr int kMaxDevices = 64;
@@ -536,20 +562,15 @@ xpr_status xpr_render_bwd_noalloc(const xpr_views* views, const xpr_config* cfg,
   Sizes S;
   xpr_status st = build_batch(views, cfg, &B, &S);
   if (st != XPR_OK) return st;
-  if (S.records > kScratchRecords) {
-    set_error("%lld records need %lld bytes of 2D gradients; the static scratch holds %lld "
-              "(%lld records)",
-              (long long)S.records, (long long)S.records * 36, (long long)kScratchRecords * 36,
-              (long long)kScratchRecords);
-    return XPR_ERR_CAPACITY;
-  }
+  st = scratch_capacity_check(S.records, grad_width(cfg->method), kScratchGradBytes);
+  if (st != XPR_OK) return st;
   float* base = nullptr;
   st = scratch_of_current_device(&base);
   if (st != XPR_OK) return st;
   int32_t* meta = S.tiles <= kScratchTiles ? reinterpret_cast<int32_t*>(base) : nullptr;
   float* g2 = base + kScratchMetaBytes / sizeof(float);
   return render_bwd_impl(views, cfg, proj, bins, dL_dimage, T_final, n_contrib, grads,
-                         accumulate, nullptr, nullptr, 0, g2, kScratchRecords, meta, stream);
+                         accumulate, nullptr, nullptr, 0, g2, kScratchGradBytes, meta, stream);
 }
 
 xpr_status xpr_l1_loss(const float* image, const float* target, int64_t n, float* loss,
@@ -574,8 +595,8 @@ xpr_status xpr_project_bwd(const xpr_views* views, const xpr_config* cfg, const 
   if (st != XPR_OK) return st;
   st = check_proj(proj, S);
   if (st != XPR_OK) return st;
-  if (cfg->method != XPR_METHOD_3DGS) {
-    set_error("the backward is built for XPR_METHOD_3DGS only");
+  if (cfg->method == XPR_METHOD_LINPRIM) {
+    set_error("the backward is built for XPR_METHOD_3DGS and XPR_METHOD_3DGUT");
     return XPR_ERR_UNSUPPORTED;
   }
   XPR_CHECK(grads != nullptr, "grads is NULL");

@@ -275,6 +275,80 @@ __global__ __launch_bounds__(256) void k_project(Batch B, float4* __restrict__ s
   tc[r] = P.tc;
 }
 
+// Backward of Rq(q / |q|), the rotation of the normalised quaternion
+// (w, x, y, z) = qn: dL/dq added to gq from dL/dRq (row-major) in gR.
+__device__ __forceinline__ void quat_vjp(const double* qn, double qinv, const double* gR,
+                                         double* gq) {
+  const double w = qn[0], x = qn[1], y = qn[2], z = qn[3];
+  const double gw = 2.0 * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
+  const double gx = 2.0 * (y * gR[1] + z * gR[2] + y * gR[3] - w * gR[5] + z * gR[6] + w * gR[7]) -
+                    4.0 * x * (gR[4] + gR[8]);
+  const double gy = 2.0 * (x * gR[1] + w * gR[2] + x * gR[3] + z * gR[5] - w * gR[6] + z * gR[7]) -
+                    4.0 * y * (gR[0] + gR[8]);
+  const double gz = 2.0 * (-w * gR[1] + x * gR[2] + w * gR[3] + y * gR[5] + x * gR[6] + y * gR[7]) -
+                    4.0 * z * (gR[0] + gR[4]);
+  const double qd = w * gw + x * gx + y * gy + z * gz;
+  gq[0] += (gw - w * qd) * qinv;
+  gq[1] += (gx - x * qd) * qinv;
+  gq[2] += (gy - y * qd) * qinv;
+  gq[3] += (gz - z * qd) * qinv;
+}
+
+__device__ __forceinline__ GradDev grad_dest(int sidx, const GradDev& G0, const GradDev& G1,
+                                             const GradDev& G2, const GradDev& G3,
+                                             const GradDev& G4, const GradDev& G5,
+                                             const GradDev& G6, const GradDev& G7) {
+  switch (sidx) {
+    case 0: return G0;
+    case 1: return G1;
+    case 2: return G2;
+    case 3: return G3;
+    case 4: return G4;
+    case 5: return G5;
+    case 6: return G6;
+    default: return G7;
+  }
+}
+
+// Writes (or, with accumulate, adds) one Gaussian's parameter gradients;
+// overwriting also zeroes the SH coefficients above the rendered degree.
+template <int NB>
+__device__ __forceinline__ void store_param_grads(const GradDev& G, const SceneDev& S, int i,
+                                                  const double (&gmu)[3], const double (&gs)[3],
+                                                  const double (&gq)[4], float go,
+                                                  const float (&gsh)[NB][3], int accumulate) {
+  const size_t ld = S.ld;
+  if (accumulate) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      G.means[k * ld + i] += (float)gmu[k];
+      G.scales[k * ld + i] += (float)gs[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) G.quats[k * ld + i] += (float)gq[k];
+    G.opac[i] += go;
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) G.sh[(3 * j + ch) * ld + i] += gsh[j][ch];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      G.means[k * ld + i] = (float)gmu[k];
+      G.scales[k * ld + i] = (float)gs[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) G.quats[k * ld + i] = (float)gq[k];
+    G.opac[i] = go;
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) G.sh[(3 * j + ch) * ld + i] = gsh[j][ch];
+    for (int j = NB; j < S.K; ++j)
+      for (int ch = 0; ch < 3; ++ch) G.sh[(3 * j + ch) * ld + i] = 0.f;
+  }
+}
+
 // Backward of the projection for one Gaussian of scene blockIdx.y, summed
 // over the views that render it. grad2d [records][9] holds dL/d(u, v, A, B,
 // C, o, r, g, b). Chain: shader data -> conic -> 2D covariance -> (J W,
@@ -409,63 +483,11 @@ __global__ __launch_bounds__(256) void k_project_bwd(Batch B, const float* __res
       }
       gs[k] += acc;
     }
-    // Rq(q) -> unit quaternion -> raw quaternion
-    const double w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
-    const double gw = 2.0 * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
-    const double gx = 2.0 * (y * gR[1] + z * gR[2] + y * gR[3] - w * gR[5] + z * gR[6] + w * gR[7]) -
-                      4.0 * x * (gR[4] + gR[8]);
-    const double gy = 2.0 * (x * gR[1] + w * gR[2] + x * gR[3] + z * gR[5] - w * gR[6] + z * gR[7]) -
-                      4.0 * y * (gR[0] + gR[8]);
-    const double gz = 2.0 * (-w * gR[1] + x * gR[2] + w * gR[3] + y * gR[5] + x * gR[6] + y * gR[7]) -
-                      4.0 * z * (gR[0] + gR[4]);
-    const double qd = w * gw + x * gx + y * gy + z * gz;
-    gq[0] += (gw - w * qd) * P.qinv;
-    gq[1] += (gx - x * qd) * P.qinv;
-    gq[2] += (gy - y * qd) * P.qinv;
-    gq[3] += (gz - z * qd) * P.qinv;
+    quat_vjp(P.qn, P.qinv, gR, gq);
   }
 
-  GradDev G;
-  switch (sidx) {
-    case 0: G = G0; break;
-    case 1: G = G1; break;
-    case 2: G = G2; break;
-    case 3: G = G3; break;
-    case 4: G = G4; break;
-    case 5: G = G5; break;
-    case 6: G = G6; break;
-    default: G = G7; break;
-  }
-  const size_t ld = S.ld;
-  if (accumulate) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      G.means[k * ld + i] += (float)gmu[k];
-      G.scales[k * ld + i] += (float)gs[k];
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) G.quats[k * ld + i] += (float)gq[k];
-    G.opac[i] += go;
-#pragma unroll
-    for (int j = 0; j < NB; ++j)
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) G.sh[(3 * j + ch) * ld + i] += gsh[j][ch];
-  } else {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      G.means[k * ld + i] = (float)gmu[k];
-      G.scales[k * ld + i] = (float)gs[k];
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) G.quats[k * ld + i] = (float)gq[k];
-    G.opac[i] = go;
-#pragma unroll
-    for (int j = 0; j < NB; ++j)
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) G.sh[(3 * j + ch) * ld + i] = gsh[j][ch];
-    for (int j = NB; j < S.K; ++j)
-      for (int ch = 0; ch < 3; ++ch) G.sh[(3 * j + ch) * ld + i] = 0.f;
-  }
+  store_param_grads<NB>(grad_dest(sidx, G0, G1, G2, G3, G4, G5, G6, G7), S, i, gmu, gs, gq, go,
+                        gsh, accumulate);
 }
 
 // 3DGUT projection (listing "Implementation of XPR-3DGUT", project), one
@@ -605,6 +627,210 @@ __global__ __launch_bounds__(256) void k_project_gut(Batch B, float4* __restrict
   rect[r] = visible ? make_short4((short)x0, (short)y0, (short)x1, (short)y1)
                     : make_short4(0, 0, 0, 0);
   tc[r] = visible ? area : 0;
+}
+
+// Backward of the 3DGUT projection, one thread per scene Gaussian over the
+// views of its scene (blockIdx.y = scene), in FP64 like the forward: from
+// dL/d(o', colour, ro, M) [record][16] to the gradients of the means,
+// activated scales and opacity, raw quaternion and SH coefficients. The
+// chain, for a visible record:
+//   ro = M (campos - mu) at fixed M: dL/dmu -= M^T dL/dro;
+//   M = S^-1 R^T with the centre fixed (the record gradient's dL/dM):
+//     dL/dR_cr += dL/dM_rc / s_r and dL/ds_r -= sum_c dL/dM_rc R_cr / s_r^2;
+//   o' = o comp, comp = sqrt(det_orig / det) of the unscented transform's
+//     2D covariance before and after the low-pass: dL/do = comp dL/do', and
+//     through det_orig and det to the covariance, its weighted deviations,
+//     the seven projected sigma points and so to mu, s and R;
+//   the colour as for 3DGS (clamped channels pass nothing).
+template <int DEG>
+__global__ __launch_bounds__(256) void k_project_bwd_gut(Batch B, const float* __restrict__ grad,
+                                                         const int32_t* __restrict__ tc,
+                                                         GradDev G0, GradDev G1, GradDev G2,
+                                                         GradDev G3, GradDev G4, GradDev G5,
+                                                         GradDev G6, GradDev G7, int accumulate) {
+  const int sidx = blockIdx.y;
+  const SceneDev& S = B.s[sidx];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= S.n) return;
+  constexpr int NB = (DEG + 1) * (DEG + 1);
+  double gmu[3] = {0.0, 0.0, 0.0}, gs[3] = {0.0, 0.0, 0.0}, gq[4] = {0.0, 0.0, 0.0, 0.0};
+  double gR[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  float go = 0.f;
+  float gsh[NB][3];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) gsh[j][0] = gsh[j][1] = gsh[j][2] = 0.f;
+  // the Gaussian's frame, as the forward forms it
+  const double mu[3] = {S.means[i], S.means[S.ld + i], S.means[2 * S.ld + i]};
+  const double q0 = S.quats[i], q1 = S.quats[S.ld + i], q2 = S.quats[2 * S.ld + i],
+               q3 = S.quats[3 * S.ld + i];
+  const double qinv = 1.0 / sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+  const double qn[4] = {q0 * qinv, q1 * qinv, q2 * qinv, q3 * qinv};
+  const double w = qn[0], x = qn[1], y = qn[2], z = qn[3];
+  const double Q[9] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y),
+                       2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x),
+                       2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)};
+  const double s[3] = {S.scales[i], S.scales[S.ld + i], S.scales[2 * S.ld + i]};
+  const double opac = S.opac[i];
+  const double k3 = 1.7320508075688772;  // sqrt(3)
+  const double lp = B.lowpass;
+
+  for (int vi = 0; vi < B.n_views; ++vi) {
+    const ViewDev& V = B.v[vi];
+    if (V.scene != sidx) continue;
+    const int r = V.rec_off + i;
+    if (tc[r] == 0) continue;
+    const float* g = grad + 16 * (size_t)r;
+    double R[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) R[k] = V.R[k];
+    const double fx = V.fx, fy = V.fy, cx = V.cx, cy = V.cy;
+    const double cp[3] = {-(R[0] * V.t[0] + R[3] * V.t[1] + R[6] * V.t[2]),
+                          -(R[1] * V.t[0] + R[4] * V.t[1] + R[7] * V.t[2]),
+                          -(R[2] * V.t[0] + R[5] * V.t[1] + R[8] * V.t[2])};
+    const double d[3] = {cp[0] - mu[0], cp[1] - mu[1], cp[2] - mu[2]};
+
+    // colour = max(0, 0.5 + sum_j sh_j Y_j(dir)), dir = (mu - campos) / |.|
+    {
+      const double dn = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      const double dir[3] = {-d[0] * dn, -d[1] * dn, -d[2] * dn};
+      const float dxf = (float)dir[0], dyf = (float)dir[1], dzf = (float)dir[2];
+      float Y[16];
+      sh_basis<DEG>(dxf, dyf, dzf, Y);
+      float graw[3];
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        float acc = 0.5f;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc += S.sh[(size_t)(3 * j + ch) * S.ld + i] * Y[j];
+        graw[ch] = acc > 0.f ? g[1 + ch] : 0.f;
+      }
+      float wsum[16];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        float acc = 0.f;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          gsh[j][ch] += Y[j] * graw[ch];
+          acc += S.sh[(size_t)(3 * j + ch) * S.ld + i] * graw[ch];
+        }
+        wsum[j] = acc;
+      }
+      float gdxf, gdyf, gdzf;
+      sh_basis_vjp<DEG>(dxf, dyf, dzf, wsum, gdxf, gdyf, gdzf);
+      const double gd[3] = {gdxf, gdyf, gdzf};
+      const double dd = dir[0] * gd[0] + dir[1] * gd[1] + dir[2] * gd[2];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) gmu[c] += (gd[c] - dir[c] * dd) * dn;
+    }
+
+    // ro = M (campos - mu) at fixed M, M_ac = Q_ca / s_a with the centre fixed
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double gro = g[4 + a];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double Mac = Q[3 * c + a] / s[a];
+        const double gM = g[7 + 3 * a + c];
+        gmu[c] -= Mac * gro;
+        gR[3 * c + a] += gM / s[a];
+        gs[a] -= gM * Mac / s[a];
+      }
+    }
+
+    // o' = o comp over the seven sigma points
+    double px[7], py[7];
+#pragma unroll
+    for (int p = 0; p < 7; ++p) {
+      double X[3] = {mu[0], mu[1], mu[2]};
+      if (p > 0) {
+        const int j = (p - 1) >> 1;
+        const double sg = ((p - 1) & 1) ? -k3 : k3;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) X[c] += sg * s[j] * Q[3 * c + j];
+      }
+      const double xc = R[0] * X[0] + R[1] * X[1] + R[2] * X[2] + (double)V.t[0];
+      const double yc = R[3] * X[0] + R[4] * X[1] + R[5] * X[2] + (double)V.t[1];
+      const double zc = R[6] * X[0] + R[7] * X[1] + R[8] * X[2] + (double)V.t[2];
+      px[p] = fx * xc / zc + cx;
+      py[p] = fy * yc / zc + cy;
+    }
+    double mx = 0.0, my = 0.0;
+#pragma unroll
+    for (int p = 1; p < 7; ++p) {
+      mx += px[p] / 6.0;
+      my += py[p] / 6.0;
+    }
+    double cxx = 0.0, cxy = 0.0, cyy = 0.0;
+#pragma unroll
+    for (int p = 0; p < 7; ++p) {
+      const double wc = p == 0 ? 2.0 : 1.0 / 6.0;
+      px[p] -= mx;  // deviations from here on
+      py[p] -= my;
+      cxx += wc * px[p] * px[p];
+      cxy += wc * px[p] * py[p];
+      cyy += wc * py[p] * py[p];
+    }
+    const double det0 = cxx * cyy - cxy * cxy;
+    const double det = (cxx + lp) * (cyy + lp) - cxy * cxy;
+    const double comp = det > 0.0 ? sqrt(fmax(det0, 0.0) / det) : 0.0;
+    go += (float)(comp * (double)g[0]);
+    if (det0 > 0.0 && det > 0.0) {
+      const double gcomp = opac * (double)g[0];
+      const double gdet0 = gcomp * comp / (2.0 * det0), gdet = -gcomp * comp / (2.0 * det);
+      const double gxx = gdet0 * cyy + gdet * (cyy + lp);
+      const double gyy = gdet0 * cxx + gdet * (cxx + lp);
+      const double gxy = -2.0 * cxy * (gdet0 + gdet);
+      // dL/d(deviation) per point; the mean's share goes back through the
+      // mean weights (0 for the centre, 1/6 for the others)
+      double sDx = 0.0, sDy = 0.0;
+#pragma unroll
+      for (int p = 0; p < 7; ++p) {
+        const double wc = p == 0 ? 2.0 : 1.0 / 6.0;
+        const double gx = wc * (2.0 * px[p] * gxx + py[p] * gxy);
+        const double gy = wc * (2.0 * py[p] * gyy + px[p] * gxy);
+        px[p] = gx;  // dL/d(deviation) from here on
+        py[p] = gy;
+        sDx += gx;
+        sDy += gy;
+      }
+#pragma unroll
+      for (int p = 0; p < 7; ++p) {
+        const double wm = p == 0 ? 0.0 : 1.0 / 6.0;
+        const double gPx = px[p] - wm * sDx, gPy = py[p] - wm * sDy;
+        double X[3] = {mu[0], mu[1], mu[2]};
+        int j = 0;
+        double sg = 0.0;
+        if (p > 0) {
+          j = (p - 1) >> 1;
+          sg = ((p - 1) & 1) ? -k3 : k3;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) X[c] += sg * s[j] * Q[3 * c + j];
+        }
+        const double xc = R[0] * X[0] + R[1] * X[1] + R[2] * X[2] + (double)V.t[0];
+        const double yc = R[3] * X[0] + R[4] * X[1] + R[5] * X[2] + (double)V.t[1];
+        const double zc = R[6] * X[0] + R[7] * X[1] + R[8] * X[2] + (double)V.t[2];
+        const double iz = 1.0 / zc;
+        const double gyv[3] = {fx * iz * gPx, fy * iz * gPy,
+                               -(fx * xc * gPx + fy * yc * gPy) * iz * iz};
+        double gX[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          gX[c] = R[c] * gyv[0] + R[3 + c] * gyv[1] + R[6 + c] * gyv[2];
+          gmu[c] += gX[c];
+        }
+        if (p > 0) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            gs[j] += sg * gX[c] * Q[3 * c + j];
+            gR[3 * c + j] += sg * s[j] * gX[c];
+          }
+        }
+      }
+    }
+  }
+  quat_vjp(qn, qinv, gR, gq);
+  store_param_grads<NB>(grad_dest(sidx, G0, G1, G2, G3, G4, G5, G6, G7), S, i, gmu, gs, gq, go,
+                        gsh, accumulate);
 }
 
 // LinPrim projection (listing "Implementation of XPR-LinPrim", project),
@@ -752,6 +978,19 @@ hipError_t launch_project_bwd(const Batch& B, int max_n, const float* grad2d, co
                               const GradDev* G, int accumulate, hipStream_t st) {
   if (max_n <= 0) return hipSuccess;
   dim3 grid((max_n + 255) / 256, B.n_scenes);
+  if (B.method == XPR_METHOD_3DGUT) {
+#define XPR_PBG(D)                                                                             \
+  hipLaunchKernelGGL(k_project_bwd_gut<D>, grid, dim3(256), 0, st, B, grad2d, tc, G[0], G[1], \
+                     G[2], G[3], G[4], G[5], G[6], G[7], accumulate)
+    switch (B.sh_degree) {
+      case 0: XPR_PBG(0); break;
+      case 1: XPR_PBG(1); break;
+      case 2: XPR_PBG(2); break;
+      default: XPR_PBG(3); break;
+    }
+#undef XPR_PBG
+    return hipGetLastError();
+  }
 #define XPR_PB(D)                                                                          \
   hipLaunchKernelGGL(k_project_bwd<D>, grid, dim3(256), 0, st, B, grad2d, tc, G[0], G[1], \
                      G[2], G[3], G[4], G[5], G[6], G[7], accumulate)

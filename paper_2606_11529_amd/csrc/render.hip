@@ -294,26 +294,6 @@ __global__ __launch_bounds__(TW* TH / PPT) void k_render_fwd(
 // atomics: row 0 X_0,2,4,6,8; row 1 X_1,3,5,7; row 2 Y_0,2,4,6,8; row 3
 // Y_1,3,5,7. 48 lane-parallel instructions instead of 2 x 9 full-wave
 // reductions.
-__device__ __forceinline__ float fold32(float x, float y) {
-  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false,
-                                                  false);
-  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-}
-
-__device__ __forceinline__ float fold16(float x, float y) {
-  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false,
-                                                  false);
-  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-}
-
-__device__ __forceinline__ float row_sum16(float x) {
-  x += dpp_f<0xB1>(x);   // quad_perm [1,0,3,2]
-  x += dpp_f<0x4E>(x);   // quad_perm [2,3,0,1]
-  x += dpp_f<0x141>(x);  // row_half_mirror
-  x += dpp_f<0x140>(x);  // row_mirror: every lane holds its row sum
-  return x;
-}
-
 __device__ __forceinline__ void reduce_pair(const float (&X)[9], const float (&Y)[9], bool ax,
                                             bool ay, float* gx, float* gy) {
   float Z[9];

@@ -104,6 +104,32 @@ __device__ __forceinline__ float wave_sum_lane63(float x) {
   return x;
 }
 
+// gfx950 lane swaps (v_permlane32_swap, v_permlane16_swap) for reducing
+// several values over a wave at once. fold32(x, y): lanes 0..31 hold
+// x[l] + x[l + 32], lanes 32..63 hold y[l - 32] + y[l]. fold16(c, d): of
+// the four 16-lane rows, row 0 holds c's rows 0 + 1, row 1 d's rows 0 + 1,
+// row 2 c's rows 2 + 3 and row 3 d's rows 2 + 3. row_sum16: every lane
+// gets the sum over its row.
+__device__ __forceinline__ float fold32(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float fold16(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float row_sum16(float x) {
+  x += dpp_f<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += dpp_f<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += dpp_f<0x141>(x);  // row_half_mirror
+  x += dpp_f<0x140>(x);  // row_mirror: every lane holds its row sum
+  return x;
+}
+
 __device__ __forceinline__ float lane63(float x) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }

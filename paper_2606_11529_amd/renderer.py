@@ -39,7 +39,7 @@ class Config:
     tile_order: bool = False    # launch tiles longest list first (implied by persistent)
     tile_cull: bool = False     # per-(Gaussian, tile) cull of XPR-3DGS in the binning
     opacity_extents: bool = False  # rect from the alpha >= alpha_min ellipse, not 3 sigma
-    method: str = "3dgs"        # "3dgs", "3dgut" or "linprim" (the last two forward only)
+    method: str = "3dgs"        # "3dgs", "3dgut" or "linprim" (the last forward only)
     bwd_split_walk: int = 2048  # backward: tiles whose walk reaches this go as four bands
 
     def to_c(self) -> L.XprConfig:
@@ -234,6 +234,14 @@ def splat_floats(cfg: "Config") -> int:
     return {"3dgut": 24, "linprim": 20}.get(cfg.method, 12)
 
 
+def grad2d_floats(cfg: "Config") -> int:
+    """Floats per record of the backward's shader-data gradient: 9 for 3DGS
+    (mean2D, conic, opacity, colour), 16 for 3DGUT (o', colour, ro, M)."""
+    if cfg.method == "linprim":
+        raise NotImplementedError("the backward covers 3dgs and 3dgut")
+    return 16 if cfg.method == "3dgut" else 9
+
+
 def empty_projected(n: int, device, floats: int = 12) -> Projected:
     n1 = max(n, 1)
     return Projected(torch.empty((n1, floats), dtype=torch.float32, device=device),
@@ -334,7 +342,8 @@ def xpr_render_bwd(views: Views, cfg: Config, proj: Projected, bins: Bins, frame
                    ws: Optional[Workspace] = None, params: bool = True,
                    grad2d: Optional[torch.Tensor] = None):
     """Returns (grads per scene or None, grad2d or None). With params=False
-    only the compositing backward runs and grad2d [records, 9] is returned."""
+    only the compositing backward runs and grad2d [records, grad2d_floats]
+    is returned."""
     ws = ws or _WS
     dev = proj.splat.device
     if params and grads is None:
@@ -342,7 +351,8 @@ def xpr_render_bwd(views: Views, cfg: Config, proj: Projected, bins: Bins, frame
     arr = _grads_c(grads) if params else None
     dimage = dimage.contiguous()
     if grad2d is None and (want_grad2d or not params):
-        grad2d = torch.empty((max(views.records, 1), 9), dtype=torch.float32, device=dev)
+        grad2d = torch.empty((max(views.records, 1), grad2d_floats(cfg)), dtype=torch.float32,
+                             device=dev)
     nbytes = L.xpr_render_bwd_workspace(views.c, views.cfg_c)
     wsb = ws.get("bwd", nbytes, dev)
     L.xpr_render_bwd(views.c, views.cfg_c, proj.to_c(), bins.to_c(), _ptr(dimage),

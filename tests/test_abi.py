@@ -147,6 +147,10 @@ def test_workspace_queries_host_only():
     # units), then 36 bytes per record
     meta = -(-(128 + 12) * 4 // 256) * 256
     assert L.xpr_render_bwd_workspace(v, c) == meta + 9 * 4 * 1000
+    # 3DGUT: 16 floats per record (o', colour, ro, M)
+    c.method = L.XPR_METHOD_3DGUT
+    assert L.xpr_render_bwd_workspace(v, c) == meta + 16 * 4 * 1000
+    c.method = L.XPR_METHOD_3DGS
     with pytest.raises(L.XprError):
         L.xpr_bin_sort_workspace(v, c, -1)
 
@@ -178,3 +182,11 @@ def test_noalloc_backward_rejects_more_records_than_its_scratch():
     st = L.lib().xpr_render_bwd_noalloc(ctypes.byref(v), ctypes.byref(c), ctypes.byref(args[0]),
                                         ctypes.byref(args[1]), 4096, 4096, 4096, None, 0, None)
     assert st == L.XPR_ERR_INVALID_ARG and "grads" in L.xpr_last_error()
+    # 3DGUT's 64 bytes per record: 1,032,192 fit, one view of 1.1M does not
+    c.method = L.XPR_METHOD_3DGUT
+    v = _views(n=1_100_000, n_views=1)
+    st = L.lib().xpr_render_bwd_noalloc(ctypes.byref(v), ctypes.byref(c), ctypes.byref(args[0]),
+                                        ctypes.byref(args[1]), 4096, 4096, 4096, grads, 0, None)
+    assert st == L.XPR_ERR_CAPACITY
+    msg = L.xpr_last_error()
+    assert "1100000 records" in msg and "1032192 records" in msg

@@ -3,15 +3,20 @@ on the HIP path with the FP64 oracle, through the C-ABI: the UT projection
 (floats within rounding bounds, rects and tile counts bit-exact outside the
 guard band), binning bit-exact (also with the extended-bound tile cull),
 compositing within 1e-5 max-abs with n_contrib exact, the image independent
-of the sort strategy, and the backward entry points refusing the method."""
+of the sort strategy, and the backward: the compositing backward's 16
+shader-data gradients per record (o', colour, ro, M) and the projection
+backward's parameter gradients within 1e-3 relative of the oracle's (each
+stage fed the GPU's previous stage; records a guard-band decision can reach
+excluded), accumulate adding, and the batched path matching per-view
+calls."""
 import functools
 
 import numpy as np
 import pytest
 
 import oracle
-from gpu_util import (cam32, check_binning, check_binning_cull, log, ocfg_of, run_gpu,
-                      TOL_PIXEL)
+from gpu_util import (cam32, check_binning, check_binning_cull, guard_records, log, ocfg_of,
+                      rel_check, run_gpu, TOL_PIXEL)
 from paper_2606_11529_amd import _lib as L
 from paper_2606_11529_amd import renderer as R
 from synth import camera_front, camera_look_at, random_cameras, scene_clusters, scene_uniform_cube
@@ -43,13 +48,19 @@ def _case(name):
 CASES = ["cube_10k_256", "ragged_t8", "ragged_t16_ext", "ragged_t32", "clusters_1M_1297x840"]
 
 
+def _dimg(cam, seed=1):
+    rng = np.random.default_rng(seed)
+    return rng.normal(size=(3, cam.height, cam.width)).astype(np.float32) / (
+        3 * cam.width * cam.height)
+
+
 @functools.lru_cache(maxsize=2)
 def _run(name, cull=False):
     sc, cam, cfg = _case(name)
     cfg.method = "3dgut"
     cfg.tile_cull = cull
     log(f"[gpu gut] case={name} cull={cull} n={sc.n} {cam.width}x{cam.height} tile={cfg.tile}")
-    return sc, cam, cfg, run_gpu(sc, cam, cfg)
+    return sc, cam, cfg, run_gpu(sc, cam, cfg, dimgs=[_dimg(cam)])
 
 
 def _check_projection(sc, cam, cfg, g, idx):
@@ -145,18 +156,119 @@ def test_gut_sort_modes_agree():
         assert np.array_equal(g["vals"], ref["vals"]) and np.array_equal(g["image"][0], ref["image"][0])
 
 
-def test_gut_backward_is_refused():
-    sc = scene_clusters(500, seed=4, n_clusters=2, box=1.0, lo=0.01, hi=0.2)
-    cam = camera_look_at((0.1, 0.2, -4.0), 48, 32)
-    cfg = R.Config(method="3dgut")
-    scene = R.Scene.from_host(sc)
-    views = R.Views([scene], [cam], [0], cfg)
+def _param_check(sc, cam, cfg, g, mask):
+    """Projection backward from the GPU's 16 shader-data gradients."""
+    ref = oracle.project_bwd_gut(sc, cam32(cam), ocfg_of(cfg), g["grad2d"].astype(np.float64))
+    worst = {}
+    m = mask & (g["tc"] > 0)
+    for k in ("means", "scales", "quats", "opacities", "sh"):
+        gk, rk = g["grads"][k], ref[k]
+        gk = gk.reshape(-1, sc.n).T if gk.ndim > 1 else gk
+        rk = rk.reshape(-1, sc.n).T if rk.ndim > 1 else rk
+        worst[k] = rel_check(gk, rk, k, m)
+    return worst
+
+
+def _backward_check(sc, cam, cfg, g, dimg):
+    oc = ocfg_of(cfg)
+    rec = g["splat"][:, :21].astype(np.float64)
+    c32 = cam32(cam)
+    ref_f = oracle.render_fwd_gut(rec, g["vals"], g["ranges"], c32, oc)
+    g16 = oracle.render_bwd_gut(rec, g["vals"], g["ranges"], c32, oc, dimg.astype(np.float64))
+    tx, _ = oracle.tiles(cam, oc)
+    excl = guard_records(ref_f, g["ncontrib"][0], g["ranges"], g["vals"], cfg.tile, tx)
+    mask = np.ones(sc.n, bool)
+    mask[excl] = False
+    assert g["grad2d"].shape == (sc.n, 16)
+    w16 = rel_check(g["grad2d"], g16, "grad16", mask)
+    listed = np.zeros(sc.n, bool)
+    listed[g["vals"]] = True
+    assert np.all(g["grad2d"][~listed] == 0), "a record in no list received a gradient"
+    return w16, _param_check(sc, cam, cfg, g, mask), excl.size
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_gut_backward(name):
+    sc, cam, cfg, g = _run(name)
+    w16, worst, nex = _backward_check(sc, cam, cfg, g, _dimg(cam))
+    lit = (np.abs(g["grad2d"]).sum(axis=1) > 0).sum()
+    log(f"[G4] {name}: grad16 {w16:.2e} x bound over {lit} records with a gradient, "
+        f"params {worst}, excluded {nex}")
+
+
+def test_gut_backward_clamped_opacity():
+    """A Gaussian whose alpha passes alpha_max near its centre (no gradient
+    to its o', ro or M there, only to its colour and, through T, to the
+    others) and a negative colour channel clamped to 0 (no gradient to its
+    SH coefficients), beside ordinary Gaussians; checked against the oracle,
+    which takes the same sides."""
+    import dataclasses
+    from helpers import axis_camera, hand_scene
+    sh = np.zeros((4, 16, 3))
+    sh[:, 0, :] = [[1.2, 0.3, 0.6], [0.4, -2.5, 0.8], [0.9, 0.9, 0.1], [0.2, 0.5, 1.1]]
+    rng = np.random.default_rng(11)
+    sh[:, 1:, :] = rng.normal(0, 0.05, size=(4, 15, 3))
+    means = [[0.05, -0.03, 3.0], [0.15, 0.1, 3.5], [-0.3, 0.2, 4.0], [0.02, 0.03, 2.5]]
+    scales = [[0.05, 0.03, 0.04], [0.08, 0.05, 0.06], [0.3, 0.2, 0.1], [0.6, 0.65, 0.6]]
+    quats = rng.normal(size=(4, 4))
+    sc = hand_scene(means, scales, quats=quats, opac=[0.7, 0.6, 0.5, 0.998], sh_degree=3, sh=sh)
+    sc = dataclasses.replace(sc, **{f: getattr(sc, f).astype(np.float32)
+                                    for f in ("means", "scales", "quats", "opacities", "sh")})
+    cam = axis_camera(88, 72, f=80.0)
+    cfg = R.Config(method="3dgut", sh_degree=3, tile=8, bg=(0.2, 0.1, 0.05))
+    dimg = _dimg(cam, seed=5)
+    g = run_gpu(sc, cam, cfg, dimgs=[dimg])
+    rec = g["splat"][:, :21].astype(np.float64)
+    assert (g["tc"] > 0).all() and rec[1, 7] == 0.0
+    px = np.array([[x, y] for y in range(cam.height) for x in range(cam.width)], np.int32)
+    resp = oracle.gut_response(np.repeat(rec[3:4], len(px), 0), px, cam32(cam))
+    assert (rec[3, 5] * resp).max() > 0.99, "the wide Gaussian must clamp near its centre"
+    w16, worst, nex = _backward_check(sc, cam, cfg, g, dimg)
+    assert np.all(g["grads"]["sh"].reshape(16, 3, 4)[:, 1, 1] == 0), "clamped green passed"
+    log(f"[G5] clamp scene: grad16 {w16:.2e}, params {worst}, excluded {nex}")
+
+
+def test_gut_backward_accumulate_and_batch():
+    """accumulate adds to the buffers; a batch of three views over two
+    scenes gives each scene the sum of its views' gradients from one call
+    (within the gradient tolerance: the float atomics sum in another
+    order)."""
+    import torch
+    sa = scene_clusters(3000, seed=11, n_clusters=4, box=1.2, lo=0.01, hi=0.25, sh_degree=1)
+    sb = scene_clusters(2000, seed=12, n_clusters=3, box=1.0, lo=0.01, hi=0.3, sh_degree=1)
+    cams = [camera_look_at((0.3, -0.2, -3.9), 90, 70), camera_look_at((-0.4, 0.1, -4.1), 64, 80),
+            camera_look_at((0.1, 0.4, -3.7), 72, 60)]
+    cfg = R.Config(method="3dgut", sh_degree=1)
+    scenes = [R.Scene.from_host(sa), R.Scene.from_host(sb)]
+    vs = [0, 1, 0]
+    views = R.Views(scenes, cams, vs, cfg)
     proj = R.xpr_project(views, cfg)
-    assert proj.splat.shape[1] == 24
     bins = R.xpr_bin_sort(views, cfg, proj)
     frame = R.xpr_render_fwd(views, cfg, proj, bins)
-    import torch
-    dimg = torch.zeros(3 * views.pixels, dtype=torch.float32, device="cuda")
-    with pytest.raises(L.XprError) as e:
-        R.xpr_render_bwd(views, cfg, proj, bins, frame, dimg)
-    assert e.value.status == L.XPR_ERR_UNSUPPORTED
+    dimgs = [_dimg(c, seed=20 + i) for i, c in enumerate(cams)]
+    flat = torch.cat([torch.from_numpy(d).reshape(-1) for d in dimgs]).cuda()
+    grads, _ = R.xpr_render_bwd(views, cfg, proj, bins, frame, flat)
+    # per-view single calls, summed per scene
+    per = [None, None]
+    for v, (cam, s) in enumerate(zip(cams, vs)):
+        one = run_gpu([sa, sb][s], cam, cfg, dimgs=[dimgs[v]])
+        if per[s] is None:
+            per[s] = {k: x.astype(np.float64) for k, x in one["grads"].items()}
+        else:
+            for k in per[s]:
+                per[s][k] += one["grads"][k]
+    for s in range(2):
+        n = scenes[s].n
+        for k in per[s]:
+            got = grads[s][k].cpu().numpy().astype(np.float64)
+            got = got.reshape(-1, n).T if got.ndim > 1 else got
+            ref = per[s][k].reshape(-1, n).T if per[s][k].ndim > 1 else per[s][k]
+            rel_check(got, ref, f"scene {s} {k}")
+    # accumulate: a second call adds the same gradient again
+    acc = [{k: t.clone() for k, t in gs.items()} for gs in grads]
+    R.xpr_render_bwd(views, cfg, proj, bins, frame, flat, grads=acc, accumulate=True)
+    for s in range(2):
+        for k in acc[s]:
+            rel_check((acc[s][k] - grads[s][k]).cpu().numpy(), grads[s][k].cpu().numpy(),
+                      f"accumulate {s} {k}")
+    log(f"[G6] batch of 3 views over 2 scenes, {views.records} records, I={bins.count}")

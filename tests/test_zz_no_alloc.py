@@ -5,7 +5,7 @@ C-ABI: two calls in a row, the second with a smaller batch, each equal to
 the existing entry point's parameter gradients within the gradient
 tolerance (float atomics vary the last bits); with accumulate the result
 adds to what the buffers held. Nothing is allocated on the device by the
-call itself."""
+call itself. For 3DGS and for 3DGUT (64 bytes of scratch per record)."""
 import numpy as np
 import pytest
 import torch
@@ -17,10 +17,10 @@ from synth import camera_look_at, scene_clusters
 pytestmark = pytest.mark.gpu
 
 
-def _forward(n, W, H, seed):
+def _forward(n, W, H, seed, method):
     sc = scene_clusters(n, seed=seed, n_clusters=8, box=1.3, lo=0.005, hi=0.25, sh_degree=3)
     cam = camera_look_at((0.4, -0.3, -3.8), W, H)
-    cfg = R.Config(sh_degree=3)
+    cfg = R.Config(sh_degree=3, method=method)
     scene = R.Scene.from_host(sc)
     views = R.Views([scene], [cam], [0], cfg)
     proj = R.xpr_project(views, cfg)
@@ -43,9 +43,10 @@ def _compare(got, ref, n, tag):
     return worst
 
 
-def test_noalloc_equals_existing_entry_point_on_two_calls():
+@pytest.mark.parametrize("method", ["3dgs", "3dgut"])
+def test_noalloc_equals_existing_entry_point_on_two_calls(method):
     for call, (n, W, H, seed) in enumerate([(40_000, 320, 240, 1), (9_000, 150, 97, 2)]):
-        scene, views, cfg, proj, bins, frame, dimg = _forward(n, W, H, seed)
+        scene, views, cfg, proj, bins, frame, dimg = _forward(n, W, H, seed, method)
         ref = R.xpr_render_bwd(views, cfg, proj, bins, frame, dimg)[0][0]
         got = scene.zeros_like_grads()
         for t in got.values():
@@ -56,7 +57,7 @@ def test_noalloc_equals_existing_entry_point_on_two_calls():
         torch.cuda.synchronize()
         assert torch.cuda.memory_allocated() == before
         worst = _compare(got, ref, n, f"call {call}")
-        log(f"[noalloc] call {call}: n={n} {W}x{H}, I={bins.count}, worst {worst}")
+        log(f"[noalloc] {method} call {call}: n={n} {W}x{H}, I={bins.count}, worst {worst}")
     # accumulate: adds the gradient to the buffers' contents
     acc = {k: v.clone() for k, v in got.items()}
     R.xpr_render_bwd_noalloc(views, cfg, proj, bins, frame, dimg, [acc], accumulate=True)
