@@ -98,6 +98,11 @@ def lib():
         L.orc_lin_chord.restype = None
         L.orc_render_fwd_lin.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P, P, P, P, P]
         L.orc_render_fwd_lin.restype = None
+        L.orc_render_bwd_lin.argtypes = [i32, i32, i32, i32, i64, P, P, P, P, P, P]
+        L.orc_render_bwd_lin.restype = None
+        L.orc_project_bwd_lin.argtypes = [i64, P, P, P, P, P, i32, P, i32, i32, P, i32, i32,
+                                          i32, P, P, P, P, P, P]
+        L.orc_project_bwd_lin.restype = None
         L.orc_render_bwd_gut.argtypes = [i32, i32, i32, i32, i64, P, P, P, P, P, P, P]
         L.orc_render_bwd_gut.restype = None
         L.orc_project_bwd_gut.argtypes = [i64, P, P, P, P, P, i32, P, i32, i32, P, i32, i32, i32,
@@ -418,10 +423,45 @@ def project_bwd_gut(scene, cam, cfg: OracleConfig, grad16):
     return g
 
 
+def render_bwd_lin(rec, vals, ranges, W: int, H: int, cfg: OracleConfig, dimg):
+    """LinPrim: dL/d(u, v, sigma, r, g, b, c0 (3), c1 (3), c2 (3), 0) [n][16]
+    from dL/dimage."""
+    rec = _f64(rec)
+    n = rec.shape[0]
+    grad = np.zeros((n, 16))
+    lib().orc_render_bwd_lin(W, H, cfg.tile_w, cfg.tile_h, n, _p(rec),
+                             _p(np.ascontiguousarray(vals, np.int32)),
+                             _p(np.ascontiguousarray(ranges, np.int32)), _p(cfg.render_cfg()),
+                             _p(_f64(dimg)), _p(grad))
+    return grad
+
+
+def project_bwd_lin(scene, cam, cfg: OracleConfig, grad16):
+    """LinPrim parameter gradients (means, half-extent scales, opacity, raw
+    quaternion, SH) from the record gradient [n][16]."""
+    m, s, q, o, sh = _scene_arrays(scene)
+    n = o.shape[0]
+    K = sh.shape[0]
+    g = dict(means=np.zeros((3, n)), scales=np.zeros((3, n)), quats=np.zeros((4, n)),
+             opacities=np.zeros(n), sh=np.zeros((K, 3, n)))
+    lib().orc_project_bwd_lin(n, _p(m), _p(s), _p(q), _p(o), _p(sh), K, _p(cam_vec(cam)),
+                              cam.width, cam.height, _p(cfg.proj_cfg()), cfg.tile_w, cfg.tile_h,
+                              cfg.sh_degree, _p(_f64(grad16)), _p(g["means"]), _p(g["scales"]),
+                              _p(g["quats"]), _p(g["opacities"]), _p(g["sh"]))
+    return g
+
+
 def backward(scene, cam, cfg: OracleConfig, dimg, state=None):
-    """Analytic gradient of <dimg, image> with respect to the scene (3DGS
-    and 3DGUT; LinPrim is forward only). ``grad9`` (3DGS) or ``grad16``
-    (3DGUT) holds the shader data's gradient."""
+    """Analytic gradient of <dimg, image> with respect to the scene (3DGS,
+    3DGUT and LinPrim). ``grad9`` (3DGS) or ``grad16`` (3DGUT, LinPrim)
+    holds the shader data's gradient."""
+    if cfg.method == "linprim":
+        st = render(scene, cam, cfg) if state is None else state
+        g16 = render_bwd_lin(st["proj"]["rec"], st["bins"]["vals"], st["bins"]["ranges"],
+                             cam.width, cam.height, cfg, dimg)
+        g = project_bwd_lin(scene, cam, cfg, g16)
+        g["grad16"] = g16
+        return g
     if cfg.method == "3dgut":
         st = render(scene, cam, cfg) if state is None else state
         g16 = render_bwd_gut(st["proj"]["rec"], st["bins"]["vals"], st["bins"]["ranges"], cam,
@@ -430,7 +470,7 @@ def backward(scene, cam, cfg: OracleConfig, dimg, state=None):
         g["grad16"] = g16
         return g
     if cfg.method != "3dgs":
-        raise NotImplementedError("the oracle's backward covers 3DGS and 3DGUT")
+        raise NotImplementedError(f"unknown method {cfg.method!r}")
     st = render(scene, cam, cfg) if state is None else state
     g9 = render_bwd(st["proj"]["rec"], st["bins"]["vals"], st["bins"]["ranges"],
                     cam.width, cam.height, cfg, dimg)

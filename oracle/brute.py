@@ -286,13 +286,23 @@ def render_gut_torch(means, scales, quats, opac, sh, cam, cfg: OracleConfig, kee
 
 def render_lin(scene, cam, cfg: OracleConfig):
     """Per-pixel brute force of LinPrim (Listing "Implementation of
-    XPR-LinPrim"), forward only, in torch float64: the linear map A of each
-    octahedron (perspective Jacobian rows over the unit viewing direction,
-    times the rotations and half-extents), its slab pairs from the rows of
-    A^-1, the chord of every pixel's ray, Beer-Lambert opacity, the gates of
-    the 3DGS path, in (float32 Euclidean depth, index) order over the
-    Gaussians whose rect holds the pixel's tile. No pairs, no sort."""
-    means, scales, quats, opac, sh = scene_tensors(scene)
+    XPR-LinPrim") in torch float64: the linear map A of each octahedron
+    (perspective Jacobian rows over the unit viewing direction, times the
+    rotations and half-extents), its slab pairs from the rows of A^-1, the
+    chord of every pixel's ray, Beer-Lambert opacity, the gates of the 3DGS
+    path, in (float32 Euclidean depth, index) order over the Gaussians whose
+    rect holds the pixel's tile. No pairs, no sort. Returns numpy image
+    [3, H, W] and T_final [H, W]."""
+    with torch.no_grad():
+        img, T = render_lin_torch(*scene_tensors(scene), cam, cfg)
+    return img.numpy(), T.numpy()
+
+
+def render_lin_torch(means, scales, quats, opac, sh, cam, cfg: OracleConfig, keep=None):
+    """render_lin on tensors, differentiable (decisions on detached values):
+    returns image [3, H, W] and T_final [H, W] tensors. With a dict ``keep``
+    the shader data u, v (mu_2D - 1/2) [G], sigma [G], colour [G, 3] and the
+    rows of A^-1 [G, 3, 3] are stored in it, their gradients retained."""
     G = opac.shape[0]
     Rw = torch.as_tensor(np.asarray(cam.R), dtype=torch.float64)
     tw = torch.as_tensor(np.asarray(cam.t), dtype=torch.float64)
@@ -305,34 +315,40 @@ def render_lin(scene, cam, cfg: OracleConfig):
                      torch.stack([x / d, y / d, z / d], 1)], 1)
     A = J @ Rw @ _quat_rot(quats) * scales[:, None, :]
     smin = scales.min(dim=1).values
-    detA = torch.linalg.det(A)
-    ok = (z > cfg.z_near) & (smin > 0) & (detA.abs() > 0)
+    detA = torch.linalg.det(A.detach())
+    ok = (z.detach() > cfg.z_near) & (smin.detach() > 0) & (detA.abs() > 0)
     Ainv = torch.linalg.inv(torch.where(ok[:, None, None], A, torch.eye(3, dtype=torch.float64)))
     u2 = cam.fx * x / z + cam.cx
     v2 = cam.fy * y / z + cam.cy
-    ex = A[:, 0, :].abs().max(dim=1).values
-    ey = A[:, 1, :].abs().max(dim=1).values
+    ex = A[:, 0, :].abs().max(dim=1).values.detach()
+    ey = A[:, 1, :].abs().max(dim=1).values.detach()
     o = torch.clamp(opac, 0.0, 0.999)
     sigma = -torch.log1p(-0.99 * o) / (2 * smin)
     u, v = u2 - 0.5, v2 - 0.5
+    ud, vd = u.detach(), v.detach()
     txn = (cam.width + cfg.tile_w - 1) // cfg.tile_w
     tyn = (cam.height + cfg.tile_h - 1) // cfg.tile_h
-    x0 = torch.clamp(torch.floor((u - ex) / cfg.tile_w), 0, txn)
-    x1 = torch.clamp(torch.floor((u + ex) / cfg.tile_w) + 1, 0, txn)
-    y0 = torch.clamp(torch.floor((v - ey) / cfg.tile_h), 0, tyn)
-    y1 = torch.clamp(torch.floor((v + ey) / cfg.tile_h) + 1, 0, tyn)
-    visible = ok & (torch.maximum(ex, ey) > 0) & ((x1 - x0) * (y1 - y0) > 0) & (d > cfg.z_near)
+    x0 = torch.clamp(torch.floor((ud - ex) / cfg.tile_w), 0, txn)
+    x1 = torch.clamp(torch.floor((ud + ex) / cfg.tile_w) + 1, 0, txn)
+    y0 = torch.clamp(torch.floor((vd - ey) / cfg.tile_h), 0, tyn)
+    y1 = torch.clamp(torch.floor((vd + ey) / cfg.tile_h) + 1, 0, tyn)
+    visible = ok & (torch.maximum(ex, ey) > 0) & ((x1 - x0) * (y1 - y0) > 0) & (d.detach() > cfg.z_near)
     campos = -(Rw.T @ tw)
     dirs = (means - campos) / (means - campos).norm(dim=1, keepdim=True)
     nb = (cfg.sh_degree + 1) ** 2
     colour = torch.clamp(0.5 + torch.einsum("gj,gjc->gc", _sh_real(cfg.sh_degree, dirs),
                                             sh[:, :nb, :]), min=0.0)
+    if keep is not None:
+        for name, t in (("u", u), ("v", v), ("sigma", sigma), ("colour", colour), ("c", Ainv)):
+            if t.requires_grad:
+                t.retain_grad()
+            keep[name] = t
     W, H = cam.width, cam.height
     ys, xs = torch.meshgrid(torch.arange(H, dtype=torch.float64),
                             torch.arange(W, dtype=torch.float64), indexing="ij")
     xs, ys = xs.reshape(-1), ys.reshape(-1)
     ptx, pty = (xs // cfg.tile_w).long(), (ys // cfg.tile_h).long()
-    order = np.lexsort((np.arange(G), d.to(torch.float32).numpy()))
+    order = np.lexsort((np.arange(G), d.detach().to(torch.float32).numpy()))
     img = torch.zeros(3, H * W, dtype=torch.float64)
     T = torch.ones(H * W, dtype=torch.float64)
     done = torch.zeros(H * W, dtype=torch.bool)
@@ -340,7 +356,7 @@ def render_lin(scene, cam, cfg: OracleConfig):
         if not bool(visible[g]):
             continue
         inside = (ptx >= int(x0[g])) & (ptx < int(x1[g])) & (pty >= int(y0[g])) & (pty < int(y1[g]))
-        dx, dy = xs + 0.5 - u2[g], ys + 0.5 - v2[g]
+        dx, dy = xs - u[g], ys - v[g]
         c = Ainv[g]
         enter = torch.full_like(xs, -math.inf)
         exit_ = torch.full_like(xs, math.inf)
@@ -349,21 +365,26 @@ def render_lin(scene, cam, cfg: OracleConfig):
             for e2 in (1.0, -1.0):
                 nvec = c[0] + e1 * c[1] + e2 * c[2]
                 w = nvec[0] * dx + nvec[1] * dy
-                if abs(float(nvec[2])) >= 1e-10:
-                    m, h = -w / nvec[2], 1.0 / abs(float(nvec[2]))
+                if abs(float(nvec[2].detach())) >= 1e-10:
+                    m, h = -w / nvec[2], 1.0 / nvec[2].abs()
                     enter = torch.maximum(enter, m - h)
                     exit_ = torch.minimum(exit_, m + h)
                 else:
-                    miss = miss | (w.abs() > 1.0)
+                    miss = miss | (w.detach().abs() > 1.0)
         chord = torch.where(miss, torch.full_like(xs, -1.0), exit_ - enter)
-        alpha = torch.clamp(-torch.expm1(-sigma[g] * chord), max=cfg.alpha_max)
-        live = inside & ~done & (chord > 0) & (alpha >= cfg.alpha_min)
-        Tn = T * (1 - alpha)
-        stop = live & (Tn < cfg.t_min)
-        done = done | stop
-        blend = live & ~stop
+        # alpha of the pixels the ray misses (chord <= 0, gated out below) is
+        # formed from chord 0, so that no overflowing exponential reaches
+        # the gradient through the gate
+        alpha = torch.clamp(-torch.expm1(-sigma[g] * torch.clamp(chord, min=0.0)),
+                            max=cfg.alpha_max)
+        with torch.no_grad():
+            live = inside & ~done & (chord > 0) & (alpha >= cfg.alpha_min)
+            Tn = T * (1 - alpha)
+            stop = live & (Tn < cfg.t_min)
+            done = done | stop
+            blend = live & ~stop
         a_ = torch.where(blend, alpha, torch.zeros_like(alpha))
         img = img + colour[g][:, None] * (a_ * T)[None, :]
         T = T * (1 - a_)
     img = img + T[None, :] * torch.as_tensor(cfg.bg, dtype=torch.float64)[:, None]
-    return img.view(3, H, W).numpy(), T.view(H, W).numpy()
+    return img.view(3, H, W), T.view(H, W)

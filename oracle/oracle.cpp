@@ -1681,4 +1681,289 @@ void orc_project_bwd_gut(int64_t n, const double* means, const double* scales,
   }
 }
 
+
+// ----------------------------------------------------------------------------
+// LinPrim backward. The forward (Listing XPR-LinPrim: project and evaluate,
+// blended by Algorithm 1) differentiated by hand, as the paper obtains it by
+// automatic differentiation (section Key Interfaces). The record gradient
+// holds the 15 values evaluate reads -- u, v (mu_2D - 1/2), sigma, the
+// colour (3), the rows c0, c1, c2 of A^-1 (9) -- and a 16th slot that stays
+// zero: [n][16]. ex, ey only place the rect (piecewise constant).
+// ----------------------------------------------------------------------------
+
+// The chord of lin_chord with the slabs that bound it: the entry point is
+// max over slabs of m_i - h_i (slab *ia), the exit min of m_i + h_i (slab
+// *ib); the first slab reaching the extreme is taken. Returns the chord
+// (<= 0 when the ray misses); slabs with |n_z| < 1e-10 bound neither.
+double lin_chord_slabs(const double* c, double dx, double dy, int* ia, int* ib) {
+  double enter = -INFINITY, exit_ = INFINITY;
+  *ia = *ib = -1;
+  for (int i = 0; i < 4; ++i) {
+    const double e1 = (i & 2) ? -1.0 : 1.0, e2 = (i & 1) ? -1.0 : 1.0;
+    const double nx = c[0] + e1 * c[3] + e2 * c[6];
+    const double ny = c[1] + e1 * c[4] + e2 * c[7];
+    const double nz = c[2] + e1 * c[5] + e2 * c[8];
+    const double w = nx * dx + ny * dy;
+    if (std::fabs(nz) >= 1e-10) {
+      const double m = -w / nz, h = 1.0 / std::fabs(nz);
+      if (m - h > enter) { enter = m - h; *ia = i; }
+      if (m + h < exit_) { exit_ = m + h; *ib = i; }
+    } else if (std::fabs(w) > 1.0) {
+      return -1.0;
+    }
+  }
+  return exit_ - enter;
+}
+
+// dL/d(u, v, sigma, r, g, b, c0, c1, c2, 0) per record [n][16] from
+// dL/dimage [3][H][W]. Per pixel the blended entries are found front to back
+// (as in orc_render_fwd_lin), then walked back with the colour behind, as
+// in orc_render_bwd. With e = exp(-sigma chord) and alpha = 1 - e (not
+// clamped): dL/dsigma = e chord dL/dalpha, dL/dchord = e sigma dL/dalpha.
+// chord = (m_b + h_b) - (m_a - h_a) for the exit slab b and entry slab a,
+// m = -(n_x dx + n_y dy) / n_z, h = 1 / |n_z|, n_i = c0 +- c1 +- c2 and
+// (dx, dy) = (x - u, y - v):
+//   dm/dn = (-dx / n_z, -dy / n_z, -m / n_z), dh/dn_z = -sgn(n_z) h^2,
+//   dm/du = n_x / n_z, dm/dv = n_y / n_z.
+void orc_render_bwd_lin(int W, int H, int tile_w, int tile_h, int64_t n, const double* rec,
+                        const int32_t* vals, const int32_t* ranges, const double* cfg,
+                        const double* dimg, double* grad) {
+  const double alpha_min = cfg[0], alpha_max = cfg[1], t_min = cfg[2];
+  const double bg[3] = {cfg[3], cfg[4], cfg[5]};
+  const int tiles_x = (W + tile_w - 1) / tile_w;
+  const int tiles_y = (H + tile_h - 1) / tile_h;
+  int nthreads = 1;
+#ifdef _OPENMP
+  nthreads = omp_get_max_threads();
+#endif
+  std::vector<std::vector<double>> part(nthreads);
+#pragma omp parallel
+  {
+    int tid = 0;
+#ifdef _OPENMP
+    tid = omp_get_thread_num();
+#endif
+    std::vector<double>& acc = part[tid];
+    acc.assign((size_t)n * 16, 0.0);
+    struct Step { int64_t g; double alpha, T, chord; int ia, ib; bool clamped; };
+    std::vector<Step> steps;
+#pragma omp for schedule(dynamic, 1)
+    for (int t = 0; t < tiles_x * tiles_y; ++t) {
+      const int tx = t % tiles_x, ty = t / tiles_x;
+      const int32_t start = ranges[2 * t], end = ranges[2 * t + 1];
+      for (int py = ty * tile_h; py < std::min(H, (ty + 1) * tile_h); ++py)
+        for (int px = tx * tile_w; px < std::min(W, (tx + 1) * tile_w); ++px) {
+          steps.clear();
+          double T = 1.0;
+          for (int32_t k = start; k < end; ++k) {
+            const int64_t gi = vals[k];
+            const double* r = rec + 17 * gi;
+            int ia, ib;
+            const double ch = lin_chord_slabs(r + 8, px - r[0], py - r[1], &ia, &ib);
+            if (!(ch > 0.0)) continue;
+            const double raw = -std::expm1(-r[2] * ch);
+            const double alpha = std::min(alpha_max, raw);
+            if (alpha < alpha_min) continue;
+            const double Tn = T * (1.0 - alpha);
+            if (Tn < t_min) break;
+            steps.push_back(Step{gi, alpha, T, ch, ia, ib, raw > alpha_max});
+            T = Tn;
+          }
+          const double Tfin = T;
+          const int64_t p = (int64_t)py * W + px;
+          const double G[3] = {dimg[p], dimg[(int64_t)W * H + p], dimg[2 * (int64_t)W * H + p]};
+          const double bgG = bg[0] * G[0] + bg[1] * G[1] + bg[2] * G[2];
+          double S[3] = {0, 0, 0};
+          for (int si = (int)steps.size() - 1; si >= 0; --si) {
+            const Step& st = steps[si];
+            const double* r = rec + 17 * st.g;
+            double* ga = acc.data() + 16 * st.g;
+            double dalpha = 0;
+            for (int c = 0; c < 3; ++c) {
+              ga[3 + c] += st.alpha * st.T * G[c];
+              dalpha += st.T * (r[3 + c] - S[c]) * G[c];
+            }
+            dalpha -= Tfin * bgG / (1.0 - st.alpha);
+            for (int c = 0; c < 3; ++c) S[c] = st.alpha * r[3 + c] + (1.0 - st.alpha) * S[c];
+            if (st.clamped) continue;
+            const double e = std::exp(-r[2] * st.chord);
+            ga[2] += e * st.chord * dalpha;
+            const double dch = e * r[2] * dalpha;
+            const double* c = r + 8;
+            const double dx = px - r[0], dy = py - r[1];
+            // exit slab (kappa = +1) and entry slab (kappa = -1)
+            for (int side = 0; side < 2; ++side) {
+              const int i = side == 0 ? st.ib : st.ia;
+              const double kappa = side == 0 ? 1.0 : -1.0;
+              const double e1 = (i & 2) ? -1.0 : 1.0, e2 = (i & 1) ? -1.0 : 1.0;
+              const double nx = c[0] + e1 * c[3] + e2 * c[6];
+              const double ny = c[1] + e1 * c[4] + e2 * c[7];
+              const double nz = c[2] + e1 * c[5] + e2 * c[8];
+              const double m = -(nx * dx + ny * dy) / nz, h = 1.0 / std::fabs(nz);
+              const double sg = nz > 0 ? 1.0 : -1.0;
+              // d chord / d n_i: kappa dm/dn + dh/dn (h enters the chord with +)
+              const double gn[3] = {dch * kappa * (-dx / nz), dch * kappa * (-dy / nz),
+                                    dch * (kappa * (-m / nz) - sg * h * h)};
+              for (int k = 0; k < 3; ++k) {
+                ga[6 + k] += gn[k];
+                ga[9 + k] += e1 * gn[k];
+                ga[12 + k] += e2 * gn[k];
+              }
+              ga[0] += dch * kappa * nx / nz;
+              ga[1] += dch * kappa * ny / nz;
+            }
+          }
+        }
+    }
+  }
+  for (int64_t k = 0; k < n * 16; ++k) {
+    double s = 0;
+    for (int th = 0; th < nthreads; ++th)
+      if (!part[th].empty()) s += part[th][k];
+    grad[k] = s;
+  }
+}
+
+// Backward of the LinPrim projection: from dL/d(u, v, sigma, colour, c0,
+// c1, c2) [n][16] to the gradients of the inputs (means, scales as
+// half-extents, opacity, raw quaternion, SH), [k][n], overwritten; not
+// visible: zero. Through mu_2D = (fx x / z + cx, fy y / z + cy) of the
+// camera-space centre (x, y, z); sigma = -log(1 - 0.99 o) / (2 s_min) with
+// o = min(0.999, max(0, opacity)) (no gradient where the clip holds, the
+// whole s_min term to the smallest scale); C = A^-1 for
+// A = J3 R_w2c Rq diag(s) (dL/dA = -C^T dL/dC C^T), J3's perspective rows
+// and unit viewing direction differentiated with respect to (x, y, z);
+// the colour as for 3DGS.
+void orc_project_bwd_lin(int64_t n, const double* means, const double* scales,
+                         const double* quats, const double* opac, const double* sh, int K,
+                         const double* camv, int W, int H, const double* cfg, int tile_w,
+                         int tile_h, int deg, const double* grad, double* g_means,
+                         double* g_scales, double* g_quats, double* g_opac, double* g_sh) {
+  const Cam cam = read_cam(camv, W, H);
+  const int nb = (deg + 1) * (deg + 1);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    for (int c = 0; c < 3; ++c) { g_means[c * n + i] = 0; g_scales[c * n + i] = 0; }
+    for (int c = 0; c < 4; ++c) g_quats[c * n + i] = 0;
+    g_opac[i] = 0;
+    for (int j = 0; j < K; ++j)
+      for (int ch = 0; ch < 3; ++ch) g_sh[(int64_t)(j * 3 + ch) * n + i] = 0;
+    LinProj L;
+    project_lin_one(i, n, means, scales, quats, opac, sh, cam, cfg, tile_w, tile_h, deg, L);
+    if (L.tc == 0) continue;
+    const double* g = grad + 16 * i;
+    const double mu[3] = {means[i], means[n + i], means[2 * n + i]};
+    const double q[4] = {quats[i], quats[n + i], quats[2 * n + i], quats[3 * n + i]};
+    const double qnorm = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const double qn[4] = {q[0] / qnorm, q[1] / qnorm, q[2] / qnorm, q[3] / qnorm};
+    double Rq[9];
+    quat_to_rot(qn, Rq);
+    const double s[3] = {scales[i], scales[n + i], scales[2 * n + i]};
+    double mc[3];
+    for (int r = 0; r < 3; ++r)
+      mc[r] = cam.R[3 * r] * mu[0] + cam.R[3 * r + 1] * mu[1] + cam.R[3 * r + 2] * mu[2] + cam.t[r];
+    const double x = mc[0], y = mc[1], z = mc[2];
+    const double d = std::sqrt(x * x + y * y + z * z);
+    double gmc[3] = {0, 0, 0}, gmu[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gRq[9] = {0};
+
+    // mean2D (u = mu_2D.x - 1/2, v likewise)
+    gmc[0] += g[0] * cam.fx / z;
+    gmc[1] += g[1] * cam.fy / z;
+    gmc[2] += -g[0] * cam.fx * x / (z * z) - g[1] * cam.fy * y / (z * z);
+
+    // sigma
+    int jmin = 0;
+    for (int j = 1; j < 3; ++j)
+      if (s[j] < s[jmin]) jmin = j;
+    const double o = std::min(0.999, std::max(0.0, opac[i]));
+    const double smin = s[jmin];
+    if (opac[i] > 0.0 && opac[i] < 0.999) g_opac[i] = g[2] * 0.99 / ((1.0 - 0.99 * o) * 2.0 * smin);
+    gs[jmin] += -g[2] * L.sigma / smin;
+
+    // colour = max(0, 0.5 + sum_j sh_j Y_j(dir)), dir = (mu - campos) / |.|
+    const double cp[3] = {
+        -(cam.R[0] * cam.t[0] + cam.R[3] * cam.t[1] + cam.R[6] * cam.t[2]),
+        -(cam.R[1] * cam.t[0] + cam.R[4] * cam.t[1] + cam.R[7] * cam.t[2]),
+        -(cam.R[2] * cam.t[0] + cam.R[5] * cam.t[1] + cam.R[8] * cam.t[2])};
+    double dv[3] = {mu[0] - cp[0], mu[1] - cp[1], mu[2] - cp[2]};
+    const double dn = std::sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+    for (int c = 0; c < 3; ++c) dv[c] /= dn;
+    double Y[16], dY[16][3];
+    sh_basis(deg, dv, Y, dY);
+    double gdir[3] = {0, 0, 0};
+    for (int ch = 0; ch < 3; ++ch) {
+      double raw = 0.5;
+      for (int j = 0; j < nb; ++j) raw += sh[(int64_t)(j * 3 + ch) * n + i] * Y[j];
+      const double gr = raw > 0 ? g[3 + ch] : 0.0;
+      for (int j = 0; j < nb; ++j) {
+        g_sh[(int64_t)(j * 3 + ch) * n + i] = Y[j] * gr;
+        const double wgt = sh[(int64_t)(j * 3 + ch) * n + i] * gr;
+        for (int c = 0; c < 3; ++c) gdir[c] += wgt * dY[j][c];
+      }
+    }
+    const double dd = dv[0] * gdir[0] + dv[1] * gdir[1] + dv[2] * gdir[2];
+    for (int c = 0; c < 3; ++c) gmu[c] += (gdir[c] - dv[c] * dd) / dn;
+
+    // C = A^-1 (rows c0, c1, c2): dL/dA = -C^T dL/dC C^T
+    const double* C = L.c;
+    const double* GC = g + 6;
+    double T1[9], GA[9];
+    for (int r = 0; r < 3; ++r)  // T1 = dL/dC C^T
+      for (int c = 0; c < 3; ++c)
+        T1[3 * r + c] = GC[3 * r] * C[3 * c] + GC[3 * r + 1] * C[3 * c + 1] + GC[3 * r + 2] * C[3 * c + 2];
+    for (int r = 0; r < 3; ++r)  // GA = -C^T T1
+      for (int c = 0; c < 3; ++c)
+        GA[3 * r + c] = -(C[r] * T1[c] + C[3 + r] * T1[3 + c] + C[6 + r] * T1[6 + c]);
+    // A = J3 Wm diag(s), Wm = R_w2c Rq
+    const double J[9] = {cam.fx / z, 0.0, -cam.fx * x / (z * z), 0.0, cam.fy / z,
+                         -cam.fy * y / (z * z), x / d, y / d, z / d};
+    double Wm[9], JW[9];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c)
+        Wm[3 * r + c] = cam.R[3 * r] * Rq[c] + cam.R[3 * r + 1] * Rq[3 + c] + cam.R[3 * r + 2] * Rq[6 + c];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c)
+        JW[3 * r + c] = J[3 * r] * Wm[c] + J[3 * r + 1] * Wm[3 + c] + J[3 * r + 2] * Wm[6 + c];
+    double GJW[9];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        gs[c] += GA[3 * r + c] * JW[3 * r + c];
+        GJW[3 * r + c] = GA[3 * r + c] * s[c];
+      }
+    double GJ[9], GW[9];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        GJ[3 * r + c] = GJW[3 * r] * Wm[3 * c] + GJW[3 * r + 1] * Wm[3 * c + 1] + GJW[3 * r + 2] * Wm[3 * c + 2];
+        GW[3 * r + c] = J[r] * GJW[c] + J[3 + r] * GJW[3 + c] + J[6 + r] * GJW[6 + c];
+      }
+    for (int r = 0; r < 3; ++r)  // Wm = R_w2c Rq: dL/dRq = R_w2c^T dL/dWm
+      for (int c = 0; c < 3; ++c)
+        gRq[3 * r + c] = cam.R[r] * GW[c] + cam.R[3 + r] * GW[3 + c] + cam.R[6 + r] * GW[6 + c];
+    // J3 with respect to (x, y, z)
+    const double z2 = z * z, z3 = z2 * z;
+    gmc[2] += -GJ[0] * cam.fx / z2 + GJ[2] * 2.0 * cam.fx * x / z3 - GJ[4] * cam.fy / z2 +
+              GJ[5] * 2.0 * cam.fy * y / z3;
+    gmc[0] += -GJ[2] * cam.fx / z2;
+    gmc[1] += -GJ[5] * cam.fy / z2;
+    const double e[3] = {x / d, y / d, z / d};
+    const double ge = GJ[6] * e[0] + GJ[7] * e[1] + GJ[8] * e[2];
+    for (int c = 0; c < 3; ++c) gmc[c] += (GJ[6 + c] - e[c] * ge) / d;
+    // mc = R_w2c mu + t
+    for (int c = 0; c < 3; ++c)
+      gmu[c] += cam.R[c] * gmc[0] + cam.R[3 + c] * gmc[1] + cam.R[6 + c] * gmc[2];
+
+    for (int c = 0; c < 3; ++c) {
+      g_means[c * n + i] = gmu[c];
+      g_scales[c * n + i] = gs[c];
+    }
+    double dR[9][4];
+    quat_to_rot_jac(qn, dR);
+    double gqn[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 9; ++k)
+      for (int c = 0; c < 4; ++c) gqn[c] += gRq[k] * dR[k][c];
+    const double qd = qn[0] * gqn[0] + qn[1] * gqn[1] + qn[2] * gqn[2] + qn[3] * gqn[3];
+    for (int c = 0; c < 4; ++c) g_quats[c * n + i] = (gqn[c] - qn[c] * qd) / qnorm;
+  }
+}
+
 }  // extern "C"
