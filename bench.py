@@ -253,8 +253,9 @@ def main():
             log(f"[bench] {key}: {cr['ms_wall']:.3f} ms/step, pairs {cpairs:.0f} "
                 f"({cpairs / pairs:.3f} of {pairs:.0f})")
     if not args.no_cull_line and cfg.method == "3dgs":
-        # the 3DGUT method (forward only) on the same frames, against the
-        # forward stages of the 3DGS frame above
+        # the 3DGUT method on the same frames: forward alone, against the
+        # forward stages of the 3DGS frame above, then the whole training
+        # frame (forward, L1 loss, backward)
         gcfg = dataclasses.replace(cfg, method="3dgut")
         gr = timed_forward(scene, cams, gcfg, args.steps, args.warmup)
         fwd3 = mean["project"] + mean["bin_sort"] + mean["render_fwd"]
@@ -264,8 +265,21 @@ def main():
                                 "3dgs_forward_stage_sum_ms": round(fwd3, 4)}
         log(f"[bench] 3dgut forward: {gr['ms_wall']:.3f} ms/frame (3DGS forward stages "
             f"{fwd3:.3f} ms), pairs {gr['pairs']:.0f}")
-        # LinPrim (forward only): the same scene's parameters read as octahedra
-        # (scales as half-extents)
+        gt = timed_frames(scene, cams, gcfg, targets, args.steps, args.warmup, args.tile, names)
+        gmean = {k: float(np.mean(v)) for k, v in gt["stage_ms"].items()}
+        out["3dgut_train"] = {
+            "ms_per_step": round(gt["ms_wall"], 4),
+            "stage_sum_ms": round(float(np.mean(np.sum([gt["stage_ms"][k] for k in names],
+                                                       axis=0))), 4),
+            "stages_ms_mean": gmean,
+            "pairs_per_frame": float(np.mean(gt["work"]["pairs"])),
+            "blended_per_frame": float(np.mean(gt["work"]["blended"])),
+            "bwd_walked_per_frame": float(np.mean(gt["work"]["bwd_walked"])),
+            "3dgs_stage_sum_ms": round(frame_ms, 4)}
+        log(f"[bench] 3dgut forward+backward: {gt['ms_wall']:.3f} ms/step (render_bwd "
+            f"{gmean['render_bwd']:.3f} ms, project_bwd {gmean['project_bwd']:.3f} ms)")
+        # LinPrim: the same scene's parameters read as octahedra (scales as
+        # half-extents), forward alone and the whole training frame
         lcfg = dataclasses.replace(cfg, method="linprim")
         lr = timed_forward(scene, cams, lcfg, args.steps, args.warmup)
         out["linprim_forward"] = {"ms_per_step": round(lr["ms_wall"], 4),
@@ -273,6 +287,18 @@ def main():
                                   "pairs_per_frame": lr["pairs"],
                                   "3dgs_forward_stage_sum_ms": round(fwd3, 4)}
         log(f"[bench] linprim forward: {lr['ms_wall']:.3f} ms/frame, pairs {lr['pairs']:.0f}")
+        lt = timed_frames(scene, cams, lcfg, targets, args.steps, args.warmup, args.tile, names)
+        lmean = {k: float(np.mean(v)) for k, v in lt["stage_ms"].items()}
+        out["linprim_train"] = {
+            "ms_per_step": round(lt["ms_wall"], 4),
+            "stage_sum_ms": round(float(np.mean(np.sum([lt["stage_ms"][k] for k in names],
+                                                       axis=0))), 4),
+            "stages_ms_mean": lmean,
+            "pairs_per_frame": float(np.mean(lt["work"]["pairs"])),
+            "blended_per_frame": float(np.mean(lt["work"]["blended"])),
+            "bwd_walked_per_frame": float(np.mean(lt["work"]["bwd_walked"]))}
+        log(f"[bench] linprim forward+backward: {lt['ms_wall']:.3f} ms/step (render_bwd "
+            f"{lmean['render_bwd']:.3f} ms, project_bwd {lmean['project_bwd']:.3f} ms)")
         lccfg = dataclasses.replace(lcfg, tile_cull=True)
         lc = timed_forward(scene, cams, lccfg, args.steps, args.warmup)
         out["linprim_forward_tile_cull"] = {"ms_per_step": round(lc["ms_wall"], 4),
@@ -306,10 +332,10 @@ def timed_frames(scene, cams, cfg, targets, steps, warmup, tile, names):
     dev = torch.device("cuda:0")
     H, W = targets[0].shape[1], targets[0].shape[2]
     views = [R.Views([scene], [c], [0], cfg) for c in cams]
-    proj = R.empty_projected(scene.n, dev)
+    proj = R.empty_projected(scene.n, dev, R.splat_floats(cfg))
     frame = None
     tw = torch.zeros((views[0].tiles, 2), dtype=torch.int32, device=dev)
-    g2 = torch.empty((scene.n, 9), dtype=torch.float32, device=dev)
+    g2 = torch.empty((scene.n, R.grad2d_floats(cfg)), dtype=torch.float32, device=dev)
     grads = [scene.zeros_like_grads()]
     ws = R.Workspace()
     loss_buf = torch.empty(1, dtype=torch.float32, device=dev)

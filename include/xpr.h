@@ -64,7 +64,7 @@ typedef enum {
 #define XPR_METHOD_3DGUT 1 /* unscented-transform projection, ray evaluate; forward and
                               backward */
 #define XPR_METHOD_LINPRIM 2 /* octahedra (scales = half-extents), slab chords, Beer-Lambert;
-                                forward only, no tile_cull */
+                                forward and backward */
 
 /* Sort strategies of xpr_bin_sort; both produce the identical list. */
 #define XPR_SORT_PRESORT 0 /* sort Gaussians by depth, then pairs by tile */
@@ -317,7 +317,7 @@ xpr_status xpr_render_fwd(const xpr_views* views, const xpr_config* cfg, const x
 /* Workspace bytes xpr_render_bwd needs: the tile data of the split backward
  * (bwd_split_walk; 4 bytes per tile plus 512) followed by the per-record
  * shader-data gradients (36 bytes per record for XPR_METHOD_3DGS, 64 for
- * XPR_METHOD_3DGUT; used when grad2d is NULL). */
+ * XPR_METHOD_3DGUT and XPR_METHOD_LINPRIM; used when grad2d is NULL). */
 xpr_status xpr_render_bwd_workspace(const xpr_views* views, const xpr_config* cfg, size_t* bytes);
 
 /* Backward of compositing and projection: the derivative of the blending
@@ -341,8 +341,11 @@ xpr_status xpr_render_bwd_workspace(const xpr_views* views, const xpr_config* cf
  *   grad2d float (may be NULL): receives the derivative with respect to the
  *   shader data per record, [records][9] dL/d(u, v, A, B, C, o, r, g, b)
  *   for XPR_METHOD_3DGS, [records][16] dL/d(o', r, g, b, ro (3), M (9,
- *   row-major)) for XPR_METHOD_3DGUT (the values its evaluate reads; the
- *   2D mean and conic only place the rect); when NULL the workspace holds it.
+ *   row-major)) for XPR_METHOD_3DGUT (the values its evaluate reads, M's
+ *   derivative taken with the Gaussian's centre fixed; the 2D mean and
+ *   conic only place the rect), [records][16] dL/d(u, v, sigma, r, g, b,
+ *   c0 (3), c1 (3), c2 (3)) and a zero for XPR_METHOD_LINPRIM (ex, ey only
+ *   place the rect); when NULL the workspace holds it.
  * The compositing backward walks each pixel's list in reverse from its last
  * blended entry (T_i recovered as T_{i+1} / (1 - a_i)); tiles are scheduled
  * as in xpr_render_fwd. Gradient sums use float atomics, so the last bits
@@ -351,7 +354,10 @@ xpr_status xpr_render_bwd_workspace(const xpr_views* views, const xpr_config* cf
  * (the response along the ray, the unscented transform's 2D covariance in
  * the Mip-Splatting opacity factor, ro and M = S^-1 R^T); cfg->lds_batch,
  * bwd_ppt, persistent and bwd_split_walk do not apply to it (one thread per
- * pixel). XPR_METHOD_LINPRIM gives XPR_ERR_UNSUPPORTED. */
+ * pixel). For XPR_METHOD_LINPRIM the derivative of evaluate and project of
+ * the listing "Implementation of XPR-LinPrim": the Beer-Lambert alpha, the
+ * chord through its entry and exit slabs, sigma, and A^-1 =
+ * (J3 R_w2c R diag(s))^-1 (same launch shape as 3DGUT). */
 xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
                           const xpr_bins* bins, const float* dL_dimage, const float* T_final,
                           const int32_t* n_contrib, const xpr_scene_grad* grads,
@@ -364,8 +370,8 @@ xpr_status xpr_render_bwd(const xpr_views* views, const xpr_config* cfg, const x
  * replaced by a file-scope static device array of 64 MiB per device (1 MiB
  * of split-backward tile data, used for batches of up to 200,000 tiles,
  * then the per-record shader-data gradients, 36 bytes per record for
- * XPR_METHOD_3DGS, at most 1,835,008 records, 64 for XPR_METHOD_3DGUT, at
- * most 1,032,192; more fail with XPR_ERR_CAPACITY before anything is
+ * XPR_METHOD_3DGS, at most 1,835,008 records, 64 for XPR_METHOD_3DGUT and
+ * XPR_METHOD_LINPRIM, at most 1,032,192; more fail with XPR_ERR_CAPACITY before anything is
  * enqueued). Calls no
  * hipMalloc, hipFree or other allocating routine; the caller still owns
  * every input and the gradient buffers. Every call on a device shares that
@@ -391,8 +397,10 @@ xpr_status xpr_render_bwd_noalloc(const xpr_views* views, const xpr_config* cfg,
  * grad2d is [records][16] and the derivative is that of the listing
  * "Implementation of XPR-3DGUT", project: ro = M (campos - mu),
  * M = S^-1 R(q)^T, the opacity factor sqrt(det_orig / det) through the
- * seven projected sigma points, and the SH colour. XPR_METHOD_LINPRIM gives
- * XPR_ERR_UNSUPPORTED. */
+ * seven projected sigma points, and the SH colour. For XPR_METHOD_LINPRIM
+ * (grad2d [records][16]) that of its project: mean2D, sigma through the
+ * clipped opacity and the smallest scale, A^-1 through J3, R_w2c, R(q) and
+ * the scales, and the SH colour. */
 xpr_status xpr_project_bwd(const xpr_views* views, const xpr_config* cfg, const xpr_projected* proj,
                            const float* grad2d, const xpr_scene_grad* grads, int32_t accumulate,
                            hipStream_t stream);

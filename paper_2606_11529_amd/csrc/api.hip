@@ -14,8 +14,8 @@ namespace xpr {
 
 hipError_t launch_project(const Batch& B, int max_n, float* splat, float* depth, int16_t* rect,
                           int32_t* tc, hipStream_t st);
-hipError_t launch_project_bwd(const Batch& B, int max_n, const float* grad2d, const int32_t* tc,
-                              const GradDev* G, int accumulate, hipStream_t st);
+hipError_t launch_project_bwd(const Batch& B, int max_n, const float* splat, const float* grad2d,
+                              const int32_t* tc, const GradDev* G, int accumulate, hipStream_t st);
 size_t bin_workspace_bytes(int64_t n_rec, int64_t cap, int64_t tiles, int sort_mode, bool cull);
 hipError_t bin_phase1(const Batch& B, int sort_mode, bool cull, const float* splat,
                       const int16_t* rect, const float* depth, const int32_t* tc,
@@ -42,6 +42,10 @@ hipError_t launch_render_bwd(const Batch& B, int lds_batch, int ppt, bool persis
                              const int32_t* vals, const int32_t* ranges, int32_t* order,
                              const float* dimg, const float* Tfin, const int32_t* ncon,
                              float* grad2d, hipStream_t st);
+hipError_t launch_render_bwd_lin(const Batch& B, const float* splat, const int32_t* vals,
+                                 const int32_t* ranges, const int32_t* order, const float* dimg,
+                                 const float* Tfin, const int32_t* ncon, float* grad,
+                                 hipStream_t st);
 hipError_t launch_render_bwd_gut(const Batch& B, const float* splat, const int32_t* vals,
                                  const int32_t* ranges, const int32_t* order, const float* dimg,
                                  const float* Tfin, const int32_t* ncon, float* grad,
@@ -243,8 +247,9 @@ static xpr_status check_grads(const xpr_views* views, const xpr_scene_grad* grad
 }
 
 // Floats per record of the backward's shader-data gradient: 9 for 3DGS
-// (mean2D, conic, opacity, colour), 16 for 3DGUT (o', colour, ro, M).
-static size_t grad_width(int method) { return method == XPR_METHOD_3DGUT ? 16 : 9; }
+// (mean2D, conic, opacity, colour), 16 for 3DGUT (o', colour, ro, M) and
+// LinPrim (mean2D, sigma, colour, the rows of A^-1, one zero).
+static size_t grad_width(int method) { return method == XPR_METHOD_3DGS ? 9 : 16; }
 
 // Refuses a batch whose shader-data gradients (gw floats per record) do not
 // fit in cap bytes of static scratch.
@@ -453,10 +458,6 @@ static xpr_status render_bwd_impl(const xpr_views* views, const xpr_config* cfg,
   if (st != XPR_OK) return st;
   st = check_proj(proj, S);
   if (st != XPR_OK) return st;
-  if (cfg->method == XPR_METHOD_LINPRIM) {
-    set_error("the backward is built for XPR_METHOD_3DGS and XPR_METHOD_3DGUT");
-    return XPR_ERR_UNSUPPORTED;
-  }
   const size_t gw = grad_width(cfg->method);
   XPR_CHECK(bins && bins->tile_ranges && dL_dimage && T_final && n_contrib, "NULL buffer");
   XPR_CHECK(grads || grad2d, "grads and grad2d both NULL");
@@ -487,11 +488,15 @@ static xpr_status render_bwd_impl(const xpr_views* views, const xpr_config* cfg,
     if (st != XPR_OK) return st;
   }
   XPR_HIP(fill_zero_f32(g2, (int64_t)gw * S.records, stream));
-  if (cfg->method == XPR_METHOD_3DGUT) {
-    XPR_HIP(launch_render_bwd_gut(B, proj->splat, bins->vals, bins->tile_ranges, bins->tile_order,
-                                  dL_dimage, T_final, n_contrib, g2, stream));
+  if (cfg->method != XPR_METHOD_3DGS) {
+    if (cfg->method == XPR_METHOD_3DGUT)
+      XPR_HIP(launch_render_bwd_gut(B, proj->splat, bins->vals, bins->tile_ranges,
+                                    bins->tile_order, dL_dimage, T_final, n_contrib, g2, stream));
+    else
+      XPR_HIP(launch_render_bwd_lin(B, proj->splat, bins->vals, bins->tile_ranges,
+                                    bins->tile_order, dL_dimage, T_final, n_contrib, g2, stream));
     if (grads)
-      XPR_HIP(launch_project_bwd(B, S.max_n, g2, proj->tiles_touched, G, accumulate ? 1 : 0,
+      XPR_HIP(launch_project_bwd(B, S.max_n, proj->splat, g2, proj->tiles_touched, G, accumulate ? 1 : 0,
                                  stream));
     return XPR_OK;
   }
@@ -500,12 +505,12 @@ static xpr_status render_bwd_impl(const xpr_views* views, const xpr_config* cfg,
                             split_meta, proj->splat, bins->vals, bins->tile_ranges,
                             bins->tile_order, dL_dimage, T_final, n_contrib, g2, stream));
   if (grads)
-    XPR_HIP(launch_project_bwd(B, S.max_n, g2, proj->tiles_touched, G, accumulate ? 1 : 0, stream));
+    XPR_HIP(launch_project_bwd(B, S.max_n, proj->splat, g2, proj->tiles_touched, G, accumulate ? 1 : 0, stream));
   return XPR_OK;
 }
 
 // File-scope scratch of xpr_render_bwd_noalloc: the per-record shader-data
-// gradients (9 floats per record for 3DGS, 16 for 3DGUT). Each device holds its own copy for the life of the
+// gradients (9 floats per record for 3DGS, 16 for 3DGUT and LinPrim). Each device holds its own copy for the life of the
 // process. In host code ``scratch`` names a host-side stand-in, never the
 // device memory: kernels and fills get the address hipGetSymbolAddress
 // returns on each device.
@@ -595,16 +600,12 @@ xpr_status xpr_project_bwd(const xpr_views* views, const xpr_config* cfg, const 
   if (st != XPR_OK) return st;
   st = check_proj(proj, S);
   if (st != XPR_OK) return st;
-  if (cfg->method == XPR_METHOD_LINPRIM) {
-    set_error("the backward is built for XPR_METHOD_3DGS and XPR_METHOD_3DGUT");
-    return XPR_ERR_UNSUPPORTED;
-  }
   XPR_CHECK(grads != nullptr, "grads is NULL");
   XPR_CHECK(S.records == 0 || (grad2d && aligned(grad2d, 4)), "grad2d NULL or misaligned");
   GradDev G[XPR_MAX_SCENES];
   st = check_grads(views, grads, G);
   if (st != XPR_OK) return st;
-  XPR_HIP(launch_project_bwd(B, S.max_n, grad2d, proj->tiles_touched, G, accumulate ? 1 : 0,
+  XPR_HIP(launch_project_bwd(B, S.max_n, proj->splat, grad2d, proj->tiles_touched, G, accumulate ? 1 : 0,
                              stream));
   return XPR_OK;
 }

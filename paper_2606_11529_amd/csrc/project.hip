@@ -354,6 +354,67 @@ __device__ __forceinline__ void store_param_grads(const GradDev& G, const SceneD
 // C, o, r, g, b). Chain: shader data -> conic -> 2D covariance -> (J W,
 // Sigma) -> (camera-space mean, scales, rotation -> quaternion); mean2D ->
 // camera-space mean -> world mean; colour -> SH coefficients and direction.
+// Writes (or, with accumulate, adds) one Gaussian's mean, scale, quaternion
+// and opacity gradients. The SH gradients were written view by view
+// (sh_out: at least one view wrote them); overwriting zeroes those no view
+// wrote and those above the rendered degree (NB coefficients).
+__device__ __forceinline__ void store_geom_grads(const GradDev& G, const SceneDev& S, int i,
+                                                 const double (&gmu)[3], const double (&gs)[3],
+                                                 const double (&gq)[4], float go, int accumulate,
+                                                 bool sh_out, int NB) {
+  const size_t ld = S.ld;
+  if (accumulate) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      G.means[k * ld + i] += (float)gmu[k];
+      G.scales[k * ld + i] += (float)gs[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) G.quats[k * ld + i] += (float)gq[k];
+    G.opac[i] += go;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      G.means[k * ld + i] = (float)gmu[k];
+      G.scales[k * ld + i] = (float)gs[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) G.quats[k * ld + i] = (float)gq[k];
+    G.opac[i] = go;
+    for (int j = sh_out ? NB : 0; j < S.K; ++j)
+      for (int ch = 0; ch < 3; ++ch) G.sh[(3 * j + ch) * ld + i] = 0.f;
+  }
+}
+
+// The SH part of one view's projection backward: colour = max(0, 0.5 +
+// sum_j sh_j Y_j(dir)) with the channels' gradients gr (zero where the
+// record's colour, max(0, raw), is 0). Writes dL/dsh (stores on the first
+// view unless accumulating, adds after) and returns dL/ddir through wsum;
+// each coefficient is read once.
+template <int DEG>
+__device__ __forceinline__ void sh_backward(const SceneDev& S, const GradDev& G, int i,
+                                            const float (&Y)[16], float gr0, float gr1, float gr2,
+                                            bool add, float (&wsum)[16]) {
+  constexpr int NB = (DEG + 1) * (DEG + 1);
+  const size_t ld = S.ld;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) wsum[j] = 0.f;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    const float gr = ch == 0 ? gr0 : (ch == 1 ? gr1 : gr2);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const size_t o = (size_t)(3 * j + ch) * ld + i;
+      const float v = Y[j] * gr;
+      if (add)
+        G.sh[o] += v;
+      else
+        G.sh[o] = v;
+      wsum[j] += S.sh[o] * gr;
+    }
+  }
+}
+
 template <int DEG>
 __global__ __launch_bounds__(256) void k_project_bwd(Batch B, const float* __restrict__ grad2d,
                                                      const int32_t* __restrict__ tc,
@@ -643,8 +704,10 @@ __global__ __launch_bounds__(256) void k_project_gut(Batch B, float4* __restrict
 //     the seven projected sigma points and so to mu, s and R;
 //   the colour as for 3DGS (clamped channels pass nothing).
 template <int DEG>
-__global__ __launch_bounds__(256) void k_project_bwd_gut(Batch B, const float* __restrict__ grad,
-                                                         const int32_t* __restrict__ tc,
+__global__ __launch_bounds__(256, 2) void k_project_bwd_gut(Batch B,
+                                                            const float* __restrict__ splat,
+                                                            const float* __restrict__ grad,
+                                                            const int32_t* __restrict__ tc,
                                                          GradDev G0, GradDev G1, GradDev G2,
                                                          GradDev G3, GradDev G4, GradDev G5,
                                                          GradDev G6, GradDev G7, int accumulate) {
@@ -653,23 +716,26 @@ __global__ __launch_bounds__(256) void k_project_bwd_gut(Batch B, const float* _
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= S.n) return;
   constexpr int NB = (DEG + 1) * (DEG + 1);
+  const GradDev G = grad_dest(sidx, G0, G1, G2, G3, G4, G5, G6, G7);
+  const size_t ld = S.ld;
   double gmu[3] = {0.0, 0.0, 0.0}, gs[3] = {0.0, 0.0, 0.0}, gq[4] = {0.0, 0.0, 0.0, 0.0};
   double gR[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   float go = 0.f;
-  float gsh[NB][3];
-#pragma unroll
-  for (int j = 0; j < NB; ++j) gsh[j][0] = gsh[j][1] = gsh[j][2] = 0.f;
+  // the SH gradient goes straight to memory, view by view (this thread owns
+  // Gaussian i): the first view stores unless accumulating, later ones add
+  bool sh_out = false;
   // the Gaussian's frame, as the forward forms it
-  const double mu[3] = {S.means[i], S.means[S.ld + i], S.means[2 * S.ld + i]};
-  const double q0 = S.quats[i], q1 = S.quats[S.ld + i], q2 = S.quats[2 * S.ld + i],
-               q3 = S.quats[3 * S.ld + i];
+  const double mu[3] = {S.means[i], S.means[ld + i], S.means[2 * ld + i]};
+  const double q0 = S.quats[i], q1 = S.quats[ld + i], q2 = S.quats[2 * ld + i],
+               q3 = S.quats[3 * ld + i];
   const double qinv = 1.0 / sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
   const double qn[4] = {q0 * qinv, q1 * qinv, q2 * qinv, q3 * qinv};
   const double w = qn[0], x = qn[1], y = qn[2], z = qn[3];
   const double Q[9] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y),
                        2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x),
                        2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)};
-  const double s[3] = {S.scales[i], S.scales[S.ld + i], S.scales[2 * S.ld + i]};
+  const double s[3] = {S.scales[i], S.scales[ld + i], S.scales[2 * ld + i]};
+  const double is[3] = {1.0 / s[0], 1.0 / s[1], 1.0 / s[2]};
   const double opac = S.opac[i];
   const double k3 = 1.7320508075688772;  // sqrt(3)
   const double lp = B.lowpass;
@@ -687,34 +753,22 @@ __global__ __launch_bounds__(256) void k_project_bwd_gut(Batch B, const float* _
     const double cp[3] = {-(R[0] * V.t[0] + R[3] * V.t[1] + R[6] * V.t[2]),
                           -(R[1] * V.t[0] + R[4] * V.t[1] + R[7] * V.t[2]),
                           -(R[2] * V.t[0] + R[5] * V.t[1] + R[8] * V.t[2])};
-    const double d[3] = {cp[0] - mu[0], cp[1] - mu[1], cp[2] - mu[2]};
 
-    // colour = max(0, 0.5 + sum_j sh_j Y_j(dir)), dir = (mu - campos) / |.|
+    // colour = max(0, 0.5 + sum_j sh_j Y_j(dir)), dir = (mu - campos) / |.|;
+    // a channel passes its gradient where the record's colour is positive
+    // (the forward stored max(0, raw): positive exactly when raw is)
     {
+      const double d[3] = {cp[0] - mu[0], cp[1] - mu[1], cp[2] - mu[2]};
       const double dn = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
       const double dir[3] = {-d[0] * dn, -d[1] * dn, -d[2] * dn};
       const float dxf = (float)dir[0], dyf = (float)dir[1], dzf = (float)dir[2];
       float Y[16];
       sh_basis<DEG>(dxf, dyf, dzf, Y);
-      float graw[3];
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) {
-        float acc = 0.5f;
-#pragma unroll
-        for (int j = 0; j < NB; ++j) acc += S.sh[(size_t)(3 * j + ch) * S.ld + i] * Y[j];
-        graw[ch] = acc > 0.f ? g[1 + ch] : 0.f;
-      }
+      const float* col = splat + 24 * (size_t)r + 6;  // (r, g, b) of the 24-float record
       float wsum[16];
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        float acc = 0.f;
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-          gsh[j][ch] += Y[j] * graw[ch];
-          acc += S.sh[(size_t)(3 * j + ch) * S.ld + i] * graw[ch];
-        }
-        wsum[j] = acc;
-      }
+      sh_backward<DEG>(S, G, i, Y, col[0] > 0.f ? g[1] : 0.f, col[1] > 0.f ? g[2] : 0.f,
+                       col[2] > 0.f ? g[3] : 0.f, sh_out || accumulate, wsum);
+      sh_out = true;
       float gdxf, gdyf, gdzf;
       sh_basis_vjp<DEG>(dxf, dyf, dzf, wsum, gdxf, gdyf, gdzf);
       const double gd[3] = {gdxf, gdyf, gdzf};
@@ -729,46 +783,51 @@ __global__ __launch_bounds__(256) void k_project_bwd_gut(Batch B, const float* _
       const double gro = g[4 + a];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const double Mac = Q[3 * c + a] / s[a];
+        const double Mac = Q[3 * c + a] * is[a];
         const double gM = g[7 + 3 * a + c];
         gmu[c] -= Mac * gro;
-        gR[3 * c + a] += gM / s[a];
-        gs[a] -= gM * Mac / s[a];
+        gR[3 * c + a] += gM * is[a];
+        gs[a] -= gM * Mac * is[a];
       }
     }
 
-    // o' = o comp over the seven sigma points
-    double px[7], py[7];
-#pragma unroll
-    for (int p = 0; p < 7; ++p) {
+    // o' = o comp over the seven sigma points. Each pass below recomputes
+    // the points (mu and mu +- sqrt(3) s_j Q e_j) and their normalised camera
+    // coordinates (x / z, y / z) instead of keeping them: four cheap passes
+    // (mean, covariance, the covariance gradient's point sums, the chain
+    // back to mu, s and R) in few registers.
+    auto point = [&](int j, double sg, double& u, double& v, double& iz) {
       double X[3] = {mu[0], mu[1], mu[2]};
-      if (p > 0) {
-        const int j = (p - 1) >> 1;
-        const double sg = ((p - 1) & 1) ? -k3 : k3;
+      if (j >= 0) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) X[c] += sg * s[j] * Q[3 * c + j];
       }
-      const double xc = R[0] * X[0] + R[1] * X[1] + R[2] * X[2] + (double)V.t[0];
-      const double yc = R[3] * X[0] + R[4] * X[1] + R[5] * X[2] + (double)V.t[1];
-      const double zc = R[6] * X[0] + R[7] * X[1] + R[8] * X[2] + (double)V.t[2];
-      px[p] = fx * xc / zc + cx;
-      py[p] = fy * yc / zc + cy;
-    }
-    double mx = 0.0, my = 0.0;
-#pragma unroll
+      iz = 1.0 / (R[6] * X[0] + R[7] * X[1] + R[8] * X[2] + (double)V.t[2]);
+      u = (R[0] * X[0] + R[1] * X[1] + R[2] * X[2] + (double)V.t[0]) * iz;
+      v = (R[3] * X[0] + R[4] * X[1] + R[5] * X[2] + (double)V.t[1]) * iz;
+    };
+    constexpr double k6 = 1.0 / 6.0;
+    double mu_u = 0.0, mu_v = 0.0;
+#pragma unroll 1
     for (int p = 1; p < 7; ++p) {
-      mx += px[p] / 6.0;
-      my += py[p] / 6.0;
+      double u, v, iz;
+      point((p - 1) >> 1, ((p - 1) & 1) ? -k3 : k3, u, v, iz);
+      mu_u += u;
+      mu_v += v;
     }
+    mu_u *= k6;
+    mu_v *= k6;
+    // 2D covariance of the deviations (pixels) from the mean
     double cxx = 0.0, cxy = 0.0, cyy = 0.0;
-#pragma unroll
+#pragma unroll 1
     for (int p = 0; p < 7; ++p) {
-      const double wc = p == 0 ? 2.0 : 1.0 / 6.0;
-      px[p] -= mx;  // deviations from here on
-      py[p] -= my;
-      cxx += wc * px[p] * px[p];
-      cxy += wc * px[p] * py[p];
-      cyy += wc * py[p] * py[p];
+      double u, v, iz;
+      point((p - 1) >> 1, ((p - 1) & 1) ? -k3 : k3, u, v, iz);
+      const double wc = p == 0 ? 2.0 : k6;
+      const double dx = fx * (u - mu_u), dy = fy * (v - mu_v);
+      cxx += wc * dx * dx;
+      cxy += wc * dx * dy;
+      cyy += wc * dy * dy;
     }
     const double det0 = cxx * cyy - cxy * cxy;
     const double det = (cxx + lp) * (cyy + lp) - cxy * cxy;
@@ -780,45 +839,49 @@ __global__ __launch_bounds__(256) void k_project_bwd_gut(Batch B, const float* _
       const double gxx = gdet0 * cyy + gdet * (cyy + lp);
       const double gyy = gdet0 * cxx + gdet * (cxx + lp);
       const double gxy = -2.0 * cxy * (gdet0 + gdet);
-      // dL/d(deviation) per point; the mean's share goes back through the
-      // mean weights (0 for the centre, 1/6 for the others)
+      // dL/d(deviation) of point p is wc (2 dx gxx + dy gxy, 2 dy gyy + dx gxy);
+      // the mean's share goes back through the mean weights (0 for the
+      // centre, 1/6 for the others), so every point needs their sum sD
       double sDx = 0.0, sDy = 0.0;
-#pragma unroll
+#pragma unroll 1
       for (int p = 0; p < 7; ++p) {
-        const double wc = p == 0 ? 2.0 : 1.0 / 6.0;
-        const double gx = wc * (2.0 * px[p] * gxx + py[p] * gxy);
-        const double gy = wc * (2.0 * py[p] * gyy + px[p] * gxy);
-        px[p] = gx;  // dL/d(deviation) from here on
-        py[p] = gy;
-        sDx += gx;
-        sDy += gy;
+        double u, v, iz;
+        point((p - 1) >> 1, ((p - 1) & 1) ? -k3 : k3, u, v, iz);
+        const double wc = p == 0 ? 2.0 : k6;
+        const double dx = fx * (u - mu_u), dy = fy * (v - mu_v);
+        sDx += wc * (2.0 * dx * gxx + dy * gxy);
+        sDy += wc * (2.0 * dy * gyy + dx * gxy);
       }
-#pragma unroll
-      for (int p = 0; p < 7; ++p) {
-        const double wm = p == 0 ? 0.0 : 1.0 / 6.0;
-        const double gPx = px[p] - wm * sDx, gPy = py[p] - wm * sDy;
-        double X[3] = {mu[0], mu[1], mu[2]};
-        int j = 0;
-        double sg = 0.0;
+      sDx *= k6;
+      sDy *= k6;
+      // through px = fx x / z + cx, py = fy y / z + cy to the point, then
+      // to mu (every point) and to s_j, Q e_j (the axis points)
+      auto back = [&](int p, double* gX) {
+        double u, v, iz;
+        point((p - 1) >> 1, ((p - 1) & 1) ? -k3 : k3, u, v, iz);
+        const double wc = p == 0 ? 2.0 : k6;
+        const double dx = fx * (u - mu_u), dy = fy * (v - mu_v);
+        double gPx = wc * (2.0 * dx * gxx + dy * gxy), gPy = wc * (2.0 * dy * gyy + dx * gxy);
         if (p > 0) {
-          j = (p - 1) >> 1;
-          sg = ((p - 1) & 1) ? -k3 : k3;
-#pragma unroll
-          for (int c = 0; c < 3; ++c) X[c] += sg * s[j] * Q[3 * c + j];
+          gPx -= sDx;
+          gPy -= sDy;
         }
-        const double xc = R[0] * X[0] + R[1] * X[1] + R[2] * X[2] + (double)V.t[0];
-        const double yc = R[3] * X[0] + R[4] * X[1] + R[5] * X[2] + (double)V.t[1];
-        const double zc = R[6] * X[0] + R[7] * X[1] + R[8] * X[2] + (double)V.t[2];
-        const double iz = 1.0 / zc;
-        const double gyv[3] = {fx * iz * gPx, fy * iz * gPy,
-                               -(fx * xc * gPx + fy * yc * gPy) * iz * iz};
-        double gX[3];
+        const double g0 = fx * iz * gPx, g1 = fy * iz * gPy,
+                     g2 = -(fx * u * gPx + fy * v * gPy) * iz;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          gX[c] = R[c] * gyv[0] + R[3 + c] * gyv[1] + R[6 + c] * gyv[2];
+          gX[c] = R[c] * g0 + R[3 + c] * g1 + R[6 + c] * g2;
           gmu[c] += gX[c];
         }
-        if (p > 0) {
+      };
+      double gX[3];
+      back(0, gX);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+#pragma unroll 1
+        for (int h = 0; h < 2; ++h) {
+          const double sg = h ? -k3 : k3;
+          back(1 + 2 * j + h, gX);
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             gs[j] += sg * gX[c] * Q[3 * c + j];
@@ -829,8 +892,7 @@ __global__ __launch_bounds__(256) void k_project_bwd_gut(Batch B, const float* _
     }
   }
   quat_vjp(qn, qinv, gR, gq);
-  store_param_grads<NB>(grad_dest(sidx, G0, G1, G2, G3, G4, G5, G6, G7), S, i, gmu, gs, gq, go,
-                        gsh, accumulate);
+  store_geom_grads(G, S, i, gmu, gs, gq, go, accumulate, sh_out, NB);
 }
 
 // LinPrim projection (listing "Implementation of XPR-LinPrim", project),
@@ -939,6 +1001,185 @@ __global__ __launch_bounds__(256) void k_project_lin(Batch B, float4* __restrict
   tc[r] = visible ? area : 0;
 }
 
+// Backward of the LinPrim projection, one thread per scene Gaussian over the
+// views of its scene (blockIdx.y = scene), in FP64 like the forward: from
+// dL/d(u, v, sigma, colour, c0, c1, c2) [record][16] to the gradients of the
+// means, half-extent scales, opacity, raw quaternion and SH coefficients.
+// For a visible record:
+//   mean2D = (fx x / z + cx, fy y / z + cy) of the camera-space centre;
+//   sigma = -log(1 - 0.99 o) / (2 s_min), o the opacity clipped to
+//     [0, 0.999] (no gradient where the clip holds; the s_min term goes to
+//     the first smallest scale);
+//   C = A^-1 with A = J3 R_w2c Rq diag(s): dL/dA = -C^T dL/dC C^T, then
+//     dL/ds_k = sum_r dL/dA_rk (J3 W)_rk, dL/dJ3 and dL/dW from
+//     dL/d(J3 W) = dL/dA diag(s), J3's perspective rows and unit viewing
+//     direction to (x, y, z), dL/dRq = R_w2c^T dL/dW;
+//   the colour as for 3DGS (clamped channels, read from the record, pass
+//     nothing).
+template <int DEG>
+__global__ __launch_bounds__(256) void k_project_bwd_lin(Batch B, const float* __restrict__ splat,
+                                                         const float* __restrict__ grad,
+                                                         const int32_t* __restrict__ tc,
+                                                         GradDev G0, GradDev G1, GradDev G2,
+                                                         GradDev G3, GradDev G4, GradDev G5,
+                                                         GradDev G6, GradDev G7, int accumulate) {
+  const int sidx = blockIdx.y;
+  const SceneDev& S = B.s[sidx];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= S.n) return;
+  constexpr int NB = (DEG + 1) * (DEG + 1);
+  const GradDev G = grad_dest(sidx, G0, G1, G2, G3, G4, G5, G6, G7);
+  const size_t ld = S.ld;
+  double gmu[3] = {0.0, 0.0, 0.0}, gs[3] = {0.0, 0.0, 0.0}, gq[4] = {0.0, 0.0, 0.0, 0.0};
+  double gR[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  float go = 0.f;
+  bool sh_out = false;
+  const double mu[3] = {S.means[i], S.means[ld + i], S.means[2 * ld + i]};
+  const double q0 = S.quats[i], q1 = S.quats[ld + i], q2 = S.quats[2 * ld + i],
+               q3 = S.quats[3 * ld + i];
+  const double qinv = 1.0 / sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+  const double qn[4] = {q0 * qinv, q1 * qinv, q2 * qinv, q3 * qinv};
+  const double w = qn[0], a = qn[1], b = qn[2], c = qn[3];
+  const double Q[9] = {1.0 - 2.0 * (b * b + c * c), 2.0 * (a * b - w * c), 2.0 * (a * c + w * b),
+                       2.0 * (a * b + w * c), 1.0 - 2.0 * (a * a + c * c), 2.0 * (b * c - w * a),
+                       2.0 * (a * c - w * b), 2.0 * (b * c + w * a), 1.0 - 2.0 * (a * a + b * b)};
+  const double s[3] = {S.scales[i], S.scales[ld + i], S.scales[2 * ld + i]};
+  int jmin = 0;
+  if (s[1] < s[jmin]) jmin = 1;
+  if (s[2] < s[jmin]) jmin = 2;
+  const double smin = s[jmin];
+  const double op = S.opac[i];
+  const double o = fmin(0.999, fmax(0.0, op));
+  const double sigma = -log1p(-0.99 * o) / (2.0 * smin);
+  const double dsig_do = (op > 0.0 && op < 0.999) ? 0.99 / ((1.0 - 0.99 * o) * 2.0 * smin) : 0.0;
+
+  for (int vi = 0; vi < B.n_views; ++vi) {
+    const ViewDev& V = B.v[vi];
+    if (V.scene != sidx) continue;
+    const int r = V.rec_off + i;
+    if (tc[r] == 0) continue;
+    const float* g = grad + 16 * (size_t)r;
+    double R[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) R[k] = V.R[k];
+    const double fx = V.fx, fy = V.fy;
+    const double x = R[0] * mu[0] + R[1] * mu[1] + R[2] * mu[2] + (double)V.t[0];
+    const double y = R[3] * mu[0] + R[4] * mu[1] + R[5] * mu[2] + (double)V.t[1];
+    const double z = R[6] * mu[0] + R[7] * mu[1] + R[8] * mu[2] + (double)V.t[2];
+    const double d = sqrt(x * x + y * y + z * z);
+    const double iz = 1.0 / z, iz2 = iz * iz;
+    double gx = 0.0, gy = 0.0, gz = 0.0;  // dL/d(x, y, z)
+
+    // mean2D
+    const double gu = g[0], gv = g[1];
+    gx += gu * fx * iz;
+    gy += gv * fy * iz;
+    gz -= (gu * fx * x + gv * fy * y) * iz2;
+
+    // sigma
+    go += (float)(g[2] * dsig_do);
+    gs[jmin] -= g[2] * sigma / smin;
+
+    // colour = max(0, 0.5 + sum_j sh_j Y_j(dir)), dir = (mu - campos) / |.|
+    {
+      const double cp[3] = {-(R[0] * V.t[0] + R[3] * V.t[1] + R[6] * V.t[2]),
+                            -(R[1] * V.t[0] + R[4] * V.t[1] + R[7] * V.t[2]),
+                            -(R[2] * V.t[0] + R[5] * V.t[1] + R[8] * V.t[2])};
+      const double dv[3] = {mu[0] - cp[0], mu[1] - cp[1], mu[2] - cp[2]};
+      const double dn = 1.0 / sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+      const double dir[3] = {dv[0] * dn, dv[1] * dn, dv[2] * dn};
+      const float dxf = (float)dir[0], dyf = (float)dir[1], dzf = (float)dir[2];
+      float Y[16];
+      sh_basis<DEG>(dxf, dyf, dzf, Y);
+      const float* col = splat + 20 * (size_t)r + 3;  // (r, g, b) of the 20-float record
+      float wsum[16];
+      sh_backward<DEG>(S, G, i, Y, col[0] > 0.f ? g[3] : 0.f, col[1] > 0.f ? g[4] : 0.f,
+                       col[2] > 0.f ? g[5] : 0.f, sh_out || accumulate, wsum);
+      sh_out = true;
+      float gdxf, gdyf, gdzf;
+      sh_basis_vjp<DEG>(dxf, dyf, dzf, wsum, gdxf, gdyf, gdzf);
+      const double gd[3] = {gdxf, gdyf, gdzf};
+      const double dd = dir[0] * gd[0] + dir[1] * gd[1] + dir[2] * gd[2];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) gmu[k] += (gd[k] - dir[k] * dd) * dn;
+    }
+
+    // A = J3 Wm diag(s), Wm = R_w2c Rq, C = A^-1 (as the forward forms them)
+    const double J[9] = {fx * iz, 0.0, -fx * x * iz2, 0.0, fy * iz, -fy * y * iz2,
+                         x / d, y / d, z / d};
+    double Wm[9], JW[9], A[9];
+#pragma unroll
+    for (int rr = 0; rr < 3; ++rr)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        Wm[3 * rr + k] = R[3 * rr] * Q[k] + R[3 * rr + 1] * Q[3 + k] + R[3 * rr + 2] * Q[6 + k];
+#pragma unroll
+    for (int rr = 0; rr < 3; ++rr)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        JW[3 * rr + k] = J[3 * rr] * Wm[k] + J[3 * rr + 1] * Wm[3 + k] + J[3 * rr + 2] * Wm[6 + k];
+        A[3 * rr + k] = JW[3 * rr + k] * s[k];
+      }
+    const double c00 = A[4] * A[8] - A[5] * A[7], c01 = A[5] * A[6] - A[3] * A[8],
+                 c02 = A[3] * A[7] - A[4] * A[6];
+    const double id = 1.0 / (A[0] * c00 + A[1] * c01 + A[2] * c02);
+    const double C[9] = {c00 * id, (A[2] * A[7] - A[1] * A[8]) * id,
+                         (A[1] * A[5] - A[2] * A[4]) * id, c01 * id,
+                         (A[0] * A[8] - A[2] * A[6]) * id, (A[2] * A[3] - A[0] * A[5]) * id,
+                         c02 * id, (A[1] * A[6] - A[0] * A[7]) * id,
+                         (A[0] * A[4] - A[1] * A[3]) * id};
+    // dL/dA = -C^T dL/dC C^T
+    double T1[9];
+#pragma unroll
+    for (int rr = 0; rr < 3; ++rr)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        T1[3 * rr + k] = (double)g[6 + 3 * rr] * C[3 * k] + (double)g[7 + 3 * rr] * C[3 * k + 1] +
+                         (double)g[8 + 3 * rr] * C[3 * k + 2];
+    double GJW[9];
+#pragma unroll
+    for (int rr = 0; rr < 3; ++rr)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double ga = -(C[rr] * T1[k] + C[3 + rr] * T1[3 + k] + C[6 + rr] * T1[6 + k]);
+        gs[k] += ga * JW[3 * rr + k];
+        GJW[3 * rr + k] = ga * s[k];
+      }
+    // dL/dJ = GJW Wm^T, dL/dWm = J^T GJW, dL/dRq = R_w2c^T dL/dWm
+    double GJ[9], GW[9];
+#pragma unroll
+    for (int rr = 0; rr < 3; ++rr)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        GJ[3 * rr + k] = GJW[3 * rr] * Wm[3 * k] + GJW[3 * rr + 1] * Wm[3 * k + 1] +
+                         GJW[3 * rr + 2] * Wm[3 * k + 2];
+        GW[3 * rr + k] = J[rr] * GJW[k] + J[3 + rr] * GJW[3 + k] + J[6 + rr] * GJW[6 + k];
+      }
+#pragma unroll
+    for (int rr = 0; rr < 3; ++rr)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        gR[3 * rr + k] += R[rr] * GW[k] + R[3 + rr] * GW[3 + k] + R[6 + rr] * GW[6 + k];
+    // J3 with respect to (x, y, z)
+    const double iz3 = iz2 * iz;
+    gz += -GJ[0] * fx * iz2 + GJ[2] * 2.0 * fx * x * iz3 - GJ[4] * fy * iz2 +
+          GJ[5] * 2.0 * fy * y * iz3;
+    gx -= GJ[2] * fx * iz2;
+    gy -= GJ[5] * fy * iz2;
+    const double id_ = 1.0 / d;
+    const double e[3] = {x * id_, y * id_, z * id_};
+    const double ge = GJ[6] * e[0] + GJ[7] * e[1] + GJ[8] * e[2];
+    gx += (GJ[6] - e[0] * ge) * id_;
+    gy += (GJ[7] - e[1] * ge) * id_;
+    gz += (GJ[8] - e[2] * ge) * id_;
+    // (x, y, z) = R_w2c mu + t
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gmu[k] += R[k] * gx + R[3 + k] * gy + R[6 + k] * gz;
+  }
+  quat_vjp(qn, qinv, gR, gq);
+  store_geom_grads(G, S, i, gmu, gs, gq, go, accumulate, sh_out, NB);
+}
+
 // Launchers ------------------------------------------------------------------
 
 hipError_t launch_project(const Batch& B, int max_n, float* splat, float* depth, int16_t* rect,
@@ -974,14 +1215,27 @@ hipError_t launch_project(const Batch& B, int max_n, float* splat, float* depth,
   return hipGetLastError();
 }
 
-hipError_t launch_project_bwd(const Batch& B, int max_n, const float* grad2d, const int32_t* tc,
-                              const GradDev* G, int accumulate, hipStream_t st) {
+hipError_t launch_project_bwd(const Batch& B, int max_n, const float* splat, const float* grad2d,
+                              const int32_t* tc, const GradDev* G, int accumulate, hipStream_t st) {
   if (max_n <= 0) return hipSuccess;
   dim3 grid((max_n + 255) / 256, B.n_scenes);
+  if (B.method == XPR_METHOD_LINPRIM) {
+#define XPR_PBL(D)                                                                         \
+  hipLaunchKernelGGL(k_project_bwd_lin<D>, grid, dim3(256), 0, st, B, splat, grad2d, tc, G[0], \
+                     G[1], G[2], G[3], G[4], G[5], G[6], G[7], accumulate)
+    switch (B.sh_degree) {
+      case 0: XPR_PBL(0); break;
+      case 1: XPR_PBL(1); break;
+      case 2: XPR_PBL(2); break;
+      default: XPR_PBL(3); break;
+    }
+#undef XPR_PBL
+    return hipGetLastError();
+  }
   if (B.method == XPR_METHOD_3DGUT) {
-#define XPR_PBG(D)                                                                             \
-  hipLaunchKernelGGL(k_project_bwd_gut<D>, grid, dim3(256), 0, st, B, grad2d, tc, G[0], G[1], \
-                     G[2], G[3], G[4], G[5], G[6], G[7], accumulate)
+#define XPR_PBG(D)                                                                         \
+  hipLaunchKernelGGL(k_project_bwd_gut<D>, grid, dim3(256), 0, st, B, splat, grad2d, tc, G[0], \
+                     G[1], G[2], G[3], G[4], G[5], G[6], G[7], accumulate)
     switch (B.sh_degree) {
       case 0: XPR_PBG(0); break;
       case 1: XPR_PBG(1); break;
@@ -991,8 +1245,8 @@ hipError_t launch_project_bwd(const Batch& B, int max_n, const float* grad2d, co
 #undef XPR_PBG
     return hipGetLastError();
   }
-#define XPR_PB(D)                                                                          \
-  hipLaunchKernelGGL(k_project_bwd<D>, grid, dim3(256), 0, st, B, grad2d, tc, G[0], G[1], \
+#define XPR_PB(D)                                                                             \
+  hipLaunchKernelGGL(k_project_bwd<D>, grid, dim3(256), 0, st, B, grad2d, tc, G[0], G[1],        \
                      G[2], G[3], G[4], G[5], G[6], G[7], accumulate)
   switch (B.sh_degree) {
     case 0: XPR_PB(0); break;

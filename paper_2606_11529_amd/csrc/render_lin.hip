@@ -231,4 +231,257 @@ hipError_t launch_render_fwd_lin(const Batch& B, const float* splat, const int32
   return hipGetLastError();
 }
 
+
+// Backward of the LinPrim compositing. The gradient of each record is taken
+// with respect to the 15 values evaluate reads -- u, v (mu_2D - 1/2),
+// sigma, the colour (3) and the rows c0, c1, c2 of A^-1 (9) -- as grad
+// [record][16] with the 16th left zero.
+//
+// Per pixel the blended entries are those at list positions <= n_contrib
+// whose chord is positive and alpha >= alpha_min (the forward's exact
+// arithmetic decides); they are walked last first with T recovered as
+// T / (1 - alpha) and the colour behind accumulated, as for 3DGS. With
+// e = exp(-sigma chord) (alpha = 1 - e when not clamped):
+//   dL/dsigma = e chord dL/dalpha,   dL/dchord = e sigma dL/dalpha.
+// The chord is (m_b + h_b) - (m_a - h_a) for the exit slab b (the first
+// reaching the minimum of m_i + h_i) and the entry slab a (the first
+// reaching the maximum of m_i - h_i), m_i = -(n_ix dx + n_iy dy) / n_iz,
+// h_i = 1 / |n_iz|. With s_i = 1 / n_iz and kappa = +1 (exit), -1 (entry):
+//   dchord/dn_i = (-kappa dx s_i, -kappa dy s_i, -s_i (kappa m_i + h_i)),
+//   dchord/du = -kappa (-n_ix s_i), likewise v,
+// and n_i = c0 + e1 c1 + e2 c2 spreads dL/dn_i to the rows. These terms are
+// formed in float64 (with dx, dy, m as the forward forms them), the rest
+// in float32; each wave sums its lanes' 16 terms with lane swaps
+// (reduce16) and four lanes add them to grad with float atomics.
+struct LinBwdRec {
+  double s[4];  // 1 / n_iz (0 for a slab with n_z ~ 0)
+  int32_t id;
+};
+
+template <int NW>
+struct LinBwdStage {
+  LinStage<NW> f;  // the forward's staged data, masks and wave lists
+  LinBwdRec b[kLinBatch];
+};
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW* TH) void k_render_bwd_lin(
+    Batch B, const float4* __restrict__ splat, const int32_t* __restrict__ vals,
+    const int2* __restrict__ ranges, const float* __restrict__ dimg,
+    const float* __restrict__ Tfin, const int32_t* __restrict__ ncon, float* __restrict__ grad,
+    const int32_t* order) {
+  constexpr int NT = TW * TH;
+  constexpr int NW = (NT + 63) / 64;
+  constexpr int RPW = 64 / TW;
+  __shared__ LinBwdStage<NW> S;
+  __shared__ int32_t s_maxlast;
+  const int g = order ? order[blockIdx.x] : (int)blockIdx.x;
+  const ViewDev& V = B.v[view_of_tile(B, g)];
+  const int lt = g - V.tile_off;
+  const int ty = lt / V.tiles_x, tx = lt - ty * V.tiles_x;
+  const int px = tx * TW + (int)(threadIdx.x % TW);
+  const int py = ty * TH + (int)(threadIdx.x / TW);
+  const bool inside = px < V.W && py < V.H;
+  const int2 rg = ranges[g];
+  const float amax = B.alpha_max, amin = B.alpha_min;
+  const int wv = threadIdx.x >> 6;
+  const double fpx = (double)px, fpy = (double)py;
+  float T = 1.f, G0 = 0.f, G1 = 0.f, G2 = 0.f;
+  int mylast = 0;
+  if (inside) {
+    const size_t WH = (size_t)V.W * V.H;
+    const size_t p = (size_t)py * V.W + px;
+    const float* gi = dimg + 3 * (size_t)V.pix_off;
+    T = Tfin[(size_t)V.pix_off + p];
+    mylast = ncon[(size_t)V.pix_off + p];
+    G0 = gi[p];
+    G1 = gi[WH + p];
+    G2 = gi[2 * WH + p];
+  }
+  const float TfbG = T * (B.bg[0] * G0 + B.bg[1] * G1 + B.bg[2] * G2);
+  float S0 = 0.f, S1 = 0.f, S2 = 0.f;
+  if (threadIdx.x == 0) s_maxlast = 0;
+  __syncthreads();
+  if (mylast > 0) atomicMax(&s_maxlast, mylast);
+  __syncthreads();
+  const int end = rg.x + min(s_maxlast, rg.y - rg.x);
+  int wlast = mylast;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) wlast = max(wlast, __shfl_xor(wlast, o, 64));
+  const int stride = splat_stride4(B);
+  const int x0 = tx * TW, x1 = tx * TW + TW - 1, y0 = ty * TH;
+  for (int hi = end; hi > rg.x; hi -= kLinBatch) {
+    const int lo = max(rg.x, hi - kLinBatch);
+    const int nb = hi - lo;
+    __syncthreads();
+    for (int k = threadIdx.x; k < nb; k += NT) {
+      const int id = vals[lo + k];
+      const float4* q = splat + (size_t)stride * (size_t)id;
+      const float4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3], q4 = q[4];
+      const double c[9] = {q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w, q4.x};
+      LinRec& L = S.f.rec[k];
+      LinBwdRec& Lb = S.b[k];
+      int flat_any = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double e1 = (i & 2) ? -1.0 : 1.0, e2 = (i & 1) ? -1.0 : 1.0;
+        const double nx = c[0] + e1 * c[3] + e2 * c[6];
+        const double ny = c[1] + e1 * c[4] + e2 * c[7];
+        const double nz = c[2] + e1 * c[5] + e2 * c[8];
+        const bool flat = !(fabs(nz) >= 1e-10);
+        L.a[i] = flat ? nx : -nx / nz;
+        L.b[i] = flat ? ny : -ny / nz;
+        L.h[i] = flat ? -1.0 : 1.0 / fabs(nz);
+        Lb.s[i] = flat ? 0.0 : 1.0 / nz;
+        flat_any |= flat ? 1 : 0;
+      }
+      L.flat = flat_any;
+      L.u = q0.x;
+      L.v = q0.y;
+      L.sigma = q0.z;
+      L.r = q0.w;
+      L.g = q1.x;
+      L.bl = q1.y;
+      Lb.id = id;
+      const double ex = (double)q1.z + 0.05, ey = (double)q1.w + 0.05;
+      uint32_t msk = 0u;
+      if (L.u + ex >= (double)x0 && L.u - ex <= (double)x1) {
+        for (int w = 0; w < NW; ++w) {
+          const double r0 = (double)(y0 + w * RPW), r1 = r0 + (double)(RPW - 1);
+          if (L.v + ey >= r0 && L.v - ey <= r1) msk |= 1u << w;
+        }
+      }
+      S.f.mask[k] = (typename LinStage<NW>::mask_t)msk;
+    }
+    __syncthreads();
+    // this wave's records of the batch within its walk, in list order
+    int cnt = 0;
+    {
+      const int lane = threadIdx.x & 63;
+      const uint64_t lt_mask = lanemask_lt();
+      const int kmax = wlast + rg.x - lo - 1;
+      for (int i0 = 0; i0 < nb; i0 += 64) {
+        const int k = i0 + lane;
+        const bool hit = k < nb && k <= kmax && ((S.f.mask[k] >> wv) & 1u);
+        const uint64_t msk = __ballot(hit);
+        if (hit) S.f.list[wv][cnt + __popcll(msk & lt_mask)] = (uint16_t)k;
+        cnt += __popcll(msk);
+      }
+    }
+    __syncthreads();
+    for (int i = cnt - 1; i >= 0; --i) {
+      const int k = S.f.list[wv][i];
+      const int pos = lo + k - rg.x + 1;
+      if (__ballot(pos <= mylast) == 0) continue;
+      const LinRec& L = S.f.rec[k];
+      // the forward's chord, operation for operation, with the bounding slabs
+      const double dx = fpx - L.u, dy = fpy - L.v;
+      double chord;
+      int ia = 0, ib = 0;
+      if (!L.flat) {
+        double m = L.a[0] * dx + L.b[0] * dy;
+        double enter = m - L.h[0], exit_ = m + L.h[0];
+#pragma unroll
+        for (int j = 1; j < 4; ++j) {
+          m = L.a[j] * dx + L.b[j] * dy;
+          const double en = m - L.h[j], xn = m + L.h[j];
+          ia = en > enter ? j : ia;
+          ib = xn < exit_ ? j : ib;
+          enter = fmax(enter, en);
+          exit_ = fmin(exit_, xn);
+        }
+        chord = exit_ - enter;
+      } else {
+        double enter = -INFINITY, exit_ = INFINITY;
+        bool miss = false;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const double m = L.a[j] * dx + L.b[j] * dy, h = L.h[j];
+          const bool fl = h < 0.0;
+          ia = (!fl && m - h > enter) ? j : ia;
+          ib = (!fl && m + h < exit_) ? j : ib;
+          enter = fl ? enter : fmax(enter, m - h);
+          exit_ = fl ? exit_ : fmin(exit_, m + h);
+          miss = miss || (fl && fabs(m) > 1.0);
+        }
+        chord = miss ? -1.0 : exit_ - enter;
+      }
+      const bool hitp = pos <= mylast && chord > 0.0;
+      if (__ballot(hitp) == 0) continue;
+      const float ef = __builtin_amdgcn_exp2f(-L.sigma * kLog2eLin * (float)chord);
+      const float raw = 1.f - ef;
+      float alpha = fminf(amax, raw);
+      alpha = (hitp && alpha >= amin) ? alpha : 0.f;
+      if (__ballot(alpha > 0.f) == 0) continue;
+      const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
+      T = T * inv;
+      const float w = alpha * T;
+      float X[16];
+      X[3] = w * G0;
+      X[4] = w * G1;
+      X[5] = w * G2;
+      X[15] = 0.f;
+      const float d0 = L.r - S0, d1 = L.g - S1, dc2 = L.bl - S2;
+      const float da = T * (d0 * G0 + d1 * G1 + dc2 * G2) - TfbG * inv;
+      S0 += alpha * d0;
+      S1 += alpha * d1;
+      S2 += alpha * dc2;
+      const bool unclamped = raw <= amax && alpha > 0.f;
+      const float ed = unclamped ? ef * da : 0.f;
+      X[2] = unclamped ? ed * (float)chord : 0.f;
+      // dL/dchord, then through the exit (kappa = +1) and entry (-1) slabs
+      const double dch = (double)(ed * L.sigma);
+      const LinBwdRec& Lb = S.b[k];
+      double gn[3] = {0.0, 0.0, 0.0}, gc1[3] = {0.0, 0.0, 0.0}, gc2[3] = {0.0, 0.0, 0.0};
+      double gu = 0.0, gv = 0.0;
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        const int j = side == 0 ? ib : ia;
+        const double kap = side == 0 ? 1.0 : -1.0;
+        const double sj = Lb.s[j];
+        const double mj = L.a[j] * dx + L.b[j] * dy;
+        const double t0 = -kap * dx * sj * dch, t1 = -kap * dy * sj * dch,
+                     t2 = -sj * (kap * mj + L.h[j]) * dch;
+        const double e1 = (j & 2) ? -1.0 : 1.0, e2 = (j & 1) ? -1.0 : 1.0;
+        gn[0] += t0; gn[1] += t1; gn[2] += t2;
+        gc1[0] += e1 * t0; gc1[1] += e1 * t1; gc1[2] += e1 * t2;
+        gc2[0] += e2 * t0; gc2[1] += e2 * t1; gc2[2] += e2 * t2;
+        // m_j = a_j dx + b_j dy with dx = x - u
+        gu -= kap * L.a[j] * dch;
+        gv -= kap * L.b[j] * dch;
+      }
+      // lanes not using the entry select zeros (their chord may be -1)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        X[6 + c] = unclamped ? (float)gn[c] : 0.f;
+        X[9 + c] = unclamped ? (float)gc1[c] : 0.f;
+        X[12 + c] = unclamped ? (float)gc2[c] : 0.f;
+      }
+      X[0] = unclamped ? (float)gu : 0.f;
+      X[1] = unclamped ? (float)gv : 0.f;
+      reduce16(X, grad + 16 * (size_t)Lb.id);
+    }
+  }
+}
+
+hipError_t launch_render_bwd_lin(const Batch& B, const float* splat, const int32_t* vals,
+                                 const int32_t* ranges, const int32_t* order, const float* dimg,
+                                 const float* Tfin, const int32_t* ncon, float* grad,
+                                 hipStream_t st) {
+  if (B.total_tiles <= 0) return hipSuccess;
+  const float4* sp = reinterpret_cast<const float4*>(splat);
+  const int2* rg = reinterpret_cast<const int2*>(ranges);
+  const dim3 grid(B.total_tiles);
+  if (B.tile_w == 8)
+    hipLaunchKernelGGL((k_render_bwd_lin<8, 8>), grid, dim3(64), 0, st, B, sp, vals, rg, dimg,
+                       Tfin, ncon, grad, order);
+  else if (B.tile_w == 32)
+    hipLaunchKernelGGL((k_render_bwd_lin<32, 32>), grid, dim3(1024), 0, st, B, sp, vals, rg,
+                       dimg, Tfin, ncon, grad, order);
+  else
+    hipLaunchKernelGGL((k_render_bwd_lin<16, 16>), grid, dim3(256), 0, st, B, sp, vals, rg, dimg,
+                       Tfin, ncon, grad, order);
+  return hipGetLastError();
+}
+
 }  // namespace xpr

@@ -130,6 +130,26 @@ __device__ __forceinline__ float row_sum16(float x) {
   return x;
 }
 
+// Sum over the 64 lanes of X[0..15], added to dst[0..15] with float
+// atomics: fold32 leaves X_i in rows 0-1 and X_{i+8} in rows 2-3, fold16 of
+// (Z_2m, Z_2m+1) then gives row 0 X_2m, row 1 X_2m+1, row 2 X_2m+8 and row 3
+// X_2m+9; lane 15 of each row issues its four atomics.
+__device__ __forceinline__ void reduce16(const float (&X)[16], float* dst) {
+  float Z[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) Z[i] = fold32(X[i], X[i + 8]);
+  float W[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) W[m] = row_sum16(fold16(Z[2 * m], Z[2 * m + 1]));
+  const int lane = threadIdx.x & 63;
+  if ((lane & 15) == 15) {
+    const int row = lane >> 4;
+    float* d = dst + (row & 1) + 8 * (row >> 1);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) atomicAdd(d + 2 * m, W[m]);
+  }
+}
+
 __device__ __forceinline__ float lane63(float x) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }

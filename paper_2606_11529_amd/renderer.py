@@ -39,7 +39,7 @@ class Config:
     tile_order: bool = False    # launch tiles longest list first (implied by persistent)
     tile_cull: bool = False     # per-(Gaussian, tile) cull of XPR-3DGS in the binning
     opacity_extents: bool = False  # rect from the alpha >= alpha_min ellipse, not 3 sigma
-    method: str = "3dgs"        # "3dgs", "3dgut" or "linprim" (the last forward only)
+    method: str = "3dgs"        # "3dgs", "3dgut" or "linprim"
     bwd_split_walk: int = 2048  # backward: tiles whose walk reaches this go as four bands
 
     def to_c(self) -> L.XprConfig:
@@ -236,10 +236,9 @@ def splat_floats(cfg: "Config") -> int:
 
 def grad2d_floats(cfg: "Config") -> int:
     """Floats per record of the backward's shader-data gradient: 9 for 3DGS
-    (mean2D, conic, opacity, colour), 16 for 3DGUT (o', colour, ro, M)."""
-    if cfg.method == "linprim":
-        raise NotImplementedError("the backward covers 3dgs and 3dgut")
-    return 16 if cfg.method == "3dgut" else 9
+    (mean2D, conic, opacity, colour), 16 for 3DGUT (o', colour, ro, M) and
+    LinPrim (mean2D, sigma, colour, the rows of A^-1, one zero)."""
+    return 9 if cfg.method == "3dgs" else 16
 
 
 def empty_projected(n: int, device, floats: int = 12) -> Projected:

@@ -147,8 +147,10 @@ def test_workspace_queries_host_only():
     # units), then 36 bytes per record
     meta = -(-(128 + 12) * 4 // 256) * 256
     assert L.xpr_render_bwd_workspace(v, c) == meta + 9 * 4 * 1000
-    # 3DGUT: 16 floats per record (o', colour, ro, M)
+    # 3DGUT and LinPrim: 16 floats per record
     c.method = L.XPR_METHOD_3DGUT
+    assert L.xpr_render_bwd_workspace(v, c) == meta + 16 * 4 * 1000
+    c.method = L.XPR_METHOD_LINPRIM
     assert L.xpr_render_bwd_workspace(v, c) == meta + 16 * 4 * 1000
     c.method = L.XPR_METHOD_3DGS
     with pytest.raises(L.XprError):

@@ -17,7 +17,6 @@ import pytest
 import oracle
 from gpu_util import (cam32, check_binning, check_binning_cull, guard_records, log, ocfg_of,
                       rel_check, run_gpu, TOL_PIXEL)
-from paper_2606_11529_amd import _lib as L
 from paper_2606_11529_amd import renderer as R
 from synth import camera_front, camera_look_at, random_cameras, scene_clusters, scene_uniform_cube
 

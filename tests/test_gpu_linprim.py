@@ -5,7 +5,11 @@ outside the guard band), binning bit-exact on the Euclidean depth,
 compositing within 1e-5 max-abs with n_contrib exact; with tile_cull the
 lists equal the oracle's kept pairs (its per-tile chord bound) bit-exactly
 outside the guard band and the images stay within the tolerance of the uncut
-ones; the backward entry points refuse LinPrim (not built)."""
+ones. The backward: the 16 per-record values (u, v, sigma, colour, the rows
+of A^-1, a zero) and the parameter gradients within 1e-3 relative of the
+oracle's, each stage fed the GPU's previous stage, records a guard-band
+decision can reach excluded; the same with tile_cull; accumulate and a
+two-scene batch against per-view sums."""
 import functools
 
 import numpy as np
@@ -13,9 +17,8 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import (cam32, check_binning, check_binning_cull, log, ocfg_of, run_gpu,
-                      TOL_PIXEL)
-from paper_2606_11529_amd import _lib as L
+from gpu_util import (cam32, check_binning, check_binning_cull, guard_records, log, ocfg_of,
+                      rel_check, run_gpu, TOL_PIXEL)
 from paper_2606_11529_amd import renderer as R
 from helpers import axis_camera, hand_scene
 from synth import camera_front, camera_look_at, random_cameras, scene_clusters, scene_uniform_cube
@@ -51,6 +54,12 @@ def _case(name):
 CASES = ["cube_10k_256", "ragged_t8", "ragged_t16", "axis_grid_t8", "clusters_1M_1297x840"]
 
 
+def _dimg(cam, seed=1):
+    rng = np.random.default_rng(seed)
+    return rng.normal(size=(3, cam.height, cam.width)).astype(np.float32) / (
+        3 * cam.width * cam.height)
+
+
 @functools.lru_cache(maxsize=1)
 def _run(name, cull=False):
     sc, cam, cfg = _case(name)
@@ -58,7 +67,7 @@ def _run(name, cull=False):
     cfg.tile_cull = cull
     log(f"[gpu linprim] case={name} n={sc.n} {cam.width}x{cam.height} tile={cfg.tile} "
         f"cull={cull}")
-    return sc, cam, cfg, run_gpu(sc, cam, cfg)
+    return sc, cam, cfg, run_gpu(sc, cam, cfg, dimgs=[_dimg(cam)])
 
 
 def _check_projection(sc, cam, cfg, g, idx):
@@ -131,20 +140,129 @@ def test_linprim_cull(name):
         f"{ref['n_guard']}, max-abs {emax:.2e}, vs uncut {dmax:.1e}")
 
 
-def test_linprim_refuses_backward():
-    sc = scene_clusters(500, seed=4, n_clusters=2, box=1.0, lo=0.01, hi=0.2)
-    cam = camera_look_at((0.1, 0.2, -4.0), 48, 32)
-    cfg = R.Config(method="linprim")
-    scene = R.Scene.from_host(sc)
-    views = R.Views([scene], [cam], [0], cfg)
+def _backward_check(sc, cam, cfg, g, dimg):
+    """The record gradient against orc_render_bwd_lin on the GPU's records
+    and lists, then the parameter gradients against orc_project_bwd_lin fed
+    the GPU's record gradient."""
+    oc = ocfg_of(cfg)
+    rec = g["splat"][:, :17].astype(np.float64)
+    ref_f = oracle.render_fwd_lin(rec, g["vals"], g["ranges"], cam.width, cam.height, oc)
+    g16 = oracle.render_bwd_lin(rec, g["vals"], g["ranges"], cam.width, cam.height, oc,
+                                dimg.astype(np.float64))
+    tx, _ = oracle.tiles(cam, oc)
+    excl = guard_records(ref_f, g["ncontrib"][0], g["ranges"], g["vals"], cfg.tile, tx)
+    mask = np.ones(sc.n, bool)
+    mask[excl] = False
+    assert g["grad2d"].shape == (sc.n, 16)
+    w16 = rel_check(g["grad2d"][:, :15], g16[:, :15], "grad16", mask)
+    assert np.all(g["grad2d"][:, 15] == 0)
+    listed = np.zeros(sc.n, bool)
+    listed[g["vals"]] = True
+    assert np.all(g["grad2d"][~listed] == 0), "a record in no list received a gradient"
+    ref = oracle.project_bwd_lin(sc, cam32(cam), oc, g["grad2d"].astype(np.float64))
+    worst = {}
+    m = mask & (g["tc"] > 0)
+    for k in ("means", "scales", "quats", "opacities", "sh"):
+        gk, rk = g["grads"][k], ref[k]
+        gk = gk.reshape(-1, sc.n).T if gk.ndim > 1 else gk
+        rk = rk.reshape(-1, sc.n).T if rk.ndim > 1 else rk
+        worst[k] = rel_check(gk, rk, k, m)
+    return w16, worst, excl.size
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_linprim_backward(name):
+    sc, cam, cfg, g = _run(name)
+    w16, worst, nex = _backward_check(sc, cam, cfg, g, _dimg(cam))
+    lit = (np.abs(g["grad2d"]).sum(axis=1) > 0).sum()
+    log(f"[L4] {name}: grad16 {w16:.2e} x bound over {lit} records with a gradient, "
+        f"params {worst}, excluded {nex}")
+
+
+@pytest.mark.parametrize("name", ["ragged_t8", "ragged_t16"])
+def test_linprim_backward_with_cull(name):
+    """The culled lists give the oracle's gradient on those lists, and (the
+    culled pairs blend nowhere) the uncut run's gradient."""
+    _, _, _, g0 = _run(name)
+    grads0 = {k: v.copy() for k, v in g0["grads"].items()}
+    sc, cam, cfg, g = _run(name, cull=True)
+    w16, worst, nex = _backward_check(sc, cam, cfg, g, _dimg(cam))
+    for k in grads0:
+        a, b = g["grads"][k], grads0[k]
+        a = a.reshape(-1, sc.n).T if a.ndim > 1 else a
+        b = b.reshape(-1, sc.n).T if b.ndim > 1 else b
+        rel_check(a, b, f"cut vs uncut {k}")
+    log(f"[L5] {name} cull: grad16 {w16:.2e}, params {worst}, excluded {nex}")
+
+
+def test_linprim_backward_clamped_opacity():
+    """An octahedron whose alpha passes alpha_max through its centre (no
+    gradient to its sigma or slabs there) and a colour channel clamped to 0
+    (none to its SH coefficients), beside ordinary octahedra."""
+    sh = np.zeros((4, 16, 3))
+    sh[:, 0, :] = [[1.2, 0.3, 0.6], [0.4, -2.5, 0.8], [0.9, 0.9, 0.1], [0.2, 0.5, 1.1]]
+    rng = np.random.default_rng(11)
+    sh[:, 1:, :] = rng.normal(0, 0.05, size=(4, 15, 3))
+    means = [[0.05, -0.03, 3.0], [0.15, 0.1, 3.5], [-0.3, 0.2, 4.0], [0.02, 0.03, 2.5]]
+    scales = [[0.15, 0.1, 0.12], [0.2, 0.15, 0.18], [0.3, 0.2, 0.25], [0.25, 0.3, 0.8]]
+    quats = rng.normal(size=(4, 4)) * [1, 0.2, 0.2, 0.2]
+    quats[3] = [1.0, 0.02, -0.03, 0.01]
+    sc = hand_scene(means, scales, quats=quats, opac=[0.7, 0.6, 0.5, 0.95], sh_degree=3, sh=sh)
+    cam = axis_camera(88, 72, f=80.0)
+    cfg = R.Config(method="linprim", sh_degree=3, tile=8, bg=(0.2, 0.1, 0.05))
+    dimg = _dimg(cam, seed=5)
+    g = run_gpu(sc, cam, cfg, dimgs=[dimg])
+    rec = g["splat"][:, :17].astype(np.float64)
+    assert (g["tc"] > 0).all() and rec[1, 4] == 0.0
+    px = np.array([[x, y] for y in range(cam.height) for x in range(cam.width)], np.int32)
+    ch = oracle.lin_chord(np.repeat(rec[3:4], len(px), 0), px)
+    assert (-np.expm1(-rec[3, 2] * ch)).max() > 0.99, "the long octahedron must clamp"
+    w16, worst, nex = _backward_check(sc, cam, cfg, g, dimg)
+    assert np.all(g["grads"]["sh"].reshape(16, 3, 4)[:, 1, 1] == 0), "clamped green passed"
+    log(f"[L6] clamp scene: grad16 {w16:.2e}, params {worst}, excluded {nex}")
+
+
+def test_linprim_backward_accumulate_and_batch():
+    """accumulate adds to the buffers; a batch of three views over two
+    scenes gives each scene the sum of its views' gradients from one call
+    (within the gradient tolerance: the float atomics sum in another
+    order)."""
+    sa = scene_clusters(3000, seed=11, n_clusters=4, box=1.2, lo=0.01, hi=0.25, sh_degree=1)
+    sb = scene_clusters(2000, seed=12, n_clusters=3, box=1.0, lo=0.01, hi=0.3, sh_degree=1)
+    cams = [camera_look_at((0.3, -0.2, -3.9), 90, 70), camera_look_at((-0.4, 0.1, -4.1), 64, 80),
+            camera_look_at((0.1, 0.4, -3.7), 72, 60)]
+    cfg = R.Config(method="linprim", sh_degree=1)
+    scenes = [R.Scene.from_host(sa), R.Scene.from_host(sb)]
+    vs = [0, 1, 0]
+    views = R.Views(scenes, cams, vs, cfg)
     proj = R.xpr_project(views, cfg)
-    assert proj.splat.shape[1] == 20
     bins = R.xpr_bin_sort(views, cfg, proj)
     frame = R.xpr_render_fwd(views, cfg, proj, bins)
-    dimg = torch.zeros(3 * views.pixels, dtype=torch.float32, device="cuda")
-    with pytest.raises(L.XprError) as e:
-        R.xpr_render_bwd(views, cfg, proj, bins, frame, dimg)
-    assert e.value.status == L.XPR_ERR_UNSUPPORTED
+    dimgs = [_dimg(c, seed=20 + i) for i, c in enumerate(cams)]
+    flat = torch.cat([torch.from_numpy(d).reshape(-1) for d in dimgs]).cuda()
+    grads, _ = R.xpr_render_bwd(views, cfg, proj, bins, frame, flat)
+    per = [None, None]
+    for v, (cam, s) in enumerate(zip(cams, vs)):
+        one = run_gpu([sa, sb][s], cam, cfg, dimgs=[dimgs[v]])
+        if per[s] is None:
+            per[s] = {k: x.astype(np.float64) for k, x in one["grads"].items()}
+        else:
+            for k in per[s]:
+                per[s][k] += one["grads"][k]
+    for s in range(2):
+        n = scenes[s].n
+        for k in per[s]:
+            got = grads[s][k].cpu().numpy().astype(np.float64)
+            got = got.reshape(-1, n).T if got.ndim > 1 else got
+            ref = per[s][k].reshape(-1, n).T if per[s][k].ndim > 1 else per[s][k]
+            rel_check(got, ref, f"scene {s} {k}")
+    acc = [{k: t.clone() for k, t in gs.items()} for gs in grads]
+    R.xpr_render_bwd(views, cfg, proj, bins, frame, flat, grads=acc, accumulate=True)
+    for s in range(2):
+        for k in acc[s]:
+            rel_check((acc[s][k] - grads[s][k]).cpu().numpy(), grads[s][k].cpu().numpy(),
+                      f"accumulate {s} {k}")
+    log(f"[L7] batch of 3 views over 2 scenes, {views.records} records, I={bins.count}")
 
 
 def test_linprim_cull_empty_and_everything_culled():

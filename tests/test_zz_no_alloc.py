@@ -5,7 +5,8 @@ C-ABI: two calls in a row, the second with a smaller batch, each equal to
 the existing entry point's parameter gradients within the gradient
 tolerance (float atomics vary the last bits); with accumulate the result
 adds to what the buffers held. Nothing is allocated on the device by the
-call itself. For 3DGS and for 3DGUT (64 bytes of scratch per record)."""
+call itself. For 3DGS, and for 3DGUT and LinPrim (64 bytes of scratch per
+record)."""
 import numpy as np
 import pytest
 import torch
@@ -43,7 +44,7 @@ def _compare(got, ref, n, tag):
     return worst
 
 
-@pytest.mark.parametrize("method", ["3dgs", "3dgut"])
+@pytest.mark.parametrize("method", ["3dgs", "3dgut", "linprim"])
 def test_noalloc_equals_existing_entry_point_on_two_calls(method):
     for call, (n, W, H, seed) in enumerate([(40_000, 320, 240, 1), (9_000, 150, 97, 2)]):
         scene, views, cfg, proj, bins, frame, dimg = _forward(n, W, H, seed, method)
