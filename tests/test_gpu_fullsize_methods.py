@@ -1,11 +1,14 @@
-"""Parity of the 3DGUT and LinPrim forward paths (LinPrim also with its tile
-cull) at the full benchmark size (3M primitives, SH degree 3, 1600x1064,
-16x16 tiles), in the launch configuration the bench times, on sampled
-outputs the oracle computes one by one: 100k sampled primitives for the
-projection, 48 sampled tiles for binning (their complete lists, bit-exact,
-the oracle applying its own cull to the GPU's float32 records) and for
-compositing (every pixel of those tiles within 1e-5, n_contrib exact), plus
-size-independent properties of the whole pair list."""
+"""Whole-frame parity of the 3DGUT and LinPrim paths (LinPrim also with its
+tile cull) at the full benchmark size (3M primitives, SH degree 3,
+1600x1064, 16x16 tiles), on the camera of the eight whose densest tile
+walks furthest, against the FP64 oracle, each stage fed the GPU's previous
+stage: every primitive's projection (P1), the whole pair list and every
+tile range bit-exact (P2; with the cull, the oracle's cull of every pair on
+the GPU's float32 records), every pixel's colour, T_final and n_contrib
+(P3), and every record's 16 shader-data gradients and every primitive's
+parameter gradients (P4). dL/dimage is zero on the guard pixels, so no
+decision in the guard band reaches a gradient and P4 covers every record.
+The oracle takes about 10 s per frame and method on 16 host cores."""
 import functools
 
 import numpy as np
@@ -14,7 +17,7 @@ import pytest
 import oracle
 import test_gpu_gut as GUT
 import test_gpu_linprim as LIN
-from gpu_util import cam32, log, ocfg_of, run_gpu, TOL_PIXEL
+from gpu_util import cam32, check_binning, check_binning_cull, log, ocfg_of, run_gpu
 from paper_2606_11529_amd import renderer as R
 from synth import random_cameras, scene_clusters
 
@@ -24,84 +27,47 @@ pytestmark = pytest.mark.gpu
 @functools.lru_cache(maxsize=1)
 def _scene():
     log("[full-m] generating 3M-primitive scene")
-    return scene_clusters(3_000_000, seed=0), random_cameras(8, 0, (1600, 1064))[0]
-
-
-def _sampled_tiles(g, tx, H, W, seed):
-    rng = np.random.default_rng(seed)
-    nonempty = np.nonzero(g["ranges"][:, 1] > g["ranges"][:, 0])[0]
-    tiles = np.sort(rng.choice(nonempty, 48, replace=False))
-    mask = np.zeros((H, W), bool)
-    for t in tiles:
-        y, x = divmod(int(t), tx)
-        mask[16 * y:16 * y + 16, 16 * x:16 * x + 16] = True
-    return tiles, mask
+    return scene_clusters(3_000_000, seed=0), random_cameras(8, 0, (1600, 1064))[5]
 
 
 @pytest.mark.parametrize("method,cull", [("3dgut", False), ("linprim", False), ("linprim", True)])
-def test_fullsize_method_sampled(method, cull):
+def test_fullsize_method_whole_frame(method, cull):
     sc, cam = _scene()
     cfg = R.Config(sh_degree=3, method=method, tile_cull=cull)
+    M = GUT if method == "3dgut" else LIN
     log(f"[full-m] method={method} cull={cull} n={sc.n} {cam.width}x{cam.height}")
-    g = run_gpu(sc, cam, cfg)
-    oc = ocfg_of(cfg)
     H, W = cam.height, cam.width
     tx, ty = (W + 15) // 16, (H + 15) // 16
-    ncol = 21 if method == "3dgut" else 17
+    oc = ocfg_of(cfg)
+    g0 = run_gpu(sc, cam, cfg)
 
-    # P1: projection of 100k sampled primitives
-    idx = np.sort(np.random.default_rng(4).choice(sc.n, 100_000, replace=False))
-    check = GUT._check_projection if method == "3dgut" else LIN._check_projection
-    ng = check(sc, cam, cfg, g, idx)
+    # P1: every primitive
+    ng = M._check_projection(sc, cam, cfg, g0, np.arange(sc.n))
 
-    # whole list: sorted by (tile, depth), ranges delimit the tiles
-    keys = g["keys"]
-    assert np.all(keys[1:] >= keys[:-1]), "keys not sorted"
-    if not cull:
-        assert g["I"] == int(g["tc"].astype(np.int64).sum())
-    tile_of = (keys >> np.uint64(32)).astype(np.int64)
-    starts = np.flatnonzero(np.r_[True, tile_of[1:] != tile_of[:-1]])
-    ends = np.r_[starts[1:], keys.size]
-    r = g["ranges"]
-    assert np.array_equal(r[tile_of[starts], 0], starts)
-    assert np.array_equal(r[tile_of[starts], 1], ends)
-    assert np.array_equal(keys & np.uint64(0xffffffff),
-                          g["depth"][g["vals"]].view(np.uint32).astype(np.uint64))
-
-    # P2: the complete lists of 48 sampled tiles, from the records touching them
-    tiles, mask = _sampled_tiles(g, tx, H, W, seed=5)
-    rect = g["rect"]
-    touch = np.zeros(rect.shape[0], bool)
-    for t in tiles:
-        y, x = divmod(int(t), tx)
-        touch |= ((g["tc"] > 0) & (rect[:, 0] <= x) & (x < rect[:, 2]) & (rect[:, 1] <= y)
-                  & (y < rect[:, 3]))
-    sub = np.flatnonzero(touch)
-    rec = g["splat"][:, :ncol].astype(np.float64)
-    cull_arg = (rec[sub], W, H, oc) if cull else None
-    ref = oracle.bin_pairs(g["depth"][sub].astype(np.float64), rect[sub], g["tc"][sub], tx, ty,
-                           cull_arg)
-    assert ref["n_guard"] == 0, f"{ref['n_guard']} guard pairs in the sampled tiles"
-    for t in tiles:
-        a, b = ref["ranges"][t]
-        assert np.array_equal(g["vals"][r[t, 0]:r[t, 1]], sub[ref["vals"][a:b]]), f"tile {t}"
-
-    # P3: compositing of the sampled tiles
-    rg = np.zeros_like(r)
-    rg[tiles] = r[tiles]
-    if method == "3dgut":
-        fr = oracle.render_fwd_gut(rec, g["vals"], rg, cam32(cam), oc)
+    # P2: the whole list and every range
+    if cull:
+        ref_b = check_binning_cull(g0, cam, cfg, (tx, ty))
+        assert g0["I"] < int(g0["tc"].astype(np.int64).sum())
     else:
-        fr = oracle.render_fwd_lin(rec, g["vals"], rg, W, H, oc)
-    sel = mask & ~fr["guard"].astype(bool)
-    emax = float(np.abs(g["image"][0] - fr["img"])[:, sel].max())
-    assert emax <= TOL_PIXEL, f"pixel max-abs {emax}"
-    assert np.array_equal(g["ncontrib"][0][sel], fr["ncontrib"][sel]), "n_contrib differs"
-    terr = float(np.abs(g["Tfinal"][0][sel] - fr["Tfinal"][sel]).max())
-    assert terr <= TOL_PIXEL, f"T_final {terr}"
-    gsel = mask & fr["guard"].astype(bool)
-    if gsel.any():
-        assert np.abs(g["image"][0] - fr["img"])[:, gsel].max() <= 1e-2
-    log(f"[full-m] {method} cull={cull}: {idx.size} projected ({ng} guard), I={g['I']}, "
-        f"{tiles.size} tiles / {sub.size} records bit-exact, max-abs {emax:.2e} over "
-        f"{int(sel.sum())} px ({int(gsel.sum())} guard)")
+        ref_b = check_binning(g0, (tx, ty))
+    log(f"[full-m] {method} cull={cull}: P1 {sc.n} ({ng} guard), P2 I={g0['I']} bit-exact "
+        f"(guard pairs {ref_b.get('n_guard', 0)})")
+
+    # P3: every pixel
+    emax, ngp = M._check_forward(g0, cam, cfg)
+
+    # P4: dL/dimage zero on the guard pixels, then every record and primitive
+    ncol = 21 if method == "3dgut" else 17
+    rec = g0["splat"][:, :ncol].astype(np.float64)
+    if method == "3dgut":
+        ref_f = oracle.render_fwd_gut(rec, g0["vals"], g0["ranges"], cam32(cam), oc)
+    else:
+        ref_f = oracle.render_fwd_lin(rec, g0["vals"], g0["ranges"], W, H, oc)
+    rng = np.random.default_rng(3)
+    dimg = rng.normal(size=(3, H, W)).astype(np.float32) / (3 * W * H)
+    dimg[:, ref_f["guard"].astype(bool)] = 0.0
+    g = run_gpu(sc, cam, cfg, dimgs=[dimg])
+    assert np.array_equal(g["vals"], g0["vals"]) and np.array_equal(g["image"][0], g0["image"][0])
+    w16, worst, _ = M._backward_check(sc, cam, cfg, g, dimg, exclude_guard=False)
+    log(f"[full-m] {method} cull={cull}: P3 {W * H} px max-abs {emax:.2e} ({ngp} guard), "
+        f"P4 grad16 {w16:.2e} x bound over all {sc.n} records, params {worst}")

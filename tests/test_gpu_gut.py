@@ -168,14 +168,15 @@ def _param_check(sc, cam, cfg, g, mask):
     return worst
 
 
-def _backward_check(sc, cam, cfg, g, dimg):
+def _backward_check(sc, cam, cfg, g, dimg, exclude_guard=True):
     oc = ocfg_of(cfg)
     rec = g["splat"][:, :21].astype(np.float64)
     c32 = cam32(cam)
     ref_f = oracle.render_fwd_gut(rec, g["vals"], g["ranges"], c32, oc)
     g16 = oracle.render_bwd_gut(rec, g["vals"], g["ranges"], c32, oc, dimg.astype(np.float64))
     tx, _ = oracle.tiles(cam, oc)
-    excl = guard_records(ref_f, g["ncontrib"][0], g["ranges"], g["vals"], cfg.tile, tx)
+    excl = (guard_records(ref_f, g["ncontrib"][0], g["ranges"], g["vals"], cfg.tile, tx)
+            if exclude_guard else np.zeros(0, np.int64))
     mask = np.ones(sc.n, bool)
     mask[excl] = False
     assert g["grad2d"].shape == (sc.n, 16)

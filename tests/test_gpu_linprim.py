@@ -140,7 +140,7 @@ def test_linprim_cull(name):
         f"{ref['n_guard']}, max-abs {emax:.2e}, vs uncut {dmax:.1e}")
 
 
-def _backward_check(sc, cam, cfg, g, dimg):
+def _backward_check(sc, cam, cfg, g, dimg, exclude_guard=True):
     """The record gradient against orc_render_bwd_lin on the GPU's records
     and lists, then the parameter gradients against orc_project_bwd_lin fed
     the GPU's record gradient."""
@@ -150,7 +150,8 @@ def _backward_check(sc, cam, cfg, g, dimg):
     g16 = oracle.render_bwd_lin(rec, g["vals"], g["ranges"], cam.width, cam.height, oc,
                                 dimg.astype(np.float64))
     tx, _ = oracle.tiles(cam, oc)
-    excl = guard_records(ref_f, g["ncontrib"][0], g["ranges"], g["vals"], cfg.tile, tx)
+    excl = (guard_records(ref_f, g["ncontrib"][0], g["ranges"], g["vals"], cfg.tile, tx)
+            if exclude_guard else np.zeros(0, np.int64))
     mask = np.ones(sc.n, bool)
     mask[excl] = False
     assert g["grad2d"].shape == (sc.n, 16)
