@@ -332,12 +332,20 @@ __device__ __forceinline__ void bwd_tile(const Batch& B, int g, int y_off,
   constexpr int NT = TW * TROWS / PPT;
   constexpr int NW = (NT + 63) / 64;
   constexpr int RPW = 64 * PPT / TW;  // pixel rows per wave
+  // One wave over the whole row span (16x16 at 4 pixels per lane): a lane's
+  // PPT pixels lie in PPT bands of NT / TW rows (pixel j in band j), and a
+  // band whose pixels no lane has in play for a record skips that record's
+  // gradient arithmetic. Several waves keep each wave's rows contiguous
+  // (PPT consecutive rows per lane) for the per-wave record lists.
+  constexpr bool BANDS = NW == 1 && PPT > 1;
+  constexpr int kRowStep = BANDS ? NT / TW : 1;
   int32_t& s_maxlast = *s_maxlast_p;
   const ViewDev& V = B.v[view_of_tile(B, g)];
   const int lt = g - V.tile_off;
   const int ty = lt / V.tiles_x, tx = lt - ty * V.tiles_x;
   const int px = tx * TW + (int)(threadIdx.x % TW);
-  const int py0 = ty * TH + y_off + (int)(threadIdx.x / TW) * PPT;
+  // pixel j of this lane is row py0 + j * kRowStep
+  const int py0 = ty * TH + y_off + (int)(threadIdx.x / TW) * (BANDS ? 1 : PPT);
   const int2 rg = ranges[g];
   const float fpx = (float)px;
   const float amax = B.alpha_max, amin = B.alpha_min;
@@ -348,7 +356,7 @@ __device__ __forceinline__ void bwd_tile(const Batch& B, int g, int y_off,
   int mylast = 0;
 #pragma unroll
   for (int j = 0; j < PPT; ++j) {
-    const int py = py0 + j;
+    const int py = py0 + j * kRowStep;
     T[j] = 1.f;
     G0[j] = G1[j] = G2[j] = 0.f;
     last[j] = 0;
@@ -400,7 +408,7 @@ __device__ __forceinline__ void bwd_tile(const Batch& B, int g, int y_off,
     bool anyp = false;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-      dy[j] = __fsub_rn((float)(py0 + j), a.y);
+      dy[j] = __fsub_rn((float)(py0 + j * kRowStep), a.y);
       P2[j] = power2(dx, dy[j], a, b.x);
       const float thr = pos <= last[j] ? b.y : __builtin_inff();
       anyp = anyp || P2[j] >= thr;
@@ -414,6 +422,8 @@ __device__ __forceinline__ void bwd_tile(const Batch& B, int g, int y_off,
     bool any = false;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
+      // a band no lane has in play: every update below is a no-op there
+      if (BANDS && __ballot(P2[j] != __builtin_inff()) == 0) continue;
       const float eP = __builtin_amdgcn_exp2f(P2[j]);
       const float raw = __fmul_rn(b.z, eP);
       float alpha = fminf(amax, raw);
