@@ -57,10 +57,17 @@ __device__ __forceinline__ float power2(float dx, float dy, float4 a, float c) {
 //   dx^2 <= thr / (A' - B'^2 / (4 C')),   dy^2 <= thr / (C' - B'^2 / (4 A')).
 // Each staged record gets a mask of the waves whose pixel rectangle meets
 // that box (computed in FP64 and widened by 1% + 0.05 px, far beyond the
-// rounding of the FP32 power; near-singular conics get every wave), and each
-// wave walks only its own records, in list order. The per-lane threshold
-// test still decides every pair, so this only skips (wave, record)
-// iterations in which no lane could pass.
+// rounding of the FP32 power; near-singular conics get every wave) and on
+// which the power's maximum reaches the threshold: P2 is concave, so its
+// maximum over the rectangle (dx in [X0, X1], dy in [Y0, Y1]) is 0 when the
+// centre lies inside, else the largest of the four edge maxima, each a
+// one-variable quadratic maximised at its clamped vertex (dy = -B' dx /
+// (2 C') on an edge of fixed dx, likewise dx). The comparison allows
+// 1e-5 S + 1e-6 below the threshold, S the largest sum of the power's
+// absolute terms over the rectangle, against an FP32 evaluation error of
+// about 1e-6 S. Each wave walks only its own records, in list order. The
+// per-lane threshold test still decides every pair, so this only skips
+// (wave, record) iterations in which no lane could pass.
 template <int BATCH, int NW>
 struct Stage {
   float4 s0[BATCH];
@@ -82,10 +89,27 @@ __device__ __forceinline__ uint32_t wave_mask(float4 a, float4 b, int x0, int x1
   const double ex = sqrt(thr * 4.0 * C / det4) * 1.01 + 0.05;
   const double ey = sqrt(thr * 4.0 * A / det4) * 1.01 + 0.05;
   if (!(a.x + ex >= (double)x0 && a.x - ex <= (double)x1)) return 0u;
+  const double X0 = (double)x0 - (double)a.x, X1 = (double)x1 - (double)a.x;
+  const double mx = fmax(fabs(X0), fabs(X1));
+  auto pw = [&](double dx, double dy) { return A * dx * dx + Bc * dx * dy + C * dy * dy; };
   uint32_t m = 0u;
   for (int w = 0; w < nw; ++w) {
     const double r0 = (double)(y0 + w * rpw), r1 = r0 + (double)(rpw - 1);
-    if (a.y + ey >= r0 && a.y - ey <= r1) m |= 1u << w;
+    if (!(a.y + ey >= r0 && a.y - ey <= r1)) continue;
+    const double Y0 = r0 - (double)a.y, Y1 = r1 - (double)a.y;
+    double best;
+    if (X0 <= 0.0 && X1 >= 0.0 && Y0 <= 0.0 && Y1 >= 0.0) {
+      best = 0.0;
+    } else {
+      const double ya = fmin(Y1, fmax(Y0, -Bc * X0 / (2.0 * C)));
+      const double yb = fmin(Y1, fmax(Y0, -Bc * X1 / (2.0 * C)));
+      const double xa = fmin(X1, fmax(X0, -Bc * Y0 / (2.0 * A)));
+      const double xb = fmin(X1, fmax(X0, -Bc * Y1 / (2.0 * A)));
+      best = fmax(fmax(pw(X0, ya), pw(X1, yb)), fmax(pw(xa, Y0), pw(xb, Y1)));
+    }
+    const double my = fmax(fabs(Y0), fabs(Y1));
+    const double S = -A * mx * mx + fabs(Bc) * mx * my - C * my * my;
+    if (best >= thr - (1e-5 * S + 1e-6)) m |= 1u << w;
   }
   return m;
 }
