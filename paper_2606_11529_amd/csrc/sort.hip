@@ -510,12 +510,29 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
 // first pair, and first[b + 1] the one holding the pair after its last, so
 // records first[b] .. first[b + 1] hold all of its pairs.
 
+// The rect and tile count of every record in depth order (perm: the record
+// at each depth-order position, key its sorted depth key): one gather of
+// the rect per visible record, all in flight together, so the pair records
+// below read their rects contiguously. A record's tile count is its rect's
+// area (the projection gives a record that touches no tile an empty rect
+// and the key 0xffffffff, which no depth has), so only the rect is gathered.
+__global__ void k_sorted_rects(const short4* __restrict__ rect, const uint32_t* __restrict__ key,
+                               const uint32_t* __restrict__ perm, int64_t n_rec,
+                               short4* __restrict__ rect_sorted, uint32_t* __restrict__ tc_sorted) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_rec) return;
+  short4 rc = make_short4(0, 0, 0, 0);
+  if (key[j] != 0xffffffffu) rc = rect[perm[j]];
+  rect_sorted[j] = rc;
+  tc_sorted[j] = (uint32_t)((rc.z - rc.x) * (rc.w - rc.y));
+}
+
 // One pass over the records in depth order: the packed record each sort
 // block reads contiguously (pair offset, record id, tile id of the rect's
 // top-left corner, rect width | tiles_x << 16), and first[b] for every block
 // b with b T < n, plus first[ceil(n / T)] = the record holding pair n - 1,
 // where n = min(I, capacity).
-__global__ void k_pair_records(Batch B, const short4* __restrict__ rect,
+__global__ void k_pair_records(Batch B, const short4* __restrict__ rect_sorted,
                                const uint32_t* __restrict__ tc_sorted,
                                const uint32_t* __restrict__ perm,
                                const uint32_t* __restrict__ offsets, int64_t n_rec,
@@ -531,7 +548,7 @@ __global__ void k_pair_records(Batch B, const short4* __restrict__ rect,
   int v = 0;
   for (int q = 1; q < B.n_views; ++q)
     if ((int32_t)r >= B.v[q].rec_off) v = q;
-  const short4 rc = rect[r];
+  const short4 rc = rect_sorted[j];
   const uint32_t tx = (uint32_t)B.v[v].tiles_x;
   packed[j] = make_uint4((uint32_t)o, r,
                          (uint32_t)B.v[v].tile_off + (uint32_t)rc.y * tx + (uint32_t)rc.x,
@@ -1883,6 +1900,7 @@ struct BinWs {
   uint32_t* first;     // [cap / kSortTile + 2]  (presort)
   uint4* packed;       // [n_rec]   (presort); [max(n_rec, cap)] row records with the cull
   uint32_t* tcs;       // [n_rec]   tile counts in depth order (presort)
+  short4* rect_s;      // [n_rec]   rects in depth order (presort without the cull)
   // per-(Gaussian, tile) cull
   uint32_t* kc;        // [n_rec]   kept pairs per record
   uint32_t* nrow;      // [n_rec]   kept rows per record
@@ -1951,6 +1969,7 @@ static BinWs bin_ws_layout(int64_t n_rec, int64_t cap, int64_t tiles, int sort_m
     // kept row holds at least one of the <= cap pairs
     L.packed = (uint4*)take(16 * (size_t)std::max<int64_t>(cull ? std::max(n_rec, cap) : n_rec, 1));
     L.tcs = (uint32_t*)take(4 * (size_t)std::max<int64_t>(n_rec, 1));
+    if (!cull) L.rect_s = (short4*)take(8 * (size_t)std::max<int64_t>(n_rec, 1));
     if (cull) {
       L.kc = (uint32_t*)take(4 * (size_t)std::max<int64_t>(n_rec, 1));
       L.nrow = (uint32_t*)take(4 * (size_t)std::max<int64_t>(n_rec, 1));
@@ -2083,12 +2102,18 @@ hipError_t bin_phase1(const Batch& B, int sort_mode, bool cull, const float* spl
                          L.dkey[0], L.perm[0]);
     }
     uint32_t *ko, *vo;
+    // with the cull the kept-pair counts ride along the last pass; without
+    // it the rects and tile counts are gathered afterwards in one kernel
     hipError_t e = radix_sort<uint32_t>(L.dkey[0], L.perm[0], L.dkey[1], L.perm[1], nullptr, n_rec,
                                         n_rec, 32, L.counts, L.partials, &ko, &vo, st, 0, nullptr,
-                                        true, counts, L.tcs);
+                                        true, cull ? counts : nullptr, cull ? L.tcs : nullptr);
     if (e != hipSuccess) return e;
     *perm_out = vo;
-    if (!cull) return device_scan(LoadArray{L.tcs}, n_rec, L.offsets, L.partials, n_isect, st);
+    if (!cull) {
+      hipLaunchKernelGGL(k_sorted_rects, dim3(grid1(n_rec)), dim3(256), 0, st,
+                         reinterpret_cast<const short4*>(rect), ko, vo, n_rec, L.rect_s, L.tcs);
+      return device_scan(LoadArray{L.tcs}, n_rec, L.offsets, L.partials, n_isect, st);
+    }
     if (pb > 0) {
       e = device_scan(LoadMask{L.tcs, (1u << pb) - 1u}, n_rec, L.offsets, L.partials, n_isect, st);
       if (e != hipSuccess) return e;
@@ -2162,8 +2187,8 @@ static hipError_t pair_sort(const Batch& B, int tile_bits, const float* depth, c
                          reinterpret_cast<const float4*>(splat), rc, L.tcs, perm, L.offsets,
                          L.roff, kmask, n_rec, n_isect, cap, L.packed, L.first, lin_req(B));
   } else
-    hipLaunchKernelGGL(k_pair_records, dim3(grid1(n_rec)), dim3(256), 0, st, B, rc, L.tcs, perm,
-                       L.offsets, n_rec, n_isect, cap, L.packed, L.first);
+    hipLaunchKernelGGL(k_pair_records, dim3(grid1(n_rec)), dim3(256), 0, st, B, L.rect_s, L.tcs,
+                       perm, L.offsets, n_rec, n_isect, cap, L.packed, L.first);
   const int nb = (int)((grid_n + kSortTile - 1) / kSortTile);
   KT* k1 = (one && !keys_out) ? nullptr : tk0;
 #define XPR_PAIR_HIST(BITS, ITEMS)                                                          \
