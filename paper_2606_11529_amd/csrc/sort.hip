@@ -209,6 +209,97 @@ static hipError_t device_scan(L load, int64_t n, uint32_t* out, uint64_t* partia
   return hipGetLastError();
 }
 
+// Exclusive scan of each digit's block counts of a radix pass, in place
+// (counts[d nb + b] becomes the count of digit d in blocks before b), and
+// each digit's total over all blocks (tot[d]). The scatter kernels turn the
+// totals into digit starts themselves. A digit's column is cut into chunks
+// of kScanTile counts: with one chunk (up to 4096 sort blocks, 16M keys) a
+// single launch scans every column; longer columns take a reduce launch over
+// all chunks, then a scan launch whose chunks add the sums of the earlier
+// chunks of their column.
+__global__ __launch_bounds__(256) void k_digit_reduce(const uint32_t* __restrict__ counts, int nb,
+                                                      int nchunk, uint32_t* __restrict__ csum) {
+  __shared__ uint64_t s_wave[4];
+  const int d = blockIdx.x / nchunk, ch = blockIdx.x - d * nchunk;
+  const uint32_t* c = counts + (int64_t)d * nb;
+  const int base = ch * kScanTile;
+  uint32_t x[kScanItems];
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    const int i = base + j * 256 + (int)threadIdx.x;
+    x[j] = i < nb ? c[i] : 0u;
+  }
+  uint64_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) s += x[j];
+  s = block_sum256_u64(s, s_wave);
+  if (threadIdx.x == 0) csum[blockIdx.x] = (uint32_t)s;
+}
+
+// csum: the chunk sums of k_digit_reduce, or null with one chunk per column.
+__global__ __launch_bounds__(256) void k_digit_scan(uint32_t* __restrict__ counts, int nb,
+                                                    int nchunk, const uint32_t* __restrict__ csum,
+                                                    uint32_t* __restrict__ tot) {
+  __shared__ uint32_t s[kScanTile + kScanTile / 16];
+  __shared__ uint32_t s_wave[4];
+  const int d = blockIdx.x / nchunk, ch = blockIdx.x - d * nchunk;
+  uint32_t* c = counts + (int64_t)d * nb;
+  const int base = ch * kScanTile;
+  const int t = threadIdx.x;
+  // the sums of the column's earlier chunks (a few at most)
+  uint32_t carry = 0;
+  if (csum)
+    for (int k = 0; k < ch; ++k) carry += csum[d * nchunk + k];
+  {
+    uint32_t y[kScanItems];
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+      const int i = base + j * 256 + t;
+      y[j] = i < nb ? c[i] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+      const int i = j * 256 + t;
+      s[i + (i >> 4)] = y[j];
+    }
+  }
+  __syncthreads();
+  uint32_t x[kScanItems];
+  uint32_t run = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    x[j] = s[17 * t + j];
+    run += x[j];
+  }
+  uint32_t total;
+  uint32_t excl = carry + block_excl_scan256(run, s_wave, &total);
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    s[17 * t + j] = excl;
+    excl += x[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    const int i = j * 256 + t;
+    if (base + i < nb) c[base + i] = s[i + (i >> 4)];
+  }
+  if (t == 0 && ch == nchunk - 1) tot[d] = carry + total;
+}
+
+// csum: nchunk * radix words of scratch (unused with one chunk).
+static hipError_t digit_scan(uint32_t* counts, int nb, int radix, uint32_t* tot, uint32_t* csum,
+                             hipStream_t st) {
+  if (nb <= 0) return hipSuccess;
+  const int nchunk = (nb + kScanTile - 1) / kScanTile;
+  if (nchunk > 1)
+    hipLaunchKernelGGL(k_digit_reduce, dim3(radix * nchunk), dim3(256), 0, st, counts, nb, nchunk,
+                       csum);
+  hipLaunchKernelGGL(k_digit_scan, dim3(radix * nchunk), dim3(256), 0, st, counts, nb, nchunk,
+                     nchunk > 1 ? csum : (const uint32_t*)nullptr, tot);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Small utility kernels.
 
@@ -230,12 +321,48 @@ __global__ void k_set_i64(int64_t* p, int64_t v) {
 
 // Depth-presort keys: the float bits of the depth (positive floats order
 // like their bit patterns); records that touch no tile sort last.
-__global__ void k_depth_keys(const float* depth, const int32_t* tc, int64_t n, uint32_t* key,
-                             uint32_t* perm) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  key[i] = tc[i] > 0 ? __float_as_uint(depth[i]) : 0xffffffffu;
-  perm[i] = (uint32_t)i;
+// Depth keys of the presort (a record that touches no tile gets the key
+// 0xffffffff, which no depth has) with the identity permutation, and the
+// first radix pass's digit counts (bits 0-7) of each sort block of
+// kSortTile keys, written digit-major like k_radix_hist; also zeroes the
+// pair count that k_sorted_rects accumulates.
+__global__ __launch_bounds__(256) void k_depth_keys(const float* __restrict__ depth,
+                                                    const int32_t* __restrict__ tc, int64_t n,
+                                                    uint32_t* __restrict__ key,
+                                                    uint32_t* __restrict__ perm,
+                                                    int64_t* n_isect,
+                                                    uint32_t* __restrict__ counts, int nblocks) {
+  constexpr int COPIES = 8;
+  __shared__ uint32_t h[COPIES][256];
+  const int t = threadIdx.x;
+  for (int k = t; k < COPIES * 256; k += 256) (&h[0][0])[k] = 0;
+  if (blockIdx.x == 0 && t == 0) *n_isect = 0;
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  float dd[kSortItems];
+  int32_t cc[kSortItems];
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int64_t i = min(base + j * 256 + t, n - 1);
+    dd[j] = depth[i];
+    cc[j] = tc[i];
+  }
+  __syncthreads();
+  uint32_t* mine = h[t & (COPIES - 1)];
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int64_t i = base + j * 256 + t;
+    if (i < n) {
+      const uint32_t k = cc[j] > 0 ? __float_as_uint(dd[j]) : 0xffffffffu;
+      key[i] = k;
+      perm[i] = (uint32_t)i;
+      atomicAdd(&mine[k & 255u], 1u);
+    }
+  }
+  __syncthreads();
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < COPIES; ++k) c += h[k][t];
+  counts[(int64_t)t * nblocks + blockIdx.x] = c;
 }
 
 // ---------------------------------------------------------------------------
@@ -430,6 +557,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
                                                        const int64_t* n_dev, int64_t cap,
                                                        int shift,
                                                        const uint32_t* __restrict__ offsets,
+                                                       const uint32_t* __restrict__ dtot,
                                                        int nblocks, int2* __restrict__ ranges,
                                                        const int32_t* __restrict__ aux_src,
                                                        uint32_t* __restrict__ aux_dst) {
@@ -458,6 +586,9 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
     key[j] = kin[idx];
     val[j] = vin[idx];
   }
+  // digit t's total and its count in earlier blocks
+  const uint32_t my_tot = t < RADIX ? dtot[t] : 0u;
+  const uint32_t my_off = t < RADIX ? offsets[(int64_t)t * nblocks + part] : 0u;
 #pragma unroll
   for (int j = 0; j < kSortItems; ++j) {
     const bool ok = base + j * 64 + lane < n;
@@ -477,8 +608,9 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
     c3 = wcnt[3][t];
   }
   const uint32_t start = block_excl_scan256(c0 + c1 + c2 + c3, s_wave, nullptr);
+  const uint32_t dstart = block_excl_scan256(my_tot, s_wave, nullptr);
   if (t < RADIX) {
-    gbase[t] = offsets[(int64_t)t * nblocks + part] - start;
+    gbase[t] = dstart + my_off - start;
     wcnt[0][t] = start;
     wcnt[1][t] = start + c0;
     wcnt[2][t] = start + c0 + c1;
@@ -510,51 +642,126 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
 // first pair, and first[b + 1] the one holding the pair after its last, so
 // records first[b] .. first[b + 1] hold all of its pairs.
 
-// The rect and tile count of every record in depth order (perm: the record
-// at each depth-order position, key its sorted depth key): one gather of
-// the rect per visible record, all in flight together, so the pair records
-// below read their rects contiguously. A record's tile count is its rect's
-// area (the projection gives a record that touches no tile an empty rect
-// and the key 0xffffffff, which no depth has), so only the rect is gathered.
-__global__ void k_sorted_rects(const short4* __restrict__ rect, const uint32_t* __restrict__ key,
-                               const uint32_t* __restrict__ perm, int64_t n_rec,
-                               short4* __restrict__ rect_sorted, uint32_t* __restrict__ tc_sorted) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n_rec) return;
-  short4 rc = make_short4(0, 0, 0, 0);
-  if (key[j] != 0xffffffffu) rc = rect[perm[j]];
-  rect_sorted[j] = rc;
-  tc_sorted[j] = (uint32_t)((rc.z - rc.x) * (rc.w - rc.y));
+// The rect of every record in depth order (perm: the record at each depth-
+// order position, key its sorted depth key): one gather of the rect per
+// visible record, all of a thread's 16 in flight together, so the pair
+// records below read their rects contiguously. A record's tile count is its
+// rect's area (the projection gives a record that touches no tile an empty
+// rect and the key 0xffffffff, which no depth has). Each block of kSortTile
+// positions writes its total tile count to partials[b] and adds it to
+// *n_isect (zeroed by k_depth_keys), so the pair count is known when the
+// depth presort ends and k_pair_records scans the counts itself. tc_sorted
+// (the counts in depth order) is written when given.
+__global__ __launch_bounds__(256) void k_sorted_rects(const short4* __restrict__ rect,
+                                                      const uint32_t* __restrict__ key,
+                                                      const uint32_t* __restrict__ perm,
+                                                      int64_t n_rec,
+                                                      short4* __restrict__ rect_sorted,
+                                                      uint32_t* __restrict__ tc_sorted,
+                                                      uint64_t* __restrict__ partials,
+                                                      int64_t* n_isect) {
+  __shared__ uint64_t s_wave[4];
+  const int t = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  uint32_t kk[kSortItems], pp[kSortItems];
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    const int64_t j = min(base + i * 256 + t, n_rec - 1);
+    kk[i] = key[j];
+    pp[i] = perm[j];
+  }
+  short4 rc[kSortItems];
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    rc[i] = make_short4(0, 0, 0, 0);
+    if (base + i * 256 + t < n_rec && kk[i] != 0xffffffffu) rc[i] = rect[pp[i]];
+  }
+  uint64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    const int64_t j = base + i * 256 + t;
+    if (j < n_rec) {
+      const uint32_t tc = (uint32_t)((rc[i].z - rc[i].x) * (rc[i].w - rc[i].y));
+      rect_sorted[j] = rc[i];
+      if (tc_sorted) tc_sorted[j] = tc;
+      s += tc;
+    }
+  }
+  s = block_sum256_u64(s, s_wave);
+  if (t == 0) {
+    partials[blockIdx.x] = s;
+    atomicAdd(reinterpret_cast<unsigned long long*>(n_isect), (unsigned long long)s);
+  }
 }
 
-// One pass over the records in depth order: the packed record each sort
-// block reads contiguously (pair offset, record id, tile id of the rect's
-// top-left corner, rect width | tiles_x << 16), and first[b] for every block
-// b with b T < n, plus first[ceil(n / T)] = the record holding pair n - 1,
-// where n = min(I, capacity).
-__global__ void k_pair_records(Batch B, const short4* __restrict__ rect_sorted,
-                               const uint32_t* __restrict__ tc_sorted,
-                               const uint32_t* __restrict__ perm,
-                               const uint32_t* __restrict__ offsets, int64_t n_rec,
-                               const int64_t* n_isect, int64_t cap, uint4* __restrict__ packed,
-                               uint32_t* __restrict__ first) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n_rec) return;
+// One pass over the records in depth order, kSortTile per block (wave w
+// takes positions base + 1024 w + 64 i + lane): a record's pair offset is
+// the tile count of all earlier records, from the block totals of
+// k_sorted_rects and wave scans of the counts. Writes the packed record
+// each sort block reads contiguously (pair offset, record id, tile id of
+// the rect's top-left corner, rect width | tiles_x << 16), and first[b] for
+// every block b with b T < n, plus first[ceil(n / T)] = the record holding
+// pair n - 1, where n = min(I, capacity).
+__global__ __launch_bounds__(256) void k_pair_records(Batch B,
+                                                      const short4* __restrict__ rect_sorted,
+                                                      const uint32_t* __restrict__ perm,
+                                                      const uint64_t* __restrict__ partials,
+                                                      int64_t n_rec, const int64_t* n_isect,
+                                                      int64_t cap, uint4* __restrict__ packed,
+                                                      uint32_t* __restrict__ first) {
+  __shared__ uint64_t s_wave64[4];
+  __shared__ uint32_t s_wtot[4];
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int64_t wbase = (int64_t)blockIdx.x * kSortTile + w * (64 * kSortItems);
+  short4 rc[kSortItems];
+  uint32_t rid[kSortItems];
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    const int64_t j = min(wbase + i * 64 + lane, n_rec - 1);
+    rc[i] = rect_sorted[j];
+    rid[i] = perm[j];
+  }
+  // the tile counts of all earlier blocks
+  uint64_t pre = 0;
+  for (int b = t; b < (int)blockIdx.x; b += 256) pre += partials[b];
+  const uint64_t boff = block_sum256_u64(pre, s_wave64);
   const int64_t n = clamp_n(n_isect, cap);
-  const int64_t o = offsets[j];
-  const int64_t e = min(o + (int64_t)tc_sorted[j], n);
-  if (e <= o) return;
-  const uint32_t r = perm[j];
-  int v = 0;
-  for (int q = 1; q < B.n_views; ++q)
-    if ((int32_t)r >= B.v[q].rec_off) v = q;
-  const short4 rc = rect_sorted[j];
-  const uint32_t tx = (uint32_t)B.v[v].tiles_x;
-  packed[j] = make_uint4((uint32_t)o, r,
-                         (uint32_t)B.v[v].tile_off + (uint32_t)rc.y * tx + (uint32_t)rc.x,
-                         (uint32_t)(rc.z - rc.x) | (tx << 16));
-  for (int64_t b = (o + kSortTile - 1) / kSortTile; b * kSortTile < e; ++b) first[b] = (uint32_t)j;
-  if (e == n) first[(n + kSortTile - 1) / kSortTile] = (uint32_t)j;
+  // the wave's exclusive scan of its 1024 counts, then the waves' offsets
+  uint32_t ex[kSortItems];
+  uint32_t carry = 0;
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    const uint32_t tc = wbase + i * 64 + lane < n_rec
+                            ? (uint32_t)((rc[i].z - rc[i].x) * (rc[i].w - rc[i].y))
+                            : 0u;
+    const uint32_t inc = wave_incl_scan_dpp(tc);
+    ex[i] = carry + inc - tc;
+    carry += lane63_u(inc);
+  }
+  if (lane == 0) s_wtot[w] = carry;
+  __syncthreads();
+  uint32_t woff = 0;
+  for (int k = 0; k < w; ++k) woff += s_wtot[k];
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    const int64_t j = wbase + i * 64 + lane;
+    if (j >= n_rec) continue;
+    const int64_t o = (int64_t)(boff + woff + ex[i]);
+    const uint32_t tc = (uint32_t)((rc[i].z - rc[i].x) * (rc[i].w - rc[i].y));
+    const int64_t e = min(o + (int64_t)tc, n);
+    if (e <= o) continue;
+    const uint32_t r = rid[i];
+    int v = 0;
+    for (int q = 1; q < B.n_views; ++q)
+      if ((int32_t)r >= B.v[q].rec_off) v = q;
+    const uint32_t tx = (uint32_t)B.v[v].tiles_x;
+    packed[j] = make_uint4((uint32_t)o, r,
+                           (uint32_t)B.v[v].tile_off + (uint32_t)rc[i].y * tx + (uint32_t)rc[i].x,
+                           (uint32_t)(rc[i].z - rc[i].x) | (tx << 16));
+    for (int64_t b = (o + kSortTile - 1) / kSortTile; b * kSortTile < e; ++b)
+      first[b] = (uint32_t)j;
+    if (e == n) first[(n + kSortTile - 1) / kSortTile] = (uint32_t)j;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1234,7 +1441,8 @@ __global__ __launch_bounds__(256) void k_pair_hist(const uint4* __restrict__ pac
 template <int BITS, bool RANGES, typename KO, class Items>
 __global__ __launch_bounds__(256) void k_pair_scatter(
     const uint4* __restrict__ packed, const uint32_t* __restrict__ first, const int64_t* n_isect,
-    int64_t cap, const uint32_t* __restrict__ doff, int nblocks, KO* __restrict__ kout,
+    int64_t cap, const uint32_t* __restrict__ doff, const uint32_t* __restrict__ dtot,
+    int nblocks, KO* __restrict__ kout,
     uint32_t* __restrict__ vout, int2* __restrict__ ranges) {
   constexpr int RADIX = 1 << BITS;
   __shared__ typename Items::Chunk S;
@@ -1255,11 +1463,13 @@ __global__ __launch_bounds__(256) void k_pair_scatter(
   // thread t owns digits [DPT t, DPT t + DPT); the block's digit offsets do
   // not depend on the items: fetch them early
   constexpr int DPT = (RADIX + 255) / 256;
-  uint32_t my_off[DPT];
+  uint32_t my_off[DPT], my_tot[DPT], tot_sum = 0;
 #pragma unroll
   for (int i = 0; i < DPT; ++i) {
     const int d = DPT * t + i;
     my_off[i] = d < RADIX ? doff[(int64_t)d * nblocks + part] : 0u;
+    my_tot[i] = d < RADIX ? dtot[d] : 0u;
+    tot_sum += my_tot[i];
   }
   gen_block_pairs<Items>(packed, first, part, n, S, sval, s_wave,
                          [&](int slot, uint32_t key, uint32_t val) {
@@ -1291,17 +1501,19 @@ __global__ __launch_bounds__(256) void k_pair_scatter(
     tot += cw[i][0] + cw[i][1] + cw[i][2] + cw[i][3];
   }
   uint32_t start = block_excl_scan256(tot, s_wave, nullptr);
+  uint32_t dstart = block_excl_scan256(tot_sum, s_wave, nullptr);
 #pragma unroll
   for (int i = 0; i < DPT; ++i) {
     const int d = DPT * t + i;
     if (d < RADIX) {
-      gbase[d] = my_off[i] - start;
+      gbase[d] = dstart + my_off[i] - start;
       wcnt[0][d] = start;
       wcnt[1][d] = start + cw[i][0];
       wcnt[2][d] = start + cw[i][0] + cw[i][1];
       wcnt[3][d] = start + cw[i][0] + cw[i][1] + cw[i][2];
     }
     start += cw[i][0] + cw[i][1] + cw[i][2] + cw[i][3];
+    dstart += my_tot[i];
   }
   __syncthreads();
 #pragma unroll
@@ -1746,18 +1958,20 @@ static inline int radix_passes(int bits) {
 template <int BITS, typename K>
 static hipError_t radix_pass(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const int64_t* n_dev,
                              int64_t cap, int nb, int shift, uint32_t* counts,
-                             uint64_t* partials, int2* ranges, const int32_t* aux_src,
-                             uint32_t* aux_dst, hipStream_t st) {
-  hipLaunchKernelGGL((k_radix_hist<BITS, K>), dim3(nb), dim3(256), 0, st, k0, n_dev, cap, shift,
-                     counts, nb);
-  hipError_t e = device_scan(LoadArray{counts}, (int64_t)nb << BITS, counts, partials, nullptr, st);
+                             uint32_t* dtot, uint32_t* csum, int2* ranges,
+                             const int32_t* aux_src, uint32_t* aux_dst, hipStream_t st,
+                             bool counted) {
+  if (!counted)
+    hipLaunchKernelGGL((k_radix_hist<BITS, K>), dim3(nb), dim3(256), 0, st, k0, n_dev, cap, shift,
+                       counts, nb);
+  hipError_t e = digit_scan(counts, nb, 1 << BITS, dtot, csum, st);
   if (e != hipSuccess) return e;
   if (ranges)
     hipLaunchKernelGGL((k_radix_scatter<BITS, K, true>), dim3(nb), dim3(256), 0, st, k0, v0, k1,
-                       v1, n_dev, cap, shift, counts, nb, ranges, aux_src, aux_dst);
+                       v1, n_dev, cap, shift, counts, dtot, nb, ranges, aux_src, aux_dst);
   else
     hipLaunchKernelGGL((k_radix_scatter<BITS, K, false>), dim3(nb), dim3(256), 0, st, k0, v0, k1,
-                       v1, n_dev, cap, shift, counts, nb, (int2*)nullptr, aux_src, aux_dst);
+                       v1, n_dev, cap, shift, counts, dtot, nb, (int2*)nullptr, aux_src, aux_dst);
   return hipGetLastError();
 }
 
@@ -1768,10 +1982,11 @@ static hipError_t radix_pass(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const int
 template <typename K>
 static hipError_t radix_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const int64_t* n_dev,
                              int64_t cap, int64_t grid_n, int bits, uint32_t* counts,
-                             uint64_t* partials, K** k_out, uint32_t** v_out, hipStream_t st,
+                             uint32_t* dtot, uint32_t* csum, K** k_out, uint32_t** v_out,
+                             hipStream_t st,
                              int first_shift = 0, int2* ranges = nullptr,
                              bool keys_last = true, const int32_t* aux_src = nullptr,
-                             uint32_t* aux_dst = nullptr) {
+                             uint32_t* aux_dst = nullptr, bool first_counted = false) {
   *k_out = k0;
   *v_out = v0;
   if (grid_n <= 0) return hipSuccess;
@@ -1786,18 +2001,20 @@ static hipError_t radix_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const int
     // each pass ranks exactly the bits it places (the last one may have
     // fewer than dbits left: one ballot per bit saved per key)
     const int pb = std::min(dbits, bits - shift);
+    // the first pass's counts may come with the keys
+    const bool counted = first_counted && shift == first_shift;
     hipError_t e;
     switch (pb) {
-      case 8: e = radix_pass<8, K>(k0, v0, kdst, v1, n_dev, cap, nb, shift, counts, partials, rg,
-                                   as, ad, st); break;
-      case 7: e = radix_pass<7, K>(k0, v0, kdst, v1, n_dev, cap, nb, shift, counts, partials, rg,
-                                   as, ad, st); break;
-      case 6: e = radix_pass<6, K>(k0, v0, kdst, v1, n_dev, cap, nb, shift, counts, partials, rg,
-                                   as, ad, st); break;
-      case 5: e = radix_pass<5, K>(k0, v0, kdst, v1, n_dev, cap, nb, shift, counts, partials, rg,
-                                   as, ad, st); break;
-      default: e = radix_pass<4, K>(k0, v0, kdst, v1, n_dev, cap, nb, shift, counts, partials, rg,
-                                    as, ad, st); break;
+      case 8: e = radix_pass<8, K>(k0, v0, kdst, v1, n_dev, cap, nb, shift, counts, dtot, csum, rg,
+                                   as, ad, st, counted); break;
+      case 7: e = radix_pass<7, K>(k0, v0, kdst, v1, n_dev, cap, nb, shift, counts, dtot, csum, rg,
+                                   as, ad, st, counted); break;
+      case 6: e = radix_pass<6, K>(k0, v0, kdst, v1, n_dev, cap, nb, shift, counts, dtot, csum, rg,
+                                   as, ad, st, counted); break;
+      case 5: e = radix_pass<5, K>(k0, v0, kdst, v1, n_dev, cap, nb, shift, counts, dtot, csum, rg,
+                                   as, ad, st, counted); break;
+      default: e = radix_pass<4, K>(k0, v0, kdst, v1, n_dev, cap, nb, shift, counts, dtot, csum, rg,
+                                    as, ad, st, counted); break;
     }
     if (e != hipSuccess) return e;
     K* tk = k0; k0 = k1; k1 = tk;
@@ -1893,6 +2110,8 @@ struct BinWs {
   uint32_t* offsets;   // [n_rec]
   uint64_t* partials;  // scan block sums
   uint32_t* counts;    // [256 * nb]
+  uint32_t* dtot;      // [1024]    digit totals of a radix pass
+  uint32_t* csum;      // [radix * chunks]  chunk sums of the digit columns
   uint32_t* vals_alt;  // [cap]
   uint32_t* dkey[2];   // [n_rec]   (presort)
   uint32_t* perm[2];   // [n_rec]   (presort)
@@ -1958,6 +2177,8 @@ static BinWs bin_ws_layout(int64_t n_rec, int64_t cap, int64_t tiles, int sort_m
   L.offsets = (uint32_t*)take(4 * (size_t)std::max<int64_t>(n_rec, 1));
   L.partials = (uint64_t*)take(8 * (size_t)nparts);
   L.counts = (uint32_t*)take(4 * (size_t)(radix_max * nb_max));
+  L.dtot = (uint32_t*)take(4 * 1024);
+  L.csum = (uint32_t*)take(4 * (size_t)(radix_max * ((nb_max + kScanTile - 1) / kScanTile)));
   L.vals_alt = (uint32_t*)take(4 * (size_t)std::max<int64_t>(std::max(cap, n_rec), 1));
   if (sort_mode == XPR_SORT_PRESORT || sort_mode == XPR_SORT_BANDS ||
       sort_mode == XPR_SORT_ONESWEEP) {
@@ -2098,21 +2319,27 @@ hipError_t bin_phase1(const Batch& B, int sort_mode, bool cull, const float* spl
                            L.nrow, L.dkey[0], L.perm[0], lin_req(B));
       counts = reinterpret_cast<const int32_t*>(L.kc);
     } else {
-      hipLaunchKernelGGL(k_depth_keys, dim3(grid1(n_rec)), dim3(256), 0, st, depth, tc, n_rec,
-                         L.dkey[0], L.perm[0]);
+      const int nbk = (int)((n_rec + kSortTile - 1) / kSortTile);
+      hipLaunchKernelGGL(k_depth_keys, dim3(nbk), dim3(256), 0, st, depth, tc, n_rec, L.dkey[0],
+                         L.perm[0], n_isect, L.counts, nbk);
     }
     uint32_t *ko, *vo;
     // with the cull the kept-pair counts ride along the last pass; without
     // it the rects and tile counts are gathered afterwards in one kernel
     hipError_t e = radix_sort<uint32_t>(L.dkey[0], L.perm[0], L.dkey[1], L.perm[1], nullptr, n_rec,
-                                        n_rec, 32, L.counts, L.partials, &ko, &vo, st, 0, nullptr,
-                                        true, cull ? counts : nullptr, cull ? L.tcs : nullptr);
+                                        n_rec, 32, L.counts, L.dtot, L.csum, &ko, &vo, st, 0,
+                                        nullptr, true, cull ? counts : nullptr,
+                                        cull ? L.tcs : nullptr, !cull);
     if (e != hipSuccess) return e;
     *perm_out = vo;
     if (!cull) {
-      hipLaunchKernelGGL(k_sorted_rects, dim3(grid1(n_rec)), dim3(256), 0, st,
-                         reinterpret_cast<const short4*>(rect), ko, vo, n_rec, L.rect_s, L.tcs);
-      return device_scan(LoadArray{L.tcs}, n_rec, L.offsets, L.partials, n_isect, st);
+      // the band path reads the counts in depth order; the pair path
+      // derives them from the rects
+      hipLaunchKernelGGL(k_sorted_rects, dim3((int)((n_rec + kSortTile - 1) / kSortTile)),
+                         dim3(256), 0, st, reinterpret_cast<const short4*>(rect), ko, vo, n_rec,
+                         L.rect_s, sort_mode == XPR_SORT_BANDS ? L.tcs : nullptr, L.partials,
+                         n_isect);
+      return hipGetLastError();
     }
     if (pb > 0) {
       e = device_scan(LoadMask{L.tcs, (1u << pb) - 1u}, n_rec, L.offsets, L.partials, n_isect, st);
@@ -2145,7 +2372,7 @@ static hipError_t tile_order_lpt(const Batch& B, const BinWs& L, const int2* ran
                      L.okey[0], L.oval[0]);
   uint32_t *ko, *vo;
   hipError_t e = radix_sort<uint32_t>(L.okey[0], L.oval[0], L.okey[1], L.oval[1], nullptr, T, T,
-                                      16, L.counts, L.partials, &ko, &vo, st);
+                                      16, L.counts, L.dtot, L.csum, &ko, &vo, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_copy_u32, dim3(grid1(T)), dim3(256), 0, st, vo, (const int64_t*)nullptr, T,
                      (uint32_t*)order);
@@ -2187,8 +2414,9 @@ static hipError_t pair_sort(const Batch& B, int tile_bits, const float* depth, c
                          reinterpret_cast<const float4*>(splat), rc, L.tcs, perm, L.offsets,
                          L.roff, kmask, n_rec, n_isect, cap, L.packed, L.first, lin_req(B));
   } else
-    hipLaunchKernelGGL(k_pair_records, dim3(grid1(n_rec)), dim3(256), 0, st, B, L.rect_s, L.tcs,
-                       perm, L.offsets, n_rec, n_isect, cap, L.packed, L.first);
+    hipLaunchKernelGGL(k_pair_records, dim3((int)((n_rec + kSortTile - 1) / kSortTile)),
+                       dim3(256), 0, st, B, L.rect_s, perm, L.partials, n_rec, n_isect, cap,
+                       L.packed, L.first);
   const int nb = (int)((grid_n + kSortTile - 1) / kSortTile);
   KT* k1 = (one && !keys_out) ? nullptr : tk0;
 #define XPR_PAIR_HIST(BITS, ITEMS)                                                          \
@@ -2200,13 +2428,12 @@ static hipError_t pair_sort(const Batch& B, int tile_bits, const float* depth, c
     if (splat) XPR_PAIR_HIST(8, RowItems); else XPR_PAIR_HIST(8, PairItems);
   }
 #undef XPR_PAIR_HIST
-  hipError_t e =
-      device_scan(LoadArray{L.counts}, (int64_t)nb << dbits, L.counts, L.partials, nullptr, st);
+  hipError_t e = digit_scan(L.counts, nb, 1 << dbits, L.dtot, L.csum, st);
   if (e != hipSuccess) return e;
 #define XPR_PAIR_SCATTER(BITS, LAST, ITEMS)                                                 \
   hipLaunchKernelGGL((k_pair_scatter<BITS, LAST, KT, ITEMS>), dim3(nb), dim3(256), 0, st,       \
                      L.packed,                                                               \
-                     L.first, n_isect, cap, L.counts, nb, k1, v1,                           \
+                     L.first, n_isect, cap, L.counts, L.dtot, nb, k1, v1,                   \
                      LAST ? ranges : (int2*)nullptr)
 #define XPR_PAIR_SCATTER_I(BITS, LAST)                                                      \
   do {                                                                                      \
@@ -2223,8 +2450,8 @@ static hipError_t pair_sort(const Batch& B, int tile_bits, const float* depth, c
   KT* ko = tk0;
   uint32_t* vo = v1;
   if (!one) {
-    e = radix_sort<KT>(tk0, v1, tk1, v2, n_isect, cap, grid_n, tile_bits, L.counts, L.partials,
-                       &ko, &vo, st, dbits, ranges, keys_out != nullptr);
+    e = radix_sort<KT>(tk0, v1, tk1, v2, n_isect, cap, grid_n, tile_bits, L.counts, L.dtot,
+                       L.csum, &ko, &vo, st, dbits, ranges, keys_out != nullptr);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_ranges_fix, dim3(grid1(tiles)), dim3(256), 0, st, ranges, tiles);
@@ -2620,12 +2847,13 @@ static hipError_t band_sort(const Batch& B, const float* depth, const short4* rc
     default: XPR_BAND_HIST(10); break;
   }
 #undef XPR_BAND_HIST
-  e = device_scan(LoadArray{L.counts}, (int64_t)nb << dbits, L.counts, L.partials, nullptr, st);
+  e = digit_scan(L.counts, nb, 1 << dbits, L.dtot, L.csum, st);
   if (e != hipSuccess) return e;
   uint16_t* k1 = one ? nullptr : tk0;
 #define XPR_BAND_SCATTER(BITS, LAST)                                                          \
   hipLaunchKernelGGL((k_pair_scatter<BITS, LAST, uint16_t, BandItems>), dim3(nb), dim3(256), 0, \
-                     st, L.packed, L.first, (const int64_t*)L.n_ent, cap, L.counts, nb, k1, v1,  \
+                     st, L.packed, L.first, (const int64_t*)L.n_ent, cap, L.counts, L.dtot, nb, k1, \
+                     v1,                                                                       \
                      LAST ? L.branges : (int2*)nullptr)
   switch (dbits) {
     case 7: if (one) XPR_BAND_SCATTER(7, true); else XPR_BAND_SCATTER(7, false); break;
@@ -2638,7 +2866,7 @@ static hipError_t band_sort(const Batch& B, const float* depth, const short4* rc
   uint32_t* vo = v1;
   if (!one) {
     e = radix_sort<uint16_t>(tk0, v1, tk1, v2, (const int64_t*)L.n_ent, cap, grid_n, bits,
-                             L.counts, L.partials, &ko, &vo, st, dbits, L.branges, false);
+                             L.counts, L.dtot, L.csum, &ko, &vo, st, dbits, L.branges, false);
     if (e != hipSuccess) return e;
   }
   if (vo != L.vals_alt) return hipErrorUnknown;  // the pass parity above guarantees it
@@ -2677,8 +2905,16 @@ hipError_t bin_phase2(const Batch& B, int sort_mode, bool cull, const float* spl
   sort_mode = effective_mode(sort_mode, cull, cap, n_rec);
   BinWs L = bin_ws_layout(n_rec, cap, B.total_tiles, sort_mode, cull, (char*)ws);
   const float* cull_splat = cull ? splat : nullptr;
-  hipLaunchKernelGGL(k_fill_u32, dim3(grid1(2 * (int64_t)B.total_tiles)), dim3(256), 0, st,
-                     (uint32_t*)ranges, 2 * (int64_t)B.total_tiles, 0u);
+  const bool band_ok =
+      sort_mode == XPR_SORT_BANDS && band_count(B) <= 65536 && n_rec < ((int64_t)1 << 23);
+  // the presort and onesweep paths initialise every tile range themselves
+  const bool own_init = n_rec > 0 && grid_n > 0 &&
+                        (sort_mode == XPR_SORT_ONESWEEP ||
+                         ((sort_mode == XPR_SORT_PRESORT || sort_mode == XPR_SORT_BANDS) &&
+                          !band_ok));
+  if (!own_init)
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid1(2 * (int64_t)B.total_tiles)), dim3(256), 0, st,
+                       (uint32_t*)ranges, 2 * (int64_t)B.total_tiles, 0u);
   if (n_rec == 0 || grid_n == 0) {
     if (tile_order) return tile_order_lpt(B, L, ranges, tile_order, st);
     return hipGetLastError();
@@ -2694,8 +2930,7 @@ hipError_t bin_phase2(const Batch& B, int sort_mode, bool cull, const float* spl
             : pair_sort_sweep<uint32_t>(B, tile_bits, depth, rc, perm, n_rec, cap, grid_n,
                                         n_isect, keys_out, vals_u, ranges, L, st);
     if (e != hipSuccess) return e;
-  } else if (sort_mode == XPR_SORT_BANDS && band_count(B) <= 65536 &&
-             n_rec < ((int64_t)1 << 23)) {
+  } else if (band_ok) {
     const hipError_t e = band_sort(B, depth, rc, perm, n_rec, cap, grid_n, keys_out, vals_u,
                                    ranges, L, st);
     if (e != hipSuccess) return e;
@@ -2717,7 +2952,7 @@ hipError_t bin_phase2(const Batch& B, int sort_mode, bool cull, const float* spl
     uint64_t* ko;
     uint32_t* vo;
     hipError_t e = radix_sort<uint64_t>(L.key64[0], v_start, L.key64[1], v_other, n_isect, cap,
-                                        grid_n, bits, L.counts, L.partials, &ko, &vo, st);
+                                        grid_n, bits, L.counts, L.dtot, L.csum, &ko, &vo, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_ranges<uint64_t>, dim3(grid1((grid_n + 3) / 4)), dim3(256), 0, st, ko,
                        n_isect, cap, B.total_tiles, ranges);
