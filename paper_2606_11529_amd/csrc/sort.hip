@@ -1255,6 +1255,8 @@ struct PairItems {
   using Chunk = RecChunk<256, true>;
   static constexpr int kStage = 256;
   static __device__ __forceinline__ uint32_t width(uint4 q) { return q.w & 0xffffu; }
+  static __device__ __forceinline__ uint32_t key0(uint4 q) { return q.z; }
+  static __device__ __forceinline__ uint32_t stride(uint4 q) { return q.w >> 16; }
   static __device__ __forceinline__ void item(uint4 q, uint32_t, uint32_t yy, uint32_t xx,
                                               uint32_t& key, uint32_t& val) {
     key = q.z + yy * (q.w >> 16) + xx;
@@ -1273,6 +1275,8 @@ struct BandItems {
   using Chunk = RecChunk<256, true>;
   static constexpr int kStage = 256;
   static __device__ __forceinline__ uint32_t width(uint4 q) { return q.z & 0xffffu; }
+  static __device__ __forceinline__ uint32_t key0(uint4 q) { return q.y; }
+  static __device__ __forceinline__ uint32_t stride(uint4 q) { return q.z >> 16; }
   static __device__ __forceinline__ void item(uint4 q, uint32_t j, uint32_t yy, uint32_t xx,
                                               uint32_t& key, uint32_t& val) {
     key = q.y + yy * (q.z >> 16) + xx;
@@ -1293,6 +1297,8 @@ struct RowItems {
   using Chunk = RecChunk<2048, false>;
   static constexpr int kStage = 2048;
   static __device__ __forceinline__ uint32_t width(uint4) { return 1u << 30; }
+  static __device__ __forceinline__ uint32_t key0(uint4 q) { return q.z; }
+  static __device__ __forceinline__ uint32_t stride(uint4) { return 0u; }
   static __device__ __forceinline__ void item(uint4 q, uint32_t, uint32_t, uint32_t xx,
                                               uint32_t& key, uint32_t& val) {
     key = q.z + xx;
@@ -1403,35 +1409,88 @@ __device__ __forceinline__ void gen_block_pairs(const uint4* __restrict__ packed
   }
 }
 
-// First-pass histogram (digit = low BITS bits of the tile id) of each sort
-// block, from regenerated pairs; counts digit-major like k_radix_hist.
+// First-pass histogram (digit = low BITS bits of the key) of each sort
+// block, counted from its records without generating the items: record k
+// of the block holds items [max(o_k, lo), min(o_(k+1), hi)) of the block's
+// range [lo, hi) (records are contiguous in item order; the block's last
+// record runs to hi), a run of rows of its grid, and each row segment is a
+// run of consecutive keys t0 .. t0 + len - 1, whose low BITS bits take
+// every digit len >> BITS times plus the cyclic run of len mod RADIX digits
+// from t0 mod RADIX once. The runs go into an LDS difference array (at
+// most three atomics per row segment instead of one per item), whose
+// prefix sums are the counts; written digit-major like k_radix_hist.
 template <int BITS, class Items>
 __global__ __launch_bounds__(256) void k_pair_hist(const uint4* __restrict__ packed,
                                                    const uint32_t* __restrict__ first,
                                                    const int64_t* n_isect, int64_t cap,
                                                    uint32_t* __restrict__ counts, int nblocks) {
   constexpr int RADIX = 1 << BITS;
-  constexpr int COPIES = RADIX <= 256 ? 8 : 2;
-  __shared__ typename Items::Chunk S;
-  __shared__ uint32_t marks[kSortTilePad];
+  constexpr int DPT = (RADIX + 255) / 256;
+  __shared__ int32_t D[RADIX];
   __shared__ uint32_t s_wave[4];
-  __shared__ uint32_t h[COPIES][RADIX];
   const int t = threadIdx.x;
-  for (int k = t; k < COPIES * RADIX; k += 256) (&h[0][0])[k] = 0;
+  for (int k = t; k < RADIX; k += 256) D[k] = 0;
   const int64_t n = clamp_n(n_isect, cap);
   const int part = live_swizzle(blockIdx.x, nblocks, n);
-  uint32_t* mine = h[t & (COPIES - 1)];
-  if ((int64_t)part * kSortTile < n)
-    gen_block_pairs<Items>(packed, first, part, n, S, marks, s_wave,
-                           [&](int, uint32_t key, uint32_t) {
-                             atomicAdd(&mine[key & (RADIX - 1)], 1u);
-                           });
   __syncthreads();
-  for (int d = t; d < RADIX; d += 256) {
-    uint32_t c = 0;
+  uint32_t whole = 0;  // sum of len >> BITS over this thread's segments
+  if ((int64_t)part * kSortTile < n) {
+    const uint32_t lo = (uint32_t)part * kSortTile;
+    const uint32_t hi = (uint32_t)min(n, (int64_t)lo + kSortTile);
+    const uint32_t j0 = first[part], j1 = first[part + 1];
+    for (uint32_t k = j0 + (uint32_t)t; k <= j1; k += 256u) {
+      const uint4 q = packed[k];
+      const uint32_t o = q.x;
+      const uint32_t end = k < j1 ? min(packed[k + 1].x, hi) : hi;
+      const uint32_t beg = max(o, lo);
+      if (beg >= end) continue;
+      const uint32_t w = Items::width(q), stride = Items::stride(q), z = Items::key0(q);
+      const uint32_t a = beg - o, b = end - o;  // items [a, b) of the record's grid
+      uint32_t y = a / w;
+      uint32_t xa = a - y * w;
+      const uint32_t ylast = (b - 1u) / w;
+      for (; y <= ylast; ++y) {
+        const uint32_t xb = y == ylast ? b - y * w : w;
+        const uint32_t t0 = z + y * stride + xa, len = xb - xa;
+        whole += len >> BITS;
+        const uint32_t r = len & (RADIX - 1), s = t0 & (RADIX - 1);
+        if (r != 0u) {
+          atomicAdd(&D[s], 1);
+          if (s + r < (uint32_t)RADIX) {
+            atomicAdd(&D[s + r], -1);
+          } else if (s + r > (uint32_t)RADIX) {
+            atomicAdd(&D[0], 1);
+            atomicAdd(&D[s + r - RADIX], -1);
+          }
+        }
+        xa = 0;
+      }
+    }
+  }
+  uint32_t all = 0;
+  {
+    // block sum of the whole-cycle counts
+    const uint32_t inc = wave_incl_scan(whole);
+    if ((t & 63) == 63) s_wave[t >> 6] = inc;
+    __syncthreads();
+    all = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    __syncthreads();
+  }
+  // counts = all + inclusive prefix sums of D; thread t holds digits
+  // [DPT t, DPT t + DPT)
+  int32_t dv[DPT], run = 0;
 #pragma unroll
-    for (int k = 0; k < COPIES; ++k) c += h[k][d];
-    counts[(int64_t)d * nblocks + part] = c;
+  for (int i = 0; i < DPT; ++i) {
+    const int d = DPT * t + i;
+    dv[i] = d < RADIX ? D[d] : 0;
+    run += dv[i];
+  }
+  int32_t pre = (int32_t)block_excl_scan256((uint32_t)run, s_wave, nullptr);
+#pragma unroll
+  for (int i = 0; i < DPT; ++i) {
+    const int d = DPT * t + i;
+    pre += dv[i];
+    if (d < RADIX) counts[(int64_t)d * nblocks + part] = all + (uint32_t)pre;
   }
 }
 
