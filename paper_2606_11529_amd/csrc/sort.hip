@@ -1360,10 +1360,17 @@ __device__ __forceinline__ void gen_block_pairs(const uint4* __restrict__ packed
 #pragma unroll
   for (int i = 0; i < 16; ++i) marks[spad(16 * t + i)] = 0u;
   __syncthreads();
-  for (uint32_t k = (uint32_t)t; k < nrec; k += 256u) {
-    const uint32_t o = in_lds ? S.off[k] : packed[j0 + k].x;
+  // (the staged and the unstaged case take separate loops: a pointer that
+  // may address either LDS or global memory would make every read a flat
+  // load that waits for all outstanding loads)
+  auto mark = [&](uint32_t k, uint32_t o) {
     const uint32_t s0 = (o > lo ? o : lo) - lo;
     if (s0 < (uint32_t)nslots) marks[spad((int)s0)] = k + 1u;
+  };
+  if (in_lds) {
+    for (uint32_t k = (uint32_t)t; k < nrec; k += 256u) mark(k, S.off[k]);
+  } else {
+    for (uint32_t k = (uint32_t)t; k < nrec; k += 256u) mark(k, packed[j0 + k].x);
   }
   __syncthreads();
   uint32_t m[16];
@@ -1374,39 +1381,41 @@ __device__ __forceinline__ void gen_block_pairs(const uint4* __restrict__ packed
     m[i] = run;
   }
   const uint32_t pre = block_excl_max256(run, s_wave);
-  auto rec = [&](int k) -> uint4 {
-    return in_lds ? make_uint4(S.off[k], S.a[k], S.b[k], kC ? S.c[k] : 0u)
-                  : packed[j0 + (uint32_t)k];
-  };
-  int kprev = (int)max(pre, m[0]) - 1;
-  uint4 q = rec(kprev);
-  uint32_t xx = 0, yy = 0;
-  {
-    const uint32_t w0 = Items::width(q);
-    const uint32_t local = lo + (uint32_t)(16 * t) - q.x;
-    yy = local / w0;
-    xx = local - yy * w0;
-  }
+  auto walk = [&](auto rec) {
+    int kprev = (int)max(pre, m[0]) - 1;
+    uint4 q = rec(kprev);
+    uint32_t xx = 0, yy = 0;
+    {
+      const uint32_t w0 = Items::width(q);
+      const uint32_t local = lo + (uint32_t)(16 * t) - q.x;
+      yy = local / w0;
+      xx = local - yy * w0;
+    }
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int s = 16 * t + i;
-    const int k = (int)max(pre, m[i]) - 1;
-    if (i > 0) {
-      const bool nk = k != kprev;
-      if (nk) q = rec(k);
-      const uint32_t w = Items::width(q);
-      const uint32_t x1 = xx + 1u;
-      const bool wrap = x1 == w;
-      xx = nk || wrap ? 0u : x1;
-      yy = nk ? 0u : (wrap ? yy + 1u : yy);
-      kprev = k;
+    for (int i = 0; i < 16; ++i) {
+      const int s = 16 * t + i;
+      const int k = (int)max(pre, m[i]) - 1;
+      if (i > 0) {
+        const bool nk = k != kprev;
+        if (nk) q = rec(k);
+        const uint32_t w = Items::width(q);
+        const uint32_t x1 = xx + 1u;
+        const bool wrap = x1 == w;
+        xx = nk || wrap ? 0u : x1;
+        yy = nk ? 0u : (wrap ? yy + 1u : yy);
+        kprev = k;
+      }
+      if (s < nslots) {
+        uint32_t key, val;
+        Items::item(q, j0 + (uint32_t)k, yy, xx, key, val);
+        emit(s, key, val);
+      }
     }
-    if (s < nslots) {
-      uint32_t key, val;
-      Items::item(q, j0 + (uint32_t)k, yy, xx, key, val);
-      emit(s, key, val);
-    }
-  }
+  };
+  if (in_lds)
+    walk([&](int k) { return make_uint4(S.off[k], S.a[k], S.b[k], kC ? S.c[k] : 0u); });
+  else
+    walk([&](int k) { return packed[j0 + (uint32_t)k]; });
 }
 
 // First-pass histogram (digit = low BITS bits of the key) of each sort
