@@ -444,21 +444,24 @@ __device__ __forceinline__ uint32_t digit_of(K k, int shift) {
 }
 
 // Lanes of the wave holding the same BITS-bit digit (among active lanes).
-// Per bit, s is the bit sign-extended (0 or all ones: one bitfield extract)
-// and the lanes with the bit set keep the ballot, the others its
-// complement, i.e. ~(ballot ^ s) in each 32-bit half; gfx950's three-input
-// bit operations fold these into the running AND (45 VALU instructions for
-// 7 bits against 60 with the 64-bit select form).
+// Per bit, s is the bit sign-extended (0 or all ones: one bitfield extract),
+// the ballot compares s itself (the compare intrinsic keeps the compiler
+// from re-deriving the bit with a shift and a second compare), and the
+// lanes with the bit set keep the ballot, the others its complement:
+// lo &= ~(ballot ^ s) in each 32-bit half, one gfx950 three-input bit
+// operation (truth table 0x90 on (lo, ballot, s)), written as the builtin
+// because the compiler otherwise splits it into xor and or chains. Four
+// VALU instructions per bit.
 template <int BITS>
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool active) {
   const uint64_t a = __ballot(active);
   uint32_t lo = (uint32_t)a, hi = (uint32_t)(a >> 32);
 #pragma unroll
   for (int b = 0; b < BITS; ++b) {
-    const uint32_t s = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
-    const uint64_t bb = __ballot(s != 0u);
-    lo &= ~((uint32_t)bb ^ s);
-    hi &= ~((uint32_t)(bb >> 32) ^ s);
+    const uint32_t s = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
+    const uint64_t bb = __builtin_amdgcn_uicmp(s, 0u, 33);  // 33: not equal
+    lo = __builtin_amdgcn_bitop3_b32(lo, (uint32_t)bb, s, 0x90);
+    hi = __builtin_amdgcn_bitop3_b32(hi, (uint32_t)(bb >> 32), s, 0x90);
   }
   return ((uint64_t)hi << 32) | lo;
 }
