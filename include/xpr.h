@@ -163,7 +163,11 @@ typedef struct xpr_views {
  *         adjusted opacity o', (u, v) = UT mean2D - 1/2 and the conic of the
  *         UT covariance: the listing's tile cull data), then ro (3), the
  *         camera position in the Gaussian's canonical frame, M = S^-1 R^T
- *         (9, row-major) and 3 zeros (the listing's shader data);
+ *         (9, row-major) (the listing's shader data), then two words whose
+ *         bit patterns hold int16 pairs X0 | X1 << 16 and Y0 | Y1 << 16, the
+ *         pixel columns and rows that can hold the record's contributions
+ *         (a bound the compositing uses for its per-wave record lists, not
+ *         part of the paper's record), and a zero;
  *         with XPR_METHOD_LINPRIM [total][20] float: u, v (mu_2D - 1/2),
  *         sigma, r | g, b, ex, ey | c0 (3), c1 (3), c2 (3), 3 zeros with
  *         c_k the rows of A^-1 (the listing's shader data)

@@ -562,9 +562,88 @@ __global__ __launch_bounds__(256) void k_project_bwd(Batch B, const float* __res
 // the bounding box is placed at mean2D - 1/2 (pixel (i, j) is the ray
 // through (i + 1/2, j + 1/2)). Record layout (24 floats):
 //   (u, v, A, B) (C, o', r, g) (b, ro) (M00 M01 M02 M10) (M11 M12 M20 M21)
-//   (M22, 0, 0, 0)
+//   (M22, bx, by, 0)
 // with (u, v) = mean2D - 1/2, (A, B, C) the scaled conic as for 3DGS, ro the
-// camera position in the Gaussian's canonical frame and M = S^-1 R^T.
+// camera position in the Gaussian's canonical frame, M = S^-1 R^T, and
+// bx, by (bit patterns) the pixel box of gut_pixel_box for the compositing
+// kernels' per-wave lists.
+//
+// The pixel box: a ray can only come within d^2 <= 9 of the centre if it
+// meets the ellipsoid (x - mu)^T Sigma^-1 (x - mu) <= 9, whose image is
+// bounded by the tangent planes through the camera centre. In camera
+// coordinates the ellipsoid is {x : (x - c)^T E^-1 (x - c) <= 1} with
+// E = 9 N N^T and c = -N ro for N = R_cam M^-1, and the plane X = a Z
+// touches it iff K00 - 2 a K02 + a^2 K22 = 0 for K = E - c c^T
+// = N (9 I - ro ro^T) N^T (likewise Y = b Z with K11, K12, K22), so the
+// image lies in x in fx [a1, a2] + cx (and y alike) when K22 < 0 (the
+// ellipsoid in front of the camera plane). Taken in float64 from the
+// record's float32 M and ro (the values the compositing reads), widened by
+// 1% + 0.05 px and rounded outward to the pixel columns X0 .. X1 and rows
+// Y0 .. Y1 whose centres it may hold, as int16 pairs bx = X0 | X1 << 16,
+// by = Y0 | Y1 << 16 (the whole int16 range when the bound does not exist:
+// K22 >= 0, det M = 0 or a NaN). Computed once per record instead of per
+// (tile, record) in the compositing kernels.
+__device__ __forceinline__ void gut_pixel_box(const double* m, const double* ro,
+                                              const ViewDev& V, uint32_t& bx, uint32_t& by) {
+  constexpr uint32_t kAll = 0x7fff8000u;  // -32768 | 32767 << 16
+  bx = by = kAll;
+  // M^-1 by the adjugate
+  const double c00 = m[4] * m[8] - m[5] * m[7], c01 = m[5] * m[6] - m[3] * m[8],
+               c02 = m[3] * m[7] - m[4] * m[6];
+  const double det = m[0] * c00 + m[1] * c01 + m[2] * c02;
+  if (!(fabs(det) > 0.0)) return;
+  const double id = 1.0 / det;
+  const double inv[9] = {c00 * id, (m[2] * m[7] - m[1] * m[8]) * id,
+                         (m[1] * m[5] - m[2] * m[4]) * id, c01 * id,
+                         (m[0] * m[8] - m[2] * m[6]) * id, (m[2] * m[3] - m[0] * m[5]) * id,
+                         c02 * id, (m[1] * m[6] - m[0] * m[7]) * id,
+                         (m[0] * m[4] - m[1] * m[3]) * id};
+  double N[9];  // R_cam M^-1
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      N[3 * r + c] = (double)V.R[3 * r] * inv[c] + (double)V.R[3 * r + 1] * inv[3 + c] +
+                     (double)V.R[3 * r + 2] * inv[6 + c];
+  // K = N (9 I - ro ro^T) N^T: entries 00, 02, 22, 11, 12
+  double Nro[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+    Nro[r] = N[3 * r] * ro[0] + N[3 * r + 1] * ro[1] + N[3 * r + 2] * ro[2];
+  auto kk = [&](int i, int j) {
+    return 9.0 * (N[3 * i] * N[3 * j] + N[3 * i + 1] * N[3 * j + 1] + N[3 * i + 2] * N[3 * j + 2]) -
+           Nro[i] * Nro[j];
+  };
+  const double k22 = kk(2, 2);
+  if (!(k22 < 0.0)) return;
+  const double k00 = kk(0, 0), k02 = kk(0, 2), k11 = kk(1, 1), k12 = kk(1, 2);
+  const double dx = fmax(k02 * k02 - k00 * k22, 0.0), dy = fmax(k12 * k12 - k11 * k22, 0.0);
+  // roots of K00 - 2 a K02 + a^2 K22 = 0: (K02 -/+ sqrt(dx)) / K22
+  const double ax0 = (k02 + sqrt(dx)) / k22, ax1 = (k02 - sqrt(dx)) / k22;
+  const double ay0 = (k12 + sqrt(dy)) / k22, ay1 = (k12 - sqrt(dy)) / k22;
+  // image box of the ray points x + 1/2, widened
+  const double ux0 = (double)V.fx * fmin(ax0, ax1) + (double)V.cx,
+               ux1 = (double)V.fx * fmax(ax0, ax1) + (double)V.cx;
+  const double uy0 = (double)V.fy * fmin(ay0, ay1) + (double)V.cy,
+               uy1 = (double)V.fy * fmax(ay0, ay1) + (double)V.cy;
+  const double wx = 0.01 * (ux1 - ux0) + 0.05, wy = 0.01 * (uy1 - uy0) + 0.05;
+  // pixel i's centre is i + 1/2: columns floor(lo - 1/2) .. ceil(hi - 1/2)
+  // hold every centre in [lo, hi]; clamped to int16 (views are at most
+  // 16384 pixels wide), a NaN bound opens the box
+  auto lo16 = [](double x) -> uint32_t {
+    x = floor(x);
+    const int v = !(x >= -32768.0) ? -32768 : (x > 32767.0 ? 32767 : (int)x);
+    return (uint32_t)(uint16_t)(int16_t)v;
+  };
+  auto hi16 = [](double x) -> uint32_t {
+    x = ceil(x);
+    const int v = !(x <= 32767.0) ? 32767 : (x < -32768.0 ? -32768 : (int)x);
+    return (uint32_t)(uint16_t)(int16_t)v;
+  };
+  bx = lo16(ux0 - wx - 0.5) | (hi16(ux1 + wx - 0.5) << 16);
+  by = lo16(uy0 - wy - 0.5) | (hi16(uy1 + wy - 0.5) << 16);
+}
+
 template <int DEG>
 __global__ __launch_bounds__(256) void k_project_gut(Batch B, float4* __restrict__ splat,
                                                      float* __restrict__ depth,
@@ -678,12 +757,22 @@ __global__ __launch_bounds__(256) void k_project_gut(Batch B, float4* __restrict
   }
   const size_t r = (size_t)V.rec_off + i;
   float4* out = splat + 6 * r;
+  float Mf[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Mf[k] = (float)M[k];
+  const float rof[3] = {(float)ro0, (float)ro1, (float)ro2};
+  uint32_t bx = 0u, by = 0u;
+  if (visible) {
+    const double md[9] = {Mf[0], Mf[1], Mf[2], Mf[3], Mf[4], Mf[5], Mf[6], Mf[7], Mf[8]};
+    const double rod[3] = {rof[0], rof[1], rof[2]};
+    gut_pixel_box(md, rod, V, bx, by);
+  }
   out[0] = make_float4((float)u, (float)v, (float)(-0.5 * c * dinv), (float)(b * dinv));
   out[1] = make_float4((float)(-0.5 * a * dinv), (float)o, col[0], col[1]);
-  out[2] = make_float4(col[2], (float)ro0, (float)ro1, (float)ro2);
-  out[3] = make_float4((float)M[0], (float)M[1], (float)M[2], (float)M[3]);
-  out[4] = make_float4((float)M[4], (float)M[5], (float)M[6], (float)M[7]);
-  out[5] = make_float4((float)M[8], 0.f, 0.f, 0.f);
+  out[2] = make_float4(col[2], rof[0], rof[1], rof[2]);
+  out[3] = make_float4(Mf[0], Mf[1], Mf[2], Mf[3]);
+  out[4] = make_float4(Mf[4], Mf[5], Mf[6], Mf[7]);
+  out[5] = make_float4(Mf[8], __uint_as_float(bx), __uint_as_float(by), 0.f);
   depth[r] = (float)zc;
   rect[r] = visible ? make_short4((short)x0, (short)y0, (short)x1, (short)y1)
                     : make_short4(0, 0, 0, 0);
@@ -749,7 +838,7 @@ __global__ __launch_bounds__(256, 2) void k_project_bwd_gut(Batch B,
     double R[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) R[k] = V.R[k];
-    const double fx = V.fx, fy = V.fy, cx = V.cx, cy = V.cy;
+    const double fx = V.fx, fy = V.fy;
     const double cp[3] = {-(R[0] * V.t[0] + R[3] * V.t[1] + R[6] * V.t[2]),
                           -(R[1] * V.t[0] + R[4] * V.t[1] + R[7] * V.t[2]),
                           -(R[2] * V.t[0] + R[5] * V.t[1] + R[8] * V.t[2])};

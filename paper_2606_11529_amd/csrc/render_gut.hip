@@ -20,18 +20,12 @@
 // threshold, d^2 < 8.97), alpha = min(alpha_max, o' response) >= alpha_min,
 // stop before blending when T (1 - alpha) < t_min.
 //
-// Per-wave record lists: a ray can only come within d^2 <= 9 of the centre
-// if it meets the ellipsoid (x - mu)^T Sigma^-1 (x - mu) <= 9, whose image
-// is bounded by the tangent planes through the camera centre. In camera
-// coordinates the ellipsoid is {x : (x - c)^T E^-1 (x - c) <= 1} with
-// E = 9 N N^T and c = -N ro for N = R_cam M^-1, and the plane X = a Z
-// touches it iff K00 - 2 a K02 + a^2 K22 = 0 for K = E - c c^T
-// = N (9 I - ro ro^T) N^T (likewise Y = b Z with K11, K12, K22), so the
-// image of the ellipsoid lies in x in fx [a1, a2] + cx (and y alike) when
-// K22 < 0 (the ellipsoid in front of the camera plane). Each staged record
-// gets the mask of the waves whose pixel rows meet that box (float64,
-// widened by 1% + 0.05 px; every wave when K22 >= 0), and each wave walks
-// only its records, in list order; the per-lane test still decides.
+// Per-wave record lists: each record carries the pixel box (int16 column
+// and row bounds, from the projection) that holds every pixel whose ray can
+// come within d^2 <= 9 of its centre; each staged record gets the mask of
+// the waves whose pixel rows meet that box (none when the box misses the
+// tile's columns), and each wave walks only its records, in list order;
+// the per-lane test still decides.
 #include "xpr_internal.h"
 
 namespace xpr {
@@ -59,57 +53,18 @@ struct GutStage {
   uint16_t list[NW][kGutBatch];
 };
 
-// Mask of the waves (rows of RPW pixels from y0) whose pixel rays can meet
-// the record's 3-sigma ellipsoid; x0 .. x1 are the tile's pixel columns.
-__device__ __forceinline__ uint32_t gut_wave_mask(const double* m, const double* ro,
-                                                  const ViewDev& V, int x0, int x1, int y0,
-                                                  int rpw, int nw) {
-  const uint32_t all = (1u << nw) - 1u;
-  // M^-1 by the adjugate
-  const double c00 = m[4] * m[8] - m[5] * m[7], c01 = m[5] * m[6] - m[3] * m[8],
-               c02 = m[3] * m[7] - m[4] * m[6];
-  const double det = m[0] * c00 + m[1] * c01 + m[2] * c02;
-  if (!(fabs(det) > 0.0)) return all;
-  const double id = 1.0 / det;
-  const double inv[9] = {c00 * id, (m[2] * m[7] - m[1] * m[8]) * id,
-                         (m[1] * m[5] - m[2] * m[4]) * id, c01 * id,
-                         (m[0] * m[8] - m[2] * m[6]) * id, (m[2] * m[3] - m[0] * m[5]) * id,
-                         c02 * id, (m[1] * m[6] - m[0] * m[7]) * id,
-                         (m[0] * m[4] - m[1] * m[3]) * id};
-  double N[9];  // R_cam M^-1
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      N[3 * r + c] = (double)V.R[3 * r] * inv[c] + (double)V.R[3 * r + 1] * inv[3 + c] +
-                     (double)V.R[3 * r + 2] * inv[6 + c];
-  // K = N (9 I - ro ro^T) N^T: entries 00, 02, 22, 11, 12
-  double Nro[3];
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-    Nro[r] = N[3 * r] * ro[0] + N[3 * r + 1] * ro[1] + N[3 * r + 2] * ro[2];
-  auto kk = [&](int i, int j) {
-    return 9.0 * (N[3 * i] * N[3 * j] + N[3 * i + 1] * N[3 * j + 1] + N[3 * i + 2] * N[3 * j + 2]) -
-           Nro[i] * Nro[j];
-  };
-  const double k22 = kk(2, 2);
-  if (!(k22 < 0.0)) return all;
-  const double k00 = kk(0, 0), k02 = kk(0, 2), k11 = kk(1, 1), k12 = kk(1, 2);
-  const double dx = fmax(k02 * k02 - k00 * k22, 0.0), dy = fmax(k12 * k12 - k11 * k22, 0.0);
-  // roots of K00 - 2 a K02 + a^2 K22 = 0: (K02 -/+ sqrt(dx)) / K22
-  const double ax0 = (k02 + sqrt(dx)) / k22, ax1 = (k02 - sqrt(dx)) / k22;
-  const double ay0 = (k12 + sqrt(dy)) / k22, ay1 = (k12 - sqrt(dy)) / k22;
-  // image box of the ray points x + 1/2, widened
-  const double ux0 = (double)V.fx * fmin(ax0, ax1) + (double)V.cx,
-               ux1 = (double)V.fx * fmax(ax0, ax1) + (double)V.cx;
-  const double uy0 = (double)V.fy * fmin(ay0, ay1) + (double)V.cy,
-               uy1 = (double)V.fy * fmax(ay0, ay1) + (double)V.cy;
-  const double wx = 0.01 * (ux1 - ux0) + 0.05, wy = 0.01 * (uy1 - uy0) + 0.05;
-  if (!(ux1 + wx >= (double)x0 + 0.5 && ux0 - wx <= (double)x1 + 0.5)) return 0u;
+// Mask of the waves (rows of RPW pixels from y0) that meet the record's
+// pixel box (bx, by: int16 pairs X0 | X1 << 16, Y0 | Y1 << 16); x0 .. x1 are
+// the tile's pixel columns.
+__device__ __forceinline__ uint32_t gut_wave_mask(uint32_t bx, uint32_t by, int x0, int x1,
+                                                  int y0, int rpw, int nw) {
+  const int X0 = (int16_t)(bx & 0xffffu), X1 = (int16_t)(bx >> 16);
+  const int Y0 = (int16_t)(by & 0xffffu), Y1 = (int16_t)(by >> 16);
+  if (X1 < x0 || X0 > x1) return 0u;
   uint32_t msk = 0u;
   for (int w = 0; w < nw; ++w) {
-    const double r0 = (double)(y0 + w * rpw) + 0.5, r1 = r0 + (double)(rpw - 1);
-    if (uy1 + wy >= r0 && uy0 - wy <= r1) msk |= 1u << w;
+    const int r0 = y0 + w * rpw;
+    if (Y1 >= r0 && Y0 <= r0 + rpw - 1) msk |= 1u << w;
   }
   return msk;
 }
@@ -173,8 +128,8 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd_gut(
       G.q[3] = mm(0, 1); G.q[4] = mm(0, 2); G.q[5] = mm(1, 2);
       G.ro2 = ro[0] * ro[0] + ro[1] * ro[1] + ro[2] * ro[2];
       G.o = q1.y; G.r = q1.z; G.g = q1.w; G.b = q2.x;
-      S.mask[k] = (typename GutStage<NW>::mask_t)gut_wave_mask(m, ro, V, tx * TW, tx * TW + TW - 1,
-                                                               ty * TH, RPW, NW);
+      S.mask[k] = (typename GutStage<NW>::mask_t)gut_wave_mask(
+          __float_as_uint(q5.y), __float_as_uint(q5.z), tx * TW, tx * TW + TW - 1, ty * TH, RPW, NW);
     }
     __syncthreads();
     // this wave's records of the batch, in list order
@@ -350,7 +305,6 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd_gut(
   }
   const double p00 = rd0 * rd0, p11 = rd1 * rd1, p22 = rd2 * rd2;
   const double p01 = 2.0 * rd0 * rd1, p02 = 2.0 * rd0 * rd2, p12 = 2.0 * rd1 * rd2;
-  const float rf0 = (float)rd0, rf1 = (float)rd1, rf2 = (float)rd2;
   float T = 1.f, G0 = 0.f, G1 = 0.f, G2 = 0.f;
   int mylast = 0;
   if (inside) {
@@ -410,7 +364,7 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd_gut(
       G.ro2 = ro[0] * ro[0] + ro[1] * ro[1] + ro[2] * ro[2];
       G.o = q1.y; G.r = q1.z; G.g = q1.w; G.b = q2.x;
       S.f.mask[k] = (typename GutStage<NW>::mask_t)gut_wave_mask(
-          m, ro, V, tx * TW, tx * TW + TW - 1, ty * TH, RPW, NW);
+          __float_as_uint(q5.y), __float_as_uint(q5.z), tx * TW, tx * TW + TW - 1, ty * TH, RPW, NW);
     }
     __syncthreads();
     // this wave's records of the batch within its walk, in list order

@@ -125,6 +125,49 @@ def test_gut_projection(name):
     log(f"[G1] {name}: {idx.size} checked, {ng} guard, visible {(g['tc'] > 0).sum()}")
 
 
+@pytest.mark.parametrize("name", ["ragged_t8", "ragged_t32", "clusters_1M_1297x840"])
+def test_gut_pixel_box_holds_every_contribution(name):
+    """The pixel box a 3DGUT record carries (columns 21-22 of the record: int16
+    column and row bounds X0 | X1 << 16, Y0 | Y1 << 16 from the projection,
+    used only to build the compositing's per-wave lists) holds every pixel
+    whose response can pass the validity gate (0.0113): brute force over
+    every pixel of the record's tile rect for a sample of visible records,
+    with the oracle's FP64 response on the GPU's float32 record."""
+    sc, cam, cfg, g = _run(name)
+    W, H = cam.width, cam.height
+    tw = th = cfg.tile
+    vis = np.flatnonzero(g["tc"] > 0)
+    rng = np.random.default_rng(11)
+    pick = rng.choice(vis, size=min(400, vis.size), replace=False)
+    bits = np.ascontiguousarray(g["splat"][pick][:, 21:23]).view(np.uint32)
+    X0 = (bits[:, 0] & 0xFFFF).astype(np.uint16).view(np.int16).astype(np.int64)
+    X1 = (bits[:, 0] >> 16).astype(np.uint16).view(np.int16).astype(np.int64)
+    Y0 = (bits[:, 1] & 0xFFFF).astype(np.uint16).view(np.int16).astype(np.int64)
+    Y1 = (bits[:, 1] >> 16).astype(np.uint16).view(np.int16).astype(np.int64)
+    rec = g["splat"][pick][:, :21].astype(np.float64)
+    rects = g["rect"][pick].astype(np.int64)
+    n_hit = n_px = 0
+    for k in range(pick.size):
+        x0, y0, x1, y1 = rects[k]
+        xs = np.arange(x0 * tw, min(x1 * tw, W))
+        ys = np.arange(y0 * th, min(y1 * th, H))
+        if xs.size * ys.size > 400_000:
+            continue
+        gx, gy = np.meshgrid(xs, ys)
+        pxy = np.stack([gx.ravel(), gy.ravel()], axis=1).astype(np.int32)
+        resp = oracle.gut_response(np.repeat(rec[k:k + 1], pxy.shape[0], axis=0), pxy, cam32(cam))
+        hit = resp > 0.0113
+        px, py = pxy[hit, 0], pxy[hit, 1]
+        inside = (px >= X0[k]) & (px <= X1[k]) & (py >= Y0[k]) & (py <= Y1[k])
+        assert inside.all(), (f"record {pick[k]}: {int((~inside).sum())} contributing pixels "
+                              f"outside its box [{X0[k]}, {X1[k]}] x [{Y0[k]}, {Y1[k]}]")
+        n_hit += int(hit.sum())
+        n_px += pxy.shape[0]
+    assert n_hit > 0
+    log(f"[gpu gut] {name}: pixel boxes hold all {n_hit} contributing pixels of {n_px} "
+        f"rect pixels ({pick.size} records)")
+
+
 @pytest.mark.parametrize("name", CASES)
 def test_gut_binning_and_forward(name):
     sc, cam, cfg, g = _run(name)
