@@ -86,12 +86,20 @@ __device__ __forceinline__ uint32_t wave_mask(float4 a, float4 b, int x0, int x1
   if (!(thr < 0.0) || !(A < 0.0) || !(C < 0.0)) return all;
   const double det4 = 4.0 * A * C - Bc * Bc;
   if (!(det4 > 1e-3 * 4.0 * A * C)) return all;
-  const double ex = sqrt(thr * 4.0 * C / det4) * 1.01 + 0.05;
-  const double ey = sqrt(thr * 4.0 * A / det4) * 1.01 + 0.05;
+  // two divisions per record; the vertices below use their reciprocals
+  // (a rounding of ~1e-16 relative in a vertex moves the edge maximum by a
+  // second-order amount, far inside the 1e-6 margin)
+  const double idet = 1.0 / det4, i4ac = 1.0 / (4.0 * A * C);
+  const double ex = sqrt(thr * 4.0 * C * idet) * 1.01 + 0.05;
+  const double ey = sqrt(thr * 4.0 * A * idet) * 1.01 + 0.05;
   if (!(a.x + ex >= (double)x0 && a.x - ex <= (double)x1)) return 0u;
   const double X0 = (double)x0 - (double)a.x, X1 = (double)x1 - (double)a.x;
   const double mx = fmax(fabs(X0), fabs(X1));
   auto pw = [&](double dx, double dy) { return A * dx * dx + Bc * dx * dy + C * dy * dy; };
+  // vertex of the power along an edge of fixed dx: dy = -B' dx / (2 C')
+  // (likewise dx = -B' dy / (2 A')), before clamping to the wave's rows
+  const double kc = -Bc * (2.0 * A) * i4ac, ka = -Bc * (2.0 * C) * i4ac;
+  const double va = X0 * kc, vb = X1 * kc;
   uint32_t m = 0u;
   for (int w = 0; w < nw; ++w) {
     const double r0 = (double)(y0 + w * rpw), r1 = r0 + (double)(rpw - 1);
@@ -101,10 +109,10 @@ __device__ __forceinline__ uint32_t wave_mask(float4 a, float4 b, int x0, int x1
     if (X0 <= 0.0 && X1 >= 0.0 && Y0 <= 0.0 && Y1 >= 0.0) {
       best = 0.0;
     } else {
-      const double ya = fmin(Y1, fmax(Y0, -Bc * X0 / (2.0 * C)));
-      const double yb = fmin(Y1, fmax(Y0, -Bc * X1 / (2.0 * C)));
-      const double xa = fmin(X1, fmax(X0, -Bc * Y0 / (2.0 * A)));
-      const double xb = fmin(X1, fmax(X0, -Bc * Y1 / (2.0 * A)));
+      const double ya = fmin(Y1, fmax(Y0, va));
+      const double yb = fmin(Y1, fmax(Y0, vb));
+      const double xa = fmin(X1, fmax(X0, Y0 * ka));
+      const double xb = fmin(X1, fmax(X0, Y1 * ka));
       best = fmax(fmax(pw(X0, ya), pw(X1, yb)), fmax(pw(xa, Y0), pw(xb, Y1)));
     }
     const double my = fmax(fabs(Y0), fabs(Y1));
