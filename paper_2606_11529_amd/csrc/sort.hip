@@ -1521,8 +1521,9 @@ __global__ __launch_bounds__(256) void k_pair_scatter(
   __shared__ uint32_t gbase[RADIX];
   __shared__ uint32_t s_wave[4];
   // pairs in slot order at spad(slot) (sval doubles as the generator's
-  // marks), then the ranked block in plain order
-  __shared__ uint32_t skey[kSortTilePad];
+  // marks), then the ranked block in plain order; keys in the output key
+  // type (16-bit tile ids take half the LDS: four blocks per CU, not three)
+  __shared__ KO skey[kSortTilePad];
   __shared__ uint32_t sval[kSortTilePad];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int64_t n = clamp_n(n_isect, cap);
@@ -1544,7 +1545,7 @@ __global__ __launch_bounds__(256) void k_pair_scatter(
   }
   gen_block_pairs<Items>(packed, first, part, n, S, sval, s_wave,
                          [&](int slot, uint32_t key, uint32_t val) {
-                           skey[spad(slot)] = key;
+                           skey[spad(slot)] = (KO)key;
                            sval[spad(slot)] = val;
                          });
   __syncthreads();
@@ -1592,13 +1593,13 @@ __global__ __launch_bounds__(256) void k_pair_scatter(
     const int slot = w * (64 * kSortItems) + j * 64 + lane;
     if (slot < nvalid) {
       const uint32_t pos = wcnt[w][key[j] & (RADIX - 1)] + lofs[j];
-      skey[pos] = key[j];
+      skey[pos] = (KO)key[j];
       sval[pos] = val[j];
     }
   }
   __syncthreads();
-  write_sorted<BITS, uint32_t, KO, RANGES>(skey, sval, gbase, nvalid, 0, kout, vout, ranges,
-                                           nullptr, nullptr);
+  write_sorted<BITS, KO, KO, RANGES>(skey, sval, gbase, nvalid, 0, kout, vout, ranges, nullptr,
+                                     nullptr);
 }
 
 // ---------------------------------------------------------------------------
