@@ -21,6 +21,9 @@ constexpr int kScanTile = 256 * kScanItems;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = 256 * kSortItems;  // keys per scatter block
 constexpr int kSortWaves = 4;
+// threads of a radix scatter block (kSortTile keys, 8 per thread: about
+// 75 VGPRs, six waves per SIMD, against 124 and four with 256 threads)
+constexpr int kRadixThreads = 512;
 
 // ---------------------------------------------------------------------------
 // Block-level helpers (256 threads = 4 waves).
@@ -67,6 +70,21 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t* s_w
   uint32_t off = 0;
   for (int k = 0; k < w; ++k) off += s_wave[k];
   if (total) *total = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+  __syncthreads();
+  return off + inc - x;
+}
+
+// Exclusive scan of one value per thread over an NT-thread block.
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_wave) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t inc = wave_incl_scan(x);
+  if (lane == 63) s_wave[w] = inc;
+  __syncthreads();
+  uint32_t off = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) off += k < w ? s_wave[k] : 0u;
   __syncthreads();
   return off + inc - x;
 }
@@ -526,14 +544,14 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys,
 // stored when kout is given. With aux_dst, aux_dst[g] = aux_src[value] is
 // stored beside each value (a per-record quantity carried into sorted
 // order).
-template <int BITS, typename KS, typename KO, bool RANGES>
+template <int BITS, typename KS, typename KO, bool RANGES, int NT = 256>
 __device__ __forceinline__ void write_sorted(const KS* skey, const uint32_t* sval,
                                              const uint32_t* gbase, int nvalid, int shift,
                                              KO* __restrict__ kout, uint32_t* __restrict__ vout,
                                              int2* __restrict__ ranges,
                                              const int32_t* __restrict__ aux_src,
                                              uint32_t* __restrict__ aux_dst) {
-  for (int k = threadIdx.x; k < nvalid; k += 256) {
+  for (int k = threadIdx.x; k < nvalid; k += NT) {
     const KS kk = skey[k];
     const uint32_t g = gbase[digit_of<BITS>(kk, shift)] + (uint32_t)k;
     if (!RANGES || kout) kout[g] = (KO)kk;
@@ -548,43 +566,48 @@ __device__ __forceinline__ void write_sorted(const KS* skey, const uint32_t* sva
   }
 }
 
-// Stable scatter of one block: rank the block's keys by digit in LDS (per
-// wave, slot by slot, the wave64 ballot match gives the rank among lanes
-// with the same digit), then write them out in digit order so each digit's
-// run is a contiguous global store.
-template <int BITS, typename K, bool RANGES>
-__global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin,
-                                                       const uint32_t* __restrict__ vin,
-                                                       K* __restrict__ kout,
-                                                       uint32_t* __restrict__ vout,
-                                                       const int64_t* n_dev, int64_t cap,
-                                                       int shift,
-                                                       const uint32_t* __restrict__ offsets,
-                                                       const uint32_t* __restrict__ dtot,
-                                                       int nblocks, int2* __restrict__ ranges,
-                                                       const int32_t* __restrict__ aux_src,
-                                                       uint32_t* __restrict__ aux_dst) {
+// Stable scatter of one block of kSortTile keys on NT threads (NT / 64
+// waves, kSortTile / NT keys per thread): rank the block's keys by digit in
+// LDS (per wave, slot by slot, the wave64 ballot match gives the rank among
+// lanes with the same digit), then write them out in digit order so each
+// digit's run is a contiguous global store. More threads hold fewer keys
+// each: fewer registers per thread, more waves per CU.
+template <int BITS, typename K, bool RANGES, int NT>
+__global__ __launch_bounds__(NT) void k_radix_scatter(const K* __restrict__ kin,
+                                                      const uint32_t* __restrict__ vin,
+                                                      K* __restrict__ kout,
+                                                      uint32_t* __restrict__ vout,
+                                                      const int64_t* n_dev, int64_t cap,
+                                                      int shift,
+                                                      const uint32_t* __restrict__ offsets,
+                                                      const uint32_t* __restrict__ dtot,
+                                                      int nblocks, int2* __restrict__ ranges,
+                                                      const int32_t* __restrict__ aux_src,
+                                                      uint32_t* __restrict__ aux_dst) {
   constexpr int RADIX = 1 << BITS;
-  __shared__ uint32_t wcnt[kSortWaves][RADIX];
+  constexpr int NW = NT / 64;
+  constexpr int IT = kSortTile / NT;
+  static_assert(RADIX <= NT && IT * NT == kSortTile, "radix scatter shape");
+  __shared__ uint32_t wcnt[NW][RADIX];
   __shared__ uint32_t gbase[RADIX];  // global offset of the digit's run minus its block start
-  __shared__ uint32_t s_wave[4];
+  __shared__ uint32_t s_wave[NW];
   __shared__ K skey[kSortTile];
   __shared__ uint32_t sval[kSortTile];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  for (int k = t; k < kSortWaves * RADIX; k += 256) (&wcnt[0][0])[k] = 0;
+  for (int k = t; k < NW * RADIX; k += NT) (&wcnt[0][0])[k] = 0;
   __syncthreads();
   const int64_t n = clamp_n(n_dev, cap);
   const int part = live_swizzle(blockIdx.x, nblocks, n);
   const int64_t bbase = (int64_t)part * kSortTile;
   if (bbase >= n) return;  // whole block beyond the list: no counts, nothing to write
-  const int64_t base = bbase + w * (64 * kSortItems);
+  const int64_t base = bbase + w * (64 * IT);
   const uint64_t lt = lanemask_lt();
-  K key[kSortItems];
-  uint32_t val[kSortItems];
-  uint32_t lofs[kSortItems];
+  K key[IT];
+  uint32_t val[IT];
+  uint32_t lofs[IT];
   // all loads first (indices clamped into the list), then the ranking
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
+  for (int j = 0; j < IT; ++j) {
     const int64_t idx = min(base + j * 64 + lane, n - 1);
     key[j] = kin[idx];
     val[j] = vin[idx];
@@ -593,7 +616,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
   const uint32_t my_tot = t < RADIX ? dtot[t] : 0u;
   const uint32_t my_off = t < RADIX ? offsets[(int64_t)t * nblocks + part] : 0u;
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
+  for (int j = 0; j < IT; ++j) {
     const bool ok = base + j * 64 + lane < n;
     const uint32_t d = digit_of<BITS>(key[j], shift);
     const uint64_t m = match_digit<BITS>(d, ok);
@@ -602,26 +625,27 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
     if (ok && (m & lt) == 0) wcnt[w][d] = before + (uint32_t)__popcll(m);
   }
   __syncthreads();
-  // digit t: block totals, exclusive block start, per-wave starts
-  uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-  if (t < RADIX) {
-    c0 = wcnt[0][t];
-    c1 = wcnt[1][t];
-    c2 = wcnt[2][t];
-    c3 = wcnt[3][t];
+  // digit t: the waves' counts, the block's exclusive start, per-wave starts
+  uint32_t c[NW], tot = 0;
+#pragma unroll
+  for (int q = 0; q < NW; ++q) {
+    c[q] = t < RADIX ? wcnt[q][t] : 0u;
+    tot += c[q];
   }
-  const uint32_t start = block_excl_scan256(c0 + c1 + c2 + c3, s_wave, nullptr);
-  const uint32_t dstart = block_excl_scan256(my_tot, s_wave, nullptr);
+  const uint32_t start = block_excl_scan<NT>(tot, s_wave);
+  const uint32_t dstart = block_excl_scan<NT>(my_tot, s_wave);
   if (t < RADIX) {
     gbase[t] = dstart + my_off - start;
-    wcnt[0][t] = start;
-    wcnt[1][t] = start + c0;
-    wcnt[2][t] = start + c0 + c1;
-    wcnt[3][t] = start + c0 + c1 + c2;
+    uint32_t s = start;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      wcnt[q][t] = s;
+      s += c[q];
+    }
   }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
+  for (int j = 0; j < IT; ++j) {
     const int64_t idx = base + j * 64 + lane;
     if (idx < n) {
       const uint32_t pos = wcnt[w][digit_of<BITS>(key[j], shift)] + lofs[j];
@@ -632,8 +656,8 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
   __syncthreads();
   const int64_t rem = n - bbase;
   const int nvalid = rem <= 0 ? 0 : (rem < kSortTile ? (int)rem : kSortTile);
-  write_sorted<BITS, K, K, RANGES>(skey, sval, gbase, nvalid, shift, kout, vout, ranges, aux_src,
-                                   aux_dst);
+  write_sorted<BITS, K, K, RANGES, NT>(skey, sval, gbase, nvalid, shift, kout, vout, ranges,
+                                       aux_src, aux_dst);
 }
 
 // ---------------------------------------------------------------------------
@@ -2038,12 +2062,14 @@ static hipError_t radix_pass(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const int
                        counts, nb);
   hipError_t e = digit_scan(counts, nb, 1 << BITS, dtot, csum, st);
   if (e != hipSuccess) return e;
+  constexpr int NT = kRadixThreads;
   if (ranges)
-    hipLaunchKernelGGL((k_radix_scatter<BITS, K, true>), dim3(nb), dim3(256), 0, st, k0, v0, k1,
-                       v1, n_dev, cap, shift, counts, dtot, nb, ranges, aux_src, aux_dst);
+    hipLaunchKernelGGL((k_radix_scatter<BITS, K, true, NT>), dim3(nb), dim3(NT), 0, st, k0, v0,
+                       k1, v1, n_dev, cap, shift, counts, dtot, nb, ranges, aux_src, aux_dst);
   else
-    hipLaunchKernelGGL((k_radix_scatter<BITS, K, false>), dim3(nb), dim3(256), 0, st, k0, v0, k1,
-                       v1, n_dev, cap, shift, counts, dtot, nb, (int2*)nullptr, aux_src, aux_dst);
+    hipLaunchKernelGGL((k_radix_scatter<BITS, K, false, NT>), dim3(nb), dim3(NT), 0, st, k0, v0,
+                       k1, v1, n_dev, cap, shift, counts, dtot, nb, (int2*)nullptr, aux_src,
+                       aux_dst);
   return hipGetLastError();
 }
 
