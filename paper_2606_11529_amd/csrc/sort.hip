@@ -24,6 +24,8 @@ constexpr int kSortWaves = 4;
 // threads of a radix scatter block (kSortTile keys, 8 per thread: about
 // 75 VGPRs, six waves per SIMD, against 124 and four with 256 threads)
 constexpr int kRadixThreads = 512;
+// threads of a first-tile-pass block (kSortTile pairs generated in LDS)
+constexpr int kPairThreads = 512;
 
 // ---------------------------------------------------------------------------
 // Block-level helpers (256 threads = 4 waves).
@@ -103,6 +105,28 @@ __device__ __forceinline__ uint32_t block_excl_max256(uint32_t x, uint32_t* s_wa
   if (lane == 63) s_wave[w] = inc;
   __syncthreads();
   for (int k = 0; k < w; ++k) ex = max(ex, s_wave[k]);
+  __syncthreads();
+  return ex;
+}
+
+// Exclusive running maximum of one value per thread over an NT-thread block.
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_max(uint32_t x, uint32_t* s_wave) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t inc = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(inc, d, 64);
+    if (lane >= d) inc = max(inc, y);
+  }
+  uint32_t ex = __shfl_up(inc, 1, 64);
+  if (lane == 0) ex = 0;
+  if (lane == 63) s_wave[w] = inc;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NW; ++k)
+    if (k < w) ex = max(ex, s_wave[k]);
   __syncthreads();
   return ex;
 }
@@ -1338,6 +1362,12 @@ struct RowItems {
 // distinct banks.
 __device__ __forceinline__ int spad(int s) { return s + (s >> 4); }
 constexpr int kSortTilePad = kSortTile + kSortTile / 16;
+// The same with one pad word per IT slots (a thread of an NT-thread block
+// owns IT = kSortTile / NT consecutive slots).
+template <int IT>
+__device__ __forceinline__ int spad_n(int s) { return s + s / IT; }
+template <int IT>
+constexpr int sort_tile_pad_n() { return kSortTile + kSortTile / IT; }
 
 // Calls emit(slot, key, value) once for every item of sort block `part`
 // (slot = item index - part T; items at or beyond n are skipped); Items says
@@ -1350,12 +1380,13 @@ constexpr int kSortTilePad = kSortTile + kSortTile / 16;
 // only for its first slot (every later record change starts a record at
 // its first item). A block holds at most T + 1 records; up to 256 are staged
 // in LDS, beyond that they are read from the packed array (L2-resident).
-template <class Items, class Emit>
+template <class Items, int NT = 256, class Emit>
 __device__ __forceinline__ void gen_block_pairs(const uint4* __restrict__ packed,
                                                 const uint32_t* __restrict__ first, int part,
                                                 int64_t n, typename Items::Chunk& S,
                                                 uint32_t* marks,
                                                 uint32_t* s_wave, Emit emit) {
+  constexpr int IT = kSortTile / NT;  // consecutive slots per thread
   const int t = threadIdx.x;
   const uint32_t lo = (uint32_t)part * kSortTile;
   const uint32_t hi = (uint32_t)min(n, (int64_t)lo + kSortTile);
@@ -1366,16 +1397,16 @@ __device__ __forceinline__ void gen_block_pairs(const uint4* __restrict__ packed
   const bool in_lds = nrec <= (uint32_t)Items::kStage;
   if (in_lds) {
     // all loads first, then the LDS stores
-    constexpr int R = Items::kStage / 256;
+    constexpr int R = (Items::kStage + NT - 1) / NT;
     uint4 q[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const uint32_t k = (uint32_t)(t + 256 * r);
+      const uint32_t k = (uint32_t)(t + NT * r);
       if (k < nrec) q[r] = packed[j0 + k];
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const uint32_t k = (uint32_t)(t + 256 * r);
+      const uint32_t k = (uint32_t)(t + NT * r);
       if (k < nrec) {
         S.off[k] = q[r].x;
         S.a[k] = q[r].y;
@@ -1385,42 +1416,42 @@ __device__ __forceinline__ void gen_block_pairs(const uint4* __restrict__ packed
     }
   }
 #pragma unroll
-  for (int i = 0; i < 16; ++i) marks[spad(16 * t + i)] = 0u;
+  for (int i = 0; i < IT; ++i) marks[spad_n<IT>(IT * t + i)] = 0u;
   __syncthreads();
   // (the staged and the unstaged case take separate loops: a pointer that
   // may address either LDS or global memory would make every read a flat
   // load that waits for all outstanding loads)
   auto mark = [&](uint32_t k, uint32_t o) {
     const uint32_t s0 = (o > lo ? o : lo) - lo;
-    if (s0 < (uint32_t)nslots) marks[spad((int)s0)] = k + 1u;
+    if (s0 < (uint32_t)nslots) marks[spad_n<IT>((int)s0)] = k + 1u;
   };
   if (in_lds) {
-    for (uint32_t k = (uint32_t)t; k < nrec; k += 256u) mark(k, S.off[k]);
+    for (uint32_t k = (uint32_t)t; k < nrec; k += (uint32_t)NT) mark(k, S.off[k]);
   } else {
-    for (uint32_t k = (uint32_t)t; k < nrec; k += 256u) mark(k, packed[j0 + k].x);
+    for (uint32_t k = (uint32_t)t; k < nrec; k += (uint32_t)NT) mark(k, packed[j0 + k].x);
   }
   __syncthreads();
-  uint32_t m[16];
+  uint32_t m[IT];
   uint32_t run = 0;
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    run = max(run, marks[spad(16 * t + i)]);
+  for (int i = 0; i < IT; ++i) {
+    run = max(run, marks[spad_n<IT>(IT * t + i)]);
     m[i] = run;
   }
-  const uint32_t pre = block_excl_max256(run, s_wave);
+  const uint32_t pre = block_excl_max<NT>(run, s_wave);
   auto walk = [&](auto rec) {
     int kprev = (int)max(pre, m[0]) - 1;
     uint4 q = rec(kprev);
     uint32_t xx = 0, yy = 0;
     {
       const uint32_t w0 = Items::width(q);
-      const uint32_t local = lo + (uint32_t)(16 * t) - q.x;
+      const uint32_t local = lo + (uint32_t)(IT * t) - q.x;
       yy = local / w0;
       xx = local - yy * w0;
     }
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int s = 16 * t + i;
+    for (int i = 0; i < IT; ++i) {
+      const int s = IT * t + i;
       const int k = (int)max(pre, m[i]) - 1;
       if (i > 0) {
         const bool nk = k != kprev;
@@ -1533,32 +1564,35 @@ __global__ __launch_bounds__(256) void k_pair_hist(const uint4* __restrict__ pac
 // First-pass scatter from regenerated pairs: the block's pairs are laid out
 // in LDS in pair order, then ranked and written exactly like k_radix_scatter
 // (digit = low BITS bits). With RANGES this is also the last pass.
-template <int BITS, bool RANGES, typename KO, class Items>
-__global__ __launch_bounds__(256) void k_pair_scatter(
+template <int BITS, bool RANGES, typename KO, class Items, int NT>
+__global__ __launch_bounds__(NT) void k_pair_scatter(
     const uint4* __restrict__ packed, const uint32_t* __restrict__ first, const int64_t* n_isect,
     int64_t cap, const uint32_t* __restrict__ doff, const uint32_t* __restrict__ dtot,
     int nblocks, KO* __restrict__ kout,
     uint32_t* __restrict__ vout, int2* __restrict__ ranges) {
   constexpr int RADIX = 1 << BITS;
+  constexpr int NW = NT / 64;
+  constexpr int IT = kSortTile / NT;
+  constexpr int PADN = sort_tile_pad_n<IT>();
   __shared__ typename Items::Chunk S;
-  __shared__ uint32_t wcnt[kSortWaves][RADIX];
+  __shared__ uint32_t wcnt[NW][RADIX];
   __shared__ uint32_t gbase[RADIX];
-  __shared__ uint32_t s_wave[4];
+  __shared__ uint32_t s_wave[NW];
   // pairs in slot order at spad(slot) (sval doubles as the generator's
   // marks), then the ranked block in plain order; keys in the output key
   // type (16-bit tile ids take half the LDS: four blocks per CU, not three)
-  __shared__ KO skey[kSortTilePad];
-  __shared__ uint32_t sval[kSortTilePad];
+  __shared__ KO skey[PADN];
+  __shared__ uint32_t sval[PADN];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int64_t n = clamp_n(n_isect, cap);
   const int part = live_swizzle(blockIdx.x, nblocks, n);
   const int64_t bbase = (int64_t)part * kSortTile;
   if (bbase >= n) return;  // whole block beyond the list: no counts, nothing to write
   const int nvalid = (int)min((int64_t)kSortTile, n - bbase);
-  for (int k = t; k < kSortWaves * RADIX; k += 256) (&wcnt[0][0])[k] = 0;
+  for (int k = t; k < NW * RADIX; k += NT) (&wcnt[0][0])[k] = 0;
   // thread t owns digits [DPT t, DPT t + DPT); the block's digit offsets do
   // not depend on the items: fetch them early
-  constexpr int DPT = (RADIX + 255) / 256;
+  constexpr int DPT = (RADIX + NT - 1) / NT;
   uint32_t my_off[DPT], my_tot[DPT], tot_sum = 0;
 #pragma unroll
   for (int i = 0; i < DPT; ++i) {
@@ -1567,20 +1601,20 @@ __global__ __launch_bounds__(256) void k_pair_scatter(
     my_tot[i] = d < RADIX ? dtot[d] : 0u;
     tot_sum += my_tot[i];
   }
-  gen_block_pairs<Items>(packed, first, part, n, S, sval, s_wave,
-                         [&](int slot, uint32_t key, uint32_t val) {
-                           skey[spad(slot)] = (KO)key;
-                           sval[spad(slot)] = val;
-                         });
+  gen_block_pairs<Items, NT>(packed, first, part, n, S, sval, s_wave,
+                             [&](int slot, uint32_t key, uint32_t val) {
+                               skey[spad_n<IT>(slot)] = (KO)key;
+                               sval[spad_n<IT>(slot)] = val;
+                             });
   __syncthreads();
   const uint64_t lt = lanemask_lt();
-  uint32_t key[kSortItems], val[kSortItems], lofs[kSortItems];
+  uint32_t key[IT], val[IT], lofs[IT];
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    const int slot = w * (64 * kSortItems) + j * 64 + lane;
+  for (int j = 0; j < IT; ++j) {
+    const int slot = w * (64 * IT) + j * 64 + lane;
     const bool ok = slot < nvalid;
-    key[j] = ok ? skey[spad(slot)] : 0u;
-    val[j] = ok ? sval[spad(slot)] : 0u;
+    key[j] = ok ? skey[spad_n<IT>(slot)] : 0u;
+    val[j] = ok ? sval[spad_n<IT>(slot)] : 0u;
     const uint32_t d = key[j] & (RADIX - 1);
     const uint64_t m = match_digit<BITS>(d, ok);
     const uint32_t before = wcnt[w][d];
@@ -1588,33 +1622,34 @@ __global__ __launch_bounds__(256) void k_pair_scatter(
     if (ok && (m & lt) == 0) wcnt[w][d] = before + (uint32_t)__popcll(m);
   }
   __syncthreads();
-  uint32_t cw[DPT][4], tot = 0;
+  uint32_t cw[DPT][NW], tot = 0;
 #pragma unroll
   for (int i = 0; i < DPT; ++i) {
     const int d = DPT * t + i;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) cw[i][q] = d < RADIX ? wcnt[q][d] : 0u;
-    tot += cw[i][0] + cw[i][1] + cw[i][2] + cw[i][3];
-  }
-  uint32_t start = block_excl_scan256(tot, s_wave, nullptr);
-  uint32_t dstart = block_excl_scan256(tot_sum, s_wave, nullptr);
-#pragma unroll
-  for (int i = 0; i < DPT; ++i) {
-    const int d = DPT * t + i;
-    if (d < RADIX) {
-      gbase[d] = dstart + my_off[i] - start;
-      wcnt[0][d] = start;
-      wcnt[1][d] = start + cw[i][0];
-      wcnt[2][d] = start + cw[i][0] + cw[i][1];
-      wcnt[3][d] = start + cw[i][0] + cw[i][1] + cw[i][2];
+    for (int q = 0; q < NW; ++q) {
+      cw[i][q] = d < RADIX ? wcnt[q][d] : 0u;
+      tot += cw[i][q];
     }
-    start += cw[i][0] + cw[i][1] + cw[i][2] + cw[i][3];
+  }
+  uint32_t start = block_excl_scan<NT>(tot, s_wave);
+  uint32_t dstart = block_excl_scan<NT>(tot_sum, s_wave);
+#pragma unroll
+  for (int i = 0; i < DPT; ++i) {
+    const int d = DPT * t + i;
+    const uint32_t sd = start;  // the digit's start in the block
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      if (d < RADIX) wcnt[q][d] = start;
+      start += cw[i][q];
+    }
+    if (d < RADIX) gbase[d] = dstart + my_off[i] - sd;
     dstart += my_tot[i];
   }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    const int slot = w * (64 * kSortItems) + j * 64 + lane;
+  for (int j = 0; j < IT; ++j) {
+    const int slot = w * (64 * IT) + j * 64 + lane;
     if (slot < nvalid) {
       const uint32_t pos = wcnt[w][key[j] & (RADIX - 1)] + lofs[j];
       skey[pos] = (KO)key[j];
@@ -1622,8 +1657,8 @@ __global__ __launch_bounds__(256) void k_pair_scatter(
     }
   }
   __syncthreads();
-  write_sorted<BITS, KO, KO, RANGES>(skey, sval, gbase, nvalid, 0, kout, vout, ranges, nullptr,
-                                     nullptr);
+  write_sorted<BITS, KO, KO, RANGES, NT>(skey, sval, gbase, nvalid, 0, kout, vout, ranges,
+                                         nullptr, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -2529,7 +2564,8 @@ static hipError_t pair_sort(const Batch& B, int tile_bits, const float* depth, c
   hipError_t e = digit_scan(L.counts, nb, 1 << dbits, L.dtot, L.csum, st);
   if (e != hipSuccess) return e;
 #define XPR_PAIR_SCATTER(BITS, LAST, ITEMS)                                                 \
-  hipLaunchKernelGGL((k_pair_scatter<BITS, LAST, KT, ITEMS>), dim3(nb), dim3(256), 0, st,       \
+  hipLaunchKernelGGL((k_pair_scatter<BITS, LAST, KT, ITEMS, kPairThreads>), dim3(nb),           \
+                     dim3(kPairThreads), 0, st,                                               \
                      L.packed,                                                               \
                      L.first, n_isect, cap, L.counts, L.dtot, nb, k1, v1,                   \
                      LAST ? ranges : (int2*)nullptr)
@@ -2949,7 +2985,8 @@ static hipError_t band_sort(const Batch& B, const float* depth, const short4* rc
   if (e != hipSuccess) return e;
   uint16_t* k1 = one ? nullptr : tk0;
 #define XPR_BAND_SCATTER(BITS, LAST)                                                          \
-  hipLaunchKernelGGL((k_pair_scatter<BITS, LAST, uint16_t, BandItems>), dim3(nb), dim3(256), 0, \
+  hipLaunchKernelGGL((k_pair_scatter<BITS, LAST, uint16_t, BandItems, kPairThreads>), dim3(nb),  \
+                     dim3(kPairThreads), 0,                                                   \
                      st, L.packed, L.first, (const int64_t*)L.n_ent, cap, L.counts, L.dtot, nb, k1, \
                      v1,                                                                       \
                      LAST ? L.branges : (int2*)nullptr)
