@@ -26,6 +26,9 @@ constexpr int kSortWaves = 4;
 constexpr int kRadixThreads = 512;
 // threads of a first-tile-pass block (kSortTile pairs generated in LDS)
 constexpr int kPairThreads = 512;
+// threads of a first-pass histogram block (one sort block's records: about
+// a hundred and fifty at this workload, so one wave)
+constexpr int kHistThreads = 64;
 
 // ---------------------------------------------------------------------------
 // Block-level helpers (256 threads = 4 waves).
@@ -1486,17 +1489,18 @@ __device__ __forceinline__ void gen_block_pairs(const uint4* __restrict__ packed
 // from t0 mod RADIX once. The runs go into an LDS difference array (at
 // most three atomics per row segment instead of one per item), whose
 // prefix sums are the counts; written digit-major like k_radix_hist.
-template <int BITS, class Items>
-__global__ __launch_bounds__(256) void k_pair_hist(const uint4* __restrict__ packed,
+template <int BITS, class Items, int NT>
+__global__ __launch_bounds__(NT) void k_pair_hist(const uint4* __restrict__ packed,
                                                    const uint32_t* __restrict__ first,
                                                    const int64_t* n_isect, int64_t cap,
                                                    uint32_t* __restrict__ counts, int nblocks) {
   constexpr int RADIX = 1 << BITS;
-  constexpr int DPT = (RADIX + 255) / 256;
+  constexpr int DPT = (RADIX + NT - 1) / NT;
+  constexpr int NW = NT / 64;
   __shared__ int32_t D[RADIX];
-  __shared__ uint32_t s_wave[4];
+  __shared__ uint32_t s_wave[NW];
   const int t = threadIdx.x;
-  for (int k = t; k < RADIX; k += 256) D[k] = 0;
+  for (int k = t; k < RADIX; k += NT) D[k] = 0;
   const int64_t n = clamp_n(n_isect, cap);
   const int part = live_swizzle(blockIdx.x, nblocks, n);
   __syncthreads();
@@ -1505,7 +1509,7 @@ __global__ __launch_bounds__(256) void k_pair_hist(const uint4* __restrict__ pac
     const uint32_t lo = (uint32_t)part * kSortTile;
     const uint32_t hi = (uint32_t)min(n, (int64_t)lo + kSortTile);
     const uint32_t j0 = first[part], j1 = first[part + 1];
-    for (uint32_t k = j0 + (uint32_t)t; k <= j1; k += 256u) {
+    for (uint32_t k = j0 + (uint32_t)t; k <= j1; k += (uint32_t)NT) {
       const uint4 q = packed[k];
       const uint32_t o = q.x;
       const uint32_t end = k < j1 ? min(packed[k + 1].x, hi) : hi;
@@ -1540,7 +1544,8 @@ __global__ __launch_bounds__(256) void k_pair_hist(const uint4* __restrict__ pac
     const uint32_t inc = wave_incl_scan(whole);
     if ((t & 63) == 63) s_wave[t >> 6] = inc;
     __syncthreads();
-    all = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+#pragma unroll
+    for (int q = 0; q < NW; ++q) all += s_wave[q];
     __syncthreads();
   }
   // counts = all + inclusive prefix sums of D; thread t holds digits
@@ -1552,7 +1557,7 @@ __global__ __launch_bounds__(256) void k_pair_hist(const uint4* __restrict__ pac
     dv[i] = d < RADIX ? D[d] : 0;
     run += dv[i];
   }
-  int32_t pre = (int32_t)block_excl_scan256((uint32_t)run, s_wave, nullptr);
+  int32_t pre = (int32_t)block_excl_scan<NT>((uint32_t)run, s_wave);
 #pragma unroll
   for (int i = 0; i < DPT; ++i) {
     const int d = DPT * t + i;
@@ -2553,7 +2558,8 @@ static hipError_t pair_sort(const Batch& B, int tile_bits, const float* depth, c
   const int nb = (int)((grid_n + kSortTile - 1) / kSortTile);
   KT* k1 = (one && !keys_out) ? nullptr : tk0;
 #define XPR_PAIR_HIST(BITS, ITEMS)                                                          \
-  hipLaunchKernelGGL((k_pair_hist<BITS, ITEMS>), dim3(nb), dim3(256), 0, st, L.packed, L.first, \
+  hipLaunchKernelGGL((k_pair_hist<BITS, ITEMS, kHistThreads>), dim3(nb), dim3(kHistThreads), 0,  \
+                     st, L.packed, L.first,                                                   \
                      n_isect, cap, L.counts, nb)
   if (dbits == 7) {
     if (splat) XPR_PAIR_HIST(7, RowItems); else XPR_PAIR_HIST(7, PairItems);
@@ -2972,7 +2978,8 @@ static hipError_t band_sort(const Batch& B, const float* depth, const short4* rc
   hipLaunchKernelGGL(k_ranges_init, dim3(grid1(nbk)), dim3(256), 0, st, L.branges, nbk);
   const int nb = (int)((grid_n + kSortTile - 1) / kSortTile);
 #define XPR_BAND_HIST(BITS)                                                                   \
-  hipLaunchKernelGGL((k_pair_hist<BITS, BandItems>), dim3(nb), dim3(256), 0, st, L.packed,        \
+  hipLaunchKernelGGL((k_pair_hist<BITS, BandItems, kHistThreads>), dim3(nb), dim3(kHistThreads),  \
+                     0, st, L.packed,                                                         \
                      L.first, (const int64_t*)L.n_ent, cap, L.counts, nb)
   switch (dbits) {
     case 7: XPR_BAND_HIST(7); break;
