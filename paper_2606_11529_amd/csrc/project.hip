@@ -833,7 +833,11 @@ __global__ __launch_bounds__(256, 2) void k_project_bwd_gut(Batch B,
     const ViewDev& V = B.v[vi];
     if (V.scene != sidx) continue;
     const int r = V.rec_off + i;
-    if (tc[r] == 0) continue;
+    // a record the view does not see adds nothing, but the first view still
+    // stores its zero SH gradient, in the same store instruction as the
+    // visible lanes (two partial stores to one line would write it twice)
+    const bool vis = tc[r] != 0;
+    if (!vis && (sh_out || accumulate)) continue;
     const float* g = grad + 16 * (size_t)r;
     double R[9];
 #pragma unroll
@@ -855,9 +859,11 @@ __global__ __launch_bounds__(256, 2) void k_project_bwd_gut(Batch B,
       sh_basis<DEG>(dxf, dyf, dzf, Y);
       const float* col = splat + 24 * (size_t)r + 6;  // (r, g, b) of the 24-float record
       float wsum[16];
-      sh_backward<DEG>(S, G, i, Y, col[0] > 0.f ? g[1] : 0.f, col[1] > 0.f ? g[2] : 0.f,
-                       col[2] > 0.f ? g[3] : 0.f, sh_out || accumulate, wsum);
+      sh_backward<DEG>(S, G, i, Y, vis && col[0] > 0.f ? g[1] : 0.f,
+                       vis && col[1] > 0.f ? g[2] : 0.f, vis && col[2] > 0.f ? g[3] : 0.f,
+                       sh_out || accumulate, wsum);
       sh_out = true;
+      if (!vis) continue;
       float gdxf, gdyf, gdzf;
       sh_basis_vjp<DEG>(dxf, dyf, dzf, wsum, gdxf, gdyf, gdzf);
       const double gd[3] = {gdxf, gdyf, gdzf};
@@ -1146,11 +1152,42 @@ __global__ __launch_bounds__(256) void k_project_bwd_lin(Batch B, const float* _
     const ViewDev& V = B.v[vi];
     if (V.scene != sidx) continue;
     const int r = V.rec_off + i;
-    if (tc[r] == 0) continue;
+    // a record the view does not see adds nothing, but the first view still
+    // stores its zero SH gradient, in the same store instruction as the
+    // visible lanes (two partial stores to one line would write it twice)
+    const bool vis = tc[r] != 0;
+    if (!vis && (sh_out || accumulate)) continue;
     const float* g = grad + 16 * (size_t)r;
     double R[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) R[k] = V.R[k];
+
+    // colour = max(0, 0.5 + sum_j sh_j Y_j(dir)), dir = (mu - campos) / |.|
+    {
+      const double cp[3] = {-(R[0] * V.t[0] + R[3] * V.t[1] + R[6] * V.t[2]),
+                            -(R[1] * V.t[0] + R[4] * V.t[1] + R[7] * V.t[2]),
+                            -(R[2] * V.t[0] + R[5] * V.t[1] + R[8] * V.t[2])};
+      const double dv[3] = {mu[0] - cp[0], mu[1] - cp[1], mu[2] - cp[2]};
+      const double dn = 1.0 / sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+      const double dir[3] = {dv[0] * dn, dv[1] * dn, dv[2] * dn};
+      const float dxf = (float)dir[0], dyf = (float)dir[1], dzf = (float)dir[2];
+      float Y[16];
+      sh_basis<DEG>(dxf, dyf, dzf, Y);
+      const float* col = splat + 20 * (size_t)r + 3;  // (r, g, b) of the 20-float record
+      float wsum[16];
+      sh_backward<DEG>(S, G, i, Y, vis && col[0] > 0.f ? g[3] : 0.f,
+                       vis && col[1] > 0.f ? g[4] : 0.f, vis && col[2] > 0.f ? g[5] : 0.f,
+                       sh_out || accumulate, wsum);
+      sh_out = true;
+      if (!vis) continue;
+      float gdxf, gdyf, gdzf;
+      sh_basis_vjp<DEG>(dxf, dyf, dzf, wsum, gdxf, gdyf, gdzf);
+      const double gd[3] = {gdxf, gdyf, gdzf};
+      const double dd = dir[0] * gd[0] + dir[1] * gd[1] + dir[2] * gd[2];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) gmu[k] += (gd[k] - dir[k] * dd) * dn;
+    }
+
     const double fx = V.fx, fy = V.fy;
     const double x = R[0] * mu[0] + R[1] * mu[1] + R[2] * mu[2] + (double)V.t[0];
     const double y = R[3] * mu[0] + R[4] * mu[1] + R[5] * mu[2] + (double)V.t[1];
@@ -1168,30 +1205,6 @@ __global__ __launch_bounds__(256) void k_project_bwd_lin(Batch B, const float* _
     // sigma
     go += (float)(g[2] * dsig_do);
     gs[jmin] -= g[2] * sigma / smin;
-
-    // colour = max(0, 0.5 + sum_j sh_j Y_j(dir)), dir = (mu - campos) / |.|
-    {
-      const double cp[3] = {-(R[0] * V.t[0] + R[3] * V.t[1] + R[6] * V.t[2]),
-                            -(R[1] * V.t[0] + R[4] * V.t[1] + R[7] * V.t[2]),
-                            -(R[2] * V.t[0] + R[5] * V.t[1] + R[8] * V.t[2])};
-      const double dv[3] = {mu[0] - cp[0], mu[1] - cp[1], mu[2] - cp[2]};
-      const double dn = 1.0 / sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-      const double dir[3] = {dv[0] * dn, dv[1] * dn, dv[2] * dn};
-      const float dxf = (float)dir[0], dyf = (float)dir[1], dzf = (float)dir[2];
-      float Y[16];
-      sh_basis<DEG>(dxf, dyf, dzf, Y);
-      const float* col = splat + 20 * (size_t)r + 3;  // (r, g, b) of the 20-float record
-      float wsum[16];
-      sh_backward<DEG>(S, G, i, Y, col[0] > 0.f ? g[3] : 0.f, col[1] > 0.f ? g[4] : 0.f,
-                       col[2] > 0.f ? g[5] : 0.f, sh_out || accumulate, wsum);
-      sh_out = true;
-      float gdxf, gdyf, gdzf;
-      sh_basis_vjp<DEG>(dxf, dyf, dzf, wsum, gdxf, gdyf, gdzf);
-      const double gd[3] = {gdxf, gdyf, gdzf};
-      const double dd = dir[0] * gd[0] + dir[1] * gd[1] + dir[2] * gd[2];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) gmu[k] += (gd[k] - dir[k] * dd) * dn;
-    }
 
     // A = J3 Wm diag(s), Wm = R_w2c Rq, C = A^-1 (as the forward forms them)
     const double J[9] = {fx * iz, 0.0, -fx * x * iz2, 0.0, fy * iz, -fy * y * iz2,
