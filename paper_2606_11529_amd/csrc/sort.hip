@@ -31,7 +31,7 @@ constexpr int kPairThreads = 512;
 constexpr int kHistThreads = 64;
 
 // ---------------------------------------------------------------------------
-// Block-level helpers (256 threads = 4 waves).
+// Block-level helpers (256 threads = 4 waves unless they take NT).
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
   const int lane = threadIdx.x & 63;
@@ -1374,15 +1374,17 @@ constexpr int sort_tile_pad_n() { return kSortTile + kSortTile / IT; }
 
 // Calls emit(slot, key, value) once for every item of sort block `part`
 // (slot = item index - part T; items at or beyond n are skipped); Items says
-// what a record's grid of items is. Must be called by all threads of the
-// block. `marks` is LDS scratch of kSortTilePad words.
+// what a record's grid of items is. Must be called by all NT threads of the
+// block. `marks` is LDS scratch of sort_tile_pad_n<IT>() words, IT =
+// kSortTile / NT.
 //
 // Each record marks the slot of its first item, and a block-wide running
 // maximum over the slots gives every slot its record; thread t then handles
-// slots 16t .. 16t + 15, stepping through its record's grid and dividing
-// only for its first slot (every later record change starts a record at
-// its first item). A block holds at most T + 1 records; up to 256 are staged
-// in LDS, beyond that they are read from the packed array (L2-resident).
+// slots IT t .. IT t + IT - 1, stepping through its record's grid and
+// dividing only for its first slot (every later record change starts a
+// record at its first item). A block holds at most T + 1 records; up to
+// Items::kStage are staged in LDS, beyond that they are read from the
+// packed array (L2-resident).
 template <class Items, int NT = 256, class Emit>
 __device__ __forceinline__ void gen_block_pairs(const uint4* __restrict__ packed,
                                                 const uint32_t* __restrict__ first, int part,
