@@ -273,7 +273,8 @@ struct GutBwdStage {
 };
 
 template <int TW, int TH>
-__global__ __launch_bounds__(TW* TH) void k_render_bwd_gut(
+__global__ __launch_bounds__(TW* TH)
+__attribute__((amdgpu_waves_per_eu(TW * TH >= 256 ? 5 : 1))) void k_render_bwd_gut(
     Batch B, const float4* __restrict__ splat, const int32_t* __restrict__ vals,
     const int2* __restrict__ ranges, const float* __restrict__ dimg,
     const float* __restrict__ Tfin, const int32_t* __restrict__ ncon, float* __restrict__ grad,
