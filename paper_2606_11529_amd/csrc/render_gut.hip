@@ -73,7 +73,8 @@ __device__ __forceinline__ uint32_t gut_wave_mask(uint32_t bx, uint32_t by, int 
 // [g][2]: per pixel the entries evaluated (up to and including the one that
 // stops it, else the whole list) and the entries blended.
 template <int TW, int TH, bool COUNT = false>
-__global__ __launch_bounds__(TW* TH) void k_render_fwd_gut(
+__global__ __launch_bounds__(TW* TH)
+__attribute__((amdgpu_waves_per_eu(TW * TH >= 256 ? 7 : 1))) void k_render_fwd_gut(
     Batch B, const float4* __restrict__ splat, const int32_t* __restrict__ vals,
     const int2* __restrict__ ranges, float* __restrict__ image, float* __restrict__ Tfin,
     int32_t* __restrict__ ncon, int32_t* __restrict__ tile_work, const int32_t* order) {
